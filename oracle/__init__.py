@@ -1,0 +1,310 @@
+"""FP64 CPU oracle for the fluctuating D3Q19 lattice-Boltzmann hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It is the plain,
+slow, obviously-correct reference the GPU library is checked against, and it
+shares no code, header, table or generator with that library.
+
+The arithmetic lives in ``lb_oracle.c`` (plain C, IEEE double, no
+contraction); this module only builds it with gcc and marshals numpy arrays
+through ctypes.  Each wrapped function names the passage of the paper it
+follows in the C source.
+
+Array layouts (all float64, C-contiguous):
+  populations  n[19, nz, ny, nx]   (index i*N + x + nx*(y + ny*z))
+  vector field  u[3, nz, ny, nx]
+  bead arrays   pos, mom [nb, 3];  mass, zeta [nb];  bonds int32 [nbonds, 2]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lb_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblb_oracle.so")
+
+Q = 19
+
+
+def build(force: bool = False) -> str:
+    """Compile lb_oracle.c into liblb_oracle.so with gcc (FP64, no contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("noise_rho0", ctypes.c_int32),
+        ("rho0", ctypes.c_double),
+        ("gamma_shear", ctypes.c_double), ("gamma_bulk", ctypes.c_double),
+        ("gamma_3a", ctypes.c_double), ("gamma_3b", ctypes.c_double),
+        ("gamma_4a", ctypes.c_double), ("gamma_4b", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("g", ctypes.c_double * 3),
+        ("seed", ctypes.c_uint64),
+        ("box", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
+    ]
+
+
+@dataclass
+class Params:
+    """Fluid parameters in lattice units (b = h = 1)."""
+    nx: int
+    ny: int
+    nz: int
+    rho0: float = 1.0
+    gamma_shear: float = 0.0
+    gamma_bulk: float = 0.0
+    gamma_3a: float = 0.0
+    gamma_3b: float = 0.0
+    gamma_4a: float = 0.0
+    gamma_4b: float = 0.0
+    kT: float = 0.0
+    g: tuple = (0.0, 0.0, 0.0)
+    seed: int = 0
+    noise_rho0: bool = False
+    box: int = 0
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def c(self) -> OrcParams:
+        p = OrcParams()
+        p.nx, p.ny, p.nz = self.nx, self.ny, self.nz
+        p.noise_rho0 = 1 if self.noise_rho0 else 0
+        p.rho0 = self.rho0
+        p.gamma_shear, p.gamma_bulk = self.gamma_shear, self.gamma_bulk
+        p.gamma_3a, p.gamma_3b = self.gamma_3a, self.gamma_3b
+        p.gamma_4a, p.gamma_4b = self.gamma_4a, self.gamma_4b
+        p.kT = self.kT
+        for a in range(3):
+            p.g[a] = float(self.g[a])
+        p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        p.box = int(self.box)
+        return p
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        up = ctypes.POINTER(ctypes.c_uint32)
+        lp = ctypes.POINTER(ctypes.c_int64)
+        pp = ctypes.POINTER(OrcParams)
+        L.orc_tables.argtypes = [ip, dp, dp, dp]
+        L.orc_philox4x32_10.argtypes = [up, up, up]
+        L.orc_fluid_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.orc_bead_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_moments_site.argtypes = [dp, dp]
+        L.orc_back_site.argtypes = [dp, dp]
+        L.orc_collide_site.argtypes = [pp, dp, dp, dp, dp]
+        L.orc_init_equilibrium.argtypes = [pp, dp, dp, dp]
+        L.orc_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32]
+        L.orc_run.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32]
+        L.orc_fields.argtypes = [pp, dp, dp, dp]
+        L.orc_totals.argtypes = [pp, dp, dp]
+        L.orc_mode_field.argtypes = [pp, dp, dp]
+        L.orc_stencil.argtypes = [pp, dp, lp, dp]
+        L.orc_couple.argtypes = [pp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
+                                 ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_coupled_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
+                                       ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double]
+        for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals",
+                     "orc_equilibrium", "orc_moments_site", "orc_back_site", "orc_collide_site",
+                     "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
+                     "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step"):
+            getattr(L, name).restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# tables, RNG
+# --------------------------------------------------------------------------
+
+def tables():
+    """Return (c [19,3] int, a [19], e [19,19], w [19]) as written in the oracle."""
+    c = np.zeros((Q, 3), np.int32)
+    a = np.zeros(Q)
+    e = np.zeros((Q, Q))
+    w = np.zeros(Q)
+    lib().orc_tables(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(a), _dp(e), _dp(w))
+    return c, a, e, w
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, np.uint32)
+    up = ctypes.POINTER(ctypes.c_uint32)
+    lib().orc_philox4x32_10(c.ctypes.data_as(up), k.ctypes.data_as(up), out.ctypes.data_as(up))
+    return out
+
+
+def fluid_normals(seed: int, site: int, step: int, box: int = 0) -> np.ndarray:
+    g = np.zeros(16)
+    lib().orc_fluid_normals(seed, site, step, box, _dp(g))
+    return g
+
+
+def bead_normals(seed: int, bead: int, step: int, box: int = 0) -> np.ndarray:
+    g = np.zeros(3)
+    lib().orc_bead_normals(seed, bead, step, box, _dp(g))
+    return g
+
+
+# --------------------------------------------------------------------------
+# single site
+# --------------------------------------------------------------------------
+
+def equilibrium(rho: float, u) -> np.ndarray:
+    uu = _f64(u)
+    out = np.zeros(Q)
+    lib().orc_equilibrium(float(rho), _dp(uu), _dp(out))
+    return out
+
+
+def moments_site(n) -> np.ndarray:
+    nn = _f64(n)
+    out = np.zeros(Q)
+    lib().orc_moments_site(_dp(nn), _dp(out))
+    return out
+
+
+def back_site(m) -> np.ndarray:
+    mm = _f64(m)
+    out = np.zeros(Q)
+    lib().orc_back_site(_dp(mm), _dp(out))
+    return out
+
+
+def collide_site(p: Params, n, F=(0.0, 0.0, 0.0), gnoise=None) -> np.ndarray:
+    nn = _f64(n)
+    FF = _f64(F)
+    g = _f64(gnoise if gnoise is not None else np.zeros(16))
+    out = np.zeros(Q)
+    pc = p.c()
+    lib().orc_collide_site(ctypes.byref(pc), _dp(nn), _dp(FF), _dp(g), _dp(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# lattice
+# --------------------------------------------------------------------------
+
+def init_equilibrium(p: Params, rho=None, u=None) -> np.ndarray:
+    n = np.zeros((Q, p.nz, p.ny, p.nx))
+    r = _f64(rho).reshape(-1) if rho is not None else None
+    uu = _f64(u).reshape(-1) if u is not None else None
+    pc = p.c()
+    lib().orc_init_equilibrium(ctypes.byref(pc), _dp(r) if r is not None else None,
+                               _dp(uu) if uu is not None else None, _dp(n))
+    return n
+
+
+def step(p: Params, n: np.ndarray, step_index: int, extra_force=None) -> None:
+    """One collide+stream step in place (extra_force: [3,nz,ny,nx] or None)."""
+    work = np.empty_like(n)
+    pc = p.c()
+    ef = _f64(extra_force) if extra_force is not None else None
+    lib().orc_step(ctypes.byref(pc), _dp(n), _dp(work), _dp(ef) if ef is not None else None, step_index)
+
+
+def run(p: Params, n: np.ndarray, nsteps: int, step0: int = 0) -> None:
+    pc = p.c()
+    lib().orc_run(ctypes.byref(pc), _dp(n), int(nsteps), int(step0))
+
+
+def fields(p: Params, n: np.ndarray):
+    rho = np.zeros((p.nz, p.ny, p.nx))
+    u = np.zeros((3, p.nz, p.ny, p.nx))
+    pc = p.c()
+    lib().orc_fields(ctypes.byref(pc), _dp(n), _dp(rho), _dp(u))
+    return rho, u
+
+
+def totals(p: Params, n: np.ndarray) -> np.ndarray:
+    out = np.zeros(4)
+    pc = p.c()
+    lib().orc_totals(ctypes.byref(pc), _dp(n), _dp(out))
+    return out
+
+
+def mode_field(p: Params, n: np.ndarray) -> np.ndarray:
+    m = np.zeros((Q, p.nz, p.ny, p.nx))
+    pc = p.c()
+    lib().orc_mode_field(ctypes.byref(pc), _dp(n), _dp(m))
+    return m
+
+
+def stencil(p: Params, R):
+    RR = _f64(R)
+    node = np.zeros(8, np.int64)
+    w = np.zeros(8)
+    pc = p.c()
+    lib().orc_stencil(ctypes.byref(pc), _dp(RR), node.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(w))
+    return node, w
+
+
+@dataclass
+class Beads:
+    """Bead state for the oracle (float64, positions unwrapped)."""
+    pos: np.ndarray
+    mom: np.ndarray
+    mass: np.ndarray
+    zeta: np.ndarray
+    bonds: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    k_bond: float = 0.0
+    r0: float = 1.0
+
+    def copy(self) -> "Beads":
+        return Beads(self.pos.copy(), self.mom.copy(), self.mass.copy(), self.zeta.copy(),
+                     self.bonds.copy(), self.k_bond, self.r0)
+
+
+def couple(p: Params, n: np.ndarray, step_index: int, beads: Beads, force: np.ndarray) -> None:
+    """Particle half-step; updates beads in place and accumulates into force [3,nz,ny,nx]."""
+    nb = beads.pos.shape[0]
+    bonds = np.ascontiguousarray(beads.bonds, dtype=np.int32).reshape(-1)
+    pc = p.c()
+    lib().orc_couple(ctypes.byref(pc), _dp(n), int(step_index), nb, _dp(beads.pos), _dp(beads.mom),
+                     _dp(beads.mass), _dp(beads.zeta), int(beads.bonds.shape[0]),
+                     bonds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if bonds.size else None,
+                     float(beads.k_bond), float(beads.r0), _dp(force))
+
+
+def coupled_step(p: Params, n: np.ndarray, step_index: int, beads: Beads) -> np.ndarray:
+    """Particle update, spreading, then one LB step.  Returns the force field used."""
+    force = np.zeros((3, p.nz, p.ny, p.nx))
+    couple(p, n, step_index, beads, force)
+    step(p, n, step_index, extra_force=force)
+    return force

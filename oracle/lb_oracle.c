@@ -1,0 +1,608 @@
+/*
+ * FP64 CPU oracle for the fluctuating D3Q19 lattice-Boltzmann method with
+ * frictional point-particle coupling (Duenweg & Ladd, "Lattice Boltzmann
+ * simulations of soft matter systems").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or generator with the HIP library: every constant below is
+ * written out here from the paper, and the counter-based random number
+ * generator is implemented here from its published definition.
+ *
+ * Arithmetic is IEEE double, compiled without floating-point contraction.
+ * Loops are written the way the paper states the algorithm: moments by a
+ * full 19x19 matrix-vector product, the equilibrium from its closed form,
+ * relaxation mode by mode, the back-transformation by the weighted basis,
+ * the forcing term in population space.  No pair sums, no fusion.
+ *
+ * Conventions (readings where the paper is silent; each is listed with its
+ * reason in the design notes):
+ *   - lattice units b = h = 1, c_s^2 = 1/3, so mu = kT / c_s^2 = 3 kT;
+ *   - velocity order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 the twelve
+ *     diagonal directions in opposite pairs (see CV below);
+ *   - state array layout n[i*N + s], s = x + nx*(y + ny*z), periodic box;
+ *   - the stored state is the pre-collision population n(r,t); one step is
+ *     collide at every site then stream, n_i(r+c_i,t+1) = n*_i(r,t);
+ *   - random numbers: Philox4x32-10 keyed by the seed, counter
+ *     (site, step, stream<<16 | call, box); 24-bit uniforms; Box-Muller.
+ *
+ * Parity status of every exported function is stated at its definition.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* ------------------------------------------------------------------------ */
+/* Lattice tables (Sec. "D3Q19 model I/II", Table 1)                         */
+/* ------------------------------------------------------------------------ */
+
+/* The 19 velocities of D3Q19: rest, 6 nearest and 12 next-nearest
+ * neighbours (D3Q19 classification in the introduction of the fluctuating LB
+ * section).  The paper fixes the set, not the order; opposite directions are
+ * adjacent here. */
+static const int CV[Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+/* Weights a^{c_i}: 1/3 for the rest particle, 1/18 for speed 1, 1/36 for
+ * speed sqrt(2) (text after eq. original_equil_distrib). */
+static double weight_of_speed2(int c2)
+{
+    if (c2 == 0) return 1.0 / 3.0;
+    if (c2 == 1) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+/* Basis polynomials e_ki of Table 1, evaluated at c_i (c = b/h = 1, so the
+ * hatted and plain velocities coincide). */
+static double basis(int k, int cx, int cy, int cz)
+{
+    const double x = cx, y = cy, z = cz;
+    const double c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return c2 - 1.0;
+    case 5: return 3.0 * x * x - c2;
+    case 6: return y * y - z * z;
+    case 7: return x * y;
+    case 8: return y * z;
+    case 9: return z * x;
+    case 10: return (3.0 * c2 - 5.0) * x;
+    case 11: return (3.0 * c2 - 5.0) * y;
+    case 12: return (3.0 * c2 - 5.0) * z;
+    case 13: return (y * y - z * z) * x;
+    case 14: return (z * z - x * x) * y;
+    case 15: return (x * x - y * y) * z;
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (3.0 * x * x - c2);
+    case 18: return (2.0 * c2 - 3.0) * (y * y - z * z);
+    }
+    return 0.0;
+}
+
+/* Normalisation factors w_k, third column of Table 1. */
+static const double WK[Q] = {1.0,       1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0,
+                             4.0 / 3.0, 4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             2.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 2.0 / 9.0, 2.0 / 9.0,
+                             2.0 / 9.0, 2.0,       4.0 / 3.0, 4.0 / 9.0};
+
+static const double CS2 = 1.0 / 3.0; /* c_s^2 = (1/3)(b/h)^2 */
+
+static double A[Q];     /* a^{c_i} */
+static double E[Q][Q];  /* e_ki */
+static int tables_ready = 0;
+
+static void init_tables(void)
+{
+    if (tables_ready) return;
+    for (int i = 0; i < Q; ++i) {
+        const int c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
+        A[i] = weight_of_speed2(c2);
+        for (int k = 0; k < Q; ++k) E[k][i] = basis(k, CV[i][0], CV[i][1], CV[i][2]);
+    }
+    tables_ready = 1;
+}
+
+/* Parity pinned: tests check sum a = 1, isotropy of the second and fourth
+ * moments (eq. w1-w4 with C4' = 0, C4 = C2^2), and that the weighted Gram
+ * matrix of e_ki is diag(w_k) (eq. orthogonality with q = a). */
+void orc_tables(int32_t *c_out, double *a_out, double *e_out, double *w_out)
+{
+    init_tables();
+    for (int i = 0; i < Q; ++i) {
+        for (int d = 0; d < 3; ++d) c_out[3 * i + d] = CV[i][d];
+        a_out[i] = A[i];
+    }
+    for (int k = 0; k < Q; ++k) {
+        w_out[k] = WK[k];
+        for (int i = 0; i < Q; ++i) e_out[k * Q + i] = E[k][i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Gaussian variates   */
+/* ------------------------------------------------------------------------ */
+
+/* Parity pinned against an independent library implementation (rocRAND's
+ * philox engine, compiled for the host) by the test suite. */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u; /* round multipliers */
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u; /* Weyl key increments */
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)M0 * (uint64_t)c[0];
+        const uint64_t p1 = (uint64_t)M1 * (uint64_t)c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n1 = lo1;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        const uint32_t n3 = lo0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+static const double TWO_M24 = 1.0 / 16777216.0; /* 2^-24 */
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+/* Box-Muller: radius from a uniform in (0,1], angle from a uniform in [0,1). */
+static void box_muller(uint32_t fa, uint32_t fb, double *g0, double *g1)
+{
+    const double ua = ((double)fa + 1.0) * TWO_M24;
+    const double ub = (double)fb * TWO_M24;
+    const double r = sqrt(-2.0 * log(ua));
+    *g0 = r * cos(TWO_PI * ub);
+    *g1 = r * sin(TWO_PI * ub);
+}
+
+/* Sixteen unit Gaussians for the fluid noise at (site, step, box).  Three
+ * Philox calls (counter word 2 = call 0,1,2; stream 0) give twelve 32-bit
+ * words; each group of three words w0,w1,w2 yields four 24-bit fields
+ * w0>>8, w1>>8, w2>>8 and the three low bytes (w0&255)|(w1&255)<<8|(w2&255)<<16.
+ * Field pairs (2p, 2p+1) feed Box-Muller pair p.  Mode k = 4..18 takes g[k-4].
+ * Parity pinned: distribution tests (moments, independence) in the suite;
+ * the integer stream is pinned through orc_philox4x32_10. */
+void orc_fluid_normals(uint64_t seed, uint32_t site, uint32_t step, uint32_t box, double g[16])
+{
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t w[12];
+    for (uint32_t call = 0; call < 3; ++call) {
+        const uint32_t ctr[4] = {site, step, (0u << 16) | call, box};
+        orc_philox4x32_10(ctr, key, &w[4 * call]);
+    }
+    uint32_t f[16];
+    for (int grp = 0; grp < 4; ++grp) {
+        const uint32_t a = w[3 * grp], b = w[3 * grp + 1], c = w[3 * grp + 2];
+        f[4 * grp + 0] = a >> 8;
+        f[4 * grp + 1] = b >> 8;
+        f[4 * grp + 2] = c >> 8;
+        f[4 * grp + 3] = (a & 0xffu) | ((b & 0xffu) << 8) | ((c & 0xffu) << 16);
+    }
+    for (int p = 0; p < 8; ++p) box_muller(f[2 * p], f[2 * p + 1], &g[2 * p], &g[2 * p + 1]);
+}
+
+/* Three unit Gaussians for the Langevin noise of bead `bead` at `step`
+ * (stream 1, one Philox call; fields w0>>8,w1>>8 and w2>>8,w3>>8). */
+void orc_bead_normals(uint64_t seed, uint32_t bead, uint32_t step, uint32_t box, double g[3])
+{
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    const uint32_t ctr[4] = {bead, step, (1u << 16) | 0u, box};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double g3;
+    box_muller(w[0] >> 8, w[1] >> 8, &g[0], &g[1]);
+    box_muller(w[2] >> 8, w[3] >> 8, &g[2], &g3);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parameters                                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t noise_rho0;   /* 0: noise amplitude uses local rho, 1: uses rho0 */
+    double rho0;
+    double gamma_shear, gamma_bulk, gamma_3a, gamma_3b, gamma_4a, gamma_4b;
+    double kT;
+    double g[3];          /* uniform body-force density */
+    uint64_t seed;
+    uint32_t box;
+    uint32_t pad;
+} orc_params;
+
+/* Eigenvalue gamma_k of each mode (Sec. "D3Q19 model II"): bulk mode 4,
+ * shear modes 5-9, kinetic groups 10-12, 13-15, 16, 17-18.  Conserved
+ * modes 0-3 are left untouched by the relaxation. */
+static void mode_gammas(const orc_params *p, double gam[Q])
+{
+    for (int k = 0; k < 4; ++k) gam[k] = 1.0;
+    gam[4] = p->gamma_bulk;
+    for (int k = 5; k <= 9; ++k) gam[k] = p->gamma_shear;
+    for (int k = 10; k <= 12; ++k) gam[k] = p->gamma_3a;
+    for (int k = 13; k <= 15; ++k) gam[k] = p->gamma_3b;
+    gam[16] = p->gamma_4a;
+    gam[17] = p->gamma_4b;
+    gam[18] = p->gamma_4b;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-site operations                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Equilibrium populations, eq. original_equil_distrib.
+ * Parity pinned: tests check its mass, momentum and second moment against
+ * eq. MBeq0-MBeq2 (rho, rho u, rho c_s^2 delta + rho u u). */
+void orc_equilibrium(double rho, const double u[3], double neq[Q])
+{
+    init_tables();
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        const double uc = u[0] * CV[i][0] + u[1] * CV[i][1] + u[2] * CV[i][2];
+        neq[i] = A[i] * rho * (1.0 + uc / CS2 + uc * uc / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+    }
+}
+
+/* Moments m_k = sum_i e_ki n_i (eq. "forward"). */
+void orc_moments_site(const double n[Q], double m[Q])
+{
+    init_tables();
+    for (int k = 0; k < Q; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += E[k][i] * n[i];
+        m[k] = s;
+    }
+}
+
+/* Back-transformation n_i = a_i sum_k e_ki m_k / w_k (eq. back_transformation
+ * with q = a). */
+void orc_back_site(const double m[Q], double n[Q])
+{
+    init_tables();
+    for (int i = 0; i < Q; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < Q; ++k) s += E[k][i] * m[k] / WK[k];
+        n[i] = A[i] * s;
+    }
+}
+
+/* One stochastic collision at one site, with force density F (Sec. "D3Q19
+ * model II/III", Sec. "External forces"):
+ *   1. m_k = sum_i e_ki n_i;  rho = m_0;  j = sum_i n_i c_i + F/2
+ *      (eq. special_choice_momentum_density);  u = j / rho;
+ *   2. n^eq(rho, u) from eq. original_equil_distrib, m^eq = E n^eq;
+ *   3. for the non-conserved modes k >= 4 (eq. lco_update and
+ *      eq. stochupdaterule1 with m-hat = m / sqrt(w_k mu rho),
+ *      eq. normalized_mk):
+ *        m*_k = m^eq_k + gamma_k (m_k - m^eq_k)
+ *               + sqrt(w_k mu rho_n) sqrt(1 - gamma_k^2) r_k,
+ *      mu = kT / c_s^2 (eq. EOS2 and the kT = mu b^3 c_s^2 relation), with
+ *      r_k the unit Gaussians g[k-4]; the conserved modes are unchanged;
+ *   4. back-transformation to populations;
+ *   5. add the forcing term Delta''_i of Sec. "External forces" with the
+ *      second moment Sigma of eq. moment_two_external_force.
+ * `g` may be NULL when kT = 0.  The result is written to nstar. */
+void orc_collide_site(const orc_params *p, const double n[Q], const double F[3], const double *gnoise,
+                      double nstar[Q])
+{
+    init_tables();
+    double gam[Q];
+    mode_gammas(p, gam);
+
+    double m[Q];
+    orc_moments_site(n, m);
+    const double rho = m[0];
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (m[1 + a] + 0.5 * F[a]) / rho;
+
+    double neq[Q], meq[Q];
+    orc_equilibrium(rho, u, neq);
+    orc_moments_site(neq, meq);
+
+    const double mu = p->kT / CS2;
+    const double rho_n = p->noise_rho0 ? p->rho0 : rho;
+    double mstar[Q];
+    for (int k = 0; k < Q; ++k) {
+        if (k < 4) {
+            mstar[k] = m[k];
+            continue;
+        }
+        mstar[k] = meq[k] + gam[k] * (m[k] - meq[k]);
+        if (p->kT > 0.0) {
+            const double phi = sqrt(1.0 - gam[k] * gam[k]);
+            mstar[k] += sqrt(WK[k] * mu * rho_n) * phi * gnoise[k - 4];
+        }
+    }
+    orc_back_site(mstar, nstar);
+
+    /* Forcing term Delta''_i (Sec. "External forces", h = 1). */
+    const double uf = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    double sig[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double dab = (a == b) ? 1.0 : 0.0;
+            sig[a][b] = 0.5 * (1.0 + p->gamma_shear) * (u[a] * F[b] + u[b] * F[a] - (2.0 / 3.0) * uf * dab) +
+                        (1.0 / 3.0) * (1.0 + p->gamma_bulk) * uf * dab;
+        }
+    for (int i = 0; i < Q; ++i) {
+        double fc = 0.0, sc = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            fc += F[a] * CV[i][a];
+            for (int b = 0; b < 3; ++b) {
+                const double dab = (a == b) ? 1.0 : 0.0;
+                sc += sig[a][b] * (CV[i][a] * CV[i][b] - CS2 * dab);
+            }
+        }
+        nstar[i] += A[i] * (fc / CS2 + sc / (2.0 * CS2 * CS2));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole-lattice operations                                                  */
+/* ------------------------------------------------------------------------ */
+
+static int64_t site_index(const orc_params *p, int x, int y, int z)
+{
+    return (int64_t)x + (int64_t)p->nx * ((int64_t)y + (int64_t)p->ny * (int64_t)z);
+}
+
+static int wrap(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Initialise every site to n^eq(rho(r), u(r)).  rho may be NULL (rho0);
+ * u may be NULL (rest).  u is laid out [3][N]. */
+void orc_init_equilibrium(const orc_params *p, const double *rho, const double *u, double *n)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    for (int64_t s = 0; s < N; ++s) {
+        const double r = rho ? rho[s] : p->rho0;
+        double v[3] = {0.0, 0.0, 0.0};
+        if (u)
+            for (int a = 0; a < 3; ++a) v[a] = u[a * N + s];
+        double neq[Q];
+        orc_equilibrium(r, v, neq);
+        for (int i = 0; i < Q; ++i) n[i * N + s] = neq[i];
+    }
+}
+
+/* One lattice-Boltzmann time step, eq. LBE: collide at every site with force
+ * density g + extra(r) (extra may be NULL, layout [3][N]), then stream
+ * n_i(r + c_i, t+1) = n*_i(r, t) with periodic wrap.  `step` keys the noise.
+ * `work` is caller scratch of 19*N doubles.  Parity pinned by the shear-wave,
+ * Kolmogorov, conservation and noise-variance tests. */
+void orc_step(const orc_params *p, double *n, double *work, const double *extra, uint32_t step)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < N; ++s) {
+        double ns[Q], nst[Q], F[3], gn[16];
+        for (int i = 0; i < Q; ++i) ns[i] = n[i * N + s];
+        for (int a = 0; a < 3; ++a) F[a] = p->g[a] + (extra ? extra[a * N + s] : 0.0);
+        if (p->kT > 0.0) orc_fluid_normals(p->seed, (uint32_t)s, step, p->box, gn);
+        orc_collide_site(p, ns, F, gn, nst);
+        for (int i = 0; i < Q; ++i) work[i * N + s] = nst[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const int64_t s = site_index(p, x, y, z);
+                for (int i = 0; i < Q; ++i) {
+                    const int64_t d = site_index(p, wrap(x + CV[i][0], p->nx), wrap(y + CV[i][1], p->ny),
+                                                 wrap(z + CV[i][2], p->nz));
+                    n[i * N + d] = work[i * N + s];
+                }
+            }
+}
+
+/* nsteps consecutive steps starting at step counter `step0`, no particles. */
+void orc_run(const orc_params *p, double *n, int32_t nsteps, uint32_t step0)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    double *work = (double *)malloc(sizeof(double) * Q * (size_t)N);
+    for (int32_t t = 0; t < nsteps; ++t) orc_step(p, n, work, NULL, step0 + (uint32_t)t);
+    free(work);
+}
+
+/* Density and velocity at every site: rho = sum n, u = (sum n c + g/2)/rho
+ * (eq. special_choice_momentum_density with the uniform body force only).
+ * u is laid out [3][N]. */
+void orc_fields(const orc_params *p, const double *n, double *rho, double *u)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    for (int64_t s = 0; s < N; ++s) {
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < Q; ++i) {
+            const double v = n[i * N + s];
+            r += v;
+            for (int a = 0; a < 3; ++a) j[a] += v * CV[i][a];
+        }
+        rho[s] = r;
+        for (int a = 0; a < 3; ++a) u[a * N + s] = (j[a] + 0.5 * p->g[a]) / r;
+    }
+}
+
+/* Total mass and momentum: out = {sum rho, sum j_x, sum j_y, sum j_z}, with
+ * j = sum_i n_i c_i (no force shift). */
+void orc_totals(const orc_params *p, const double *n, double out[4])
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    double M = 0.0, P[3] = {0.0, 0.0, 0.0};
+    for (int64_t s = 0; s < N; ++s)
+        for (int i = 0; i < Q; ++i) {
+            const double v = n[i * N + s];
+            M += v;
+            for (int a = 0; a < 3; ++a) P[a] += v * CV[i][a];
+        }
+    out[0] = M;
+    out[1] = P[0];
+    out[2] = P[1];
+    out[3] = P[2];
+}
+
+/* All 19 moments at every site, layout [19][N]. */
+void orc_mode_field(const orc_params *p, const double *n, double *m)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    for (int64_t s = 0; s < N; ++s) {
+        double ns[Q], ms[Q];
+        for (int i = 0; i < Q; ++i) ns[i] = n[i * N + s];
+        orc_moments_site(ns, ms);
+        for (int k = 0; k < Q; ++k) m[k * N + s] = ms[k];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Point-particle coupling (Sec. "Force coupling", "Interpolating functions")*/
+/* ------------------------------------------------------------------------ */
+
+/* Two-point interpolation kernel phi_2 of eq. 2point. */
+static double phi2(double r)
+{
+    const double a = fabs(r);
+    return a < 1.0 ? 1.0 - a : 0.0;
+}
+
+/* The 8 lattice nodes around position R (periodic box) and their weights
+ * Delta(r - R) = phi2(x) phi2(y) phi2(z) (eq. Delta).  Nodes sit at integer
+ * coordinates; the stencil starts at floor(R) with periodic wrap. */
+void orc_stencil(const orc_params *p, const double R[3], int64_t node[8], double wgt[8])
+{
+    const int L[3] = {p->nx, p->ny, p->nz};
+    int base[3];
+    double frac[3];
+    for (int a = 0; a < 3; ++a) {
+        const double f = floor(R[a]);
+        frac[a] = R[a] - f;
+        base[a] = wrap((int)(f - (double)L[a] * floor(f / (double)L[a])), L[a]);
+    }
+    int q = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                node[q] = site_index(p, wrap(base[0] + dx, L[0]), wrap(base[1] + dy, L[1]), wrap(base[2] + dz, L[2]));
+                wgt[q] = phi2(frac[0] - dx) * phi2(frac[1] - dy) * phi2(frac[2] - dz);
+                ++q;
+            }
+}
+
+/* Particle half of one coupled time step (Sec. "Force coupling": the
+ * Trotter splitting eq. pTrotter, the momentum update
+ * eq. langevin_momentum_update, the interpolation eq. ufluid_discrete and
+ * the reaction force eq. ftotal):
+ *   1. R' = R + (h/2) P/m for every bead;
+ *   2. conservative forces F^c at R' from harmonic bonds
+ *      F = -k (|d| - r0) d/|d|  (bond list, pairs (a,b), d = R_b - R_a);
+ *   3. u_b = sum over the 8 nodes of Delta * u(node), u(node) from the
+ *      current (pre-collision) populations n: u = (sum n c + g/2)/rho;
+ *   4. P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta, with
+ *      C1 = exp(-zeta h/m), C2 = (m/zeta)(1 - C1),
+ *      C3 = sqrt(m kT (1 - exp(-2 zeta h/m)));
+ *   5. the fluid receives the momentum the bead exchanged with it,
+ *      I = -(P'' - P - h F^c), spread as force density I Delta / h into
+ *      `force` (layout [3][N], accumulated);
+ *   6. R = R' + (h/2) P''/m, P = P''.
+ * pos, mom: [3*nb] interleaved (x,y,z per bead), unwrapped positions.
+ * `step` keys the bead noise.  Parity pinned by the frozen-fluid OU tests,
+ * the partition-of-unity and transpose tests, and the total-momentum test. */
+void orc_couple(const orc_params *p, const double *n, uint32_t step, int32_t nb, double *pos, double *mom,
+                const double *mass, const double *zeta, int32_t nbonds, const int32_t *bonds, double kbond,
+                double r0, double *force)
+{
+    init_tables();
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const double h = 1.0;
+    double *half = (double *)malloc(sizeof(double) * 3 * (size_t)(nb > 0 ? nb : 1));
+    double *fc = (double *)calloc(3 * (size_t)(nb > 0 ? nb : 1), sizeof(double));
+
+    for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < 3; ++a) half[3 * b + a] = pos[3 * b + a] + 0.5 * h * mom[3 * b + a] / mass[b];
+
+    for (int q = 0; q < nbonds; ++q) {
+        const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = half[3 * ib + a] - half[3 * ia + a];
+            r2 += d[a] * d[a];
+        }
+        const double r = sqrt(r2);
+        if (r == 0.0) continue;
+        const double mag = -kbond * (r - r0) / r;
+        for (int a = 0; a < 3; ++a) {
+            fc[3 * ib + a] += mag * d[a];
+            fc[3 * ia + a] -= mag * d[a];
+        }
+    }
+
+    for (int b = 0; b < nb; ++b) {
+        int64_t node[8];
+        double wgt[8];
+        orc_stencil(p, &half[3 * b], node, wgt);
+        double ub[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 8; ++q) {
+            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < Q; ++i) {
+                const double v = n[i * N + node[q]];
+                r += v;
+                for (int a = 0; a < 3; ++a) j[a] += v * CV[i][a];
+            }
+            for (int a = 0; a < 3; ++a) ub[a] += wgt[q] * (j[a] + 0.5 * p->g[a]) / r;
+        }
+        const double m = mass[b], z = zeta[b];
+        double C1, C2, C3;
+        if (z > 0.0) {
+            C1 = exp(-z * h / m);
+            C2 = (m / z) * (1.0 - C1);
+            C3 = sqrt(m * p->kT * (1.0 - exp(-2.0 * z * h / m)));
+        } else {
+            C1 = 1.0;
+            C2 = h;
+            C3 = 0.0;
+        }
+        double th[3] = {0.0, 0.0, 0.0};
+        if (p->kT > 0.0 && z > 0.0) orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
+        double Pn[3], I[3];
+        for (int a = 0; a < 3; ++a) {
+            Pn[a] = C1 * mom[3 * b + a] + C2 * (fc[3 * b + a] + z * ub[a]) + C3 * th[a];
+            I[a] = -(Pn[a] - mom[3 * b + a] - h * fc[3 * b + a]);
+        }
+        for (int q = 0; q < 8; ++q)
+            for (int a = 0; a < 3; ++a) force[a * N + node[q]] += wgt[q] * I[a] / h;
+        for (int a = 0; a < 3; ++a) {
+            mom[3 * b + a] = Pn[a];
+            pos[3 * b + a] = half[3 * b + a] + 0.5 * h * Pn[a] / m;
+        }
+    }
+    free(half);
+    free(fc);
+}
+
+/* One full coupled step (particle update, spreading, then one LB step with
+ * the spread force in the collision).  `work` is 19*N doubles and `force`
+ * is 3*N doubles of caller scratch. */
+void orc_coupled_step(const orc_params *p, double *n, double *work, double *force, uint32_t step, int32_t nb,
+                      double *pos, double *mom, const double *mass, const double *zeta, int32_t nbonds,
+                      const int32_t *bonds, double kbond, double r0)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    memset(force, 0, sizeof(double) * 3 * (size_t)N);
+    orc_couple(p, n, step, nb, pos, mom, mass, zeta, nbonds, bonds, kbond, r0, force);
+    orc_step(p, n, work, force, step);
+}
