@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the fluctuating D3Q19 hot path on one MI355X.
+
+One step = the whole hot path on the 256^3 workload: bead half-drift, bond
+forces, trilinear interpolation, Langevin momentum update and spreading for
+64 chains x 32 beads, then the fused pull-stream + MRT collision with thermal
+noise and forcing over all 16.8M sites, the re-collision of the bead-touched
+nodes, and the fused FP64 mass/momentum totals.  Inputs are synthetic
+(seeded), resident in HBM before the timed region.
+
+Prints ONE JSON line (the driver's contract) with, beside the throughput:
+  roofline      the dominant kernel (fused stream-collide): algorithmic bytes
+                (19 reads + 19 writes of a 4-byte population per site) per
+                launch over its average launch duration, timed with events
+                on the launch stream, against the 8 TB/s HBM peak;
+  cpu_baseline  the FP64 oracle on the host cores, timed on a bounded sample
+                of the same workload (a few coupled steps of the full box).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % of HBM peak, FP32 vs BF16-storage vs batched; backward MLUPS at 1e-6 err"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_256.json")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0803_2826_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--L", type=int, default=256, help="box edge (default: the 256^3 workload)")
+    ap.add_argument("--kernel-steps", type=int, default=200, help="launches timed for the dominant kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    return ap.parse_args()
+
+
+def cpu_baseline(L: int, n_chains: int, length: int, steps: int):
+    """FP64 oracle on the host: `steps` coupled steps of the same workload after
+    one untimed warm-up step."""
+    import numpy as np
+
+    import oracle
+    from paper_0803_2826_amd.inputs import random_walk_chains
+
+    oracle.build()
+    pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed=0)
+    nb = pos.shape[0]
+    p = oracle.Params(nx=L, ny=L, nz=L, kT=1e-4, seed=0)
+    beads = oracle.Beads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, 10.0, 1.0)
+    n = oracle.init_equilibrium(p)
+    oracle.coupled_step(p, n, 0, beads)
+    t0 = time.perf_counter()
+    for t in range(steps):
+        oracle.coupled_step(p, n, 1 + t, beads)
+    dt = time.perf_counter() - t0
+    del n
+    return {
+        "value": L ** 3 * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} coupled steps (after 1 warm-up) of the full {L}^3 box with {n_chains}x{length} beads, "
+                  f"FP64, OpenMP over sites; {dt:.1f} s",
+    }
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
+              f"design-only in this build.", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_0803_2826_amd import lattice
+    from paper_0803_2826_amd.inputs import random_walk_chains
+
+    torch.cuda.set_device(0)
+    L = args.L
+    n_chains, length = 64, 32
+    N = L ** 3
+    pd = lattice.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=1e-4, seed=0, track_totals=True)
+    lat = lattice.Lattice(pd)
+    lat.init_equilibrium()
+    pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed=0)
+    nb = pos.shape[0]
+    beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, 10.0, 1.0)
+    tot0 = lat.totals(exact=True)
+    stream = lat.stream
+
+    for _ in range(args.warmup):
+        lat.coupled_step(beads)
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        lat.coupled_step(beads)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+    mlups = N * args.steps / (ms_per_step * args.steps * 1e-3) / 1e6
+    print(f"# timed {args.steps} steps: {ms_per_step:.4f} ms/step, {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    tot1 = lat.totals()
+    tot1x = lat.totals(exact=True)
+    lat.sync()
+
+    # dominant kernel: back-to-back fused stream-collide launches (no bead
+    # force pending, so each lb_step(1) is exactly one launch of that kernel)
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    lat.step(5)
+    torch.cuda.synchronize()
+    k0.record(stream)
+    for _ in range(args.kernel_steps):
+        lat.step(1)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = k0.elapsed_time(k1) / args.kernel_steps
+    alg_bytes = 2 * 19 * 4 * N
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == source_hash() and tr.get("L") == L:
+            traffic = tr.get("traffic_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_stream_collide<f32,thermal,totals>", "kernel_ms": round(kern_ms, 5),
+                "alg_bytes_per_launch": alg_bytes}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(L, n_chains, length, args.cpu_steps)
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fluctuating D3Q19 MRT {L}^3 periodic, FP32 shifted storage, kT=1e-4, tau=1, "
+                               f"{n_chains} chains x {length} beads (k=10, r0=1, zeta=20, m=1), "
+                               f"trilinear interpolation + spreading every step",
+                   "sites": N, "beads": nb, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mass_drift_rel": (tot1x[0] - tot0[0]) / tot0[0],
+        "fused_vs_exact_totals_abs": max(abs(a - b) for a, b in zip(tot1, tot1x)),
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

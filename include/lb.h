@@ -1,0 +1,201 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) fluctuating lattice-Boltzmann library
+ * (liblbmi.so).
+ *
+ * The library advances a periodic D3Q19 fluid with the stochastic
+ * multiple-relaxation-time collision of Duenweg & Ladd ("Lattice Boltzmann
+ * simulations of soft matter systems": Sec. "D3Q19 model I-III", Sec.
+ * "External forces") and couples point particles to it by friction
+ * (Sec. "Force coupling", Sec. "Interpolating functions").
+ *
+ * Units are lattice units: spacing b = 1, time step h = 1, c_s^2 = 1/3, so
+ * the mass density of one LB particle is mu = kT / c_s^2 = 3 kT.
+ *
+ * Conventions shared by every entry point:
+ *   - Velocity order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 =
+ *     (+,+,0),(-,-,0),(+,-,0),(-,+,0),(+,0,+),(-,0,-),(+,0,-),(-,0,+),
+ *     (0,+,+),(0,-,-),(0,+,-),(0,-,+).  Opposite directions are adjacent.
+ *   - Site index s = x + nx*(y + ny*z); population arrays are [19][N]
+ *     (structure of arrays), vector fields are [3][N].
+ *   - "The state" is the pre-collision population n_i(r,t) of eq. LBE.
+ *     One step is collision at every site followed by streaming
+ *     n_i(r + c_i, t+1) = n*_i(r, t).
+ *   - All pointers passed to the library are DEVICE pointers on the device
+ *     that was current at lb_create, unless a parameter says "host".
+ *     The caller owns them; the library never frees or retains them past
+ *     the call (stream-ordered: the work may still be in flight on the
+ *     context stream when the call returns).
+ *   - All work is enqueued on the stream given to lb_create, in call order.
+ *     Calls that return data to host memory synchronise that stream.
+ *   - Every function returns LB_OK (0) or a negative status.  Argument errors
+ *     are detected on the host before anything is enqueued and leave the
+ *     context unchanged.  Errors found on the device (non-finite
+ *     populations) latch and are returned by the next synchronising call
+ *     (lb_totals, lb_mode_stats, lb_sync).  lb_last_error() gives a message.
+ *   - A context is not thread-safe.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,       /* invalid argument (shape, parameter range, NULL) */
+    LB_ENOMEM = -2,       /* device allocation failed */
+    LB_EDEVICE = -3,      /* HIP runtime error (message in lb_last_error) */
+    LB_ENONFINITE = -4,   /* a NaN or Inf population was seen on the device */
+    LB_ESTATE = -5,       /* call order violated (e.g. two lb_couple without lb_step) */
+    LB_EUNSUPPORTED = -6  /* valid request the library does not implement */
+};
+
+/* Storage type of populations (the collision always computes in FP32). */
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16 = 2, LB_F16 = 3 } lb_dtype;
+
+/* Fluid parameters.
+ * gamma_*: eigenvalues of the linearised collision operator per mode group
+ *   (eq. lco_update; groups per Sec. "D3Q19 model II": bulk mode 4, shear
+ *   modes 5-9, kinetic modes 10-12, 13-15, 16, 17-18).  Stability requires
+ *   |gamma| <= 1 (text after eq. lco_update); gamma_shear and gamma_bulk must
+ *   satisfy |gamma| < 1 so that the viscosities of eq. shearviscosity /
+ *   eq. bulkviscosity are finite.  nu = (1/6)(1+gamma_shear)/(1-gamma_shear).
+ * kT: temperature; the noise of eq. stochupdaterule1 has amplitude
+ *   sqrt(w_k mu rho (1 - gamma_k^2)) per mode k >= 4 (eq. detailedbalance1,
+ *   eq. normalized_mk), mu = 3 kT.  kT = 0 gives the deterministic model.
+ * body_force: uniform force density g (Sec. "External forces").
+ * seed: key of the Philox4x32-10 generator (noise keyed by site, step, mode).
+ * storage: LB_F32, LB_BF16 or LB_F16; populations are stored as deviations
+ *   n_i - a_i rho0 (FP16 additionally scaled by 2^8 before rounding).
+ * noise_rho0: 0 = noise amplitude uses the local density rho = m_0,
+ *   1 = uses rho0.
+ * block: threads per block of the fused step kernel (64..1024, multiple of
+ *   64); 0 selects 256.
+ * track_totals: 1 = the step kernel also accumulates FP64 totals of mass and
+ *   momentum every step (read with lb_totals); 0 = totals are computed on
+ *   demand by lb_totals with a separate pass. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t storage;
+    double rho0;
+    double gamma_shear, gamma_bulk;
+    double gamma_3a, gamma_3b, gamma_4a, gamma_4b;
+    double kT;
+    double body_force[3];
+    uint64_t seed;
+    int32_t noise_rho0;
+    int32_t block;
+    int32_t track_totals;
+    int32_t box_id;        /* fourth Philox counter word (replica index) */
+} lb_params;
+
+/* Point particles with harmonic bonds (Sec. "Force coupling").
+ * All arrays are device FP64 (bonds int32), caller-owned:
+ *   pos  [n][3]  unwrapped positions (in/out)
+ *   mom  [n][3]  momenta p (in/out)
+ *   mass [n]     m_i > 0
+ *   zeta [n]     friction Gamma_i >= 0 (eq. fdrag)
+ *   bonds [nbonds][2]  bead index pairs, potential (k_bond/2)(|d| - r0)^2 */
+typedef struct {
+    int32_t n;
+    int32_t nbonds;
+    double *pos;
+    double *mom;
+    const double *mass;
+    const double *zeta;
+    const int32_t *bonds;
+    double k_bond;
+    double r0;
+} lb_beads;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Create a context: allocates two population buffers (2 * 19 * N * storage
+ * bytes) and small bookkeeping on the current device, enqueues on `stream`
+ * (a hipStream_t; NULL = the null stream).  The state is uninitialised until
+ * lb_init_equilibrium or lb_set_populations.  The step counter starts at 0.
+ * Errors: LB_EINVAL (any extent < 2, N >= 2^31, |gamma| out of range,
+ * kT < 0, rho0 <= 0, unknown storage, bad block), LB_ENOMEM, LB_EDEVICE. */
+int lb_create(const lb_params *params, void *stream, lb_ctx **out);
+
+/* Release all device memory of the context (synchronises its stream). */
+int lb_destroy(lb_ctx *ctx);
+
+/* Set every site to the equilibrium n^eq(rho(r), u(r)) of
+ * eq. original_equil_distrib.  rho: device FP64 [N] or NULL (rho0);
+ * u: device FP64 [3][N] or NULL (rest). */
+int lb_init_equilibrium(lb_ctx *ctx, const double *rho, const double *u);
+
+/* Copy the state in / out.  src/dst: device arrays [19][N] of type `dtype`
+ * (LB_F64 or LB_F32).  shifted = 0: full populations n_i; shifted = 1:
+ * deviations n_i - a_i rho0.  Storage rounding applies on the way in. */
+int lb_set_populations(lb_ctx *ctx, const void *src, int32_t dtype, int32_t shifted);
+int lb_get_populations(lb_ctx *ctx, void *dst, int32_t dtype, int32_t shifted);
+
+/* Advance nsteps >= 0 time steps (eq. LBE with the collision of
+ * eq. coll_operator_plus_noise_plus_force, noise keyed by the step counter).
+ * A force spread by a preceding lb_couple enters the first of these steps
+ * only; the counter increases by nsteps. */
+int lb_step(lb_ctx *ctx, int32_t nsteps);
+
+/* Particle half of one coupled time step (Sec. "Force coupling": half
+ * drift, harmonic bond forces at the half-step positions, trilinear
+ * interpolation of u (eq. ufluid_discrete with the two-point kernel of
+ * eq. 2point), the exact Langevin momentum update
+ * eq. langevin_momentum_update, spreading of the exchanged impulse to the
+ * 8 surrounding nodes (eq. ftotal), second half drift).  The interpolated
+ * velocity is u = (sum_i n_i c_i + g/2)/rho from the current state.  The
+ * spread force is applied by the next lb_step.  Bead noise is keyed by
+ * (bead index, step counter).  Errors: LB_EINVAL (n < 0, NULL arrays with
+ * n > 0), LB_ESTATE (a previous lb_couple's force not yet consumed). */
+int lb_couple(lb_ctx *ctx, const lb_beads *beads);
+
+/* Density and velocity of the current state: rho = sum_i n_i,
+ * u = (sum_i n_i c_i + g/2) / rho (eq. special_choice_momentum_density with
+ * the uniform body force).  rho: device FP64 [N]; u: device FP64 [3][N];
+ * either may be NULL. */
+int lb_moments(lb_ctx *ctx, double *rho, double *u);
+
+/* FP64 totals of the current state, host out[4] = {sum rho, sum j_x, sum j_y,
+ * sum j_z} with j = sum_i n_i c_i.  With track_totals the values come from
+ * the last step's fused accumulation (stored, rounded populations);
+ * otherwise (or before any step) from a full reduction pass.  Synchronises;
+ * returns LB_ENONFINITE if a non-finite population was seen. */
+int lb_totals(lb_ctx *ctx, double out[4]);
+
+/* Same as lb_totals but always runs the full reduction pass. */
+int lb_totals_exact(lb_ctx *ctx, double out[4]);
+
+/* Per-mode statistics of the current state: host var[19] =
+ * mean over sites of (m_k - mean m_k)^2 with m_k = sum_i e_ki n_i (Table 1
+ * basis).  At equilibrium var[k] = mu w_k rho0 (variance of eq. Pdistneq).
+ * Synchronises. */
+int lb_mode_stats(lb_ctx *ctx, double var[19]);
+
+/* The fifteen unit Gaussians r_k (k = 4..18, eq. stochupdaterule1) that the
+ * collision at sites site0 .. site0+count-1 draws at step `step`, with this
+ * context's seed and box id.  out: device FP32 [count][15].  Lets a caller
+ * check the device generator against an independent implementation.
+ * Errors: LB_EINVAL (out NULL, site range beyond N). */
+int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, float *out);
+
+/* Synchronise the context stream and report latched device errors. */
+int lb_sync(lb_ctx *ctx);
+
+/* Step counter (keys the noise).  lb_set_step_count lets a restarted run
+ * continue the same random stream. */
+uint64_t lb_step_count(const lb_ctx *ctx);
+int lb_set_step_count(lb_ctx *ctx, uint64_t step);
+
+/* Message for the last error on this context ("" if none). ctx may be NULL
+ * (then: the last lb_create failure). */
+const char *lb_last_error(const lb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

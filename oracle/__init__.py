@@ -129,6 +129,8 @@ def lib():
                                  ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double, dp]
         L.orc_coupled_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
                                        ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double]
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals",
                      "orc_equilibrium", "orc_moments_site", "orc_back_site", "orc_collide_site",
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
@@ -136,6 +138,10 @@ def lib():
             getattr(L, name).restype = None
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _dp(a: np.ndarray):

@@ -30,11 +30,24 @@
  * Parity status of every exported function is stated at its definition.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define Q 19
+
+/* Number of threads the whole-lattice loops use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Lattice tables (Sec. "D3Q19 model I/II", Table 1)                         */

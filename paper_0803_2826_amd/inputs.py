@@ -1,0 +1,56 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke
+check.  Holds none of the method's arithmetic: only initial fields and bead
+configurations, drawn with numpy's PCG64 generator from a fixed seed.
+
+Recipes (lattice units):
+  shear_wave      rho = rho0, u_flow(coord) = A sin(2 pi coord / L)
+  random_walk_chains
+                  n_chains chains of `length` beads; each chain starts at a
+                  uniform random point of the box and takes unit-length steps
+                  in uniformly random directions (isotropic unit vectors);
+                  positions are unwrapped; momenta zero; bonds join
+                  consecutive beads of a chain.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def shear_wave(nx: int, ny: int, nz: int, amp: float = 0.01, flow_axis: int = 0, var_axis: int = 2):
+    """Velocity field [3, nz, ny, nx] of a sinusoidal shear wave."""
+    dims = (nx, ny, nz)
+    L = dims[var_axis]
+    prof = amp * np.sin(2.0 * np.pi * np.arange(L) / L)
+    shape = [1, 1, 1]
+    shape[2 - var_axis] = L
+    u = np.zeros((3, nz, ny, nx))
+    u[flow_axis] = np.broadcast_to(prof.reshape(shape), (nz, ny, nx))
+    return u
+
+
+def random_velocity(nx: int, ny: int, nz: int, scale: float, seed: int):
+    rng = np.random.default_rng(seed)
+    return rng.normal(scale=scale, size=(3, nz, ny, nx))
+
+
+def random_walk_chains(n_chains: int, length: int, box, seed: int):
+    """Returns pos [n,3], mom [n,3], bonds [n_chains*(length-1), 2] (int32)."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=float)
+    pos = np.zeros((n_chains * length, 3))
+    bonds = []
+    for c in range(n_chains):
+        start = rng.uniform(0.0, 1.0, size=3) * L
+        steps = rng.normal(size=(length - 1, 3))
+        steps /= np.linalg.norm(steps, axis=1, keepdims=True)
+        chain = np.vstack([start, start + np.cumsum(steps, axis=0)])
+        pos[c * length:(c + 1) * length] = chain
+        for k in range(length - 1):
+            bonds.append((c * length + k, c * length + k + 1))
+    bonds = np.asarray(bonds, dtype=np.int32).reshape(-1, 2)
+    return pos, np.zeros_like(pos), bonds
+
+
+def uniform_beads(n: int, box, seed: int):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(n, 3)) * np.asarray(box, dtype=float)

@@ -1,0 +1,215 @@
+"""Python face of liblbmi: a periodic fluctuating D3Q19 box with point beads.
+
+PyTorch supplies device memory (CUDA/HIP tensors) and the stream; every
+numerical step is a HIP kernel behind the C ABI of include/lb.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import LB_BF16, LB_F16, LB_F32, LB_F64, check
+
+Q = 19
+_STORAGE = {"f32": LB_F32, "bf16": LB_BF16, "f16": LB_F16, LB_F32: LB_F32, LB_BF16: LB_BF16, LB_F16: LB_F16}
+
+
+@dataclass
+class FluidParams:
+    """Fluid parameters (lattice units).  nu = (1/6)(1+gamma_shear)/(1-gamma_shear)."""
+    nx: int
+    ny: int
+    nz: int
+    storage: str = "f32"
+    rho0: float = 1.0
+    gamma_shear: float = 0.0
+    gamma_bulk: float = 0.0
+    gamma_3a: float = 0.0
+    gamma_3b: float = 0.0
+    gamma_4a: float = 0.0
+    gamma_4b: float = 0.0
+    kT: float = 0.0
+    body_force: tuple = (0.0, 0.0, 0.0)
+    seed: int = 0
+    noise_rho0: bool = False
+    block: int = 0
+    track_totals: bool = True
+    box_id: int = 0
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def to_c(self) -> _lib.lb_params:
+        p = _lib.lb_params()
+        p.nx, p.ny, p.nz = self.nx, self.ny, self.nz
+        p.storage = _STORAGE[self.storage]
+        p.rho0 = self.rho0
+        p.gamma_shear, p.gamma_bulk = self.gamma_shear, self.gamma_bulk
+        p.gamma_3a, p.gamma_3b, p.gamma_4a, p.gamma_4b = self.gamma_3a, self.gamma_3b, self.gamma_4a, self.gamma_4b
+        p.kT = self.kT
+        for a in range(3):
+            p.body_force[a] = float(self.body_force[a])
+        p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        p.noise_rho0 = 1 if self.noise_rho0 else 0
+        p.block = int(self.block)
+        p.track_totals = 1 if self.track_totals else 0
+        p.box_id = int(self.box_id)
+        return p
+
+
+class DeviceBeads:
+    """Bead state on the device (float64 tensors, positions unwrapped)."""
+
+    def __init__(self, pos, mom, mass, zeta, bonds=None, k_bond=0.0, r0=1.0, device="cuda"):
+        dev = torch.device(device)
+        self.pos = torch.as_tensor(pos, dtype=torch.float64, device=dev).reshape(-1, 3).contiguous()
+        self.mom = torch.as_tensor(mom, dtype=torch.float64, device=dev).reshape(-1, 3).contiguous()
+        self.mass = torch.as_tensor(mass, dtype=torch.float64, device=dev).reshape(-1).contiguous()
+        self.zeta = torch.as_tensor(zeta, dtype=torch.float64, device=dev).reshape(-1).contiguous()
+        if bonds is None:
+            bonds = torch.zeros((0, 2), dtype=torch.int32)
+        self.bonds = torch.as_tensor(bonds, dtype=torch.int32, device=dev).reshape(-1, 2).contiguous()
+        self.k_bond = float(k_bond)
+        self.r0 = float(r0)
+        n = self.pos.shape[0]
+        if self.mom.shape[0] != n or self.mass.shape[0] != n or self.zeta.shape[0] != n:
+            raise ValueError("bead arrays must have matching lengths")
+
+    @property
+    def n(self) -> int:
+        return self.pos.shape[0]
+
+    def to_c(self) -> _lib.lb_beads:
+        b = _lib.lb_beads()
+        b.n = self.n
+        b.nbonds = self.bonds.shape[0]
+        b.pos = self.pos.data_ptr()
+        b.mom = self.mom.data_ptr()
+        b.mass = self.mass.data_ptr()
+        b.zeta = self.zeta.data_ptr()
+        b.bonds = self.bonds.data_ptr() if self.bonds.numel() else None
+        b.k_bond = self.k_bond
+        b.r0 = self.r0
+        return b
+
+
+class Lattice:
+    """One periodic box on the current GPU, enqueued on torch's current stream."""
+
+    def __init__(self, params: FluidParams, stream: torch.cuda.Stream | None = None):
+        self.L = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbmi needs a GPU (torch.cuda.is_available() is False)")
+        self.params = params
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._p = params.to_c()
+        ctx = ctypes.c_void_p()
+        rc = self.L.lb_create(ctypes.byref(self._p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != 0:
+            raise _lib.LBError(rc, self.L.lb_last_error(None).decode())
+        self.ctx = ctx
+
+    # -- lifetime
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            self.L.lb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int) -> None:
+        check(rc, self.ctx)
+
+    @property
+    def N(self) -> int:
+        return self.params.N
+
+    def _dev(self, t: torch.Tensor, dtype) -> torch.Tensor:
+        t = torch.as_tensor(t, dtype=dtype, device=self.device).contiguous()
+        return t
+
+    # -- state
+    def init_equilibrium(self, rho=None, u=None) -> None:
+        r = self._dev(rho, torch.float64).reshape(-1) if rho is not None else None
+        uu = self._dev(u, torch.float64).reshape(-1) if u is not None else None
+        if r is not None and r.numel() != self.N:
+            raise ValueError("rho must have N elements")
+        if uu is not None and uu.numel() != 3 * self.N:
+            raise ValueError("u must have 3N elements")
+        self._check(self.L.lb_init_equilibrium(self.ctx, r.data_ptr() if r is not None else None,
+                                               uu.data_ptr() if uu is not None else None))
+        self._keep = (r, uu)
+
+    def set_populations(self, n, shifted: bool = False) -> None:
+        t = torch.as_tensor(n, device=self.device)
+        if t.dtype not in (torch.float64, torch.float32):
+            t = t.to(torch.float64)
+        t = t.contiguous()
+        if t.numel() != Q * self.N:
+            raise ValueError("populations must have 19*N elements")
+        dt = LB_F64 if t.dtype == torch.float64 else LB_F32
+        self._check(self.L.lb_set_populations(self.ctx, t.data_ptr(), dt, 1 if shifted else 0))
+        self._keep = t
+
+    def get_populations(self, dtype=torch.float64, shifted: bool = False) -> torch.Tensor:
+        out = torch.empty((Q, self.params.nz, self.params.ny, self.params.nx), dtype=dtype, device=self.device)
+        dt = LB_F64 if dtype == torch.float64 else LB_F32
+        self._check(self.L.lb_get_populations(self.ctx, out.data_ptr(), dt, 1 if shifted else 0))
+        return out
+
+    # -- dynamics
+    def step(self, nsteps: int = 1) -> None:
+        self._check(self.L.lb_step(self.ctx, int(nsteps)))
+
+    def couple(self, beads: DeviceBeads) -> None:
+        b = beads.to_c()
+        self._check(self.L.lb_couple(self.ctx, ctypes.byref(b)))
+
+    def coupled_step(self, beads: DeviceBeads) -> None:
+        """Particle update + spreading, then one LB step (the paper's schedule)."""
+        self.couple(beads)
+        self.step(1)
+
+    # -- observables
+    def moments(self):
+        rho = torch.empty((self.params.nz, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+        u = torch.empty((3, self.params.nz, self.params.ny, self.params.nx), dtype=torch.float64,
+                        device=self.device)
+        self._check(self.L.lb_moments(self.ctx, rho.data_ptr(), u.data_ptr()))
+        return rho, u
+
+    def totals(self, exact: bool = False):
+        out = (ctypes.c_double * 4)()
+        fn = self.L.lb_totals_exact if exact else self.L.lb_totals
+        self._check(fn(self.ctx, out))
+        return [out[i] for i in range(4)]
+
+    def mode_stats(self):
+        out = (ctypes.c_double * 19)()
+        self._check(self.L.lb_mode_stats(self.ctx, out))
+        return [out[i] for i in range(19)]
+
+    def noise_sample(self, site0: int, count: int, step: int) -> torch.Tensor:
+        out = torch.empty((count, 15), dtype=torch.float32, device=self.device)
+        self._check(self.L.lb_noise_sample(self.ctx, int(site0), int(count), int(step), out.data_ptr()))
+        return out
+
+    def sync(self) -> None:
+        self._check(self.L.lb_sync(self.ctx))
+
+    @property
+    def step_count(self) -> int:
+        return int(self.L.lb_step_count(self.ctx))
+
+    @step_count.setter
+    def step_count(self, v: int) -> None:
+        self._check(self.L.lb_set_step_count(self.ctx, int(v)))

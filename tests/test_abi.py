@@ -1,0 +1,89 @@
+"""CPU checks of the C ABI: the built library exports every function that
+include/lb.h declares, the ctypes mirrors of lb_params / lb_beads have the
+same layout as the C structs, and the binding refuses to run without the
+library (no fallback path exists)."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb.h")
+LIB = os.path.join(ROOT, "paper_0803_2826_amd", "liblbmi.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"^(?:int|uint64_t|const char \*)\s*\*?(lb_\w+)\(", text, re.M)
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ("lb_create", "lb_step", "lb_couple", "lb_moments", "lb_totals", "lb_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("liblbmi.so not built")
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_declared_symbol():
+    from paper_0803_2826_amd import _lib
+    assert set(_lib.EXPORTS) == set(declared_functions())
+
+
+def test_struct_layout_matches_header():
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    from paper_0803_2826_amd import _lib
+    src = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "lb.h"
+#define F(S, m) printf(#S "." #m " %zu\n", offsetof(S, m));
+int main(void) {
+  printf("lb_params %zu\nlb_beads %zu\n", sizeof(lb_params), sizeof(lb_beads));
+  F(lb_params, storage) F(lb_params, rho0) F(lb_params, kT) F(lb_params, body_force) F(lb_params, seed)
+  F(lb_params, noise_rho0) F(lb_params, block) F(lb_params, track_totals) F(lb_params, box_id)
+  F(lb_beads, pos) F(lb_beads, mom) F(lb_beads, mass) F(lb_beads, zeta) F(lb_beads, bonds)
+  F(lb_beads, k_bond) F(lb_beads, r0)
+  return 0;
+}
+'''
+    d = tempfile.mkdtemp()
+    try:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "l")
+        subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), "-o", exe, c], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    vals = dict(line.rsplit(" ", 1) for line in out if line)
+    assert int(vals["lb_params"]) == ctypes.sizeof(_lib.lb_params)
+    assert int(vals["lb_beads"]) == ctypes.sizeof(_lib.lb_beads)
+    for key, v in vals.items():
+        if "." in key:
+            s, m = key.split(".")
+            cls = getattr(_lib, s)
+            assert getattr(cls, m).offset == int(v), key
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_0803_2826_amd import _lib
+    saved = _lib._lib
+    _lib._lib = None
+    try:
+        with pytest.raises(ImportError):
+            _lib.load(str(tmp_path / "missing.so"))
+    finally:
+        _lib._lib = saved
