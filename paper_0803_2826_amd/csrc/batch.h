@@ -1,0 +1,178 @@
+// Batched form: many independent periodic replica boxes of uneven size
+// advanced by ONE persistent launch per time step, replayable as a HIP graph.
+//
+// Layout: all boxes share two population buffers; box b owns the element
+// range [off_b, off_b + 19 N_b) of each ([19][N_b] structure of arrays).
+// Work list: the sites of each box are cut into tiles of blockDim sites; the
+// tile -> box table is built on the host.  Each block walks a contiguous chunk
+// of tiles, so it stays inside one box for long stretches; that is what lets
+// the ensemble-VACF accumulation (below) keep per-thread partial sums and
+// flush them only when the box changes.
+//
+// The step counter that keys the noise lives in device memory and is advanced
+// by a one-thread kernel after each step, so a captured sequence of launches
+// can be replayed unchanged.
+//
+// Ensemble velocity autocorrelation (sampled every step, pre-collision
+// momentum j = sum_i n_i c_i): for each box and each axis a, the lowest
+// Fourier mode k = 2 pi / L_a of the two momentum components transverse to
+// a, j_hat(k) = sum_r j(r) exp(-i k r_a) (6 complex amplitudes per box).  A
+// ring buffer of the last R samples per box gives
+// C_b(tau) += sum_modes Re[j_hat(t) conj(j_hat(t - tau))].  At gamma = 0 its
+// mean is N_b kT rho0 lambda(k)^tau, lambda = 1 - (2/3) sin^2(k/2)
+// (linear dynamics of eq. LBE with the equipartition of eq. Pdistneq).
+#pragma once
+
+#include "kernels.h"
+
+namespace lbmi {
+
+struct BoxDesc {
+    Geom geo;
+    uint64_t off;         // element offset of this box's [19][N_b] block
+    uint32_t box_id;      // fourth Philox counter word
+    uint32_t first_tile;  // index of the box's first tile in the work list
+    float inv_L[3];       // 1 / L_x, 1 / L_y, 1 / L_z
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const void *src;
+    void *dst;
+    const BoxDesc *boxes;
+    const uint32_t *tile_box;  // [ntiles] box index of each tile
+    uint32_t ntiles;
+    uint32_t chunk;            // tiles per block (contiguous)
+    CollideConst cc;           // `box` is replaced per tile
+    const uint32_t *step_ptr;  // device step counter
+    float *amp;                // [nbox][12] VACF accumulators (re, im of 6 modes)
+    int32_t *flags;
+};
+
+// Block-wide sum of 12 floats, atomically added to dst[0..11].  Every thread
+// of the block must call it (it synchronises).
+__device__ __forceinline__ void flush_amp12(float acc[12], float *dst)
+{
+    __shared__ float red[16][12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        float x = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        acc[c] = x;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) red[wid][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int nw = (blockDim.x + 63) >> 6;
+        float s = 0.f;
+        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+        atomicAdd(&dst[threadIdx.x], s);
+    }
+}
+
+template <int ST, bool THERMAL, bool VACF>
+__global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const uint32_t step = *a.step_ptr;
+    const uint32_t t_begin = blockIdx.x * a.chunk;
+    const uint32_t t_end = min(t_begin + a.chunk, a.ntiles);
+    float acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = 0.f;
+    int cur_box = -1;
+    CollideConst cc = a.cc;
+    for (uint32_t t = t_begin; t < t_end; ++t) {
+        const uint32_t box = a.tile_box[t];
+        if (VACF && (int)box != cur_box) {
+            if (cur_box >= 0) {
+                flush_amp12(acc, a.amp + 12 * (size_t)cur_box);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[c] = 0.f;
+            }
+            cur_box = (int)box;
+        }
+        const BoxDesc d = a.boxes[box];
+        const uint32_t s = (t - d.first_tile) * blockDim.x + threadIdx.x;
+        if (s >= d.geo.N) continue;
+        uint32_t x, y, z;
+        const PullOffsets o = pull_offsets(s, d.geo, x, y, z);
+        const T *__restrict__ src = static_cast<const T *>(a.src) + d.off;
+        T *__restrict__ dst = static_cast<T *>(a.dst) + d.off;
+        const uint32_t N = d.geo.N;
+        float dd[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dd[i] = S::ld(ld_plane(src + (size_t)i * N, pull_src(s, o, i)), 0.f);
+        if (VACF) {
+            const float jx = (dd[1] - dd[2]) + (dd[7] - dd[8]) + (dd[9] - dd[10]) + (dd[11] - dd[12]) + (dd[13] - dd[14]);
+            const float jy = (dd[3] - dd[4]) + (dd[7] - dd[8]) - (dd[9] - dd[10]) + (dd[15] - dd[16]) + (dd[17] - dd[18]);
+            const float jz = (dd[5] - dd[6]) + (dd[11] - dd[12]) - (dd[13] - dd[14]) + (dd[15] - dd[16]) - (dd[17] - dd[18]);
+            const float fx = (float)x * d.inv_L[0], fy = (float)y * d.inv_L[1], fz = (float)z * d.inv_L[2];
+            const float cx = __builtin_amdgcn_cosf(fx), sx = __builtin_amdgcn_sinf(fx);
+            const float cy = __builtin_amdgcn_cosf(fy), sy = __builtin_amdgcn_sinf(fy);
+            const float cz = __builtin_amdgcn_cosf(fz), sz = __builtin_amdgcn_sinf(fz);
+            // exp(-i phi) = cos - i sin
+            acc[0] += jx * cz;  acc[1] -= jx * sz;   // k along z, j_x
+            acc[2] += jy * cz;  acc[3] -= jy * sz;   // k along z, j_y
+            acc[4] += jx * cy;  acc[5] -= jx * sy;   // k along y, j_x
+            acc[6] += jz * cy;  acc[7] -= jz * sy;   // k along y, j_z
+            acc[8] += jy * cx;  acc[9] -= jy * sx;   // k along x, j_y
+            acc[10] += jz * cx; acc[11] -= jz * sx;  // k along x, j_z
+        }
+        cc.box = d.box_id;
+        float out[Q];
+        collide_site<THERMAL>(dd, cc.g, cc, s, step, out);
+        if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) st_plane(dst + (size_t)i * N, s, S::st(out[i], 0.f));
+    }
+    if (VACF && cur_box >= 0) flush_amp12(acc, a.amp + 12 * (size_t)cur_box);
+}
+
+// Push this step's amplitudes into the ring, accumulate C_b(tau), clear the
+// accumulators.  One block per box, one thread per lag (blockDim >= R).
+__global__ void k_vacf_update(float *amp, float *ring, double *corr, int R, const uint32_t *nsamp_ptr)
+{
+    const int b = blockIdx.x;
+    const uint32_t ns = *nsamp_ptr;  // samples taken before this one
+    const int slot = (int)(ns % (uint32_t)R);
+    float *ringb = ring + (size_t)b * R * 12;
+    __shared__ float cur[12];
+    if (threadIdx.x < 12) {
+        cur[threadIdx.x] = amp[12 * (size_t)b + threadIdx.x];
+        ringb[slot * 12 + threadIdx.x] = cur[threadIdx.x];
+    }
+    __syncthreads();
+    const int tau = threadIdx.x;
+    if (tau < R && (uint32_t)tau <= ns) {
+        const float *old = ringb + ((slot - tau + R) % R) * 12;
+        double s = 0.0;
+        for (int m = 0; m < 6; ++m)
+            s += (double)cur[2 * m] * old[2 * m] + (double)cur[2 * m + 1] * old[2 * m + 1];
+        corr[(size_t)b * R + tau] += s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) amp[12 * (size_t)b + threadIdx.x] = 0.f;
+}
+
+// Advance the device step counter (and the VACF sample count).
+__global__ void k_advance(uint32_t *step_ptr, uint32_t *nsamp_ptr, int sampled)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        step_ptr[0] += 1u;
+        if (sampled) nsamp_ptr[0] += 1u;
+    }
+}
+
+__global__ void k_set_u32(uint32_t *p, uint32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+}  // namespace lbmi

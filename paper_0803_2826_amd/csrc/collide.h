@@ -31,6 +31,19 @@
 
 namespace lbmi {
 
+// Multiplication by the weights a = 1/3, 1/18, 1/36, none of which is exact
+// in FP32: x * (hi + lo) with hi = fl(a), lo = fl(a - hi), so the product is
+// rounded once from the (near) exact value instead of carrying the constant's
+// own rounding error, which would bias every step the same way.
+template <int DEN>
+__device__ __forceinline__ float mul_weight(float x)
+{
+    constexpr double a = 1.0 / (double)DEN;
+    constexpr float hi = (float)a;
+    constexpr float lo = (float)(a - (double)hi);
+    return __builtin_fmaf(x, hi, x * lo);
+}
+
 // Per-launch constants of the collision (kernel-argument resident).
 struct CollideConst {
     float gam[19];   // gamma_k, modes 4..18 used
@@ -140,8 +153,7 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     const float u13 = 4.5f * ms[13], u14 = 4.5f * ms[14], u15 = 4.5f * ms[15];
     const float u16 = 0.5f * ms[16], u17 = 0.75f * ms[17], u18 = 2.25f * ms[18];
 
-    const float a0 = 1.f / 3.f, a1 = 1.f / 18.f, a2 = 1.f / 36.f;
-    out[0] = a0 * ((u0 - u4) + u16);
+    out[0] = mul_weight<3>((u0 - u4) + u16);
 
     // speed-1 pairs
     const float e1c = (u0 - 2.f * u16);  // common even part of the axis directions
@@ -149,12 +161,12 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     const float E2 = e1c - u5 + u6 + u17 - u18;
     const float E3 = e1c - u5 - u6 + u17 + u18;
     const float O1 = u1 - 2.f * u10, O2 = u2 - 2.f * u11, O3 = u3 - 2.f * u12;
-    out[1] = a1 * (E1 + O1);
-    out[2] = a1 * (E1 - O1);
-    out[3] = a1 * (E2 + O2);
-    out[4] = a1 * (E2 - O2);
-    out[5] = a1 * (E3 + O3);
-    out[6] = a1 * (E3 - O3);
+    out[1] = mul_weight<18>(E1 + O1);
+    out[2] = mul_weight<18>(E1 - O1);
+    out[3] = mul_weight<18>(E2 + O2);
+    out[4] = mul_weight<18>(E2 - O2);
+    out[5] = mul_weight<18>(E3 + O3);
+    out[6] = mul_weight<18>(E3 - O3);
 
     // speed-sqrt2 pairs
     const float e2c = (u0 + u4) + u16;
@@ -171,18 +183,18 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     const float O7 = (px - pz) - (u13 + u15);
     const float O8 = (py + pz) + (u14 - u15);
     const float O9 = (py - pz) + (u14 + u15);
-    out[7] = a2 * (E4 + O4);
-    out[8] = a2 * (E4 - O4);
-    out[9] = a2 * (E5 + O5);
-    out[10] = a2 * (E5 - O5);
-    out[11] = a2 * (E6 + O6);
-    out[12] = a2 * (E6 - O6);
-    out[13] = a2 * (E7 + O7);
-    out[14] = a2 * (E7 - O7);
-    out[15] = a2 * (E8 + O8);
-    out[16] = a2 * (E8 - O8);
-    out[17] = a2 * (E9 + O9);
-    out[18] = a2 * (E9 - O9);
+    out[7] = mul_weight<36>(E4 + O4);
+    out[8] = mul_weight<36>(E4 - O4);
+    out[9] = mul_weight<36>(E5 + O5);
+    out[10] = mul_weight<36>(E5 - O5);
+    out[11] = mul_weight<36>(E6 + O6);
+    out[12] = mul_weight<36>(E6 - O6);
+    out[13] = mul_weight<36>(E7 + O7);
+    out[14] = mul_weight<36>(E7 - O7);
+    out[15] = mul_weight<36>(E8 + O8);
+    out[16] = mul_weight<36>(E8 - O8);
+    out[17] = mul_weight<36>(E9 + O9);
+    out[18] = mul_weight<36>(E9 - O9);
 }
 
 }  // namespace lbmi

@@ -3,17 +3,20 @@
 // gathered from the stored populations.
 //
 // One coupled step on the device:
-//   k_bead_half     R' = R + (h/2) P/m, clear conservative forces
+//   k_bead_half     R' = R + (h/2) P/m, clear conservative forces, reset the
+//                   touched-node count
 //   k_bonds         harmonic bond forces at R' (FP64 atomics; a bead with at
 //                   most two bonds gets a bitwise reproducible sum)
-//   k_bead_update   u_b by trilinear interpolation (phi_2 product kernel,
-//                   eq. Delta/eq. 2point) of u = (sum n c + g/2)/rho,
-//                   P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta
-//                   (eq. langevin_momentum_update), impulse
-//                   I = -(P'' - P - h F^c) spread to the 8 nodes
-//                   (eq. ftotal) into a sparse force field, R = R' + (h/2) P''/m
-//   k_fixup         (inside the next lb_step) re-collides the touched nodes
-//                   with the full force g + f(r) and clears the force field.
+//   k_bead_update   8 lanes per bead, one per stencil node: each lane gathers
+//                   its node's 19 populations and forms w u(node) with
+//                   u = (sum n c + g/2)/rho (trilinear phi_2 product kernel,
+//                   eq. Delta / eq. 2point); a lane reduction gives u_b; every
+//                   lane then evaluates P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta
+//                   (eq. langevin_momentum_update) and spreads w I / h with
+//                   I = -(P'' - P - h F^c) to its own node (eq. ftotal), setting
+//                   the node's bit in the force bitmap; R = R' + (h/2) P''/m
+//   (next lb_step)  the fused stream-collide kernel adds the bead force at
+//                   flagged sites, then k_clear_touched zeroes force and bits.
 #pragma once
 
 #include "aux_kernels.h"
@@ -35,7 +38,7 @@ struct CoupleArgs {
     double *half;         // [n][3]
     double *fc;           // [n][3]
     float *force;         // [3][N] sparse force field (zero outside touched nodes)
-    int32_t *mark;        // [N] 1 = node already in the list
+    uint32_t *fmask;      // [ceil(N/32)] force bitmap
     int32_t *list;        // [8 n] touched nodes
     int32_t *count;       // number of entries in list
 };
@@ -43,6 +46,7 @@ struct CoupleArgs {
 __global__ void k_bead_half(CoupleArgs a)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) *a.count = 0;
     if (b >= a.n) return;
     const double m = a.mass[b];
     for (int c = 0; c < 3; ++c) {
@@ -72,51 +76,58 @@ __global__ void k_bonds(const double *__restrict__ half, double *fc, const int32
     }
 }
 
-__global__ void k_reset_count(int32_t *count) { *count = 0; }
-
+// 8 consecutive lanes per bead (blockDim a multiple of 64, so a bead's lanes
+// never straddle a wave).
 template <int ST>
-__global__ void k_bead_update(CoupleArgs a)
+__global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.n) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = t >> 3, q = t & 7;
+    const bool live = b < a.n;
     const Geom &g = a.geo;
-    const uint32_t L[3] = {g.nx, g.ny, g.nz};
-    uint32_t base[3];
-    double frac[3];
-    for (int c = 0; c < 3; ++c) {
-        const double r = a.half[3 * b + c];
-        const double f = floor(r);
-        frac[c] = r - f;
-        double w = f - (double)L[c] * floor(f / (double)L[c]);  // f mod L in [0, L)
-        uint32_t wi = (uint32_t)w;
-        if (wi >= L[c]) wi = 0;
-        base[c] = wi;
-    }
-    const T *pop = static_cast<const T *>(a.pop);
-    uint32_t node[8];
-    double wgt[8];
     double ub[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < 8; ++q) {
-        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
-        const uint32_t x = (base[0] + dx) % L[0], y = (base[1] + dy) % L[1], z = (base[2] + dz) % L[2];
-        const uint32_t s = x + g.nx * (y + g.ny * z);
-        node[q] = s;
-        wgt[q] = (dx ? frac[0] : 1.0 - frac[0]) * (dy ? frac[1] : 1.0 - frac[1]) * (dz ? frac[2] : 1.0 - frac[2]);
+    uint32_t node = 0;
+    double wq = 0.0;
+    if (live) {
+        const uint32_t L[3] = {g.nx, g.ny, g.nz};
+        uint32_t cpos[3];
+        double frac[3];
+        for (int c = 0; c < 3; ++c) {
+            const double r = a.half[3 * b + c];
+            const double f = floor(r);
+            frac[c] = r - f;
+            const double w = f - (double)L[c] * floor(f / (double)L[c]);  // f mod L in [0, L)
+            uint32_t wi = (uint32_t)w;
+            if (wi >= L[c]) wi = 0;
+            const uint32_t bit = (q >> c) & 1;
+            cpos[c] = (wi + bit) % L[c];
+            frac[c] = bit ? frac[c] : 1.0 - frac[c];
+        }
+        node = cpos[0] + g.nx * (cpos[1] + g.ny * cpos[2]);
+        wq = frac[0] * frac[1] * frac[2];
         uint32_t xx, yy, zz;
-        const PullOffsets o = pull_offsets(s, g, xx, yy, zz);
+        const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
+        const T *pop = static_cast<const T *>(a.pop);
         double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double v = (double)S::ld(pop[(size_t)i * g.N + pull_src(s, o, i)], 0.f);
+            const double v = (double)S::ld(pop[(size_t)i * g.N + pull_src(node, o, i)], 0.f);
             m += v;
             j[0] += v * kCX[i];
             j[1] += v * kCY[i];
             j[2] += v * kCZ[i];
         }
         const double rho = a.rho0 + m;
-        for (int c = 0; c < 3; ++c) ub[c] += wgt[q] * (j[c] + 0.5 * a.g[c]) / rho;
+        for (int c = 0; c < 3; ++c) ub[c] = wq * (j[c] + 0.5 * a.g[c]) / rho;
     }
+    // sum the 8 node contributions of the bead (lanes q = 0..7 of one group)
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ub[c] += __shfl_xor(ub[c], off, 64);
+    if (!live) return;
     const double m = a.mass[b], z = a.zeta[b], h = 1.0;
     double C1, C2, C3;
     if (z > 0.0) {
@@ -136,78 +147,33 @@ __global__ void k_bead_update(CoupleArgs a)
         Pn[c] = C1 * P + C2 * (Fc + z * ub[c]) + C3 * th[c];
         I[c] = -(Pn[c] - P - h * Fc);
     }
-    for (int q = 0; q < 8; ++q) {
-        if (wgt[q] == 0.0) continue;
-        for (int c = 0; c < 3; ++c) atomicAdd(&a.force[(size_t)c * g.N + node[q]], (float)(wgt[q] * I[c] / h));
-        if (atomicExch(&a.mark[node[q]], 1) == 0) {
+    if (wq != 0.0) {
+        for (int c = 0; c < 3; ++c) atomicAdd(&a.force[(size_t)c * g.N + node], (float)(wq * I[c] / h));
+        const uint32_t bit = 1u << (node & 31u);
+        if ((atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u) {
             const int slot = atomicAdd(a.count, 1);
-            a.list[slot] = (int32_t)node[q];
+            a.list[slot] = (int32_t)node;
         }
     }
-    for (int c = 0; c < 3; ++c) {
-        a.mom[3 * b + c] = Pn[c];
-        a.pos[3 * b + c] = a.half[3 * b + c] + 0.5 * h * Pn[c] / m;
-    }
+    if (q == 0)
+        for (int c = 0; c < 3; ++c) {
+            a.mom[3 * b + c] = Pn[c];
+            a.pos[3 * b + c] = a.half[3 * b + c] + 0.5 * h * Pn[c] / m;
+        }
 }
 
-struct FixupArgs {
-    StepArgs st;
-    float *force;
-    int32_t *mark;
-    const int32_t *list;
-    const int32_t *count;
-    int32_t cap;
-    double *fixpartials;  // [cap][4] totals corrections
-};
-
-// Re-collide the nodes that received bead force, with F = g + f(node); write
-// over the step kernel's output at those nodes; record the change of the
-// stored totals; clear the force field and marks.
-template <int ST, bool THERMAL>
-__global__ void k_fixup(FixupArgs f)
+// After the step that consumed the bead force: zero the force and the bitmap
+// word of every touched node (all set bits belong to listed nodes).
+__global__ void k_clear_touched(float *force, uint32_t *fmask, const int32_t *list, const int32_t *count, int cap,
+                                uint32_t N)
 {
-    using S = Storage<ST>;
-    using T = typename S::T;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= f.cap) return;
-    double *part = f.fixpartials + 4 * (size_t)idx;
-    if (idx >= *f.count) {
-        part[0] = part[1] = part[2] = part[3] = 0.0;
-        return;
-    }
-    const StepArgs &a = f.st;
-    const uint32_t s = (uint32_t)f.list[idx];
-    const uint32_t N = a.geo.N;
-    uint32_t x, y, z;
-    const PullOffsets o = pull_offsets(s, a.geo, x, y, z);
-    const T *src = static_cast<const T *>(a.src);
-    T *dst = static_cast<T *>(a.dst);
-    float d[Q];
-    for (int i = 0; i < Q; ++i) d[i] = S::ld(src[(size_t)i * N + pull_src(s, o, i)], 0.f);
-    float F[3];
-    for (int c = 0; c < 3; ++c) {
-        F[c] = a.cc.g[c] + f.force[(size_t)c * N + s];
-        f.force[(size_t)c * N + s] = 0.f;
-    }
-    f.mark[s] = 0;
-    float out[Q];
-    collide_site<THERMAL>(d, F, a.cc, s, a.step, out);
-    double dm = 0.0, dp[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < Q; ++i) {
-        const double old = (double)S::ld(dst[(size_t)i * N + s], 0.f);
-        const T v = S::st(out[i], 0.f);
-        dst[(size_t)i * N + s] = v;
-        const double diff = (double)S::ld(v, 0.f) - old;
-        dm += diff;
-        dp[0] += diff * kCX[i];
-        dp[1] += diff * kCY[i];
-        dp[2] += diff * kCZ[i];
-    }
-    if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    part[0] = dm;
-    part[1] = dp[0];
-    part[2] = dp[1];
-    part[3] = dp[2];
+    if (idx >= cap || idx >= *count) return;
+    const uint32_t s = (uint32_t)list[idx];
+    force[s] = 0.f;
+    force[(size_t)N + s] = 0.f;
+    force[2 * (size_t)N + s] = 0.f;
+    fmask[s >> 5] = 0u;
 }
 
 }  // namespace lbmi

@@ -131,16 +131,34 @@ __device__ __forceinline__ void st_plane(T *__restrict__ plane, uint32_t idx, T 
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(plane) + (uint32_t)(idx * (uint32_t)sizeof(T))));
 }
 
+// Streaming store of element idx through a raw buffer resource built from a
+// wave-uniform plane base (scalar registers): one shared 32-bit byte offset,
+// non-temporal cache policy, and stores beyond `nbytes` are dropped by the
+// hardware.  gfx9 resource word 3 = 0x00020000; cache-policy bit 1 = nt.
+template <typename T>
+__device__ __forceinline__ void st_plane_nt(void *plane, uint32_t nbytes, uint32_t idx, T v)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, (short)0, (int)nbytes, 0x00020000);
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)(idx * 4u), 0, 2);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)(idx * 2u), 0, 2);
+}
+
 // Arguments of the fused step kernel.
 struct StepArgs {
     const void *src;      // buffer A, [19][N]
     void *dst;            // buffer B, [19][N]
+    const void *srcp[19]; // plane i of A (scalar base of every load)
+    void *dstp[19];       // plane i of B (scalar base of every store)
     Geom geo;
     CollideConst cc;
     uint32_t step;
     uint32_t xcd_remap;   // 1: map blocks so that consecutive tiles share an XCD
     double *partials;     // [gridDim][4] per-block totals (TOTALS only)
     int32_t *flags;       // bit 0: non-finite density seen
+    const uint32_t *fmask;  // [ceil(N/32)] 1 bit per site: bead force present (FORCE only)
+    const float *force;     // [3][N] bead force density at flagged sites (FORCE only)
 };
 
 __device__ __forceinline__ uint32_t tile_index(uint32_t remap)
@@ -150,24 +168,29 @@ __device__ __forceinline__ uint32_t tile_index(uint32_t remap)
     return b;
 }
 
-// Block-wide sum of 4 floats into one FP64 partial per block.
-template <int NV>
-__device__ __forceinline__ void block_sum_to(double *out, float v[NV])
+// Block-wide sums of (FP64 mass, 3 FP32 momentum components) into one FP64
+// partial row per block.  Every thread of the block must call it.
+__device__ __forceinline__ void block_sum_totals(double *out, double mass, float mom[3])
 {
-    __shared__ double red[16][NV];
+    __shared__ double red[16][4];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        float x = v[c];
+    for (int off = 32; off > 0; off >>= 1) mass += __shfl_xor(mass, off, 64);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float x = mom[c];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        v[c] = x;
+        mom[c] = x;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int c = 0; c < NV; ++c) red[wid][c] = (double)v[c];
+    if (lane == 0) {
+        red[wid][0] = mass;
+        red[wid][1] = (double)mom[0];
+        red[wid][2] = (double)mom[1];
+        red[wid][3] = (double)mom[2];
+    }
     __syncthreads();
-    if (threadIdx.x < NV) {
+    if (threadIdx.x < 4) {
         const int nw = (blockDim.x + 63) >> 6;
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
@@ -175,46 +198,74 @@ __device__ __forceinline__ void block_sum_to(double *out, float v[NV])
     }
 }
 
-template <int ST, bool THERMAL, bool TOTALS>
+// Store the post-collision populations of site s.  The rest population is
+// replaced by the residual that makes the stored values of the site sum to the
+// stored input values (both sums in FP64), so the site's mass changes only by
+// the single rounding of that residual to the storage type.  Returns the
+// stored values' FP64 mass and FP32 momentum for the totals.
+template <int ST, bool TOTALS>
+__device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_bytes, uint32_t s, const float d[Q],
+                                           const float out[Q], double &mass, float mom[3])
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    double m_in = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) m_in += (double)d[i];
+    T v[Q];
+    float back[Q];
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        v[i] = S::st(out[i], 0.f);
+        back[i] = S::ld(v[i], 0.f);
+        sum += (double)back[i];
+    }
+    v[0] = S::st((float)(m_in - sum), 0.f);
+    back[0] = S::ld(v[0], 0.f);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st_plane_nt<T>(dstp[i], plane_bytes, s, v[i]);
+    if (TOTALS) {
+        mass = (double)back[0] + sum;
+        mom[0] = (back[1] - back[2]) + (back[7] - back[8]) + (back[9] - back[10]) + (back[11] - back[12]) +
+                 (back[13] - back[14]);
+        mom[1] = (back[3] - back[4]) + (back[7] - back[8]) - (back[9] - back[10]) + (back[15] - back[16]) +
+                 (back[17] - back[18]);
+        mom[2] = (back[5] - back[6]) + (back[11] - back[12]) - (back[13] - back[14]) + (back[15] - back[16]) -
+                 (back[17] - back[18]);
+    }
+}
+
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE>
 __global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
     const uint32_t s = tile_index(a.xcd_remap) * blockDim.x + threadIdx.x;
     const bool active = s < a.geo.N;
-    float tot[4] = {0.f, 0.f, 0.f, 0.f};
+    double mass = 0.0;
+    float mom[3] = {0.f, 0.f, 0.f};
     if (active) {
         uint32_t x, y, z;
         const PullOffsets o = pull_offsets(s, a.geo, x, y, z);
-        const T *__restrict__ src = static_cast<const T *>(a.src);
-        T *__restrict__ dst = static_cast<T *>(a.dst);
         const uint32_t N = a.geo.N;
         float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = S::ld(ld_plane(src + (size_t)i * N, pull_src(s, o, i)), 0.f);
+        for (int i = 0; i < Q; ++i) d[i] = S::ld(ld_plane(static_cast<const T *>(a.srcp[i]), pull_src(s, o, i)), 0.f);
+        float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
+        if (FORCE) {
+            if ((a.fmask[s >> 5] >> (s & 31u)) & 1u) {
+                F[0] += a.force[s];
+                F[1] += a.force[(size_t)N + s];
+                F[2] += a.force[2 * (size_t)N + s];
+            }
+        }
         float out[Q];
-        collide_site<THERMAL>(d, a.cc.g, a.cc, s, a.step, out);
+        collide_site<THERMAL>(d, F, a.cc, s, a.step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const T v = S::st(out[i], 0.f);
-            st_plane(dst + (size_t)i * N, s, v);
-            if (TOTALS) out[i] = S::ld(v, 0.f);
-        }
-        if (TOTALS) {
-            float msum = out[0];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) msum += out[i];
-            tot[0] = msum;
-            tot[1] = (out[1] - out[2]) + (out[7] - out[8]) + (out[9] - out[10]) + (out[11] - out[12]) +
-                     (out[13] - out[14]);
-            tot[2] = (out[3] - out[4]) + (out[7] - out[8]) - (out[9] - out[10]) + (out[15] - out[16]) +
-                     (out[17] - out[18]);
-            tot[3] = (out[5] - out[6]) + (out[11] - out[12]) - (out[13] - out[14]) + (out[15] - out[16]) -
-                     (out[17] - out[18]);
-        }
+        store_site<ST, TOTALS>(a.dstp, N * (uint32_t)sizeof(T), s, d, out, mass, mom);
     }
-    if (TOTALS) block_sum_to<4>(a.partials + 4 * (size_t)blockIdx.x, tot);
+    if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)blockIdx.x, mass, mom);
 }
 
 }  // namespace lbmi

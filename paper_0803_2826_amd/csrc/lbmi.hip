@@ -34,20 +34,18 @@ struct lb_ctx {
     double *dev_out = nullptr;       // [64] reduced outputs
     int32_t *flags = nullptr;        // latched device errors
     bool totals_valid = false;       // fused totals of the last step are in `partials`
-    int last_fix_rows = 0;           // rows of fixpartials valid for the last step
     bool thermal = false;
     // bead coupling (allocated on first lb_couple)
-    float *force = nullptr;
-    int32_t *mark = nullptr;
-    int32_t *list = nullptr;
+    float *force = nullptr;          // [3][N]
+    uint32_t *fmask = nullptr;       // [ceil(N/32)] bit per site: bead force present
+    int32_t *list = nullptr;         // touched nodes of the pending force
     int32_t *count = nullptr;
-    double *fixpartials = nullptr;
     int list_cap = 0;
     double *half = nullptr;
     double *fc = nullptr;
     int bead_cap = 0;
     bool pending_force = false;
-    int pending_rows = 0;
+    int pending_rows = 0;            // upper bound of touched nodes (8 per bead)
     std::string err;
 };
 
@@ -150,30 +148,29 @@ void fill_collide_const(lb_ctx *c)
     c->thermal = p.kT > 0.0;
 }
 
-template <int ST, bool TH, bool TOT>
+template <int ST, bool TH, bool TOT, bool FRC>
 void launch_step_t(lb_ctx *c, const StepArgs &a)
 {
-    hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
+    hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
+}
+
+template <int ST, bool TH, bool TOT>
+void launch_step_f(lb_ctx *c, const StepArgs &a, bool frc)
+{
+    if (frc) launch_step_t<ST, TH, TOT, true>(c, a);
+    else launch_step_t<ST, TH, TOT, false>(c, a);
 }
 
 template <int ST>
-void launch_step_st(lb_ctx *c, const StepArgs &a, bool tot)
+void launch_step_st(lb_ctx *c, const StepArgs &a, bool tot, bool frc)
 {
     if (c->thermal) {
-        if (tot) launch_step_t<ST, true, true>(c, a);
-        else launch_step_t<ST, true, false>(c, a);
+        if (tot) launch_step_f<ST, true, true>(c, a, frc);
+        else launch_step_f<ST, true, false>(c, a, frc);
     } else {
-        if (tot) launch_step_t<ST, false, true>(c, a);
-        else launch_step_t<ST, false, false>(c, a);
+        if (tot) launch_step_f<ST, false, true>(c, a, frc);
+        else launch_step_f<ST, false, false>(c, a, frc);
     }
-}
-
-template <int ST>
-void launch_fixup_st(lb_ctx *c, const FixupArgs &f)
-{
-    const unsigned grid = grid_for((size_t)f.cap, 256);
-    if (c->thermal) hipLaunchKernelGGL((k_fixup<ST, true>), dim3(grid), dim3(256), 0, c->stream, f);
-    else hipLaunchKernelGGL((k_fixup<ST, false>), dim3(grid), dim3(256), 0, c->stream, f);
 }
 
 // Dispatch on the storage type: F(integral_constant<int, ST>) for ST in {1,2,3}.
@@ -210,26 +207,27 @@ int read_flags(lb_ctx *c)
 int ensure_bead_buffers(lb_ctx *c, int n)
 {
     const size_t N = c->geo.N;
+    const size_t nwords = (N + 31) / 32;
     if (!c->force) {
         if (hipMalloc(&c->force, 3 * N * sizeof(float)) != hipSuccess ||
-            hipMalloc(&c->mark, N * sizeof(int32_t)) != hipSuccess || hipMalloc(&c->count, sizeof(int32_t)) != hipSuccess)
+            hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&c->count, sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead force field allocation failed");
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->force, 3 * N);
-        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, c->mark, (uint32_t)N);
+        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nwords, 256)), dim3(256), 0, c->stream,
+                           reinterpret_cast<int32_t *>(c->fmask), (uint32_t)nwords);
         LB_LAUNCH_CHECK(c, "zero force field");
     }
     if (n > c->bead_cap) {
         (void)hipFree(c->half);
         (void)hipFree(c->fc);
         (void)hipFree(c->list);
-        (void)hipFree(c->fixpartials);
-        c->half = c->fc = c->fixpartials = nullptr;
+        c->half = c->fc = nullptr;
         c->list = nullptr;
         const int cap = n < 64 ? 64 : n;
         if (hipMalloc(&c->half, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->fc, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->list, 8 * (size_t)cap * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->fixpartials, 8 * (size_t)cap * 4 * sizeof(double)) != hipSuccess)
+            hipMalloc(&c->list, 8 * (size_t)cap * sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead scratch allocation failed");
         c->bead_cap = cap;
         c->list_cap = 8 * cap;
@@ -289,7 +287,7 @@ int lb_destroy(lb_ctx *c)
     use_device(c);
     (void)hipStreamSynchronize(c->stream);
     void *ptrs[] = {c->bufA, c->bufB, c->partials, c->scratch, c->dev_out, c->flags, c->force,
-                    c->mark, c->list, c->count, c->fixpartials, c->half, c->fc};
+                    c->fmask, c->list, c->count, c->half, c->fc};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete c;
@@ -360,27 +358,25 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         StepArgs a;
         a.src = c->bufA;
         a.dst = c->bufB;
+        for (int i = 0; i < 19; ++i) {
+            a.srcp[i] = static_cast<const char *>(c->bufA) + (size_t)i * c->geo.N * c->elem;
+            a.dstp[i] = static_cast<char *>(c->bufB) + (size_t)i * c->geo.N * c->elem;
+        }
         a.geo = c->geo;
         a.cc = c->cc;
         a.step = (uint32_t)c->step;
         a.xcd_remap = 1;
         a.partials = c->partials;
         a.flags = c->flags;
-        by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot); });
+        a.fmask = c->fmask;
+        a.force = c->force;
+        const bool frc = c->pending_force;
+        by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
         LB_LAUNCH_CHECK(c, "stream_collide");
-        c->last_fix_rows = 0;
-        if (c->pending_force) {
-            FixupArgs f;
-            f.st = a;
-            f.force = c->force;
-            f.mark = c->mark;
-            f.list = c->list;
-            f.count = c->count;
-            f.cap = c->pending_rows;
-            f.fixpartials = c->fixpartials;
-            by_storage(c->p.storage, [&](auto st) { launch_fixup_st<decltype(st)::value>(c, f); });
-            LB_LAUNCH_CHECK(c, "fixup");
-            c->last_fix_rows = c->pending_rows;
+        if (frc) {
+            hipLaunchKernelGGL(k_clear_touched, dim3(grid_for((size_t)c->pending_rows, 256)), dim3(256), 0, c->stream,
+                               c->force, c->fmask, c->list, c->count, c->pending_rows, c->geo.N);
+            LB_LAUNCH_CHECK(c, "clear_touched");
             c->pending_force = false;
         }
         std::swap(c->bufA, c->bufB);
@@ -421,17 +417,17 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     a.half = c->half;
     a.fc = c->fc;
     a.force = c->force;
-    a.mark = c->mark;
+    a.fmask = c->fmask;
     a.list = c->list;
     a.count = c->count;
     const unsigned gb = grid_for((size_t)b->n, 256);
-    hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, c->stream, c->count);
     hipLaunchKernelGGL(k_bead_half, dim3(gb), dim3(256), 0, c->stream, a);
     if (b->nbonds > 0)
         hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
                            b->bonds, b->nbonds, b->k_bond, b->r0, b->n);
     by_storage(c->p.storage, [&](auto st) {
-        hipLaunchKernelGGL((k_bead_update<decltype(st)::value>), dim3(gb), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL((k_bead_update<decltype(st)::value>), dim3(grid_for(8 * (size_t)b->n, 256)), dim3(256), 0,
+                           c->stream, a);
     });
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
@@ -453,22 +449,18 @@ int lb_moments(lb_ctx *c, double *rho, double *u)
     return LB_OK;
 }
 
-static int totals_from_partials(lb_ctx *c, const double *partials, int rows, double out[4], bool add_fix)
+static int totals_from_partials(lb_ctx *c, const double *partials, int rows, double out[4])
 {
     hipLaunchKernelGGL(k_reduce_cols, dim3(4), dim3(256), 0, c->stream, partials, rows, 4, c->dev_out);
-    if (add_fix && c->last_fix_rows > 0)
-        hipLaunchKernelGGL(k_reduce_cols, dim3(4), dim3(256), 0, c->stream, c->fixpartials, c->last_fix_rows, 4,
-                           c->dev_out + 4);
     LB_LAUNCH_CHECK(c, "reduce totals");
-    double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const size_t nbytes = (add_fix && c->last_fix_rows > 0 ? 8 : 4) * sizeof(double);
-    LB_TRY(check(c, hipMemcpyAsync(h, c->dev_out, nbytes, hipMemcpyDeviceToHost, c->stream), "totals copy"));
+    double h[4] = {0, 0, 0, 0};
+    LB_TRY(check(c, hipMemcpyAsync(h, c->dev_out, sizeof(h), hipMemcpyDeviceToHost, c->stream), "totals copy"));
     LB_TRY(read_flags(c));
     const double N = (double)c->geo.N;
-    out[0] = N * c->p.rho0 + (h[0] + h[4]);
-    out[1] = h[1] + h[5];
-    out[2] = h[2] + h[6];
-    out[3] = h[3] + h[7];
+    out[0] = N * c->p.rho0 + h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+    out[3] = h[3];
     return LB_OK;
 }
 
@@ -483,7 +475,7 @@ int lb_totals_exact(lb_ctx *c, double out[4])
                            c->scratch);
     });
     LB_LAUNCH_CHECK(c, "totals_exact");
-    return totals_from_partials(c, c->scratch, nb, out, false);
+    return totals_from_partials(c, c->scratch, nb, out);
 }
 
 int lb_totals(lb_ctx *c, double out[4])
@@ -491,7 +483,7 @@ int lb_totals(lb_ctx *c, double out[4])
     if (!c || !out) return LB_EINVAL;
     if (!c->totals_valid) return lb_totals_exact(c, out);
     LB_TRY(use_device(c));
-    return totals_from_partials(c, c->partials, c->nblocks, out, true);
+    return totals_from_partials(c, c->partials, c->nblocks, out);
 }
 
 int lb_mode_stats(lb_ctx *c, double var[19])
