@@ -129,12 +129,16 @@ def lib():
                                  ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double, dp]
         L.orc_coupled_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
                                        ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double]
+        L.orc_collide_site_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, dp]
+        L.orc_step_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_uint32, dp]
+        L.orc_backward.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, dp, dp]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals",
                      "orc_equilibrium", "orc_moments_site", "orc_back_site", "orc_collide_site",
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
-                     "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step"):
+                     "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step",
+                     "orc_collide_site_adjoint", "orc_step_adjoint", "orc_backward"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -314,3 +318,28 @@ def coupled_step(p: Params, n: np.ndarray, step_index: int, beads: Beads) -> np.
     couple(p, n, step_index, beads, force)
     step(p, n, step_index, extra_force=force)
     return force
+
+
+# --------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------
+
+def collide_site_adjoint(p: Params, n, F, gnoise, nbar_star):
+    """Returns (dL/dn, dL/dF) given dL/dn* for one collision."""
+    nn, FF = _f64(n), _f64(F)
+    g = _f64(gnoise if gnoise is not None else np.zeros(16))
+    nbs = _f64(nbar_star)
+    nb = np.zeros(Q)
+    Fb = np.zeros(3)
+    pc = p.c()
+    lib().orc_collide_site_adjoint(ctypes.byref(pc), _dp(nn), _dp(FF), _dp(g), _dp(nbs), _dp(nb), _dp(Fb))
+    return nb, Fb
+
+
+def backward(p: Params, n0: np.ndarray, nsteps: int, lam_T: np.ndarray, step0: int = 0):
+    """dL/dn(0) and dL/dg (through the dynamics) from dL/dn(T), no particles."""
+    lam = np.ascontiguousarray(lam_T, dtype=np.float64).copy()
+    gbar = np.zeros(3)
+    pc = p.c()
+    lib().orc_backward(ctypes.byref(pc), _dp(_f64(n0)), int(nsteps), int(step0), _dp(lam), _dp(gbar))
+    return lam, gbar

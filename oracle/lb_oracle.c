@@ -619,3 +619,176 @@ void orc_coupled_step(const orc_params *p, double *n, double *work, double *forc
     orc_couple(p, n, step, nb, pos, mom, mass, zeta, nbonds, bonds, kbond, r0, force);
     orc_step(p, n, work, force, step);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint (reverse mode) of the fluid step                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Transpose of the Jacobian of orc_collide_site with respect to the
+ * pre-collision populations n and the force density F, applied to nbs (the
+ * adjoint of n*).  The steps of orc_collide_site are taken back in reverse
+ * order (forcing term, back-transformation, relaxation + noise, equilibrium,
+ * velocity, moments).  The noise variates g are replayed: only the
+ * sqrt(rho) amplitude of the local-density noise depends on the state.
+ * Outputs: nb (adjoint of n, overwritten), Fb (adjoint of F, accumulated).
+ * Parity pinned by central finite differences of orc_collide_site. */
+void orc_collide_site_adjoint(const orc_params *p, const double n[Q], const double F[3], const double *gnoise,
+                              const double nbs[Q], double nb[Q], double Fb[3])
+{
+    init_tables();
+    double gam[Q];
+    mode_gammas(p, gam);
+
+    /* forward quantities */
+    double m[Q];
+    orc_moments_site(n, m);
+    const double rho = m[0];
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (m[1 + a] + 0.5 * F[a]) / rho;
+    const double uf = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    (void)uf;
+
+    double ub[3] = {0.0, 0.0, 0.0};
+    double rhob = 0.0;
+
+    /* 5. forcing term Delta''_i = a_i (F.c_i / cs2 + Sigma : (c c - cs2 I) / (2 cs4)) */
+    double Sb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a) {
+            Fb[a] += nbs[i] * A[i] * CV[i][a] / CS2;
+            for (int b = 0; b < 3; ++b) {
+                const double dab = (a == b) ? 1.0 : 0.0;
+                Sb[a][b] += nbs[i] * A[i] * (CV[i][a] * CV[i][b] - CS2 * dab) / (2.0 * CS2 * CS2);
+            }
+        }
+    /* Sigma = As (u F + F u - (2/3) u.F I) + (1/3)(1 + gamma_bulk) u.F I */
+    const double As = 0.5 * (1.0 + p->gamma_shear);
+    const double Bs = -(2.0 / 3.0) * As + (1.0 / 3.0) * (1.0 + p->gamma_bulk);
+    const double trSb = Sb[0][0] + Sb[1][1] + Sb[2][2];
+    for (int g = 0; g < 3; ++g) {
+        double sF = 0.0, sTF = 0.0, su = 0.0, sTu = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            sF += Sb[g][a] * F[a];
+            sTF += Sb[a][g] * F[a];
+            su += Sb[g][a] * u[a];
+            sTu += Sb[a][g] * u[a];
+        }
+        ub[g] += As * (sF + sTF) + Bs * F[g] * trSb;
+        Fb[g] += As * (su + sTu) + Bs * u[g] * trSb;
+    }
+
+    /* 4. back-transformation n_pre_i = a_i sum_k e_ki m*_k / w_k */
+    double msb[Q];
+    for (int k = 0; k < Q; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += A[i] * E[k][i] * nbs[i];
+        msb[k] = s / WK[k];
+    }
+
+    /* 3. relaxation + noise */
+    double mb[Q], meqb[Q];
+    for (int k = 0; k < Q; ++k) {
+        meqb[k] = 0.0;
+        if (k < 4) {
+            mb[k] = msb[k];
+            continue;
+        }
+        mb[k] = gam[k] * msb[k];
+        meqb[k] = (1.0 - gam[k]) * msb[k];
+        if (p->kT > 0.0 && !p->noise_rho0) {
+            const double mu = p->kT / CS2;
+            const double phi = sqrt(1.0 - gam[k] * gam[k]);
+            rhob += msb[k] * sqrt(WK[k] * mu) * phi * gnoise[k - 4] * 0.5 / sqrt(rho);
+        }
+    }
+
+    /* 2. equilibrium moments m^eq = E n^eq(rho, u) */
+    for (int i = 0; i < Q; ++i) {
+        double neqb = 0.0;
+        for (int k = 4; k < Q; ++k) neqb += E[k][i] * meqb[k];
+        const double uc = u[0] * CV[i][0] + u[1] * CV[i][1] + u[2] * CV[i][2];
+        rhob += neqb * A[i] * (1.0 + uc / CS2 + uc * uc / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+        for (int a = 0; a < 3; ++a)
+            ub[a] += neqb * A[i] * rho * (CV[i][a] / CS2 + uc * CV[i][a] / (CS2 * CS2) - u[a] / CS2);
+    }
+
+    /* 1. u = (m_{1..3} + F/2) / rho, rho = m_0 */
+    for (int a = 0; a < 3; ++a) {
+        mb[1 + a] += ub[a] / rho;
+        Fb[a] += 0.5 * ub[a] / rho;
+        rhob -= ub[a] * u[a] / rho;
+    }
+    mb[0] += rhob;
+
+    /* 0. m = E n */
+    for (int i = 0; i < Q; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < Q; ++k) s += E[k][i] * mb[k];
+        nb[i] = s;
+    }
+}
+
+/* Adjoint of one orc_step.  n: pre-collision state at step `step`;
+ * lam: on entry the adjoint of the state after the step (pre-collision at
+ * step+1), on exit the adjoint of n.  Streaming n_i(r + c_i) = n*_i(r) is a
+ * permutation, so the adjoint of n* at r is lam_i(r + c_i).  extra: the
+ * extra force field of the step or NULL; its adjoint is accumulated into
+ * extra_bar ([3][N]) when not NULL.  gbar accumulates the adjoint of the
+ * uniform body force.  work: 19*N doubles of caller scratch. */
+void orc_step_adjoint(const orc_params *p, const double *n, double *lam, double *work, const double *extra,
+                      double *extra_bar, uint32_t step, double gbar[3])
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    double gsum[3] = {0.0, 0.0, 0.0};
+#pragma omp parallel
+    {
+        double gloc[3] = {0.0, 0.0, 0.0};
+#pragma omp for schedule(static)
+        for (int z = 0; z < p->nz; ++z)
+            for (int y = 0; y < p->ny; ++y)
+                for (int x = 0; x < p->nx; ++x) {
+                    const int64_t s = site_index(p, x, y, z);
+                    double ns[Q], nbs[Q], nb[Q], F[3], Fb[3] = {0.0, 0.0, 0.0}, gn[16];
+                    for (int i = 0; i < Q; ++i) {
+                        ns[i] = n[i * N + s];
+                        const int64_t d = site_index(p, wrap(x + CV[i][0], p->nx), wrap(y + CV[i][1], p->ny),
+                                                     wrap(z + CV[i][2], p->nz));
+                        nbs[i] = lam[i * N + d];
+                    }
+                    for (int a = 0; a < 3; ++a) F[a] = p->g[a] + (extra ? extra[a * N + s] : 0.0);
+                    if (p->kT > 0.0) orc_fluid_normals(p->seed, (uint32_t)s, step, p->box, gn);
+                    orc_collide_site_adjoint(p, ns, F, gn, nbs, nb, Fb);
+                    for (int i = 0; i < Q; ++i) work[i * N + s] = nb[i];
+                    for (int a = 0; a < 3; ++a) {
+                        gloc[a] += Fb[a];
+                        if (extra_bar) extra_bar[a * N + s] += Fb[a];
+                    }
+                }
+#pragma omp critical
+        for (int a = 0; a < 3; ++a) gsum[a] += gloc[a];
+    }
+    memcpy(lam, work, sizeof(double) * Q * (size_t)N);
+    for (int a = 0; a < 3; ++a) gbar[a] += gsum[a];
+}
+
+/* Reverse-mode gradient of a loss of the state after nsteps fluid steps
+ * (no particles), starting from n0 at step counter step0.  lam: on entry
+ * dL/dn(T), on exit dL/dn(0).  gbar: dL/dg (uniform body force) through the
+ * dynamics, accumulated.  Stores all intermediate states (plain and slow). */
+void orc_backward(const orc_params *p, const double *n0, int32_t nsteps, uint32_t step0, double *lam, double gbar[3])
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const size_t sz = sizeof(double) * Q * (size_t)N;
+    double *states = (double *)malloc(sz * (size_t)(nsteps > 0 ? nsteps : 1));
+    double *work = (double *)malloc(sz);
+    memcpy(states, n0, sz);
+    for (int32_t t = 0; t + 1 < nsteps; ++t) {
+        memcpy(states + (size_t)(t + 1) * Q * N, states + (size_t)t * Q * N, sz);
+        orc_step(p, states + (size_t)(t + 1) * Q * N, work, NULL, step0 + (uint32_t)t);
+    }
+    for (int32_t t = nsteps - 1; t >= 0; --t)
+        orc_step_adjoint(p, states + (size_t)t * Q * N, lam, work, NULL, NULL, step0 + (uint32_t)t, gbar);
+    free(work);
+    free(states);
+}

@@ -1,0 +1,107 @@
+"""Pins of the oracle's hand-written adjoint against central finite
+differences of the oracle's own forward map (FP64, eps = 1e-6, truncation
+O(eps^2)); the loss is a random linear functional of the final populations
+or the kinetic energy in a probe region (the loss of the differentiation
+form: mean |u|^2 over a sub-box, u = (sum n c + g/2)/rho)."""
+import numpy as np
+import pytest
+
+
+def test_collision_adjoint_is_transpose_of_jacobian(orc):
+    rng = np.random.default_rng(0)
+    p = orc.Params(nx=4, ny=4, nz=4, kT=1e-4, gamma_shear=0.3, gamma_bulk=-0.2, gamma_3a=0.1, gamma_3b=0.4,
+                   gamma_4a=-0.3, gamma_4b=0.6)
+    eps = 1e-6
+    for noise_rho0 in (False, True):
+        p.noise_rho0 = noise_rho0
+        for _ in range(10):
+            n = orc.equilibrium(1 + 0.05 * rng.normal(), rng.normal(scale=0.03, size=3)) + rng.normal(scale=1e-3,
+                                                                                                        size=19)
+            F = rng.normal(scale=1e-3, size=3)
+            g = rng.normal(size=16)
+            w = rng.normal(size=19)
+            v = rng.normal(size=19)
+            vF = rng.normal(size=3)
+            nb, Fb = orc.collide_site_adjoint(p, n, F, g, w)
+            fd = (w @ orc.collide_site(p, n + eps * v, F, g) - w @ orc.collide_site(p, n - eps * v, F, g)) / (2 * eps)
+            assert nb @ v == pytest.approx(fd, rel=1e-7, abs=1e-10)
+            fdF = (w @ orc.collide_site(p, n, F + eps * vF, g) - w @ orc.collide_site(p, n, F - eps * vF, g)) / (2 * eps)
+            assert Fb @ vF == pytest.approx(fdF, rel=1e-7, abs=1e-10)
+
+
+def _run(orc, p, n0, T):
+    n = n0.copy()
+    orc.run(p, n, T)
+    return n
+
+
+@pytest.mark.parametrize("noise_rho0", [False, True])
+def test_backward_matches_finite_differences_linear_loss(orc, noise_rho0):
+    rng = np.random.default_rng(1)
+    p = orc.Params(nx=3, ny=4, nz=5, kT=1e-4, seed=7, g=(1e-4, -2e-4, 5e-5), gamma_shear=0.2, gamma_bulk=0.1,
+                   gamma_3a=-0.1, gamma_3b=0.3, gamma_4a=0.2, gamma_4b=-0.4, noise_rho0=noise_rho0)
+    n0 = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 5, 4, 3)))
+    T = 6
+    w = rng.normal(size=n0.shape)
+    lam0, gbar = orc.backward(p, n0, T, w)
+    eps = 1e-6
+    for _ in range(3):
+        v = rng.normal(size=n0.shape)
+        fd = ((w * _run(orc, p, n0 + eps * v, T)).sum() - (w * _run(orc, p, n0 - eps * v, T)).sum()) / (2 * eps)
+        assert (lam0 * v).sum() == pytest.approx(fd, rel=1e-6)
+    for a in range(3):
+        gp, gm = list(p.g), list(p.g)
+        gp[a] += eps
+        gm[a] -= eps
+        pp = orc.Params(**{**p.__dict__, "g": tuple(gp)})
+        pm = orc.Params(**{**p.__dict__, "g": tuple(gm)})
+        fd = ((w * _run(orc, pp, n0, T)).sum() - (w * _run(orc, pm, n0, T)).sum()) / (2 * eps)
+        assert gbar[a] == pytest.approx(fd, rel=1e-6)
+
+
+def probe_loss(orc, p, n, lo, hi):
+    rho, u = orc.fields(p, n)
+    sl = (slice(None), slice(lo, hi), slice(lo, hi), slice(lo, hi))
+    return (u[sl] ** 2).sum(axis=0).mean()
+
+
+def probe_loss_grad(orc, p, n, lo, hi):
+    """dL/dn of L = mean over the probe of |u|^2 (u = J/rho, J = sum n c + g/2):
+    dL/dn_i = (2/P)(u.c_i - |u|^2)/rho, and dL/dg = (1/P) sum u/rho."""
+    c, a, e, w = orc.tables()
+    rho, u = orc.fields(p, n)
+    mask = np.zeros(rho.shape, bool)
+    mask[lo:hi, lo:hi, lo:hi] = True
+    P = mask.sum()
+    uc = np.einsum("ia,azyx->izyx", c.astype(float), u)
+    usq = (u ** 2).sum(axis=0)
+    grad = 2.0 / P * (uc - usq) / rho * mask
+    gdir = (u / rho * mask).sum(axis=(1, 2, 3)) / P
+    return grad, gdir
+
+
+def test_backward_probe_kinetic_energy_loss(orc):
+    rng = np.random.default_rng(2)
+    L = 6
+    p = orc.Params(nx=L, ny=L, nz=L, kT=1e-4, seed=3, g=(2e-4, 0.0, -1e-4))
+    n0 = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, L, L, L)))
+    T = 8
+    lo, hi = 2, 4
+    nT = _run(orc, p, n0, T)
+    lamT, g_direct = probe_loss_grad(orc, p, nT, lo, hi)
+    lam0, gbar = orc.backward(p, n0, T, lamT)
+    gbar = gbar + g_direct
+    eps = 1e-6
+    v = rng.normal(size=n0.shape)
+    fd = (probe_loss(orc, p, _run(orc, p, n0 + eps * v, T), lo, hi) -
+          probe_loss(orc, p, _run(orc, p, n0 - eps * v, T), lo, hi)) / (2 * eps)
+    assert (lam0 * v).sum() == pytest.approx(fd, rel=1e-6)
+    for a in range(3):
+        gp, gm = list(p.g), list(p.g)
+        gp[a] += eps
+        gm[a] -= eps
+        pp = orc.Params(**{**p.__dict__, "g": tuple(gp)})
+        pm = orc.Params(**{**p.__dict__, "g": tuple(gm)})
+        fd = (probe_loss(orc, pp, _run(orc, pp, n0, T), lo, hi) - probe_loss(orc, pm, _run(orc, pm, n0, T), lo, hi)) / (
+            2 * eps)
+        assert gbar[a] == pytest.approx(fd, rel=1e-5, abs=1e-12)
