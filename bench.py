@@ -39,14 +39,18 @@ K_BOND = 10.0 * KT
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_256.json")
 
 
+KERNEL_SOURCES = ("kernels.h", "collide.h", "rng.h")  # everything the fused step kernel is built from
+
+
 def source_hash() -> str:
+    """Hash of the sources of the fused stream-collide kernel; the committed
+    PMC traffic figure is used only while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_0803_2826_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -73,7 +73,9 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16 = 2, LB_F16 = 3 } lb_dtype;
  * noise_rho0: 0 = noise amplitude uses the local density rho = m_0,
  *   1 = uses rho0.
  * block: threads per block of the fused step kernel (64..1024, multiple of
- *   64); 0 selects 256.
+ *   64); 0 selects 256 for a single box; -1 (and 0 for a batch) lets the
+ *   library time the candidates on the first lb_step and keep the fastest
+ *   (see lb_launch_config).
  * track_totals: 1 = the step kernel also accumulates FP64 totals of mass and
  *   momentum every step (read with lb_totals); 0 = totals are computed on
  *   demand by lb_totals with a separate pass. */
@@ -90,6 +92,8 @@ typedef struct {
     int32_t block;
     int32_t track_totals;
     int32_t box_id;        /* fourth Philox counter word (replica index) */
+    int32_t vacf_lags;     /* batch only: lags R of the on-device ensemble VACF (0 = off, <= 1024) */
+    int32_t graph_steps;   /* batch only: steps per captured HIP graph (even, 0 = no graph) */
 } lb_params;
 
 /* Point particles with harmonic bonds (Sec. "Force coupling").
@@ -120,6 +124,38 @@ typedef struct lb_ctx lb_ctx;
  * Errors: LB_EINVAL (any extent < 2, N >= 2^31, |gamma| out of range,
  * kT < 0, rho0 <= 0, unknown storage, bad block), LB_ENOMEM, LB_EDEVICE. */
 int lb_create(const lb_params *params, void *stream, lb_ctx **out);
+
+/* Batched form: nbox independent periodic replica boxes of extents
+ * dims[3*b .. 3*b+2] (host array), all with the physical parameters of
+ * `params` (its extents are ignored).  Box b uses box id params->box_id + b
+ * as the fourth Philox counter word, so every replica draws its own noise.
+ * All boxes advance together: one persistent launch per step walks a list of
+ * (box, tile) work items; with graph_steps > 0 the launches of graph_steps
+ * steps are captured once into a HIP graph and replayed.  Populations of all
+ * boxes live in one allocation, box after box, each [19][N_b].  The context
+ * runs on its own stream, ordered after / before the caller's `stream` at the
+ * entry / exit of every call.  Bead coupling is not available on a batch
+ * (lb_couple returns LB_EUNSUPPORTED).  With vacf_lags = R > 0 every step also
+ * samples, per box, the lowest transverse Fourier modes of the momentum
+ * density (k = 2 pi / L_a along each axis a, the two components normal to a)
+ * and accumulates their autocorrelation on the device (read with lb_vacf).
+ * Layout of the batch forms of lb_init_equilibrium / lb_set_populations /
+ * lb_get_populations / lb_moments: box after box, each in the single-box
+ * layout.  Errors: as lb_create, plus LB_EINVAL for nbox < 1, a box extent
+ * < 2, a total site count >= 2^31, odd graph_steps or vacf_lags > 1024. */
+int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, void *stream, lb_ctx **out);
+
+/* Ensemble velocity autocorrelation of a batch: host out[nbox][vacf_lags],
+ * out[b][tau] = mean over samples t and the 6 modes of
+ * Re[j_hat(k, t + tau) conj(j_hat(k, t))] / (N_b kT rho0), which at gamma = 0
+ * should decay as lambda(k)^tau, lambda = 1 - (2/3) sin^2(k/2) (eq. LBE with
+ * the equipartition of eq. Pdistneq).  *nsamples receives the number of
+ * sampled steps.  Synchronises.  LB_EINVAL if the context has no VACF. */
+int lb_vacf(lb_ctx *ctx, double *out, int64_t *nsamples);
+
+/* Launch configuration in use: out[0] = threads per block, out[1] = blocks
+ * per step, out[2] = tiles per block (batch) or 1. */
+int lb_launch_config(lb_ctx *ctx, int32_t out[3]);
 
 /* Release all device memory of the context (synchronises its stream). */
 int lb_destroy(lb_ctx *ctx);
@@ -181,6 +217,24 @@ int lb_mode_stats(lb_ctx *ctx, double var[19]);
  * check the device generator against an independent implementation.
  * Errors: LB_EINVAL (out NULL, site range beyond N). */
 int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, float *out);
+
+/* Differentiation form.  lb_tape_begin starts recording at the current step:
+ * the state is checkpointed now and after every `checkpoint_every` steps
+ * (device copies of the population buffer, 19 * N * storage bytes each).
+ * lb_backward then returns, for the T steps taken since lb_tape_begin,
+ *   dL_dn_0 = dL/dn(t0) given dL_dn_T = dL/dn(t0 + T)   (device [19][N] of
+ *             `dtype` LB_F64 or LB_F32, full populations, natural layout),
+ *   dL_dg   = dL/dg through the dynamics (host out[3]; a loss that also
+ *             uses g directly adds that part itself),
+ * by reverse-mode differentiation of eq. LBE: the transpose of streaming
+ * and of the moment-space collision (eq. lco_update, eq. stochupdaterule1,
+ * eq. moment_two_external_force), segment by segment from the checkpoints
+ * with the states of a segment recomputed forward (checkpoint_every step
+ * buffers are allocated), the noise replayed from its Philox counters.
+ * Errors: LB_ESTATE (no tape), LB_EUNSUPPORTED (bead forces entered a taped
+ * step, or a batch context), LB_ENOMEM. */
+int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
+int lb_backward(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3]);
 
 /* Synchronise the context stream and report latched device errors. */
 int lb_sync(lb_ctx *ctx);

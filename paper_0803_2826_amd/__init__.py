@@ -7,11 +7,11 @@ include/lb.h; this package is the Python binding.
 """
 from ._lib import LBError, load  # noqa: F401
 
-__all__ = ["LBError", "load", "Lattice", "FluidParams", "DeviceBeads"]
+__all__ = ["LBError", "load", "Lattice", "BatchLattice", "FluidParams", "DeviceBeads"]
 
 
 def __getattr__(name):
-    if name in ("Lattice", "FluidParams", "DeviceBeads"):
+    if name in ("Lattice", "BatchLattice", "FluidParams", "DeviceBeads"):
         from . import lattice
         return getattr(lattice, name)
     raise AttributeError(name)

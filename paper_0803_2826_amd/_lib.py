@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", 
 EXPORTS = (
     "lb_create", "lb_destroy", "lb_init_equilibrium", "lb_set_populations", "lb_get_populations", "lb_step",
     "lb_couple", "lb_moments", "lb_totals", "lb_totals_exact", "lb_mode_stats", "lb_noise_sample", "lb_sync", "lb_step_count",
-    "lb_set_step_count", "lb_last_error",
+    "lb_set_step_count", "lb_last_error", "lb_create_batch", "lb_vacf", "lb_launch_config",
+    "lb_tape_begin", "lb_backward",
 )
 
 
@@ -48,6 +49,8 @@ class lb_params(ctypes.Structure):
         ("block", ctypes.c_int32),
         ("track_totals", ctypes.c_int32),
         ("box_id", ctypes.c_int32),
+        ("vacf_lags", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32),
     ]
 
 
@@ -98,6 +101,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.lb_step_count.argtypes = [vp]
     L.lb_step_count.restype = ctypes.c_uint64
     L.lb_set_step_count.argtypes = [vp, ctypes.c_uint64]
+    L.lb_create_batch.argtypes = [ctypes.POINTER(lb_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp,
+                                  ctypes.POINTER(vp)]
+    L.lb_vacf.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+    L.lb_launch_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.lb_tape_begin.argtypes = [vp, ctypes.c_int32]
+    L.lb_backward.argtypes = [vp, vp, ctypes.c_int32, vp, dp]
     L.lb_last_error.argtypes = [vp]
     L.lb_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

@@ -129,8 +129,12 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
         float out[Q];
         collide_site<THERMAL>(dd, cc.g, cc, s, step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        void *dstp[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) st_plane(dst + (size_t)i * N, s, S::st(out[i], 0.f));
+        for (int i = 0; i < Q; ++i) dstp[i] = dst + (size_t)i * N;
+        double mass;
+        float mom[3];
+        store_site<ST, false>(dstp, N * (uint32_t)sizeof(T), s, dd, out, mass, mom);
     }
     if (VACF && cur_box >= 0) flush_amp12(acc, a.amp + 12 * (size_t)cur_box);
 }

@@ -6,12 +6,17 @@
 // numerical step runs in the HIP kernels of this directory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/lb.h"
+#include "adjoint.h"
+#include "batch.h"
 #include "couple.h"
 
 using namespace lbmi;
@@ -19,7 +24,9 @@ using namespace lbmi;
 struct lb_ctx {
     lb_params p;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // stream all work of this context is enqueued on
+    hipStream_t user_stream = nullptr;  // caller's stream (differs from `stream` for a batch)
+    void *buf0 = nullptr;               // first allocated population buffer (graph parity)
     Geom geo{};
     CollideConst cc{};
     size_t elem = 4;
@@ -46,6 +53,34 @@ struct lb_ctx {
     int bead_cap = 0;
     bool pending_force = false;
     int pending_rows = 0;            // upper bound of touched nodes (8 per bead)
+    bool tuned = false;              // launch configuration chosen (autotune done or fixed)
+    // batched replicas
+    bool batch = false;
+    int nbox = 0;
+    std::vector<BoxDesc> boxes_h;
+    BoxDesc *boxes_d = nullptr;
+    uint32_t *tile_box = nullptr;    // [ntiles]
+    uint32_t ntiles = 0;
+    uint32_t chunk = 1;              // tiles per block
+    uint64_t total_sites = 0;
+    hipStream_t bstream = nullptr;   // private stream of a batch (graph capture)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    uint32_t *dstep = nullptr;       // [2]: device step counter, VACF sample count
+    float *amp = nullptr;            // [nbox][12]
+    float *ring = nullptr;           // [nbox][R][12]
+    double *corr = nullptr;          // [nbox][R]
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // per buffer parity
+    // differentiation (tape of checkpoints)
+    bool taping = false;
+    int tape_k = 0;
+    uint64_t tape_step0 = 0;
+    bool tape_force_used = false;
+    std::vector<void *> checkpoints;  // A-buffer copies at tape_step0 + s * tape_k
+    void *seg = nullptr;              // tape_k step buffers of one segment
+    size_t seg_bytes = 0;
+    float *lamA = nullptr, *lamB = nullptr;
+    double *gbar_d = nullptr;
+    double *adj_partials = nullptr;
     std::string err;
 };
 
@@ -112,8 +147,8 @@ int validate(const lb_params *p, std::string &msg)
         if (!(std::fabs(gk) <= 1.0)) { msg = "kinetic eigenvalues must satisfy |gamma| <= 1"; return LB_EINVAL; }
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p->body_force[c])) { msg = "body force must be finite"; return LB_EINVAL; }
-    if (p->block != 0 && (p->block < 64 || p->block > 1024 || (p->block % 64) != 0)) {
-        msg = "block must be 0 or a multiple of 64 in [64, 1024]";
+    if (p->block != 0 && p->block != -1 && (p->block < 64 || p->block > 1024 || (p->block % 64) != 0)) {
+        msg = "block must be 0, -1 or a multiple of 64 in [64, 1024]";
         return LB_EINVAL;
     }
     return LB_OK;
@@ -235,6 +270,265 @@ int ensure_bead_buffers(lb_ctx *c, int n)
     return LB_OK;
 }
 
+
+
+// ---------------------------------------------------------------------------
+// differentiation: checkpoints and the adjoint sweep
+// ---------------------------------------------------------------------------
+
+size_t state_bytes(const lb_ctx *c) { return (size_t)19 * c->geo.N * c->elem; }
+
+int push_checkpoint(lb_ctx *c)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, state_bytes(c)) != hipSuccess) return fail(c, LB_ENOMEM, "checkpoint allocation failed");
+    c->checkpoints.push_back(p);
+    return check(c, hipMemcpyAsync(p, c->bufA, state_bytes(c), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+}
+
+void free_tape(lb_ctx *c)
+{
+    for (void *p : c->checkpoints) (void)hipFree(p);
+    c->checkpoints.clear();
+    c->taping = false;
+}
+
+StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
+{
+    StepArgs a;
+    a.src = src;
+    a.dst = dst;
+    for (int i = 0; i < 19; ++i) {
+        a.srcp[i] = static_cast<const char *>(src) + (size_t)i * c->geo.N * c->elem;
+        a.dstp[i] = static_cast<char *>(dst) + (size_t)i * c->geo.N * c->elem;
+    }
+    a.geo = c->geo;
+    a.cc = c->cc;
+    a.step = step;
+    a.xcd_remap = 1;
+    a.partials = c->partials;
+    a.flags = c->flags;
+    a.fmask = nullptr;
+    a.force = nullptr;
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// batched replicas and launch-configuration search
+// ---------------------------------------------------------------------------
+
+// Orders the context's private stream after the caller's stream at entry and
+// the caller's stream after the private stream at exit (batch contexts only).
+struct Join {
+    lb_ctx *c;
+    explicit Join(lb_ctx *cc) : c(cc)
+    {
+        if (c && c->batch) {
+            (void)hipEventRecord(c->ev_in, c->user_stream);
+            (void)hipStreamWaitEvent(c->stream, c->ev_in, 0);
+        }
+    }
+    ~Join()
+    {
+        if (c && c->batch) {
+            (void)hipEventRecord(c->ev_out, c->stream);
+            (void)hipStreamWaitEvent(c->user_stream, c->ev_out, 0);
+        }
+    }
+};
+
+int batch_build_tiles(lb_ctx *c, int block)
+{
+    std::vector<uint32_t> tiles;
+    uint32_t first = 0;
+    for (int b = 0; b < c->nbox; ++b) {
+        BoxDesc &d = c->boxes_h[b];
+        const uint32_t nt = (d.geo.N + block - 1) / block;
+        d.first_tile = first;
+        for (uint32_t t = 0; t < nt; ++t) tiles.push_back((uint32_t)b);
+        first += nt;
+    }
+    c->ntiles = first;
+    (void)hipFree(c->tile_box);
+    c->tile_box = nullptr;
+    if (hipMalloc(&c->tile_box, tiles.size() * sizeof(uint32_t)) != hipSuccess)
+        return fail(c, LB_ENOMEM, "tile table allocation failed");
+    LB_TRY(check(c, hipMemcpyAsync(c->tile_box, tiles.data(), tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                   c->stream), "tile table upload"));
+    LB_TRY(check(c, hipMemcpyAsync(c->boxes_d, c->boxes_h.data(), c->boxes_h.size() * sizeof(BoxDesc),
+                                   hipMemcpyHostToDevice, c->stream), "box table upload"));
+    LB_TRY(check(c, hipStreamSynchronize(c->stream), "tile table sync"));
+    c->block = block;
+    return LB_OK;
+}
+
+template <int ST, bool TH, bool VA>
+void batch_launch_t(lb_ctx *c, const BatchArgs &a, unsigned grid)
+{
+    hipLaunchKernelGGL((k_batch_step<ST, TH, VA>), dim3(grid), dim3(c->block), 0, c->stream, a);
+}
+
+void batch_launch_step(lb_ctx *c, const void *src, void *dst, bool vacf)
+{
+    BatchArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.boxes = c->boxes_d;
+    a.tile_box = c->tile_box;
+    a.ntiles = c->ntiles;
+    a.chunk = c->chunk;
+    a.cc = c->cc;
+    a.step_ptr = c->dstep;
+    a.amp = c->amp;
+    a.flags = c->flags;
+    const unsigned grid = (c->ntiles + c->chunk - 1) / c->chunk;
+    c->nblocks = (int)grid;
+    by_storage(c->p.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        if (c->thermal) {
+            if (vacf) batch_launch_t<ST, true, true>(c, a, grid);
+            else batch_launch_t<ST, true, false>(c, a, grid);
+        } else {
+            if (vacf) batch_launch_t<ST, false, true>(c, a, grid);
+            else batch_launch_t<ST, false, false>(c, a, grid);
+        }
+    });
+}
+
+// One batched time step: fused step kernel, VACF sample, counter advance.
+void batch_enqueue_step(lb_ctx *c, const void *src, void *dst)
+{
+    const bool vacf = c->p.vacf_lags > 0;
+    batch_launch_step(c, src, dst, vacf);
+    if (vacf) {
+        const int R = c->p.vacf_lags;
+        hipLaunchKernelGGL(k_vacf_update, dim3(c->nbox), dim3(std::max(R, 64)), 0, c->stream, c->amp, c->ring, c->corr,
+                           R, c->dstep + 1);
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->dstep, c->dstep + 1, vacf ? 1 : 0);
+}
+
+float time_launches(lb_ctx *c, int reps, const std::function<void()> &launch)
+{
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    launch();  // warm-up
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps; ++r) launch();
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+// Launch-configuration search: each candidate runs the step kernel from A
+// into B (the state and the step counter are not advanced) and the fastest is
+// kept.  Batch: threads per block x blocks per step; single box: threads per
+// block.
+int autotune(lb_ctx *c)
+{
+    if (c->batch) {
+        const int blocks[] = {128, 256, 512, 1024};
+        const int per_cu[] = {2, 4, 8, 16};
+        float best = 1e30f;
+        int bb = 256;
+        uint32_t bc = 1;
+        for (int blk : blocks) {
+            LB_TRY(batch_build_tiles(c, blk));
+            for (int pc : per_cu) {
+                const uint32_t grid = 256u * (uint32_t)pc;
+                c->chunk = std::max<uint32_t>(1u, (c->ntiles + grid - 1) / grid);
+                const float ms = time_launches(c, 3, [&] { batch_launch_step(c, c->bufA, c->bufB, false); });
+                LB_LAUNCH_CHECK(c, "autotune batch");
+                if (ms < best) {
+                    best = ms;
+                    bb = blk;
+                    bc = c->chunk;
+                }
+            }
+        }
+        LB_TRY(batch_build_tiles(c, bb));
+        c->chunk = bc;
+        c->nblocks = (int)((c->ntiles + c->chunk - 1) / c->chunk);
+    } else {
+        const int blocks[] = {64, 128, 256, 512, 1024};
+        float best = 1e30f;
+        int bb = 256;
+        for (int blk : blocks) {
+            c->block = blk;
+            c->nblocks = (int)grid_for(c->geo.N, blk);
+            StepArgs a;
+            a.src = c->bufA;
+            a.dst = c->bufB;
+            for (int i = 0; i < 19; ++i) {
+                a.srcp[i] = static_cast<const char *>(c->bufA) + (size_t)i * c->geo.N * c->elem;
+                a.dstp[i] = static_cast<char *>(c->bufB) + (size_t)i * c->geo.N * c->elem;
+            }
+            a.geo = c->geo;
+            a.cc = c->cc;
+            a.step = (uint32_t)c->step;
+            a.xcd_remap = 1;
+            a.partials = c->partials;
+            a.flags = c->flags;
+            a.fmask = nullptr;
+            a.force = nullptr;
+            const bool tot = c->p.track_totals != 0;
+            const float ms = time_launches(c, 3, [&] {
+                by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, false); });
+            });
+            LB_LAUNCH_CHECK(c, "autotune");
+            if (ms < best) {
+                best = ms;
+                bb = blk;
+            }
+        }
+        c->block = bb;
+        c->nblocks = (int)grid_for(c->geo.N, bb);
+    }
+    c->tuned = true;
+    return LB_OK;
+}
+
+int batch_step(lb_ctx *c, int32_t nsteps)
+{
+    if (!c->tuned) LB_TRY(autotune(c));
+    const int G = c->p.graph_steps;
+    int32_t done = 0;
+    if (G > 0) {
+        while (nsteps - done >= G) {
+            const int par = (c->bufA == c->buf0) ? 0 : 1;
+            if (!c->graph_exec[par]) {
+                hipGraph_t g = nullptr;
+                LB_TRY(check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture"));
+                void *A = c->bufA, *B = c->bufB;
+                for (int k = 0; k < G; ++k) {
+                    batch_enqueue_step(c, A, B);
+                    std::swap(A, B);
+                }
+                LB_TRY(check(c, hipStreamEndCapture(c->stream, &g), "end capture"));
+                LB_TRY(check(c, hipGraphInstantiate(&c->graph_exec[par], g, nullptr, nullptr, 0), "instantiate"));
+                (void)hipGraphDestroy(g);
+            }
+            LB_TRY(check(c, hipGraphLaunch(c->graph_exec[par], c->stream), "graph launch"));
+            // G is even: the buffers are back in the same roles
+            done += G;
+            c->step += (uint64_t)G;
+        }
+    }
+    for (; done < nsteps; ++done) {
+        batch_enqueue_step(c, c->bufA, c->bufB);
+        LB_LAUNCH_CHECK(c, "batch step");
+        std::swap(c->bufA, c->bufB);
+        ++c->step;
+    }
+    c->totals_valid = false;
+    return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -253,6 +547,7 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
         return fail(nullptr, LB_EDEVICE, "no HIP device");
     }
     c->stream = static_cast<hipStream_t>(stream);
+    c->user_stream = c->stream;
     const uint32_t nx = params->nx, ny = params->ny, nz = params->nz;
     c->geo.nx = nx;
     c->geo.ny = ny;
@@ -262,16 +557,18 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     c->geo.div_nx = make_fastdiv(nx);
     c->geo.div_ny = make_fastdiv(ny);
     c->elem = storage_bytes(params->storage);
-    c->block = params->block ? params->block : 256;
+    c->block = params->block > 0 ? params->block : 256;
+    c->tuned = params->block != -1;
     c->nblocks = (int)grid_for(c->geo.N, c->block);
     fill_collide_const(c);
     const size_t bytes = (size_t)19 * c->geo.N * c->elem;
     if (hipMalloc(&c->bufA, bytes) != hipSuccess || hipMalloc(&c->bufB, bytes) != hipSuccess ||
-        hipMalloc(&c->partials, (size_t)c->nblocks * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->partials, (size_t)grid_for(c->geo.N, 64) * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->dev_out, 64 * sizeof(double)) != hipSuccess || hipMalloc(&c->flags, sizeof(int32_t)) != hipSuccess) {
         lb_destroy(c);
         return fail(nullptr, LB_ENOMEM, "device allocation failed");
     }
+    c->buf0 = c->bufA;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, c->flags, 1u);
     if (hipGetLastError() != hipSuccess) {
         lb_destroy(c);
@@ -281,15 +578,124 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     return LB_OK;
 }
 
+int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, void *stream, lb_ctx **out)
+{
+    std::string msg;
+    if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || !dims || nbox < 1) return fail(nullptr, LB_EINVAL, "need params, dims and nbox >= 1");
+    lb_params p = *params;
+    p.nx = dims[0];
+    p.ny = dims[1];
+    p.nz = dims[2];
+    const int v = validate(&p, msg);
+    if (v != LB_OK) return fail(nullptr, v, msg);
+    if (p.graph_steps < 0 || (p.graph_steps & 1)) return fail(nullptr, LB_EINVAL, "graph_steps must be even and >= 0");
+    if (p.vacf_lags < 0 || p.vacf_lags > 1024) return fail(nullptr, LB_EINVAL, "vacf_lags must be in [0, 1024]");
+    lb_ctx *c = new lb_ctx();
+    c->p = p;
+    c->batch = true;
+    c->nbox = nbox;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LB_EDEVICE, "no HIP device");
+    }
+    uint64_t off = 0;
+    for (int b = 0; b < nbox; ++b) {
+        const int32_t *e = dims + 3 * b;
+        if (e[0] < 2 || e[1] < 2 || e[2] < 2) {
+            delete c;
+            return fail(nullptr, LB_EINVAL, "every box extent must be >= 2");
+        }
+        const uint64_t Nb = (uint64_t)e[0] * e[1] * e[2];
+        if (Nb >= (1ull << 30)) {
+            delete c;
+            return fail(nullptr, LB_EINVAL, "box site count must be < 2^30");
+        }
+        BoxDesc d{};
+        d.geo.nx = e[0];
+        d.geo.ny = e[1];
+        d.geo.nz = e[2];
+        d.geo.nxny = (uint32_t)(e[0] * e[1]);
+        d.geo.N = (uint32_t)Nb;
+        d.geo.div_nx = make_fastdiv(e[0]);
+        d.geo.div_ny = make_fastdiv(e[1]);
+        d.off = off;
+        d.box_id = (uint32_t)(p.box_id + b);
+        d.inv_L[0] = 1.0f / (float)e[0];
+        d.inv_L[1] = 1.0f / (float)e[1];
+        d.inv_L[2] = 1.0f / (float)e[2];
+        c->boxes_h.push_back(d);
+        off += 19 * Nb;
+        c->total_sites += Nb;
+    }
+    if (c->total_sites >= (1ull << 31)) {
+        delete c;
+        return fail(nullptr, LB_EINVAL, "total site count must be < 2^31");
+    }
+    c->geo = c->boxes_h[0].geo;  // first box (diagnostic helpers loop over all boxes)
+    c->elem = storage_bytes(p.storage);
+    fill_collide_const(c);
+    c->user_stream = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)off * c->elem;
+    const int R = p.vacf_lags;
+    bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipMalloc(&c->bufA, bytes) == hipSuccess && hipMalloc(&c->bufB, bytes) == hipSuccess &&
+         hipMalloc(&c->boxes_d, nbox * sizeof(BoxDesc)) == hipSuccess &&
+         hipMalloc(&c->dstep, 2 * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc(&c->dev_out, 64 * sizeof(double)) == hipSuccess && hipMalloc(&c->flags, sizeof(int32_t)) == hipSuccess;
+    if (ok && R > 0)
+        ok = hipMalloc(&c->amp, (size_t)nbox * 12 * sizeof(float)) == hipSuccess &&
+             hipMalloc(&c->ring, (size_t)nbox * R * 12 * sizeof(float)) == hipSuccess &&
+             hipMalloc(&c->corr, (size_t)nbox * R * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        lb_destroy(c);
+        return fail(nullptr, LB_ENOMEM, "batch allocation failed");
+    }
+    c->buf0 = c->bufA;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, c->flags, 1u);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t *>(c->dstep), 2u);
+    if (R > 0) {
+        hipLaunchKernelGGL(k_zero_f32, dim3(64), dim3(256), 0, c->stream, c->amp, (size_t)nbox * 12);
+        hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->corr),
+                           (size_t)nbox * R * 2);
+    }
+    c->block = p.block > 0 ? p.block : 256;
+    c->tuned = p.block > 0;
+    if (batch_build_tiles(c, c->block) != LB_OK || hipGetLastError() != hipSuccess) {
+        const std::string e = c->err;
+        lb_destroy(c);
+        return fail(nullptr, LB_EDEVICE, "batch set-up failed: " + e);
+    }
+    c->chunk = std::max<uint32_t>(1u, (c->ntiles + 2047u) / 2048u);
+    c->nblocks = (int)((c->ntiles + c->chunk - 1) / c->chunk);
+    *out = c;
+    return LB_OK;
+}
+
 int lb_destroy(lb_ctx *c)
 {
     if (!c) return LB_OK;
     use_device(c);
     (void)hipStreamSynchronize(c->stream);
-    void *ptrs[] = {c->bufA, c->bufB, c->partials, c->scratch, c->dev_out, c->flags, c->force,
-                    c->fmask, c->list, c->count, c->half, c->fc};
+    void *ptrs[] = {c->bufA, c->bufB, c->partials, c->scratch, c->dev_out, c->flags, c->force, c->fmask,
+                    c->list,  c->count, c->half,     c->fc,      c->boxes_d, c->tile_box, c->dstep, c->amp,
+                    c->ring,  c->corr};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (int k = 0; k < 2; ++k)
+        if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
+    free_tape(c);
+    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials};
+    for (void *q : adj)
+        if (q) (void)hipFree(q);
+    if (c->batch) {
+        if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+        if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
+    }
     delete c;
     return LB_OK;
 }
@@ -298,6 +704,20 @@ int lb_init_equilibrium(lb_ctx *c, const double *rho, const double *u)
 {
     if (!c) return LB_EINVAL;
     LB_TRY(use_device(c));
+    Join j(c);
+    if (c->batch) {
+        uint64_t site0 = 0;
+        for (const BoxDesc &d : c->boxes_h) {
+            by_storage(c->p.storage, [&](auto st) {
+                hipLaunchKernelGGL((k_init_equilibrium<decltype(st)::value>), dim3(grid_for(d.geo.N, 256)), dim3(256), 0,
+                                   c->stream, static_cast<char *>(c->bufA) + d.off * c->elem, d.geo, c->p.rho0,
+                                   rho ? rho + site0 : nullptr, u ? u + 3 * site0 : nullptr);
+            });
+            site0 += d.geo.N;
+        }
+        LB_LAUNCH_CHECK(c, "init_equilibrium");
+        return LB_OK;
+    }
     by_storage(c->p.storage, [&](auto st) {
         hipLaunchKernelGGL((k_init_equilibrium<decltype(st)::value>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0,
                            c->stream, c->bufA, c->geo, c->p.rho0, rho, u);
@@ -313,15 +733,25 @@ int lb_set_populations(lb_ctx *c, const void *src, int32_t dtype, int32_t shifte
     if (!src) return fail(c, LB_EINVAL, "src is NULL");
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
     LB_TRY(use_device(c));
-    by_storage(c->p.storage, [&](auto st) {
-        constexpr int ST = decltype(st)::value;
-        if (dtype == LB_F64)
-            hipLaunchKernelGGL((k_set_pops<ST, double>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0, c->stream,
-                               c->bufA, c->geo, c->p.rho0, static_cast<const double *>(src), shifted);
-        else
-            hipLaunchKernelGGL((k_set_pops<ST, float>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0, c->stream,
-                               c->bufA, c->geo, c->p.rho0, static_cast<const float *>(src), shifted);
-    });
+    Join j(c);
+    const size_t isz = dtype == LB_F64 ? 8 : 4;
+    auto one = [&](void *buf, const Geom &g, const void *sp) {
+        by_storage(c->p.storage, [&](auto st) {
+            constexpr int ST = decltype(st)::value;
+            if (dtype == LB_F64)
+                hipLaunchKernelGGL((k_set_pops<ST, double>), dim3(grid_for(g.N, 256)), dim3(256), 0, c->stream, buf, g,
+                                   c->p.rho0, static_cast<const double *>(sp), shifted);
+            else
+                hipLaunchKernelGGL((k_set_pops<ST, float>), dim3(grid_for(g.N, 256)), dim3(256), 0, c->stream, buf, g,
+                                   c->p.rho0, static_cast<const float *>(sp), shifted);
+        });
+    };
+    if (c->batch) {
+        for (const BoxDesc &d : c->boxes_h)
+            one(static_cast<char *>(c->bufA) + d.off * c->elem, d.geo, static_cast<const char *>(src) + d.off * isz);
+    } else {
+        one(c->bufA, c->geo, src);
+    }
     LB_LAUNCH_CHECK(c, "set_populations");
     c->totals_valid = false;
     return LB_OK;
@@ -333,15 +763,25 @@ int lb_get_populations(lb_ctx *c, void *dst, int32_t dtype, int32_t shifted)
     if (!dst) return fail(c, LB_EINVAL, "dst is NULL");
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
     LB_TRY(use_device(c));
-    by_storage(c->p.storage, [&](auto st) {
-        constexpr int ST = decltype(st)::value;
-        if (dtype == LB_F64)
-            hipLaunchKernelGGL((k_get_pops<ST, double>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0, c->stream,
-                               c->bufA, c->geo, c->p.rho0, static_cast<double *>(dst), shifted);
-        else
-            hipLaunchKernelGGL((k_get_pops<ST, float>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0, c->stream,
-                               c->bufA, c->geo, c->p.rho0, static_cast<float *>(dst), shifted);
-    });
+    Join j(c);
+    const size_t isz = dtype == LB_F64 ? 8 : 4;
+    auto one = [&](const void *buf, const Geom &g, void *dp) {
+        by_storage(c->p.storage, [&](auto st) {
+            constexpr int ST = decltype(st)::value;
+            if (dtype == LB_F64)
+                hipLaunchKernelGGL((k_get_pops<ST, double>), dim3(grid_for(g.N, 256)), dim3(256), 0, c->stream, buf, g,
+                                   c->p.rho0, static_cast<double *>(dp), shifted);
+            else
+                hipLaunchKernelGGL((k_get_pops<ST, float>), dim3(grid_for(g.N, 256)), dim3(256), 0, c->stream, buf, g,
+                                   c->p.rho0, static_cast<float *>(dp), shifted);
+        });
+    };
+    if (c->batch) {
+        for (const BoxDesc &d : c->boxes_h)
+            one(static_cast<const char *>(c->bufA) + d.off * c->elem, d.geo, static_cast<char *>(dst) + d.off * isz);
+    } else {
+        one(c->bufA, c->geo, dst);
+    }
     LB_LAUNCH_CHECK(c, "get_populations");
     return LB_OK;
 }
@@ -353,6 +793,11 @@ int lb_step(lb_ctx *c, int32_t nsteps)
     if (nsteps == 0) return LB_OK;
     if (c->step + (uint64_t)nsteps > 0xffffffffull) return fail(c, LB_EINVAL, "step counter would exceed 2^32");
     LB_TRY(use_device(c));
+    if (c->batch) {
+        Join j(c);
+        return batch_step(c, nsteps);
+    }
+    if (!c->tuned) LB_TRY(autotune(c));
     const bool tot = c->p.track_totals != 0;
     for (int32_t t = 0; t < nsteps; ++t) {
         StepArgs a;
@@ -371,6 +816,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         a.fmask = c->fmask;
         a.force = c->force;
         const bool frc = c->pending_force;
+        if (frc && c->taping) c->tape_force_used = true;
         by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
         LB_LAUNCH_CHECK(c, "stream_collide");
         if (frc) {
@@ -382,6 +828,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         std::swap(c->bufA, c->bufB);
         ++c->step;
         c->totals_valid = tot;
+        if (c->taping && (c->step - c->tape_step0) % (uint64_t)c->tape_k == 0) LB_TRY(push_checkpoint(c));
     }
     return LB_OK;
 }
@@ -389,6 +836,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
 int lb_couple(lb_ctx *c, const lb_beads *b)
 {
     if (!c) return LB_EINVAL;
+    if (c->batch) return fail(c, LB_EUNSUPPORTED, "bead coupling is not available on a batch context");
     if (!b) return fail(c, LB_EINVAL, "beads is NULL");
     if (b->n < 0 || b->nbonds < 0) return fail(c, LB_EINVAL, "bead and bond counts must be >= 0");
     if (b->n > (1 << 26)) return fail(c, LB_EINVAL, "too many beads");
@@ -440,11 +888,23 @@ int lb_moments(lb_ctx *c, double *rho, double *u)
     if (!c) return LB_EINVAL;
     if (!rho && !u) return LB_OK;
     LB_TRY(use_device(c));
-    by_storage(c->p.storage, [&](auto st) {
-        hipLaunchKernelGGL((k_moments<decltype(st)::value>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0, c->stream,
-                           c->bufA, c->geo, c->p.rho0, c->p.body_force[0], c->p.body_force[1], c->p.body_force[2],
-                           rho, u);
-    });
+    Join j(c);
+    auto one = [&](const void *buf, const Geom &g, double *r, double *uu) {
+        by_storage(c->p.storage, [&](auto st) {
+            hipLaunchKernelGGL((k_moments<decltype(st)::value>), dim3(grid_for(g.N, 256)), dim3(256), 0, c->stream, buf,
+                               g, c->p.rho0, c->p.body_force[0], c->p.body_force[1], c->p.body_force[2], r, uu);
+        });
+    };
+    if (c->batch) {
+        uint64_t site0 = 0;
+        for (const BoxDesc &d : c->boxes_h) {
+            one(static_cast<const char *>(c->bufA) + d.off * c->elem, d.geo, rho ? rho + site0 : nullptr,
+                u ? u + 3 * site0 : nullptr);
+            site0 += d.geo.N;
+        }
+    } else {
+        one(c->bufA, c->geo, rho, u);
+    }
     LB_LAUNCH_CHECK(c, "moments");
     return LB_OK;
 }
@@ -468,6 +928,23 @@ int lb_totals_exact(lb_ctx *c, double out[4])
 {
     if (!c || !out) return LB_EINVAL;
     LB_TRY(use_device(c));
+    Join j(c);
+    if (c->batch) {
+        const int nbper = 64;
+        LB_TRY(ensure_scratch(c, (size_t)c->nbox * nbper * 4 * sizeof(double)));
+        for (int b = 0; b < c->nbox; ++b) {
+            const BoxDesc &d = c->boxes_h[b];
+            by_storage(c->p.storage, [&](auto st) {
+                hipLaunchKernelGGL((k_totals_exact<decltype(st)::value>), dim3(nbper), dim3(256), 0, c->stream,
+                                   static_cast<const char *>(c->bufA) + d.off * c->elem, d.geo,
+                                   c->scratch + (size_t)b * nbper * 4);
+            });
+        }
+        LB_LAUNCH_CHECK(c, "totals_exact");
+        LB_TRY(totals_from_partials(c, c->scratch, c->nbox * nbper, out));
+        out[0] += ((double)c->total_sites - (double)c->geo.N) * c->p.rho0;
+        return LB_OK;
+    }
     const int nb = 2048;
     LB_TRY(ensure_scratch(c, (size_t)nb * 4 * sizeof(double)));
     by_storage(c->p.storage, [&](auto st) {
@@ -481,7 +958,7 @@ int lb_totals_exact(lb_ctx *c, double out[4])
 int lb_totals(lb_ctx *c, double out[4])
 {
     if (!c || !out) return LB_EINVAL;
-    if (!c->totals_valid) return lb_totals_exact(c, out);
+    if (c->batch || !c->totals_valid) return lb_totals_exact(c, out);
     LB_TRY(use_device(c));
     return totals_from_partials(c, c->partials, c->nblocks, out);
 }
@@ -490,18 +967,33 @@ int lb_mode_stats(lb_ctx *c, double var[19])
 {
     if (!c || !var) return LB_EINVAL;
     LB_TRY(use_device(c));
-    const int nb = 1024;
-    LB_TRY(ensure_scratch(c, (size_t)nb * 38 * sizeof(double)));
-    by_storage(c->p.storage, [&](auto st) {
-        hipLaunchKernelGGL((k_mode_stats<decltype(st)::value>), dim3(nb), dim3(256), 0, c->stream, c->bufA, c->geo,
-                           c->p.rho0, c->scratch);
-    });
-    hipLaunchKernelGGL(k_reduce_cols, dim3(38), dim3(256), 0, c->stream, c->scratch, nb, 38, c->dev_out);
+    Join j(c);
+    int rows = 1024;
+    if (c->batch) {
+        const int nbper = 32;
+        rows = c->nbox * nbper;
+        LB_TRY(ensure_scratch(c, (size_t)rows * 38 * sizeof(double)));
+        for (int b = 0; b < c->nbox; ++b) {
+            const BoxDesc &d = c->boxes_h[b];
+            by_storage(c->p.storage, [&](auto st) {
+                hipLaunchKernelGGL((k_mode_stats<decltype(st)::value>), dim3(nbper), dim3(256), 0, c->stream,
+                                   static_cast<const char *>(c->bufA) + d.off * c->elem, d.geo, c->p.rho0,
+                                   c->scratch + (size_t)b * nbper * 38);
+            });
+        }
+    } else {
+        LB_TRY(ensure_scratch(c, (size_t)rows * 38 * sizeof(double)));
+        by_storage(c->p.storage, [&](auto st) {
+            hipLaunchKernelGGL((k_mode_stats<decltype(st)::value>), dim3(rows), dim3(256), 0, c->stream, c->bufA,
+                               c->geo, c->p.rho0, c->scratch);
+        });
+    }
+    hipLaunchKernelGGL(k_reduce_cols, dim3(38), dim3(256), 0, c->stream, c->scratch, rows, 38, c->dev_out);
     LB_LAUNCH_CHECK(c, "mode_stats");
     double h[38];
     LB_TRY(check(c, hipMemcpyAsync(h, c->dev_out, sizeof(h), hipMemcpyDeviceToHost, c->stream), "mode stats copy"));
     LB_TRY(read_flags(c));
-    const double N = (double)c->geo.N;
+    const double N = c->batch ? (double)c->total_sites : (double)c->geo.N;
     for (int k = 0; k < 19; ++k) {
         const double mean = h[k] / N;
         var[k] = h[19 + k] / N - mean * mean;
@@ -512,6 +1004,7 @@ int lb_mode_stats(lb_ctx *c, double var[19])
 int lb_noise_sample(lb_ctx *c, uint32_t site0, uint32_t count, uint32_t step, float *out)
 {
     if (!c) return LB_EINVAL;
+    if (c->batch) return fail(c, LB_EUNSUPPORTED, "noise sampling is per single box");
     if (!out) return fail(c, LB_EINVAL, "out is NULL");
     if ((uint64_t)site0 + count > c->geo.N) return fail(c, LB_EINVAL, "site range beyond N");
     if (count == 0) return LB_OK;
@@ -529,6 +1022,142 @@ int lb_sync(lb_ctx *c)
     return read_flags(c);
 }
 
+int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
+{
+    if (!c) return LB_EINVAL;
+    if (c->batch) return fail(c, LB_EUNSUPPORTED, "differentiation is per single box");
+    if (checkpoint_every < 1) return fail(c, LB_EINVAL, "checkpoint_every must be >= 1");
+    LB_TRY(use_device(c));
+    free_tape(c);
+    c->tape_k = checkpoint_every;
+    c->tape_step0 = c->step;
+    c->tape_force_used = false;
+    c->taping = true;
+    return push_checkpoint(c);
+}
+
+int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3])
+{
+    if (!c) return LB_EINVAL;
+    if (!c->taping) return fail(c, LB_ESTATE, "lb_backward needs lb_tape_begin before the steps");
+    if (c->tape_force_used) return fail(c, LB_EUNSUPPORTED, "the taped steps used bead forces (not differentiated)");
+    if (!dL_dn_T || !dL_dn_0) return fail(c, LB_EINVAL, "gradient arrays must be non-NULL");
+    if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
+    LB_TRY(use_device(c));
+    const size_t N = c->geo.N, n19 = 19 * N;
+    const uint64_t T = c->step - c->tape_step0;
+    const int K = c->tape_k;
+    const size_t sb = state_bytes(c);
+    if (c->seg_bytes < (size_t)K * sb) {
+        (void)hipFree(c->seg);
+        c->seg = nullptr;
+        c->seg_bytes = 0;
+        if (hipMalloc(&c->seg, (size_t)K * sb) != hipSuccess) return fail(c, LB_ENOMEM, "segment buffer allocation failed");
+        c->seg_bytes = (size_t)K * sb;
+    }
+    const unsigned nb = grid_for(N, 256);
+    if (!c->lamA) {
+        if (hipMalloc(&c->lamA, n19 * sizeof(float)) != hipSuccess || hipMalloc(&c->lamB, n19 * sizeof(float)) != hipSuccess ||
+            hipMalloc(&c->gbar_d, 3 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "adjoint buffers allocation failed");
+    }
+    if (dtype == LB_F64)
+        hipLaunchKernelGGL(k_to_f32<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double *>(dL_dn_T),
+                           c->lamA, n19);
+    else
+        hipLaunchKernelGGL(k_to_f32<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float *>(dL_dn_T),
+                           c->lamA, n19);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<float *>(c->gbar_d), (size_t)6);
+    LB_LAUNCH_CHECK(c, "backward set-up");
+    const int nseg = (int)((T + K - 1) / K);
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const uint64_t t0 = (uint64_t)sg * K;
+        const int len = (int)std::min<uint64_t>((uint64_t)K, T - t0);
+        char *seg = static_cast<char *>(c->seg);
+        LB_TRY(check(c, hipMemcpyAsync(seg, c->checkpoints[sg], sb, hipMemcpyDeviceToDevice, c->stream),
+                     "checkpoint restore"));
+        for (int k = 0; k + 1 < len; ++k) {
+            const StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb,
+                                               (uint32_t)(c->tape_step0 + t0 + k));
+            const unsigned saved = c->nblocks;
+            const int saved_block = c->block;
+            c->block = 256;
+            c->nblocks = (int)nb;
+            by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
+            c->block = saved_block;
+            c->nblocks = (int)saved;
+        }
+        LB_LAUNCH_CHECK(c, "backward recompute");
+        for (int k = len - 1; k >= 0; --k) {
+            AdjArgs aa;
+            aa.state = seg + (size_t)k * sb;
+            aa.lam_in = c->lamA;
+            aa.lam_out = c->lamB;
+            aa.geo = c->geo;
+            aa.cc = c->cc;
+            aa.step = (uint32_t)(c->tape_step0 + t0 + k);
+            aa.partials = c->adj_partials;
+            by_storage(c->p.storage, [&](auto st) {
+                constexpr int ST = decltype(st)::value;
+                if (c->thermal) hipLaunchKernelGGL((k_adjoint_step<ST, true>), dim3(nb), dim3(256), 0, c->stream, aa);
+                else hipLaunchKernelGGL((k_adjoint_step<ST, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+            });
+            hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3,
+                               c->gbar_d);
+            std::swap(c->lamA, c->lamB);
+        }
+        LB_LAUNCH_CHECK(c, "adjoint step");
+    }
+    if (dtype == LB_F64)
+        hipLaunchKernelGGL(k_from_f32<double>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
+                           static_cast<double *>(dL_dn_0), n19);
+    else
+        hipLaunchKernelGGL(k_from_f32<float>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
+                           static_cast<float *>(dL_dn_0), n19);
+    LB_LAUNCH_CHECK(c, "backward output");
+    double h[3] = {0, 0, 0};
+    LB_TRY(check(c, hipMemcpyAsync(h, c->gbar_d, sizeof(h), hipMemcpyDeviceToHost, c->stream), "gbar copy"));
+    LB_TRY(read_flags(c));
+    if (dL_dg)
+        for (int k = 0; k < 3; ++k) dL_dg[k] = h[k];
+    return LB_OK;
+}
+
+int lb_vacf(lb_ctx *c, double *out, int64_t *nsamples)
+{
+    if (!c || !out) return LB_EINVAL;
+    if (!c->batch || c->p.vacf_lags <= 0) return fail(c, LB_EINVAL, "context has no VACF (batch with vacf_lags > 0)");
+    LB_TRY(use_device(c));
+    const int R = c->p.vacf_lags;
+    std::vector<double> h((size_t)c->nbox * R);
+    uint32_t ns = 0;
+    LB_TRY(check(c, hipMemcpyAsync(h.data(), c->corr, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                 "vacf copy"));
+    LB_TRY(check(c, hipMemcpyAsync(&ns, c->dstep + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
+                 "vacf count copy"));
+    LB_TRY(read_flags(c));
+    const double kT = c->p.kT > 0.0 ? c->p.kT : 1.0;
+    for (int b = 0; b < c->nbox; ++b) {
+        const double norm = 6.0 * (double)c->boxes_h[b].geo.N * kT * c->p.rho0;
+        for (int t = 0; t < R; ++t) {
+            const double cnt = (double)ns - (double)t;
+            out[(size_t)b * R + t] = cnt > 0 ? h[(size_t)b * R + t] / (cnt * norm) : 0.0;
+        }
+    }
+    if (nsamples) *nsamples = ns;
+    return LB_OK;
+}
+
+int lb_launch_config(lb_ctx *c, int32_t out[3])
+{
+    if (!c || !out) return LB_EINVAL;
+    out[0] = c->block;
+    out[1] = c->batch ? (int32_t)((c->ntiles + c->chunk - 1) / c->chunk) : c->nblocks;
+    out[2] = c->batch ? (int32_t)c->chunk : 1;
+    return LB_OK;
+}
+
 uint64_t lb_step_count(const lb_ctx *c) { return c ? c->step : 0; }
 
 int lb_set_step_count(lb_ctx *c, uint64_t step)
@@ -536,6 +1165,12 @@ int lb_set_step_count(lb_ctx *c, uint64_t step)
     if (!c) return LB_EINVAL;
     if (step > 0xffffffffull) return fail(c, LB_EINVAL, "step counter must be < 2^32");
     c->step = step;
+    if (c->batch) {
+        LB_TRY(use_device(c));
+        Join j(c);
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, c->stream, c->dstep, (uint32_t)step);
+        LB_LAUNCH_CHECK(c, "set step");
+    }
     return LB_OK;
 }
 

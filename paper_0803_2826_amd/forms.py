@@ -1,0 +1,140 @@
+"""Measurement helpers of the three forms beside the plain FP32 path.
+
+precision_study  storage FP32 / BF16 / FP16 (shifted deviations, FP32
+                 collision arithmetic): decay rate of a shear wave and the
+                 stationary per-mode noise variances, each against its closed
+                 form, plus MLUPS.
+batch_study      many uneven replica boxes in one persistent launch per step
+                 (HIP graph replay): MLUPS and the ensemble VACF.
+
+The closed forms used as references (both pinned against the FP64 oracle in
+the test suite):
+  shear wave at gamma = 0: j_x(z, t) = A lambda^t sin(kz),
+      lambda = 1 - (2/3) sin^2(k/2);
+  stationary variance of mode k: mu w_k rho0 = 3 kT w_k rho0.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from .inputs import shear_wave
+from .lattice import BatchLattice, FluidParams, Lattice
+
+W_K = np.array([1, 1 / 3, 1 / 3, 1 / 3, 2 / 3, 4 / 3, 4 / 9, 1 / 9, 1 / 9, 1 / 9, 2 / 3, 2 / 3, 2 / 3, 2 / 9, 2 / 9, 2 / 9,
+                2, 4 / 3, 4 / 9])
+
+
+def _jx_mode(lat: Lattice, nz: int) -> float:
+    """Projection of the momentum density j_x on sin(2 pi z / nz)."""
+    rho, u = lat.moments()
+    jx = (u[0] * rho).mean(dim=(1, 2))  # [nz]
+    s = torch.sin(2 * math.pi * torch.arange(nz, device=jx.device, dtype=torch.float64) / nz)
+    return float((jx * s).sum() * 2.0 / nz)
+
+
+def decay_rate(storage: str, nx: int, ny: int, nz: int, steps: int, kT: float, amp: float = 0.01, seed: int = 0,
+               samples: int = 20):
+    """Fitted per-step decay rate of a shear wave (k = 2 pi / nz), noise
+    cancelled by subtracting a run with the same seed and no wave."""
+    runs = []
+    for a in (amp, 0.0):
+        p = FluidParams(nx=nx, ny=ny, nz=nz, storage=storage, kT=kT, seed=seed, track_totals=False)
+        lat = Lattice(p)
+        lat.init_equilibrium(u=shear_wave(nx, ny, nz, a))
+        series = [_jx_mode(lat, nz)]
+        per = steps // samples
+        for _ in range(samples):
+            lat.step(per)
+            series.append(_jx_mode(lat, nz))
+        lat.close()
+        runs.append(np.array(series))
+    diff = runs[0] - runs[1]
+    t = np.arange(samples + 1) * (steps // samples)
+    slope = np.polyfit(t, np.log(np.abs(diff)), 1)[0]
+    lam = 1 - (2 / 3) * math.sin(math.pi / nz) ** 2
+    exact = -math.log(lam)
+    return {"rate": -slope, "rate_exact": exact, "rel_err": (-slope - exact) / exact,
+            "amp_final": float(diff[-1]), "amp_final_exact": amp * lam ** t[-1]}
+
+
+def mode_variances(storage: str, L: int, kT: float, steps: int, seed: int = 1, samples: int = 10):
+    """Stationary per-mode variances / (3 kT w_k rho0)."""
+    p = FluidParams(nx=L, ny=L, nz=L, storage=storage, kT=kT, seed=seed, track_totals=False)
+    lat = Lattice(p)
+    lat.init_equilibrium()
+    lat.step(steps)
+    acc = np.zeros(19)
+    for _ in range(samples):
+        lat.step(5)
+        acc += np.array(lat.mode_stats())
+    lat.close()
+    return acc / samples / (3 * kT * W_K)
+
+
+def step_mlups(storage: str, L: int, kT: float, steps: int = 50) -> float:
+    p = FluidParams(nx=L, ny=L, nz=L, storage=storage, kT=kT, seed=0, track_totals=True)
+    lat = Lattice(p)
+    lat.init_equilibrium()
+    lat.step(5)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lat.close()
+    return L ** 3 / (ms * 1e-3) / 1e6
+
+
+def precision_study(decay_box=(8, 8, 512), decay_steps=2000, var_L=32, var_steps=300, kT=1e-4, mlups_L=256):
+    out = {}
+    for st in ("f32", "bf16", "f16"):
+        d = decay_rate(st, *decay_box, steps=decay_steps, kT=kT)
+        v = mode_variances(st, var_L, kT, var_steps)
+        out[st] = {"decay_rate_rel_err": d["rel_err"], "mode_var_ratio_max_dev": float(np.abs(v - 1).max()),
+                   "mode_var_ratio": [round(float(x), 4) for x in v],
+                   "mlups": step_mlups(st, mlups_L, kT) if mlups_L else None}
+    return out
+
+
+def edge_draws(nbox: int, seed: int = 0, choices=(24, 32, 40, 48, 64)):
+    """Replica box edges drawn uniformly from `choices` (seeded numpy PCG64)."""
+    rng = np.random.default_rng(seed)
+    e = rng.choice(np.asarray(choices), size=nbox)
+    return [(int(v), int(v), int(v)) for v in e]
+
+
+def batch_study(nbox: int = 512, steps: int = 500, kT: float = 1e-4, lags: int = 32, graph_steps: int = 10,
+                seed: int = 0, block: int = 0):
+    dims = edge_draws(nbox, seed)
+    p = FluidParams(nx=2, ny=2, nz=2, kT=kT, seed=seed, vacf_lags=lags, graph_steps=graph_steps, block=block)
+    B = BatchLattice(p, dims)
+    B.init_equilibrium()
+    B.step(graph_steps)  # launch-configuration search happens on the first step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(B.stream)
+    B.step(steps)
+    e1.record(B.stream)
+    torch.cuda.synchronize()
+    ms = max(e0.elapsed_time(e1), (time.perf_counter() - t0) * 1e3) / steps
+    C, ns = B.vacf()
+    cfg = B.launch_config()
+    edges = np.array([d[0] for d in dims])
+    by_L = {}
+    for Lb in sorted(set(edges.tolist())):
+        sel = edges == Lb
+        lam = 1 - (2 / 3) * math.sin(math.pi / Lb) ** 2
+        c = C[sel].mean(axis=0)
+        by_L[int(Lb)] = {"count": int(sel.sum()), "C0": float(c[0]), "C_ratio": [float(x) for x in (c / c[0])[:8]],
+                         "lambda_pow": [float(lam ** k) for k in range(8)]}
+    B.close()
+    return {"sites": int(sum(d[0] * d[1] * d[2] for d in dims)), "ms_per_step": ms,
+            "mlups": sum(d[0] * d[1] * d[2] for d in dims) / (ms * 1e-3) / 1e6, "launch": cfg, "samples": ns,
+            "vacf_by_edge": by_L}

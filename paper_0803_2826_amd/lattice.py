@@ -38,6 +38,8 @@ class FluidParams:
     block: int = 0
     track_totals: bool = True
     box_id: int = 0
+    vacf_lags: int = 0
+    graph_steps: int = 0
 
     @property
     def N(self) -> int:
@@ -58,6 +60,8 @@ class FluidParams:
         p.block = int(self.block)
         p.track_totals = 1 if self.track_totals else 0
         p.box_id = int(self.box_id)
+        p.vacf_lags = int(self.vacf_lags)
+        p.graph_steps = int(self.graph_steps)
         return p
 
 
@@ -206,6 +210,28 @@ class Lattice:
     def sync(self) -> None:
         self._check(self.L.lb_sync(self.ctx))
 
+    def tape_begin(self, checkpoint_every: int) -> None:
+        self._check(self.L.lb_tape_begin(self.ctx, int(checkpoint_every)))
+
+    def backward(self, dL_dnT: torch.Tensor):
+        """dL/dn(t0) and dL/dg for the steps taken since tape_begin."""
+        t = torch.as_tensor(dL_dnT, device=self.device)
+        if t.dtype not in (torch.float64, torch.float32):
+            t = t.to(torch.float64)
+        t = t.contiguous()
+        if t.numel() != Q * self.N:
+            raise ValueError("dL_dnT must have 19*N elements")
+        out = torch.empty_like(t)
+        gbar = (ctypes.c_double * 3)()
+        dt = LB_F64 if t.dtype == torch.float64 else LB_F32
+        self._check(self.L.lb_backward(self.ctx, t.data_ptr(), dt, out.data_ptr(), gbar))
+        return out.reshape(t.shape), [gbar[i] for i in range(3)]
+
+    def launch_config(self):
+        out = (ctypes.c_int32 * 3)()
+        self._check(self.L.lb_launch_config(self.ctx, out))
+        return tuple(out)
+
     @property
     def step_count(self) -> int:
         return int(self.L.lb_step_count(self.ctx))
@@ -213,3 +239,62 @@ class Lattice:
     @step_count.setter
     def step_count(self, v: int) -> None:
         self._check(self.L.lb_set_step_count(self.ctx, int(v)))
+
+
+class BatchLattice(Lattice):
+    """Many independent periodic replica boxes advanced together (one
+    persistent launch per step, optionally replayed from a HIP graph).
+
+    dims: sequence of (nx, ny, nz).  Box b uses Philox box id params.box_id + b.
+    Population / field arrays are concatenated box after box, each in the
+    single-box layout ([19][N_b] resp. [3][N_b])."""
+
+    def __init__(self, params: FluidParams, dims, stream: torch.cuda.Stream | None = None):
+        self.L = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbmi needs a GPU (torch.cuda.is_available() is False)")
+        self.params = params
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.sizes = [d[0] * d[1] * d[2] for d in self.dims]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._p = params.to_c()
+        flat = (ctypes.c_int32 * (3 * len(self.dims)))(*[v for d in self.dims for v in d])
+        ctx = ctypes.c_void_p()
+        rc = self.L.lb_create_batch(ctypes.byref(self._p), len(self.dims), flat,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != 0:
+            raise _lib.LBError(rc, self.L.lb_last_error(None).decode())
+        self.ctx = ctx
+
+    @property
+    def N(self) -> int:
+        return sum(self.sizes)
+
+    def get_populations(self, dtype=torch.float64, shifted: bool = False) -> torch.Tensor:
+        out = torch.empty(Q * self.N, dtype=dtype, device=self.device)
+        dt = LB_F64 if dtype == torch.float64 else LB_F32
+        self._check(self.L.lb_get_populations(self.ctx, out.data_ptr(), dt, 1 if shifted else 0))
+        return out
+
+    def split(self, flat: torch.Tensor, comps: int = Q):
+        """Split a concatenated per-box array into [comps, nz, ny, nx] views."""
+        outs, o = [], 0
+        for (nx, ny, nz), n in zip(self.dims, self.sizes):
+            outs.append(flat[o:o + comps * n].reshape(comps, nz, ny, nx))
+            o += comps * n
+        return outs
+
+    def moments(self):
+        rho = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        u = torch.empty(3 * self.N, dtype=torch.float64, device=self.device)
+        self._check(self.L.lb_moments(self.ctx, rho.data_ptr(), u.data_ptr()))
+        return rho, u
+
+    def vacf(self):
+        R = self.params.vacf_lags
+        out = (ctypes.c_double * (len(self.dims) * R))()
+        ns = ctypes.c_int64()
+        self._check(self.L.lb_vacf(self.ctx, out, ctypes.byref(ns)))
+        import numpy as np
+        return np.frombuffer(out, dtype=np.float64).reshape(len(self.dims), R).copy(), int(ns.value)

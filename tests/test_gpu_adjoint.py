@@ -1,0 +1,168 @@
+"""Differentiation form on the GPU (lb_tape_begin / lb_backward and the
+torch.autograd.Function), checked against the oracle's FP64 adjoint (itself
+pinned by central finite differences) and, at 128^3, against a central
+finite difference of the FP64 oracle forward along one random direction.
+
+Tolerance: the GPU computes forward and adjoint in FP32; each step rounds
+the adjoint at ~1e-7 relative and the rounding of T steps random-walks, so
+the gradient error relative to its largest entry is ~1e-7 sqrt(T) (<= 1e-5
+for T <= 1e4); bound 2e-5.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def lat():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_0803_2826_amd import lattice
+    return lattice
+
+
+def pair(orc, lat, nx, ny, nz, **kw):
+    po = orc.Params(nx=nx, ny=ny, nz=nz, **kw)
+    pd = lat.FluidParams(nx=nx, ny=ny, nz=nz, kT=po.kT, seed=po.seed, body_force=po.g, gamma_shear=po.gamma_shear,
+                         gamma_bulk=po.gamma_bulk, gamma_3a=po.gamma_3a, gamma_3b=po.gamma_3b,
+                         gamma_4a=po.gamma_4a, gamma_4b=po.gamma_4b, noise_rho0=po.noise_rho0, track_totals=False)
+    return po, pd
+
+
+@pytest.mark.parametrize("noise_rho0", [False, True])
+def test_gpu_adjoint_matches_oracle_adjoint(orc, lat, noise_rho0):
+    import torch
+    rng = np.random.default_rng(0)
+    po, pd = pair(orc, lat, 12, 10, 8, kT=1e-4, seed=5, g=(1e-4, -5e-5, 2e-5), gamma_shear=0.2, gamma_bulk=-0.1,
+                  gamma_3a=0.3, gamma_3b=-0.2, gamma_4a=0.1, gamma_4b=0.4, noise_rho0=noise_rho0)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, 8, 10, 12)))
+    T = 20
+    w = rng.normal(size=n0.shape)
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n0))
+    n0r = dev.get_populations().cpu().numpy()   # the device's rounded start
+    dev.tape_begin(7)                            # segments of 7, 7, 6 steps
+    dev.step(T)
+    dn0, dg = dev.backward(torch.from_numpy(w))
+    ref, gref = orc.backward(po, n0r, T, w)
+    err = np.abs(dn0.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"adjoint rel err {err:.2e}, dg {dg} vs {gref}")
+    assert err <= REL_TOL
+    np.testing.assert_allclose(dg, gref, rtol=REL_TOL * 10, atol=1e-6 * np.abs(gref).max())
+    dev.close()
+
+
+def test_checkpoint_interval_does_not_change_gradient(orc, lat):
+    import torch
+    rng = np.random.default_rng(1)
+    po, pd = pair(orc, lat, 10, 9, 8, kT=1e-4, seed=2)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, 8, 9, 10)))
+    w = torch.from_numpy(rng.normal(size=n0.shape))
+    outs = []
+    for K in (1, 4, 13, 100):
+        dev = lat.Lattice(pd)
+        dev.set_populations(torch.from_numpy(n0))
+        dev.tape_begin(K)
+        dev.step(13)
+        outs.append(dev.backward(w))
+        dev.close()
+    for dn, dg in outs[1:]:
+        assert torch.equal(dn, outs[0][0])
+        assert dg == outs[0][1]
+
+
+def velocity_table(device):
+    import torch
+    c = [[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 0], [-1, -1, 0],
+         [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1],
+         [0, -1, 1]]
+    return torch.tensor(c, dtype=torch.float64, device=device)
+
+
+def probe_loss_torch(nT, g, lo, hi):
+    """Mean |u|^2 over a probe sub-box, u = (sum n c + g/2)/rho."""
+    import torch
+    c = velocity_table(nT.device)
+    J = torch.einsum("ia,izyx->azyx", c, nT) + 0.5 * g.reshape(3, 1, 1, 1)
+    rho = nT.sum(0)
+    u = J / rho
+    return (u[:, lo:hi, lo:hi, lo:hi] ** 2).sum(0).mean()
+
+
+def test_autograd_probe_loss_matches_oracle(orc, lat):
+    import torch
+    from paper_0803_2826_amd.autograd import rollout
+    import test_oracle_adjoint as toa
+    rng = np.random.default_rng(3)
+    L = 12
+    po, pd = pair(orc, lat, L, L, L, kT=1e-4, seed=9, g=(2e-4, 0.0, -1e-4))
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, L, L, L)))
+    T, lo, hi = 30, 4, 8
+    n0_t = torch.tensor(n0, device="cuda", requires_grad=True)
+    g_t = torch.tensor(po.g, dtype=torch.float64, device="cuda", requires_grad=True)
+    nT = rollout(n0_t, g_t, pd, T, checkpoint_every=10)
+    loss = probe_loss_torch(nT, g_t, lo, hi)
+    loss.backward()
+    # oracle: forward, loss gradient, FP64 adjoint
+    nT_ref = n0.copy()
+    orc.run(po, nT_ref, T)
+    lamT, g_direct = toa.probe_loss_grad(orc, po, nT_ref, lo, hi)
+    lam0, gbar = orc.backward(po, n0, T, lamT)
+    err = np.abs(n0_t.grad.cpu().numpy() - lam0).max() / np.abs(lam0).max()
+    print(f"probe-loss gradient rel err {err:.2e}")
+    assert err <= REL_TOL
+    np.testing.assert_allclose(g_t.grad.cpu().numpy(), gbar + g_direct, rtol=1e-4)
+
+
+def test_backward_error_paths(orc, lat):
+    import torch
+    from paper_0803_2826_amd._lib import LB_ESTATE, LB_EUNSUPPORTED, LBError
+    dev = lat.Lattice(lat.FluidParams(nx=8, ny=8, nz=8, kT=1e-4))
+    dev.init_equilibrium()
+    dev.step(2)
+    with pytest.raises(LBError) as ei:
+        dev.backward(torch.zeros(19 * 512, dtype=torch.float64))
+    assert ei.value.code == LB_ESTATE
+    dev.tape_begin(4)
+    beads = lat.DeviceBeads(np.array([[1.5, 2.5, 3.5]]), np.zeros((1, 3)), np.ones(1), np.ones(1))
+    dev.coupled_step(beads)
+    with pytest.raises(LBError) as ei:
+        dev.backward(torch.zeros(19 * 512, dtype=torch.float64))
+    assert ei.value.code == LB_EUNSUPPORTED
+    dev.close()
+
+
+@pytest.mark.slow
+def test_full_size_directional_derivative(orc, lat):
+    """128^3 (the differentiation workload's box), 10 steps: <dL/dn0, v> from the
+    GPU adjoint against a central difference of the FP64 oracle forward
+    (eps = 1e-4 along a unit-scale random v; truncation O(eps^2))."""
+    import torch
+    L, T = 128, 10
+    rng = np.random.default_rng(4)
+    po, pd = pair(orc, lat, L, L, L, kT=1e-4, seed=1, g=(1e-5, 0.0, 0.0))
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.01, size=(3, L, L, L)))
+    w = rng.normal(size=n0.shape)
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n0))
+    n0 = dev.get_populations().cpu().numpy()
+    dev.tape_begin(5)
+    dev.step(T)
+    dn0, _ = dev.backward(torch.from_numpy(w))
+    dev.close()
+    v = rng.normal(size=n0.shape) * 1e-3
+    eps = 1e-4
+
+    def fwd(x):
+        y = x.copy()
+        orc.run(po, y, T)
+        return (w * y).sum()
+    fd = (fwd(n0 + eps * v) - fwd(n0 - eps * v)) / (2 * eps)
+    got = (dn0.cpu().numpy() * v).sum()
+    print(f"directional derivative: gpu {got:.10e} fd {fd:.10e}")
+    assert got == pytest.approx(fd, rel=1e-4)
