@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         float rhob = 0.f;
         if (THERMAL && !a.cc.noise_rho0) {
             float r[15];
-            fluid_normals(s, a.step, a.cc.box, a.cc.key0, a.cc.key1, r);
+            fluid_normals(s, a.step, a.cc.box, a.cc.key0, a.cc.key1, 1.0f, r);
             const float h = 0.5f / __builtin_amdgcn_sqrtf(rho);
 #pragma unroll
             for (int k = 4; k <= 18; ++k) rhob += mb[k] * a.cc.sig[k] * r[k - 4];
@@ -125,14 +125,17 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         Fbs[0] = mb[1];
         Fbs[1] = mb[2];
         Fbs[2] = mb[3];
-        // stress modes: equilibrium (weight 1 - gamma) and force moments (weight (1 + gamma)/2)
+        // stress modes: equilibrium (weight 1 - gamma) and force moments (weight (1 + gamma)/2).
+        // Each meq_k is written as a product of j and u with u held separately
+        // (m4 = j.u, m5 = 2 jx ux - jy uy - jz uz, m6 = jy uy - jz uz, m7 = jx uy,
+        // m8 = jy uz, m9 = jz ux); the chain rule through u = j / rho follows.
         float e[10], f[10];
 #pragma unroll
         for (int k = 4; k <= 9; ++k) {
             e[k] = (1.f - a.cc.gam[k]) * mb[k];
             f[k] = 0.5f * (1.f + a.cc.gam[k]) * mb[k];
         }
-        float jbx = e[4] * ux + 2.f * e[5] * ux + e[7] * uy + e[9] * uz;
+        float jbx = e[4] * ux + 2.f * e[5] * ux + e[7] * uy;
         float jby = e[4] * uy - e[5] * uy + e[6] * uy + e[8] * uz;
         float jbz = e[4] * uz - e[5] * uz - e[6] * uz + e[9] * ux;
         float ubx = e[4] * jx + 2.f * e[5] * jx + e[9] * jz;

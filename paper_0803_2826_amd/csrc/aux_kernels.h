@@ -242,7 +242,7 @@ __global__ void k_noise_sample(uint32_t site0, uint32_t count, uint32_t step, Co
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
     float r[15];
-    fluid_normals(site0 + t, step, cc.box, cc.key0, cc.key1, r);
+    fluid_normals(site0 + t, step, cc.box, cc.key0, cc.key1, 1.0f, r);
     for (int k = 0; k < 15; ++k) out[(size_t)t * 15 + k] = r[k];
 }
 

@@ -137,11 +137,12 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     for (int k = 10; k <= 18; ++k) ms[k] = cc.gam[k] * m[k];
 
     if (THERMAL) {
+        // r_k sqrt(rho_n): the density factor of the amplitude rides on the
+        // Box-Muller radius
         float r[15];
-        fluid_normals(site, step, cc.box, cc.key0, cc.key1, r);
-        const float srho = cc.noise_rho0 ? cc.sqrt_rho0 : __builtin_amdgcn_sqrtf(rho);
+        fluid_normals(site, step, cc.box, cc.key0, cc.key1, cc.noise_rho0 ? cc.rho0 : rho, r);
 #pragma unroll
-        for (int k = 4; k <= 18; ++k) ms[k] += (cc.sig[k] * srho) * r[k - 4];
+        for (int k = 4; k <= 18; ++k) ms[k] += cc.sig[k] * r[k - 4];
     }
 
     // ---- back-transformation: scale by 1/w_k, then pair even/odd parts

@@ -45,27 +45,30 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 // -2 ln(2): turns log2 into -2 ln for the Box-Muller radius.
 #define LBMI_M2LN2 (-1.38629436111989061883f)
 
-__device__ __forceinline__ float bm_radius(uint32_t field24)
+// Box-Muller radius times sqrt(scale): sqrt(-2 ln(ua) * scale), with the
+// factor -2 ln 2 * scale (log2 -> ln) passed in as m2ln2_scale.
+__device__ __forceinline__ float bm_radius(uint32_t field24, float m2ln2_scale)
 {
     const float ua = (float)(field24 + 1u) * 0x1p-24f;  // (0, 1], exact
-    return __builtin_amdgcn_sqrtf(LBMI_M2LN2 * __builtin_amdgcn_logf(ua));
+    return __builtin_amdgcn_sqrtf(m2ln2_scale * __builtin_amdgcn_logf(ua));
 }
 
-__device__ __forceinline__ void box_muller(uint32_t fa, uint32_t fb, float &g0, float &g1)
+__device__ __forceinline__ void box_muller(uint32_t fa, uint32_t fb, float m2ln2_scale, float &g0, float &g1)
 {
-    const float r = bm_radius(fa);
+    const float r = bm_radius(fa, m2ln2_scale);
     const float ub = (float)fb * 0x1p-24f;  // [0, 1), revolutions
     g0 = r * __builtin_amdgcn_cosf(ub);
     g1 = r * __builtin_amdgcn_sinf(ub);
 }
 
-// Fifteen Gaussians g[0..14] for modes 4..18 at (site, step, box).  Three
-// Philox calls give words w[0..11]; each group of three words (a, b, c)
-// yields 24-bit fields a>>8, b>>8, c>>8 and (a&255)|(b&255)<<8|(c&255)<<16;
-// fields (2p, 2p+1) feed Box-Muller pair p.
+// Fifteen Gaussians g[0..14] for modes 4..18 at (site, step, box), each
+// multiplied by sqrt(scale).  Three Philox calls give words w[0..11]; each
+// group of three words (a, b, c) yields 24-bit fields a>>8, b>>8, c>>8 and
+// (a&255)|(b&255)<<8|(c&255)<<16; fields (2p, 2p+1) feed Box-Muller pair p.
 __device__ __forceinline__ void fluid_normals(uint32_t site, uint32_t step, uint32_t box, uint32_t k0, uint32_t k1,
-                                              float g[15])
+                                              float scale, float g[15])
 {
+    const float c = LBMI_M2LN2 * scale;
     const Philox4 A = philox4x32_10(site, step, 0u, box, k0, k1);
     const Philox4 B = philox4x32_10(site, step, 1u, box, k0, k1);
     const Philox4 C = philox4x32_10(site, step, 2u, box, k0, k1);
@@ -80,9 +83,9 @@ __device__ __forceinline__ void fluid_normals(uint32_t site, uint32_t step, uint
         f[4 * grp + 3] = (a & 0xffu) | ((b & 0xffu) << 8) | ((c & 0xffu) << 16);
     }
 #pragma unroll
-    for (int p = 0; p < 7; ++p) box_muller(f[2 * p], f[2 * p + 1], g[2 * p], g[2 * p + 1]);
+    for (int p = 0; p < 7; ++p) box_muller(f[2 * p], f[2 * p + 1], c, g[2 * p], g[2 * p + 1]);
     // last pair: only the cosine output is used
-    g[14] = bm_radius(f[14]) * __builtin_amdgcn_cosf((float)f[15] * 0x1p-24f);
+    g[14] = bm_radius(f[14], c) * __builtin_amdgcn_cosf((float)f[15] * 0x1p-24f);
 }
 
 // Three Gaussians for the Langevin noise of one bead (double precision
