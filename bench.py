@@ -3,18 +3,27 @@
 
 One step = the whole hot path on the 256^3 workload: bead half-drift, bond
 forces, trilinear interpolation, Langevin momentum update and spreading for
-64 chains x 32 beads, then the fused pull-stream + MRT collision with thermal
-noise and forcing over all 16.8M sites, the re-collision of the bead-touched
-nodes, and the fused FP64 mass/momentum totals.  Inputs are synthetic
-(seeded), resident in HBM before the timed region.
+64 chains x 32 beads into the force field and its site bitmap, then the fused
+pull-stream + MRT collision with thermal noise and forcing (body force plus
+the bead force at bitmap-marked sites) over all 16.8M sites, with fused FP64
+mass/momentum totals, and the clear of the touched force rows.  Inputs are
+synthetic (seeded), resident in HBM before the timed region.
 
-Prints ONE JSON line (the driver's contract) with, beside the throughput:
-  roofline      the dominant kernel (fused stream-collide): algorithmic bytes
-                (19 reads + 19 writes of a 4-byte population per site) per
-                launch over its average launch duration, timed with events
-                on the launch stream, against the 8 TB/s HBM peak;
+Prints ONE JSON line with, beside the throughput:
+  roofline      the dominant kernel (fused stream-collide, bead-force
+                variant): algorithmic bytes per launch (19 reads + 19 writes
+                of a 4-byte population per site, plus the 1-bit-per-site
+                force bitmap) over its average duration, timed with events
+                on the launch stream around each step's launch inside the
+                timed region, against the 8 TB/s HBM peak;
   cpu_baseline  the FP64 oracle on the host cores, timed on a bounded sample
-                of the same workload (a few coupled steps of the full box).
+                of the same workload (a few coupled steps of the full box);
+  forms         the other throughputs the metric names: BF16-storage MLUPS
+                (nearest and stochastic rounding) on the same box without
+                beads, the batched form (512 replica boxes, edges drawn from
+                {24, 32, 40, 48, 64}, HIP graph replay) and the
+                differentiation form (taped forward and adjoint, 128^3, 500
+                steps, checkpoints every 50).
 """
 from __future__ import annotations
 
@@ -60,9 +69,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=256, help="box edge (default: the 256^3 workload)")
-    ap.add_argument("--kernel-steps", type=int, default=200, help="launches timed for the dominant kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
     return ap.parse_args()
 
 
@@ -96,6 +105,45 @@ def cpu_baseline(L: int, n_chains: int, length: int, steps: int):
     }
 
 
+def run_forms(L: int) -> dict:
+    """Throughputs of the precision, batched and differentiation forms (each
+    after its own warm-up, timed with events on the context stream)."""
+    import torch
+
+    from paper_0803_2826_amd import forms, lattice
+
+    out = {}
+    for st, rd in (("bf16", "nearest"), ("bf16", "stochastic")):
+        out[f"{st}_{rd}_mlups"] = round(forms.step_mlups(st, L, KT, steps=100, rounding=rd), 1)
+    print("# forms: precision done", file=sys.stderr, flush=True)
+    b = forms.batch_study(nbox=512, steps=200, kT=KT, lags=0, graph_steps=10)
+    out["batched_mlups"] = round(b["mlups"], 1)
+    out["batched_sites"] = b["sites"]
+    print("# forms: batch done", file=sys.stderr, flush=True)
+    Lb, T, K = 128, 500, 50
+    p = lattice.FluidParams(nx=Lb, ny=Lb, nz=Lb, kT=KT, seed=0, body_force=(1e-5, 0.0, 0.0), track_totals=False)
+    lat = lattice.Lattice(p)
+    lat.init_equilibrium()
+    lat.step(2)
+    w = torch.randn(19 * Lb ** 3, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record(lat.stream)
+    lat.tape_begin(K)
+    lat.step(T)
+    e[1].record(lat.stream)
+    lat.backward(w)
+    e[2].record(lat.stream)
+    torch.cuda.synchronize()
+    lat.close()
+    fwd_ms, bwd_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    out["taped_forward_mlups"] = round(Lb ** 3 * T / (fwd_ms * 1e-3) / 1e6, 1)
+    out["backward_mlups"] = round(Lb ** 3 * T / (bwd_ms * 1e-3) / 1e6, 1)
+    out["backward_config"] = f"{Lb}^3, {T} steps, checkpoints every {K}, FP32"
+    print("# forms: backward done", file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -112,7 +160,7 @@ def main() -> int:
     L = args.L
     n_chains, length = 64, 32
     N = L ** 3
-    pd = lattice.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=1e-4, seed=0, track_totals=True)
+    pd = lattice.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=KT, seed=0, track_totals=True, block=-1)
     lat = lattice.Lattice(pd)
     lat.init_equilibrium()
     pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed=0)
@@ -121,6 +169,9 @@ def main() -> int:
     tot0 = lat.totals(exact=True)
     stream = lat.stream
 
+    # warm-up (the first steps with and without bead force search the launch
+    # configuration of their kernel variant)
+    lat.step(1)
     for _ in range(args.warmup):
         lat.coupled_step(beads)
     torch.cuda.synchronize()
@@ -128,36 +179,31 @@ def main() -> int:
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
-        lat.coupled_step(beads)
+    for k0, k1 in kev:
+        lat.couple(beads)
+        k0.record(stream)
+        lat.step(1)
+        k1.record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
-    mlups = N * args.steps / (ms_per_step * args.steps * 1e-3) / 1e6
-    print(f"# timed {args.steps} steps: {ms_per_step:.4f} ms/step, {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+    mlups = N / (ms_per_step * 1e-3) / 1e6
+    kern_ms = sum(k0.elapsed_time(k1) for k0, k1 in kev) / args.steps
+    print(f"# timed {args.steps} steps: {ms_per_step:.4f} ms/step, {mlups:.0f} MLUPS; fused kernel {kern_ms:.4f} ms",
+          file=sys.stderr, flush=True)
 
     tot1 = lat.totals()
     tot1x = lat.totals(exact=True)
     lat.sync()
+    cfg = lat.launch_config(force=True)
 
-    # dominant kernel: back-to-back fused stream-collide launches (no bead
-    # force pending, so each lb_step(1) is exactly one launch of that kernel)
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    lat.step(5)
-    torch.cuda.synchronize()
-    k0.record(stream)
-    for _ in range(args.kernel_steps):
-        lat.step(1)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = k0.elapsed_time(k1) / args.kernel_steps
-    alg_bytes = 2 * 19 * 4 * N
+    alg_bytes = 2 * 19 * 4 * N + N // 8
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -167,11 +213,14 @@ def main() -> int:
             traffic = tr.get("traffic_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_stream_collide<f32,thermal,totals>", "kernel_ms": round(kern_ms, 5),
-                "alg_bytes_per_launch": alg_bytes}
+                "kernel": "k_stream_collide<f32,thermal,totals,force>", "kernel_ms": round(kern_ms, 5),
+                "alg_bytes_per_launch": alg_bytes,
+                "launch": {"threads": cfg[0], "blocks": cfg[1], "xcd_map": cfg[3]}}
     lat.close()
     del lat
     torch.cuda.empty_cache()
+
+    forms = None if args.no_forms else run_forms(L)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -197,6 +246,7 @@ def main() -> int:
                    "sites": N, "beads": nb, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "mass_drift_rel": (tot1x[0] - tot0[0]) / tot0[0],
         "fused_vs_exact_totals_abs": max(abs(a - b) for a, b in zip(tot1, tot1x)),
         "source_hash": source_hash(),

@@ -56,6 +56,23 @@ enum {
 /* Storage type of populations (the collision always computes in FP32). */
 typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16 = 2, LB_F16 = 3 } lb_dtype;
 
+/* Rounding of the step kernels' 16-bit stores.
+ * LB_ROUND_NEAREST: round to nearest even.  Every step rounds every stored
+ *   deviation, and with thermally dithered values this shrinks each
+ *   population's mean by the factor 1 - u^2 / (32 ln 2) per step, u the
+ *   relative spacing (2^-7 BF16, 2^-10 FP16): an extra damping of all
+ *   hydrodynamic modes of 2.7e-6 (BF16) or 4.3e-8 (FP16) per step, to be
+ *   compared with the viscous rate nu k^2 (Sec. "D3Q19 model III": the shear
+ *   wave rate of a 512 box is 2.5e-5 per step).
+ * LB_ROUND_STOCHASTIC: unbiased stochastic rounding with 6-bit probability
+ *   resolution (a value is stored as one of its two representable
+ *   neighbours, the one away from zero with probability equal, to within
+ *   1/64, to its position between them, and exactly so on average over the
+ *   FP32 values between them); the random bits come from Philox4x32-10 with counter
+ *   (site, step, 3 << 16, box) and key seed, so runs stay reproducible.
+ *   Only with LB_BF16 or LB_F16 storage. */
+typedef enum { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_rounding;
+
 /* Fluid parameters.
  * gamma_*: eigenvalues of the linearised collision operator per mode group
  *   (eq. lco_update; groups per Sec. "D3Q19 model II": bulk mode 4, shear
@@ -74,8 +91,12 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16 = 2, LB_F16 = 3 } lb_dtype;
  *   1 = uses rho0.
  * block: threads per block of the fused step kernel (64..1024, multiple of
  *   64); 0 selects 256 for a single box; -1 (and 0 for a batch) lets the
- *   library time the candidates on the first lb_step and keep the fastest
- *   (see lb_launch_config).
+ *   library time the candidates on the first lb_step and keep the fastest:
+ *   for a single box threads per block x mapping of consecutive tiles to one
+ *   XCD, separately for steps with and without a pending bead force; for a
+ *   batch threads per block x blocks per step (see lb_launch_config).  The
+ *   launch configuration never changes the results.
+ * rounding: see lb_rounding; LB_ROUND_STOCHASTIC needs 16-bit storage.
  * track_totals: 1 = the step kernel also accumulates FP64 totals of mass and
  *   momentum every step (read with lb_totals); 0 = totals are computed on
  *   demand by lb_totals with a separate pass. */
@@ -94,6 +115,8 @@ typedef struct {
     int32_t box_id;        /* fourth Philox counter word (replica index) */
     int32_t vacf_lags;     /* batch only: lags R of the on-device ensemble VACF (0 = off, <= 1024) */
     int32_t graph_steps;   /* batch only: steps per captured HIP graph (even, 0 = no graph) */
+    int32_t rounding;      /* lb_rounding of the step kernels' stores (16-bit storage) */
+    int32_t reserved;      /* must be 0 */
 } lb_params;
 
 /* Point particles with harmonic bonds (Sec. "Force coupling").
@@ -153,9 +176,14 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
  * sampled steps.  Synchronises.  LB_EINVAL if the context has no VACF. */
 int lb_vacf(lb_ctx *ctx, double *out, int64_t *nsamples);
 
-/* Launch configuration in use: out[0] = threads per block, out[1] = blocks
- * per step, out[2] = tiles per block (batch) or 1. */
-int lb_launch_config(lb_ctx *ctx, int32_t out[3]);
+/* Launch configuration of the step kernel: out[0] = threads per block,
+ * out[1] = blocks per step, out[2] = tiles per block (batch) or 1, out[3] =
+ * 1 if consecutive tiles are mapped to one XCD (single box) or 0.  For a
+ * single box `force` selects the variant that runs after lb_couple (its
+ * configuration is searched separately, on its first use); a batch ignores
+ * it.  Before the first lb_step of a searching context the entries hold the
+ * defaults (256 threads, no XCD mapping). */
+int lb_launch_config(lb_ctx *ctx, int32_t force, int32_t out[4]);
 
 /* Release all device memory of the context (synchronises its stream). */
 int lb_destroy(lb_ctx *ctx);

@@ -34,6 +34,9 @@ EXPORTS = (
 )
 
 
+LB_ROUND_NEAREST, LB_ROUND_STOCHASTIC = 0, 1
+
+
 class lb_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
@@ -51,6 +54,8 @@ class lb_params(ctypes.Structure):
         ("box_id", ctypes.c_int32),
         ("vacf_lags", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
+        ("rounding", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -73,11 +78,13 @@ class LBError(RuntimeError):
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load liblbmi.so (importing torch first so both share one HIP runtime)."""
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load liblbmi.so (importing torch first so both share one HIP runtime).
+    LBMI_LIBRARY may name another build of the same library."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("LBMI_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"liblbmi.so not built at {path}; run __graft_entry__.build() or "
                           f"python paper_0803_2826_amd/build.py")
@@ -104,7 +111,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.lb_create_batch.argtypes = [ctypes.POINTER(lb_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp,
                                   ctypes.POINTER(vp)]
     L.lb_vacf.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
-    L.lb_launch_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.lb_launch_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.lb_tape_begin.argtypes = [vp, ctypes.c_int32]
     L.lb_backward.argtypes = [vp, vp, ctypes.c_int32, vp, dp]
     L.lb_last_error.argtypes = [vp]

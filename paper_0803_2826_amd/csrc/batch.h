@@ -109,6 +109,7 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
         float dd[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) dd[i] = S::ld(ld_plane(src + (size_t)i * N, pull_src(s, o, i)), 0.f);
+        const mass_acc_t<ST> m_in = site_mass<ST>(dd);
         if (VACF) {
             const float jx = (dd[1] - dd[2]) + (dd[7] - dd[8]) + (dd[9] - dd[10]) + (dd[11] - dd[12]) + (dd[13] - dd[14]);
             const float jy = (dd[3] - dd[4]) + (dd[7] - dd[8]) - (dd[9] - dd[10]) + (dd[15] - dd[16]) + (dd[17] - dd[18]);
@@ -134,7 +135,9 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
         for (int i = 0; i < Q; ++i) dstp[i] = dst + (size_t)i * N;
         double mass;
         float mom[3];
-        store_site<ST, false>(dstp, N * (uint32_t)sizeof(T), s, dd, out, mass, mom);
+        Philox4 rw = {0u, 0u, 0u, 0u};
+        if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, step, d.box_id, cc.key0, cc.key1);
+        store_site<ST, false>(dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
     }
     if (VACF && cur_box >= 0) flush_amp12(acc, a.amp + 12 * (size_t)cur_box);
 }

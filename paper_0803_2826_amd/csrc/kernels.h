@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "collide.h"
 
 namespace lbmi {
@@ -62,6 +64,55 @@ template <> struct Storage<3> {  // LB_F16, stored value = 2^8 * deviation
     static __device__ __forceinline__ float ld(T v, float) { return (float)v * 0x1p-8f; }
     static __device__ __forceinline__ T st(float f, float) { return (_Float16)(f * 0x1p8f); }
 };
+
+// Stochastic rounding of the step kernels' stores (16-bit storage only).
+// Round to nearest even applied every step to thermally dithered values
+// shrinks every population's mean deviation by a factor 1 - u^2 / (32 ln 2)
+// per step (u = relative spacing of the format: the rounding cell of a power
+// of two reaches a quarter spacing below and half a spacing above it), which
+// acts on the hydrodynamic modes like a friction of that size: for BF16
+// (u = 2^-7) 2.7e-6 per step, about 11 % of the viscous decay rate of the
+// longest shear wave of a 512 box.  Stochastic rounding has no such bias:
+// a value is rounded up in magnitude with probability equal to its distance
+// from the lower neighbour in units of the spacing.  Here the probability is
+// resolved to 1/64: with D dropped FP32 mantissa bits (16 for BF16, 13 for
+// FP16) the offset r6 2^(D-6) + c, c = 2^(D-7) - 1 + (r6 & 1), is added to
+// the magnitude bits before they are cut.  Its mean is (2^D - 1) / 2, the
+// mean of the dropped bits, so over the FP32 values of a cell the rounding
+// is exactly unbiased (a constant c = 2^(D-7) would add half an FP32 ulp to
+// every magnitude: a growth of 2^-24 per step); the binade-edge term left by
+// the 1/64 resolution is 4096 times smaller than that of nearest rounding.
+// The 6-bit fields come from one Philox4x32-10 call of its own stream.
+template <> struct Storage<4> : Storage<2> {  // LB_BF16, stochastic rounding
+    static __device__ __forceinline__ T st_sr(float f, uint32_t r6)
+    {
+        const uint32_t b = (__float_as_uint(f) + ((r6 << 10) + 511u + (r6 & 1u))) >> 16;
+        return __builtin_bit_cast(__bf16, (uint16_t)b);
+    }
+};
+template <> struct Storage<5> : Storage<3> {  // LB_F16, stochastic rounding
+    static __device__ __forceinline__ T st_sr(float f, uint32_t r6)
+    {
+        // clear the 13 mantissa bits FP16 drops; the conversion of the result
+        // is exact wherever 2^8 |f| is an FP16 normal number (|f| >= 2^-22)
+        const uint32_t b = (__float_as_uint(f * 0x1p8f) + ((r6 << 7) + 63u + (r6 & 1u))) & 0xFFFFE000u;
+        return (_Float16)__uint_as_float(b);
+    }
+};
+template <int ST> struct is_stochastic { static constexpr bool value = ST >= 4; };
+
+// The four random words of one site's stochastic rounding: Philox counter
+// (site, step, stream 3 << 16, box), key = seed.  Population i uses the
+// 6-bit field (i % 5) of word i / 5.
+__device__ __forceinline__ Philox4 rounding_words(uint32_t s, uint32_t step, uint32_t box, uint32_t k0, uint32_t k1)
+{
+    return philox4x32_10(s, step, 3u << 16, box, k0, k1);
+}
+__device__ __forceinline__ uint32_t rounding_field(const Philox4 &w, int i)
+{
+    const uint32_t word = (i < 5) ? w.v0 : (i < 10) ? w.v1 : (i < 15) ? w.v2 : w.v3;
+    return (word >> (6 * (i % 5))) & 63u;
+}
 
 // Geometry of one periodic box.
 struct Geom {
@@ -198,35 +249,52 @@ __device__ __forceinline__ void block_sum_totals(double *out, double mass, float
     }
 }
 
+// Accumulation type of a site's mass: FP32 storage sums in FP64; 16-bit
+// storage sums its (exactly FP32-representable) values in FP32, whose
+// rounding is far below the 16-bit rounding of the residual.
+template <int ST> using mass_acc_t = typename std::conditional<ST == 1, double, float>::type;
+
+// Input mass of a site: the sum of its gathered deviations.  Taken right
+// after the gather, so that the 19 inputs do not stay live through the
+// collision (that would cost the step kernel a sixth of its occupancy).
+template <int ST>
+__device__ __forceinline__ mass_acc_t<ST> site_mass(const float d[Q])
+{
+    mass_acc_t<ST> m = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) m += (mass_acc_t<ST>)d[i];
+    return m;
+}
+
 // Store the post-collision populations of site s.  The rest population is
 // replaced by the residual that makes the stored values of the site sum to the
-// stored input values (both sums in FP64), so the site's mass changes only by
-// the single rounding of that residual to the storage type.  Returns the
-// stored values' FP64 mass and FP32 momentum for the totals.
+// stored input values (m_in, from site_mass), so the site's mass changes only
+// by the single rounding of that residual to the storage type.  Returns the
+// stored values' mass (FP64) and momentum (FP32) for the totals.
 template <int ST, bool TOTALS>
-__device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_bytes, uint32_t s, const float d[Q],
-                                           const float out[Q], double &mass, float mom[3])
+__device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_bytes, uint32_t s, mass_acc_t<ST> m_in,
+                                           const float out[Q], double &mass, float mom[3], const Philox4 &rw)
 {
     using S = Storage<ST>;
     using T = typename S::T;
-    double m_in = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) m_in += (double)d[i];
+    using Acc = mass_acc_t<ST>;
     T v[Q];
     float back[Q];
-    double sum = 0.0;
+    Acc sum = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        v[i] = S::st(out[i], 0.f);
+        if constexpr (is_stochastic<ST>::value) v[i] = S::st_sr(out[i], rounding_field(rw, i));
+        else v[i] = S::st(out[i], 0.f);
         back[i] = S::ld(v[i], 0.f);
-        sum += (double)back[i];
+        sum += (Acc)back[i];
     }
-    v[0] = S::st((float)(m_in - sum), 0.f);
+    if constexpr (is_stochastic<ST>::value) v[0] = S::st_sr((float)(m_in - sum), rounding_field(rw, 0));
+    else v[0] = S::st((float)(m_in - sum), 0.f);
     back[0] = S::ld(v[0], 0.f);
 #pragma unroll
     for (int i = 0; i < Q; ++i) st_plane_nt<T>(dstp[i], plane_bytes, s, v[i]);
     if (TOTALS) {
-        mass = (double)back[0] + sum;
+        mass = (double)back[0] + (double)sum;
         mom[0] = (back[1] - back[2]) + (back[7] - back[8]) + (back[9] - back[10]) + (back[11] - back[12]) +
                  (back[13] - back[14]);
         mom[1] = (back[3] - back[4]) + (back[7] - back[8]) - (back[9] - back[10]) + (back[15] - back[16]) +
@@ -236,8 +304,10 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
     }
 }
 
+// One site of the fused step: gather with pull streaming, collide, store,
+// optionally accumulate the block's totals.
 template <int ST, bool THERMAL, bool TOTALS, bool FORCE>
-__global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
+__device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
@@ -252,6 +322,7 @@ __global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
         float d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = S::ld(ld_plane(static_cast<const T *>(a.srcp[i]), pull_src(s, o, i)), 0.f);
+        const mass_acc_t<ST> m_in = site_mass<ST>(d);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         if (FORCE) {
             if ((a.fmask[s >> 5] >> (s & 31u)) & 1u) {
@@ -263,9 +334,22 @@ __global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
         float out[Q];
         collide_site<THERMAL>(d, F, a.cc, s, a.step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        store_site<ST, TOTALS>(a.dstp, N * (uint32_t)sizeof(T), s, d, out, mass, mom);
+        Philox4 rw = {0u, 0u, 0u, 0u};
+        if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, a.step, a.cc.box, a.cc.key0, a.cc.key1);
+        store_site<ST, TOTALS>(a.dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
     }
     if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)blockIdx.x, mass, mom);
+}
+
+// The fused step kernel.  Occupancy is the compiler's own allocation: the
+// thermal variants need 90-99 VGPRs (5 waves per SIMD); a cap at 80 (6 waves)
+// makes it keep 16-20 bytes per lane in scratch memory, whose traffic (about
+// 16 B per site, 10 % of the kernel's own) costs more than the extra wave
+// gains.
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE>
+__global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
+{
+    stream_collide_site<ST, THERMAL, TOTALS, FORCE>(a);
 }
 
 }  // namespace lbmi

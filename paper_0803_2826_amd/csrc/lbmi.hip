@@ -21,6 +21,10 @@
 
 using namespace lbmi;
 
+#ifndef LBMI_XCD_REMAP
+#define LBMI_XCD_REMAP 0
+#endif
+
 struct lb_ctx {
     lb_params p;
     int device = 0;
@@ -54,6 +58,14 @@ struct lb_ctx {
     bool pending_force = false;
     int pending_rows = 0;            // upper bound of touched nodes (8 per bead)
     bool tuned = false;              // launch configuration chosen (autotune done or fixed)
+    uint32_t xcd_remap = LBMI_XCD_REMAP;  // step kernel: consecutive tiles on one XCD (if the grid allows)
+    // single box: launch configuration of the step kernel without / with a
+    // pending bead force (the two variants differ in register use), each
+    // searched on its first use when block = -1
+    bool search = false;
+    bool tuned_f[2] = {false, false};
+    int block_f[2] = {256, 256};
+    uint32_t remap_f[2] = {LBMI_XCD_REMAP, LBMI_XCD_REMAP};
     // batched replicas
     bool batch = false;
     int nbox = 0;
@@ -147,6 +159,15 @@ int validate(const lb_params *p, std::string &msg)
         if (!(std::fabs(gk) <= 1.0)) { msg = "kinetic eigenvalues must satisfy |gamma| <= 1"; return LB_EINVAL; }
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p->body_force[c])) { msg = "body force must be finite"; return LB_EINVAL; }
+    if (p->rounding != LB_ROUND_NEAREST && p->rounding != LB_ROUND_STOCHASTIC) {
+        msg = "rounding must be LB_ROUND_NEAREST or LB_ROUND_STOCHASTIC";
+        return LB_EINVAL;
+    }
+    if (p->rounding == LB_ROUND_STOCHASTIC && p->storage == LB_F32) {
+        msg = "stochastic rounding applies to 16-bit storage only";
+        return LB_EINVAL;
+    }
+    if (p->reserved != 0) { msg = "reserved must be 0"; return LB_EINVAL; }
     if (p->block != 0 && p->block != -1 && (p->block < 64 || p->block > 1024 || (p->block % 64) != 0)) {
         msg = "block must be 0, -1 or a multiple of 64 in [64, 1024]";
         return LB_EINVAL;
@@ -216,6 +237,20 @@ void by_storage(int st, F &&fn)
     case LB_F32: fn(std::integral_constant<int, LB_F32>{}); break;
     case LB_BF16: fn(std::integral_constant<int, LB_BF16>{}); break;
     default: fn(std::integral_constant<int, LB_F16>{}); break;
+    }
+}
+
+// Storage template of the step kernels: the storage type, or 4 / 5 for BF16 /
+// FP16 stores with stochastic rounding.  Every other kernel only loads or
+// converts once and uses the plain storage type.
+template <class F>
+void by_step_storage(const lb_params &p, F &&fn)
+{
+    if (p.rounding == LB_ROUND_STOCHASTIC) {
+        if (p.storage == LB_BF16) fn(std::integral_constant<int, 4>{});
+        else fn(std::integral_constant<int, 5>{});
+    } else {
+        by_storage(p.storage, fn);
     }
 }
 
@@ -305,7 +340,7 @@ StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
     a.geo = c->geo;
     a.cc = c->cc;
     a.step = step;
-    a.xcd_remap = 1;
+    a.xcd_remap = c->xcd_remap;
     a.partials = c->partials;
     a.flags = c->flags;
     a.fmask = nullptr;
@@ -383,7 +418,7 @@ void batch_launch_step(lb_ctx *c, const void *src, void *dst, bool vacf)
     a.flags = c->flags;
     const unsigned grid = (c->ntiles + c->chunk - 1) / c->chunk;
     c->nblocks = (int)grid;
-    by_storage(c->p.storage, [&](auto st) {
+    by_step_storage(c->p, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         if (c->thermal) {
             if (vacf) batch_launch_t<ST, true, true>(c, a, grid);
@@ -408,27 +443,34 @@ void batch_enqueue_step(lb_ctx *c, const void *src, void *dst)
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->dstep, c->dstep + 1, vacf ? 1 : 0);
 }
 
+// Mean duration of one launch: a warm-up launch, one timed launch to size the
+// repetition count, then at least `reps` launches and about 2 ms in total.
 float time_launches(lb_ctx *c, int reps, const std::function<void()> &launch)
 {
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
+    auto timed = [&](int n) {
+        (void)hipEventRecord(e0, c->stream);
+        for (int r = 0; r < n; ++r) launch();
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / n;
+    };
     launch();  // warm-up
-    (void)hipEventRecord(e0, c->stream);
-    for (int r = 0; r < reps; ++r) launch();
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
+    const float first = timed(1);
+    const int n = std::max(reps, std::min(200, (int)(2.0f / std::max(first, 1e-3f))));
+    const float ms = timed(n);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return ms / reps;
+    return ms;
 }
 
-// Launch-configuration search: each candidate runs the step kernel from A
-// into B (the state and the step counter are not advanced) and the fastest is
-// kept.  Batch: threads per block x blocks per step; single box: threads per
-// block.
+// Launch-configuration search of a batch: each candidate (threads per block x
+// blocks per step) runs the step kernel from A into B (the state and the step
+// counter are not advanced) and the fastest is kept.
 int autotune(lb_ctx *c)
 {
     if (c->batch) {
@@ -454,44 +496,55 @@ int autotune(lb_ctx *c)
         LB_TRY(batch_build_tiles(c, bb));
         c->chunk = bc;
         c->nblocks = (int)((c->ntiles + c->chunk - 1) / c->chunk);
-    } else {
-        const int blocks[] = {64, 128, 256, 512, 1024};
-        float best = 1e30f;
-        int bb = 256;
-        for (int blk : blocks) {
-            c->block = blk;
-            c->nblocks = (int)grid_for(c->geo.N, blk);
-            StepArgs a;
-            a.src = c->bufA;
-            a.dst = c->bufB;
-            for (int i = 0; i < 19; ++i) {
-                a.srcp[i] = static_cast<const char *>(c->bufA) + (size_t)i * c->geo.N * c->elem;
-                a.dstp[i] = static_cast<char *>(c->bufB) + (size_t)i * c->geo.N * c->elem;
-            }
-            a.geo = c->geo;
-            a.cc = c->cc;
-            a.step = (uint32_t)c->step;
-            a.xcd_remap = 1;
-            a.partials = c->partials;
-            a.flags = c->flags;
-            a.fmask = nullptr;
-            a.force = nullptr;
-            const bool tot = c->p.track_totals != 0;
-            const float ms = time_launches(c, 3, [&] {
-                by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, false); });
-            });
-            LB_LAUNCH_CHECK(c, "autotune");
-            if (ms < best) {
-                best = ms;
-                bb = blk;
-            }
-        }
-        c->block = bb;
-        c->nblocks = (int)grid_for(c->geo.N, bb);
     }
     c->tuned = true;
     return LB_OK;
 }
+
+// Single box: search threads per block x XCD remap for the step kernel
+// variant with or without bead force; each candidate runs the kernel from A
+// into B without advancing the state (with a pending force the force buffers
+// hold this step's force and are only read).
+int autotune_single(lb_ctx *c, bool frc)
+{
+    const int blocks[] = {64, 128, 256, 512, 1024};
+    float best = 1e30f;
+    const int k = frc ? 1 : 0;
+    for (int cand = 0; cand < 10; ++cand) {
+        c->block = blocks[cand >> 1];
+        c->xcd_remap = (uint32_t)(cand & 1);
+        c->nblocks = (int)grid_for(c->geo.N, c->block);
+        StepArgs a = plain_step_args(c, c->bufA, c->bufB, (uint32_t)c->step);
+        if (frc) {
+            a.fmask = c->fmask;
+            a.force = c->force;
+        }
+        const bool tot = c->p.track_totals != 0;
+        const float ms = time_launches(c, 3, [&] {
+            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
+        });
+        LB_LAUNCH_CHECK(c, "autotune");
+        if (ms < best) {
+            best = ms;
+            c->block_f[k] = c->block;
+            c->remap_f[k] = c->xcd_remap;
+        }
+    }
+    c->tuned_f[k] = true;
+    return LB_OK;
+}
+
+// Launch configuration of the next single-box step launch.
+int select_launch(lb_ctx *c, bool frc)
+{
+    const int k = frc ? 1 : 0;
+    if (c->search && !c->tuned_f[k]) LB_TRY(autotune_single(c, frc));
+    c->block = c->block_f[k];
+    c->xcd_remap = c->remap_f[k];
+    c->nblocks = (int)grid_for(c->geo.N, c->block);
+    return LB_OK;
+}
+
 
 int batch_step(lb_ctx *c, int32_t nsteps)
 {
@@ -558,7 +611,9 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     c->geo.div_ny = make_fastdiv(ny);
     c->elem = storage_bytes(params->storage);
     c->block = params->block > 0 ? params->block : 256;
-    c->tuned = params->block != -1;
+    c->tuned = true;
+    c->search = params->block == -1;
+    c->block_f[0] = c->block_f[1] = c->block;
     c->nblocks = (int)grid_for(c->geo.N, c->block);
     fill_collide_const(c);
     const size_t bytes = (size_t)19 * c->geo.N * c->elem;
@@ -797,9 +852,10 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         Join j(c);
         return batch_step(c, nsteps);
     }
-    if (!c->tuned) LB_TRY(autotune(c));
     const bool tot = c->p.track_totals != 0;
     for (int32_t t = 0; t < nsteps; ++t) {
+        const bool frc = c->pending_force;
+        LB_TRY(select_launch(c, frc));
         StepArgs a;
         a.src = c->bufA;
         a.dst = c->bufB;
@@ -810,14 +866,13 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         a.geo = c->geo;
         a.cc = c->cc;
         a.step = (uint32_t)c->step;
-        a.xcd_remap = 1;
+        a.xcd_remap = c->xcd_remap;
         a.partials = c->partials;
         a.flags = c->flags;
         a.fmask = c->fmask;
         a.force = c->force;
-        const bool frc = c->pending_force;
         if (frc && c->taping) c->tape_force_used = true;
-        by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
+        by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
         LB_LAUNCH_CHECK(c, "stream_collide");
         if (frc) {
             hipLaunchKernelGGL(k_clear_touched, dim3(grid_for((size_t)c->pending_rows, 256)), dim3(256), 0, c->stream,
@@ -1084,7 +1139,7 @@ int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, do
             const int saved_block = c->block;
             c->block = 256;
             c->nblocks = (int)nb;
-            by_storage(c->p.storage, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
+            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
             c->block = saved_block;
             c->nblocks = (int)saved;
         }
@@ -1149,12 +1204,21 @@ int lb_vacf(lb_ctx *c, double *out, int64_t *nsamples)
     return LB_OK;
 }
 
-int lb_launch_config(lb_ctx *c, int32_t out[3])
+int lb_launch_config(lb_ctx *c, int32_t force, int32_t out[4])
 {
     if (!c || !out) return LB_EINVAL;
-    out[0] = c->block;
-    out[1] = c->batch ? (int32_t)((c->ntiles + c->chunk - 1) / c->chunk) : c->nblocks;
-    out[2] = c->batch ? (int32_t)c->chunk : 1;
+    if (c->batch) {
+        out[0] = c->block;
+        out[1] = (int32_t)((c->ntiles + c->chunk - 1) / c->chunk);
+        out[2] = (int32_t)c->chunk;
+        out[3] = 0;
+        return LB_OK;
+    }
+    const int k = force ? 1 : 0;
+    out[0] = c->block_f[k];
+    out[1] = (int32_t)grid_for(c->geo.N, c->block_f[k]);
+    out[2] = 1;
+    out[3] = (int32_t)c->remap_f[k];
     return LB_OK;
 }
 

@@ -1,7 +1,8 @@
 """Measurement helpers of the three forms beside the plain FP32 path.
 
 precision_study  storage FP32 / BF16 / FP16 (shifted deviations, FP32
-                 collision arithmetic): decay rate of a shear wave and the
+                 collision arithmetic), 16-bit stores rounded to nearest or
+                 stochastically: decay rate of a shear wave and the
                  stationary per-mode noise variances, each against its closed
                  form, plus MLUPS.
 batch_study      many uneven replica boxes in one persistent launch per step
@@ -12,6 +13,9 @@ the test suite):
   shear wave at gamma = 0: j_x(z, t) = A lambda^t sin(kz),
       lambda = 1 - (2/3) sin^2(k/2);
   stationary variance of mode k: mu w_k rho0 = 3 kT w_k rho0.
+Round to nearest on thermally dithered 16-bit values adds a damping
+rounding_shrink(storage) per step to every hydrodynamic mode (derivation with
+LB_ROUND_NEAREST in the C header); stochastic rounding removes it.
 """
 from __future__ import annotations
 
@@ -28,6 +32,13 @@ W_K = np.array([1, 1 / 3, 1 / 3, 1 / 3, 2 / 3, 4 / 3, 4 / 9, 1 / 9, 1 / 9, 1 / 9
                 2, 4 / 3, 4 / 9])
 
 
+def rounding_shrink(storage: str) -> float:
+    """Mean shrink per round-to-nearest store of a dithered value: u^2 / (32 ln 2),
+    u the relative spacing (BF16 2^-7, FP16 2^-10, FP32 2^-23)."""
+    u = {"f32": 2.0 ** -23, "bf16": 2.0 ** -7, "f16": 2.0 ** -10}[storage]
+    return u * u / (32 * math.log(2))
+
+
 def _jx_mode(lat: Lattice, nz: int) -> float:
     """Projection of the momentum density j_x on sin(2 pi z / nz)."""
     rho, u = lat.moments()
@@ -37,12 +48,13 @@ def _jx_mode(lat: Lattice, nz: int) -> float:
 
 
 def decay_rate(storage: str, nx: int, ny: int, nz: int, steps: int, kT: float, amp: float = 0.01, seed: int = 0,
-               samples: int = 20):
+               samples: int = 20, rounding: str = "nearest"):
     """Fitted per-step decay rate of a shear wave (k = 2 pi / nz), noise
     cancelled by subtracting a run with the same seed and no wave."""
     runs = []
     for a in (amp, 0.0):
-        p = FluidParams(nx=nx, ny=ny, nz=nz, storage=storage, kT=kT, seed=seed, track_totals=False)
+        p = FluidParams(nx=nx, ny=ny, nz=nz, storage=storage, kT=kT, seed=seed, track_totals=False,
+                        rounding=rounding)
         lat = Lattice(p)
         lat.init_equilibrium(u=shear_wave(nx, ny, nz, a))
         series = [_jx_mode(lat, nz)]
@@ -61,9 +73,10 @@ def decay_rate(storage: str, nx: int, ny: int, nz: int, steps: int, kT: float, a
             "amp_final": float(diff[-1]), "amp_final_exact": amp * lam ** t[-1]}
 
 
-def mode_variances(storage: str, L: int, kT: float, steps: int, seed: int = 1, samples: int = 10):
+def mode_variances(storage: str, L: int, kT: float, steps: int, seed: int = 1, samples: int = 10,
+                   rounding: str = "nearest"):
     """Stationary per-mode variances / (3 kT w_k rho0)."""
-    p = FluidParams(nx=L, ny=L, nz=L, storage=storage, kT=kT, seed=seed, track_totals=False)
+    p = FluidParams(nx=L, ny=L, nz=L, storage=storage, kT=kT, seed=seed, track_totals=False, rounding=rounding)
     lat = Lattice(p)
     lat.init_equilibrium()
     lat.step(steps)
@@ -75,8 +88,8 @@ def mode_variances(storage: str, L: int, kT: float, steps: int, seed: int = 1, s
     return acc / samples / (3 * kT * W_K)
 
 
-def step_mlups(storage: str, L: int, kT: float, steps: int = 50) -> float:
-    p = FluidParams(nx=L, ny=L, nz=L, storage=storage, kT=kT, seed=0, track_totals=True)
+def step_mlups(storage: str, L: int, kT: float, steps: int = 50, rounding: str = "nearest") -> float:
+    p = FluidParams(nx=L, ny=L, nz=L, storage=storage, kT=kT, seed=0, track_totals=True, rounding=rounding)
     lat = Lattice(p)
     lat.init_equilibrium()
     lat.step(5)
@@ -93,12 +106,16 @@ def step_mlups(storage: str, L: int, kT: float, steps: int = 50) -> float:
 
 def precision_study(decay_box=(8, 8, 512), decay_steps=2000, var_L=32, var_steps=300, kT=1e-4, mlups_L=256):
     out = {}
-    for st in ("f32", "bf16", "f16"):
-        d = decay_rate(st, *decay_box, steps=decay_steps, kT=kT)
-        v = mode_variances(st, var_L, kT, var_steps)
-        out[st] = {"decay_rate_rel_err": d["rel_err"], "mode_var_ratio_max_dev": float(np.abs(v - 1).max()),
-                   "mode_var_ratio": [round(float(x), 4) for x in v],
-                   "mlups": step_mlups(st, mlups_L, kT) if mlups_L else None}
+    for st, rd in (("f32", "nearest"), ("bf16", "nearest"), ("f16", "nearest"), ("bf16", "stochastic"),
+                   ("f16", "stochastic")):
+        d = decay_rate(st, *decay_box, steps=decay_steps, kT=kT, rounding=rd)
+        v = mode_variances(st, var_L, kT, var_steps, rounding=rd)
+        shrink = rounding_shrink(st) if rd == "nearest" else 0.0
+        out[f"{st}-{rd}"] = {"decay_rate_rel_err": d["rel_err"],
+                             "predicted_rel_err": shrink / d["rate_exact"],
+                             "mode_var_ratio_max_dev": float(np.abs(v - 1).max()),
+                             "mode_var_ratio": [round(float(x), 4) for x in v],
+                             "mlups": step_mlups(st, mlups_L, kT, rounding=rd) if mlups_L else None}
     return out
 
 
@@ -124,11 +141,11 @@ def batch_study(nbox: int = 512, steps: int = 500, kT: float = 1e-4, lags: int =
     e1.record(B.stream)
     torch.cuda.synchronize()
     ms = max(e0.elapsed_time(e1), (time.perf_counter() - t0) * 1e3) / steps
-    C, ns = B.vacf()
+    C, ns = B.vacf() if lags > 0 else (None, 0)
     cfg = B.launch_config()
     edges = np.array([d[0] for d in dims])
     by_L = {}
-    for Lb in sorted(set(edges.tolist())):
+    for Lb in (sorted(set(edges.tolist())) if lags > 0 else []):
         sel = edges == Lb
         lam = 1 - (2 / 3) * math.sin(math.pi / Lb) ** 2
         c = C[sel].mean(axis=0)

@@ -40,6 +40,7 @@ class FluidParams:
     box_id: int = 0
     vacf_lags: int = 0
     graph_steps: int = 0
+    rounding: str = "nearest"   # "nearest" or "stochastic" (16-bit storage)
 
     @property
     def N(self) -> int:
@@ -62,6 +63,7 @@ class FluidParams:
         p.box_id = int(self.box_id)
         p.vacf_lags = int(self.vacf_lags)
         p.graph_steps = int(self.graph_steps)
+        p.rounding = {"nearest": _lib.LB_ROUND_NEAREST, "stochastic": _lib.LB_ROUND_STOCHASTIC}[self.rounding]
         return p
 
 
@@ -227,9 +229,11 @@ class Lattice:
         self._check(self.L.lb_backward(self.ctx, t.data_ptr(), dt, out.data_ptr(), gbar))
         return out.reshape(t.shape), [gbar[i] for i in range(3)]
 
-    def launch_config(self):
-        out = (ctypes.c_int32 * 3)()
-        self._check(self.L.lb_launch_config(self.ctx, out))
+    def launch_config(self, force: bool = False):
+        """(threads per block, blocks per step, tiles per block, XCD mapping) of
+        the step kernel; `force`: the variant that runs after couple()."""
+        out = (ctypes.c_int32 * 4)()
+        self._check(self.L.lb_launch_config(self.ctx, 1 if force else 0, out))
         return tuple(out)
 
     @property

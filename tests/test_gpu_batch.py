@@ -79,7 +79,7 @@ def test_autotune_does_not_change_results(lat):
     for X in (F, T):
         X.init_equilibrium()
         X.step(6)
-    blk, grid, chunk = T.launch_config()
+    blk, grid, chunk, _ = T.launch_config()
     assert blk in (128, 256, 512, 1024) and grid >= 1 and chunk >= 1
     assert torch.equal(F.get_populations(dtype=torch.float32), T.get_populations(dtype=torch.float32))
     F.close()
@@ -87,15 +87,28 @@ def test_autotune_does_not_change_results(lat):
 
 
 def test_single_box_autotune(orc, lat):
+    """The searched launch configurations (without and with bead force) give
+    the same state as a fixed one, bit for bit."""
     import torch
-    p = dict(nx=40, ny=30, nz=20, kT=1e-4, seed=2)
+    from paper_0803_2826_amd.inputs import random_walk_chains
+    p = dict(nx=40, ny=32, nz=24, kT=1e-4, seed=2)
+    pos, mom, bonds = random_walk_chains(4, 8, (40, 32, 24), seed=1)
+    nb = pos.shape[0]
     A = lat.Lattice(lat.FluidParams(**p, block=256))
     T = lat.Lattice(lat.FluidParams(**p, block=-1))
     for X in (A, T):
         X.init_equilibrium()
-        X.step(5)
-    assert T.launch_config()[0] in (64, 128, 256, 512, 1024)
+        X.step(3)
+        beads = lat.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 5.0), bonds, 1e-3, 1.0)
+        for _ in range(3):
+            X.coupled_step(beads)
+        X.step(2)
+    for force in (False, True):
+        blk, grid, tiles, remap = T.launch_config(force)
+        assert blk in (64, 128, 256, 512, 1024) and tiles == 1 and remap in (0, 1)
+        assert grid * blk >= 40 * 32 * 24
     assert torch.equal(A.get_populations(dtype=torch.float32), T.get_populations(dtype=torch.float32))
+    assert A.totals(exact=True) == T.totals(exact=True)
     A.close()
     T.close()
 
