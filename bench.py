@@ -15,12 +15,14 @@ Prints ONE JSON line with, beside the throughput:
                 of a 4-byte population per site, plus the 1-bit-per-site
                 force bitmap) over its average duration, timed with events
                 on the launch stream around each step's launch inside the
-                timed region, against the 8 TB/s HBM peak;
+                timed region, against the 8 TB/s HBM peak, and beside it
+                the rate of a plain device copy of one population buffer
+                (the practical ceiling of a streaming kernel);
   cpu_baseline  the FP64 oracle on the host cores, timed on a bounded sample
                 of the same workload (a few coupled steps of the full box);
-  forms         the other throughputs the metric names: BF16-storage MLUPS
-                (nearest and stochastic rounding) on the same box without
-                beads, the batched form (512 replica boxes, edges drawn from
+  forms         the other throughputs the metric names: FP32 and BF16-storage
+                MLUPS (nearest and stochastic rounding, kT > 0 and kT = 0)
+                on the same box without beads, the batched form (512 replica boxes, edges drawn from
                 {24, 32, 40, 48, 64}, HIP graph replay) and the
                 differentiation form (taped forward and adjoint, 128^3, 500
                 steps, checkpoints every 50).
@@ -105,6 +107,42 @@ def cpu_baseline(L: int, n_chains: int, length: int, steps: int):
     }
 
 
+def copy_ceiling(nbytes: int) -> tuple:
+    """(GB/s, threads per block) of the best plain streaming copy of nbytes
+    (read + write, the copy kernel of libbwprobe.so over 256 / 512 / 1024
+    threads per block): the practical HBM ceiling a streaming kernel can
+    reach."""
+    import ctypes
+
+    import torch
+
+    from paper_0803_2826_amd import build as hip_build
+
+    if not os.path.exists(hip_build.PROBE):
+        raise RuntimeError(f"{hip_build.PROBE} is not built (run __graft_entry__.build())")
+    P = ctypes.CDLL(hip_build.PROBE)
+    P.bw_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]
+    a = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    best = (0.0, 0)
+    for block in (256, 512, 1024):
+        launch = lambda: P.bw_copy(a.data_ptr(), b.data_ptr(), nbytes, block, ctypes.c_void_p(s.cuda_stream))
+        if launch() != 0:
+            raise RuntimeError("bw_copy failed")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(20):
+            launch()
+        e1.record(s)
+        torch.cuda.synchronize()
+        gbs = 2 * nbytes / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+        best = max(best, (gbs, block))
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
 def run_forms(L: int) -> dict:
     """Throughputs of the precision, batched and differentiation forms (each
     after its own warm-up, timed with events on the context stream)."""
@@ -113,8 +151,11 @@ def run_forms(L: int) -> dict:
     from paper_0803_2826_amd import forms, lattice
 
     out = {}
+    for kT in (KT, 0.0):
+        out[f"f32_fluid_only_kT{kT:g}_mlups"] = round(forms.step_mlups("f32", L, kT, steps=100), 1)
     for st, rd in (("bf16", "nearest"), ("bf16", "stochastic")):
         out[f"{st}_{rd}_mlups"] = round(forms.step_mlups(st, L, KT, steps=100, rounding=rd), 1)
+    out["bf16_nearest_kT0_mlups"] = round(forms.step_mlups("bf16", L, 0.0, steps=100), 1)
     print("# forms: precision done", file=sys.stderr, flush=True)
     b = forms.batch_study(nbox=512, steps=200, kT=KT, lags=0, graph_steps=10)
     out["batched_mlups"] = round(b["mlups"], 1)
@@ -219,6 +260,11 @@ def main() -> int:
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    ceiling, cblock = copy_ceiling(19 * 4 * N)
+    roofline["copy_ceiling"] = {"achieved": round(ceiling, 1), "unit": "GB/s",
+                                "kernel": f"streaming copy (16 B per thread, {cblock} threads per block) of one "
+                                          f"{19 * 4 * N / 1e9:.2f} GB population buffer",
+                                "frac_of_copy": round(achieved / ceiling, 4)}
 
     forms = None if args.no_forms else run_forms(L)
 

@@ -50,7 +50,8 @@ enum {
     LB_EDEVICE = -3,      /* HIP runtime error (message in lb_last_error) */
     LB_ENONFINITE = -4,   /* a NaN or Inf population was seen on the device */
     LB_ESTATE = -5,       /* call order violated (e.g. two lb_couple without lb_step) */
-    LB_EUNSUPPORTED = -6  /* valid request the library does not implement */
+    LB_EUNSUPPORTED = -6, /* valid request the library does not implement */
+    LB_EIO = -7           /* checkpoint file missing, unwritable, truncated or of another layout */
 };
 
 /* Storage type of populations (the collision always computes in FP32). */
@@ -184,6 +185,21 @@ int lb_vacf(lb_ctx *ctx, double *out, int64_t *nsamples);
  * it.  Before the first lb_step of a searching context the entries hold the
  * defaults (256 threads, no XCD mapping). */
 int lb_launch_config(lb_ctx *ctx, int32_t force, int32_t out[4]);
+
+/* Checkpoint / resume.  lb_save writes the current state (the stored
+ * populations of every box, bit for bit, with the step counter, the
+ * parameters and the box extents) to the host file `path`; lb_load reads
+ * such a file into a context of the same layout (box extents, box count,
+ * storage type) and sets its step counter, so that, with the same
+ * parameters and seed, the run continues exactly as the saved one would
+ * have (the noise is keyed by site and step).  The parameters stored in the
+ * file are not applied.  Bead state is caller-owned and saved by the caller;
+ * a batch's VACF accumulators are not saved.  Both synchronise.  Errors:
+ * LB_EIO (open / read / write failure, not a checkpoint, other layout),
+ * LB_ESTATE (called between lb_couple and lb_step; lb_load while a tape is
+ * recording). */
+int lb_save(lb_ctx *ctx, const char *path);
+int lb_load(lb_ctx *ctx, const char *path);
 
 /* Release all device memory of the context (synchronises its stream). */
 int lb_destroy(lb_ctx *ctx);

@@ -1238,6 +1238,112 @@ int lb_set_step_count(lb_ctx *c, uint64_t step)
     return LB_OK;
 }
 
+// Checkpoint file: this header, the box extents (int32 [nbox][3]), then the
+// stored populations of every box (buffer A, box after box, [19][N_b] in the
+// storage type), as they are in device memory.
+struct SaveHeader {
+    char magic[8];          // "LBMICKP1"
+    uint32_t version;       // 1
+    uint32_t header_bytes;  // sizeof(SaveHeader)
+    lb_params params;
+    int32_t nbox;           // 1 for a single box
+    int32_t elem;           // bytes per stored population
+    uint64_t step;
+    uint64_t total_sites;
+};
+static const char kSaveMagic[8] = {'L', 'B', 'M', 'I', 'C', 'K', 'P', '1'};
+
+static void ctx_dims(const lb_ctx *c, std::vector<int32_t> &dims)
+{
+    dims.clear();
+    if (c->batch) {
+        for (const BoxDesc &d : c->boxes_h) {
+            dims.push_back((int32_t)d.geo.nx);
+            dims.push_back((int32_t)d.geo.ny);
+            dims.push_back((int32_t)d.geo.nz);
+        }
+    } else {
+        dims = {(int32_t)c->geo.nx, (int32_t)c->geo.ny, (int32_t)c->geo.nz};
+    }
+}
+
+static size_t ctx_sites(const lb_ctx *c) { return c->batch ? (size_t)c->total_sites : (size_t)c->geo.N; }
+
+int lb_save(lb_ctx *c, const char *path)
+{
+    if (!c) return LB_EINVAL;
+    if (!path) return fail(c, LB_EINVAL, "path is NULL");
+    if (c->pending_force) return fail(c, LB_ESTATE, "lb_save between lb_couple and lb_step");
+    LB_TRY(use_device(c));
+    std::vector<int32_t> dims;
+    ctx_dims(c, dims);
+    SaveHeader h{};
+    std::memcpy(h.magic, kSaveMagic, 8);
+    h.version = 1;
+    h.header_bytes = (uint32_t)sizeof(SaveHeader);
+    h.params = c->p;
+    h.nbox = c->batch ? c->nbox : 1;
+    h.elem = (int32_t)c->elem;
+    h.step = c->step;
+    h.total_sites = ctx_sites(c);
+    const size_t bytes = (size_t)19 * h.total_sites * c->elem;
+    std::vector<char> host(bytes);
+    {
+        Join j(c);
+        LB_TRY(check(c, hipMemcpyAsync(host.data(), c->bufA, bytes, hipMemcpyDeviceToHost, c->stream), "state copy"));
+        LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    }
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(c, LB_EIO, std::string("cannot open for writing: ") + path);
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+              std::fwrite(dims.data(), sizeof(int32_t), dims.size(), f) == dims.size() &&
+              std::fwrite(host.data(), 1, bytes, f) == bytes;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(c, LB_EIO, std::string("write failed: ") + path);
+    return LB_OK;
+}
+
+int lb_load(lb_ctx *c, const char *path)
+{
+    if (!c) return LB_EINVAL;
+    if (!path) return fail(c, LB_EINVAL, "path is NULL");
+    if (c->pending_force) return fail(c, LB_ESTATE, "lb_load between lb_couple and lb_step");
+    if (c->taping) return fail(c, LB_ESTATE, "lb_load while a tape is recording");
+    LB_TRY(use_device(c));
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(c, LB_EIO, std::string("cannot open for reading: ") + path);
+    SaveHeader h{};
+    std::vector<int32_t> dims, want;
+    ctx_dims(c, want);
+    const size_t bytes = (size_t)19 * ctx_sites(c) * c->elem;
+    std::vector<char> host;
+    std::string why;
+    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1 ||
+        h.header_bytes != sizeof(SaveHeader)) {
+        why = "not a checkpoint of this library";
+    } else if (h.nbox != (c->batch ? c->nbox : 1) || h.params.storage != c->p.storage || h.elem != (int32_t)c->elem ||
+               h.total_sites != ctx_sites(c)) {
+        why = "checkpoint layout (boxes, storage, sites) differs from the context";
+    } else {
+        dims.resize(want.size());
+        host.resize(bytes);
+        if (std::fread(dims.data(), sizeof(int32_t), dims.size(), f) != dims.size() || dims != want)
+            why = "checkpoint box extents differ from the context";
+        else if (std::fread(host.data(), 1, bytes, f) != bytes)
+            why = "checkpoint file is truncated";
+    }
+    std::fclose(f);
+    if (!why.empty()) return fail(c, LB_EIO, why + ": " + path);
+    if (h.step > 0xffffffffull) return fail(c, LB_EIO, "checkpoint step counter out of range");
+    {
+        Join j(c);
+        LB_TRY(check(c, hipMemcpyAsync(c->bufA, host.data(), bytes, hipMemcpyHostToDevice, c->stream), "state copy"));
+        LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    }
+    c->totals_valid = false;
+    return lb_set_step_count(c, h.step);
+}
+
 const char *lb_last_error(const lb_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

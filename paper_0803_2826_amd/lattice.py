@@ -6,6 +6,7 @@ numerical step is a HIP kernel behind the C ABI of include/lb.h.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import torch
@@ -228,6 +229,14 @@ class Lattice:
         dt = LB_F64 if t.dtype == torch.float64 else LB_F32
         self._check(self.L.lb_backward(self.ctx, t.data_ptr(), dt, out.data_ptr(), gbar))
         return out.reshape(t.shape), [gbar[i] for i in range(3)]
+
+    def save(self, path: str) -> None:
+        """Write the state and step counter to a checkpoint file (lb_save)."""
+        self._check(self.L.lb_save(self.ctx, os.fsencode(path)))
+
+    def load(self, path: str) -> None:
+        """Resume from a checkpoint file of the same layout (lb_load)."""
+        self._check(self.L.lb_load(self.ctx, os.fsencode(path)))
 
     def launch_config(self, force: bool = False):
         """(threads per block, blocks per step, tiles per block, XCD mapping) of
