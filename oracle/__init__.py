@@ -132,13 +132,18 @@ def lib():
         L.orc_collide_site_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         L.orc_step_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_uint32, dp]
         L.orc_backward.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, dp, dp]
+        L.orc_couple_adjoint.argtypes = [pp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp, ctypes.c_int32,
+                                         ip, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp, dp]
+        L.orc_backward_coupled.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
+                                           ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals",
                      "orc_equilibrium", "orc_moments_site", "orc_back_site", "orc_collide_site",
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
                      "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step",
-                     "orc_collide_site_adjoint", "orc_step_adjoint", "orc_backward"):
+                     "orc_collide_site_adjoint", "orc_step_adjoint", "orc_backward", "orc_couple_adjoint",
+                     "orc_backward_coupled"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -334,6 +339,42 @@ def collide_site_adjoint(p: Params, n, F, gnoise, nbar_star):
     pc = p.c()
     lib().orc_collide_site_adjoint(ctypes.byref(pc), _dp(nn), _dp(FF), _dp(g), _dp(nbs), _dp(nb), _dp(Fb))
     return nb, Fb
+
+
+def _bonds_ptr(beads: "Beads"):
+    bonds = np.ascontiguousarray(beads.bonds, dtype=np.int32).reshape(-1)
+    return bonds, (bonds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if bonds.size else None)
+
+
+def couple_adjoint(p: Params, n: np.ndarray, step_index: int, beads: "Beads", force_bar: np.ndarray,
+                   pos_bar: np.ndarray, mom_bar: np.ndarray, lam: np.ndarray, gbar: np.ndarray) -> None:
+    """Adjoint of couple() for the bead state `beads` the step started from:
+    pos_bar / mom_bar (in: after the step, out: before it), lam and gbar
+    accumulate; force_bar [3,nz,ny,nx] is the adjoint of the spread force."""
+    bonds, bp = _bonds_ptr(beads)
+    pc = p.c()
+    lib().orc_couple_adjoint(ctypes.byref(pc), _dp(_f64(n)), int(step_index), beads.pos.shape[0],
+                             _dp(_f64(beads.pos)), _dp(_f64(beads.mom)), _dp(_f64(beads.mass)),
+                             _dp(_f64(beads.zeta)), int(beads.bonds.shape[0]), bp, float(beads.k_bond),
+                             float(beads.r0), _dp(_f64(force_bar)), _dp(pos_bar), _dp(mom_bar), _dp(lam), _dp(gbar))
+
+
+def backward_coupled(p: Params, n0: np.ndarray, nsteps: int, beads: "Beads", lam_T: np.ndarray,
+                     pos_bar_T=None, mom_bar_T=None, step0: int = 0):
+    """dL/dn(0), dL/dg, dL/dR(0), dL/dP(0) through nsteps coupled steps from
+    (n0, beads) given dL/dn(T), dL/dR(T), dL/dP(T)."""
+    nb = beads.pos.shape[0]
+    lam = np.ascontiguousarray(lam_T, dtype=np.float64).copy()
+    pb = np.zeros((nb, 3)) if pos_bar_T is None else np.ascontiguousarray(pos_bar_T, dtype=np.float64).copy()
+    mb = np.zeros((nb, 3)) if mom_bar_T is None else np.ascontiguousarray(mom_bar_T, dtype=np.float64).copy()
+    gbar = np.zeros(3)
+    bonds, bp = _bonds_ptr(beads)
+    pc = p.c()
+    lib().orc_backward_coupled(ctypes.byref(pc), _dp(_f64(n0)), int(nsteps), int(step0), nb, _dp(_f64(beads.pos)),
+                               _dp(_f64(beads.mom)), _dp(_f64(beads.mass)), _dp(_f64(beads.zeta)),
+                               int(beads.bonds.shape[0]), bp, float(beads.k_bond), float(beads.r0), _dp(lam),
+                               _dp(gbar), _dp(pb), _dp(mb))
+    return lam, gbar, pb, mb
 
 
 def backward(p: Params, n0: np.ndarray, nsteps: int, lam_T: np.ndarray, step0: int = 0):

@@ -792,3 +792,259 @@ void orc_backward(const orc_params *p, const double *n0, int32_t nsteps, uint32_
     free(work);
     free(states);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint (reverse mode) of the particle half of a coupled step             */
+/* ------------------------------------------------------------------------ */
+
+/* d phi2(r) / dr where the kernel is differentiable (|r| < 1, r != 0). */
+static double dphi2(double r)
+{
+    if (r <= -1.0 || r >= 1.0) return 0.0;
+    return r > 0.0 ? -1.0 : 1.0;
+}
+
+/* Weights of the 8-node stencil (eq. Delta) and their gradients with
+ * respect to R: dw[q][a] = d wgt[q] / d R_a.  Same node order as
+ * orc_stencil. */
+static void stencil_grad(const double R[3], double dw[8][3])
+{
+    double frac[3];
+    for (int a = 0; a < 3; ++a) frac[a] = R[a] - floor(R[a]);
+    int q = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const double r[3] = {frac[0] - dx, frac[1] - dy, frac[2] - dz};
+                const double f[3] = {phi2(r[0]), phi2(r[1]), phi2(r[2])};
+                dw[q][0] = dphi2(r[0]) * f[1] * f[2];
+                dw[q][1] = f[0] * dphi2(r[1]) * f[2];
+                dw[q][2] = f[0] * f[1] * dphi2(r[2]);
+                ++q;
+            }
+}
+
+/* Transpose of the Jacobian of orc_couple (with its bead noise replayed).
+ * Inputs: the fluid state n and bead state (pos, mom) the step started
+ * from, and force_bar ([3][N]), the adjoint of the spread force field
+ * (from orc_step_adjoint's extra_bar).  pos_bar, mom_bar: on entry the
+ * adjoints of the bead state after the step, on exit those of the state
+ * before it.  lam ([19][N], the adjoint of n) and gbar accumulate the
+ * contributions of the interpolated velocity u = (sum n c + g/2)/rho.
+ * The forward map is retraced in reverse: R = R' + (h/2)P''/m, the reaction
+ * I = -(P'' - P - h F^c) spread with the weights Delta(R'), the momentum
+ * update P'' = C1 P + C2 (F^c + zeta u_b), the interpolation
+ * u_b = sum Delta u(node), the bond forces F^c(R') and the half drift
+ * R' = R + (h/2) P/m.  The weights are differentiated where the stencil is
+ * differentiable (R' off the node planes).  Parity pinned by central
+ * finite differences of the coupled forward map. */
+void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int32_t nb, const double *pos,
+                        const double *mom, const double *mass, const double *zeta, int32_t nbonds,
+                        const int32_t *bonds, double kbond, double r0, const double *force_bar, double *pos_bar,
+                        double *mom_bar, double *lam, double gbar[3])
+{
+    init_tables();
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const double h = 1.0;
+    const size_t nb3 = 3 * (size_t)(nb > 0 ? nb : 1);
+    double *half = (double *)malloc(sizeof(double) * nb3);
+    double *fc = (double *)calloc(nb3, sizeof(double));
+    double *half_bar = (double *)calloc(nb3, sizeof(double));
+    double *fc_bar = (double *)calloc(nb3, sizeof(double));
+    double *p_bar = (double *)calloc(nb3, sizeof(double));
+
+    /* forward quantities: half-step positions and bond forces */
+    for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < 3; ++a) half[3 * b + a] = pos[3 * b + a] + 0.5 * h * mom[3 * b + a] / mass[b];
+    for (int q = 0; q < nbonds; ++q) {
+        const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = half[3 * ib + a] - half[3 * ia + a];
+            r2 += d[a] * d[a];
+        }
+        const double r = sqrt(r2);
+        if (r == 0.0) continue;
+        const double mag = -kbond * (r - r0) / r;
+        for (int a = 0; a < 3; ++a) {
+            fc[3 * ib + a] += mag * d[a];
+            fc[3 * ia + a] -= mag * d[a];
+        }
+    }
+
+    for (int b = 0; b < nb; ++b) {
+        const double m = mass[b], z = zeta[b];
+        int64_t node[8];
+        double wgt[8], dw[8][3], un[8][3], rn[8];
+        orc_stencil(p, &half[3 * b], node, wgt);
+        stencil_grad(&half[3 * b], dw);
+        double ub[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 8; ++q) {
+            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < Q; ++i) {
+                const double v = n[i * N + node[q]];
+                r += v;
+                for (int a = 0; a < 3; ++a) j[a] += v * CV[i][a];
+            }
+            rn[q] = r;
+            for (int a = 0; a < 3; ++a) {
+                un[q][a] = (j[a] + 0.5 * p->g[a]) / r;
+                ub[a] += wgt[q] * un[q][a];
+            }
+        }
+        double C1, C2, C3;
+        if (z > 0.0) {
+            C1 = exp(-z * h / m);
+            C2 = (m / z) * (1.0 - C1);
+            C3 = sqrt(m * p->kT * (1.0 - exp(-2.0 * z * h / m)));
+        } else {
+            C1 = 1.0;
+            C2 = h;
+            C3 = 0.0;
+        }
+        double th[3] = {0.0, 0.0, 0.0};
+        if (p->kT > 0.0 && z > 0.0) orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
+        double I[3];
+        for (int a = 0; a < 3; ++a) {
+            const double Pn = C1 * mom[3 * b + a] + C2 * (fc[3 * b + a] + z * ub[a]) + C3 * th[a];
+            I[a] = -(Pn - mom[3 * b + a] - h * fc[3 * b + a]);
+        }
+
+        /* reverse: R_new = R' + (h/2) P''/m, P_new = P'' */
+        double Pn_bar[3], I_bar[3] = {0.0, 0.0, 0.0}, ub_bar[3];
+        for (int a = 0; a < 3; ++a) {
+            half_bar[3 * b + a] = pos_bar[3 * b + a];
+            Pn_bar[a] = mom_bar[3 * b + a] + 0.5 * h / m * pos_bar[3 * b + a];
+        }
+        /* force[node] += Delta I / h */
+        for (int q = 0; q < 8; ++q)
+            for (int a = 0; a < 3; ++a) I_bar[a] += wgt[q] * force_bar[a * N + node[q]] / h;
+        double wgt_bar[8];
+        for (int q = 0; q < 8; ++q) {
+            wgt_bar[q] = 0.0;
+            for (int a = 0; a < 3; ++a) wgt_bar[q] += I[a] * force_bar[a * N + node[q]] / h;
+        }
+        /* I = -(P'' - P - h F^c) */
+        for (int a = 0; a < 3; ++a) {
+            Pn_bar[a] -= I_bar[a];
+            p_bar[3 * b + a] = I_bar[a];
+            fc_bar[3 * b + a] = h * I_bar[a];
+        }
+        /* P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta */
+        for (int a = 0; a < 3; ++a) {
+            p_bar[3 * b + a] += C1 * Pn_bar[a];
+            fc_bar[3 * b + a] += C2 * Pn_bar[a];
+            ub_bar[a] = C2 * z * Pn_bar[a];
+        }
+        /* u_b = sum Delta u(node); u = (sum n c + g/2) / rho */
+        for (int q = 0; q < 8; ++q) {
+            double uq_bar[3];
+            for (int a = 0; a < 3; ++a) {
+                wgt_bar[q] += ub_bar[a] * un[q][a];
+                uq_bar[a] = wgt[q] * ub_bar[a];
+                gbar[a] += 0.5 * uq_bar[a] / rn[q];
+            }
+            for (int i = 0; i < Q; ++i) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a) s += (CV[i][a] - un[q][a]) * uq_bar[a];
+                lam[i * N + node[q]] += s / rn[q];
+            }
+        }
+        /* the weights depend on R' */
+        for (int q = 0; q < 8; ++q)
+            for (int a = 0; a < 3; ++a) half_bar[3 * b + a] += wgt_bar[q] * dw[q][a];
+    }
+
+    /* bond forces F_b = mag d, F_a = -mag d, d = R'_b - R'_a,
+     * mag = -k (1 - r0/r): dF_b/dd = mag I - k r0 d d^T / r^3 (symmetric) */
+    for (int q = 0; q < nbonds; ++q) {
+        const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = half[3 * ib + a] - half[3 * ia + a];
+            r2 += d[a] * d[a];
+        }
+        const double r = sqrt(r2);
+        if (r == 0.0) continue;
+        const double mag = -kbond * (r - r0) / r;
+        double v[3], dv = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fc_bar[3 * ib + a] - fc_bar[3 * ia + a];
+            dv += d[a] * v[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            const double d_bar = mag * v[a] - kbond * r0 * d[a] * dv / (r * r * r);
+            half_bar[3 * ib + a] += d_bar;
+            half_bar[3 * ia + a] -= d_bar;
+        }
+    }
+
+    /* R' = R + (h/2) P/m */
+    for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < 3; ++a) {
+            pos_bar[3 * b + a] = half_bar[3 * b + a];
+            mom_bar[3 * b + a] = p_bar[3 * b + a] + 0.5 * h / mass[b] * half_bar[3 * b + a];
+        }
+    free(half);
+    free(fc);
+    free(half_bar);
+    free(fc_bar);
+    free(p_bar);
+}
+
+/* Reverse-mode gradient through nsteps coupled steps (orc_coupled_step)
+ * from n0 and the bead state (pos0, mom0) at step counter step0.
+ * lam: on entry dL/dn(T), on exit dL/dn(0); pos_bar, mom_bar: on entry
+ * dL/dR(T), dL/dP(T), on exit dL/dR(0), dL/dP(0); gbar accumulates dL/dg.
+ * Per step, in reverse: the fluid step's adjoint (which also gives the
+ * adjoint of the spread force at every site), then the particle half's.
+ * Stores all intermediate states (plain and slow). */
+void orc_backward_coupled(const orc_params *p, const double *n0, int32_t nsteps, uint32_t step0, int32_t nb,
+                          const double *pos0, const double *mom0, const double *mass, const double *zeta,
+                          int32_t nbonds, const int32_t *bonds, double kbond, double r0, double *lam, double gbar[3],
+                          double *pos_bar, double *mom_bar)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const size_t sz = sizeof(double) * Q * (size_t)N;
+    const size_t bsz = sizeof(double) * 3 * (size_t)(nb > 0 ? nb : 1);
+    const size_t T = (size_t)(nsteps > 0 ? nsteps : 1);
+    double *states = (double *)malloc(sz * T);
+    double *bpos = (double *)malloc(bsz * T);
+    double *bmom = (double *)malloc(bsz * T);
+    double *work = (double *)malloc(sz);
+    double *force = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *force_bar = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *tp = (double *)malloc(bsz), *tm = (double *)malloc(bsz);
+    memcpy(states, n0, sz);
+    memcpy(bpos, pos0, bsz);
+    memcpy(bmom, mom0, bsz);
+    for (int32_t t = 0; t + 1 < nsteps; ++t) {
+        double *nt = states + (size_t)(t + 1) * Q * N;
+        memcpy(nt, states + (size_t)t * Q * N, sz);
+        memcpy(bpos + (size_t)(t + 1) * 3 * nb, bpos + (size_t)t * 3 * nb, bsz);
+        memcpy(bmom + (size_t)(t + 1) * 3 * nb, bmom + (size_t)t * 3 * nb, bsz);
+        orc_coupled_step(p, nt, work, force, step0 + (uint32_t)t, nb, bpos + (size_t)(t + 1) * 3 * nb,
+                         bmom + (size_t)(t + 1) * 3 * nb, mass, zeta, nbonds, bonds, kbond, r0);
+    }
+    for (int32_t t = nsteps - 1; t >= 0; --t) {
+        const double *nt = states + (size_t)t * Q * N;
+        const uint32_t st = step0 + (uint32_t)t;
+        /* the spread force of step t, from the bead state it started with */
+        memcpy(tp, bpos + (size_t)t * 3 * nb, bsz);
+        memcpy(tm, bmom + (size_t)t * 3 * nb, bsz);
+        memset(force, 0, sizeof(double) * 3 * (size_t)N);
+        orc_couple(p, nt, st, nb, tp, tm, mass, zeta, nbonds, bonds, kbond, r0, force);
+        memset(force_bar, 0, sizeof(double) * 3 * (size_t)N);
+        orc_step_adjoint(p, nt, lam, work, force, force_bar, st, gbar);
+        orc_couple_adjoint(p, nt, st, nb, bpos + (size_t)t * 3 * nb, bmom + (size_t)t * 3 * nb, mass, zeta, nbonds,
+                           bonds, kbond, r0, force_bar, pos_bar, mom_bar, lam, gbar);
+    }
+    free(tp);
+    free(tm);
+    free(force_bar);
+    free(force);
+    free(work);
+    free(bmom);
+    free(bpos);
+    free(states);
+}

@@ -105,3 +105,105 @@ def test_backward_probe_kinetic_energy_loss(orc):
         fd = (probe_loss(orc, pp, _run(orc, pp, n0, T), lo, hi) - probe_loss(orc, pm, _run(orc, pm, n0, T), lo, hi)) / (
             2 * eps)
         assert gbar[a] == pytest.approx(fd, rel=1e-5, abs=1e-12)
+
+
+def _bead_system(orc, rng, L=(8, 7, 6), chains=2, length=3, zeta=(0.5, 2.0)):
+    """Chains of unit-ish bonds placed well inside the box, positions kept at
+    least 0.05 away from the node planes so that the stencil weights are
+    differentiable along the finite-difference path."""
+    nb = chains * length
+    pos = np.zeros((nb, 3))
+    for c in range(chains):
+        start = rng.uniform(1.0, min(L) - 3.0, size=3)
+        for k in range(length):
+            pos[c * length + k] = start + np.array([0.9 * k, 0.3 * k, 0.2 * k])
+    frac = pos - np.floor(pos)
+    pos = np.floor(pos) + np.clip(frac, 0.05, 0.95)
+    mom = rng.normal(scale=0.01, size=(nb, 3))
+    bonds = np.array([[c * length + k, c * length + k + 1] for c in range(chains) for k in range(length - 1)],
+                     dtype=np.int32)
+    z = np.array([zeta[b % len(zeta)] for b in range(nb)])
+    return orc.Beads(pos, mom, np.ones(nb), z, bonds, 0.05, 1.0)
+
+
+def test_couple_adjoint_matches_finite_differences(orc):
+    """One particle half-step (interpolation, OU update, bonds, spreading):
+    the adjoint w.r.t. n, g, R, P of L = wf.force + a.R_new + b.P_new."""
+    rng = np.random.default_rng(5)
+    p = orc.Params(nx=8, ny=7, nz=6, kT=1e-4, seed=4, g=(1e-4, -5e-5, 2e-5))
+    n = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 6, 7, 8)))
+    beads = _bead_system(orc, rng)
+    nb = beads.pos.shape[0]
+    wf = rng.normal(size=(3, 6, 7, 8))
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+
+    def loss(nn, pp, bb):
+        force = np.zeros((3, 6, 7, 8))
+        c = bb.copy()
+        orc.couple(pp, nn, 3, c, force)
+        return (wf * force).sum() + (a * c.pos).sum() + (b * c.mom).sum()
+
+    lam = np.zeros_like(n)
+    gbar = np.zeros(3)
+    pb, mb = a.copy(), b.copy()
+    orc.couple_adjoint(p, n, 3, beads, wf, pb, mb, lam, gbar)
+    eps = 1e-6
+    v = rng.normal(size=n.shape)
+    fd = (loss(n + eps * v, p, beads) - loss(n - eps * v, p, beads)) / (2 * eps)
+    assert (lam * v).sum() == pytest.approx(fd, rel=1e-6, abs=1e-12)
+    for name, bar in (("pos", pb), ("mom", mb)):
+        vb = rng.normal(size=(nb, 3))
+        bp_, bm_ = beads.copy(), beads.copy()
+        setattr(bp_, name, getattr(beads, name) + eps * vb)
+        setattr(bm_, name, getattr(beads, name) - eps * vb)
+        fd = (loss(n, p, bp_) - loss(n, p, bm_)) / (2 * eps)
+        assert (bar * vb).sum() == pytest.approx(fd, rel=1e-6, abs=1e-12), name
+    for k in range(3):
+        gp, gm = list(p.g), list(p.g)
+        gp[k] += eps
+        gm[k] -= eps
+        pp = orc.Params(**{**p.__dict__, "g": tuple(gp)})
+        pm = orc.Params(**{**p.__dict__, "g": tuple(gm)})
+        fd = (loss(n, pp, beads) - loss(n, pm, beads)) / (2 * eps)
+        assert gbar[k] == pytest.approx(fd, rel=1e-6, abs=1e-12)
+
+
+def test_coupled_backward_matches_finite_differences(orc):
+    """Whole coupled steps (particles + fluid with the spread force): the
+    adjoint w.r.t. n(0), g, R(0), P(0) of L = w.n(T) + a.R(T) + b.P(T)."""
+    rng = np.random.default_rng(6)
+    p = orc.Params(nx=8, ny=7, nz=6, kT=1e-4, seed=8, g=(1e-4, -5e-5, 2e-5), gamma_shear=0.2, gamma_bulk=-0.1)
+    n0 = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 6, 7, 8)))
+    beads = _bead_system(orc, rng)
+    nb = beads.pos.shape[0]
+    T = 4
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+
+    def loss(nn, pp, bb):
+        n = nn.copy()
+        c = bb.copy()
+        for t in range(T):
+            orc.coupled_step(pp, n, t, c)
+        return (w * n).sum() + (a * c.pos).sum() + (b * c.mom).sum()
+
+    lam0, gbar, pb0, mb0 = orc.backward_coupled(p, n0, T, beads, w, a, b)
+    eps = 1e-6
+    v = rng.normal(size=n0.shape)
+    fd = (loss(n0 + eps * v, p, beads) - loss(n0 - eps * v, p, beads)) / (2 * eps)
+    assert (lam0 * v).sum() == pytest.approx(fd, rel=1e-6)
+    for name, bar in (("pos", pb0), ("mom", mb0)):
+        vb = rng.normal(size=(nb, 3))
+        bp_, bm_ = beads.copy(), beads.copy()
+        setattr(bp_, name, getattr(beads, name) + eps * vb)
+        setattr(bm_, name, getattr(beads, name) - eps * vb)
+        fd = (loss(n0, p, bp_) - loss(n0, p, bm_)) / (2 * eps)
+        assert (bar * vb).sum() == pytest.approx(fd, rel=1e-6), name
+    for k in range(3):
+        gp, gm = list(p.g), list(p.g)
+        gp[k] += eps
+        gm[k] -= eps
+        pp = orc.Params(**{**p.__dict__, "g": tuple(gp)})
+        pm = orc.Params(**{**p.__dict__, "g": tuple(gm)})
+        fd = (loss(n0, pp, beads) - loss(n0, pm, beads)) / (2 * eps)
+        assert gbar[k] == pytest.approx(fd, rel=1e-6)
