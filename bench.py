@@ -24,8 +24,9 @@ Prints ONE JSON line with, beside the throughput:
                 MLUPS (nearest and stochastic rounding, kT > 0 and kT = 0)
                 on the same box without beads, the batched form (512 replica boxes, edges drawn from
                 {24, 32, 40, 48, 64}, HIP graph replay) and the
-                differentiation form (taped forward and adjoint, 128^3, 500
-                steps, checkpoints every 50).
+                differentiation form (taped forward and adjoint of 500
+                coupled steps at 128^3 with 16 x 32 beads, checkpoints every
+                50).
 """
 from __future__ import annotations
 
@@ -161,26 +162,35 @@ def run_forms(L: int) -> dict:
     out["batched_mlups"] = round(b["mlups"], 1)
     out["batched_sites"] = b["sites"]
     print("# forms: batch done", file=sys.stderr, flush=True)
+    import numpy as np
+
+    from paper_0803_2826_amd.inputs import random_walk_chains
+
     Lb, T, K = 128, 500, 50
     p = lattice.FluidParams(nx=Lb, ny=Lb, nz=Lb, kT=KT, seed=0, body_force=(1e-5, 0.0, 0.0), track_totals=False)
     lat = lattice.Lattice(p)
     lat.init_equilibrium()
+    pos, mom, bonds = random_walk_chains(16, 32, (Lb, Lb, Lb), seed=0)
+    nb = pos.shape[0]
+    beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, K_BOND, 1.0)
     lat.step(2)
     w = torch.randn(19 * Lb ** 3, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record(lat.stream)
     lat.tape_begin(K)
-    lat.step(T)
+    for _ in range(T):
+        lat.coupled_step(beads)
     e[1].record(lat.stream)
-    lat.backward(w)
+    lat.backward_coupled(w)
     e[2].record(lat.stream)
     torch.cuda.synchronize()
     lat.close()
     fwd_ms, bwd_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
     out["taped_forward_mlups"] = round(Lb ** 3 * T / (fwd_ms * 1e-3) / 1e6, 1)
     out["backward_mlups"] = round(Lb ** 3 * T / (bwd_ms * 1e-3) / 1e6, 1)
-    out["backward_config"] = f"{Lb}^3, {T} steps, checkpoints every {K}, FP32"
+    out["backward_config"] = (f"{Lb}^3, {T} coupled steps with 16 x 32 beads (zeta 20, k 10 kT), checkpoints every "
+                              f"{K}, FP32 fluid, FP64 beads; gradients w.r.t. n(0), g, R(0), P(0)")
     print("# forms: backward done", file=sys.stderr, flush=True)
     return out
 

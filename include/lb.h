@@ -275,10 +275,33 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * eq. moment_two_external_force), segment by segment from the checkpoints
  * with the states of a segment recomputed forward (checkpoint_every step
  * buffers are allocated), the noise replayed from its Philox counters.
- * Errors: LB_ESTATE (no tape), LB_EUNSUPPORTED (bead forces entered a taped
- * step, or a batch context), LB_ENOMEM. */
+ * Taped coupled steps (lb_couple before lb_step) are differentiated too:
+ * each lb_couple while recording stores a device copy of the bead state
+ * (R, P) it starts from and keeps the lb_beads descriptor, so the arrays
+ * mass, zeta and bonds must stay valid and unchanged until lb_backward, the
+ * bead count must be the same in every taped coupled step, and the bead
+ * state must change only through lb_couple between taped steps.  In the
+ * reverse sweep a coupled step rebuilds its spread force from the stored
+ * bead state, the fluid adjoint also yields the adjoint of the bead force at
+ * the touched nodes, and the adjoint of the particle half (half drift,
+ * harmonic bonds, trilinear interpolation with the weights differentiated in
+ * R, the momentum update eq. langevin_momentum_update with its noise
+ * replayed, the spread reaction eq. ftotal) carries the bead adjoints back
+ * and adds the interpolation's share to dL/dn and dL/dg.
+ * lb_backward_coupled takes and returns the bead adjoints as well:
+ *   dL_dR_T, dL_dP_T: dL/dR, dL/dP of the bead state after the last step
+ *                     (device FP64 [n][3]; NULL = zero),
+ *   dL_dR_0, dL_dP_0: dL/dR, dL/dP of the bead state at the first taped
+ *                     coupled step (device FP64 [n][3]; NULL = not wanted);
+ * without taped coupled steps they are ignored.  lb_backward is
+ * lb_backward_coupled with all four NULL.
+ * Errors: LB_ESTATE (no tape, or called between lb_couple and lb_step;
+ * lb_tape_begin between lb_couple and lb_step), LB_EUNSUPPORTED (a batch
+ * context; the bead count changed between taped coupled steps), LB_ENOMEM. */
 int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
 int lb_backward(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3]);
+int lb_backward_coupled(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, const double *dL_dR_T, const double *dL_dP_T,
+                        void *dL_dn_0, double dL_dg[3], double *dL_dR_0, double *dL_dP_0);
 
 /* Synchronise the context stream and report latched device errors. */
 int lb_sync(lb_ctx *ctx);

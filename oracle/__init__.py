@@ -341,6 +341,17 @@ def collide_site_adjoint(p: Params, n, F, gnoise, nbar_star):
     return nb, Fb
 
 
+def step_adjoint(p: Params, n: np.ndarray, lam: np.ndarray, step_index: int, gbar: np.ndarray, extra_force=None,
+                 extra_bar=None) -> None:
+    """Adjoint of step(): lam (in: dL/dn after the step, out: before it) and
+    gbar in place; with extra_force, its adjoint accumulates into extra_bar."""
+    work = np.empty_like(lam)
+    pc = p.c()
+    ef = _f64(extra_force) if extra_force is not None else None
+    lib().orc_step_adjoint(ctypes.byref(pc), _dp(_f64(n)), _dp(lam), _dp(work), _dp(ef) if ef is not None else None,
+                           _dp(extra_bar) if extra_bar is not None else None, int(step_index), _dp(gbar))
+
+
 def _bonds_ptr(beads: "Beads"):
     bonds = np.ascontiguousarray(beads.bonds, dtype=np.int32).reshape(-1)
     return bonds, (bonds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if bonds.size else None)

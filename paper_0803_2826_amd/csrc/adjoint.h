@@ -32,12 +32,17 @@ struct AdjArgs {
     CollideConst cc;
     uint32_t step;
     double *partials;       // [gridDim][3] block sums of Fbar
+    // bead force of the step (FORCE variant): F = g + force at sites whose
+    // bit is set in fmask; the adjoint of that force is written to fbar there
+    const float *force;     // [3][N]
+    const uint32_t *fmask;  // [ceil(N/32)]
+    float *fbar;            // [3][N]
 };
 
 // Opposite direction of population i (pairs are adjacent: 1<->2, 3<->4, ...).
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
-template <int ST, bool THERMAL>
+template <int ST, bool THERMAL, bool FORCE>
 __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
 {
     using S = Storage<ST>;
@@ -62,7 +67,16 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
             jy += (float)kCY[i] * d[i];
             jz += (float)kCZ[i] * d[i];
         }
-        const float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
+        float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
+        bool flagged = false;
+        if (FORCE) {
+            flagged = (a.fmask[s >> 5] >> (s & 31u)) & 1u;
+            if (flagged) {
+                F[0] += a.force[s];
+                F[1] += a.force[(size_t)N + s];
+                F[2] += a.force[2 * (size_t)N + s];
+            }
+        }
         const float rho = a.cc.rho0 + m0;
         const float inv_rho = 1.0f / rho;
         jx += 0.5f * F[0];
@@ -198,6 +212,11 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         out[18] = E9 - O9;
 #pragma unroll
         for (int i = 0; i < Q; ++i) st_plane_nt<float>(a.lam_out + (size_t)i * N, N * 4u, s, out[i]);
+        if (FORCE && flagged) {
+            a.fbar[s] = Fbs[0];
+            a.fbar[(size_t)N + s] = Fbs[1];
+            a.fbar[2 * (size_t)N + s] = Fbs[2];
+        }
     }
     // block sums of Fbar (FP64 partial per block)
     __shared__ double red[4][3];

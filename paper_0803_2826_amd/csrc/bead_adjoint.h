@@ -1,0 +1,218 @@
+// Differentiation form, particle half: adjoint (reverse mode) of one
+// coupled step's bead kernels (k_bead_half, k_bonds, k_bead_update of
+// couple.h; Sec. "Force coupling", Sec. "Interpolating functions").
+//
+// The forward map of the particle half, per bead (h = 1):
+//   R' = R + (h/2) P/m                      half drift (eq. pTrotter)
+//   F^c = F^c(R')                           harmonic bonds
+//   u_b = sum_q w_q(R') u_q,  u_q = (sum_i n_i c_i + g/2) / rho_q   (eq. ufluid_discrete)
+//   P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta   (eq. langevin_momentum_update)
+//   I = -(P'' - P - h F^c),  f(node_q) += w_q I / h                  (eq. ftotal)
+//   R_new = R' + (h/2) P''/m,  P_new = P''
+// Given the adjoints of (R_new, P_new) and fbar, the adjoint of the spread
+// force at every node (written by the FORCE variant of k_adjoint_step), the
+// kernels below produce the adjoints of (R, P), add the interpolation's
+// contribution w_q (c_i - u_q).ubar_b / rho_q to lambda_i at the bead's 8
+// nodes and w_q ubar_b / (2 rho_q) to gbar.  The stencil weights are
+// differentiated where they are differentiable (R' off the node planes):
+// d w_q / d R'_a = (+1 or -1) times the other two 1-D weights.  The bead
+// noise is not needed: P'' is taken from the recomputed forward update.
+#pragma once
+
+#include "couple.h"
+
+namespace lbmi {
+
+struct BeadAdjArgs {
+    const void *pop;        // state buffer A of the step (pre-collision n_t(r) = A_i(r - c_i))
+    Geom geo;
+    double rho0;
+    double g[3];
+    int32_t n;
+    const double *mom0;     // P at the start of the step [n][3]
+    const double *mom1;     // P'' of the recomputed forward update [n][3]
+    const double *mass;
+    const double *zeta;
+    const double *half;     // R' [n][3]
+    const double *fc;       // F^c at R' [n][3]
+    const float *fbar;      // [3][N] adjoint of the spread force
+    const double *pos_bar;  // adjoint of R_new [n][3]
+    const double *mom_bar;  // adjoint of P_new [n][3]
+    double *half_bar;       // out: adjoint of R' without the bond term [n][3]
+    double *fc_bar;         // out: adjoint of F^c [n][3]
+    double *p_bar;          // out: adjoint of P without the half-drift term [n][3]
+    float *lam;             // [19][N] adjoint of n_t, accumulated at the nodes
+    double *gbar;           // [3] accumulated
+};
+
+// Sum over the 8 lanes of one bead (lanes 8b .. 8b+7 of a wave).
+__device__ __forceinline__ double bead_lane_sum(double v)
+{
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// 8 consecutive lanes per bead, one per stencil node (node order and
+// weights as in k_bead_update).
+template <int ST>
+__global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = t >> 3, q = t & 7;
+    const bool live = b < a.n;
+    const Geom &g = a.geo;
+    uint32_t node = 0;
+    double wq = 0.0, dw[3] = {0.0, 0.0, 0.0}, uq[3] = {0.0, 0.0, 0.0}, rho = 1.0, fb[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        const uint32_t L[3] = {g.nx, g.ny, g.nz};
+        uint32_t cpos[3];
+        double w1[3], sgn[3];
+        for (int c = 0; c < 3; ++c) {
+            const double r = a.half[3 * b + c];
+            const double f = floor(r);
+            const double frac = r - f;
+            const double wrapped = f - (double)L[c] * floor(f / (double)L[c]);
+            uint32_t wi = (uint32_t)wrapped;
+            if (wi >= L[c]) wi = 0;
+            const uint32_t bit = (q >> c) & 1;
+            cpos[c] = (wi + bit) % L[c];
+            w1[c] = bit ? frac : 1.0 - frac;
+            sgn[c] = bit ? 1.0 : -1.0;
+        }
+        node = cpos[0] + g.nx * (cpos[1] + g.ny * cpos[2]);
+        wq = w1[0] * w1[1] * w1[2];
+        dw[0] = sgn[0] * w1[1] * w1[2];
+        dw[1] = w1[0] * sgn[1] * w1[2];
+        dw[2] = w1[0] * w1[1] * sgn[2];
+        uint32_t xx, yy, zz;
+        const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
+        const T *pop = static_cast<const T *>(a.pop);
+        double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double v = (double)S::ld(pop[(size_t)i * g.N + pull_src(node, o, i)], 0.f);
+            m += v;
+            j[0] += v * kCX[i];
+            j[1] += v * kCY[i];
+            j[2] += v * kCZ[i];
+        }
+        rho = a.rho0 + m;
+        for (int c = 0; c < 3; ++c) {
+            uq[c] = (j[c] + 0.5 * a.g[c]) / rho;
+            fb[c] = (double)a.fbar[(size_t)c * g.N + node];
+        }
+    }
+    // adjoint of the spread reaction: Ibar = sum_q w_q fbar(node_q) / h
+    const double h = 1.0;
+    double Ib[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Ib[c] = bead_lane_sum(wq * fb[c]) / h;
+    if (!live) return;
+    const double m = a.mass[b], z = a.zeta[b];
+    double C1, C2;
+    if (z > 0.0) {
+        C1 = exp(-z * h / m);
+        C2 = (m / z) * (1.0 - C1);
+    } else {
+        C1 = 1.0;
+        C2 = h;
+    }
+    double I[3], Pnb[3], ubb[3], pb[3], fcb[3];
+    for (int c = 0; c < 3; ++c) {
+        const double P = a.mom0[3 * b + c], Pn = a.mom1[3 * b + c], Fc = a.fc[3 * b + c];
+        I[c] = -(Pn - P - h * Fc);
+        // R_new = R' + (h/2) P''/m, P_new = P'';  I = -(P'' - P - h F^c)
+        Pnb[c] = a.mom_bar[3 * b + c] + 0.5 * h / m * a.pos_bar[3 * b + c] - Ib[c];
+        pb[c] = Ib[c] + C1 * Pnb[c];
+        fcb[c] = h * Ib[c] + C2 * Pnb[c];
+        ubb[c] = C2 * z * Pnb[c];
+    }
+    // weights: from the spread (I . fbar / h) and from the interpolation (ubar . u_q)
+    double wb = 0.0, gq[3];
+    for (int c = 0; c < 3; ++c) {
+        wb += I[c] * fb[c] / h + ubb[c] * uq[c];
+        gq[c] = 0.5 * wq * ubb[c] / rho;
+    }
+    // u_q = (sum n c + g/2) / rho: lambda_i(node) += w_q (c_i - u_q) . ubar / rho
+    if (wq != 0.0) {
+        const double s0 = -(uq[0] * ubb[0] + uq[1] * ubb[1] + uq[2] * ubb[2]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double v = wq * (s0 + kCX[i] * ubb[0] + kCY[i] * ubb[1] + kCZ[i] * ubb[2]) / rho;
+            atomicAdd(&a.lam[(size_t)i * g.N + node], (float)v);
+        }
+    }
+    double hb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        hb[c] = bead_lane_sum(wb * dw[c]);
+        gq[c] = bead_lane_sum(gq[c]);
+    }
+    if (q == 0) {
+        for (int c = 0; c < 3; ++c) {
+            a.half_bar[3 * b + c] = a.pos_bar[3 * b + c] + hb[c];
+            a.fc_bar[3 * b + c] = fcb[c];
+            a.p_bar[3 * b + c] = pb[c];
+            atomicAdd(&a.gbar[c], gq[c]);
+        }
+    }
+}
+
+// Bond forces F_b = mag d, F_a = -mag d (d = R'_b - R'_a, mag = -k (1 - r0/r)):
+// dF_b/dd = mag I - k r0 d d^T / r^3 (symmetric), so
+// dbar = (dF_b/dd)(fcbar_b - fcbar_a), half_bar_b += dbar, half_bar_a -= dbar.
+__global__ void k_bonds_adjoint(const double *__restrict__ half, const double *__restrict__ fc_bar, double *half_bar,
+                                const int32_t *__restrict__ bonds, int nbonds, double kb, double r0, int nbeads)
+{
+    const int qd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qd >= nbonds) return;
+    const int ia = bonds[2 * qd], ib = bonds[2 * qd + 1];
+    if (ia < 0 || ib < 0 || ia >= nbeads || ib >= nbeads) return;
+    double d[3], v[3], r2 = 0.0, dv = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        d[c] = half[3 * ib + c] - half[3 * ia + c];
+        v[c] = fc_bar[3 * ib + c] - fc_bar[3 * ia + c];
+        r2 += d[c] * d[c];
+        dv += d[c] * v[c];
+    }
+    const double r = sqrt(r2);
+    if (r == 0.0) return;
+    const double mag = -kb * (r - r0) / r;
+    for (int c = 0; c < 3; ++c) {
+        const double db = mag * v[c] - kb * r0 * d[c] * dv / (r2 * r);
+        atomicAdd(&half_bar[3 * ib + c], db);
+        atomicAdd(&half_bar[3 * ia + c], -db);
+    }
+}
+
+// R' = R + (h/2) P/m:  Rbar = R'bar,  Pbar = pbar + (h/2m) R'bar.
+__global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, const double *__restrict__ half_bar,
+                                      const double *__restrict__ p_bar, double *pos_bar, double *mom_bar)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const double hm = 0.5 / mass[b];
+    for (int c = 0; c < 3; ++c) {
+        pos_bar[3 * b + c] = half_bar[3 * b + c];
+        mom_bar[3 * b + c] = p_bar[3 * b + c] + hm * half_bar[3 * b + c];
+    }
+}
+
+// Zero the force, its adjoint and the bitmap word of every touched node.
+__global__ void k_clear_touched_adj(float *force, float *fbar, uint32_t *fmask, const int32_t *list,
+                                    const int32_t *count, int cap, uint32_t N)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cap || idx >= *count) return;
+    const uint32_t s = (uint32_t)list[idx];
+    for (int c = 0; c < 3; ++c) {
+        force[(size_t)c * N + s] = 0.f;
+        fbar[(size_t)c * N + s] = 0.f;
+    }
+    fmask[s >> 5] = 0u;
+}
+
+}  // namespace lbmi

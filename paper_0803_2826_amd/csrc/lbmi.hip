@@ -16,6 +16,7 @@
 
 #include "../../include/lb.h"
 #include "adjoint.h"
+#include "bead_adjoint.h"
 #include "batch.h"
 #include "couple.h"
 
@@ -86,13 +87,25 @@ struct lb_ctx {
     bool taping = false;
     int tape_k = 0;
     uint64_t tape_step0 = 0;
-    bool tape_force_used = false;
     std::vector<void *> checkpoints;  // A-buffer copies at tape_step0 + s * tape_k
     void *seg = nullptr;              // tape_k step buffers of one segment
     size_t seg_bytes = 0;
     float *lamA = nullptr, *lamB = nullptr;
     double *gbar_d = nullptr;
     double *adj_partials = nullptr;
+    // bead state of the taped coupled steps: slot per taped step (-1: no
+    // bead force), the bead configuration and a snapshot of (R, P) at the
+    // start of each coupled step, [slot][2][n][3] FP64
+    std::vector<int32_t> tape_slot;
+    std::vector<lb_beads> tape_beads;
+    int pending_slot = -1;
+    int tape_nb = 0;
+    double *snap = nullptr;
+    size_t snap_cap = 0;              // slots allocated
+    // backward scratch of the particle adjoint
+    double *bead_work = nullptr;      // [7][n][3]: pos_w, mom_w, half_bar, fc_bar, p_bar, pos_bar, mom_bar
+    int bead_work_n = 0;
+    float *fbar = nullptr;            // [3][N] adjoint of the spread force (zero outside touched nodes)
     std::string err;
 };
 
@@ -326,6 +339,80 @@ void free_tape(lb_ctx *c)
     for (void *p : c->checkpoints) (void)hipFree(p);
     c->checkpoints.clear();
     c->taping = false;
+    c->tape_slot.clear();
+    c->tape_beads.clear();
+    c->pending_slot = -1;
+    c->tape_nb = 0;
+}
+
+// The particle half of one coupled step (k_bead_half, k_bonds,
+// k_bead_update) on the populations `pop`, updating (pos, mom) in place and
+// spreading into the force field, its bitmap and the touched-node list.
+void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, double *mom, uint32_t step)
+{
+    CoupleArgs a;
+    a.pop = pop;
+    a.geo = c->geo;
+    a.rho0 = c->p.rho0;
+    for (int k = 0; k < 3; ++k) a.g[k] = c->p.body_force[k];
+    a.kT = c->p.kT;
+    a.key0 = c->cc.key0;
+    a.key1 = c->cc.key1;
+    a.box = c->cc.box;
+    a.step = step;
+    a.n = b->n;
+    a.pos = pos;
+    a.mom = mom;
+    a.mass = b->mass;
+    a.zeta = b->zeta;
+    a.half = c->half;
+    a.fc = c->fc;
+    a.force = c->force;
+    a.fmask = c->fmask;
+    a.list = c->list;
+    a.count = c->count;
+    const unsigned gb = grid_for((size_t)b->n, 256);
+    hipLaunchKernelGGL(k_bead_half, dim3(gb), dim3(256), 0, c->stream, a);
+    if (b->nbonds > 0)
+        hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
+                           b->bonds, b->nbonds, b->k_bond, b->r0, b->n);
+    by_storage(c->p.storage, [&](auto st) {
+        hipLaunchKernelGGL((k_bead_update<decltype(st)::value>), dim3(grid_for(8 * (size_t)b->n, 256)), dim3(256), 0,
+                           c->stream, a);
+    });
+}
+
+// Snapshot of the bead state at the start of a taped coupled step.
+int tape_bead_snapshot(lb_ctx *c, const lb_beads *b)
+{
+    if (c->tape_nb == 0) c->tape_nb = b->n;
+    if (b->n != c->tape_nb)
+        return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
+    const size_t slot_doubles = 6 * (size_t)b->n;
+    const size_t slot = c->tape_beads.size();
+    if (slot + 1 > c->snap_cap) {
+        const size_t cap = std::max<size_t>(16, 2 * c->snap_cap);
+        double *p = nullptr;
+        if (hipMalloc(&p, cap * slot_doubles * sizeof(double)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "bead tape allocation failed");
+        if (c->snap && slot > 0)
+            LB_TRY(check(c, hipMemcpyAsync(p, c->snap, slot * slot_doubles * sizeof(double), hipMemcpyDeviceToDevice,
+                                           c->stream), "bead tape copy"));
+        if (c->snap) {
+            LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+            (void)hipFree(c->snap);
+        }
+        c->snap = p;
+        c->snap_cap = cap;
+    }
+    double *dst = c->snap + slot * slot_doubles;
+    LB_TRY(check(c, hipMemcpyAsync(dst, b->pos, 3 * (size_t)b->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+                 "bead snapshot"));
+    LB_TRY(check(c, hipMemcpyAsync(dst + 3 * (size_t)b->n, b->mom, 3 * (size_t)b->n * sizeof(double),
+                                   hipMemcpyDeviceToDevice, c->stream), "bead snapshot"));
+    c->tape_beads.push_back(*b);
+    c->pending_slot = (int)slot;
+    return LB_OK;
 }
 
 StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
@@ -743,7 +830,7 @@ int lb_destroy(lb_ctx *c)
     for (int k = 0; k < 2; ++k)
         if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
     free_tape(c);
-    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials};
+    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials, c->snap, c->bead_work, c->fbar};
     for (void *q : adj)
         if (q) (void)hipFree(q);
     if (c->batch) {
@@ -856,6 +943,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
     for (int32_t t = 0; t < nsteps; ++t) {
         const bool frc = c->pending_force;
         LB_TRY(select_launch(c, frc));
+        if (c->taping) c->tape_slot.push_back(frc ? c->pending_slot : -1);
         StepArgs a;
         a.src = c->bufA;
         a.dst = c->bufB;
@@ -871,7 +959,6 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         a.flags = c->flags;
         a.fmask = c->fmask;
         a.force = c->force;
-        if (frc && c->taping) c->tape_force_used = true;
         by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
         LB_LAUNCH_CHECK(c, "stream_collide");
         if (frc) {
@@ -879,6 +966,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
                                c->force, c->fmask, c->list, c->count, c->pending_rows, c->geo.N);
             LB_LAUNCH_CHECK(c, "clear_touched");
             c->pending_force = false;
+            c->pending_slot = -1;
         }
         std::swap(c->bufA, c->bufB);
         ++c->step;
@@ -902,36 +990,9 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     if (!std::isfinite(b->k_bond) || !std::isfinite(b->r0)) return fail(c, LB_EINVAL, "bond parameters must be finite");
     LB_TRY(use_device(c));
     LB_TRY(ensure_bead_buffers(c, b->n));
-    CoupleArgs a;
-    a.pop = c->bufA;
-    a.geo = c->geo;
-    a.rho0 = c->p.rho0;
-    for (int k = 0; k < 3; ++k) a.g[k] = c->p.body_force[k];
-    a.kT = c->p.kT;
-    a.key0 = c->cc.key0;
-    a.key1 = c->cc.key1;
-    a.box = c->cc.box;
-    a.step = (uint32_t)c->step;
-    a.n = b->n;
-    a.pos = b->pos;
-    a.mom = b->mom;
-    a.mass = b->mass;
-    a.zeta = b->zeta;
-    a.half = c->half;
-    a.fc = c->fc;
-    a.force = c->force;
-    a.fmask = c->fmask;
-    a.list = c->list;
-    a.count = c->count;
-    const unsigned gb = grid_for((size_t)b->n, 256);
-    hipLaunchKernelGGL(k_bead_half, dim3(gb), dim3(256), 0, c->stream, a);
-    if (b->nbonds > 0)
-        hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
-                           b->bonds, b->nbonds, b->k_bond, b->r0, b->n);
-    by_storage(c->p.storage, [&](auto st) {
-        hipLaunchKernelGGL((k_bead_update<decltype(st)::value>), dim3(grid_for(8 * (size_t)b->n, 256)), dim3(256), 0,
-                           c->stream, a);
-    });
+    c->pending_slot = -1;
+    if (c->taping) LB_TRY(tape_bead_snapshot(c, b));
+    launch_couple(c, c->bufA, b, b->pos, b->mom, (uint32_t)c->step);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
     c->pending_rows = 8 * b->n;
@@ -1082,20 +1143,30 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
     if (!c) return LB_EINVAL;
     if (c->batch) return fail(c, LB_EUNSUPPORTED, "differentiation is per single box");
     if (checkpoint_every < 1) return fail(c, LB_EINVAL, "checkpoint_every must be >= 1");
+    if (c->pending_force) return fail(c, LB_ESTATE, "lb_tape_begin between lb_couple and lb_step");
     LB_TRY(use_device(c));
     free_tape(c);
     c->tape_k = checkpoint_every;
     c->tape_step0 = c->step;
-    c->tape_force_used = false;
     c->taping = true;
     return push_checkpoint(c);
 }
 
-int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3])
+// Reverse sweep over the tape.  Per segment: restore its checkpoint and
+// recompute its step buffers with the forward kernels (the bead force of a
+// coupled step is rebuilt from that step's bead snapshot, with the same
+// noise); then, from the last step of the segment back, the adjoint step:
+// for a coupled step the force is rebuilt once more, the fluid adjoint
+// (FORCE variant) also writes the adjoint of the spread force at the
+// flagged sites, and the particle adjoint (k_bead_adjoint, k_bonds_adjoint,
+// k_bead_adjoint_finish) carries the bead adjoints back and adds the
+// interpolation's share to lambda and gbar.
+static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const double *dR_T, const double *dP_T,
+                         void *dL_dn_0, double dL_dg[3], double *dR_0, double *dP_0)
 {
     if (!c) return LB_EINVAL;
     if (!c->taping) return fail(c, LB_ESTATE, "lb_backward needs lb_tape_begin before the steps");
-    if (c->tape_force_used) return fail(c, LB_EUNSUPPORTED, "the taped steps used bead forces (not differentiated)");
+    if (c->pending_force) return fail(c, LB_ESTATE, "lb_backward between lb_couple and lb_step");
     if (!dL_dn_T || !dL_dn_0) return fail(c, LB_EINVAL, "gradient arrays must be non-NULL");
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
     LB_TRY(use_device(c));
@@ -1103,6 +1174,8 @@ int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, do
     const uint64_t T = c->step - c->tape_step0;
     const int K = c->tape_k;
     const size_t sb = state_bytes(c);
+    const int nbd = c->tape_nb;
+    const bool coupled = !c->tape_beads.empty();
     if (c->seg_bytes < (size_t)K * sb) {
         (void)hipFree(c->seg);
         c->seg = nullptr;
@@ -1117,6 +1190,43 @@ int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, do
             hipMalloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double)) != hipSuccess)
             return fail(c, LB_ENOMEM, "adjoint buffers allocation failed");
     }
+    double *pos_w = nullptr, *mom_w = nullptr, *half_bar = nullptr, *fc_bar = nullptr, *p_bar = nullptr;
+    double *pos_bar = nullptr, *mom_bar = nullptr;
+    if (coupled) {
+        if (c->bead_work_n < nbd) {
+            (void)hipFree(c->bead_work);
+            c->bead_work = nullptr;
+            c->bead_work_n = 0;
+            if (hipMalloc(&c->bead_work, 21 * (size_t)nbd * sizeof(double)) != hipSuccess)
+                return fail(c, LB_ENOMEM, "bead adjoint buffers allocation failed");
+            c->bead_work_n = nbd;
+        }
+        if (!c->fbar) {
+            if (hipMalloc(&c->fbar, 3 * N * sizeof(float)) != hipSuccess)
+                return fail(c, LB_ENOMEM, "force adjoint allocation failed");
+            hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->fbar, 3 * N);
+        }
+        const size_t n3 = 3 * (size_t)nbd;
+        pos_w = c->bead_work;
+        mom_w = pos_w + n3;
+        half_bar = mom_w + n3;
+        fc_bar = half_bar + n3;
+        p_bar = fc_bar + n3;
+        pos_bar = p_bar + n3;
+        mom_bar = pos_bar + n3;
+        if (dR_T)
+            LB_TRY(check(c, hipMemcpyAsync(pos_bar, dR_T, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+                         "bead gradient copy"));
+        else
+            hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(2 * n3, 256)), dim3(256), 0, c->stream,
+                               reinterpret_cast<float *>(pos_bar), 2 * n3);
+        if (dP_T)
+            LB_TRY(check(c, hipMemcpyAsync(mom_bar, dP_T, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+                         "bead gradient copy"));
+        else
+            hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(2 * n3, 256)), dim3(256), 0, c->stream,
+                               reinterpret_cast<float *>(mom_bar), 2 * n3);
+    }
     if (dtype == LB_F64)
         hipLaunchKernelGGL(k_to_f32<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double *>(dL_dn_T),
                            c->lamA, n19);
@@ -1125,45 +1235,114 @@ int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, do
                            c->lamA, n19);
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<float *>(c->gbar_d), (size_t)6);
     LB_LAUNCH_CHECK(c, "backward set-up");
+
+    // rebuild the bead force of taped step t (slot >= 0) from its snapshot on the populations `pop`
+    auto rebuild_force = [&](int slot, const void *pop, uint32_t step) {
+        const size_t n3 = 3 * (size_t)nbd;
+        const double *snap = c->snap + (size_t)slot * 2 * n3;
+        (void)hipMemcpyAsync(pos_w, snap, 2 * n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        launch_couple(c, pop, &c->tape_beads[slot], pos_w, mom_w, step);
+    };
+    auto clear_force = [&]() {
+        hipLaunchKernelGGL(k_clear_touched_adj, dim3(grid_for(8 * (size_t)nbd, 256)), dim3(256), 0, c->stream,
+                           c->force, c->fbar, c->fmask, c->list, c->count, 8 * nbd, c->geo.N);
+    };
+
+    const unsigned saved_blocks = c->nblocks;
+    const int saved_block = c->block;
+    c->block = 256;
+    c->nblocks = (int)nb;
     const int nseg = (int)((T + K - 1) / K);
-    for (int sg = nseg - 1; sg >= 0; --sg) {
+    int rc = LB_OK;
+    for (int sg = nseg - 1; sg >= 0 && rc == LB_OK; --sg) {
         const uint64_t t0 = (uint64_t)sg * K;
         const int len = (int)std::min<uint64_t>((uint64_t)K, T - t0);
         char *seg = static_cast<char *>(c->seg);
-        LB_TRY(check(c, hipMemcpyAsync(seg, c->checkpoints[sg], sb, hipMemcpyDeviceToDevice, c->stream),
-                     "checkpoint restore"));
+        rc = check(c, hipMemcpyAsync(seg, c->checkpoints[sg], sb, hipMemcpyDeviceToDevice, c->stream),
+                   "checkpoint restore");
+        if (rc != LB_OK) break;
         for (int k = 0; k + 1 < len; ++k) {
-            const StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb,
-                                               (uint32_t)(c->tape_step0 + t0 + k));
-            const unsigned saved = c->nblocks;
-            const int saved_block = c->block;
-            c->block = 256;
-            c->nblocks = (int)nb;
-            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
-            c->block = saved_block;
-            c->nblocks = (int)saved;
+            const uint32_t step = (uint32_t)(c->tape_step0 + t0 + k);
+            const int slot = c->tape_slot[t0 + k];
+            StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb, step);
+            if (slot >= 0) {
+                rebuild_force(slot, seg + (size_t)k * sb, step);
+                a.fmask = c->fmask;
+                a.force = c->force;
+            }
+            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, slot >= 0); });
+            if (slot >= 0) clear_force();
         }
-        LB_LAUNCH_CHECK(c, "backward recompute");
+        if ((rc = hipGetLastError() == hipSuccess ? LB_OK : fail(c, LB_EDEVICE, "backward recompute")) != LB_OK) break;
         for (int k = len - 1; k >= 0; --k) {
+            const uint32_t step = (uint32_t)(c->tape_step0 + t0 + k);
+            const int slot = c->tape_slot[t0 + k];
+            const void *pop = seg + (size_t)k * sb;
             AdjArgs aa;
-            aa.state = seg + (size_t)k * sb;
+            aa.state = pop;
             aa.lam_in = c->lamA;
             aa.lam_out = c->lamB;
             aa.geo = c->geo;
             aa.cc = c->cc;
-            aa.step = (uint32_t)(c->tape_step0 + t0 + k);
+            aa.step = step;
             aa.partials = c->adj_partials;
+            aa.force = c->force;
+            aa.fmask = c->fmask;
+            aa.fbar = c->fbar;
+            if (slot >= 0) rebuild_force(slot, pop, step);
             by_storage(c->p.storage, [&](auto st) {
                 constexpr int ST = decltype(st)::value;
-                if (c->thermal) hipLaunchKernelGGL((k_adjoint_step<ST, true>), dim3(nb), dim3(256), 0, c->stream, aa);
-                else hipLaunchKernelGGL((k_adjoint_step<ST, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+                if (slot >= 0) {
+                    if (c->thermal) hipLaunchKernelGGL((k_adjoint_step<ST, true, true>), dim3(nb), dim3(256), 0, c->stream, aa);
+                    else hipLaunchKernelGGL((k_adjoint_step<ST, false, true>), dim3(nb), dim3(256), 0, c->stream, aa);
+                } else {
+                    if (c->thermal) hipLaunchKernelGGL((k_adjoint_step<ST, true, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+                    else hipLaunchKernelGGL((k_adjoint_step<ST, false, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+                }
             });
             hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3,
                                c->gbar_d);
+            if (slot >= 0) {
+                const lb_beads &bc = c->tape_beads[slot];
+                const size_t n3 = 3 * (size_t)nbd;
+                BeadAdjArgs ba;
+                ba.pop = pop;
+                ba.geo = c->geo;
+                ba.rho0 = c->p.rho0;
+                for (int q = 0; q < 3; ++q) ba.g[q] = c->p.body_force[q];
+                ba.n = nbd;
+                ba.mom0 = c->snap + (size_t)slot * 2 * n3 + n3;
+                ba.mom1 = mom_w;
+                ba.mass = bc.mass;
+                ba.zeta = bc.zeta;
+                ba.half = c->half;
+                ba.fc = c->fc;
+                ba.fbar = c->fbar;
+                ba.pos_bar = pos_bar;
+                ba.mom_bar = mom_bar;
+                ba.half_bar = half_bar;
+                ba.fc_bar = fc_bar;
+                ba.p_bar = p_bar;
+                ba.lam = c->lamB;
+                ba.gbar = c->gbar_d;
+                by_storage(c->p.storage, [&](auto st) {
+                    hipLaunchKernelGGL((k_bead_adjoint<decltype(st)::value>), dim3(grid_for(8 * (size_t)nbd, 256)),
+                                       dim3(256), 0, c->stream, ba);
+                });
+                if (bc.nbonds > 0)
+                    hipLaunchKernelGGL(k_bonds_adjoint, dim3(grid_for((size_t)bc.nbonds, 256)), dim3(256), 0, c->stream,
+                                       c->half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd);
+                hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for((size_t)nbd, 256)), dim3(256), 0, c->stream,
+                                   nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar);
+                clear_force();
+            }
             std::swap(c->lamA, c->lamB);
         }
-        LB_LAUNCH_CHECK(c, "adjoint step");
+        if (hipGetLastError() != hipSuccess) rc = fail(c, LB_EDEVICE, "adjoint step");
     }
+    c->block = saved_block;
+    c->nblocks = (int)saved_blocks;
+    if (rc != LB_OK) return rc;
     if (dtype == LB_F64)
         hipLaunchKernelGGL(k_from_f32<double>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
                            static_cast<double *>(dL_dn_0), n19);
@@ -1171,12 +1350,32 @@ int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, do
         hipLaunchKernelGGL(k_from_f32<float>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
                            static_cast<float *>(dL_dn_0), n19);
     LB_LAUNCH_CHECK(c, "backward output");
+    if (coupled) {
+        const size_t n3 = 3 * (size_t)nbd;
+        if (dR_0)
+            LB_TRY(check(c, hipMemcpyAsync(dR_0, pos_bar, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+                         "bead gradient copy"));
+        if (dP_0)
+            LB_TRY(check(c, hipMemcpyAsync(dP_0, mom_bar, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+                         "bead gradient copy"));
+    }
     double h[3] = {0, 0, 0};
     LB_TRY(check(c, hipMemcpyAsync(h, c->gbar_d, sizeof(h), hipMemcpyDeviceToHost, c->stream), "gbar copy"));
     LB_TRY(read_flags(c));
     if (dL_dg)
         for (int k = 0; k < 3; ++k) dL_dg[k] = h[k];
     return LB_OK;
+}
+
+int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3])
+{
+    return backward_impl(c, dL_dn_T, dtype, nullptr, nullptr, dL_dn_0, dL_dg, nullptr, nullptr);
+}
+
+int lb_backward_coupled(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const double *dL_dR_T, const double *dL_dP_T,
+                        void *dL_dn_0, double dL_dg[3], double *dL_dR_0, double *dL_dP_0)
+{
+    return backward_impl(c, dL_dn_T, dtype, dL_dR_T, dL_dP_T, dL_dn_0, dL_dg, dL_dR_0, dL_dP_0);
 }
 
 int lb_vacf(lb_ctx *c, double *out, int64_t *nsamples)

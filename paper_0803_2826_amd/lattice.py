@@ -180,6 +180,8 @@ class Lattice:
     def couple(self, beads: DeviceBeads) -> None:
         b = beads.to_c()
         self._check(self.L.lb_couple(self.ctx, ctypes.byref(b)))
+        if getattr(self, "_taped_beads", None) is not None:
+            self._taped_beads = beads.n
 
     def coupled_step(self, beads: DeviceBeads) -> None:
         """Particle update + spreading, then one LB step (the paper's schedule)."""
@@ -215,6 +217,7 @@ class Lattice:
 
     def tape_begin(self, checkpoint_every: int) -> None:
         self._check(self.L.lb_tape_begin(self.ctx, int(checkpoint_every)))
+        self._taped_beads = 0
 
     def backward(self, dL_dnT: torch.Tensor):
         """dL/dn(t0) and dL/dg for the steps taken since tape_begin."""
@@ -229,6 +232,37 @@ class Lattice:
         dt = LB_F64 if t.dtype == torch.float64 else LB_F32
         self._check(self.L.lb_backward(self.ctx, t.data_ptr(), dt, out.data_ptr(), gbar))
         return out.reshape(t.shape), [gbar[i] for i in range(3)]
+
+    def backward_coupled(self, dL_dnT: torch.Tensor, dL_dRT: torch.Tensor | None = None,
+                         dL_dPT: torch.Tensor | None = None):
+        """(dL/dn(t0), dL/dg, dL/dR(t0), dL/dP(t0)) for the steps taken since
+        tape_begin, coupled steps included; the bead adjoints are float64
+        [n, 3] device tensors (None if no coupled step was taped)."""
+        t = torch.as_tensor(dL_dnT, device=self.device)
+        if t.dtype not in (torch.float64, torch.float32):
+            t = t.to(torch.float64)
+        t = t.contiguous()
+        if t.numel() != Q * self.N:
+            raise ValueError("dL_dnT must have 19*N elements")
+        nb = getattr(self, "_taped_beads", 0)
+        out = torch.empty_like(t)
+        gbar = (ctypes.c_double * 3)()
+        dt = LB_F64 if t.dtype == torch.float64 else LB_F32
+
+        def bead_in(x):
+            if x is None or nb == 0:
+                return None
+            x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
+            if x.numel() != 3 * nb:
+                raise ValueError("bead gradients must have n*3 elements")
+            return x
+        rt, pt = bead_in(dL_dRT), bead_in(dL_dPT)
+        r0 = torch.empty((nb, 3), dtype=torch.float64, device=self.device) if nb else None
+        p0 = torch.empty((nb, 3), dtype=torch.float64, device=self.device) if nb else None
+        ptr = lambda x: x.data_ptr() if x is not None else None
+        self._check(self.L.lb_backward_coupled(self.ctx, t.data_ptr(), dt, ptr(rt), ptr(pt), out.data_ptr(), gbar,
+                                               ptr(r0), ptr(p0)))
+        return out.reshape(t.shape), [gbar[i] for i in range(3)], r0, p0
 
     def save(self, path: str) -> None:
         """Write the state and step counter to a checkpoint file (lb_save)."""

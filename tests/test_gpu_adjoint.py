@@ -121,20 +121,22 @@ def test_autograd_probe_loss_matches_oracle(orc, lat):
 
 def test_backward_error_paths(orc, lat):
     import torch
-    from paper_0803_2826_amd._lib import LB_ESTATE, LB_EUNSUPPORTED, LBError
+    from paper_0803_2826_amd._lib import LB_EINVAL, LB_ESTATE, LB_EUNSUPPORTED, LBError
     dev = lat.Lattice(lat.FluidParams(nx=8, ny=8, nz=8, kT=1e-4))
     dev.init_equilibrium()
     dev.step(2)
     with pytest.raises(LBError) as ei:
         dev.backward(torch.zeros(19 * 512, dtype=torch.float64))
     assert ei.value.code == LB_ESTATE
-    dev.tape_begin(4)
-    beads = lat.DeviceBeads(np.array([[1.5, 2.5, 3.5]]), np.zeros((1, 3)), np.ones(1), np.ones(1))
-    dev.coupled_step(beads)
     with pytest.raises(LBError) as ei:
-        dev.backward(torch.zeros(19 * 512, dtype=torch.float64))
-    assert ei.value.code == LB_EUNSUPPORTED
+        dev.tape_begin(0)
+    assert ei.value.code == LB_EINVAL
     dev.close()
+    B = lat.BatchLattice(lat.FluidParams(nx=2, ny=2, nz=2, kT=1e-4, block=256), [(8, 8, 8)])
+    with pytest.raises(LBError) as ei:
+        B.tape_begin(4)
+    assert ei.value.code == LB_EUNSUPPORTED
+    B.close()
 
 
 @pytest.mark.slow

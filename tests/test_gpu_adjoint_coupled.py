@@ -1,0 +1,264 @@
+"""Differentiation form with beads on the GPU (lb_backward_coupled and the
+coupled autograd Function), against the oracle's FP64 adjoint of whole
+coupled steps, which is itself pinned by central finite differences.
+
+Tolerance: as for the fluid-only adjoint, the GPU computes the fluid forward
+and adjoint in FP32 (~1e-7 relative per step, random-walking over T steps)
+and the particle adjoint in FP64 from FP32 inputs; bound 2e-5 relative to the
+largest entry of each gradient.  The spread force of several beads meets at
+shared nodes through FP32 atomics, so runs differ in the last bits; the
+checkpoint-interval test compares at 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 2e-5
+C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 0], [-1, -1, 0],
+              [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1],
+              [0, 1, -1], [0, -1, 1]], dtype=float)
+
+
+@pytest.fixture(scope="module")
+def lat():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_0803_2826_amd import lattice
+    return lattice
+
+
+def rel_err(got, ref):
+    return np.abs(np.asarray(got) - ref).max() / np.abs(ref).max()
+
+
+def system(orc, lat, rng, dims=(12, 10, 8), chains=2, length=4, **kw):
+    nx, ny, nz = dims
+    from paper_0803_2826_amd.inputs import random_walk_chains
+    po = orc.Params(nx=nx, ny=ny, nz=nz, **kw)
+    pd = lat.FluidParams(nx=nx, ny=ny, nz=nz, kT=po.kT, seed=po.seed, body_force=po.g, gamma_shear=po.gamma_shear,
+                         gamma_bulk=po.gamma_bulk, track_totals=False)
+    pos, mom, bonds = random_walk_chains(chains, length, (nx, ny, nz), seed=int(rng.integers(1 << 30)))
+    mom = rng.normal(scale=0.01, size=mom.shape)
+    nb = pos.shape[0]
+    zeta = np.where(np.arange(nb) % 2 == 0, 0.5, 2.0)
+    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta, bonds.copy(), 0.05, 1.0)
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 0.05, 1.0)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, nz, ny, nx)))
+    return po, pd, n0, ob, db
+
+
+def run_gpu(lat, pd, n0, db, T, K, w, a, b, plain_steps=()):
+    import torch
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n0))
+    n0r = dev.get_populations().cpu().numpy()
+    dev.tape_begin(K)
+    for t in range(T):
+        if t in plain_steps:
+            dev.step(1)
+        else:
+            dev.coupled_step(db)
+    dn0, dg, dR0, dP0 = dev.backward_coupled(torch.from_numpy(w), torch.from_numpy(a), torch.from_numpy(b))
+    out = dn0.cpu().numpy(), np.array(dg), dR0.cpu().numpy(), dP0.cpu().numpy()
+    dev.close()
+    return n0r, out
+
+
+def test_gpu_coupled_adjoint_matches_oracle(orc, lat):
+    rng = np.random.default_rng(0)
+    po, pd, n0, ob, db = system(orc, lat, rng, kT=1e-4, seed=5, g=(1e-4, -5e-5, 2e-5), gamma_shear=0.2,
+                                gamma_bulk=-0.1)
+    T, K = 8, 3
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(ob.pos.shape[0], 3)), rng.normal(size=(ob.pos.shape[0], 3))
+    n0r, (dn0, dg, dR0, dP0) = run_gpu(lat, pd, n0, db, T, K, w, a, b)
+    lam0, gbar, pb0, mb0 = orc.backward_coupled(po, n0r, T, ob, w, a, b)
+    errs = [rel_err(dn0, lam0), rel_err(dg, gbar), rel_err(dR0, pb0), rel_err(dP0, mb0)]
+    print("coupled adjoint rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
+    assert max(errs) <= REL_TOL
+
+
+def oracle_mixed_backward(orc, po, n0, ob, T, plain_steps, w, a, b):
+    """Reverse sweep composed from the oracle's step and particle adjoints
+    for a run whose steps in `plain_steps` have no particle half."""
+    nz, ny, nx = n0.shape[1:]
+    states, beads = [n0.copy()], [ob.copy()]
+    n, bb = n0.copy(), ob.copy()
+    for t in range(T):
+        if t in plain_steps:
+            orc.step(po, n, t)
+        else:
+            orc.coupled_step(po, n, t, bb)
+        states.append(n.copy())
+        beads.append(bb.copy())
+    lam, gbar = w.copy(), np.zeros(3)
+    pb, mb = a.copy(), b.copy()
+    for t in range(T - 1, -1, -1):
+        if t in plain_steps:
+            orc.step_adjoint(po, states[t], lam, t, gbar)
+            continue
+        force = np.zeros((3, nz, ny, nx))
+        orc.couple(po, states[t], t, beads[t].copy(), force)
+        fbar = np.zeros((3, nz, ny, nx))
+        orc.step_adjoint(po, states[t], lam, t, gbar, extra_force=force, extra_bar=fbar)
+        orc.couple_adjoint(po, states[t], t, beads[t], fbar, pb, mb, lam, gbar)
+    return lam, gbar, pb, mb
+
+
+def test_gpu_mixed_tape_matches_oracle(orc, lat):
+    """Coupled and plain steps interleaved (plain steps keep the bead state)."""
+    rng = np.random.default_rng(1)
+    po, pd, n0, ob, db = system(orc, lat, rng, kT=1e-4, seed=9, g=(5e-5, 0.0, -2e-5))
+    T, K, plain = 9, 4, (3, 4, 7)
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(ob.pos.shape[0], 3)), rng.normal(size=(ob.pos.shape[0], 3))
+    n0r, (dn0, dg, dR0, dP0) = run_gpu(lat, pd, n0, db, T, K, w, a, b, plain_steps=plain)
+    lam0, gbar, pb0, mb0 = oracle_mixed_backward(orc, po, n0r, ob, T, plain, w, a, b)
+    errs = [rel_err(dn0, lam0), rel_err(dg, gbar), rel_err(dR0, pb0), rel_err(dP0, mb0)]
+    print("mixed tape rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
+    assert max(errs) <= REL_TOL
+
+
+def test_coupled_checkpoint_interval_invariance(orc, lat):
+    rng = np.random.default_rng(2)
+    po, pd, n0, ob, db0 = system(orc, lat, rng, kT=1e-4, seed=3)
+    T = 7
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(ob.pos.shape[0], 3)), rng.normal(size=(ob.pos.shape[0], 3))
+    outs = []
+    for K in (1, 3, 100):
+        db = lat.DeviceBeads(ob.pos, ob.mom, ob.mass, ob.zeta, ob.bonds, ob.k_bond, ob.r0)
+        outs.append(run_gpu(lat, pd, n0, db, T, K, w, a, b)[1])
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert rel_err(x, y) <= 1e-6
+
+
+def drag_loss_grads(orc, po, nT, posT, momT, mass, zeta, lo, hi):
+    """dL/dn_T, dL/dR_T, dL/dP_T and the direct dL/dg of the loss
+    mean_probe abs(u)^2 + mean_b abs(zeta (P/m - u(R)))^2, from the oracle's
+    fields and stencil (u = (sum n c + g/2)/rho)."""
+    import test_oracle_adjoint as toa
+    lam, gdir = toa.probe_loss_grad(orc, po, nT, lo, hi)
+    rho, u = orc.fields(po, nT)
+    N = po.nx * po.ny * po.nz
+    lam = lam.reshape(19, N).copy()
+    rho, u = rho.reshape(N), u.reshape(3, N)
+    nb = posT.shape[0]
+    dR, dP = np.zeros((nb, 3)), np.zeros((nb, 3))
+    for k in range(nb):
+        node, wgt = orc.stencil(po, posT[k])
+        ub = (wgt[None, :] * u[:, node]).sum(1)
+        e = zeta[k] * (momT[k] / mass[k] - ub)
+        dP[k] = 2.0 / nb * zeta[k] * e / mass[k]
+        dub = -2.0 / nb * zeta[k] * e
+        frac = posT[k] - np.floor(posT[k])
+        for q in range(8):
+            bits = (q & 1, (q >> 1) & 1, (q >> 2) & 1)
+            w1 = [frac[ax] if bits[ax] else 1 - frac[ax] for ax in range(3)]
+            sg = [1.0 if bits[ax] else -1.0 for ax in range(3)]
+            grad_w = np.array([sg[0] * w1[1] * w1[2], w1[0] * sg[1] * w1[2], w1[0] * w1[1] * sg[2]])
+            uq = u[:, node[q]]
+            dR[k] += (dub @ uq) * grad_w
+            duq = wgt[q] * dub
+            lam[:, node[q]] += ((C - uq[None, :]) @ duq) / rho[node[q]]
+            gdir += 0.5 * duq / rho[node[q]]
+    return lam.reshape(nT.shape), gdir, dR, dP
+
+
+def test_autograd_probe_drag_loss_matches_oracle(orc, lat):
+    """The differentiation workload's loss (probe kinetic energy plus bead
+    drag) through LBCoupledRollout, against the oracle's adjoint."""
+    import torch
+    from paper_0803_2826_amd.autograd import coupled_rollout, probe_drag_loss
+    rng = np.random.default_rng(3)
+    L = 12
+    po, pd, n0, ob, db = system(orc, lat, rng, dims=(L, L, L), kT=1e-4, seed=11, g=(2e-4, 0.0, -1e-4))
+    T, lo, hi = 10, 4, 8
+    n0_t = torch.tensor(n0, device="cuda", requires_grad=True)
+    g_t = torch.tensor(po.g, dtype=torch.float64, device="cuda", requires_grad=True)
+    R0 = torch.tensor(ob.pos, device="cuda", requires_grad=True)
+    P0 = torch.tensor(ob.mom, device="cuda", requires_grad=True)
+    nT, RT, PT = coupled_rollout(n0_t, g_t, R0, P0, db, pd, T, checkpoint_every=4)
+    loss = probe_drag_loss(nT, g_t, RT, PT, db.mass, db.zeta, lo, hi)
+    loss.backward()
+    # oracle: forward from the same (FP64) start, loss gradients, coupled adjoint
+    n, bb = n0.copy(), ob.copy()
+    for t in range(T):
+        orc.coupled_step(po, n, t, bb)
+    lamT, gdir, dRT, dPT = drag_loss_grads(orc, po, n, bb.pos, bb.mom, ob.mass, ob.zeta, lo, hi)
+    lam0, gbar, dR0, dP0 = orc.backward_coupled(po, n0, T, ob, lamT, dRT, dPT)
+    errs = [rel_err(n0_t.grad.cpu().numpy(), lam0), rel_err(g_t.grad.cpu().numpy(), gbar + gdir),
+            rel_err(R0.grad.cpu().numpy(), dR0), rel_err(P0.grad.cpu().numpy(), dP0)]
+    print("probe+drag loss gradient rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
+    assert max(errs) <= 1e-4
+
+
+def test_coupled_backward_error_paths(orc, lat):
+    import torch
+    from paper_0803_2826_amd._lib import LB_ESTATE, LB_EUNSUPPORTED, LBError
+    dev = lat.Lattice(lat.FluidParams(nx=8, ny=8, nz=8, kT=1e-4))
+    dev.init_equilibrium()
+    one = lat.DeviceBeads(np.array([[1.5, 2.5, 3.5]]), np.zeros((1, 3)), np.ones(1), np.ones(1))
+    two = lat.DeviceBeads(np.array([[1.5, 2.5, 3.5], [4.2, 4.4, 4.6]]), np.zeros((2, 3)), np.ones(2), np.ones(2))
+    dev.couple(one)
+    with pytest.raises(LBError) as ei:
+        dev.tape_begin(4)
+    assert ei.value.code == LB_ESTATE
+    dev.step(1)
+    dev.tape_begin(4)
+    dev.coupled_step(one)
+    dev.couple(one)
+    with pytest.raises(LBError) as ei:
+        dev.backward_coupled(torch.zeros(19 * 512, dtype=torch.float64))
+    assert ei.value.code == LB_ESTATE
+    dev.step(1)
+    with pytest.raises(LBError) as ei:
+        dev.couple(two)
+    assert ei.value.code == LB_EUNSUPPORTED
+    dn0, dg, dR0, dP0 = dev.backward_coupled(torch.zeros(19 * 512, dtype=torch.float64))
+    assert dR0.shape == (1, 3) and float(dn0.abs().max()) == 0.0
+    dev.close()
+
+
+@pytest.mark.slow
+def test_full_size_coupled_directional_derivative(orc, lat):
+    """The differentiation workload's box: 128^3 with 16 chains x 32 beads,
+    10 coupled steps.  <grad, v> from lb_backward_coupled against a central
+    difference of the FP64 oracle forward (eps = 1e-4), once along a fluid
+    direction and once along a bead direction; the bead positions move by
+    1e-8 along v, so no bead crosses a node plane within the difference
+    (expected crossings ~3e-4 for 512 beads x 3 axes x 10 steps)."""
+    rng = np.random.default_rng(4)
+    L, T = 128, 10
+    po, pd, n0, ob, db = system(orc, lat, rng, dims=(L, L, L), chains=16, length=32, kT=1e-4, seed=1,
+                                g=(1e-5, 0.0, 0.0))
+    w = rng.normal(size=n0.shape)
+    nb = ob.pos.shape[0]
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+    n0r, (dn0, _, dR0, dP0) = run_gpu(lat, pd, n0, db, T, 5, w, a, b)
+    eps = 1e-4
+
+    def fwd(vn, vR, vP):
+        n = n0r + vn
+        bb = ob.copy()
+        bb.pos = ob.pos + vR
+        bb.mom = ob.mom + vP
+        for t in range(T):
+            orc.coupled_step(po, n, t, bb)
+        return (w * n).sum() + (a * bb.pos).sum() + (b * bb.mom).sum()
+
+    vn = rng.normal(size=n0.shape) * 1e-3
+    zn, zb = np.zeros_like(n0r), np.zeros((nb, 3))
+    fd = (fwd(eps * vn, zb, zb) - fwd(-eps * vn, zb, zb)) / (2 * eps)
+    got = (dn0 * vn).sum()
+    print(f"fluid direction: gpu {got:.10e} fd {fd:.10e}")
+    assert got == pytest.approx(fd, rel=1e-4)
+    vR, vP = rng.normal(size=(nb, 3)) * 1e-4, rng.normal(size=(nb, 3)) * 1e-2
+    fd = (fwd(zn, eps * vR, eps * vP) - fwd(zn, -eps * vR, -eps * vP)) / (2 * eps)
+    got = (dR0 * vR).sum() + (dP0 * vP).sum()
+    print(f"bead direction: gpu {got:.10e} fd {fd:.10e}")
+    assert got == pytest.approx(fd, rel=1e-4)

@@ -207,3 +207,33 @@ def test_coupled_backward_matches_finite_differences(orc):
         pm = orc.Params(**{**p.__dict__, "g": tuple(gm)})
         fd = (loss(n0, pp, beads) - loss(n0, pm, beads)) / (2 * eps)
         assert gbar[k] == pytest.approx(fd, rel=1e-6)
+
+
+def test_composed_reverse_sweep_equals_backward_coupled(orc):
+    """The oracle's step and particle adjoints, composed by hand step by step,
+    give the same gradients as orc_backward_coupled (the composition used by
+    the GPU tests of mixed tapes)."""
+    rng = np.random.default_rng(7)
+    p = orc.Params(nx=8, ny=7, nz=6, kT=1e-4, seed=2, g=(1e-4, 0.0, 3e-5))
+    n0 = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 6, 7, 8)))
+    beads = _bead_system(orc, rng)
+    nb = beads.pos.shape[0]
+    T = 3
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+    ref = orc.backward_coupled(p, n0, T, beads, w, a, b)
+    states, bstates = [n0.copy()], [beads.copy()]
+    n, bb = n0.copy(), beads.copy()
+    for t in range(T):
+        orc.coupled_step(p, n, t, bb)
+        states.append(n.copy())
+        bstates.append(bb.copy())
+    lam, gbar, pb, mb = w.copy(), np.zeros(3), a.copy(), b.copy()
+    for t in range(T - 1, -1, -1):
+        force = np.zeros((3, 6, 7, 8))
+        orc.couple(p, states[t], t, bstates[t].copy(), force)
+        fbar = np.zeros((3, 6, 7, 8))
+        orc.step_adjoint(p, states[t], lam, t, gbar, extra_force=force, extra_bar=fbar)
+        orc.couple_adjoint(p, states[t], t, bstates[t], fbar, pb, mb, lam, gbar)
+    for x, y in zip((lam, gbar, pb, mb), ref):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-14 * np.abs(y).max())
