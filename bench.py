@@ -17,7 +17,9 @@ Prints ONE JSON line with, beside the throughput:
                 on the launch stream around each step's launch inside the
                 timed region, against the 8 TB/s HBM peak, and beside it
                 the rate of a plain device copy of one population buffer
-                (the practical ceiling of a streaming kernel);
+                (the practical ceiling of a streaming kernel) and of the
+                step's 19-plane pull pattern alone (the ceiling of its
+                access pattern);
   cpu_baseline  the FP64 oracle on the host cores, timed on a bounded sample
                 of the same workload (a few coupled steps of the full box);
   forms         the other throughputs the metric names: FP32 and BF16-storage
@@ -138,6 +140,43 @@ def copy_ceiling(nbytes: int) -> tuple:
         e1.record(s)
         torch.cuda.synchronize()
         gbs = 2 * nbytes / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+        best = max(best, (gbs, block))
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
+def pull_ceiling(L: int) -> tuple:
+    """(GB/s, threads per block) of the best run of the step's memory pattern
+    alone (bw_pull19: 19 planes pulled from the D3Q19 neighbours, no
+    arithmetic) over an L^3 box, or (None, None) if L is not a power of two."""
+    import ctypes
+
+    import torch
+
+    from paper_0803_2826_amd import build as hip_build
+
+    lg = L.bit_length() - 1
+    if (1 << lg) != L or not 4 <= lg <= 10:
+        return None, None
+    P = ctypes.CDLL(hip_build.PROBE)
+    P.bw_pull19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    N = L ** 3
+    a = torch.zeros(19 * N, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    best = (0.0, 0)
+    for block in (256, 512, 1024):
+        launch = lambda: P.bw_pull19(a.data_ptr(), b.data_ptr(), lg, block, ctypes.c_void_p(s.cuda_stream))
+        if launch() != 0:
+            raise RuntimeError("bw_pull19 failed")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(20):
+            launch()
+        e1.record(s)
+        torch.cuda.synchronize()
+        gbs = 2 * 19 * 4 * N / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
         best = max(best, (gbs, block))
     del a, b
     torch.cuda.empty_cache()
@@ -275,6 +314,12 @@ def main() -> int:
                                 "kernel": f"streaming copy (16 B per thread, {cblock} threads per block) of one "
                                           f"{19 * 4 * N / 1e9:.2f} GB population buffer",
                                 "frac_of_copy": round(achieved / ceiling, 4)}
+    pull, pblock = pull_ceiling(L)
+    if pull:
+        roofline["pull_pattern_ceiling"] = {"achieved": round(pull, 1), "unit": "GB/s",
+                                            "kernel": f"the step's 19-plane pull pattern without arithmetic "
+                                                      f"({pblock} threads per block)",
+                                            "frac_of_pattern": round(achieved / pull, 4)}
 
     forms = None if args.no_forms else run_forms(L)
 

@@ -18,6 +18,23 @@ Q = 19
 _STORAGE = {"f32": LB_F32, "bf16": LB_BF16, "f16": LB_F16, LB_F32: LB_F32, LB_BF16: LB_BF16, LB_F16: LB_F16}
 
 
+def two_rate(gamma_e: float, magic: float = 3.0 / 16.0) -> dict:
+    """Two-rate relaxation (Sec. "D3Q19 model II": a single even rate for
+    bulk, shear and the even kinetic modes, gamma_v = gamma_s = gamma_4a =
+    gamma_4b = gamma_e, and a single odd rate gamma_3a = gamma_3b = gamma_o).
+    gamma_o follows from the product of the two relaxation times,
+    Lambda = (1/(1 - gamma_e) - 1/2)(1/(1 - gamma_o) - 1/2); Lambda = 3/16
+    puts a stationary bounce-back wall exactly half way along the link for
+    plane Poiseuille flow.  Returns keyword arguments for FluidParams."""
+    if not abs(gamma_e) < 1.0 or not magic > 0.0:
+        raise ValueError("two_rate needs |gamma_e| < 1 and magic > 0")
+    te = 1.0 / (1.0 - gamma_e)
+    to = 0.5 + magic / (te - 0.5)
+    go = 1.0 - 1.0 / to
+    return dict(gamma_shear=gamma_e, gamma_bulk=gamma_e, gamma_4a=gamma_e, gamma_4b=gamma_e, gamma_3a=go,
+                gamma_3b=go)
+
+
 @dataclass
 class FluidParams:
     """Fluid parameters (lattice units).  nu = (1/6)(1+gamma_shear)/(1-gamma_shear)."""

@@ -163,3 +163,127 @@ def test_transverse_current_autocorrelation(orc):
     assert c1 / c0 == pytest.approx(lam, abs=0.02)
     N = L ** 3
     assert c0 / 1199 / (N * kT) == pytest.approx(1.0, rel=0.2)
+
+
+# ---------------------------------------------------------------------------
+# Linear stability operator (eq. lco_eigen, eq. lco_update): the 19 x 19 map
+# of a Fourier mode exp(i k.r) of population deviations through one step,
+# A(k) = S(k) E^-1 diag(gamma) E with S = diag(exp(-i k.c_i)) (streaming) and
+# E the Table 1 basis (equilibrium moments of order >= 2 vanish at linear
+# order around rest).  Built from the golden Table 1 fixture and numpy's
+# eigensolver only.
+# ---------------------------------------------------------------------------
+
+def _table1_basis(c):
+    from test_oracle_lattice import load_table1
+    rows = load_table1()
+    E = np.zeros((19, 19))
+    w = np.zeros(19)
+    for k, poly, wk in rows:
+        for i in range(19):
+            cx, cy, cz = (float(v) for v in c[i])
+            E[k, i] = eval(poly, {}, {"cx": cx, "cy": cy, "cz": cz, "c2": cx * cx + cy * cy + cz * cz})
+        w[k] = float(wk)
+    return E, w
+
+
+def _mode_gammas(gs, gv, g3a, g3b, g4a, g4b):
+    return np.array([1, 1, 1, 1, gv] + [gs] * 5 + [g3a] * 3 + [g3b] * 3 + [g4a] + [g4b] * 2, dtype=float)
+
+
+def linear_operator(c, gam, kvec):
+    E, w = _table1_basis(c)
+    a = np.array([{0: 1 / 3, 1: 1 / 18, 2: 1 / 36}[int((ci ** 2).sum())] for ci in c])
+    Einv = (a[:, None] * E.T) / w[None, :]         # back-transformation n_i = a_i sum_k e_ki m_k / w_k
+    Cl = Einv @ np.diag(gam) @ E
+    S = np.diag(np.exp(-1j * (c.astype(float) @ kvec)))
+    return S @ Cl
+
+
+def two_rate(gamma_e, magic=3.0 / 16.0):
+    """Odd kinetic eigenvalue from the even one for a given
+    Lambda = (1/(1 - gamma_e) - 1/2)(1/(1 - gamma_o) - 1/2)."""
+    te = 1.0 / (1.0 - gamma_e)
+    to = 0.5 + magic / (te - 0.5)
+    return 1.0 - 1.0 / to
+
+
+RELAX_SETS = {
+    "gamma0": (0.0, 0.0, 0.0, 0.0, 0.0, 0.0),
+    "tau0.8": (-0.25, -0.25, 0.0, 0.0, 0.0, 0.0),
+    "general": (0.3, -0.2, 0.1, -0.4, 0.5, 0.2),
+    "two_rate_magic": (0.3, 0.3, two_rate(0.3), two_rate(0.3), 0.3, 0.3),
+}
+
+
+def test_linear_operator_reproduces_closed_form_shear_rate(orc):
+    """At gamma = 0 the shear eigenvalue is 1 - (2/3) sin^2(k/2), and for small
+    k at general gamma_s it approaches exp(-nu k^2), nu = (1/6)(1+g)/(1-g)
+    (eq. shearviscosity with rho c_s^2 h / 2 and rho = 1)."""
+    c, a, e, w = orc.tables()
+    for L in (16, 32):
+        k = 2 * np.pi / L
+        lam = np.linalg.eigvals(linear_operator(c, _mode_gammas(*RELAX_SETS["gamma0"]), np.array([0, 0, k])))
+        assert np.min(np.abs(lam - (1 - (2 / 3) * np.sin(k / 2) ** 2))) < 1e-14
+    gs = 0.3
+    k = 2 * np.pi / 512
+    lam = np.linalg.eigvals(linear_operator(c, _mode_gammas(gs, -0.2, 0.1, -0.4, 0.5, 0.2), np.array([0, 0, k])))
+    nu = (1 / 6) * (1 + gs) / (1 - gs)
+    # the hydrodynamic limit holds to O(k^4) = 2.3e-8 at k = 2 pi / 512
+    assert np.min(np.abs(lam - np.exp(-nu * k * k))) < 1e-8
+
+
+@pytest.mark.parametrize("name", list(RELAX_SETS))
+def test_shear_eigenmode_evolves_by_its_eigenvalue(orc, name):
+    """T5: a shear eigenmode of A(k), k = 2 pi / L along z, seeded at amplitude
+    1e-8 into the oracle (kT = 0), is multiplied by its eigenvalue every
+    step: after T steps the state equals lambda^T times the mode to 1e-7
+    relative (the collision's quadratic terms are O(amplitude))."""
+    gs, gv, g3a, g3b, g4a, g4b = RELAX_SETS[name]
+    p = orc.Params(nx=4, ny=4, nz=16, gamma_shear=gs, gamma_bulk=gv, gamma_3a=g3a, gamma_3b=g3b, gamma_4a=g4a,
+                   gamma_4b=g4b)
+    c, a, e, w = orc.tables()
+    k = 2 * np.pi / p.nz
+    lam, V = np.linalg.eig(linear_operator(c, _mode_gammas(gs, gv, g3a, g3b, g4a, g4b), np.array([0, 0, k])))
+    jx = c[:, 0].astype(float) @ V                  # x-momentum of each eigenvector
+    m = int(np.argmax(np.abs(jx) * (np.abs(lam) > 0.5)))
+    v = V[:, m] / jx[m]                             # normalised to unit j_x
+    assert abs(lam[m].imag) < 1e-12
+    eps, T = 1e-8, 12
+    z = np.arange(p.nz)
+    mode = np.real(v[:, None] * np.exp(1j * k * z)[None, :])      # [19, nz]
+    n = (a[:, None, None, None] + eps * mode[:, :, None, None] * np.ones((1, 1, p.ny, p.nx)))
+    n = np.ascontiguousarray(n)
+    orc.run(p, n, T)
+    expect = a[:, None, None, None] + eps * np.real(lam[m] ** T * v[:, None] * np.exp(1j * k * z)[None, :])[:, :, None,
+                                                                                                              None]
+    err = np.abs(n - expect).max() / eps
+    print(name, "eigenvalue", lam[m].real, "rel err", err)
+    assert err < 1e-7
+
+
+@pytest.mark.parametrize("name", list(RELAX_SETS))
+def test_linear_dynamics_equal_operator_power(orc, name):
+    """The whole linearised step: a random complex population perturbation on
+    an oblique wave vector k = 2 pi (1/nx, 2/ny, 1/nz), seeded at amplitude
+    1e-8, after T oracle steps equals A(k)^T applied to it (every eigenvalue
+    group and direction enters: bulk, shear, both odd and both even kinetic
+    groups)."""
+    gs, gv, g3a, g3b, g4a, g4b = RELAX_SETS[name]
+    p = orc.Params(nx=6, ny=8, nz=10, gamma_shear=gs, gamma_bulk=gv, gamma_3a=g3a, gamma_3b=g3b, gamma_4a=g4a,
+                   gamma_4b=g4b)
+    c, a, e, w = orc.tables()
+    rng = np.random.default_rng(3)
+    kvec = 2 * np.pi * np.array([1 / p.nx, 2 / p.ny, 1 / p.nz])
+    A = linear_operator(c, _mode_gammas(gs, gv, g3a, g3b, g4a, g4b), kvec)
+    v = rng.normal(size=19) + 1j * rng.normal(size=19)
+    z, y, x = np.meshgrid(np.arange(p.nz), np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    phase = np.exp(1j * (kvec[0] * x + kvec[1] * y + kvec[2] * z))
+    eps, T = 1e-8, 9
+    n = np.ascontiguousarray(a[:, None, None, None] + eps * np.real(v[:, None, None, None] * phase[None]))
+    orc.run(p, n, T)
+    vT = np.linalg.matrix_power(A, T) @ v
+    expect = a[:, None, None, None] + eps * np.real(vT[:, None, None, None] * phase[None])
+    err = np.abs(n - expect).max() / (eps * np.abs(v).max())
+    print(name, "rel err", err)
+    assert err < 1e-7
