@@ -54,7 +54,7 @@ class OrcParams(ctypes.Structure):
         ("g", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64),
         ("box", ctypes.c_uint32),
-        ("pad", ctypes.c_uint32),
+        ("walls", ctypes.c_uint32),
     ]
 
 
@@ -76,6 +76,7 @@ class Params:
     seed: int = 0
     noise_rho0: bool = False
     box: int = 0
+    walls: bool = False   # stationary walls at z = -1/2 and z = nz - 1/2
 
     @property
     def N(self) -> int:
@@ -94,6 +95,7 @@ class Params:
             p.g[a] = float(self.g[a])
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.box = int(self.box)
+        p.walls = 1 if self.walls else 0
         return p
 
 

@@ -235,8 +235,18 @@ typedef struct {
     double g[3];          /* uniform body-force density */
     uint64_t seed;
     uint32_t box;
-    uint32_t pad;
+    uint32_t walls;       /* 1: stationary walls at z = -1/2 and z = nz - 1/2 */
 } orc_params;
+
+/* Opposite direction of velocity i (the table keeps opposites adjacent). */
+static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+/* Whether the link from site z along velocity i crosses a stationary wall. */
+static int crosses_wall(const orc_params *p, int z, int i)
+{
+    const int zz = z + CV[i][2];
+    return p->walls && (zz < 0 || zz >= p->nz);
+}
 
 /* Eigenvalue gamma_k of each mode (Sec. "D3Q19 model II"): bulk mode 4,
  * shear modes 5-9, kinetic groups 10-12, 13-15, 16, 17-18.  Conserved
@@ -397,7 +407,10 @@ void orc_init_equilibrium(const orc_params *p, const double *rho, const double *
 
 /* One lattice-Boltzmann time step, eq. LBE: collide at every site with force
  * density g + extra(r) (extra may be NULL, layout [3][N]), then stream
- * n_i(r + c_i, t+1) = n*_i(r, t) with periodic wrap.  `step` keys the noise.
+ * n_i(r + c_i, t+1) = n*_i(r, t) with periodic wrap.  With walls, a
+ * population whose link crosses a wall returns to its own site reversed,
+ * n_{-i}(r, t+1) = n*_i(r, t) (eq. MBB with a wall at rest, u_b = 0, the wall
+ * half way along the link).  `step` keys the noise.
  * `work` is caller scratch of 19*N doubles.  Parity pinned by the shear-wave,
  * Kolmogorov, conservation and noise-variance tests. */
 void orc_step(const orc_params *p, double *n, double *work, const double *extra, uint32_t step)
@@ -418,6 +431,10 @@ void orc_step(const orc_params *p, double *n, double *work, const double *extra,
             for (int x = 0; x < p->nx; ++x) {
                 const int64_t s = site_index(p, x, y, z);
                 for (int i = 0; i < Q; ++i) {
+                    if (crosses_wall(p, z, i)) {
+                        n[opposite(i) * N + s] = work[i * N + s];
+                        continue;
+                    }
                     const int64_t d = site_index(p, wrap(x + CV[i][0], p->nx), wrap(y + CV[i][1], p->ny),
                                                  wrap(z + CV[i][2], p->nz));
                     n[i * N + d] = work[i * N + s];
@@ -732,7 +749,8 @@ void orc_collide_site_adjoint(const orc_params *p, const double n[Q], const doub
 /* Adjoint of one orc_step.  n: pre-collision state at step `step`;
  * lam: on entry the adjoint of the state after the step (pre-collision at
  * step+1), on exit the adjoint of n.  Streaming n_i(r + c_i) = n*_i(r) is a
- * permutation, so the adjoint of n* at r is lam_i(r + c_i).  extra: the
+ * permutation, so the adjoint of n* at r is lam_i(r + c_i), or lam_{-i}(r)
+ * where the link crosses a wall.  extra: the
  * extra force field of the step or NULL; its adjoint is accumulated into
  * extra_bar ([3][N]) when not NULL.  gbar accumulates the adjoint of the
  * uniform body force.  work: 19*N doubles of caller scratch. */
@@ -752,6 +770,10 @@ void orc_step_adjoint(const orc_params *p, const double *n, double *lam, double 
                     double ns[Q], nbs[Q], nb[Q], F[3], Fb[3] = {0.0, 0.0, 0.0}, gn[16];
                     for (int i = 0; i < Q; ++i) {
                         ns[i] = n[i * N + s];
+                        if (crosses_wall(p, z, i)) {
+                            nbs[i] = lam[opposite(i) * N + s];
+                            continue;
+                        }
                         const int64_t d = site_index(p, wrap(x + CV[i][0], p->nx), wrap(y + CV[i][1], p->ny),
                                                      wrap(z + CV[i][2], p->nz));
                         nbs[i] = lam[i * N + d];
