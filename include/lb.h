@@ -98,6 +98,15 @@ typedef enum { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_rounding;
  *   batch threads per block x blocks per step (see lb_launch_config).  The
  *   launch configuration never changes the results.
  * rounding: see lb_rounding; LB_ROUND_STOCHASTIC needs 16-bit storage.
+ * walls: 0 = periodic in every direction; 1 = a plane channel: stationary
+ *   solid walls half way along the links at z = -1/2 and z = nz - 1/2
+ *   (Sec. "Boundary conditions", eq. MBB with the wall at rest): a population
+ *   whose link crosses a wall returns reversed to the site it left,
+ *   n_{-i}(r, t+1) = n*_i(r, t).  x and y stay periodic.  Mass is conserved,
+ *   momentum is exchanged with the walls.  Every entry point (state access,
+ *   moments, coupling, the adjoint) follows the same rule.  Beads must keep
+ *   0 <= z < nz - 1 so that their 8-node stencil stays inside the channel.
+ *   Not available for a batch (LB_EUNSUPPORTED).
  * track_totals: 1 = the step kernel also accumulates FP64 totals of mass and
  *   momentum every step (read with lb_totals); 0 = totals are computed on
  *   demand by lb_totals with a separate pass. */
@@ -117,7 +126,7 @@ typedef struct {
     int32_t vacf_lags;     /* batch only: lags R of the on-device ensemble VACF (0 = off, <= 1024) */
     int32_t graph_steps;   /* batch only: steps per captured HIP graph (even, 0 = no graph) */
     int32_t rounding;      /* lb_rounding of the step kernels' stores (16-bit storage) */
-    int32_t reserved;      /* must be 0 */
+    int32_t walls;         /* 1: stationary walls at z = -1/2 and z = nz - 1/2 (single box only) */
 } lb_params;
 
 /* Point particles with harmonic bonds (Sec. "Force coupling").

@@ -56,7 +56,7 @@ class lb_params(ctypes.Structure):
         ("vacf_lags", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
         ("rounding", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("walls", ctypes.c_int32),
     ]
 
 

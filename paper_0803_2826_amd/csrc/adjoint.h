@@ -39,10 +39,8 @@ struct AdjArgs {
     float *fbar;            // [3][N]
 };
 
-// Opposite direction of population i (pairs are adjacent: 1<->2, 3<->4, ...).
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
-template <int ST, bool THERMAL, bool FORCE>
+template <int ST, bool THERMAL, bool FORCE, bool WALLS>
 __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
 {
     using S = Storage<ST>;
@@ -58,7 +56,7 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         // forward hydrodynamic fields of n(r, t)
         float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = S::ld(ld_plane(st + (size_t)i * N, pull_src(s, o, i)), 0.f);
+        for (int i = 0; i < Q; ++i) d[i] = S::ld(st[pull_index<WALLS>(s, o, i, z, a.geo)], 0.f);
         float m0 = d[0], jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -84,11 +82,13 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         jz += 0.5f * F[2];
         const float ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
 
-        // nbar*_i(r) = lambda_i(r + c_i): r + c_i is the pull source of the opposite direction
+        // nbar*_i(r) = lambda_i(r + c_i): r + c_i is the pull source of the opposite direction;
+        // across a wall the reader of n*_i(r) is population opp(i) at r itself
         float q[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float lb = ld_plane(a.lam_in + (size_t)i * N, pull_src(s, o, opp(i)));
+            const float lb = push_crosses<WALLS>(a.geo, z, i) ? a.lam_in[(size_t)opp(i) * N + s]
+                                                        : ld_plane(a.lam_in + (size_t)i * N, pull_src(s, o, opp(i)));
             q[i] = lb * (i == 0 ? (1.f / 3.f) : (i <= 6 ? (1.f / 18.f) : (1.f / 36.f)));
         }
         // msb_k = (1/w_k) sum_i e_ki (a_i nbar*_i): the moment map applied to q

@@ -39,7 +39,10 @@ __global__ void k_init_equilibrium(void *buf, Geom g, double rho0, const double 
     site_xyz(s, g, x, y, z);
     T *b = static_cast<T *>(buf);
     for (int i = 0; i < Q; ++i) {
-        const uint32_t r = push_dst(x, y, z, g, i);
+        // the reader of A_i(s): population i at s + c_i, or opp(i) at s across a wall
+        const bool wall = push_crosses(g, z, i);
+        const int j = wall ? opp(i) : i;
+        const uint32_t r = wall ? s : push_dst(x, y, z, g, i);
         const double rr = rho ? rho[r] : rho0;
         double ux = 0.0, uy = 0.0, uz = 0.0;
         if (u) {
@@ -47,15 +50,16 @@ __global__ void k_init_equilibrium(void *buf, Geom g, double rho0, const double 
             uy = u[(size_t)g.N + r];
             uz = u[2 * (size_t)g.N + r];
         }
-        const double uc = ux * kCX[i] + uy * kCY[i] + uz * kCZ[i];
+        const double uc = ux * kCX[j] + uy * kCY[j] + uz * kCZ[j];
         const double usq = ux * ux + uy * uy + uz * uz;
-        const double a = weight_of(i);
+        const double a = weight_of(j);
         const double neq = a * rr * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * usq);
         b[(size_t)i * g.N + s] = S::st((float)(neq - a * rho0), 0.f);
     }
 }
 
-// Set: A_i(r) = src_i(r + c_i); src is F64 or F32, shifted or not.
+// Set: A_i(r) = src_i(r + c_i) (src_opp(i)(r) across a wall); src is F64 or
+// F32, shifted or not.
 template <int ST, typename TIn>
 __global__ void k_set_pops(void *buf, Geom g, double rho0, const TIn *__restrict__ src, int shifted)
 {
@@ -67,14 +71,16 @@ __global__ void k_set_pops(void *buf, Geom g, double rho0, const TIn *__restrict
     site_xyz(s, g, x, y, z);
     T *b = static_cast<T *>(buf);
     for (int i = 0; i < Q; ++i) {
-        const uint32_t r = push_dst(x, y, z, g, i);
-        double v = (double)src[(size_t)i * g.N + r];
-        if (!shifted) v -= weight_of(i) * rho0;
+        const bool wall = push_crosses(g, z, i);
+        const int j = wall ? opp(i) : i;
+        const uint32_t r = wall ? s : push_dst(x, y, z, g, i);
+        double v = (double)src[(size_t)j * g.N + r];
+        if (!shifted) v -= weight_of(j) * rho0;
         b[(size_t)i * g.N + s] = S::st((float)v, 0.f);
     }
 }
 
-// Get: dst_i(r) = A_i(r - c_i).
+// Get: dst_i(r) = A_i(r - c_i) (A_opp(i)(r) across a wall).
 template <int ST, typename TOut>
 __global__ void k_get_pops(const void *buf, Geom g, double rho0, TOut *__restrict__ dst, int shifted)
 {
@@ -86,7 +92,7 @@ __global__ void k_get_pops(const void *buf, Geom g, double rho0, TOut *__restric
     const PullOffsets o = pull_offsets(s, g, x, y, z);
     const T *b = static_cast<const T *>(buf);
     for (int i = 0; i < Q; ++i) {
-        double v = (double)S::ld(b[(size_t)i * g.N + pull_src(s, o, i)], 0.f);
+        double v = (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
         if (!shifted) v += weight_of(i) * rho0;
         dst[(size_t)i * g.N + s] = (TOut)v;
     }
@@ -106,7 +112,7 @@ __global__ void k_moments(const void *buf, Geom g, double rho0, double gx, doubl
     const T *b = static_cast<const T *>(buf);
     double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int i = 0; i < Q; ++i) {
-        const double v = (double)S::ld(b[(size_t)i * g.N + pull_src(s, o, i)], 0.f);
+        const double v = (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
         m += v;
         jx += v * kCX[i];
         jy += v * kCY[i];
@@ -208,7 +214,7 @@ __global__ void __launch_bounds__(256) k_mode_stats(const void *buf, Geom g, dou
         uint32_t x, y, z;
         const PullOffsets o = pull_offsets(s, g, x, y, z);
         double n[Q];
-        for (int i = 0; i < Q; ++i) n[i] = (double)S::ld(b[(size_t)i * g.N + pull_src(s, o, i)], 0.f);
+        for (int i = 0; i < Q; ++i) n[i] = (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
         for (int k = 0; k < Q; ++k) {
             double m = (k == 0) ? rho0 : 0.0;
             for (int i = 0; i < Q; ++i) m += basis_k(k, kCX[i], kCY[i], kCZ[i]) * n[i];

@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
         double m = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double v = (double)S::ld(pop[(size_t)i * g.N + pull_src(node, o, i)], 0.f);
+            const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
             m += v;
             j[0] += v * kCX[i];
             j[1] += v * kCY[i];

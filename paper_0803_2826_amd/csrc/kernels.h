@@ -118,6 +118,7 @@ __device__ __forceinline__ uint32_t rounding_field(const Philox4 &w, int i)
 struct Geom {
     uint32_t nx, ny, nz, N, nxny;
     FastDiv div_nx, div_ny;
+    uint32_t walls;  // 1: stationary walls at z = -1/2 and z = nz - 1/2
 };
 
 // Neighbour offsets of site s: off[c+1] for c = -1, 0, +1 along each axis is
@@ -166,6 +167,40 @@ __device__ __forceinline__ uint32_t pull_src(uint32_t s, const PullOffsets &o, i
     case 17: return s + o.oy_m + o.oz_p;
     default: return s + o.oy_p + o.oz_m;
     }
+}
+
+// Opposite direction of population i (pairs are adjacent: 1<->2, 3<->4, ...).
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// Stationary walls half way along the links at z = -1/2 and z = nz - 1/2
+// (eq. MBB with the wall at rest, u_b = 0): a population whose link crosses a
+// wall comes back reversed to the site it left.
+//   pull_crosses: the pull source r - c_i of population i at layer z lies
+//                 beyond a wall, so n_i(r, t+1) = A_{opp(i)}(r);
+//   push_crosses: the link r -> r + c_i crosses a wall, so the stored A_i(r)
+//                 is read back as n_{opp(i)}(r).
+// WALLS = false compiles the wall test away (kernels instantiated for the
+// periodic box); the default checks the geometry's flag at run time.
+template <bool WALLS = true>
+__device__ __forceinline__ bool pull_crosses(const Geom &g, uint32_t z, int i)
+{
+    if constexpr (!WALLS) return false;
+    return g.walls && ((kCZ[i] > 0 && z == 0u) || (kCZ[i] < 0 && z + 1u == g.nz));
+}
+template <bool WALLS = true>
+__device__ __forceinline__ bool push_crosses(const Geom &g, uint32_t z, int i)
+{
+    if constexpr (!WALLS) return false;
+    return g.walls && ((kCZ[i] < 0 && z == 0u) || (kCZ[i] > 0 && z + 1u == g.nz));
+}
+
+// Flat index (plane * N + site) of the stored value that population i of
+// site s (layer z) pulls.
+template <bool WALLS = true>
+__device__ __forceinline__ size_t pull_index(uint32_t s, const PullOffsets &o, int i, uint32_t z, const Geom &g)
+{
+    if (pull_crosses<WALLS>(g, z, i)) return (size_t)opp(i) * g.N + s;
+    return (size_t)i * g.N + pull_src(s, o, i);
 }
 
 // Load element idx of population plane `plane` (byte offset arithmetic kept
@@ -306,7 +341,7 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
 
 // One site of the fused step: gather with pull streaming, collide, store,
 // optionally accumulate the block's totals.
-template <int ST, bool THERMAL, bool TOTALS, bool FORCE>
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS>
 __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 {
     using S = Storage<ST>;
@@ -322,6 +357,14 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         float d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = S::ld(ld_plane(static_cast<const T *>(a.srcp[i]), pull_src(s, o, i)), 0.f);
+        if constexpr (WALLS) {
+            if (z == 0u || z + 1u == a.geo.nz) {
+                // wall layers: the populations coming off a wall are the reversed ones of this site
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (pull_crosses(a.geo, z, i)) d[i] = S::ld(ld_plane(static_cast<const T *>(a.srcp[opp(i)]), s), 0.f);
+            }
+        }
         const mass_acc_t<ST> m_in = site_mass<ST>(d);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         if (FORCE) {
@@ -346,10 +389,10 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 // makes it keep 16-20 bytes per lane in scratch memory, whose traffic (about
 // 16 B per site, 10 % of the kernel's own) costs more than the extra wave
 // gains.
-template <int ST, bool THERMAL, bool TOTALS, bool FORCE>
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS>
 __global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
 {
-    stream_collide_site<ST, THERMAL, TOTALS, FORCE>(a);
+    stream_collide_site<ST, THERMAL, TOTALS, FORCE, WALLS>(a);
 }
 
 }  // namespace lbmi

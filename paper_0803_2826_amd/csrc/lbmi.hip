@@ -180,7 +180,7 @@ int validate(const lb_params *p, std::string &msg)
         msg = "stochastic rounding applies to 16-bit storage only";
         return LB_EINVAL;
     }
-    if (p->reserved != 0) { msg = "reserved must be 0"; return LB_EINVAL; }
+    if (p->walls != 0 && p->walls != 1) { msg = "walls must be 0 or 1"; return LB_EINVAL; }
     if (p->block != 0 && p->block != -1 && (p->block < 64 || p->block > 1024 || (p->block % 64) != 0)) {
         msg = "block must be 0, -1 or a multiple of 64 in [64, 1024]";
         return LB_EINVAL;
@@ -220,7 +220,10 @@ void fill_collide_const(lb_ctx *c)
 template <int ST, bool TH, bool TOT, bool FRC>
 void launch_step_t(lb_ctx *c, const StepArgs &a)
 {
-    hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
+    if (c->geo.walls)
+        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, true>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, false>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
 }
 
 template <int ST, bool TH, bool TOT>
@@ -696,6 +699,7 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     c->geo.N = nx * ny * nz;
     c->geo.div_nx = make_fastdiv(nx);
     c->geo.div_ny = make_fastdiv(ny);
+    c->geo.walls = (uint32_t)params->walls;
     c->elem = storage_bytes(params->storage);
     c->block = params->block > 0 ? params->block : 256;
     c->tuned = true;
@@ -733,6 +737,7 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
     const int v = validate(&p, msg);
     if (v != LB_OK) return fail(nullptr, v, msg);
     if (p.graph_steps < 0 || (p.graph_steps & 1)) return fail(nullptr, LB_EINVAL, "graph_steps must be even and >= 0");
+    if (p.walls) return fail(nullptr, LB_EUNSUPPORTED, "walls are available for a single box only");
     if (p.vacf_lags < 0 || p.vacf_lags > 1024) return fail(nullptr, LB_EINVAL, "vacf_lags must be in [0, 1024]");
     lb_ctx *c = new lb_ctx();
     c->p = p;
@@ -1292,12 +1297,21 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             if (slot >= 0) rebuild_force(slot, pop, step);
             by_storage(c->p.storage, [&](auto st) {
                 constexpr int ST = decltype(st)::value;
+                auto go = [&](auto th, auto frc) {
+                    constexpr bool TH = decltype(th)::value, FRC = decltype(frc)::value;
+                    if (c->geo.walls)
+                        hipLaunchKernelGGL((k_adjoint_step<ST, TH, FRC, true>), dim3(nb), dim3(256), 0, c->stream, aa);
+                    else
+                        hipLaunchKernelGGL((k_adjoint_step<ST, TH, FRC, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+                };
+                using T_ = std::true_type;
+                using F_ = std::false_type;
                 if (slot >= 0) {
-                    if (c->thermal) hipLaunchKernelGGL((k_adjoint_step<ST, true, true>), dim3(nb), dim3(256), 0, c->stream, aa);
-                    else hipLaunchKernelGGL((k_adjoint_step<ST, false, true>), dim3(nb), dim3(256), 0, c->stream, aa);
+                    if (c->thermal) go(T_{}, T_{});
+                    else go(F_{}, T_{});
                 } else {
-                    if (c->thermal) hipLaunchKernelGGL((k_adjoint_step<ST, true, false>), dim3(nb), dim3(256), 0, c->stream, aa);
-                    else hipLaunchKernelGGL((k_adjoint_step<ST, false, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+                    if (c->thermal) go(T_{}, F_{});
+                    else go(F_{}, F_{});
                 }
             });
             hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3,

@@ -59,6 +59,7 @@ class FluidParams:
     vacf_lags: int = 0
     graph_steps: int = 0
     rounding: str = "nearest"   # "nearest" or "stochastic" (16-bit storage)
+    walls: bool = False         # stationary walls at z = -1/2 and z = nz - 1/2
 
     @property
     def N(self) -> int:
@@ -82,6 +83,7 @@ class FluidParams:
         p.vacf_lags = int(self.vacf_lags)
         p.graph_steps = int(self.graph_steps)
         p.rounding = {"nearest": _lib.LB_ROUND_NEAREST, "stochastic": _lib.LB_ROUND_STOCHASTIC}[self.rounding]
+        p.walls = 1 if self.walls else 0
         return p
 
 
