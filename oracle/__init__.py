@@ -58,6 +58,17 @@ class OrcParams(ctypes.Structure):
     ]
 
 
+
+class OrcBeadset(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("nbonds", ctypes.c_int32),
+        ("mass", ctypes.POINTER(ctypes.c_double)), ("zeta", ctypes.POINTER(ctypes.c_double)),
+        ("bonds", ctypes.POINTER(ctypes.c_int32)),
+        ("kbond", ctypes.c_double), ("r0", ctypes.c_double),
+        ("stencil", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("fext", ctypes.POINTER(ctypes.c_double)),
+    ]
+
 @dataclass
 class Params:
     """Fluid parameters in lattice units (b = h = 1)."""
@@ -127,17 +138,18 @@ def lib():
         L.orc_totals.argtypes = [pp, dp, dp]
         L.orc_mode_field.argtypes = [pp, dp, dp]
         L.orc_stencil.argtypes = [pp, dp, lp, dp]
-        L.orc_couple.argtypes = [pp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
-                                 ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double, dp]
-        L.orc_coupled_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
-                                       ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double]
+        L.orc_couple.argtypes = [pp, dp, ctypes.c_uint32, ctypes.POINTER(OrcBeadset), dp, dp, dp]
+        L.orc_coupled_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32, ctypes.POINTER(OrcBeadset), dp, dp]
+        L.orc_stencil_w.argtypes = [pp, dp, ctypes.c_int32, lp, dp, dp]
+        L.orc_stencil_w.restype = ctypes.c_int
+        L.orc_phi.argtypes = [ctypes.c_int32, ctypes.c_double, dp]
         L.orc_collide_site_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         L.orc_step_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_uint32, dp]
         L.orc_backward.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, dp, dp]
-        L.orc_couple_adjoint.argtypes = [pp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp, ctypes.c_int32,
-                                         ip, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp, dp]
-        L.orc_backward_coupled.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, dp, dp, dp, dp,
-                                           ctypes.c_int32, ip, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+        L.orc_couple_adjoint.argtypes = [pp, dp, ctypes.c_uint32, ctypes.POINTER(OrcBeadset), dp, dp, dp, dp, dp, dp,
+                                         dp]
+        L.orc_backward_coupled.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(OrcBeadset), dp, dp,
+                                           dp, dp, dp, dp]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals",
@@ -145,7 +157,7 @@ def lib():
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
                      "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step",
                      "orc_collide_site_adjoint", "orc_step_adjoint", "orc_backward", "orc_couple_adjoint",
-                     "orc_backward_coupled"):
+                     "orc_backward_coupled", "orc_phi"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -302,21 +314,38 @@ class Beads:
     bonds: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
     k_bond: float = 0.0
     r0: float = 1.0
+    stencil: int = 2                 # points per axis of the interpolation kernel: 2, 3 or 4
+    fext: np.ndarray | None = None   # [nb, 3] external force per bead
 
     def copy(self) -> "Beads":
         return Beads(self.pos.copy(), self.mom.copy(), self.mass.copy(), self.zeta.copy(),
-                     self.bonds.copy(), self.k_bond, self.r0)
+                     self.bonds.copy(), self.k_bond, self.r0, self.stencil,
+                     None if self.fext is None else self.fext.copy())
+
+    def c(self):
+        """ctypes bead-set descriptor (and the arrays it points to)."""
+        keep = [np.ascontiguousarray(self.mass, dtype=np.float64), np.ascontiguousarray(self.zeta, dtype=np.float64),
+                np.ascontiguousarray(self.bonds, dtype=np.int32).reshape(-1),
+                None if self.fext is None else np.ascontiguousarray(self.fext, dtype=np.float64)]
+        b = OrcBeadset()
+        b.n = self.pos.shape[0]
+        b.nbonds = self.bonds.shape[0]
+        b.mass = _dp(keep[0])
+        b.zeta = _dp(keep[1])
+        b.bonds = keep[2].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if keep[2].size else None
+        b.kbond = float(self.k_bond)
+        b.r0 = float(self.r0)
+        b.stencil = int(self.stencil)
+        b.fext = _dp(keep[3]) if keep[3] is not None else None
+        return b, keep
 
 
 def couple(p: Params, n: np.ndarray, step_index: int, beads: Beads, force: np.ndarray) -> None:
     """Particle half-step; updates beads in place and accumulates into force [3,nz,ny,nx]."""
-    nb = beads.pos.shape[0]
-    bonds = np.ascontiguousarray(beads.bonds, dtype=np.int32).reshape(-1)
+    bs, keep = beads.c()
     pc = p.c()
-    lib().orc_couple(ctypes.byref(pc), _dp(n), int(step_index), nb, _dp(beads.pos), _dp(beads.mom),
-                     _dp(beads.mass), _dp(beads.zeta), int(beads.bonds.shape[0]),
-                     bonds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if bonds.size else None,
-                     float(beads.k_bond), float(beads.r0), _dp(force))
+    lib().orc_couple(ctypes.byref(pc), _dp(n), int(step_index), ctypes.byref(bs), _dp(beads.pos), _dp(beads.mom),
+                     _dp(force))
 
 
 def coupled_step(p: Params, n: np.ndarray, step_index: int, beads: Beads) -> np.ndarray:
@@ -325,6 +354,24 @@ def coupled_step(p: Params, n: np.ndarray, step_index: int, beads: Beads) -> np.
     couple(p, n, step_index, beads, force)
     step(p, n, step_index, extra_force=force)
     return force
+
+
+def stencil_w(p: Params, R, W: int):
+    """(nodes, weights, d weights / dR) of the W-point interpolation stencil at R."""
+    node = np.zeros(64, np.int64)
+    w = np.zeros(64)
+    dw = np.zeros(192)
+    pc = p.c()
+    q = lib().orc_stencil_w(ctypes.byref(pc), _dp(_f64(R)), int(W), node.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            _dp(w), _dp(dw))
+    return node[:q], w[:q], dw[:3 * q].reshape(q, 3)
+
+
+def phi(W: int, r: float):
+    """(phi_W(r), phi_W'(r))."""
+    out = np.zeros(2)
+    lib().orc_phi(int(W), float(r), _dp(out))
+    return out[0], out[1]
 
 
 # --------------------------------------------------------------------------
@@ -354,22 +401,16 @@ def step_adjoint(p: Params, n: np.ndarray, lam: np.ndarray, step_index: int, gba
                            _dp(extra_bar) if extra_bar is not None else None, int(step_index), _dp(gbar))
 
 
-def _bonds_ptr(beads: "Beads"):
-    bonds = np.ascontiguousarray(beads.bonds, dtype=np.int32).reshape(-1)
-    return bonds, (bonds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if bonds.size else None)
-
-
 def couple_adjoint(p: Params, n: np.ndarray, step_index: int, beads: "Beads", force_bar: np.ndarray,
                    pos_bar: np.ndarray, mom_bar: np.ndarray, lam: np.ndarray, gbar: np.ndarray) -> None:
     """Adjoint of couple() for the bead state `beads` the step started from:
     pos_bar / mom_bar (in: after the step, out: before it), lam and gbar
     accumulate; force_bar [3,nz,ny,nx] is the adjoint of the spread force."""
-    bonds, bp = _bonds_ptr(beads)
+    bs, keep = beads.c()
     pc = p.c()
-    lib().orc_couple_adjoint(ctypes.byref(pc), _dp(_f64(n)), int(step_index), beads.pos.shape[0],
-                             _dp(_f64(beads.pos)), _dp(_f64(beads.mom)), _dp(_f64(beads.mass)),
-                             _dp(_f64(beads.zeta)), int(beads.bonds.shape[0]), bp, float(beads.k_bond),
-                             float(beads.r0), _dp(_f64(force_bar)), _dp(pos_bar), _dp(mom_bar), _dp(lam), _dp(gbar))
+    lib().orc_couple_adjoint(ctypes.byref(pc), _dp(_f64(n)), int(step_index), ctypes.byref(bs), _dp(_f64(beads.pos)),
+                             _dp(_f64(beads.mom)), _dp(_f64(force_bar)), _dp(pos_bar), _dp(mom_bar), _dp(lam),
+                             _dp(gbar))
 
 
 def backward_coupled(p: Params, n0: np.ndarray, nsteps: int, beads: "Beads", lam_T: np.ndarray,
@@ -381,12 +422,10 @@ def backward_coupled(p: Params, n0: np.ndarray, nsteps: int, beads: "Beads", lam
     pb = np.zeros((nb, 3)) if pos_bar_T is None else np.ascontiguousarray(pos_bar_T, dtype=np.float64).copy()
     mb = np.zeros((nb, 3)) if mom_bar_T is None else np.ascontiguousarray(mom_bar_T, dtype=np.float64).copy()
     gbar = np.zeros(3)
-    bonds, bp = _bonds_ptr(beads)
+    bs, keep = beads.c()
     pc = p.c()
-    lib().orc_backward_coupled(ctypes.byref(pc), _dp(_f64(n0)), int(nsteps), int(step0), nb, _dp(_f64(beads.pos)),
-                               _dp(_f64(beads.mom)), _dp(_f64(beads.mass)), _dp(_f64(beads.zeta)),
-                               int(beads.bonds.shape[0]), bp, float(beads.k_bond), float(beads.r0), _dp(lam),
-                               _dp(gbar), _dp(pb), _dp(mb))
+    lib().orc_backward_coupled(ctypes.byref(pc), _dp(_f64(n0)), int(nsteps), int(step0), ctypes.byref(bs),
+                               _dp(_f64(beads.pos)), _dp(_f64(beads.mom)), _dp(lam), _dp(gbar), _dp(pb), _dp(mb))
     return lam, gbar, pb, mb
 
 

@@ -503,34 +503,183 @@ void orc_mode_field(const orc_params *p, const double *n, double *m)
 /* Point-particle coupling (Sec. "Force coupling", "Interpolating functions")*/
 /* ------------------------------------------------------------------------ */
 
-/* Two-point interpolation kernel phi_2 of eq. 2point. */
+/* Interpolation kernels phi_W of eq. 2point, eq. 3point and eq. 4point
+ * (W = 2, 3, 4 points per axis) and their derivatives (phi_3 and phi_4 have
+ * continuous first derivatives; phi_2 is differentiated away from the
+ * nodes). */
 static double phi2(double r)
 {
     const double a = fabs(r);
     return a < 1.0 ? 1.0 - a : 0.0;
 }
 
-/* The 8 lattice nodes around position R (periodic box) and their weights
- * Delta(r - R) = phi2(x) phi2(y) phi2(z) (eq. Delta).  Nodes sit at integer
- * coordinates; the stencil starts at floor(R) with periodic wrap. */
-void orc_stencil(const orc_params *p, const double R[3], int64_t node[8], double wgt[8])
+static double phi3(double r)
+{
+    const double a = fabs(r);
+    if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+    if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(-2.0 + 6.0 * a - 3.0 * r * r)) / 6.0;
+    return 0.0;
+}
+
+static double phi4(double r)
+{
+    const double a = fabs(r);
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * r * r)) / 8.0;
+    if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * r * r)) / 8.0;
+    return 0.0;
+}
+
+static double dphi2(double r)
+{
+    if (r <= -1.0 || r >= 1.0) return 0.0;
+    return r > 0.0 ? -1.0 : 1.0;
+}
+
+static double dphi3(double r)
+{
+    const double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+    if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
+    if (a <= 1.5) return sg * (-0.5 - (1.0 - a) / (2.0 * sqrt(-2.0 + 6.0 * a - 3.0 * r * r)));
+    return 0.0;
+}
+
+static double dphi4(double r)
+{
+    const double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+    if (a <= 1.0) return sg * (-2.0 + (4.0 - 8.0 * a) / (2.0 * sqrt(1.0 + 4.0 * a - 4.0 * r * r))) / 8.0;
+    if (a <= 2.0) return sg * (-2.0 - (12.0 - 8.0 * a) / (2.0 * sqrt(-7.0 + 12.0 * a - 4.0 * r * r))) / 8.0;
+    return 0.0;
+}
+
+static double phi_w(int W, double r) { return W == 3 ? phi3(r) : (W == 4 ? phi4(r) : phi2(r)); }
+static double dphi_w(int W, double r) { return W == 3 ? dphi3(r) : (W == 4 ? dphi4(r) : dphi2(r)); }
+
+/* First node of the W-point stencil along one axis: every node within the
+ * kernel's support, floor(R) for W = 2, the nearest node minus one for
+ * W = 3, floor(R) - 1 for W = 4. */
+static double stencil_first(int W, double R)
+{
+    if (W == 3) return floor(R + 0.5) - 1.0;
+    if (W == 4) return floor(R) - 1.0;
+    return floor(R);
+}
+
+/* The W^3 lattice nodes around position R (periodic box, x fastest) and
+ * their weights Delta(r - R) = phi_W(x) phi_W(y) phi_W(z) (eq. Delta); with
+ * dw != NULL also d Delta / d R.  Nodes sit at integer coordinates.
+ * Returns W^3. */
+int orc_stencil_w(const orc_params *p, const double R[3], int32_t W, int64_t *node, double *wgt, double *dw)
 {
     const int L[3] = {p->nx, p->ny, p->nz};
-    int base[3];
-    double frac[3];
-    for (int a = 0; a < 3; ++a) {
-        const double f = floor(R[a]);
-        frac[a] = R[a] - f;
-        base[a] = wrap((int)(f - (double)L[a] * floor(f / (double)L[a])), L[a]);
-    }
+    double first[3];
+    for (int a = 0; a < 3; ++a) first[a] = stencil_first(W, R[a]);
     int q = 0;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                node[q] = site_index(p, wrap(base[0] + dx, L[0]), wrap(base[1] + dy, L[1]), wrap(base[2] + dz, L[2]));
-                wgt[q] = phi2(frac[0] - dx) * phi2(frac[1] - dy) * phi2(frac[2] - dz);
+    for (int dz = 0; dz < W; ++dz)
+        for (int dy = 0; dy < W; ++dy)
+            for (int dx = 0; dx < W; ++dx) {
+                const double c[3] = {first[0] + dx, first[1] + dy, first[2] + dz};
+                int idx[3];
+                double f[3], d[3];
+                for (int a = 0; a < 3; ++a) {
+                    const double m = c[a] - (double)L[a] * floor(c[a] / (double)L[a]);
+                    idx[a] = wrap((int)m, L[a]);
+                    f[a] = phi_w(W, R[a] - c[a]);
+                    d[a] = dphi_w(W, R[a] - c[a]);
+                }
+                node[q] = site_index(p, idx[0], idx[1], idx[2]);
+                wgt[q] = f[0] * f[1] * f[2];
+                if (dw) {
+                    dw[3 * q + 0] = d[0] * f[1] * f[2];
+                    dw[3 * q + 1] = f[0] * d[1] * f[2];
+                    dw[3 * q + 2] = f[0] * f[1] * d[2];
+                }
                 ++q;
             }
+    return q;
+}
+
+/* The 8-node two-point stencil (orc_stencil_w with W = 2). */
+void orc_stencil(const orc_params *p, const double R[3], int64_t node[8], double wgt[8])
+{
+    orc_stencil_w(p, R, 2, node, wgt, NULL);
+}
+
+/* One 1-D kernel value phi_W(r) and derivative (for the kernel pins). */
+void orc_phi(int32_t W, double r, double out[2])
+{
+    out[0] = phi_w(W, r);
+    out[1] = dphi_w(W, r);
+}
+
+/* Bead set of the particle half: masses, frictions, harmonic bonds
+ * F = -k (|d| - r0) d/|d| (pairs (a,b), d = R_b - R_a), the interpolation
+ * kernel's width and an optional external force per bead (added to the
+ * conservative force, constant in time). */
+typedef struct {
+    int32_t n, nbonds;
+    const double *mass, *zeta;
+    const int32_t *bonds;
+    double kbond, r0;
+    int32_t stencil;      /* 2, 3 or 4: phi_2 (8 nodes), phi_3 (27), phi_4 (64) */
+    int32_t pad;
+    const double *fext;   /* [n][3] or NULL */
+} orc_beadset;
+
+static int bs_width(const orc_beadset *bs) { return (bs->stencil == 3 || bs->stencil == 4) ? bs->stencil : 2; }
+
+/* Half-step positions R' = R + (h/2) P/m and conservative forces at R'
+ * (bonds plus the external force). */
+static void half_and_forces(const orc_beadset *bs, const double *pos, const double *mom, double *half, double *fc)
+{
+    const double h = 1.0;
+    for (int b = 0; b < bs->n; ++b)
+        for (int a = 0; a < 3; ++a) {
+            half[3 * b + a] = pos[3 * b + a] + 0.5 * h * mom[3 * b + a] / bs->mass[b];
+            fc[3 * b + a] = bs->fext ? bs->fext[3 * b + a] : 0.0;
+        }
+    for (int q = 0; q < bs->nbonds; ++q) {
+        const int ia = bs->bonds[2 * q], ib = bs->bonds[2 * q + 1];
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = half[3 * ib + a] - half[3 * ia + a];
+            r2 += d[a] * d[a];
+        }
+        const double r = sqrt(r2);
+        if (r == 0.0) continue;
+        const double mag = -bs->kbond * (r - bs->r0) / r;
+        for (int a = 0; a < 3; ++a) {
+            fc[3 * ib + a] += mag * d[a];
+            fc[3 * ia + a] -= mag * d[a];
+        }
+    }
+}
+
+/* Momentum-update constants of eq. langevin_momentum_update. */
+static void ou_constants(double m, double z, double kT, double *C1, double *C2, double *C3)
+{
+    const double h = 1.0;
+    if (z > 0.0) {
+        *C1 = exp(-z * h / m);
+        *C2 = (m / z) * (1.0 - *C1);
+        *C3 = sqrt(m * kT * (1.0 - exp(-2.0 * z * h / m)));
+    } else {
+        *C1 = 1.0;
+        *C2 = h;
+        *C3 = 0.0;
+    }
+}
+
+/* u = (sum n c + g/2) / rho at one site of the pre-collision state. */
+static void site_velocity(const orc_params *p, const double *n, int64_t N, int64_t s, double *rho, double u[3])
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        const double v = n[i * N + s];
+        r += v;
+        for (int a = 0; a < 3; ++a) j[a] += v * CV[i][a];
+    }
+    *rho = r;
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * p->g[a]) / r;
 }
 
 /* Particle half of one coupled time step (Sec. "Force coupling": the
@@ -538,9 +687,8 @@ void orc_stencil(const orc_params *p, const double R[3], int64_t node[8], double
  * eq. langevin_momentum_update, the interpolation eq. ufluid_discrete and
  * the reaction force eq. ftotal):
  *   1. R' = R + (h/2) P/m for every bead;
- *   2. conservative forces F^c at R' from harmonic bonds
- *      F = -k (|d| - r0) d/|d|  (bond list, pairs (a,b), d = R_b - R_a);
- *   3. u_b = sum over the 8 nodes of Delta * u(node), u(node) from the
+ *   2. conservative forces F^c at R': harmonic bonds plus the external force;
+ *   3. u_b = sum over the W^3 nodes of Delta * u(node), u(node) from the
  *      current (pre-collision) populations n: u = (sum n c + g/2)/rho;
  *   4. P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta, with
  *      C1 = exp(-zeta h/m), C2 = (m/zeta)(1 - C1),
@@ -549,63 +697,33 @@ void orc_stencil(const orc_params *p, const double R[3], int64_t node[8], double
  *      I = -(P'' - P - h F^c), spread as force density I Delta / h into
  *      `force` (layout [3][N], accumulated);
  *   6. R = R' + (h/2) P''/m, P = P''.
- * pos, mom: [3*nb] interleaved (x,y,z per bead), unwrapped positions.
+ * pos, mom: [3*n] interleaved (x,y,z per bead), unwrapped positions.
  * `step` keys the bead noise.  Parity pinned by the frozen-fluid OU tests,
  * the partition-of-unity and transpose tests, and the total-momentum test. */
-void orc_couple(const orc_params *p, const double *n, uint32_t step, int32_t nb, double *pos, double *mom,
-                const double *mass, const double *zeta, int32_t nbonds, const int32_t *bonds, double kbond,
-                double r0, double *force)
+void orc_couple(const orc_params *p, const double *n, uint32_t step, const orc_beadset *bs, double *pos, double *mom,
+                double *force)
 {
     init_tables();
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const double h = 1.0;
-    double *half = (double *)malloc(sizeof(double) * 3 * (size_t)(nb > 0 ? nb : 1));
-    double *fc = (double *)calloc(3 * (size_t)(nb > 0 ? nb : 1), sizeof(double));
-
-    for (int b = 0; b < nb; ++b)
-        for (int a = 0; a < 3; ++a) half[3 * b + a] = pos[3 * b + a] + 0.5 * h * mom[3 * b + a] / mass[b];
-
-    for (int q = 0; q < nbonds; ++q) {
-        const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
-        double d[3], r2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            d[a] = half[3 * ib + a] - half[3 * ia + a];
-            r2 += d[a] * d[a];
-        }
-        const double r = sqrt(r2);
-        if (r == 0.0) continue;
-        const double mag = -kbond * (r - r0) / r;
-        for (int a = 0; a < 3; ++a) {
-            fc[3 * ib + a] += mag * d[a];
-            fc[3 * ia + a] -= mag * d[a];
-        }
-    }
-
+    const int nb = bs->n, W = bs_width(bs);
+    const size_t nb3 = 3 * (size_t)(nb > 0 ? nb : 1);
+    double *half = (double *)malloc(sizeof(double) * nb3);
+    double *fc = (double *)malloc(sizeof(double) * nb3);
+    half_and_forces(bs, pos, mom, half, fc);
     for (int b = 0; b < nb; ++b) {
-        int64_t node[8];
-        double wgt[8];
-        orc_stencil(p, &half[3 * b], node, wgt);
+        int64_t node[64];
+        double wgt[64];
+        const int nq = orc_stencil_w(p, &half[3 * b], W, node, wgt, NULL);
         double ub[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < 8; ++q) {
-            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
-            for (int i = 0; i < Q; ++i) {
-                const double v = n[i * N + node[q]];
-                r += v;
-                for (int a = 0; a < 3; ++a) j[a] += v * CV[i][a];
-            }
-            for (int a = 0; a < 3; ++a) ub[a] += wgt[q] * (j[a] + 0.5 * p->g[a]) / r;
+        for (int q = 0; q < nq; ++q) {
+            double r, u[3];
+            site_velocity(p, n, N, node[q], &r, u);
+            for (int a = 0; a < 3; ++a) ub[a] += wgt[q] * u[a];
         }
-        const double m = mass[b], z = zeta[b];
+        const double m = bs->mass[b], z = bs->zeta[b];
         double C1, C2, C3;
-        if (z > 0.0) {
-            C1 = exp(-z * h / m);
-            C2 = (m / z) * (1.0 - C1);
-            C3 = sqrt(m * p->kT * (1.0 - exp(-2.0 * z * h / m)));
-        } else {
-            C1 = 1.0;
-            C2 = h;
-            C3 = 0.0;
-        }
+        ou_constants(m, z, p->kT, &C1, &C2, &C3);
         double th[3] = {0.0, 0.0, 0.0};
         if (p->kT > 0.0 && z > 0.0) orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
         double Pn[3], I[3];
@@ -613,7 +731,7 @@ void orc_couple(const orc_params *p, const double *n, uint32_t step, int32_t nb,
             Pn[a] = C1 * mom[3 * b + a] + C2 * (fc[3 * b + a] + z * ub[a]) + C3 * th[a];
             I[a] = -(Pn[a] - mom[3 * b + a] - h * fc[3 * b + a]);
         }
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < nq; ++q)
             for (int a = 0; a < 3; ++a) force[a * N + node[q]] += wgt[q] * I[a] / h;
         for (int a = 0; a < 3; ++a) {
             mom[3 * b + a] = Pn[a];
@@ -627,13 +745,12 @@ void orc_couple(const orc_params *p, const double *n, uint32_t step, int32_t nb,
 /* One full coupled step (particle update, spreading, then one LB step with
  * the spread force in the collision).  `work` is 19*N doubles and `force`
  * is 3*N doubles of caller scratch. */
-void orc_coupled_step(const orc_params *p, double *n, double *work, double *force, uint32_t step, int32_t nb,
-                      double *pos, double *mom, const double *mass, const double *zeta, int32_t nbonds,
-                      const int32_t *bonds, double kbond, double r0)
+void orc_coupled_step(const orc_params *p, double *n, double *work, double *force, uint32_t step,
+                      const orc_beadset *bs, double *pos, double *mom)
 {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     memset(force, 0, sizeof(double) * 3 * (size_t)N);
-    orc_couple(p, n, step, nb, pos, mom, mass, zeta, nbonds, bonds, kbond, r0, force);
+    orc_couple(p, n, step, bs, pos, mom, force);
     orc_step(p, n, work, force, step);
 }
 
@@ -819,33 +936,6 @@ void orc_backward(const orc_params *p, const double *n0, int32_t nsteps, uint32_
 /* Adjoint (reverse mode) of the particle half of a coupled step             */
 /* ------------------------------------------------------------------------ */
 
-/* d phi2(r) / dr where the kernel is differentiable (|r| < 1, r != 0). */
-static double dphi2(double r)
-{
-    if (r <= -1.0 || r >= 1.0) return 0.0;
-    return r > 0.0 ? -1.0 : 1.0;
-}
-
-/* Weights of the 8-node stencil (eq. Delta) and their gradients with
- * respect to R: dw[q][a] = d wgt[q] / d R_a.  Same node order as
- * orc_stencil. */
-static void stencil_grad(const double R[3], double dw[8][3])
-{
-    double frac[3];
-    for (int a = 0; a < 3; ++a) frac[a] = R[a] - floor(R[a]);
-    int q = 0;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                const double r[3] = {frac[0] - dx, frac[1] - dy, frac[2] - dz};
-                const double f[3] = {phi2(r[0]), phi2(r[1]), phi2(r[2])};
-                dw[q][0] = dphi2(r[0]) * f[1] * f[2];
-                dw[q][1] = f[0] * dphi2(r[1]) * f[2];
-                dw[q][2] = f[0] * f[1] * dphi2(r[2]);
-                ++q;
-            }
-}
-
 /* Transpose of the Jacobian of orc_couple (with its bead noise replayed).
  * Inputs: the fluid state n and bead state (pos, mom) the step started
  * from, and force_bar ([3][N]), the adjoint of the spread force field
@@ -857,73 +947,39 @@ static void stencil_grad(const double R[3], double dw[8][3])
  * I = -(P'' - P - h F^c) spread with the weights Delta(R'), the momentum
  * update P'' = C1 P + C2 (F^c + zeta u_b), the interpolation
  * u_b = sum Delta u(node), the bond forces F^c(R') and the half drift
- * R' = R + (h/2) P/m.  The weights are differentiated where the stencil is
- * differentiable (R' off the node planes).  Parity pinned by central
- * finite differences of the coupled forward map. */
-void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int32_t nb, const double *pos,
-                        const double *mom, const double *mass, const double *zeta, int32_t nbonds,
-                        const int32_t *bonds, double kbond, double r0, const double *force_bar, double *pos_bar,
+ * R' = R + (h/2) P/m.  The weights are differentiated with the kernels'
+ * derivatives (phi_2: where R' is off the node planes).  The external force
+ * is constant and has no adjoint.  Parity pinned by central finite
+ * differences of the coupled forward map. */
+void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, const orc_beadset *bs,
+                        const double *pos, const double *mom, const double *force_bar, double *pos_bar,
                         double *mom_bar, double *lam, double gbar[3])
 {
     init_tables();
+    (void)step;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const double h = 1.0;
+    const int nb = bs->n, W = bs_width(bs);
     const size_t nb3 = 3 * (size_t)(nb > 0 ? nb : 1);
     double *half = (double *)malloc(sizeof(double) * nb3);
-    double *fc = (double *)calloc(nb3, sizeof(double));
+    double *fc = (double *)malloc(sizeof(double) * nb3);
     double *half_bar = (double *)calloc(nb3, sizeof(double));
     double *fc_bar = (double *)calloc(nb3, sizeof(double));
     double *p_bar = (double *)calloc(nb3, sizeof(double));
-
-    /* forward quantities: half-step positions and bond forces */
-    for (int b = 0; b < nb; ++b)
-        for (int a = 0; a < 3; ++a) half[3 * b + a] = pos[3 * b + a] + 0.5 * h * mom[3 * b + a] / mass[b];
-    for (int q = 0; q < nbonds; ++q) {
-        const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
-        double d[3], r2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            d[a] = half[3 * ib + a] - half[3 * ia + a];
-            r2 += d[a] * d[a];
-        }
-        const double r = sqrt(r2);
-        if (r == 0.0) continue;
-        const double mag = -kbond * (r - r0) / r;
-        for (int a = 0; a < 3; ++a) {
-            fc[3 * ib + a] += mag * d[a];
-            fc[3 * ia + a] -= mag * d[a];
-        }
-    }
+    half_and_forces(bs, pos, mom, half, fc);
 
     for (int b = 0; b < nb; ++b) {
-        const double m = mass[b], z = zeta[b];
-        int64_t node[8];
-        double wgt[8], dw[8][3], un[8][3], rn[8];
-        orc_stencil(p, &half[3 * b], node, wgt);
-        stencil_grad(&half[3 * b], dw);
+        const double m = bs->mass[b], z = bs->zeta[b];
+        int64_t node[64];
+        double wgt[64], dw[192], un[64][3], rn[64];
+        const int nq = orc_stencil_w(p, &half[3 * b], W, node, wgt, dw);
         double ub[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < 8; ++q) {
-            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
-            for (int i = 0; i < Q; ++i) {
-                const double v = n[i * N + node[q]];
-                r += v;
-                for (int a = 0; a < 3; ++a) j[a] += v * CV[i][a];
-            }
-            rn[q] = r;
-            for (int a = 0; a < 3; ++a) {
-                un[q][a] = (j[a] + 0.5 * p->g[a]) / r;
-                ub[a] += wgt[q] * un[q][a];
-            }
+        for (int q = 0; q < nq; ++q) {
+            site_velocity(p, n, N, node[q], &rn[q], un[q]);
+            for (int a = 0; a < 3; ++a) ub[a] += wgt[q] * un[q][a];
         }
         double C1, C2, C3;
-        if (z > 0.0) {
-            C1 = exp(-z * h / m);
-            C2 = (m / z) * (1.0 - C1);
-            C3 = sqrt(m * p->kT * (1.0 - exp(-2.0 * z * h / m)));
-        } else {
-            C1 = 1.0;
-            C2 = h;
-            C3 = 0.0;
-        }
+        ou_constants(m, z, p->kT, &C1, &C2, &C3);
         double th[3] = {0.0, 0.0, 0.0};
         if (p->kT > 0.0 && z > 0.0) orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
         double I[3];
@@ -939,10 +995,10 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int
             Pn_bar[a] = mom_bar[3 * b + a] + 0.5 * h / m * pos_bar[3 * b + a];
         }
         /* force[node] += Delta I / h */
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < nq; ++q)
             for (int a = 0; a < 3; ++a) I_bar[a] += wgt[q] * force_bar[a * N + node[q]] / h;
-        double wgt_bar[8];
-        for (int q = 0; q < 8; ++q) {
+        double wgt_bar[64];
+        for (int q = 0; q < nq; ++q) {
             wgt_bar[q] = 0.0;
             for (int a = 0; a < 3; ++a) wgt_bar[q] += I[a] * force_bar[a * N + node[q]] / h;
         }
@@ -959,7 +1015,7 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int
             ub_bar[a] = C2 * z * Pn_bar[a];
         }
         /* u_b = sum Delta u(node); u = (sum n c + g/2) / rho */
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < nq; ++q) {
             double uq_bar[3];
             for (int a = 0; a < 3; ++a) {
                 wgt_bar[q] += ub_bar[a] * un[q][a];
@@ -973,14 +1029,14 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int
             }
         }
         /* the weights depend on R' */
-        for (int q = 0; q < 8; ++q)
-            for (int a = 0; a < 3; ++a) half_bar[3 * b + a] += wgt_bar[q] * dw[q][a];
+        for (int q = 0; q < nq; ++q)
+            for (int a = 0; a < 3; ++a) half_bar[3 * b + a] += wgt_bar[q] * dw[3 * q + a];
     }
 
     /* bond forces F_b = mag d, F_a = -mag d, d = R'_b - R'_a,
      * mag = -k (1 - r0/r): dF_b/dd = mag I - k r0 d d^T / r^3 (symmetric) */
-    for (int q = 0; q < nbonds; ++q) {
-        const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
+    for (int q = 0; q < bs->nbonds; ++q) {
+        const int ia = bs->bonds[2 * q], ib = bs->bonds[2 * q + 1];
         double d[3], r2 = 0.0;
         for (int a = 0; a < 3; ++a) {
             d[a] = half[3 * ib + a] - half[3 * ia + a];
@@ -988,14 +1044,14 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int
         }
         const double r = sqrt(r2);
         if (r == 0.0) continue;
-        const double mag = -kbond * (r - r0) / r;
+        const double mag = -bs->kbond * (r - bs->r0) / r;
         double v[3], dv = 0.0;
         for (int a = 0; a < 3; ++a) {
             v[a] = fc_bar[3 * ib + a] - fc_bar[3 * ia + a];
             dv += d[a] * v[a];
         }
         for (int a = 0; a < 3; ++a) {
-            const double d_bar = mag * v[a] - kbond * r0 * d[a] * dv / (r * r * r);
+            const double d_bar = mag * v[a] - bs->kbond * bs->r0 * d[a] * dv / (r * r * r);
             half_bar[3 * ib + a] += d_bar;
             half_bar[3 * ia + a] -= d_bar;
         }
@@ -1005,7 +1061,7 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int
     for (int b = 0; b < nb; ++b)
         for (int a = 0; a < 3; ++a) {
             pos_bar[3 * b + a] = half_bar[3 * b + a];
-            mom_bar[3 * b + a] = p_bar[3 * b + a] + 0.5 * h / mass[b] * half_bar[3 * b + a];
+            mom_bar[3 * b + a] = p_bar[3 * b + a] + 0.5 * h / bs->mass[b] * half_bar[3 * b + a];
         }
     free(half);
     free(fc);
@@ -1021,12 +1077,12 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, int
  * Per step, in reverse: the fluid step's adjoint (which also gives the
  * adjoint of the spread force at every site), then the particle half's.
  * Stores all intermediate states (plain and slow). */
-void orc_backward_coupled(const orc_params *p, const double *n0, int32_t nsteps, uint32_t step0, int32_t nb,
-                          const double *pos0, const double *mom0, const double *mass, const double *zeta,
-                          int32_t nbonds, const int32_t *bonds, double kbond, double r0, double *lam, double gbar[3],
+void orc_backward_coupled(const orc_params *p, const double *n0, int32_t nsteps, uint32_t step0,
+                          const orc_beadset *bs, const double *pos0, const double *mom0, double *lam, double gbar[3],
                           double *pos_bar, double *mom_bar)
 {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const int nb = bs->n;
     const size_t sz = sizeof(double) * Q * (size_t)N;
     const size_t bsz = sizeof(double) * 3 * (size_t)(nb > 0 ? nb : 1);
     const size_t T = (size_t)(nsteps > 0 ? nsteps : 1);
@@ -1045,8 +1101,8 @@ void orc_backward_coupled(const orc_params *p, const double *n0, int32_t nsteps,
         memcpy(nt, states + (size_t)t * Q * N, sz);
         memcpy(bpos + (size_t)(t + 1) * 3 * nb, bpos + (size_t)t * 3 * nb, bsz);
         memcpy(bmom + (size_t)(t + 1) * 3 * nb, bmom + (size_t)t * 3 * nb, bsz);
-        orc_coupled_step(p, nt, work, force, step0 + (uint32_t)t, nb, bpos + (size_t)(t + 1) * 3 * nb,
-                         bmom + (size_t)(t + 1) * 3 * nb, mass, zeta, nbonds, bonds, kbond, r0);
+        orc_coupled_step(p, nt, work, force, step0 + (uint32_t)t, bs, bpos + (size_t)(t + 1) * 3 * nb,
+                         bmom + (size_t)(t + 1) * 3 * nb);
     }
     for (int32_t t = nsteps - 1; t >= 0; --t) {
         const double *nt = states + (size_t)t * Q * N;
@@ -1055,11 +1111,11 @@ void orc_backward_coupled(const orc_params *p, const double *n0, int32_t nsteps,
         memcpy(tp, bpos + (size_t)t * 3 * nb, bsz);
         memcpy(tm, bmom + (size_t)t * 3 * nb, bsz);
         memset(force, 0, sizeof(double) * 3 * (size_t)N);
-        orc_couple(p, nt, st, nb, tp, tm, mass, zeta, nbonds, bonds, kbond, r0, force);
+        orc_couple(p, nt, st, bs, tp, tm, force);
         memset(force_bar, 0, sizeof(double) * 3 * (size_t)N);
         orc_step_adjoint(p, nt, lam, work, force, force_bar, st, gbar);
-        orc_couple_adjoint(p, nt, st, nb, bpos + (size_t)t * 3 * nb, bmom + (size_t)t * 3 * nb, mass, zeta, nbonds,
-                           bonds, kbond, r0, force_bar, pos_bar, mom_bar, lam, gbar);
+        orc_couple_adjoint(p, nt, st, bs, bpos + (size_t)t * 3 * nb, bmom + (size_t)t * 3 * nb, force_bar, pos_bar,
+                           mom_bar, lam, gbar);
     }
     free(tp);
     free(tm);

@@ -237,3 +237,39 @@ def test_composed_reverse_sweep_equals_backward_coupled(orc):
         orc.couple_adjoint(p, states[t], t, bstates[t], fbar, pb, mb, lam, gbar)
     for x, y in zip((lam, gbar, pb, mb), ref):
         np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-14 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("W", [3, 4])
+def test_coupled_backward_wide_stencils_match_finite_differences(orc, W):
+    """The coupled adjoint with the three- and four-point kernels (their
+    derivatives enter through the weights) and an external bead force."""
+    rng = np.random.default_rng(20 + W)
+    p = orc.Params(nx=10, ny=9, nz=8, kT=1e-4, seed=5, g=(1e-4, -5e-5, 2e-5))
+    n0 = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 8, 9, 10)))
+    beads = _bead_system(orc, rng, L=(10, 9, 8))
+    beads.stencil = W
+    beads.fext = rng.normal(scale=1e-4, size=beads.pos.shape)
+    nb = beads.pos.shape[0]
+    T = 3
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+
+    def loss(nn, pp, bb):
+        n = nn.copy()
+        c = bb.copy()
+        for t in range(T):
+            orc.coupled_step(pp, n, t, c)
+        return (w * n).sum() + (a * c.pos).sum() + (b * c.mom).sum()
+
+    lam0, gbar, pb0, mb0 = orc.backward_coupled(p, n0, T, beads, w, a, b)
+    eps = 1e-6
+    v = rng.normal(size=n0.shape)
+    fd = (loss(n0 + eps * v, p, beads) - loss(n0 - eps * v, p, beads)) / (2 * eps)
+    assert (lam0 * v).sum() == pytest.approx(fd, rel=1e-6)
+    for name, bar in (("pos", pb0), ("mom", mb0)):
+        vb = rng.normal(size=(nb, 3))
+        bp_, bm_ = beads.copy(), beads.copy()
+        setattr(bp_, name, getattr(beads, name) + eps * vb)
+        setattr(bm_, name, getattr(beads, name) - eps * vb)
+        fd = (loss(n0, p, bp_) - loss(n0, p, bm_)) / (2 * eps)
+        assert (bar * vb).sum() == pytest.approx(fd, rel=1e-6), name

@@ -190,3 +190,119 @@ def test_coupled_bead_temperature(orc):
             acc += (beads.mom ** 2).mean()
             cnt += 1
     assert acc / cnt / kT == pytest.approx(1.0, rel=0.08)
+
+
+# ---------------------------------------------------------------------------
+# Three- and four-point kernels (eq. 3point, eq. 4point) and the W-point
+# stencils built from them; external bead forces.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W", [2, 3, 4])
+def test_kernel_moment_conditions(orc, W):
+    """eq. C1 and eq. C2 hold for all three kernels; eq. C3 (sum of squares
+    independent of u) holds for phi_3 (= 1/2) and phi_4 (= 3/8) and fails for
+    phi_2; phi_W' equals the central difference of phi_W."""
+    rng = np.random.default_rng(W)
+    sq = []
+    for u in rng.uniform(-3, 3, size=200):
+        js = np.arange(np.floor(u) - 3, np.floor(u) + 4)
+        ph = np.array([orc.phi(W, u - j)[0] for j in js])
+        assert ph.sum() == pytest.approx(1.0, abs=1e-14)
+        assert (js * ph).sum() == pytest.approx(u, abs=1e-13)
+        sq.append((ph ** 2).sum())
+        d = orc.phi(W, u)[1]
+        fd = (orc.phi(W, u + 1e-7)[0] - orc.phi(W, u - 1e-7)[0]) / 2e-7
+        if min(abs(abs(u) - k) for k in (0.0, 0.5, 1.0, 1.5, 2.0)) > 1e-5:
+            assert d == pytest.approx(fd, abs=2e-6)
+    sq = np.array(sq)
+    if W == 2:
+        assert sq.max() - sq.min() > 0.1
+    else:
+        np.testing.assert_allclose(sq, {3: 0.5, 4: 0.375}[W], atol=1e-14)
+
+
+@pytest.mark.parametrize("W", [3, 4])
+def test_kernel_derivative_is_continuous(orc, W):
+    """phi_3 and phi_4 have continuous first derivatives (the property the
+    text after eq. 3point points out), also across their piece boundaries."""
+    for k in {3: (0.5, 1.5), 4: (1.0, 2.0)}[W]:
+        for sgn in (1, -1):
+            a, b = orc.phi(W, sgn * (k - 1e-9))[1], orc.phi(W, sgn * (k + 1e-9))[1]
+            assert a == pytest.approx(b, abs=1e-4)
+
+
+@pytest.mark.parametrize("W", [2, 3, 4])
+def test_w_point_stencil(orc, W):
+    """W^3 nodes: partition of unity (eq. DnormDiscrete), first moment equal
+    to R, and the weight gradients equal central differences."""
+    p = orc.Params(nx=12, ny=11, nz=10)
+    L = np.array([12, 11, 10])
+    rng = np.random.default_rng(10 + W)
+    for _ in range(100):
+        R = rng.uniform(-20, 30, size=3)
+        node, w, dw = orc.stencil_w(p, R, W)
+        assert len(node) == W ** 3 and (w >= -1e-16).all()
+        assert w.sum() == pytest.approx(1.0, abs=1e-14)
+        coords = np.stack([node % 12, (node // 12) % 11, node // 132], 1).astype(float)
+        first = np.floor(R) - (1 if W == 4 else 0)
+        unwrapped = first + ((coords - first) % L)
+        if W == 3:
+            unwrapped = np.floor(R + 0.5) - 1 + ((coords - (np.floor(R + 0.5) - 1)) % L)
+        np.testing.assert_allclose(w @ unwrapped, R, atol=1e-12)
+        np.testing.assert_allclose(dw.sum(0), 0.0, atol=1e-12)
+        if W > 2:
+            for a in range(3):
+                e = np.zeros(3)
+                e[a] = 1e-7
+                fd = (orc.stencil_w(p, R + e, W)[1] - orc.stencil_w(p, R - e, W)[1]) / 2e-7
+                np.testing.assert_allclose(dw[:, a], fd, atol=2e-6)
+
+
+@pytest.mark.parametrize("W", [3, 4])
+def test_wide_stencil_linear_field_interpolated_exactly(orc, W):
+    L = 12
+    p = orc.Params(nx=L, ny=L, nz=L)
+    a = np.array([1e-3, -2e-3, 5e-4])
+    B = np.array([[1e-4, 2e-4, -1e-4], [3e-5, -2e-4, 1e-4], [-1e-4, 5e-5, 2e-4]])
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    r = np.stack([x, y, z]).astype(float)
+    n = orc.init_equilibrium(p, u=a[:, None, None, None] + np.einsum("ab,bzyx->azyx", B, r))
+    rng = np.random.default_rng(W)
+    for _ in range(10):
+        R = rng.uniform(3, 8, size=3)
+        b = one_bead(R, zeta=3.0)
+        b.stencil = W
+        orc.couple(p, n, 0, b, np.zeros((3, L, L, L)))
+        C1 = math.exp(-3.0)
+        ub = b.mom[0] / ((1 / 3.0) * (1 - C1) * 3.0)
+        np.testing.assert_allclose(ub, a + B @ R, atol=1e-14)
+
+
+@pytest.mark.parametrize("W", [3, 4])
+def test_wide_stencil_momentum_with_external_force(orc, W):
+    """Total (fluid + bead) momentum changes by N g + sum of the external
+    bead forces per coupled step (the fluid receives only the friction
+    impulse); the spread force sums to that impulse; mass is unchanged."""
+    import oracle as O
+    L = 10
+    g = (1e-5, 0.0, -2e-5)
+    p = orc.Params(nx=L, ny=L, nz=L, kT=1e-4, g=g, seed=3)
+    rng = np.random.default_rng(5)
+    n = orc.init_equilibrium(p, u=rng.normal(scale=0.005, size=(3, L, L, L)))
+    nb = 6
+    pos = rng.uniform(0, L, size=(nb, 3))
+    fext = rng.normal(scale=1e-4, size=(nb, 3))
+    beads = O.Beads(pos, rng.normal(scale=0.01, size=(nb, 3)), np.ones(nb), np.full(nb, 5.0),
+                    np.array([[0, 1], [2, 3]], np.int32), 0.1, 1.0, W, fext)
+    for t in range(4):
+        tot0 = orc.totals(p, n)
+        P0 = beads.mom.sum(0)
+        f = np.zeros((3, L, L, L))
+        orc.couple(p, n, t, beads, f)
+        imp = -(beads.mom.sum(0) - P0 - fext.sum(0))
+        np.testing.assert_allclose(f.sum(axis=(1, 2, 3)), imp, atol=1e-15)
+        orc.step(p, n, t, extra_force=f)
+        tot1 = orc.totals(p, n)
+        assert tot1[0] == pytest.approx(tot0[0], rel=1e-14)
+        dP = (tot1[1:] - tot0[1:]) + (beads.mom.sum(0) - P0)
+        np.testing.assert_allclose(dP, L ** 3 * np.array(g) + fext.sum(0), atol=1e-14)
