@@ -135,7 +135,15 @@ typedef struct {
  *   mom  [n][3]  momenta p (in/out)
  *   mass [n]     m_i > 0
  *   zeta [n]     friction Gamma_i >= 0 (eq. fdrag)
- *   bonds [nbonds][2]  bead index pairs, potential (k_bond/2)(|d| - r0)^2 */
+ *   bonds [nbonds][2]  bead index pairs, potential (k_bond/2)(|d| - r0)^2
+ *   fext [n][3]  external force on each bead, added to the conservative force
+ *                (constant over the call; its reaction is not given to the
+ *                fluid), or NULL
+ *   stencil      points per axis of the interpolation kernel (Sec.
+ *                "Interpolating functions"): 2 = phi_2 (eq. 2point, 8 nodes;
+ *                also selected by 0), 3 = phi_3 (eq. 3point, 27 nodes),
+ *                4 = phi_4 (eq. 4point, 64 nodes); the kernel is used for
+ *                both the interpolation and the spreading. */
 typedef struct {
     int32_t n;
     int32_t nbonds;
@@ -146,6 +154,9 @@ typedef struct {
     const int32_t *bonds;
     double k_bond;
     double r0;
+    const double *fext;
+    int32_t stencil;
+    int32_t reserved;  /* must be 0 */
 } lb_beads;
 
 typedef struct lb_ctx lb_ctx;

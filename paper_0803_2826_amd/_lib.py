@@ -67,6 +67,8 @@ class lb_beads(ctypes.Structure):
         ("mass", ctypes.c_void_p), ("zeta", ctypes.c_void_p),
         ("bonds", ctypes.c_void_p),
         ("k_bond", ctypes.c_double), ("r0", ctypes.c_double),
+        ("fext", ctypes.c_void_p),
+        ("stencil", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -12,11 +12,11 @@
 // Given the adjoints of (R_new, P_new) and fbar, the adjoint of the spread
 // force at every node (written by the FORCE variant of k_adjoint_step), the
 // kernels below produce the adjoints of (R, P), add the interpolation's
-// contribution w_q (c_i - u_q).ubar_b / rho_q to lambda_i at the bead's 8
+// contribution w_q (c_i - u_q).ubar_b / rho_q to lambda_i at the bead's stencil
 // nodes and w_q ubar_b / (2 rho_q) to gbar.  The stencil weights are
-// differentiated where they are differentiable (R' off the node planes):
-// d w_q / d R'_a = (+1 or -1) times the other two 1-D weights.  The bead
-// noise is not needed: P'' is taken from the recomputed forward update.
+// differentiated with the kernels' derivatives (phi_2 where R' is off the
+// node planes).  The bead noise is not needed: P'' is taken from the
+// recomputed forward update; the external bead force is constant.
 #pragma once
 
 #include "couple.h"
@@ -45,71 +45,48 @@ struct BeadAdjArgs {
     double *gbar;           // [3] accumulated
 };
 
-// Sum over the 8 lanes of one bead (lanes 8b .. 8b+7 of a wave).
-__device__ __forceinline__ double bead_lane_sum(double v)
-{
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// 8 consecutive lanes per bead, one per stencil node (node order and
+// StencilLanes<W> lanes per bead, one per stencil node (node order and
 // weights as in k_bead_update).
-template <int ST>
+template <int ST, int W>
 __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
+    constexpr int LANES = StencilLanes<W>::value;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = t >> 3, q = t & 7;
+    const int b = t / LANES, q = t % LANES;
     const bool live = b < a.n;
     const Geom &g = a.geo;
     uint32_t node = 0;
     double wq = 0.0, dw[3] = {0.0, 0.0, 0.0}, uq[3] = {0.0, 0.0, 0.0}, rho = 1.0, fb[3] = {0.0, 0.0, 0.0};
     if (live) {
-        const uint32_t L[3] = {g.nx, g.ny, g.nz};
-        uint32_t cpos[3];
-        double w1[3], sgn[3];
-        for (int c = 0; c < 3; ++c) {
-            const double r = a.half[3 * b + c];
-            const double f = floor(r);
-            const double frac = r - f;
-            const double wrapped = f - (double)L[c] * floor(f / (double)L[c]);
-            uint32_t wi = (uint32_t)wrapped;
-            if (wi >= L[c]) wi = 0;
-            const uint32_t bit = (q >> c) & 1;
-            cpos[c] = (wi + bit) % L[c];
-            w1[c] = bit ? frac : 1.0 - frac;
-            sgn[c] = bit ? 1.0 : -1.0;
-        }
-        node = cpos[0] + g.nx * (cpos[1] + g.ny * cpos[2]);
-        wq = w1[0] * w1[1] * w1[2];
-        dw[0] = sgn[0] * w1[1] * w1[2];
-        dw[1] = w1[0] * sgn[1] * w1[2];
-        dw[2] = w1[0] * w1[1] * sgn[2];
-        uint32_t xx, yy, zz;
-        const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
-        const T *pop = static_cast<const T *>(a.pop);
-        double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+        const double R[3] = {a.half[3 * b], a.half[3 * b + 1], a.half[3 * b + 2]};
+        stencil_node<W>(R, q, g, node, wq, dw);
+        if (q < W * W * W) {
+            uint32_t xx, yy, zz;
+            const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
+            const T *pop = static_cast<const T *>(a.pop);
+            double m = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
-            m += v;
-            j[0] += v * kCX[i];
-            j[1] += v * kCY[i];
-            j[2] += v * kCZ[i];
-        }
-        rho = a.rho0 + m;
-        for (int c = 0; c < 3; ++c) {
-            uq[c] = (j[c] + 0.5 * a.g[c]) / rho;
-            fb[c] = (double)a.fbar[(size_t)c * g.N + node];
+            for (int i = 0; i < Q; ++i) {
+                const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
+                m += v;
+                j[0] += v * kCX[i];
+                j[1] += v * kCY[i];
+                j[2] += v * kCZ[i];
+            }
+            rho = a.rho0 + m;
+            for (int c = 0; c < 3; ++c) {
+                uq[c] = (j[c] + 0.5 * a.g[c]) / rho;
+                fb[c] = (double)a.fbar[(size_t)c * g.N + node];
+            }
         }
     }
     // adjoint of the spread reaction: Ibar = sum_q w_q fbar(node_q) / h
     const double h = 1.0;
     double Ib[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) Ib[c] = bead_lane_sum(wq * fb[c]) / h;
+    for (int c = 0; c < 3; ++c) Ib[c] = bead_sum<LANES>(wq * fb[c]) / h;
     if (!live) return;
     const double m = a.mass[b], z = a.zeta[b];
     double C1, C2;
@@ -148,8 +125,8 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
     double hb[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        hb[c] = bead_lane_sum(wb * dw[c]);
-        gq[c] = bead_lane_sum(gq[c]);
+        hb[c] = bead_sum<LANES>(wb * dw[c]);
+        gq[c] = bead_sum<LANES>(gq[c]);
     }
     if (q == 0) {
         for (int c = 0; c < 3; ++c) {

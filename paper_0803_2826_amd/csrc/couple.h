@@ -3,18 +3,20 @@
 // gathered from the stored populations.
 //
 // One coupled step on the device:
-//   k_bead_half     R' = R + (h/2) P/m, clear conservative forces, reset the
-//                   touched-node count
+//   k_bead_half     R' = R + (h/2) P/m; the conservative force starts from the
+//                   external bead force (or zero); reset the touched-node count
 //   k_bonds         harmonic bond forces at R' (FP64 atomics; a bead with at
 //                   most two bonds gets a bitwise reproducible sum)
-//   k_bead_update   8 lanes per bead, one per stencil node: each lane gathers
-//                   its node's 19 populations and forms w u(node) with
-//                   u = (sum n c + g/2)/rho (trilinear phi_2 product kernel,
-//                   eq. Delta / eq. 2point); a lane reduction gives u_b; every
-//                   lane then evaluates P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta
-//                   (eq. langevin_momentum_update) and spreads w I / h with
-//                   I = -(P'' - P - h F^c) to its own node (eq. ftotal), setting
-//                   the node's bit in the force bitmap; R = R' + (h/2) P''/m
+//   k_bead_update   one lane per stencil node (W^3 of them, W = 2, 3, 4 for the
+//                   kernels phi_2, phi_3, phi_4 of eq. 2point, eq. 3point,
+//                   eq. 4point): each lane gathers its node's 19 populations
+//                   and forms w u(node) with u = (sum n c + g/2)/rho and the
+//                   product weight of eq. Delta; a lane reduction gives u_b;
+//                   every lane then evaluates P'' = C1 P + C2 (F^c + zeta u_b)
+//                   + C3 theta (eq. langevin_momentum_update) and spreads
+//                   w I / h with I = -(P'' - P - h F^c) to its own node
+//                   (eq. ftotal), setting the node's bit in the force bitmap;
+//                   R = R' + (h/2) P''/m
 //   (next lb_step)  the fused stream-collide kernel adds the bead force at
 //                   flagged sites, then k_clear_touched zeroes force and bits.
 #pragma once
@@ -35,6 +37,7 @@ struct CoupleArgs {
     double *mom;
     const double *mass;
     const double *zeta;
+    const double *fext;   // [n][3] external bead force or NULL
     double *half;         // [n][3]
     double *fc;           // [n][3]
     float *force;         // [3][N] sparse force field (zero outside touched nodes)
@@ -51,8 +54,88 @@ __global__ void k_bead_half(CoupleArgs a)
     const double m = a.mass[b];
     for (int c = 0; c < 3; ++c) {
         a.half[3 * b + c] = a.pos[3 * b + c] + 0.5 * a.mom[3 * b + c] / m;
-        a.fc[3 * b + c] = 0.0;
+        a.fc[3 * b + c] = a.fext ? a.fext[3 * b + c] : 0.0;
     }
+}
+
+// Interpolation kernels phi_W (eq. 2point, eq. 3point, eq. 4point) and their
+// derivatives (phi_2 differentiated away from the nodes).
+template <int W>
+__device__ __forceinline__ double phi_kernel(double r)
+{
+    const double a = fabs(r);
+    if constexpr (W == 2) return a < 1.0 ? 1.0 - a : 0.0;
+    if constexpr (W == 3) {
+        if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+        if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(-2.0 + 6.0 * a - 3.0 * r * r)) / 6.0;
+        return 0.0;
+    }
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * r * r)) / 8.0;
+    if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * r * r)) / 8.0;
+    return 0.0;
+}
+
+template <int W>
+__device__ __forceinline__ double dphi_kernel(double r)
+{
+    const double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+    if constexpr (W == 2) return (a < 1.0) ? -sg : 0.0;
+    if constexpr (W == 3) {
+        if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
+        if (a <= 1.5) return sg * (-0.5 - (1.0 - a) / (2.0 * sqrt(-2.0 + 6.0 * a - 3.0 * r * r)));
+        return 0.0;
+    }
+    if (a <= 1.0) return sg * (-2.0 + (4.0 - 8.0 * a) / (2.0 * sqrt(1.0 + 4.0 * a - 4.0 * r * r))) / 8.0;
+    if (a <= 2.0) return sg * (-2.0 - (12.0 - 8.0 * a) / (2.0 * sqrt(-7.0 + 12.0 * a - 4.0 * r * r))) / 8.0;
+    return 0.0;
+}
+
+// Lanes per bead: W^3 stencil nodes rounded up to a power of two dividing 64,
+// so that a bead's lanes never straddle a wave.
+template <int W> struct StencilLanes { static constexpr int value = W == 2 ? 8 : (W == 3 ? 32 : 64); };
+
+// Node and weight of lane q of the W-point stencil around R' (x fastest; the
+// first node along an axis: floor(R) for W = 2, the nearest node minus one
+// for W = 3, floor(R) - 1 for W = 4).  Lanes q >= W^3 get weight 0.  With
+// dw != nullptr also the weight's gradient in R'.
+template <int W>
+__device__ __forceinline__ void stencil_node(const double R[3], int q, const Geom &g, uint32_t &node, double &w,
+                                             double *dw)
+{
+    node = 0u;
+    w = 0.0;
+    if (dw) dw[0] = dw[1] = dw[2] = 0.0;
+    if (q >= W * W * W) return;
+    const int d[3] = {q % W, (q / W) % W, q / (W * W)};
+    const uint32_t L[3] = {g.nx, g.ny, g.nz};
+    uint32_t cpos[3];
+    double f[3], df[3];
+    for (int c = 0; c < 3; ++c) {
+        const double first = (W == 3) ? floor(R[c] + 0.5) - 1.0 : ((W == 4) ? floor(R[c]) - 1.0 : floor(R[c]));
+        const double xc = first + (double)d[c];
+        const double m = xc - (double)L[c] * floor(xc / (double)L[c]);  // xc mod L in [0, L)
+        uint32_t wi = (uint32_t)m;
+        if (wi >= L[c]) wi = 0;
+        cpos[c] = wi;
+        f[c] = phi_kernel<W>(R[c] - xc);
+        df[c] = dw ? dphi_kernel<W>(R[c] - xc) : 0.0;
+    }
+    node = cpos[0] + g.nx * (cpos[1] + g.ny * cpos[2]);
+    w = f[0] * f[1] * f[2];
+    if (dw) {
+        dw[0] = df[0] * f[1] * f[2];
+        dw[1] = f[0] * df[1] * f[2];
+        dw[2] = f[0] * f[1] * df[2];
+    }
+}
+
+// Sum over the LANES lanes of one bead.
+template <int LANES>
+__device__ __forceinline__ double bead_sum(double v)
+{
+#pragma unroll
+    for (int off = 1; off < LANES; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 __global__ void k_bonds(const double *__restrict__ half, double *fc, const int32_t *__restrict__ bonds, int nbonds,
@@ -76,57 +159,43 @@ __global__ void k_bonds(const double *__restrict__ half, double *fc, const int32
     }
 }
 
-// 8 consecutive lanes per bead (blockDim a multiple of 64, so a bead's lanes
-// never straddle a wave).
-template <int ST>
+// StencilLanes<W> consecutive lanes per bead (blockDim a multiple of 64).
+template <int ST, int W>
 __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
+    constexpr int LANES = StencilLanes<W>::value;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = t >> 3, q = t & 7;
+    const int b = t / LANES, q = t % LANES;
     const bool live = b < a.n;
     const Geom &g = a.geo;
     double ub[3] = {0.0, 0.0, 0.0};
     uint32_t node = 0;
     double wq = 0.0;
     if (live) {
-        const uint32_t L[3] = {g.nx, g.ny, g.nz};
-        uint32_t cpos[3];
-        double frac[3];
-        for (int c = 0; c < 3; ++c) {
-            const double r = a.half[3 * b + c];
-            const double f = floor(r);
-            frac[c] = r - f;
-            const double w = f - (double)L[c] * floor(f / (double)L[c]);  // f mod L in [0, L)
-            uint32_t wi = (uint32_t)w;
-            if (wi >= L[c]) wi = 0;
-            const uint32_t bit = (q >> c) & 1;
-            cpos[c] = (wi + bit) % L[c];
-            frac[c] = bit ? frac[c] : 1.0 - frac[c];
-        }
-        node = cpos[0] + g.nx * (cpos[1] + g.ny * cpos[2]);
-        wq = frac[0] * frac[1] * frac[2];
-        uint32_t xx, yy, zz;
-        const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
-        const T *pop = static_cast<const T *>(a.pop);
-        double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+        const double R[3] = {a.half[3 * b], a.half[3 * b + 1], a.half[3 * b + 2]};
+        stencil_node<W>(R, q, g, node, wq, nullptr);
+        if (q < W * W * W) {
+            uint32_t xx, yy, zz;
+            const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
+            const T *pop = static_cast<const T *>(a.pop);
+            double m = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
-            m += v;
-            j[0] += v * kCX[i];
-            j[1] += v * kCY[i];
-            j[2] += v * kCZ[i];
+            for (int i = 0; i < Q; ++i) {
+                const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
+                m += v;
+                j[0] += v * kCX[i];
+                j[1] += v * kCY[i];
+                j[2] += v * kCZ[i];
+            }
+            const double rho = a.rho0 + m;
+            for (int c = 0; c < 3; ++c) ub[c] = wq * (j[c] + 0.5 * a.g[c]) / rho;
         }
-        const double rho = a.rho0 + m;
-        for (int c = 0; c < 3; ++c) ub[c] = wq * (j[c] + 0.5 * a.g[c]) / rho;
     }
-    // sum the 8 node contributions of the bead (lanes q = 0..7 of one group)
+    // sum the node contributions of the bead (its LANES lanes)
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ub[c] += __shfl_xor(ub[c], off, 64);
+    for (int c = 0; c < 3; ++c) ub[c] = bead_sum<LANES>(ub[c]);
     if (!live) return;
     const double m = a.mass[b], z = a.zeta[b], h = 1.0;
     double C1, C2, C3;

@@ -256,6 +256,18 @@ void by_storage(int st, F &&fn)
     }
 }
 
+// Dispatch on the interpolation kernel width: F(integral_constant<int, W>) for
+// W in {2, 3, 4} (0 selects 2).
+template <typename F>
+void by_stencil(int w, F &&fn)
+{
+    switch (w) {
+    case 3: fn(std::integral_constant<int, 3>{}); break;
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    default: fn(std::integral_constant<int, 2>{}); break;
+    }
+}
+
 // Storage template of the step kernels: the storage type, or 4 / 5 for BF16 /
 // FP16 stores with stochastic rounding.  Every other kernel only loads or
 // converts once and uses the plain storage type.
@@ -313,10 +325,10 @@ int ensure_bead_buffers(lb_ctx *c, int n)
         const int cap = n < 64 ? 64 : n;
         if (hipMalloc(&c->half, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->fc, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->list, 8 * (size_t)cap * sizeof(int32_t)) != hipSuccess)
+            hipMalloc(&c->list, 64 * (size_t)cap * sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead scratch allocation failed");
         c->bead_cap = cap;
-        c->list_cap = 8 * cap;
+        c->list_cap = 64 * cap;
     }
     return LB_OK;
 }
@@ -368,6 +380,7 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, d
     a.mom = mom;
     a.mass = b->mass;
     a.zeta = b->zeta;
+    a.fext = b->fext;
     a.half = c->half;
     a.fc = c->fc;
     a.force = c->force;
@@ -380,8 +393,12 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, d
         hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
                            b->bonds, b->nbonds, b->k_bond, b->r0, b->n);
     by_storage(c->p.storage, [&](auto st) {
-        hipLaunchKernelGGL((k_bead_update<decltype(st)::value>), dim3(grid_for(8 * (size_t)b->n, 256)), dim3(256), 0,
-                           c->stream, a);
+        constexpr int ST = decltype(st)::value;
+        by_stencil(b->stencil, [&](auto w) {
+            constexpr int W = decltype(w)::value;
+            hipLaunchKernelGGL((k_bead_update<ST, W>), dim3(grid_for(StencilLanes<W>::value * (size_t)b->n, 256)),
+                               dim3(256), 0, c->stream, a);
+        });
     });
 }
 
@@ -993,6 +1010,9 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     if (!b->pos || !b->mom || !b->mass || !b->zeta || (b->nbonds > 0 && !b->bonds))
         return fail(c, LB_EINVAL, "bead arrays must be non-NULL");
     if (!std::isfinite(b->k_bond) || !std::isfinite(b->r0)) return fail(c, LB_EINVAL, "bond parameters must be finite");
+    if (b->stencil != 0 && b->stencil != 2 && b->stencil != 3 && b->stencil != 4)
+        return fail(c, LB_EINVAL, "stencil must be 0, 2, 3 or 4");
+    if (b->reserved != 0) return fail(c, LB_EINVAL, "lb_beads.reserved must be 0");
     LB_TRY(use_device(c));
     LB_TRY(ensure_bead_buffers(c, b->n));
     c->pending_slot = -1;
@@ -1000,7 +1020,8 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     launch_couple(c, c->bufA, b, b->pos, b->mom, (uint32_t)c->step);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
-    c->pending_rows = 8 * b->n;
+    const int W = (b->stencil == 3 || b->stencil == 4) ? b->stencil : 2;
+    c->pending_rows = W * W * W * b->n;
     return LB_OK;
 }
 
@@ -1249,8 +1270,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         launch_couple(c, pop, &c->tape_beads[slot], pos_w, mom_w, step);
     };
     auto clear_force = [&]() {
-        hipLaunchKernelGGL(k_clear_touched_adj, dim3(grid_for(8 * (size_t)nbd, 256)), dim3(256), 0, c->stream,
-                           c->force, c->fbar, c->fmask, c->list, c->count, 8 * nbd, c->geo.N);
+        hipLaunchKernelGGL(k_clear_touched_adj, dim3(grid_for(64 * (size_t)nbd, 256)), dim3(256), 0, c->stream,
+                           c->force, c->fbar, c->fmask, c->list, c->count, 64 * nbd, c->geo.N);
     };
 
     const unsigned saved_blocks = c->nblocks;
@@ -1340,8 +1361,13 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 ba.lam = c->lamB;
                 ba.gbar = c->gbar_d;
                 by_storage(c->p.storage, [&](auto st) {
-                    hipLaunchKernelGGL((k_bead_adjoint<decltype(st)::value>), dim3(grid_for(8 * (size_t)nbd, 256)),
-                                       dim3(256), 0, c->stream, ba);
+                    constexpr int ST = decltype(st)::value;
+                    by_stencil(bc.stencil, [&](auto w) {
+                        constexpr int W = decltype(w)::value;
+                        hipLaunchKernelGGL((k_bead_adjoint<ST, W>),
+                                           dim3(grid_for(StencilLanes<W>::value * (size_t)nbd, 256)), dim3(256), 0,
+                                           c->stream, ba);
+                    });
                 });
                 if (bc.nbonds > 0)
                     hipLaunchKernelGGL(k_bonds_adjoint, dim3(grid_for((size_t)bc.nbonds, 256)), dim3(256), 0, c->stream,

@@ -26,7 +26,7 @@ import numpy as np
 import torch
 
 from .inputs import shear_wave
-from .lattice import BatchLattice, FluidParams, Lattice
+from .lattice import BatchLattice, DeviceBeads, FluidParams, Lattice
 
 W_K = np.array([1, 1 / 3, 1 / 3, 1 / 3, 2 / 3, 4 / 3, 4 / 9, 1 / 9, 1 / 9, 1 / 9, 2 / 3, 2 / 3, 2 / 3, 2 / 9, 2 / 9, 2 / 9,
                 2, 4 / 3, 4 / 9])
@@ -155,3 +155,45 @@ def batch_study(nbox: int = 512, steps: int = 500, kT: float = 1e-4, lags: int =
     return {"sites": int(sum(d[0] * d[1] * d[2] for d in dims)), "ms_per_step": ms,
             "mlups": sum(d[0] * d[1] * d[2] for d in dims) / (ms * 1e-3) / 1e6, "launch": cfg, "samples": ns,
             "vacf_by_edge": by_L}
+
+
+def settling_study(L: int = 16, steps: int = 2500, a0: float = 1.0, force: float = 1e-4, stencils=(2, 3, 4)):
+    """Grid dependence of a point particle's mobility (Sec. "Interpolating
+    functions", the settling experiment): one bead of input radius a0 (bare
+    friction Gamma = 6 pi eta a0, eta = 1/6 at gamma = 0) held at the
+    positions (i, j, k)/10 + 3 (0 <= i <= j <= k <= 5, 56 positions) of an
+    L^3 periodic box at kT = 0 under an external force F along x, with the
+    compensating uniform force density -F/L^3 on the fluid so that the net
+    force is zero.  After `steps` coupled steps (position reset every step,
+    momentum kept) the steady velocity U = P/m gives 1/a = 6 pi eta U/F and
+    the kernel's radius parameter g from eq. aeffcorr,
+    1/(g b) = 1/a + 2.84/L - 1/a0 (b = 1).  Returns, per kernel width, the
+    mobilities, the g values and the largest relative deviation of g from
+    its mean over the positions."""
+    eta = 1.0 / 6.0
+    zeta = 6.0 * math.pi * eta * a0
+    out = {}
+    positions = [(i, j, k) for k in range(6) for j in range(k + 1) for i in range(j + 1)]
+    for W in stencils:
+        mob = []
+        for i, j, k in positions:
+            R0 = torch.tensor([[3 + i / 10, 3 + j / 10, 3 + k / 10]], dtype=torch.float64, device="cuda")
+            p = FluidParams(nx=L, ny=L, nz=L, body_force=(-force / L ** 3, 0.0, 0.0), track_totals=False)
+            lat = Lattice(p)
+            lat.init_equilibrium()
+            b = DeviceBeads(R0.cpu().numpy(), np.zeros((1, 3)), np.ones(1), np.full(1, zeta), stencil=W,
+                            fext=np.array([[force, 0.0, 0.0]]))
+            for _ in range(steps):
+                lat.coupled_step(b)
+                b.pos.copy_(R0)
+            torch.cuda.synchronize()
+            mob.append(float(b.mom[0, 0]) / force)
+            lat.close()
+        mob = np.array(mob)
+        inv_a = 6.0 * math.pi * eta * mob
+        g = 1.0 / (inv_a + 2.84 / L - 1.0 / a0)
+        out[W] = {"mobility": mob.tolist(), "g": g.tolist(), "g_mean": float(g.mean()),
+                  "g_max_dev": float(np.abs(g / g.mean() - 1).max()),
+                  "mobility_spread": float((mob.max() - mob.min()) / mob.mean())}
+    return out
+

@@ -90,8 +90,15 @@ class FluidParams:
 class DeviceBeads:
     """Bead state on the device (float64 tensors, positions unwrapped)."""
 
-    def __init__(self, pos, mom, mass, zeta, bonds=None, k_bond=0.0, r0=1.0, device="cuda"):
+    def __init__(self, pos, mom, mass, zeta, bonds=None, k_bond=0.0, r0=1.0, device="cuda", stencil: int = 2,
+                 fext=None):
+        """stencil: points per axis of the interpolation kernel (2, 3, 4 for
+        phi_2, phi_3, phi_4); fext: optional [n, 3] external force per bead."""
         dev = torch.device(device)
+        self.stencil = int(stencil)
+        self.fext = None if fext is None else torch.as_tensor(fext, dtype=torch.float64, device=dev).reshape(-1, 3)
+        if self.fext is not None:
+            self.fext = self.fext.contiguous()
         self.pos = torch.as_tensor(pos, dtype=torch.float64, device=dev).reshape(-1, 3).contiguous()
         self.mom = torch.as_tensor(mom, dtype=torch.float64, device=dev).reshape(-1, 3).contiguous()
         self.mass = torch.as_tensor(mass, dtype=torch.float64, device=dev).reshape(-1).contiguous()
@@ -120,6 +127,9 @@ class DeviceBeads:
         b.bonds = self.bonds.data_ptr() if self.bonds.numel() else None
         b.k_bond = self.k_bond
         b.r0 = self.r0
+        b.fext = self.fext.data_ptr() if self.fext is not None else None
+        b.stencil = self.stencil
+        b.reserved = 0
         return b
 
 
