@@ -65,8 +65,9 @@ class OrcBeadset(ctypes.Structure):
         ("mass", ctypes.POINTER(ctypes.c_double)), ("zeta", ctypes.POINTER(ctypes.c_double)),
         ("bonds", ctypes.POINTER(ctypes.c_int32)),
         ("kbond", ctypes.c_double), ("r0", ctypes.c_double),
-        ("stencil", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("stencil", ctypes.c_int32), ("fene", ctypes.c_int32),
         ("fext", ctypes.POINTER(ctypes.c_double)),
+        ("wca_eps", ctypes.c_double), ("wca_sigma", ctypes.c_double),
     ]
 
 @dataclass
@@ -143,6 +144,7 @@ def lib():
         L.orc_stencil_w.argtypes = [pp, dp, ctypes.c_int32, lp, dp, dp]
         L.orc_stencil_w.restype = ctypes.c_int
         L.orc_phi.argtypes = [ctypes.c_int32, ctypes.c_double, dp]
+        L.orc_bead_forces.argtypes = [pp, ctypes.POINTER(OrcBeadset), dp, dp]
         L.orc_collide_site_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         L.orc_step_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_uint32, dp]
         L.orc_backward.argtypes = [pp, dp, ctypes.c_int32, ctypes.c_uint32, dp, dp]
@@ -157,7 +159,7 @@ def lib():
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
                      "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step",
                      "orc_collide_site_adjoint", "orc_step_adjoint", "orc_backward", "orc_couple_adjoint",
-                     "orc_backward_coupled", "orc_phi"):
+                     "orc_backward_coupled", "orc_phi", "orc_bead_forces"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -316,11 +318,14 @@ class Beads:
     r0: float = 1.0
     stencil: int = 2                 # points per axis of the interpolation kernel: 2, 3 or 4
     fext: np.ndarray | None = None   # [nb, 3] external force per bead
+    fene: bool = False               # FENE bonds (k_bond = k, r0 = R0) instead of harmonic
+    wca_eps: float = 0.0             # WCA interaction strength (0: off)
+    wca_sigma: float = 1.0
 
     def copy(self) -> "Beads":
         return Beads(self.pos.copy(), self.mom.copy(), self.mass.copy(), self.zeta.copy(),
                      self.bonds.copy(), self.k_bond, self.r0, self.stencil,
-                     None if self.fext is None else self.fext.copy())
+                     None if self.fext is None else self.fext.copy(), self.fene, self.wca_eps, self.wca_sigma)
 
     def c(self):
         """ctypes bead-set descriptor (and the arrays it points to)."""
@@ -336,7 +341,10 @@ class Beads:
         b.kbond = float(self.k_bond)
         b.r0 = float(self.r0)
         b.stencil = int(self.stencil)
+        b.fene = 1 if self.fene else 0
         b.fext = _dp(keep[3]) if keep[3] is not None else None
+        b.wca_eps = float(self.wca_eps)
+        b.wca_sigma = float(self.wca_sigma)
         return b, keep
 
 
@@ -365,6 +373,15 @@ def stencil_w(p: Params, R, W: int):
     q = lib().orc_stencil_w(ctypes.byref(pc), _dp(_f64(R)), int(W), node.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                             _dp(w), _dp(dw))
     return node[:q], w[:q], dw[:3 * q].reshape(q, 3)
+
+
+def bead_forces(p: Params, beads: Beads, R: np.ndarray) -> np.ndarray:
+    """Conservative forces [nb, 3] (bonds, WCA, external) at positions R."""
+    bs, keep = beads.c()
+    out = np.zeros((beads.pos.shape[0], 3))
+    pc = p.c()
+    lib().orc_bead_forces(ctypes.byref(pc), ctypes.byref(bs), _dp(_f64(R)), _dp(out))
+    return out
 
 
 def phi(W: int, r: float):

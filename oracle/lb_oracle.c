@@ -611,27 +611,49 @@ void orc_phi(int32_t W, double r, double out[2])
     out[1] = dphi_w(W, r);
 }
 
-/* Bead set of the particle half: masses, frictions, harmonic bonds
- * F = -k (|d| - r0) d/|d| (pairs (a,b), d = R_b - R_a), the interpolation
- * kernel's width and an optional external force per bead (added to the
- * conservative force, constant in time). */
+/* Bead set of the particle half: masses, frictions, bonds (pairs (a,b),
+ * d = R_b - R_a) that are either harmonic, V = (k/2)(|d| - r0)^2, or FENE
+ * (eq. ufene), V = -(k/2) R0^2 ln(1 - |d|^2/R0^2) with R0 = r0; the purely
+ * repulsive Lennard-Jones (WCA) interaction of eq. ulennardjones between all
+ * pairs (off when wca_eps = 0); the interpolation kernel's width and an
+ * optional external force per bead (added to the conservative force,
+ * constant in time). */
 typedef struct {
     int32_t n, nbonds;
     const double *mass, *zeta;
     const int32_t *bonds;
     double kbond, r0;
     int32_t stencil;      /* 2, 3 or 4: phi_2 (8 nodes), phi_3 (27), phi_4 (64) */
-    int32_t pad;
+    int32_t fene;         /* 0: harmonic bonds, 1: FENE bonds */
     const double *fext;   /* [n][3] or NULL */
+    double wca_eps, wca_sigma;
 } orc_beadset;
 
 static int bs_width(const orc_beadset *bs) { return (bs->stencil == 3 || bs->stencil == 4) ? bs->stencil : 2; }
 
-/* Half-step positions R' = R + (h/2) P/m and conservative forces at R'
- * (bonds plus the external force). */
-static void half_and_forces(const orc_beadset *bs, const double *pos, const double *mom, double *half, double *fc)
+/* WCA force on bead j from bead i, F_j = -dV/dR_j for eq. ulennardjones:
+ * d = R_j - R_i (minimum image), f(r) d with f = 24 eps (2 (s/r)^12 - (s/r)^6)
+ * / r^2 below the cutoff 2^(1/6) s, zero above. */
+static double wca_factor(double eps, double sigma, double r2)
+{
+    const double rc2 = pow(2.0, 1.0 / 3.0) * sigma * sigma;
+    if (r2 >= rc2) return 0.0;
+    const double s6 = pow(sigma * sigma / r2, 3.0);
+    return 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
+}
+
+/* Minimum-image difference along one periodic axis of length L. */
+static double min_image(double d, double L) { return d - L * floor(d / L + 0.5); }
+
+/* Half-step positions R' = R + (h/2) P/m and conservative forces at R':
+ * bonds (harmonic or FENE), WCA between all pairs (minimum image in the
+ * periodic box), plus the external force.  A FENE bond stretched to
+ * |d| >= R0 has no finite force (NaN). */
+static void half_and_forces(const orc_params *p, const orc_beadset *bs, const double *pos, const double *mom,
+                            double *half, double *fc)
 {
     const double h = 1.0;
+    const double Lb[3] = {(double)p->nx, (double)p->ny, (double)p->nz};
     for (int b = 0; b < bs->n; ++b)
         for (int a = 0; a < 3; ++a) {
             half[3 * b + a] = pos[3 * b + a] + 0.5 * h * mom[3 * b + a] / bs->mass[b];
@@ -644,14 +666,47 @@ static void half_and_forces(const orc_beadset *bs, const double *pos, const doub
             d[a] = half[3 * ib + a] - half[3 * ia + a];
             r2 += d[a] * d[a];
         }
-        const double r = sqrt(r2);
-        if (r == 0.0) continue;
-        const double mag = -bs->kbond * (r - bs->r0) / r;
+        double mag;
+        if (bs->fene) {
+            const double R02 = bs->r0 * bs->r0;
+            mag = r2 < R02 ? -bs->kbond / (1.0 - r2 / R02) : NAN;
+        } else {
+            const double r = sqrt(r2);
+            if (r == 0.0) continue;
+            mag = -bs->kbond * (r - bs->r0) / r;
+        }
         for (int a = 0; a < 3; ++a) {
             fc[3 * ib + a] += mag * d[a];
             fc[3 * ia + a] -= mag * d[a];
         }
     }
+    if (bs->wca_eps > 0.0)
+        for (int i = 0; i < bs->n; ++i)
+            for (int j = i + 1; j < bs->n; ++j) {
+                double d[3], r2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = min_image(half[3 * j + a] - half[3 * i + a], Lb[a]);
+                    r2 += d[a] * d[a];
+                }
+                const double f = wca_factor(bs->wca_eps, bs->wca_sigma, r2);
+                if (f == 0.0) continue;
+                for (int a = 0; a < 3; ++a) {
+                    fc[3 * j + a] += f * d[a];
+                    fc[3 * i + a] -= f * d[a];
+                }
+            }
+}
+
+/* Conservative forces (bonds, WCA, external) at given positions, for the
+ * pins of the interaction potentials. */
+void orc_bead_forces(const orc_params *p, const orc_beadset *bs, const double *R, double *fc)
+{
+    const size_t nb3 = 3 * (size_t)(bs->n > 0 ? bs->n : 1);
+    double *zero = (double *)calloc(nb3, sizeof(double));
+    double *half = (double *)malloc(sizeof(double) * nb3);
+    half_and_forces(p, bs, R, zero, half, fc);
+    free(zero);
+    free(half);
 }
 
 /* Momentum-update constants of eq. langevin_momentum_update. */
@@ -710,7 +765,7 @@ void orc_couple(const orc_params *p, const double *n, uint32_t step, const orc_b
     const size_t nb3 = 3 * (size_t)(nb > 0 ? nb : 1);
     double *half = (double *)malloc(sizeof(double) * nb3);
     double *fc = (double *)malloc(sizeof(double) * nb3);
-    half_and_forces(bs, pos, mom, half, fc);
+    half_and_forces(p, bs, pos, mom, half, fc);
     for (int b = 0; b < nb; ++b) {
         int64_t node[64];
         double wgt[64];
@@ -949,8 +1004,9 @@ void orc_backward(const orc_params *p, const double *n0, int32_t nsteps, uint32_
  * u_b = sum Delta u(node), the bond forces F^c(R') and the half drift
  * R' = R + (h/2) P/m.  The weights are differentiated with the kernels'
  * derivatives (phi_2: where R' is off the node planes).  The external force
- * is constant and has no adjoint.  Parity pinned by central finite
- * differences of the coupled forward map. */
+ * is constant and has no adjoint.  Only harmonic bonds are differentiated:
+ * with FENE bonds or the WCA interaction the bead adjoints come back NaN.
+ * Parity pinned by central finite differences of the coupled forward map. */
 void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, const orc_beadset *bs,
                         const double *pos, const double *mom, const double *force_bar, double *pos_bar,
                         double *mom_bar, double *lam, double gbar[3])
@@ -960,13 +1016,18 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const double h = 1.0;
     const int nb = bs->n, W = bs_width(bs);
+    if (bs->fene || bs->wca_eps > 0.0) {
+        /* only harmonic bonds are differentiated */
+        for (int k = 0; k < 3 * nb; ++k) pos_bar[k] = mom_bar[k] = NAN;
+        return;
+    }
     const size_t nb3 = 3 * (size_t)(nb > 0 ? nb : 1);
     double *half = (double *)malloc(sizeof(double) * nb3);
     double *fc = (double *)malloc(sizeof(double) * nb3);
     double *half_bar = (double *)calloc(nb3, sizeof(double));
     double *fc_bar = (double *)calloc(nb3, sizeof(double));
     double *p_bar = (double *)calloc(nb3, sizeof(double));
-    half_and_forces(bs, pos, mom, half, fc);
+    half_and_forces(p, bs, pos, mom, half, fc);
 
     for (int b = 0; b < nb; ++b) {
         const double m = bs->mass[b], z = bs->zeta[b];

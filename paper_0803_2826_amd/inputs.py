@@ -54,3 +54,46 @@ def random_walk_chains(n_chains: int, length: int, box, seed: int):
 def uniform_beads(n: int, box, seed: int):
     rng = np.random.default_rng(seed)
     return rng.uniform(0.0, 1.0, size=(n, 3)) * np.asarray(box, dtype=float)
+
+
+def kremer_grest_chains(n_chains: int, length: int, box, seed: int, bond: float = 0.97, min_dist: float = 0.95,
+                        max_tries: int = 200):
+    """Self-avoiding random-walk chains for the bead-spring (Kremer-Grest)
+    model: starts uniform in the box, consecutive beads `bond` apart in
+    isotropic random directions, every new bead at least `min_dist` (minimum
+    image) from all beads placed so far.  Returns pos [n, 3] (unwrapped),
+    mom (zeros), bonds [n_chains*(length-1), 2] (int32)."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=float)
+    pos = np.zeros((n_chains * length, 3))
+    count = 0
+
+    def free(x):
+        if count == 0:
+            return True
+        d = pos[:count] - x
+        d -= L * np.round(d / L)
+        return (d * d).sum(1).min() >= min_dist * min_dist
+
+    for c in range(n_chains):
+        for _ in range(max_tries):
+            start = rng.uniform(0.0, 1.0, size=3) * L
+            if free(start):
+                break
+        else:
+            raise RuntimeError("no room for a new chain")
+        pos[count] = start
+        count += 1
+        for k in range(1, length):
+            for _ in range(max_tries):
+                step = rng.normal(size=3)
+                x = pos[count - 1] + bond * step / np.linalg.norm(step)
+                if free(x):
+                    break
+            else:
+                raise RuntimeError("chain growth is stuck")
+            pos[count] = x
+            count += 1
+    bonds = np.array([(c * length + k, c * length + k + 1) for c in range(n_chains) for k in range(length - 1)],
+                     dtype=np.int32).reshape(-1, 2)
+    return pos, np.zeros_like(pos), bonds
