@@ -129,13 +129,25 @@ typedef struct {
     int32_t walls;         /* 1: stationary walls at z = -1/2 and z = nz - 1/2 (single box only) */
 } lb_params;
 
-/* Point particles with harmonic bonds (Sec. "Force coupling").
- * All arrays are device FP64 (bonds int32), caller-owned:
+/* Bond potential of lb_beads.bonds, with d the bond vector and r = |d|:
+ * LB_BOND_HARMONIC: (k_bond/2)(r - r0)^2;
+ * LB_BOND_FENE: -(k_bond/2) r0^2 ln(1 - r^2/r0^2) for r < r0 (eq. ufene,
+ *   r0 = R_0 the maximum extension).  A bond at r >= r0 has no finite
+ *   force: the step gives its beads' momenta a NaN, spreads their NaN
+ *   impulse to the fluid at their stencil nodes (the oracle does the same)
+ *   and latches a device flag that the next synchronising call reports as
+ *   LB_ENONFINITE. */
+typedef enum { LB_BOND_HARMONIC = 0, LB_BOND_FENE = 1 } lb_bond;
+
+/* Point particles with bonds and an optional purely repulsive pair
+ * potential (Sec. "Force coupling"; the Kremer-Grest bead-spring model of
+ * Sec. "Coarse-grained models").  All arrays are device FP64 (bonds int32), caller-owned:
  *   pos  [n][3]  unwrapped positions (in/out)
  *   mom  [n][3]  momenta p (in/out)
  *   mass [n]     m_i > 0
  *   zeta [n]     friction Gamma_i >= 0 (eq. fdrag)
- *   bonds [nbonds][2]  bead index pairs, potential (k_bond/2)(|d| - r0)^2
+ *   bonds [nbonds][2]  bead index pairs with the potential `bond` (lb_bond)
+ *                of parameters k_bond, r0
  *   fext [n][3]  external force on each bead, added to the conservative force
  *                (constant over the call; its reaction is not given to the
  *                fluid), or NULL
@@ -143,7 +155,15 @@ typedef struct {
  *                "Interpolating functions"): 2 = phi_2 (eq. 2point, 8 nodes;
  *                also selected by 0), 3 = phi_3 (eq. 3point, 27 nodes),
  *                4 = phi_4 (eq. 4point, 64 nodes); the kernel is used for
- *                both the interpolation and the spreading. */
+ *                both the interpolation and the spreading
+ *   wca_epsilon, wca_sigma  the Lennard-Jones potential of eq. ulennardjones
+ *                cut and shifted at its minimum r_c = 2^(1/6) sigma (purely
+ *                repulsive) between every pair of beads, bonded or not, at
+ *                their periodic minimum-image distance; wca_epsilon = 0
+ *                switches it off.  Pairs are found with a cell list of cells
+ *                no narrower than r_c, rebuilt every call; r_c must be below
+ *                half of every box extent, and the periodic box has no walls.
+ * Units are lattice units (spacing a = 1, time step h = 1). */
 typedef struct {
     int32_t n;
     int32_t nbonds;
@@ -156,7 +176,9 @@ typedef struct {
     double r0;
     const double *fext;
     int32_t stencil;
-    int32_t reserved;  /* must be 0 */
+    int32_t bond;      /* lb_bond */
+    double wca_epsilon;
+    double wca_sigma;
 } lb_beads;
 
 typedef struct lb_ctx lb_ctx;
@@ -241,16 +263,19 @@ int lb_get_populations(lb_ctx *ctx, void *dst, int32_t dtype, int32_t shifted);
  * only; the counter increases by nsteps. */
 int lb_step(lb_ctx *ctx, int32_t nsteps);
 
-/* Particle half of one coupled time step (Sec. "Force coupling": half
- * drift, harmonic bond forces at the half-step positions, trilinear
- * interpolation of u (eq. ufluid_discrete with the two-point kernel of
- * eq. 2point), the exact Langevin momentum update
- * eq. langevin_momentum_update, spreading of the exchanged impulse to the
- * 8 surrounding nodes (eq. ftotal), second half drift).  The interpolated
- * velocity is u = (sum_i n_i c_i + g/2)/rho from the current state.  The
- * spread force is applied by the next lb_step.  Bead noise is keyed by
- * (bead index, step counter).  Errors: LB_EINVAL (n < 0, NULL arrays with
- * n > 0), LB_ESTATE (a previous lb_couple's force not yet consumed). */
+/* Particle half of one coupled time step (Sec. "Force coupling"): half
+ * drift; conservative forces at the half-step positions (bonds, WCA pairs,
+ * fext); interpolation of u at each bead with the stencil's kernel
+ * (eq. ufluid_discrete; trilinear for phi_2, eq. 2point); the exact Langevin
+ * momentum update eq. langevin_momentum_update; spreading of the exchanged
+ * impulse over the same stencil nodes (eq. ftotal); second half drift.  The
+ * interpolated velocity is u = (sum_i n_i c_i + g/2)/rho from the current
+ * state.  The spread force is applied by the next lb_step.  Bead noise is
+ * keyed by (bead index, step counter).  Errors: LB_EINVAL (n < 0, NULL
+ * arrays with n > 0, unknown stencil or bond kind, non-finite or negative
+ * bond or WCA parameters, r_c >= half a box extent), LB_EUNSUPPORTED (WCA
+ * with walls; FENE or WCA while a tape is recording), LB_ESTATE (a previous
+ * lb_couple's force not yet consumed). */
 int lb_couple(lb_ctx *ctx, const lb_beads *beads);
 
 /* Density and velocity of the current state: rho = sum_i n_i,
@@ -304,8 +329,8 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * reverse sweep a coupled step rebuilds its spread force from the stored
  * bead state, the fluid adjoint also yields the adjoint of the bead force at
  * the touched nodes, and the adjoint of the particle half (half drift,
- * harmonic bonds, trilinear interpolation with the weights differentiated in
- * R, the momentum update eq. langevin_momentum_update with its noise
+ * harmonic bonds, the interpolation with the stencil weights differentiated
+ * in R, the momentum update eq. langevin_momentum_update with its noise
  * replayed, the spread reaction eq. ftotal) carries the bead adjoints back
  * and adds the interpolation's share to dL/dn and dL/dg.
  * lb_backward_coupled takes and returns the bead adjoints as well:

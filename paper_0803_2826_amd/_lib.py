@@ -36,6 +36,7 @@ EXPORTS = (
 
 
 LB_ROUND_NEAREST, LB_ROUND_STOCHASTIC = 0, 1
+LB_BOND_HARMONIC, LB_BOND_FENE = 0, 1
 
 
 class lb_params(ctypes.Structure):
@@ -68,7 +69,8 @@ class lb_beads(ctypes.Structure):
         ("bonds", ctypes.c_void_p),
         ("k_bond", ctypes.c_double), ("r0", ctypes.c_double),
         ("fext", ctypes.c_void_p),
-        ("stencil", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("stencil", ctypes.c_int32), ("bond", ctypes.c_int32),
+        ("wca_epsilon", ctypes.c_double), ("wca_sigma", ctypes.c_double),
     ]
 
 

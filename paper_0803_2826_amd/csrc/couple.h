@@ -3,10 +3,13 @@
 // gathered from the stored populations.
 //
 // One coupled step on the device:
-//   k_bead_half     R' = R + (h/2) P/m; the conservative force starts from the
-//                   external bead force (or zero); reset the touched-node count
-//   k_bonds         harmonic bond forces at R' (FP64 atomics; a bead with at
-//                   most two bonds gets a bitwise reproducible sum)
+//   k_bead_half     R' = R + (h/2) P/m; zero the conservative force; reset
+//                   the touched-node count
+//   k_bonds         harmonic or FENE bond forces at R' (FP64 atomics into
+//                   zeros: a bead with at most two bonds gets the same bits on
+//                   every run)
+//   k_cell_* k_wca  WCA pair forces at R' with a cell list (pairs.h), when on
+//   k_add_fext      the external bead force, when given
 //   k_bead_update   one lane per stencil node (W^3 of them, W = 2, 3, 4 for the
 //                   kernels phi_2, phi_3, phi_4 of eq. 2point, eq. 3point,
 //                   eq. 4point): each lane gathers its node's 19 populations
@@ -22,6 +25,7 @@
 #pragma once
 
 #include "aux_kernels.h"
+#include "pairs.h"
 
 namespace lbmi {
 
@@ -37,7 +41,6 @@ struct CoupleArgs {
     double *mom;
     const double *mass;
     const double *zeta;
-    const double *fext;   // [n][3] external bead force or NULL
     double *half;         // [n][3]
     double *fc;           // [n][3]
     float *force;         // [3][N] sparse force field (zero outside touched nodes)
@@ -54,8 +57,15 @@ __global__ void k_bead_half(CoupleArgs a)
     const double m = a.mass[b];
     for (int c = 0; c < 3; ++c) {
         a.half[3 * b + c] = a.pos[3 * b + c] + 0.5 * a.mom[3 * b + c] / m;
-        a.fc[3 * b + c] = a.fext ? a.fext[3 * b + c] : 0.0;
+        a.fc[3 * b + c] = 0.0;
     }
+}
+
+// Last term of the conservative force: F^c = (bonds + pairs) + fext.
+__global__ void k_add_fext(int n, const double *__restrict__ fext, double *fc)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < 3 * n) fc[k] += fext[k];
 }
 
 // Interpolation kernels phi_W (eq. 2point, eq. 3point, eq. 4point) and their
@@ -114,8 +124,8 @@ __device__ __forceinline__ void stencil_node(const double R[3], int q, const Geo
         const double first = (W == 3) ? floor(R[c] + 0.5) - 1.0 : ((W == 4) ? floor(R[c]) - 1.0 : floor(R[c]));
         const double xc = first + (double)d[c];
         const double m = xc - (double)L[c] * floor(xc / (double)L[c]);  // xc mod L in [0, L)
-        uint32_t wi = (uint32_t)m;
-        if (wi >= L[c]) wi = 0;
+        // a non-finite position (a bead given a NaN) maps to node 0
+        uint32_t wi = (m >= 0.0 && m < (double)L[c]) ? (uint32_t)m : 0u;
         cpos[c] = wi;
         f[c] = phi_kernel<W>(R[c] - xc);
         df[c] = dw ? dphi_kernel<W>(R[c] - xc) : 0.0;
@@ -138,8 +148,11 @@ __device__ __forceinline__ double bead_sum(double v)
     return v;
 }
 
+// Bond forces at R': F_b = mag d = -F_a, d = R'_b - R'_a, with
+// mag = -k (r - r0) / r (harmonic) or mag = -k / (1 - r^2/r0^2) (FENE,
+// eq. ufene; NaN at r >= r0, latched as bit 1 of *flags).
 __global__ void k_bonds(const double *__restrict__ half, double *fc, const int32_t *__restrict__ bonds, int nbonds,
-                        double kb, double r0, int nbeads)
+                        double kb, double r0, int nbeads, int fene, int32_t *flags)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nbonds) return;
@@ -150,9 +163,20 @@ __global__ void k_bonds(const double *__restrict__ half, double *fc, const int32
         d[c] = half[3 * ib + c] - half[3 * ia + c];
         r2 += d[c] * d[c];
     }
-    const double r = sqrt(r2);
-    if (r == 0.0) return;
-    const double mag = -kb * (r - r0) / r;
+    double mag;
+    if (fene) {
+        const double x = r2 / (r0 * r0);
+        if (x < 1.0) {
+            mag = -kb / (1.0 - x);
+        } else {
+            mag = __builtin_nan("");
+            __hip_atomic_fetch_or(flags, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        const double r = sqrt(r2);
+        if (r == 0.0) return;
+        mag = -kb * (r - r0) / r;
+    }
     for (int c = 0; c < 3; ++c) {
         atomicAdd(&fc[3 * ib + c], mag * d[c]);
         atomicAdd(&fc[3 * ia + c], -mag * d[c]);

@@ -15,6 +15,8 @@
 #include <vector>
 
 #include "../../include/lb.h"
+#include <hipcub/hipcub.hpp>
+
 #include "adjoint.h"
 #include "bead_adjoint.h"
 #include "batch.h"
@@ -58,6 +60,16 @@ struct lb_ctx {
     int bead_cap = 0;
     bool pending_force = false;
     int pending_rows = 0;            // upper bound of touched nodes (8 per bead)
+    // WCA cell list (allocated on the first lb_couple with wca_epsilon > 0)
+    int32_t *cell_count = nullptr;   // [ncell + 1] counts, then (cell_start) their exclusive scan
+    int32_t *cell_start = nullptr;   // [ncell + 1]
+    size_t cell_cap = 0;             // cells allocated (plus one)
+    int32_t *bead_cell = nullptr;    // [n] cell, slot within the cell, cell-ordered bead list
+    int32_t *bead_slot = nullptr;
+    int32_t *cell_sorted = nullptr;
+    int pair_cap = 0;
+    void *scan_tmp = nullptr;        // hipcub scan workspace
+    size_t scan_tmp_bytes = 0;
     bool tuned = false;              // launch configuration chosen (autotune done or fixed)
     uint32_t xcd_remap = LBMI_XCD_REMAP;  // step kernel: consecutive tiles on one XCD (if the grid allows)
     // single box: launch configuration of the step kernel without / with a
@@ -298,6 +310,7 @@ int read_flags(lb_ctx *c)
     int32_t h = 0;
     LB_TRY(check(c, hipMemcpyAsync(&h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream), "flags copy"));
     LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    if (h & 2) return fail(c, LB_ENONFINITE, "a FENE bond was stretched to r >= r0 (bead momentum is NaN)");
     if (h & 1) return fail(c, LB_ENONFINITE, "non-finite population encountered on the device");
     return LB_OK;
 }
@@ -360,9 +373,94 @@ void free_tape(lb_ctx *c)
     c->tape_nb = 0;
 }
 
-// The particle half of one coupled step (k_bead_half, k_bonds,
-// k_bead_update) on the populations `pop`, updating (pos, mom) in place and
-// spreading into the force field, its bitmap and the touched-node list.
+// Cell grid of the WCA pair search for n beads: cells no narrower than
+// r_c, at most about 2n cells (so that rebuilding the list stays cheap for
+// dilute chains), an axis with fewer than 3 cells folded into one.
+CellGrid cell_grid(const lb_ctx *c, const lb_beads *b)
+{
+    CellGrid cg;
+    const double sig2 = b->wca_sigma * b->wca_sigma;
+    cg.rc2 = std::cbrt(2.0) * sig2;
+    cg.sig2 = sig2;
+    cg.eps24 = 24.0 * b->wca_epsilon;
+    const double rc = std::sqrt(cg.rc2);
+    const int cap = std::min(128, std::max(3, (int)std::ceil(std::cbrt(2.0 * (double)b->n))));
+    const int32_t ext[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (int a = 0; a < 3; ++a) {
+        cg.L[a] = (double)ext[a];
+        int nc = (int)std::floor(cg.L[a] / rc);
+        nc = std::min(nc, cap);
+        if (nc < 3) nc = 1;
+        cg.nc[a] = nc;
+        cg.inv_w[a] = (double)nc / cg.L[a];
+    }
+    return cg;
+}
+
+int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
+{
+    if (ncell + 1 > c->cell_cap) {
+        (void)hipFree(c->cell_count);
+        (void)hipFree(c->cell_start);
+        c->cell_count = c->cell_start = nullptr;
+        c->cell_cap = 0;
+        if (hipMalloc(&c->cell_count, (ncell + 1) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->cell_start, (ncell + 1) * sizeof(int32_t)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "cell list allocation failed");
+        c->cell_cap = ncell + 1;
+    }
+    size_t tmp = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, c->cell_count, c->cell_start, (int)(ncell + 1), c->stream) !=
+        hipSuccess)
+        return fail(c, LB_EDEVICE, "scan workspace query failed");
+    if (tmp > c->scan_tmp_bytes) {
+        (void)hipFree(c->scan_tmp);
+        c->scan_tmp = nullptr;
+        c->scan_tmp_bytes = 0;
+        if (hipMalloc(&c->scan_tmp, tmp) != hipSuccess) return fail(c, LB_ENOMEM, "scan workspace allocation failed");
+        c->scan_tmp_bytes = tmp;
+    }
+    if (n > c->pair_cap) {
+        (void)hipFree(c->bead_cell);
+        (void)hipFree(c->bead_slot);
+        (void)hipFree(c->cell_sorted);
+        c->bead_cell = c->bead_slot = c->cell_sorted = nullptr;
+        c->pair_cap = 0;
+        if (hipMalloc(&c->bead_cell, (size_t)n * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->bead_slot, (size_t)n * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->cell_sorted, (size_t)n * sizeof(int32_t)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "cell list allocation failed");
+        c->pair_cap = n;
+    }
+    return LB_OK;
+}
+
+// WCA forces at the half-step positions, added to c->fc: rebuild the cell
+// list, then one thread per bead over its neighbour cells.
+void launch_wca(lb_ctx *c, const lb_beads *b)
+{
+    const CellGrid cg = cell_grid(c, b);
+    const size_t ncell = (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2];
+    const unsigned gb = grid_for((size_t)b->n, 256);
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(ncell + 1, 256)), dim3(256), 0, c->stream, c->cell_count,
+                       (uint32_t)(ncell + 1));
+    hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(256), 0, c->stream, c->half, b->n, cg, c->bead_cell, c->bead_slot,
+                       c->cell_count);
+    size_t tmp = c->scan_tmp_bytes;
+    (void)hipcub::DeviceScan::ExclusiveSum(c->scan_tmp, tmp, c->cell_count, c->cell_start, (int)(ncell + 1),
+                                           c->stream);
+    hipLaunchKernelGGL(k_cell_fill, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->bead_slot, c->cell_start,
+                       c->cell_sorted);
+    hipLaunchKernelGGL(k_cell_order, dim3(grid_for(ncell, 256)), dim3(256), 0, c->stream, (int)ncell, c->cell_start,
+                       c->cell_sorted);
+    hipLaunchKernelGGL(k_wca, dim3(gb), dim3(256), 0, c->stream, c->half, b->n, cg, c->bead_cell, c->cell_start,
+                       c->cell_sorted, c->fc);
+}
+
+// The particle half of one coupled step (k_bead_half, k_bonds, the WCA pair
+// search, k_add_fext, k_bead_update) on the populations `pop`, updating
+// (pos, mom) in place and spreading into the force field, its bitmap and the
+// touched-node list.
 void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, double *mom, uint32_t step)
 {
     CoupleArgs a;
@@ -380,7 +478,6 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, d
     a.mom = mom;
     a.mass = b->mass;
     a.zeta = b->zeta;
-    a.fext = b->fext;
     a.half = c->half;
     a.fc = c->fc;
     a.force = c->force;
@@ -391,7 +488,11 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, d
     hipLaunchKernelGGL(k_bead_half, dim3(gb), dim3(256), 0, c->stream, a);
     if (b->nbonds > 0)
         hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
-                           b->bonds, b->nbonds, b->k_bond, b->r0, b->n);
+                           b->bonds, b->nbonds, b->k_bond, b->r0, b->n, (int)(b->bond == LB_BOND_FENE), c->flags);
+    if (b->wca_epsilon > 0.0) launch_wca(c, b);
+    if (b->fext)
+        hipLaunchKernelGGL(k_add_fext, dim3(grid_for(3 * (size_t)b->n, 256)), dim3(256), 0, c->stream, b->n, b->fext,
+                           c->fc);
     by_storage(c->p.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         by_stencil(b->stencil, [&](auto w) {
@@ -844,9 +945,10 @@ int lb_destroy(lb_ctx *c)
     if (!c) return LB_OK;
     use_device(c);
     (void)hipStreamSynchronize(c->stream);
-    void *ptrs[] = {c->bufA, c->bufB, c->partials, c->scratch, c->dev_out, c->flags, c->force, c->fmask,
-                    c->list,  c->count, c->half,     c->fc,      c->boxes_d, c->tile_box, c->dstep, c->amp,
-                    c->ring,  c->corr};
+    void *ptrs[] = {c->bufA,       c->bufB,      c->partials,  c->scratch,   c->dev_out,   c->flags,
+                    c->force,      c->fmask,     c->list,      c->count,     c->half,      c->fc,
+                    c->boxes_d,    c->tile_box,  c->dstep,     c->amp,       c->ring,      c->corr,
+                    c->cell_count, c->cell_start, c->bead_cell, c->bead_slot, c->cell_sorted, c->scan_tmp};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int k = 0; k < 2; ++k)
@@ -1012,9 +1114,28 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     if (!std::isfinite(b->k_bond) || !std::isfinite(b->r0)) return fail(c, LB_EINVAL, "bond parameters must be finite");
     if (b->stencil != 0 && b->stencil != 2 && b->stencil != 3 && b->stencil != 4)
         return fail(c, LB_EINVAL, "stencil must be 0, 2, 3 or 4");
-    if (b->reserved != 0) return fail(c, LB_EINVAL, "lb_beads.reserved must be 0");
+    if (b->bond != LB_BOND_HARMONIC && b->bond != LB_BOND_FENE) return fail(c, LB_EINVAL, "unknown bond kind");
+    if (b->bond == LB_BOND_FENE && b->nbonds > 0 && !(b->r0 > 0.0 && b->k_bond >= 0.0))
+        return fail(c, LB_EINVAL, "FENE bonds need r0 > 0 and k_bond >= 0");
+    if (!(std::isfinite(b->wca_epsilon) && b->wca_epsilon >= 0.0))
+        return fail(c, LB_EINVAL, "wca_epsilon must be finite and >= 0");
+    const bool wca = b->wca_epsilon > 0.0;
+    if (wca) {
+        if (!(std::isfinite(b->wca_sigma) && b->wca_sigma > 0.0))
+            return fail(c, LB_EINVAL, "wca_sigma must be finite and > 0");
+        const double rc = std::cbrt(std::sqrt(2.0)) * b->wca_sigma;
+        if (!(2.0 * rc < (double)std::min(c->p.nx, std::min(c->p.ny, c->p.nz))))
+            return fail(c, LB_EINVAL, "the WCA cutoff 2^(1/6) sigma must be below half of every box extent");
+        if (c->p.walls) return fail(c, LB_EUNSUPPORTED, "WCA pair forces are only available in a periodic box");
+    }
+    if (c->taping && (wca || (b->bond == LB_BOND_FENE && b->nbonds > 0)))
+        return fail(c, LB_EUNSUPPORTED, "FENE bonds and WCA pairs cannot be differentiated (tape recording)");
     LB_TRY(use_device(c));
     LB_TRY(ensure_bead_buffers(c, b->n));
+    if (wca) {
+        const CellGrid cg = cell_grid(c, b);
+        LB_TRY(ensure_pair_buffers(c, b->n, (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2]));
+    }
     c->pending_slot = -1;
     if (c->taping) LB_TRY(tape_bead_snapshot(c, b));
     launch_couple(c, c->bufA, b, b->pos, b->mom, (uint32_t)c->step);

@@ -91,11 +91,21 @@ class DeviceBeads:
     """Bead state on the device (float64 tensors, positions unwrapped)."""
 
     def __init__(self, pos, mom, mass, zeta, bonds=None, k_bond=0.0, r0=1.0, device="cuda", stencil: int = 2,
-                 fext=None):
+                 fext=None, bond: str = "harmonic", wca_epsilon: float = 0.0, wca_sigma: float = 1.0):
         """stencil: points per axis of the interpolation kernel (2, 3, 4 for
-        phi_2, phi_3, phi_4); fext: optional [n, 3] external force per bead."""
+        phi_2, phi_3, phi_4); fext: optional [n, 3] external force per bead;
+        bond: "harmonic" ((k/2)(r - r0)^2) or "fene" (-(k/2) r0^2 ln(1 - r^2/r0^2),
+        r0 the maximum extension); wca_epsilon > 0 adds the purely repulsive
+        Lennard-Jones pair force (cut at 2^(1/6) wca_sigma) between all beads."""
         dev = torch.device(device)
         self.stencil = int(stencil)
+        kinds = {"harmonic": _lib.LB_BOND_HARMONIC, "fene": _lib.LB_BOND_FENE}
+        if bond not in kinds:
+            raise ValueError(f"bond must be one of {sorted(kinds)}")
+        self.bond = bond
+        self._bond_code = kinds[bond]
+        self.wca_epsilon = float(wca_epsilon)
+        self.wca_sigma = float(wca_sigma)
         self.fext = None if fext is None else torch.as_tensor(fext, dtype=torch.float64, device=dev).reshape(-1, 3)
         if self.fext is not None:
             self.fext = self.fext.contiguous()
@@ -129,7 +139,9 @@ class DeviceBeads:
         b.r0 = self.r0
         b.fext = self.fext.data_ptr() if self.fext is not None else None
         b.stencil = self.stencil
-        b.reserved = 0
+        b.bond = self._bond_code
+        b.wca_epsilon = self.wca_epsilon
+        b.wca_sigma = self.wca_sigma
         return b
 
 

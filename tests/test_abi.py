@@ -56,7 +56,8 @@ int main(void) {
   F(lb_params, noise_rho0) F(lb_params, block) F(lb_params, track_totals) F(lb_params, box_id)
   F(lb_params, vacf_lags) F(lb_params, graph_steps) F(lb_params, rounding) F(lb_params, walls)
   F(lb_beads, pos) F(lb_beads, mom) F(lb_beads, mass) F(lb_beads, zeta) F(lb_beads, bonds)
-  F(lb_beads, k_bond) F(lb_beads, r0) F(lb_beads, fext) F(lb_beads, stencil) F(lb_beads, reserved)
+  F(lb_beads, k_bond) F(lb_beads, r0) F(lb_beads, fext) F(lb_beads, stencil) F(lb_beads, bond)
+  F(lb_beads, wca_epsilon) F(lb_beads, wca_sigma)
   return 0;
 }
 '''

@@ -1,0 +1,228 @@
+"""Kremer-Grest bead-spring chains on the GPU (Sec. "Coarse-grained models":
+the WCA pair potential of eq. ulennardjones, the FENE bond of eq. ufene),
+against the FP64 oracle's all-pairs forces.
+
+Forces are read off one coupled step with zero friction, no noise and zero
+initial momenta: then R' = R and P'' = F^c(R') exactly (eq.
+langevin_momentum_update with zeta = 0).  Both sides sum the same FP64 terms
+in different orders, so they agree to a few ulps of the largest pair term;
+the bound is 1e-12 of the largest force.  The coupled run with friction and
+noise keeps the tolerances of the other coupled parity tests (populations
+1e-6 absolute, bead state 1e-7)."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+EPS, SIG = 1e-4, 1.0
+K_FENE, R0 = 30 * EPS / SIG ** 2, 1.5 * SIG
+
+
+@pytest.fixture(scope="module")
+def lat():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_0803_2826_amd import lattice
+    return lattice
+
+
+def shifted_chains(pos, length, L, rng):
+    """Move every chain by a random whole number of box lengths per axis
+    (the bond vectors stay the same; WCA pairs see the minimum image)."""
+    pos = pos.copy()
+    for c in range(pos.shape[0] // length):
+        pos[c * length:(c + 1) * length] += np.asarray(L) * rng.integers(-2, 3, size=3)
+    return pos
+
+
+def gpu_forces(lat, dims, pos, bonds, eps=EPS, sig=SIG, bond="fene", k=K_FENE, r0=R0):
+    import torch
+    nb = pos.shape[0]
+    dev = lat.Lattice(lat.FluidParams(nx=dims[0], ny=dims[1], nz=dims[2], track_totals=False))
+    dev.init_equilibrium()
+    db = lat.DeviceBeads(pos, np.zeros((nb, 3)), np.ones(nb), np.zeros(nb), bonds, k, r0, bond=bond,
+                         wca_epsilon=eps, wca_sigma=sig)
+    dev.couple(db)
+    dev.sync()
+    F = db.mom.cpu().numpy()
+    R = db.pos.cpu().numpy()
+    dev.step(1)
+    dev.close()
+    torch.cuda.synchronize()
+    return F, R
+
+
+def oracle_forces(orc, dims, pos, bonds, eps=EPS, sig=SIG, fene=True, k=K_FENE, r0=R0):
+    p = orc.Params(nx=dims[0], ny=dims[1], nz=dims[2])
+    nb = pos.shape[0]
+    b = orc.Beads(pos.copy(), np.zeros((nb, 3)), np.ones(nb), np.zeros(nb), bonds, k, r0, fene=fene, wca_eps=eps,
+                  wca_sigma=sig)
+    return orc.bead_forces(p, b, pos)
+
+
+@pytest.mark.parametrize("dims,n_chains,length,sig", [
+    ((12, 12, 12), 8, 24, 1.0),     # many cells per axis, capped by the bead count
+    ((3, 5, 40), 4, 10, 1.0),       # a one-cell axis (3 < 3 r_c) beside multi-cell axes
+    ((9, 16, 7), 5, 12, 1.3),       # sigma != 1: wider cells
+])
+def test_kg_forces_match_oracle(orc, lat, dims, n_chains, length, sig):
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    rng = np.random.default_rng(sum(dims))
+    pos, _, bonds = kremer_grest_chains(n_chains, length, dims, seed=int(sum(dims)), bond=0.97 * sig,
+                                        min_dist=0.95 * sig)
+    pos = shifted_chains(pos, length, dims, rng)
+    F, R = gpu_forces(lat, dims, pos, bonds, sig=sig, k=K_FENE / sig ** 2, r0=1.5 * sig)
+    ref = oracle_forces(orc, dims, pos, bonds, sig=sig, k=K_FENE / sig ** 2, r0=1.5 * sig)
+    scale = np.abs(ref).max()
+    err = np.abs(F - ref).max()
+    print(dims, "KG force err", err, "scale", scale)
+    assert scale > 10 * EPS            # the configuration has interacting pairs
+    assert err <= 1e-12 * scale
+    # R = R' + (h/2) P''/m with R' = R
+    np.testing.assert_allclose(R, pos + 0.5 * ref, rtol=0, atol=1e-12 * scale + 1e-13 * np.abs(pos).max())
+    # pair and bond forces cancel in total
+    assert np.abs(F.sum(0)).max() <= 1e-13 * scale * np.sqrt(pos.shape[0])
+
+
+def test_wca_edge_positions_and_dense_cluster(orc, lat):
+    """Beads on cell boundaries, at 0 and just below L, far outside the box
+    (unwrapped) and a dense cluster that puts many beads in one cell; pure
+    WCA, no bonds."""
+    dims = (10, 10, 10)
+    rng = np.random.default_rng(5)
+    edge = np.array([[0.0, 0.0, 0.0], [10.0 - 1e-13, 0.5, 0.2], [0.4, 10.0 - 1e-12, 9.6], [-20.3, 30.1, -0.9],
+                     [3.3333333333333335, 5.0, 6.666666666666667], [4.2, 5.0, 6.666666666666667]])
+    cluster = np.array([5.0, 5.0, 5.0]) + rng.uniform(-1.1, 1.1, size=(40, 3))
+    # keep a minimum separation of 0.7 sigma in the cluster
+    keep = []
+    for x in cluster:
+        if all(np.linalg.norm(x - y) >= 0.7 for y in keep):
+            keep.append(x)
+    pos = np.vstack([edge, np.array(keep)])
+    bonds = np.zeros((0, 2), np.int32)
+    F, _ = gpu_forces(lat, dims, pos, bonds, bond="harmonic", k=0.0, r0=1.0)
+    ref = oracle_forces(orc, dims, pos, bonds, fene=False, k=0.0, r0=1.0)
+    scale = np.abs(ref).max()
+    err = np.abs(F - ref).max()
+    print("edge/cluster err", err, "scale", scale, "beads", pos.shape[0])
+    assert err <= 1e-12 * scale
+    assert np.abs(ref[:3]).max() > 0   # beads 0, 1, 2 interact across the boundary
+
+
+def test_kg_forces_are_reproducible(lat):
+    """The cell lists are put in bead order, so the pair sums run in a fixed
+    order and two calls give identical bits."""
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    dims = (16, 16, 16)
+    pos, _, bonds = kremer_grest_chains(16, 20, dims, seed=3)
+    a, _ = gpu_forces(lat, dims, pos, bonds)
+    b, _ = gpu_forces(lat, dims, pos, bonds)
+    assert np.array_equal(a, b)
+
+
+def test_kg_coupled_parity(orc, lat):
+    """30 coupled steps of FENE + WCA chains with friction and noise."""
+    import torch
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    dims = (16, 16, 16)
+    pos, mom, bonds = kremer_grest_chains(6, 12, dims, seed=7)
+    nb = pos.shape[0]
+    eps = 1e-3
+    rng = np.random.default_rng(8)
+    mom = rng.normal(scale=np.sqrt(1e-4), size=(nb, 3))
+    po = orc.Params(nx=16, ny=16, nz=16, kT=1e-4, seed=9, g=(1e-5, 0.0, 0.0))
+    pd = lat.FluidParams(nx=16, ny=16, nz=16, kT=1e-4, seed=9, body_force=(1e-5, 0.0, 0.0), track_totals=False)
+    n = orc.init_equilibrium(po)
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n))
+    zeta = np.full(nb, 0.5)
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 30 * eps, 1.5, bond="fene", wca_epsilon=eps,
+                         wca_sigma=1.0)
+    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta.copy(), bonds.copy(), 30 * eps, 1.5, fene=True,
+                   wca_eps=eps, wca_sigma=1.0)
+    for t in range(30):
+        dev.coupled_step(db)
+        orc.coupled_step(po, n, t, ob)
+    ep = np.abs(dev.get_populations().cpu().numpy() - n).max()
+    er = np.abs(db.pos.cpu().numpy() - ob.pos).max()
+    em = np.abs(db.mom.cpu().numpy() - ob.mom).max()
+    print("KG coupled parity: pop", ep, "pos", er, "mom", em)
+    assert ep <= 1e-6 and er <= 1e-7 and em <= 1e-7
+    # the chains moved and interacted
+    assert np.abs(ob.pos - pos).max() > 1e-2
+    dev.close()
+
+
+def test_kg_full_size_forces(orc, lat):
+    """64 chains of 32 beads in the 256^3 box of the polymer workload, FENE +
+    WCA with eps = kT = 1e-4: every bead's force against the oracle's all-pairs
+    sum."""
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    dims = (256, 256, 256)
+    pos, _, bonds = kremer_grest_chains(64, 32, dims, seed=11)
+    F, _ = gpu_forces(lat, dims, pos, bonds)
+    ref = oracle_forces(orc, dims, pos, bonds)
+    scale = np.abs(ref).max()
+    err = np.abs(F - ref).max()
+    print("full-size KG force err", err, "scale", scale)
+    assert err <= 1e-12 * scale
+
+
+def test_fene_overstretch_is_reported(lat):
+    import torch
+    from paper_0803_2826_amd._lib import LB_ENONFINITE, LBError
+    dev = lat.Lattice(lat.FluidParams(nx=8, ny=8, nz=8, track_totals=False))
+    dev.init_equilibrium()
+    pos = np.array([[2.0, 2.0, 2.0], [3.6, 2.0, 2.0], [5.0, 5.0, 5.0], [5.9, 5.0, 5.0]])
+    db = lat.DeviceBeads(pos, np.zeros((4, 3)), np.ones(4), np.full(4, 1.0), np.array([[0, 1], [2, 3]], np.int32),
+                         K_FENE, R0, bond="fene")
+    dev.couple(db)
+    with pytest.raises(LBError) as ei:
+        dev.sync()
+    assert ei.value.code == LB_ENONFINITE and "FENE" in str(ei.value)
+    mom = db.mom.cpu().numpy()
+    assert not np.isfinite(mom[:2]).any()
+    assert np.isfinite(mom[2:]).all()     # the other chain is unaffected
+    # the NaN impulse reaches the fluid only at the broken bond's stencil nodes
+    # (x in 2..4, y = z = 2) and, after one step, their neighbours
+    dev.step(1)
+    bad = np.argwhere(~np.isfinite(dev.get_populations().cpu().numpy()).all(0))   # (z, y, x)
+    assert bad.shape[0] > 0
+    assert (bad[:, 2] >= 1).all() and (bad[:, 2] <= 5).all()
+    assert (bad[:, :2] >= 1).all() and (bad[:, :2] <= 3).all()
+    dev.close()
+    torch.cuda.synchronize()
+
+
+def test_kg_argument_errors(lat):
+    from paper_0803_2826_amd._lib import LB_EINVAL, LB_EUNSUPPORTED, LBError
+    pos = np.array([[1.0, 1.0, 1.0], [2.0, 1.0, 1.0]])
+    bonds = np.array([[0, 1]], np.int32)
+
+    def code(params, tape=False, **kw):
+        dev = lat.Lattice(params)
+        dev.init_equilibrium()
+        if tape:
+            dev.tape_begin(4)
+        db = lat.DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), bonds, K_FENE, R0, **kw)
+        try:
+            dev.couple(db)
+            return 0
+        except LBError as e:
+            return e.code
+        finally:
+            dev.close()
+
+    p8 = lat.FluidParams(nx=8, ny=8, nz=8)
+    assert code(p8, wca_epsilon=-1.0) == LB_EINVAL
+    assert code(p8, wca_epsilon=EPS, wca_sigma=0.0) == LB_EINVAL
+    assert code(p8, wca_epsilon=EPS, wca_sigma=3.6) == LB_EINVAL        # 2 r_c = 8.08 > 8
+    assert code(p8, wca_epsilon=EPS, wca_sigma=3.5) == 0
+    assert code(lat.FluidParams(nx=8, ny=8, nz=8, walls=True), wca_epsilon=EPS) == LB_EUNSUPPORTED
+    assert code(p8, tape=True, bond="fene") == LB_EUNSUPPORTED
+    assert code(p8, tape=True, wca_epsilon=EPS) == LB_EUNSUPPORTED
+    assert code(p8, tape=True) == 0
+    with pytest.raises(ValueError):
+        lat.DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), bonds, bond="morse")
