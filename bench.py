@@ -28,7 +28,9 @@ Prints ONE JSON line with, beside the throughput:
                 {24, 32, 40, 48, 64}, HIP graph replay) and the
                 differentiation form (taped forward and adjoint of 500
                 coupled steps at 128^3 with 16 x 32 beads, checkpoints every
-                50).
+                50), and the coupled step with Kremer-Grest chains (FENE
+                bonds, WCA pairs with a cell list) in place of the harmonic
+                ones.
 """
 from __future__ import annotations
 
@@ -231,6 +233,40 @@ def run_forms(L: int) -> dict:
     out["backward_config"] = (f"{Lb}^3, {T} coupled steps with 16 x 32 beads (zeta 20, k 10 kT), checkpoints every "
                               f"{K}, FP32 fluid, FP64 beads; gradients w.r.t. n(0), g, R(0), P(0)")
     print("# forms: backward done", file=sys.stderr, flush=True)
+
+    # Kremer-Grest chains: the same box and chain count with FENE bonds and
+    # WCA pairs (cell list rebuilt every step), eps = kT, sigma = 1
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+
+    pk = lattice.FluidParams(nx=L, ny=L, nz=L, kT=KT, seed=0, track_totals=True)
+    lat = lattice.Lattice(pk)
+    lat.init_equilibrium()
+    pos, mom, bonds = kremer_grest_chains(64, 32, (L, L, L), seed=0)
+    nb = pos.shape[0]
+    kg = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, 30 * KT, 1.5, bond="fene",
+                             wca_epsilon=KT, wca_sigma=1.0)
+    for _ in range(5):
+        lat.coupled_step(kg)
+    Tk = 50
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    half = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(Tk)]
+    torch.cuda.synchronize()
+    ev[0].record(lat.stream)
+    for h0, h1 in half:
+        h0.record(lat.stream)
+        lat.couple(kg)
+        h1.record(lat.stream)
+        lat.step(1)
+    ev[1].record(lat.stream)
+    torch.cuda.synchronize()
+    lat.sync()
+    lat.close()
+    ms = ev[0].elapsed_time(ev[1]) / Tk
+    out["kg_coupled_mlups"] = round(L ** 3 / (ms * 1e-3) / 1e6, 1)
+    out["kg_particle_half_ms"] = round(sum(a.elapsed_time(b) for a, b in half) / Tk, 4)
+    out["kg_config"] = (f"{L}^3 fluid as above, 64 x 32 Kremer-Grest chains: FENE k = 30 kT, R0 = 1.5, WCA "
+                        f"eps = kT, sigma = 1 (cell list), zeta = 20, m = 1")
+    print("# forms: Kremer-Grest done", file=sys.stderr, flush=True)
     return out
 
 
@@ -273,8 +309,11 @@ def main() -> int:
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record(stream)
-    for k0, k1 in kev:
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for (k0, k1), (c0, c1) in zip(kev, cev):
+        c0.record(stream)
         lat.couple(beads)
+        c1.record(stream)
         k0.record(stream)
         lat.step(1)
         k1.record(stream)
@@ -285,6 +324,7 @@ def main() -> int:
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     mlups = N / (ms_per_step * 1e-3) / 1e6
     kern_ms = sum(k0.elapsed_time(k1) for k0, k1 in kev) / args.steps
+    half_ms = sum(c0.elapsed_time(c1) for c0, c1 in cev) / args.steps
     print(f"# timed {args.steps} steps: {ms_per_step:.4f} ms/step, {mlups:.0f} MLUPS; fused kernel {kern_ms:.4f} ms",
           file=sys.stderr, flush=True)
 
@@ -348,6 +388,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
+        "particle_half_ms": round(half_ms, 5),
         "mass_drift_rel": (tot1x[0] - tot0[0]) / tot0[0],
         "fused_vs_exact_totals_abs": max(abs(a - b) for a, b in zip(tot1, tot1x)),
         "source_hash": source_hash(),

@@ -67,6 +67,7 @@ struct lb_ctx {
     int32_t *bead_cell = nullptr;    // [n] cell, slot within the cell, cell-ordered bead list
     int32_t *bead_slot = nullptr;
     int32_t *cell_sorted = nullptr;
+    double4 *cell_pos = nullptr;     // [n] positions in cell order (x, y, z, bead index)
     int pair_cap = 0;
     void *scan_tmp = nullptr;        // hipcub scan workspace
     size_t scan_tmp_bytes = 0;
@@ -374,8 +375,10 @@ void free_tape(lb_ctx *c)
 }
 
 // Cell grid of the WCA pair search for n beads: cells no narrower than
-// r_c, at most about 2n cells (so that rebuilding the list stays cheap for
-// dilute chains), an axis with fewer than 3 cells folded into one.
+// r_c, at most about 512 n cells and 128 per axis (rebuilding the list costs
+// a few passes over the cells; dilute chains cluster, so cells much wider
+// than r_c would give long candidate lists), an axis with fewer than 3
+// cells folded into one.
 CellGrid cell_grid(const lb_ctx *c, const lb_beads *b)
 {
     CellGrid cg;
@@ -384,7 +387,7 @@ CellGrid cell_grid(const lb_ctx *c, const lb_beads *b)
     cg.sig2 = sig2;
     cg.eps24 = 24.0 * b->wca_epsilon;
     const double rc = std::sqrt(cg.rc2);
-    const int cap = std::min(128, std::max(3, (int)std::ceil(std::cbrt(2.0 * (double)b->n))));
+    const int cap = std::min(128, std::max(3, (int)std::ceil(std::cbrt(512.0 * (double)b->n))));
     const int32_t ext[3] = {c->p.nx, c->p.ny, c->p.nz};
     for (int a = 0; a < 3; ++a) {
         cg.L[a] = (double)ext[a];
@@ -408,6 +411,10 @@ int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
             hipMalloc(&c->cell_start, (ncell + 1) * sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "cell list allocation failed");
         c->cell_cap = ncell + 1;
+        // counts start at zero; each use leaves them at zero (k_cell_fill)
+        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(ncell + 1, 256)), dim3(256), 0, c->stream, c->cell_count,
+                           (uint32_t)(ncell + 1));
+        LB_LAUNCH_CHECK(c, "zero cell counts");
     }
     size_t tmp = 0;
     if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, c->cell_count, c->cell_start, (int)(ncell + 1), c->stream) !=
@@ -424,37 +431,39 @@ int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
         (void)hipFree(c->bead_cell);
         (void)hipFree(c->bead_slot);
         (void)hipFree(c->cell_sorted);
+        (void)hipFree(c->cell_pos);
         c->bead_cell = c->bead_slot = c->cell_sorted = nullptr;
+        c->cell_pos = nullptr;
         c->pair_cap = 0;
         if (hipMalloc(&c->bead_cell, (size_t)n * sizeof(int32_t)) != hipSuccess ||
             hipMalloc(&c->bead_slot, (size_t)n * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->cell_sorted, (size_t)n * sizeof(int32_t)) != hipSuccess)
+            hipMalloc(&c->cell_sorted, (size_t)n * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->cell_pos, (size_t)n * sizeof(double4)) != hipSuccess)
             return fail(c, LB_ENOMEM, "cell list allocation failed");
         c->pair_cap = n;
     }
     return LB_OK;
 }
 
-// WCA forces at the half-step positions, added to c->fc: rebuild the cell
-// list, then one thread per bead over its neighbour cells.
+// WCA forces at the half-step positions, added to c->fc with the external
+// force: rebuild the cell list, then kPairLanes lanes per bead over its
+// neighbour cells.
 void launch_wca(lb_ctx *c, const lb_beads *b)
 {
     const CellGrid cg = cell_grid(c, b);
     const size_t ncell = (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2];
     const unsigned gb = grid_for((size_t)b->n, 256);
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(ncell + 1, 256)), dim3(256), 0, c->stream, c->cell_count,
-                       (uint32_t)(ncell + 1));
     hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(256), 0, c->stream, c->half, b->n, cg, c->bead_cell, c->bead_slot,
                        c->cell_count);
     size_t tmp = c->scan_tmp_bytes;
     (void)hipcub::DeviceScan::ExclusiveSum(c->scan_tmp, tmp, c->cell_count, c->cell_start, (int)(ncell + 1),
                                            c->stream);
     hipLaunchKernelGGL(k_cell_fill, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->bead_slot, c->cell_start,
-                       c->cell_sorted);
-    hipLaunchKernelGGL(k_cell_order, dim3(grid_for(ncell, 256)), dim3(256), 0, c->stream, (int)ncell, c->cell_start,
-                       c->cell_sorted);
-    hipLaunchKernelGGL(k_wca, dim3(gb), dim3(256), 0, c->stream, c->half, b->n, cg, c->bead_cell, c->cell_start,
-                       c->cell_sorted, c->fc);
+                       c->cell_sorted, c->cell_count);
+    hipLaunchKernelGGL(k_cell_rank, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->cell_start,
+                       c->cell_sorted, c->half, c->cell_pos);
+    hipLaunchKernelGGL(k_wca, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, c->half, b->n,
+                       cg, c->bead_cell, c->cell_start, c->cell_pos, b->fext, c->fc);
 }
 
 // The particle half of one coupled step (k_bead_half, k_bonds, the WCA pair
@@ -489,8 +498,9 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, d
     if (b->nbonds > 0)
         hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
                            b->bonds, b->nbonds, b->k_bond, b->r0, b->n, (int)(b->bond == LB_BOND_FENE), c->flags);
-    if (b->wca_epsilon > 0.0) launch_wca(c, b);
-    if (b->fext)
+    if (b->wca_epsilon > 0.0)
+        launch_wca(c, b);  // adds fext too
+    else if (b->fext)
         hipLaunchKernelGGL(k_add_fext, dim3(grid_for(3 * (size_t)b->n, 256)), dim3(256), 0, c->stream, b->n, b->fext,
                            c->fc);
     by_storage(c->p.storage, [&](auto st) {
@@ -948,7 +958,8 @@ int lb_destroy(lb_ctx *c)
     void *ptrs[] = {c->bufA,       c->bufB,      c->partials,  c->scratch,   c->dev_out,   c->flags,
                     c->force,      c->fmask,     c->list,      c->count,     c->half,      c->fc,
                     c->boxes_d,    c->tile_box,  c->dstep,     c->amp,       c->ring,      c->corr,
-                    c->cell_count, c->cell_start, c->bead_cell, c->bead_slot, c->cell_sorted, c->scan_tmp};
+                    c->cell_count, c->cell_start, c->bead_cell, c->bead_slot, c->cell_sorted, c->scan_tmp,
+                    c->cell_pos};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int k = 0; k < 2; ++k)

@@ -10,14 +10,20 @@
 //                   it are candidates and the minimum image picks the pair's
 //                   single image within r_c < L_a / 2)
 //   k_cell_count    cell of each bead, its slot = atomic increment of the
-//                   cell's count
+//                   cell's count (the counts are zero on entry: zeroed once
+//                   at allocation, then by k_cell_fill after their use)
 //   (scan)          exclusive prefix sum of the counts: first entry per cell
-//   k_cell_fill     sorted[start[cell] + slot] = bead
-//   k_cell_order    per cell, the bead indices in ascending order, so that the
-//                   force sums below run in a fixed order (reproducible bits)
-//   k_wca           one thread per bead: the 27 neighbour cells (3 per axis,
-//                   1 on a one-cell axis) in a fixed order; every pair is
-//                   evaluated from both ends, so no atomics are needed.
+//   k_cell_fill     members[start[cell] + slot] = bead (in arrival order);
+//                   the cell's count back to zero
+//   k_cell_rank     each bead's rank in its cell by index (the number of
+//                   members with a smaller index) and a copy of its position
+//                   at that place, cpos[start + rank] = (R', index): cells in
+//                   index order, one 32-byte load per candidate below
+//   k_wca           32 lanes per bead, lane l scans neighbour cell l (27 cells,
+//                   fewer on one-cell axes) in cell order; a fixed butterfly
+//                   sums the lanes.  Every pair is evaluated from both ends,
+//                   so no atomics are needed and the bits are the same on
+//                   every run.  The external force is added last.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,75 +69,89 @@ __global__ void k_cell_count(const double *__restrict__ half, int n, CellGrid cg
 }
 
 __global__ void k_cell_fill(int n, const int32_t *__restrict__ cell_of, const int32_t *__restrict__ slot,
-                            const int32_t *__restrict__ start, int32_t *sorted)
+                            const int32_t *__restrict__ start, int32_t *members, int32_t *count)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
-    sorted[start[cell_of[b]] + slot[b]] = b;
+    const int cell = cell_of[b];
+    members[start[cell] + slot[b]] = b;
+    count[cell] = 0;
 }
 
-// Insertion sort of each cell's (short) bead list.
-__global__ void k_cell_order(int ncell, const int32_t *__restrict__ start, int32_t *sorted)
+__global__ void k_cell_rank(int n, const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
+                            const int32_t *__restrict__ members, const double *__restrict__ half, double4 *cpos)
 {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= ncell) return;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const int cell = cell_of[b];
     const int lo = start[cell], hi = start[cell + 1];
-    for (int k = lo + 1; k < hi; ++k) {
-        const int32_t v = sorted[k];
-        int m = k - 1;
-        while (m >= lo && sorted[m] > v) {
-            sorted[m + 1] = sorted[m];
-            --m;
-        }
-        sorted[m + 1] = v;
-    }
+    int rank = 0;
+    for (int k = lo; k < hi; ++k) rank += members[k] < b ? 1 : 0;
+    cpos[lo + rank] = make_double4(half[3 * b], half[3 * b + 1], half[3 * b + 2], (double)b);
 }
+
+constexpr int kPairLanes = 32;
 
 // F_i += sum_j f(r_ij) (R_i - R_j) over beads j != i within r_c, with
 // f = 24 eps (2 (sigma/r)^12 - (sigma/r)^6) / r^2 = -V'(r)/r of eq. ulennardjones.
+// kPairLanes consecutive lanes per bead (blockDim a multiple of 64).
 __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, int n, CellGrid cg,
                                              const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
-                                             const int32_t *__restrict__ sorted, double *fc)
+                                             const double4 *__restrict__ cpos, const double *__restrict__ fext,
+                                             double *fc)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
-    const int cell = cell_of[i];
-    const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
-    const int span[3] = {cg.nc[0] >= 3 ? 1 : 0, cg.nc[1] >= 3 ? 1 : 0, cg.nc[2] >= 3 ? 1 : 0};
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / kPairLanes, l = t % kPairLanes;
     double F[3] = {0.0, 0.0, 0.0};
-    for (int oz = -span[2]; oz <= span[2]; ++oz) {
-        int cz = ci[2] + oz;
-        cz += cz < 0 ? cg.nc[2] : (cz >= cg.nc[2] ? -cg.nc[2] : 0);
-        for (int oy = -span[1]; oy <= span[1]; ++oy) {
-            int cy = ci[1] + oy;
-            cy += cy < 0 ? cg.nc[1] : (cy >= cg.nc[1] ? -cg.nc[1] : 0);
-            for (int ox = -span[0]; ox <= span[0]; ++ox) {
-                int cx = ci[0] + ox;
-                cx += cx < 0 ? cg.nc[0] : (cx >= cg.nc[0] ? -cg.nc[0] : 0);
-                const int nb = cx + cg.nc[0] * (cy + cg.nc[1] * cz);
-                const int hi = start[nb + 1];
-                for (int k = start[nb]; k < hi; ++k) {
-                    const int j = sorted[k];
-                    if (j == i) continue;
-                    double d[3], r2 = 0.0;
+    if (i < n) {
+        const int span[3] = {cg.nc[0] >= 3 ? 1 : 0, cg.nc[1] >= 3 ? 1 : 0, cg.nc[2] >= 3 ? 1 : 0};
+        const int w0 = 2 * span[0] + 1, w1 = 2 * span[1] + 1, w2 = 2 * span[2] + 1;
+        if (l < w0 * w1 * w2) {
+            const int cell = cell_of[i];
+            const int o[3] = {l % w0 - span[0], (l / w0) % w1 - span[1], l / (w0 * w1) - span[2]};
+            const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
+            int cn[3];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        d[a] = nearest_image(Ri[a] - half[3 * j + a], cg.L[a]);
-                        r2 += d[a] * d[a];
-                    }
+            for (int a = 0; a < 3; ++a) {
+                cn[a] = ci[a] + o[a];
+                cn[a] += cn[a] < 0 ? cg.nc[a] : (cn[a] >= cg.nc[a] ? -cg.nc[a] : 0);
+            }
+            const int nb = cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
+            const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
+            const double self = (double)i;
+            const int lo = start[nb], hi = start[nb + 1];
+            // four candidates per round, their loads issued together
+            constexpr int U = 4;
+            for (int k0 = lo; k0 < hi; k0 += U) {
+                double4 q[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) q[u] = cpos[k0 + u < hi ? k0 + u : lo];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (k0 + u >= hi || q[u].w == self) continue;
+                    const double d0 = nearest_image(Ri[0] - q[u].x, cg.L[0]);
+                    const double d1 = nearest_image(Ri[1] - q[u].y, cg.L[1]);
+                    const double d2 = nearest_image(Ri[2] - q[u].z, cg.L[2]);
+                    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
                     if (!(r2 < cg.rc2)) continue;
                     const double s2 = cg.sig2 / r2;
                     const double s6 = s2 * s2 * s2;
                     const double f = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) F[a] += f * d[a];
+                    F[0] += f * d0;
+                    F[1] += f * d1;
+                    F[2] += f * d2;
                 }
             }
         }
     }
+    // butterfly over the bead's lanes (every lane ends with the same bits)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) fc[3 * i + a] += F[a];
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int off = 1; off < kPairLanes; off <<= 1) F[a] += __shfl_xor(F[a], off, 64);
+    if (i < n && l == 0)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fc[3 * i + a] = (fc[3 * i + a] + F[a]) + (fext ? fext[3 * i + a] : 0.0);
 }
 
 }  // namespace lbmi
