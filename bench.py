@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--chains", choices=("harmonic", "kg"), default="harmonic",
+                    help="bead model of the timed loop: the harmonic chains of the workload (default) or "
+                         "Kremer-Grest chains (FENE bonds + WCA pairs, eps = kT) for profiling that path")
     return ap.parse_args()
 
 
@@ -289,9 +292,19 @@ def main() -> int:
     pd = lattice.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=KT, seed=0, track_totals=True, block=-1)
     lat = lattice.Lattice(pd)
     lat.init_equilibrium()
-    pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed=0)
-    nb = pos.shape[0]
-    beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, K_BOND, 1.0)
+    if args.chains == "kg":
+        from paper_0803_2826_amd.inputs import kremer_grest_chains
+
+        pos, mom, bonds = kremer_grest_chains(n_chains, length, (L, L, L), seed=0)
+        nb = pos.shape[0]
+        beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, 30 * KT, 1.5, bond="fene",
+                                    wca_epsilon=KT, wca_sigma=1.0)
+        chain_desc = "Kremer-Grest chains (FENE k=30 kT, R0=1.5; WCA eps=kT, sigma=1), zeta=20, m=1"
+    else:
+        pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed=0)
+        nb = pos.shape[0]
+        beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, K_BOND, 1.0)
+        chain_desc = "(k=10 kT/b^2, r0=1, zeta=20, m=1)"
     tot0 = lat.totals(exact=True)
     stream = lat.stream
 
@@ -382,7 +395,7 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"fluctuating D3Q19 MRT {L}^3 periodic, FP32 shifted storage, kT=1e-4, tau=1, "
-                               f"{n_chains} chains x {length} beads (k=10 kT/b^2, r0=1, zeta=20, m=1), "
+                               f"{n_chains} chains x {length} beads {chain_desc}, "
                                f"trilinear interpolation + spreading every step",
                    "sites": N, "beads": nb, "parallelism": "single GPU"},
         "roofline": roofline,
