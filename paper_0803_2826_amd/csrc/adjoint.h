@@ -31,7 +31,7 @@ struct AdjArgs {
     Geom geo;
     CollideConst cc;
     uint32_t step;
-    double *partials;       // [gridDim][3] block sums of Fbar
+    double *partials;       // [gridDim][3] block sums of Fbar, accumulated over the steps of a sweep
     // bead force of the step (FORCE variant): F = g + force at sites whose
     // bit is set in fmask; the adjoint of that force is written to fbar there
     const float *force;     // [3][N]
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
     if (threadIdx.x < 3) {
         double sacc = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sacc += red[w][threadIdx.x];
-        a.partials[3 * (size_t)blockIdx.x + threadIdx.x] = sacc;
+        a.partials[3 * (size_t)blockIdx.x + threadIdx.x] += sacc;
     }
 }
 

@@ -178,6 +178,41 @@ __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, co
     }
 }
 
+// Recompute sweep of a segment: keep the spread force of a coupled step
+// compactly (its touched nodes and their force values) while zeroing the
+// force field and its bitmap, so that the adjoint sweep can restore it
+// without running the particle half again.
+__global__ void k_save_clear_touched(float *force, uint32_t *fmask, const int32_t *list, const int32_t *count,
+                                     int cap, uint32_t N, int32_t *slist, int32_t *scount, float *svals)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cnt = min(*count, cap);
+    if (idx == 0) *scount = cnt;
+    if (idx >= cnt) return;
+    const uint32_t s = (uint32_t)list[idx];
+    slist[idx] = (int32_t)s;
+    for (int c = 0; c < 3; ++c) {
+        svals[3 * idx + c] = force[(size_t)c * N + s];
+        force[(size_t)c * N + s] = 0.f;
+    }
+    fmask[s >> 5] = 0u;
+}
+
+// Adjoint sweep: put a saved spread force back (values, bitmap bits, the
+// touched-node list and its count).  The force field is zero on entry.
+__global__ void k_restore_touched(const int32_t *slist, const int32_t *scount, const float *svals, int cap,
+                                  uint32_t N, float *force, uint32_t *fmask, int32_t *list, int32_t *count)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cnt = min(*scount, cap);
+    if (idx == 0) *count = cnt;
+    if (idx >= cnt) return;
+    const uint32_t s = (uint32_t)slist[idx];
+    for (int c = 0; c < 3; ++c) force[(size_t)c * N + s] = svals[3 * idx + c];
+    atomicOr(&fmask[s >> 5], 1u << (s & 31u));
+    list[idx] = (int32_t)s;
+}
+
 // Zero the force, its adjoint and the bitmap word of every touched node.
 __global__ void k_clear_touched_adj(float *force, float *fbar, uint32_t *fmask, const int32_t *list,
                                     const int32_t *count, int cap, uint32_t N)

@@ -37,7 +37,9 @@ struct CoupleArgs {
     double kT;
     uint32_t key0, key1, box, step;
     int32_t n;
-    double *pos;
+    const double *pos_in;  // bead state the step starts from (may equal pos / mom)
+    const double *mom_in;
+    double *pos;           // out: state after the step
     double *mom;
     const double *mass;
     const double *zeta;
@@ -56,7 +58,7 @@ __global__ void k_bead_half(CoupleArgs a)
     if (b >= a.n) return;
     const double m = a.mass[b];
     for (int c = 0; c < 3; ++c) {
-        a.half[3 * b + c] = a.pos[3 * b + c] + 0.5 * a.mom[3 * b + c] / m;
+        a.half[3 * b + c] = a.pos_in[3 * b + c] + 0.5 * a.mom_in[3 * b + c] / m;
         a.fc[3 * b + c] = 0.0;
     }
 }
@@ -236,7 +238,7 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
     if (a.kT > 0.0 && z > 0.0) bead_normals((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
     double Pn[3], I[3];
     for (int c = 0; c < 3; ++c) {
-        const double P = a.mom[3 * b + c], Fc = a.fc[3 * b + c];
+        const double P = a.mom_in[3 * b + c], Fc = a.fc[3 * b + c];
         Pn[c] = C1 * P + C2 * (Fc + z * ub[c]) + C3 * th[c];
         I[c] = -(Pn[c] - P - h * Fc);
     }

@@ -103,6 +103,8 @@ struct lb_ctx {
     std::vector<void *> checkpoints;  // A-buffer copies at tape_step0 + s * tape_k
     void *seg = nullptr;              // tape_k step buffers of one segment
     size_t seg_bytes = 0;
+    void *seg_bead = nullptr;         // per step of a segment: R', F^c, P'' and the compact spread force
+    size_t seg_bead_bytes = 0;
     float *lamA = nullptr, *lamB = nullptr;
     double *gbar_d = nullptr;
     double *adj_partials = nullptr;
@@ -470,7 +472,8 @@ void launch_wca(lb_ctx *c, const lb_beads *b)
 // search, k_add_fext, k_bead_update) on the populations `pop`, updating
 // (pos, mom) in place and spreading into the force field, its bitmap and the
 // touched-node list.
-void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, double *mom, uint32_t step)
+void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *pos_in, const double *mom_in,
+                   double *pos, double *mom, uint32_t step)
 {
     CoupleArgs a;
     a.pop = pop;
@@ -483,6 +486,8 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, double *pos, d
     a.box = c->cc.box;
     a.step = step;
     a.n = b->n;
+    a.pos_in = pos_in;
+    a.mom_in = mom_in;
     a.pos = pos;
     a.mom = mom;
     a.mass = b->mass;
@@ -965,7 +970,7 @@ int lb_destroy(lb_ctx *c)
     for (int k = 0; k < 2; ++k)
         if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
     free_tape(c);
-    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials, c->snap, c->bead_work, c->fbar};
+    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials, c->snap, c->bead_work, c->fbar, c->seg_bead};
     for (void *q : adj)
         if (q) (void)hipFree(q);
     if (c->batch) {
@@ -1149,7 +1154,7 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     }
     c->pending_slot = -1;
     if (c->taping) LB_TRY(tape_bead_snapshot(c, b));
-    launch_couple(c, c->bufA, b, b->pos, b->mom, (uint32_t)c->step);
+    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
     const int W = (b->stencil == 3 || b->stencil == 4) ? b->stencil : 2;
@@ -1350,6 +1355,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     }
     double *pos_w = nullptr, *mom_w = nullptr, *half_bar = nullptr, *fc_bar = nullptr, *p_bar = nullptr;
     double *pos_bar = nullptr, *mom_bar = nullptr;
+    int seg_rows = 0;       // touched-node capacity per saved step
+    size_t seg_stride = 0;  // bytes per saved step in seg_bead
     if (coupled) {
         if (c->bead_work_n < nbd) {
             (void)hipFree(c->bead_work);
@@ -1365,6 +1372,18 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->fbar, 3 * N);
         }
         const size_t n3 = 3 * (size_t)nbd;
+        int wmax = 2;
+        for (const lb_beads &bt : c->tape_beads) wmax = std::max(wmax, (bt.stencil == 3 || bt.stencil == 4) ? bt.stencil : 2);
+        seg_rows = wmax * wmax * wmax * nbd;
+        seg_stride = 3 * n3 * sizeof(double) + (size_t)seg_rows * 4 * sizeof(float) + 256;
+        if (c->seg_bead_bytes < (size_t)K * seg_stride) {
+            (void)hipFree(c->seg_bead);
+            c->seg_bead = nullptr;
+            c->seg_bead_bytes = 0;
+            if (hipMalloc(&c->seg_bead, (size_t)K * seg_stride) != hipSuccess)
+                return fail(c, LB_ENOMEM, "segment bead buffer allocation failed");
+            c->seg_bead_bytes = (size_t)K * seg_stride;
+        }
         pos_w = c->bead_work;
         mom_w = pos_w + n3;
         half_bar = mom_w + n3;
@@ -1392,19 +1411,42 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         hipLaunchKernelGGL(k_to_f32<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float *>(dL_dn_T),
                            c->lamA, n19);
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<float *>(c->gbar_d), (size_t)6);
+    // the adjoint steps add their block sums of dL/dg into adj_partials; one
+    // reduction at the end of the sweep
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(6 * (size_t)nb, 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<float *>(c->adj_partials), 6 * (size_t)nb);
     LB_LAUNCH_CHECK(c, "backward set-up");
 
     // rebuild the bead force of taped step t (slot >= 0) from its snapshot on the populations `pop`
     auto rebuild_force = [&](int slot, const void *pop, uint32_t step) {
         const size_t n3 = 3 * (size_t)nbd;
         const double *snap = c->snap + (size_t)slot * 2 * n3;
-        (void)hipMemcpyAsync(pos_w, snap, 2 * n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-        launch_couple(c, pop, &c->tape_beads[slot], pos_w, mom_w, step);
+        launch_couple(c, pop, &c->tape_beads[slot], snap, snap + n3, pos_w, mom_w, step);
     };
     auto clear_force = [&]() {
         hipLaunchKernelGGL(k_clear_touched_adj, dim3(grid_for(64 * (size_t)nbd, 256)), dim3(256), 0, c->stream,
                            c->force, c->fbar, c->fmask, c->list, c->count, 64 * nbd, c->geo.N);
     };
+    // saved step k of the segment: R' [n3], F^c [n3], P'' [n3] (FP64), then
+    // the touched count, nodes and force values
+    struct Saved {
+        double *half, *fc, *mom;
+        int32_t *count, *list;
+        float *vals;
+    };
+    auto saved = [&](int k) {
+        char *b = static_cast<char *>(c->seg_bead) + (size_t)k * seg_stride;
+        const size_t n3 = 3 * (size_t)nbd;
+        Saved v;
+        v.half = reinterpret_cast<double *>(b);
+        v.fc = v.half + n3;
+        v.mom = v.fc + n3;
+        v.count = reinterpret_cast<int32_t *>(v.mom + n3);
+        v.list = v.count + 64;
+        v.vals = reinterpret_cast<float *>(v.list + seg_rows);
+        return v;
+    };
+    double *const ctx_half = c->half, *const ctx_fc = c->fc;
 
     const unsigned saved_blocks = c->nblocks;
     const int saved_block = c->block;
@@ -1424,12 +1466,24 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             const int slot = c->tape_slot[t0 + k];
             StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb, step);
             if (slot >= 0) {
-                rebuild_force(slot, seg + (size_t)k * sb, step);
+                // the particle half writes R', F^c and P'' straight into the saved step
+                const Saved v = saved(k);
+                const size_t n3 = 3 * (size_t)nbd;
+                const double *snap = c->snap + (size_t)slot * 2 * n3;
+                c->half = v.half;
+                c->fc = v.fc;
+                launch_couple(c, seg + (size_t)k * sb, &c->tape_beads[slot], snap, snap + n3, pos_w, v.mom, step);
+                c->half = ctx_half;
+                c->fc = ctx_fc;
                 a.fmask = c->fmask;
                 a.force = c->force;
             }
             by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, slot >= 0); });
-            if (slot >= 0) clear_force();
+            if (slot >= 0) {
+                const Saved v = saved(k);
+                hipLaunchKernelGGL(k_save_clear_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
+                                   c->force, c->fmask, c->list, c->count, seg_rows, c->geo.N, v.list, v.count, v.vals);
+            }
         }
         if ((rc = hipGetLastError() == hipSuccess ? LB_OK : fail(c, LB_EDEVICE, "backward recompute")) != LB_OK) break;
         for (int k = len - 1; k >= 0; --k) {
@@ -1447,7 +1501,16 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             aa.force = c->force;
             aa.fmask = c->fmask;
             aa.fbar = c->fbar;
-            if (slot >= 0) rebuild_force(slot, pop, step);
+            // a coupled step recomputed above gets its spread force back from the
+            // saved step; the last step of the segment runs its particle half again
+            const bool have = slot >= 0 && k + 1 < len;
+            if (have) {
+                const Saved v = saved(k);
+                hipLaunchKernelGGL(k_restore_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
+                                   v.list, v.count, v.vals, seg_rows, c->geo.N, c->force, c->fmask, c->list, c->count);
+            } else if (slot >= 0) {
+                rebuild_force(slot, pop, step);
+            }
             by_storage(c->p.storage, [&](auto st) {
                 constexpr int ST = decltype(st)::value;
                 auto go = [&](auto th, auto frc) {
@@ -1467,8 +1530,6 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                     else go(F_{}, F_{});
                 }
             });
-            hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3,
-                               c->gbar_d);
             if (slot >= 0) {
                 const lb_beads &bc = c->tape_beads[slot];
                 const size_t n3 = 3 * (size_t)nbd;
@@ -1479,11 +1540,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 for (int q = 0; q < 3; ++q) ba.g[q] = c->p.body_force[q];
                 ba.n = nbd;
                 ba.mom0 = c->snap + (size_t)slot * 2 * n3 + n3;
-                ba.mom1 = mom_w;
+                ba.mom1 = have ? saved(k).mom : mom_w;
                 ba.mass = bc.mass;
                 ba.zeta = bc.zeta;
-                ba.half = c->half;
-                ba.fc = c->fc;
+                ba.half = have ? saved(k).half : c->half;
+                ba.fc = have ? saved(k).fc : c->fc;
                 ba.fbar = c->fbar;
                 ba.pos_bar = pos_bar;
                 ba.mom_bar = mom_bar;
@@ -1503,7 +1564,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 });
                 if (bc.nbonds > 0)
                     hipLaunchKernelGGL(k_bonds_adjoint, dim3(grid_for((size_t)bc.nbonds, 256)), dim3(256), 0, c->stream,
-                                       c->half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd);
+                                       ba.half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd);
                 hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for((size_t)nbd, 256)), dim3(256), 0, c->stream,
                                    nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar);
                 clear_force();
@@ -1515,6 +1576,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     c->block = saved_block;
     c->nblocks = (int)saved_blocks;
     if (rc != LB_OK) return rc;
+    hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3, c->gbar_d);
     if (dtype == LB_F64)
         hipLaunchKernelGGL(k_from_f32<double>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
                            static_cast<double *>(dL_dn_0), n19);
