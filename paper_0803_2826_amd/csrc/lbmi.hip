@@ -468,6 +468,10 @@ void launch_wca(lb_ctx *c, const lb_beads *b)
                        cg, c->bead_cell, c->cell_start, c->cell_pos, b->fext, c->fc);
 }
 
+// Threads per block of the per-bead stencil kernels: one wave, so that a few
+// thousand beads spread over many CUs (the kernels are latency-bound).
+constexpr int kBeadBlock = 64;
+
 // The particle half of one coupled step (k_bead_half, k_bonds, the WCA pair
 // search, k_add_fext, k_bead_update) on the populations `pop`, updating
 // (pos, mom) in place and spreading into the force field, its bitmap and the
@@ -512,8 +516,9 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
         constexpr int ST = decltype(st)::value;
         by_stencil(b->stencil, [&](auto w) {
             constexpr int W = decltype(w)::value;
-            hipLaunchKernelGGL((k_bead_update<ST, W>), dim3(grid_for(StencilLanes<W>::value * (size_t)b->n, 256)),
-                               dim3(256), 0, c->stream, a);
+            hipLaunchKernelGGL((k_bead_update<ST, W>),
+                               dim3(grid_for(StencilLanes<W>::value * (size_t)b->n, kBeadBlock)), dim3(kBeadBlock), 0,
+                               c->stream, a);
         });
     });
 }
@@ -1558,7 +1563,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                     by_stencil(bc.stencil, [&](auto w) {
                         constexpr int W = decltype(w)::value;
                         hipLaunchKernelGGL((k_bead_adjoint<ST, W>),
-                                           dim3(grid_for(StencilLanes<W>::value * (size_t)nbd, 256)), dim3(256), 0,
+                                           dim3(grid_for(StencilLanes<W>::value * (size_t)nbd, kBeadBlock)),
+                                           dim3(kBeadBlock), 0,
                                            c->stream, ba);
                     });
                 });
