@@ -10,6 +10,11 @@ Recipes (lattice units):
                   in uniformly random directions (isotropic unit vectors);
                   positions are unwrapped; momenta zero; bonds join
                   consecutive beads of a chain.
+  kremer_grest_chains
+                  self-avoiding random walks for the bead-spring model:
+                  uniform starts, steps of `bond` (0.97 sigma) in isotropic
+                  random directions, every new bead at least `min_dist`
+                  (0.95 sigma, minimum image) from all beads placed before.
 """
 from __future__ import annotations
 

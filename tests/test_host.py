@@ -1,0 +1,92 @@
+"""Host-side logic that needs no GPU: the parameter helpers of the Python
+binding, the seeded input generators and the descriptors handed to the C
+ABI."""
+import math
+
+import numpy as np
+import pytest
+
+
+def test_two_rate_puts_lambda_at_its_target():
+    from paper_0803_2826_amd.lattice import two_rate
+    for ge in (-0.5, 0.0, 0.3, 0.8):
+        for magic in (3 / 16, 0.25):
+            kw = two_rate(ge, magic)
+            te = 1 / (1 - kw["gamma_shear"])
+            to = 1 / (1 - kw["gamma_3a"])
+            assert (te - 0.5) * (to - 0.5) == pytest.approx(magic, rel=1e-14)
+            assert kw["gamma_bulk"] == kw["gamma_4a"] == kw["gamma_4b"] == kw["gamma_shear"] == ge
+            assert kw["gamma_3b"] == kw["gamma_3a"]
+            assert abs(kw["gamma_3a"]) < 1
+    # gamma_e = 0 (tau = 1) with Lambda = 3/16 gives tau_o = 7/8
+    assert 1 / (1 - two_rate(0.0)["gamma_3a"]) == pytest.approx(7 / 8)
+    with pytest.raises(ValueError):
+        two_rate(1.0)
+
+
+def test_fluid_params_descriptor():
+    from paper_0803_2826_amd import _lib
+    from paper_0803_2826_amd.lattice import FluidParams
+    c = FluidParams(nx=5, ny=6, nz=7, storage="bf16", kT=1e-4, body_force=(1e-5, 0, -2e-5), seed=2 ** 64 + 3,
+                    rounding="stochastic", walls=True).to_c()
+    assert (c.nx, c.ny, c.nz) == (5, 6, 7)
+    assert c.storage == _lib.LB_BF16 and c.rounding == _lib.LB_ROUND_STOCHASTIC and c.walls == 1
+    assert c.seed == 3 and list(c.body_force) == [1e-5, 0.0, -2e-5]
+
+
+def test_bead_descriptor_fields():
+    from paper_0803_2826_amd import _lib
+    from paper_0803_2826_amd.lattice import DeviceBeads
+    pos = np.array([[1.0, 2.0, 3.0], [2.0, 2.0, 3.0]])
+    b = DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.full(2, 0.5), np.array([[0, 1]]), 3e-3, 1.5, device="cpu",
+                    stencil=3, bond="fene", wca_epsilon=1e-4, wca_sigma=1.2)
+    c = b.to_c()
+    assert (c.n, c.nbonds, c.stencil) == (2, 1, 3)
+    assert c.bond == _lib.LB_BOND_FENE and c.wca_epsilon == 1e-4 and c.wca_sigma == 1.2
+    assert c.k_bond == 3e-3 and c.r0 == 1.5 and c.fext is None
+    assert DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), device="cpu").to_c().bond == _lib.LB_BOND_HARMONIC
+    with pytest.raises(ValueError):
+        DeviceBeads(pos, np.zeros((3, 3)), np.ones(2), np.ones(2), device="cpu")
+    with pytest.raises(ValueError):
+        DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), device="cpu", bond="morse")
+
+
+def test_random_walk_chains():
+    from paper_0803_2826_amd.inputs import random_walk_chains
+    pos, mom, bonds = random_walk_chains(5, 12, (16, 20, 24), seed=3)
+    assert pos.shape == (60, 3) and bonds.shape == (55, 2) and bonds.dtype == np.int32
+    d = pos[bonds[:, 1]] - pos[bonds[:, 0]]
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, rtol=1e-14)
+    starts = pos[::12]
+    assert (starts >= 0).all() and (starts < [16, 20, 24]).all()
+    assert not mom.any()
+    again = random_walk_chains(5, 12, (16, 20, 24), seed=3)[0]
+    assert np.array_equal(pos, again)
+
+
+def test_kremer_grest_chains_are_self_avoiding():
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    L = np.array([10.0, 12.0, 9.0])
+    pos, _, bonds = kremer_grest_chains(6, 15, tuple(L), seed=4)
+    d = pos[bonds[:, 1]] - pos[bonds[:, 0]]
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), 0.97, rtol=1e-14)
+    # every pair at least 0.95 apart at the minimum image
+    dd = pos[:, None, :] - pos[None, :, :]
+    dd -= L * np.round(dd / L)
+    r = np.linalg.norm(dd, axis=2)
+    r[np.diag_indices_from(r)] = np.inf
+    assert r.min() >= 0.95 - 1e-12
+    assert np.array_equal(pos, kremer_grest_chains(6, 15, tuple(L), seed=4)[0])
+
+
+def test_shear_wave_and_edges():
+    from paper_0803_2826_amd.forms import edge_draws, rounding_shrink
+    from paper_0803_2826_amd.inputs import shear_wave
+    u = shear_wave(4, 3, 32, 0.01)
+    assert u.shape == (3, 32, 3, 4)
+    np.testing.assert_allclose(u[0, :, 1, 2], 0.01 * np.sin(2 * np.pi * np.arange(32) / 32))
+    assert not u[1:].any()
+    e = edge_draws(512, seed=0)
+    assert len(e) == 512 and {v[0] for v in e} == {24, 32, 40, 48, 64}
+    assert all(v[0] == v[1] == v[2] for v in e)
+    assert rounding_shrink("bf16") == pytest.approx(2.0 ** -14 / (32 * math.log(2)))
