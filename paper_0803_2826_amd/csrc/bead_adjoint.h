@@ -179,11 +179,11 @@ __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, co
 }
 
 // Recompute sweep of a segment: keep the spread force of a coupled step
-// compactly (its touched nodes and their force values) while zeroing the
-// force field and its bitmap, so that the adjoint sweep can restore it
-// without running the particle half again.
-__global__ void k_save_clear_touched(float *force, uint32_t *fmask, const int32_t *list, const int32_t *count,
-                                     int cap, uint32_t N, int32_t *slist, int32_t *scount, float *svals)
+// compactly (its touched nodes and their force values) before the step
+// consumes it, so that the adjoint sweep can restore it without running the
+// particle half again.
+__global__ void k_save_touched(const float *force, const int32_t *list, const int32_t *count, int cap, uint32_t N,
+                               int32_t *slist, int32_t *scount, float *svals)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int cnt = min(*count, cap);
@@ -191,11 +191,7 @@ __global__ void k_save_clear_touched(float *force, uint32_t *fmask, const int32_
     if (idx >= cnt) return;
     const uint32_t s = (uint32_t)list[idx];
     slist[idx] = (int32_t)s;
-    for (int c = 0; c < 3; ++c) {
-        svals[3 * idx + c] = force[(size_t)c * N + s];
-        force[(size_t)c * N + s] = 0.f;
-    }
-    fmask[s >> 5] = 0u;
+    for (int c = 0; c < 3; ++c) svals[3 * idx + c] = force[(size_t)c * N + s];
 }
 
 // Adjoint sweep: put a saved spread force back (values, bitmap bits, the

@@ -21,7 +21,8 @@
 //                   (eq. ftotal), setting the node's bit in the force bitmap;
 //                   R = R' + (h/2) P''/m
 //   (next lb_step)  the fused stream-collide kernel adds the bead force at
-//                   flagged sites, then k_clear_touched zeroes force and bits.
+//                   flagged sites and leaves those force rows and bitmap
+//                   words zero.
 #pragma once
 
 #include "aux_kernels.h"
@@ -255,20 +256,6 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
             a.mom[3 * b + c] = Pn[c];
             a.pos[3 * b + c] = a.half[3 * b + c] + 0.5 * h * Pn[c] / m;
         }
-}
-
-// After the step that consumed the bead force: zero the force and the bitmap
-// word of every touched node (all set bits belong to listed nodes).
-__global__ void k_clear_touched(float *force, uint32_t *fmask, const int32_t *list, const int32_t *count, int cap,
-                                uint32_t N)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cap || idx >= *count) return;
-    const uint32_t s = (uint32_t)list[idx];
-    force[s] = 0.f;
-    force[(size_t)N + s] = 0.f;
-    force[2 * (size_t)N + s] = 0.f;
-    fmask[s >> 5] = 0u;
 }
 
 }  // namespace lbmi

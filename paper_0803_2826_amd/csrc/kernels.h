@@ -243,8 +243,9 @@ struct StepArgs {
     uint32_t xcd_remap;   // 1: map blocks so that consecutive tiles share an XCD
     double *partials;     // [gridDim][4] per-block totals (TOTALS only)
     int32_t *flags;       // bit 0: non-finite density seen
-    const uint32_t *fmask;  // [ceil(N/32)] 1 bit per site: bead force present (FORCE only)
-    const float *force;     // [3][N] bead force density at flagged sites (FORCE only)
+    uint32_t *fmask;        // [ceil(N/32)] 1 bit per site: bead force present (FORCE only)
+    float *force;           // [3][N] bead force density at flagged sites (FORCE only)
+    uint32_t consume;       // FORCE: 1 = zero the force rows and bitmap words this step read
 };
 
 __device__ __forceinline__ uint32_t tile_index(uint32_t remap)
@@ -368,11 +369,21 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         const mass_acc_t<ST> m_in = site_mass<ST>(d);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         if (FORCE) {
-            if ((a.fmask[s >> 5] >> (s & 31u)) & 1u) {
+            const uint32_t word = a.fmask[s >> 5];
+            if ((word >> (s & 31u)) & 1u) {
                 F[0] += a.force[s];
                 F[1] += a.force[(size_t)N + s];
                 F[2] += a.force[2 * (size_t)N + s];
+                if (a.consume) {
+                    a.force[s] = 0.f;
+                    a.force[(size_t)N + s] = 0.f;
+                    a.force[2 * (size_t)N + s] = 0.f;
+                }
             }
+            // The 32 sites of a bitmap word lie in one wave (waves start at
+            // multiples of 64 sites) and read the word with one instruction;
+            // its first site clears it once the loaded value is known.
+            if (a.consume && (s & 31u) == 0u && word != 0u) a.fmask[s >> 5] = 0u;
         }
         float out[Q];
         collide_site<THERMAL>(d, F, a.cc, s, a.step, out);

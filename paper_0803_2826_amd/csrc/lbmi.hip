@@ -573,6 +573,7 @@ StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
     a.flags = c->flags;
     a.fmask = nullptr;
     a.force = nullptr;
+    a.consume = 0u;
     return a;
 }
 
@@ -1089,27 +1090,16 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         const bool frc = c->pending_force;
         LB_TRY(select_launch(c, frc));
         if (c->taping) c->tape_slot.push_back(frc ? c->pending_slot : -1);
-        StepArgs a;
-        a.src = c->bufA;
-        a.dst = c->bufB;
-        for (int i = 0; i < 19; ++i) {
-            a.srcp[i] = static_cast<const char *>(c->bufA) + (size_t)i * c->geo.N * c->elem;
-            a.dstp[i] = static_cast<char *>(c->bufB) + (size_t)i * c->geo.N * c->elem;
+        StepArgs a = plain_step_args(c, c->bufA, c->bufB, (uint32_t)c->step);
+        if (frc) {
+            // the step reads the bead force and leaves the field and its bitmap zero
+            a.fmask = c->fmask;
+            a.force = c->force;
+            a.consume = 1u;
         }
-        a.geo = c->geo;
-        a.cc = c->cc;
-        a.step = (uint32_t)c->step;
-        a.xcd_remap = c->xcd_remap;
-        a.partials = c->partials;
-        a.flags = c->flags;
-        a.fmask = c->fmask;
-        a.force = c->force;
         by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
         LB_LAUNCH_CHECK(c, "stream_collide");
         if (frc) {
-            hipLaunchKernelGGL(k_clear_touched, dim3(grid_for((size_t)c->pending_rows, 256)), dim3(256), 0, c->stream,
-                               c->force, c->fmask, c->list, c->count, c->pending_rows, c->geo.N);
-            LB_LAUNCH_CHECK(c, "clear_touched");
             c->pending_force = false;
             c->pending_slot = -1;
         }
@@ -1480,15 +1470,13 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 launch_couple(c, seg + (size_t)k * sb, &c->tape_beads[slot], snap, snap + n3, pos_w, v.mom, step);
                 c->half = ctx_half;
                 c->fc = ctx_fc;
+                hipLaunchKernelGGL(k_save_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
+                                   c->force, c->list, c->count, seg_rows, c->geo.N, v.list, v.count, v.vals);
                 a.fmask = c->fmask;
                 a.force = c->force;
+                a.consume = 1u;
             }
             by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, slot >= 0); });
-            if (slot >= 0) {
-                const Saved v = saved(k);
-                hipLaunchKernelGGL(k_save_clear_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
-                                   c->force, c->fmask, c->list, c->count, seg_rows, c->geo.N, v.list, v.count, v.vals);
-            }
         }
         if ((rc = hipGetLastError() == hipSuccess ? LB_OK : fail(c, LB_EDEVICE, "backward recompute")) != LB_OK) break;
         for (int k = len - 1; k >= 0; --k) {
