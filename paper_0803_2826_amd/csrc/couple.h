@@ -3,18 +3,18 @@
 // gathered from the stored populations.
 //
 // One coupled step on the device:
-//   k_bead_half     R' = R + (h/2) P/m; zero the conservative force; reset
-//                   the touched-node count
-//   k_bonds         harmonic or FENE bond forces at R' (FP64 atomics into
-//                   zeros: a bead with at most two bonds gets the same bits on
-//                   every run)
+//   k_bead_half     R' = R + (h/2) P/m; harmonic or FENE bond forces at R'
+//                   (FP64 atomics into a zeroed accumulator: a bead with at
+//                   most two bonds gets the same bits on every run); zero the
+//                   other accumulator for the next call; reset the
+//                   touched-node count
 //   k_cell_* k_wca  WCA pair forces at R' with a cell list (pairs.h), when on
-//   k_add_fext      the external bead force, when given
 //   k_bead_update   one lane per stencil node (W^3 of them, W = 2, 3, 4 for the
 //                   kernels phi_2, phi_3, phi_4 of eq. 2point, eq. 3point,
 //                   eq. 4point): each lane gathers its node's 19 populations
 //                   and forms w u(node) with u = (sum n c + g/2)/rho and the
 //                   product weight of eq. Delta; a lane reduction gives u_b;
+//                   F^c = (bonds + pairs) + fext, kept for the adjoint;
 //                   every lane then evaluates P'' = C1 P + C2 (F^c + zeta u_b)
 //                   + C3 theta (eq. langevin_momentum_update) and spreads
 //                   w I / h with I = -(P'' - P - h F^c) to its own node
@@ -44,31 +44,77 @@ struct CoupleArgs {
     double *mom;
     const double *mass;
     const double *zeta;
-    double *half;         // [n][3]
-    double *fc;           // [n][3]
+    double *half;         // [n][3] out: R'
+    double *fc;           // [n][3] out: the conservative force F^c at R' (bonds + pairs + fext)
+    double *fb;           // [n][3] bond forces, accumulated here (zero on entry)
+    double *fb_next;      // [cap][3] the other bond accumulator, zeroed here for the next call
+    int32_t cap;          // entries of fb_next to zero
+    const double *fp;     // [n][3] pair (WCA) forces at R' or NULL
+    const double *fext;   // [n][3] external forces or NULL
+    const int32_t *bonds; // [nbonds][2]
+    int32_t nbonds;
+    int32_t fene;         // 1: FENE bonds, 0: harmonic
+    double kb, r0;
+    int32_t *flags;       // bit 1: a FENE bond at r >= r0
     float *force;         // [3][N] sparse force field (zero outside touched nodes)
     uint32_t *fmask;      // [ceil(N/32)] force bitmap
     int32_t *list;        // [8 n] touched nodes
     int32_t *count;       // number of entries in list
 };
 
-__global__ void k_bead_half(CoupleArgs a)
+// R' = R + (h/2) P/m of bead b, component c (one expression wherever R' is
+// formed, so that every kernel sees the same bits).
+__device__ __forceinline__ double half_coord(const CoupleArgs &a, int b, int c)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b == 0) *a.count = 0;
-    if (b >= a.n) return;
-    const double m = a.mass[b];
+    return a.pos_in[3 * b + c] + 0.5 * a.mom_in[3 * b + c] / a.mass[b];
+}
+
+// Bond forces at R': F_b = mag d = -F_a, d = R'_b - R'_a, with
+// mag = -k (r - r0) / r (harmonic) or mag = -k / (1 - r^2/r0^2) (FENE,
+// eq. ufene; NaN at r >= r0, latched as bit 1 of *flags), added to a.fb.
+__device__ __forceinline__ void bond_force(const CoupleArgs &a, int q)
+{
+    const int ia = a.bonds[2 * q], ib = a.bonds[2 * q + 1];
+    if (ia < 0 || ib < 0 || ia >= a.n || ib >= a.n) return;
+    double d[3], r2 = 0.0;
     for (int c = 0; c < 3; ++c) {
-        a.half[3 * b + c] = a.pos_in[3 * b + c] + 0.5 * a.mom_in[3 * b + c] / m;
-        a.fc[3 * b + c] = 0.0;
+        d[c] = half_coord(a, ib, c) - half_coord(a, ia, c);
+        r2 += d[c] * d[c];
+    }
+    double mag;
+    if (a.fene) {
+        const double x = r2 / (a.r0 * a.r0);
+        if (x < 1.0) {
+            mag = -a.kb / (1.0 - x);
+        } else {
+            mag = __builtin_nan("");
+            __hip_atomic_fetch_or(a.flags, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        const double r = sqrt(r2);
+        if (r == 0.0) return;
+        mag = -a.kb * (r - a.r0) / r;
+    }
+    for (int c = 0; c < 3; ++c) {
+        atomicAdd(&a.fb[3 * ib + c], mag * d[c]);
+        atomicAdd(&a.fb[3 * ia + c], -mag * d[c]);
     }
 }
 
-// Last term of the conservative force: F^c = (bonds + pairs) + fext.
-__global__ void k_add_fext(int n, const double *__restrict__ fext, double *fc)
+// One thread per bead, per bond and per entry of the idle bond accumulator
+// (grid of max(n, nbonds, cap) threads): R' of the bead, the bond's forces
+// (each bond forms R' of its two beads itself, so nothing waits for the
+// first role), zero the accumulator of the next call, reset the touched-node
+// count.
+__global__ void k_bead_half(CoupleArgs a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < 3 * n) fc[k] += fext[k];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *a.count = 0;
+    if (t < a.n)
+        for (int c = 0; c < 3; ++c) a.half[3 * t + c] = half_coord(a, t, c);
+    if (t < a.cap)
+        for (int c = 0; c < 3; ++c) a.fb_next[3 * t + c] = 0.0;
+    if (t < a.nbonds) bond_force(a, t);
 }
 
 // Interpolation kernels phi_W (eq. 2point, eq. 3point, eq. 4point) and their
@@ -151,41 +197,6 @@ __device__ __forceinline__ double bead_sum(double v)
     return v;
 }
 
-// Bond forces at R': F_b = mag d = -F_a, d = R'_b - R'_a, with
-// mag = -k (r - r0) / r (harmonic) or mag = -k / (1 - r^2/r0^2) (FENE,
-// eq. ufene; NaN at r >= r0, latched as bit 1 of *flags).
-__global__ void k_bonds(const double *__restrict__ half, double *fc, const int32_t *__restrict__ bonds, int nbonds,
-                        double kb, double r0, int nbeads, int fene, int32_t *flags)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nbonds) return;
-    const int ia = bonds[2 * q], ib = bonds[2 * q + 1];
-    if (ia < 0 || ib < 0 || ia >= nbeads || ib >= nbeads) return;
-    double d[3], r2 = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        d[c] = half[3 * ib + c] - half[3 * ia + c];
-        r2 += d[c] * d[c];
-    }
-    double mag;
-    if (fene) {
-        const double x = r2 / (r0 * r0);
-        if (x < 1.0) {
-            mag = -kb / (1.0 - x);
-        } else {
-            mag = __builtin_nan("");
-            __hip_atomic_fetch_or(flags, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else {
-        const double r = sqrt(r2);
-        if (r == 0.0) return;
-        mag = -kb * (r - r0) / r;
-    }
-    for (int c = 0; c < 3; ++c) {
-        atomicAdd(&fc[3 * ib + c], mag * d[c]);
-        atomicAdd(&fc[3 * ia + c], -mag * d[c]);
-    }
-}
-
 // StencilLanes<W> consecutive lanes per bead (blockDim a multiple of 64).
 template <int ST, int W>
 __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
@@ -237,11 +248,15 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
     }
     double th[3] = {0.0, 0.0, 0.0};
     if (a.kT > 0.0 && z > 0.0) bead_normals((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
-    double Pn[3], I[3];
+    double Pn[3], I[3], Fc[3];
     for (int c = 0; c < 3; ++c) {
-        const double P = a.mom_in[3 * b + c], Fc = a.fc[3 * b + c];
-        Pn[c] = C1 * P + C2 * (Fc + z * ub[c]) + C3 * th[c];
-        I[c] = -(Pn[c] - P - h * Fc);
+        // F^c = (bonds + pairs) + fext
+        Fc[c] = a.fb[3 * b + c];
+        if (a.fp) Fc[c] += a.fp[3 * b + c];
+        if (a.fext) Fc[c] += a.fext[3 * b + c];
+        const double P = a.mom_in[3 * b + c];
+        Pn[c] = C1 * P + C2 * (Fc[c] + z * ub[c]) + C3 * th[c];
+        I[c] = -(Pn[c] - P - h * Fc[c]);
     }
     if (wq != 0.0) {
         for (int c = 0; c < 3; ++c) atomicAdd(&a.force[(size_t)c * g.N + node], (float)(wq * I[c] / h));
@@ -255,6 +270,7 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
         for (int c = 0; c < 3; ++c) {
             a.mom[3 * b + c] = Pn[c];
             a.pos[3 * b + c] = a.half[3 * b + c] + 0.5 * h * Pn[c] / m;
+            a.fc[3 * b + c] = Fc[c];
         }
 }
 

@@ -57,6 +57,9 @@ struct lb_ctx {
     int list_cap = 0;
     double *half = nullptr;
     double *fc = nullptr;
+    double *fb2 = nullptr;           // [2][cap][3] bond-force accumulators, used by alternate calls
+    double *fp = nullptr;            // [cap][3] WCA pair forces
+    int fb_par = 0;                  // accumulator of the next call
     int bead_cap = 0;
     bool pending_force = false;
     int pending_rows = 0;            // upper bound of touched nodes (8 per bead)
@@ -336,13 +339,23 @@ int ensure_bead_buffers(lb_ctx *c, int n)
         (void)hipFree(c->half);
         (void)hipFree(c->fc);
         (void)hipFree(c->list);
-        c->half = c->fc = nullptr;
+        (void)hipFree(c->fb2);
+        (void)hipFree(c->fp);
+        c->half = c->fc = c->fb2 = c->fp = nullptr;
         c->list = nullptr;
+        c->bead_cap = 0;
         const int cap = n < 64 ? 64 : n;
         if (hipMalloc(&c->half, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->fc, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->fb2, 6 * (size_t)cap * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->fp, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->list, 64 * (size_t)cap * sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead scratch allocation failed");
+        // both bond accumulators start at zero; each call zeroes the other one
+        hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(12 * (size_t)cap, 256)), dim3(256), 0, c->stream,
+                           reinterpret_cast<float *>(c->fb2), 12 * (size_t)cap);
+        LB_LAUNCH_CHECK(c, "zero bond accumulators");
+        c->fb_par = 0;
         c->bead_cap = cap;
         c->list_cap = 64 * cap;
     }
@@ -447,9 +460,8 @@ int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
     return LB_OK;
 }
 
-// WCA forces at the half-step positions, added to c->fc with the external
-// force: rebuild the cell list, then kPairLanes lanes per bead over its
-// neighbour cells.
+// WCA forces at the half-step positions into c->fp: rebuild the cell list,
+// then kPairLanes lanes per bead over its neighbour cells.
 void launch_wca(lb_ctx *c, const lb_beads *b)
 {
     const CellGrid cg = cell_grid(c, b);
@@ -465,17 +477,17 @@ void launch_wca(lb_ctx *c, const lb_beads *b)
     hipLaunchKernelGGL(k_cell_rank, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->cell_start,
                        c->cell_sorted, c->half, c->cell_pos);
     hipLaunchKernelGGL(k_wca, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, c->half, b->n,
-                       cg, c->bead_cell, c->cell_start, c->cell_pos, b->fext, c->fc);
+                       cg, c->bead_cell, c->cell_start, c->cell_pos, c->fp);
 }
 
 // Threads per block of the per-bead stencil kernels: one wave, so that a few
 // thousand beads spread over many CUs (the kernels are latency-bound).
 constexpr int kBeadBlock = 64;
 
-// The particle half of one coupled step (k_bead_half, k_bonds, the WCA pair
-// search, k_add_fext, k_bead_update) on the populations `pop`, updating
-// (pos, mom) in place and spreading into the force field, its bitmap and the
-// touched-node list.
+// The particle half of one coupled step (k_bead_half with the bonds, the WCA
+// pair search, k_bead_update) on the populations `pop`: (pos_in, mom_in) ->
+// (pos, mom) (the same arrays for lb_couple), spreading into the force field,
+// its bitmap and the touched-node list, with R' in c->half and F^c in c->fc.
 void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *pos_in, const double *mom_in,
                    double *pos, double *mom, uint32_t step)
 {
@@ -498,20 +510,27 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     a.zeta = b->zeta;
     a.half = c->half;
     a.fc = c->fc;
+    const size_t n3cap = 3 * (size_t)c->bead_cap;
+    a.fb = c->fb2 + (size_t)c->fb_par * n3cap;
+    a.fb_next = c->fb2 + (size_t)(c->fb_par ^ 1) * n3cap;
+    c->fb_par ^= 1;
+    a.cap = c->bead_cap;
+    const bool wca = b->wca_epsilon > 0.0;
+    a.fp = wca ? c->fp : nullptr;
+    a.fext = b->fext;
+    a.bonds = b->bonds;
+    a.nbonds = b->nbonds;
+    a.fene = (int32_t)(b->bond == LB_BOND_FENE);
+    a.kb = b->k_bond;
+    a.r0 = b->r0;
+    a.flags = c->flags;
     a.force = c->force;
     a.fmask = c->fmask;
     a.list = c->list;
     a.count = c->count;
-    const unsigned gb = grid_for((size_t)b->n, 256);
-    hipLaunchKernelGGL(k_bead_half, dim3(gb), dim3(256), 0, c->stream, a);
-    if (b->nbonds > 0)
-        hipLaunchKernelGGL(k_bonds, dim3(grid_for((size_t)b->nbonds, 256)), dim3(256), 0, c->stream, c->half, c->fc,
-                           b->bonds, b->nbonds, b->k_bond, b->r0, b->n, (int)(b->bond == LB_BOND_FENE), c->flags);
-    if (b->wca_epsilon > 0.0)
-        launch_wca(c, b);  // adds fext too
-    else if (b->fext)
-        hipLaunchKernelGGL(k_add_fext, dim3(grid_for(3 * (size_t)b->n, 256)), dim3(256), 0, c->stream, b->n, b->fext,
-                           c->fc);
+    const size_t roles = std::max<size_t>({(size_t)b->n, (size_t)b->nbonds, (size_t)c->bead_cap});
+    hipLaunchKernelGGL(k_bead_half, dim3(grid_for(roles, 256)), dim3(256), 0, c->stream, a);
+    if (wca) launch_wca(c, b);
     by_storage(c->p.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         by_stencil(b->stencil, [&](auto w) {
@@ -970,7 +989,7 @@ int lb_destroy(lb_ctx *c)
                     c->force,      c->fmask,     c->list,      c->count,     c->half,      c->fc,
                     c->boxes_d,    c->tile_box,  c->dstep,     c->amp,       c->ring,      c->corr,
                     c->cell_count, c->cell_start, c->bead_cell, c->bead_slot, c->cell_sorted, c->scan_tmp,
-                    c->cell_pos};
+                    c->cell_pos,   c->fb2,        c->fp};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int k = 0; k < 2; ++k)

@@ -23,7 +23,7 @@
 //                   fewer on one-cell axes) in cell order; a fixed butterfly
 //                   sums the lanes.  Every pair is evaluated from both ends,
 //                   so no atomics are needed and the bits are the same on
-//                   every run.  The external force is added last.
+//                   every run.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -92,13 +92,12 @@ __global__ void k_cell_rank(int n, const int32_t *__restrict__ cell_of, const in
 
 constexpr int kPairLanes = 32;
 
-// F_i += sum_j f(r_ij) (R_i - R_j) over beads j != i within r_c, with
+// fp_i = sum_j f(r_ij) (R_i - R_j) over beads j != i within r_c, with
 // f = 24 eps (2 (sigma/r)^12 - (sigma/r)^6) / r^2 = -V'(r)/r of eq. ulennardjones.
 // kPairLanes consecutive lanes per bead (blockDim a multiple of 64).
 __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, int n, CellGrid cg,
                                              const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
-                                             const double4 *__restrict__ cpos, const double *__restrict__ fext,
-                                             double *fc)
+                                             const double4 *__restrict__ cpos, double *fp)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kPairLanes, l = t % kPairLanes;
@@ -151,7 +150,7 @@ __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, in
         for (int off = 1; off < kPairLanes; off <<= 1) F[a] += __shfl_xor(F[a], off, 64);
     if (i < n && l == 0)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fc[3 * i + a] = (fc[3 * i + a] + F[a]) + (fext ? fext[3 * i + a] : 0.0);
+        for (int a = 0; a < 3; ++a) fp[3 * i + a] = F[a];
 }
 
 }  // namespace lbmi
