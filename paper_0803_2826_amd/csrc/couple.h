@@ -258,13 +258,22 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
         Pn[c] = C1 * P + C2 * (Fc[c] + z * ub[c]) + C3 * th[c];
         I[c] = -(Pn[c] - P - h * Fc[c]);
     }
+    bool first = false;  // this lane set its node's bit: the node joins the touched list
     if (wq != 0.0) {
         for (int c = 0; c < 3; ++c) atomicAdd(&a.force[(size_t)c * g.N + node], (float)(wq * I[c] / h));
         const uint32_t bit = 1u << (node & 31u);
-        if ((atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u) {
-            const int slot = atomicAdd(a.count, 1);
-            a.list[slot] = (int32_t)node;
-        }
+        first = (atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u;
+    }
+    // list slots for the whole wave with one atomic on the shared count (the
+    // lanes still running here are exactly the live ones)
+    const uint64_t newcomers = __ballot(first);
+    if (newcomers) {
+        const int lane = (int)__lane_id();
+        const int leader = __ffsll((unsigned long long)newcomers) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(a.count, (int)__popcll(newcomers));
+        base = __shfl(base, leader, 64);
+        if (first) a.list[base + (int)__popcll(newcomers & ((1ull << lane) - 1ull))] = (int32_t)node;
     }
     if (q == 0)
         for (int c = 0; c < 3; ++c) {
