@@ -722,15 +722,19 @@ float time_launches(lb_ctx *c, int reps, const std::function<void()> &launch)
 int autotune(lb_ctx *c)
 {
     if (c->batch) {
+        // blocks per CU of the persistent launch; 0 = one tile per block (no
+        // tile loop, the hardware deals tiles out), only without the VACF,
+        // whose per-box sums are flushed once per block
         const int blocks[] = {128, 256, 512, 1024};
-        const int per_cu[] = {2, 4, 8, 16};
+        const int per_cu[] = {2, 4, 8, 16, 0};
         float best = 1e30f;
         int bb = 256;
         uint32_t bc = 1;
         for (int blk : blocks) {
             LB_TRY(batch_build_tiles(c, blk));
             for (int pc : per_cu) {
-                const uint32_t grid = 256u * (uint32_t)pc;
+                if (pc == 0 && c->p.vacf_lags > 0) continue;
+                const uint32_t grid = pc > 0 ? 256u * (uint32_t)pc : c->ntiles;
                 c->chunk = std::max<uint32_t>(1u, (c->ntiles + grid - 1) / grid);
                 const float ms = time_launches(c, 3, [&] { batch_launch_step(c, c->bufA, c->bufB, false); });
                 LB_LAUNCH_CHECK(c, "autotune batch");
