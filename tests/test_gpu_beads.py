@@ -118,3 +118,43 @@ def test_bead_on_node_and_wrapping(orc, lat):
     np.testing.assert_allclose(bd.mom.cpu().numpy(), bo.mom, atol=1e-7)
     assert np.abs(dev.get_populations().cpu().numpy() - n).max() <= 1e-6
     dev.close()
+
+
+def test_changing_bead_sets_and_plain_steps(orc, lat):
+    """Bead sets of different sizes in consecutive coupled steps (a larger one
+    after a smaller one reuses the bond accumulators), plain steps after a
+    coupled one (the step consumes the spread force: nothing is left for the
+    next step), an external force on one set, all against the oracle."""
+    import torch
+    from paper_0803_2826_amd.inputs import random_walk_chains
+    L, kT = 16, 1e-4
+    po = orc.Params(nx=L, ny=L, nz=L, kT=kT, seed=11, g=(0.0, 2e-6, 0.0))
+    pd = lat.FluidParams(nx=L, ny=L, nz=L, kT=kT, seed=11, body_force=(0.0, 2e-6, 0.0))
+    sets = []
+    for n_chains, length, seed in ((6, 10, 1), (2, 5, 2), (6, 10, 3)):
+        pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed)
+        nb = pos.shape[0]
+        fext = np.random.default_rng(seed).normal(scale=1e-4, size=(nb, 3)) if seed == 2 else None
+        sets.append((orc.Beads(pos.copy(), mom.copy(), np.ones(nb), np.full(nb, 5.0), bonds.copy(), 1e-3, 1.0,
+                               fext=None if fext is None else fext.copy()),
+                     lat.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 5.0), bonds, 1e-3, 1.0, fext=fext)))
+    n = orc.init_equilibrium(po)
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n))
+    t = 0
+    for rep in range(2):
+        for ob, db in sets:
+            orc.coupled_step(po, n, t, ob)
+            dev.coupled_step(db)
+            t += 1
+            for _ in range(2):  # plain steps in between
+                orc.step(po, n, t)
+                t += 1
+            dev.step(2)
+    got = dev.get_populations().cpu().numpy()
+    print("pop err", np.abs(got - n).max())
+    assert np.abs(got - n).max() <= 1e-6
+    for ob, db in sets:
+        np.testing.assert_allclose(db.pos.cpu().numpy(), ob.pos, atol=1e-7)
+        np.testing.assert_allclose(db.mom.cpu().numpy(), ob.mom, atol=1e-7)
+    dev.close()
