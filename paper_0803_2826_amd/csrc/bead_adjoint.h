@@ -1,5 +1,5 @@
 // Differentiation form, particle half: adjoint (reverse mode) of one
-// coupled step's bead kernels (k_bead_half, k_bonds, k_bead_update of
+// coupled step's bead kernels (k_bead_half with its bond forces, k_bead_update of
 // couple.h; Sec. "Force coupling", Sec. "Interpolating functions").
 //
 // The forward map of the particle half, per bead (h = 1):
