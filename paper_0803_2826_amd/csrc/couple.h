@@ -18,8 +18,9 @@
 //                   every lane then evaluates P'' = C1 P + C2 (F^c + zeta u_b)
 //                   + C3 theta (eq. langevin_momentum_update) and spreads
 //                   w I / h with I = -(P'' - P - h F^c) to its own node
-//                   (eq. ftotal), setting the node's bit in the force bitmap;
-//                   R = R' + (h/2) P''/m
+//                   (eq. ftotal), setting the node's bit in the force bitmap
+//                   (and, for the backward sweep, listing the nodes it is the
+//                   first to flag); R = R' + (h/2) P''/m
 //   (next lb_step)  the fused stream-collide kernel adds the bead force at
 //                   flagged sites and leaves those force rows and bitmap
 //                   words zero.
@@ -58,7 +59,7 @@ struct CoupleArgs {
     int32_t *flags;       // bit 1: a FENE bond at r >= r0
     float *force;         // [3][N] sparse force field (zero outside touched nodes)
     uint32_t *fmask;      // [ceil(N/32)] force bitmap
-    int32_t *list;        // [8 n] touched nodes
+    int32_t *list;        // [W^3 n] touched nodes, or NULL (no list kept)
     int32_t *count;       // number of entries in list
 };
 
@@ -109,7 +110,7 @@ __device__ __forceinline__ void bond_force(const CoupleArgs &a, int q)
 __global__ void k_bead_half(CoupleArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) *a.count = 0;
+    if (t == 0 && a.list) *a.count = 0;
     if (t < a.n)
         for (int c = 0; c < 3; ++c) a.half[3 * t + c] = half_coord(a, t, c);
     if (t < a.cap)
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
     if (z > 0.0) {
         C1 = exp(-z * h / m);
         C2 = (m / z) * (1.0 - C1);
-        C3 = sqrt(m * a.kT * (1.0 - exp(-2.0 * z * h / m)));
+        C3 = sqrt(m * a.kT * (1.0 - C1 * C1));  // exp(-2 zeta h/m) = C1^2
     } else {
         C1 = 1.0;
         C2 = h;
@@ -262,11 +263,14 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
     if (wq != 0.0) {
         for (int c = 0; c < 3; ++c) atomicAdd(&a.force[(size_t)c * g.N + node], (float)(wq * I[c] / h));
         const uint32_t bit = 1u << (node & 31u);
-        first = (atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u;
+        if (a.list)
+            first = (atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u;
+        else
+            atomicOr(&a.fmask[node >> 5], bit);  // no list: the old bits are not needed
     }
     // list slots for the whole wave with one atomic on the shared count (the
     // lanes still running here are exactly the live ones)
-    const uint64_t newcomers = __ballot(first);
+    const uint64_t newcomers = a.list ? __ballot(first) : 0ull;
     if (newcomers) {
         const int lane = (int)__lane_id();
         const int leader = __ffsll((unsigned long long)newcomers) - 1;

@@ -489,7 +489,7 @@ constexpr int kBeadBlock = 64;
 // (pos, mom) (the same arrays for lb_couple), spreading into the force field,
 // its bitmap and the touched-node list, with R' in c->half and F^c in c->fc.
 void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *pos_in, const double *mom_in,
-                   double *pos, double *mom, uint32_t step)
+                   double *pos, double *mom, uint32_t step, bool with_list)
 {
     CoupleArgs a;
     a.pop = pop;
@@ -526,7 +526,9 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     a.flags = c->flags;
     a.force = c->force;
     a.fmask = c->fmask;
-    a.list = c->list;
+    // the touched-node list is only read by the backward sweep (the step
+    // finds the touched nodes in the bitmap and clears them itself)
+    a.list = with_list ? c->list : nullptr;
     a.count = c->count;
     const size_t roles = std::max<size_t>({(size_t)b->n, (size_t)b->nbonds, (size_t)c->bead_cap});
     hipLaunchKernelGGL(k_bead_half, dim3(grid_for(roles, 256)), dim3(256), 0, c->stream, a);
@@ -1172,7 +1174,7 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     }
     c->pending_slot = -1;
     if (c->taping) LB_TRY(tape_bead_snapshot(c, b));
-    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step);
+    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step, false);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
     const int W = (b->stencil == 3 || b->stencil == 4) ? b->stencil : 2;
@@ -1439,7 +1441,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     auto rebuild_force = [&](int slot, const void *pop, uint32_t step) {
         const size_t n3 = 3 * (size_t)nbd;
         const double *snap = c->snap + (size_t)slot * 2 * n3;
-        launch_couple(c, pop, &c->tape_beads[slot], snap, snap + n3, pos_w, mom_w, step);
+        launch_couple(c, pop, &c->tape_beads[slot], snap, snap + n3, pos_w, mom_w, step, true);
     };
     auto clear_force = [&]() {
         hipLaunchKernelGGL(k_clear_touched_adj, dim3(grid_for(64 * (size_t)nbd, 256)), dim3(256), 0, c->stream,
@@ -1490,7 +1492,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 const double *snap = c->snap + (size_t)slot * 2 * n3;
                 c->half = v.half;
                 c->fc = v.fc;
-                launch_couple(c, seg + (size_t)k * sb, &c->tape_beads[slot], snap, snap + n3, pos_w, v.mom, step);
+                launch_couple(c, seg + (size_t)k * sb, &c->tape_beads[slot], snap, snap + n3, pos_w, v.mom, step,
+                              true);
                 c->half = ctx_half;
                 c->fc = ctx_fc;
                 hipLaunchKernelGGL(k_save_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
