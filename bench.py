@@ -53,6 +53,12 @@ KT = 1e-4
 # the explicit bead-fluid scheme diverge within ten steps at zeta = 20, m = 1.
 K_BOND = 10.0 * KT
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_256.json")
+# Friction of the Kremer-Grest chains: velocity relaxation time m/zeta = 5 steps
+# (0.05 of the Lennard-Jones time sigma sqrt(m/eps) = 100 steps at eps = kT).
+# With the harmonic chains' zeta = 20 the beads follow the lattice-scale fluid
+# noise so closely that the WCA core (eps = kT) is breached within ~100 steps
+# and a FENE bond overstretches, in the FP64 oracle as on the device.
+KG_ZETA = 0.2
 
 
 KERNEL_SOURCES = ("kernels.h", "collide.h", "rng.h")  # everything the fused step kernel is built from
@@ -246,7 +252,7 @@ def run_forms(L: int) -> dict:
     lat.init_equilibrium()
     pos, mom, bonds = kremer_grest_chains(64, 32, (L, L, L), seed=0)
     nb = pos.shape[0]
-    kg = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, 30 * KT, 1.5, bond="fene",
+    kg = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, KG_ZETA), bonds, 30 * KT, 1.5, bond="fene",
                              wca_epsilon=KT, wca_sigma=1.0)
     for _ in range(5):
         lat.coupled_step(kg)
@@ -268,7 +274,7 @@ def run_forms(L: int) -> dict:
     out["kg_coupled_mlups"] = round(L ** 3 / (ms * 1e-3) / 1e6, 1)
     out["kg_particle_half_ms"] = round(sum(a.elapsed_time(b) for a, b in half) / Tk, 4)
     out["kg_config"] = (f"{L}^3 fluid as above, 64 x 32 Kremer-Grest chains: FENE k = 30 kT, R0 = 1.5, WCA "
-                        f"eps = kT, sigma = 1 (cell list), zeta = 20, m = 1")
+                        f"eps = kT, sigma = 1 (cell list), zeta = {KG_ZETA}, m = 1")
     print("# forms: Kremer-Grest done", file=sys.stderr, flush=True)
     return out
 
@@ -297,9 +303,9 @@ def main() -> int:
 
         pos, mom, bonds = kremer_grest_chains(n_chains, length, (L, L, L), seed=0)
         nb = pos.shape[0]
-        beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, 30 * KT, 1.5, bond="fene",
+        beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, KG_ZETA), bonds, 30 * KT, 1.5, bond="fene",
                                     wca_epsilon=KT, wca_sigma=1.0)
-        chain_desc = "Kremer-Grest chains (FENE k=30 kT, R0=1.5; WCA eps=kT, sigma=1), zeta=20, m=1"
+        chain_desc = f"Kremer-Grest chains (FENE k=30 kT, R0=1.5; WCA eps=kT, sigma=1), zeta={KG_ZETA}, m=1"
     else:
         pos, mom, bonds = random_walk_chains(n_chains, length, (L, L, L), seed=0)
         nb = pos.shape[0]
