@@ -226,3 +226,29 @@ def test_kg_argument_errors(lat):
     assert code(p8, tape=True) == 0
     with pytest.raises(ValueError):
         lat.DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), bonds, bond="morse")
+
+
+def test_kg_chains_stay_bound_over_a_long_run(lat):
+    """500 coupled steps of FENE + WCA chains in a thermal fluid (eps = kT,
+    zeta = 0.2): momenta stay finite and every bond stays well inside the FENE
+    range (the mean bond length of a Kremer-Grest chain at eps = kT is about
+    0.97 sigma)."""
+    import torch
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    L, KT = 24, 1e-4
+    pos, mom, bonds = kremer_grest_chains(8, 32, (L, L, L), seed=0)
+    nb = pos.shape[0]
+    dev = lat.Lattice(lat.FluidParams(nx=L, ny=L, nz=L, kT=KT, seed=0, track_totals=False))
+    dev.init_equilibrium()
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 0.2), bonds, 30 * KT, 1.5, bond="fene", wca_epsilon=KT,
+                         wca_sigma=1.0)
+    for _ in range(500):
+        dev.coupled_step(db)
+    dev.sync()
+    p = db.pos.cpu().numpy()
+    d = np.linalg.norm(p[bonds[:, 1]] - p[bonds[:, 0]], axis=1)
+    print("bond length mean", d.mean(), "max", d.max())
+    assert np.isfinite(db.mom.cpu().numpy()).all()
+    assert d.max() < 1.35 and abs(d.mean() - 0.97) < 0.05
+    dev.close()
+    torch.cuda.synchronize()
