@@ -22,9 +22,8 @@ import numpy as np
 import pytest
 
 
-def one_bead(pos, mom=(0, 0, 0), m=1.0, zeta=20.0):
-    import oracle as O
-    return O.Beads(np.array([pos], float), np.array([mom], float), np.array([m]), np.array([zeta]))
+def one_bead(orc, pos, mom=(0, 0, 0), m=1.0, zeta=20.0):
+    return orc.Beads(np.array([pos], float), np.array([mom], float), np.array([m]), np.array([zeta]))
 
 
 def test_stencil_partition_and_first_moment(orc):
@@ -69,7 +68,7 @@ def test_linear_velocity_field_interpolated_exactly(orc):
     rng = np.random.default_rng(1)
     for _ in range(20):
         R = rng.uniform(2, 7, size=3)
-        b = one_bead(R, mom=(0, 0, 0), m=1.0, zeta=3.0)
+        b = one_bead(orc, R, mom=(0, 0, 0), m=1.0, zeta=3.0)
         Rh = R.copy()  # P = 0: half drift does not move it
         f = np.zeros((3, L, L, L))
         orc.couple(p, n, 0, b, f)
@@ -83,7 +82,7 @@ def test_ou_mean_decay_frozen_fluid(orc):
     p = orc.Params(nx=4, ny=4, nz=4)
     n = orc.init_equilibrium(p)
     m, z = 2.0, 0.7
-    b = one_bead((1.3, 2.2, 0.4), mom=(0.3, -0.2, 0.1), m=m, zeta=z)
+    b = one_bead(orc, (1.3, 2.2, 0.4), mom=(0.3, -0.2, 0.1), m=m, zeta=z)
     P0 = b.mom.copy()
     for t in range(5):
         f = np.zeros((3, 4, 4, 4))
@@ -91,22 +90,38 @@ def test_ou_mean_decay_frozen_fluid(orc):
     np.testing.assert_allclose(b.mom, P0 * math.exp(-z / m) ** 5, rtol=1e-14)
 
 
+@pytest.mark.parametrize("W", [2, 3, 4])
+def test_bead_in_forced_fluid_at_rest_sees_half_the_force(orc, W):
+    """A fluid at rest under a uniform body force g: the velocity a bead
+    interpolates on the first step is the physical one of
+    eq. special_choice_momentum_density, u = (j + g/2)/rho = g/2, so a bead
+    at rest without conservative force gets P'' = m (1 - exp(-zeta h/m)) g/2
+    (eq. langevin_momentum_update with kT = 0), for every kernel width."""
+    g = np.array([2e-5, -1e-5, 3e-5])
+    p = orc.Params(nx=8, ny=8, nz=8, g=tuple(g))
+    n = orc.init_equilibrium(p)
+    m, z = 1.5, 0.8
+    b = one_bead(orc, (3.3, 4.6, 2.1), m=m, zeta=z)
+    b.stencil = W
+    orc.couple(p, n, 0, b, np.zeros((3, 8, 8, 8)))
+    np.testing.assert_allclose(b.mom[0], m * (1 - math.exp(-z / m)) * g / 2, rtol=1e-12)
+
+
 def test_ou_variance_frozen_fluid(orc):
-    import oracle as O
     kT = 1e-4
     p = orc.Params(nx=4, ny=4, nz=4, kT=kT, seed=5)
     n = orc.init_equilibrium(p)
     nb = 20000
     m, z = 1.0, 20.0
     rng = np.random.default_rng(2)
-    beads = O.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z))
+    beads = orc.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z))
     f = np.zeros((3, 4, 4, 4))
     orc.couple(p, n, 0, beads, f)
     var1 = beads.mom.var()
     assert var1 == pytest.approx(m * kT * (1 - math.exp(-2 * z / m)), rel=0.03)
     # a bead with small friction approaches m kT
     z2 = 0.05
-    beads = O.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z2))
+    beads = orc.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z2))
     for t in range(3):
         orc.couple(p, n, t, beads, np.zeros((3, 4, 4, 4)))
     expect = m * kT * (1 - math.exp(-2 * z2 * 3 / m))
@@ -116,13 +131,12 @@ def test_ou_variance_frozen_fluid(orc):
 def test_bond_force_is_gradient(orc):
     """Two beads, zero friction (C2 = h), kT = 0: P'' = P + h F^c, so the bond
     force can be read off and compared with -dV/dr of V = (k/2)(r-r0)^2."""
-    import oracle as O
     p = orc.Params(nx=8, ny=8, nz=8)
     n = orc.init_equilibrium(p)
     k, r0 = 10.0, 1.0
     Ra = np.array([1.0, 2.0, 3.0])
     Rb = np.array([2.1, 2.4, 2.7])
-    beads = O.Beads(np.array([Ra, Rb]), np.zeros((2, 3)), np.ones(2), np.zeros(2),
+    beads = orc.Beads(np.array([Ra, Rb]), np.zeros((2, 3)), np.ones(2), np.zeros(2),
                     np.array([[0, 1]], np.int32), k, r0)
     orc.couple(p, n, 0, beads, np.zeros((3, 8, 8, 8)))
     Fb = beads.mom[1]
@@ -139,7 +153,6 @@ def test_bond_force_is_gradient(orc):
 def test_spread_sums_to_impulse_and_total_momentum(orc):
     """Coupled step: sum of spread force = sum of bead impulses; total fluid +
     bead momentum changes by exactly N g; fluid mass unchanged."""
-    import oracle as O
     L = 8
     g = (1e-5, 0.0, -2e-5)
     p = orc.Params(nx=L, ny=L, nz=L, kT=1e-4, g=g, seed=3)
@@ -150,7 +163,7 @@ def test_spread_sums_to_impulse_and_total_momentum(orc):
     steps *= 1.05 / np.linalg.norm(steps, axis=1, keepdims=True)  # bonds slightly stretched
     pos = np.cumsum(steps, 0) + 3.0
     bonds = np.array([[i, i + 1] for i in range(nb - 1)], np.int32)
-    beads = O.Beads(pos, rng.normal(scale=0.01, size=(nb, 3)), np.ones(nb), np.full(nb, 20.0), bonds, 0.1, 1.0)
+    beads = orc.Beads(pos, rng.normal(scale=0.01, size=(nb, 3)), np.ones(nb), np.full(nb, 20.0), bonds, 0.1, 1.0)
     c, a, e, w = orc.tables()
     for t in range(5):
         tot0 = orc.totals(p, n)
@@ -174,18 +187,17 @@ def test_coupled_bead_temperature(orc):
     scheme adds the lattice-scale fluid velocity variance interpolated at the
     bead, about 0.3 kT, on top of the bead noise; that excess belongs to the
     time discretisation, not to a coding error.)"""
-    import oracle as O
     L = 8
     kT = 1e-4
     p = orc.Params(nx=L, ny=L, nz=L, kT=kT, seed=21)
     n = orc.init_equilibrium(p)
     rng = np.random.default_rng(8)
     nb = 64
-    beads = O.Beads(rng.uniform(0, L, (nb, 3)), np.zeros((nb, 3)), np.ones(nb), np.full(nb, 0.25))
+    beads = orc.Beads(rng.uniform(0, L, (nb, 3)), np.zeros((nb, 3)), np.ones(nb), np.full(nb, 0.25))
     acc = 0.0
     cnt = 0
     for t in range(600):
-        O.coupled_step(p, n, t, beads)
+        orc.coupled_step(p, n, t, beads)
         if t >= 100:
             acc += (beads.mom ** 2).mean()
             cnt += 1
@@ -270,7 +282,7 @@ def test_wide_stencil_linear_field_interpolated_exactly(orc, W):
     rng = np.random.default_rng(W)
     for _ in range(10):
         R = rng.uniform(3, 8, size=3)
-        b = one_bead(R, zeta=3.0)
+        b = one_bead(orc, R, zeta=3.0)
         b.stencil = W
         orc.couple(p, n, 0, b, np.zeros((3, L, L, L)))
         C1 = math.exp(-3.0)
@@ -283,7 +295,6 @@ def test_wide_stencil_momentum_with_external_force(orc, W):
     """Total (fluid + bead) momentum changes by N g + sum of the external
     bead forces per coupled step (the fluid receives only the friction
     impulse); the spread force sums to that impulse; mass is unchanged."""
-    import oracle as O
     L = 10
     g = (1e-5, 0.0, -2e-5)
     p = orc.Params(nx=L, ny=L, nz=L, kT=1e-4, g=g, seed=3)
@@ -292,7 +303,7 @@ def test_wide_stencil_momentum_with_external_force(orc, W):
     nb = 6
     pos = rng.uniform(0, L, size=(nb, 3))
     fext = rng.normal(scale=1e-4, size=(nb, 3))
-    beads = O.Beads(pos, rng.normal(scale=0.01, size=(nb, 3)), np.ones(nb), np.full(nb, 5.0),
+    beads = orc.Beads(pos, rng.normal(scale=0.01, size=(nb, 3)), np.ones(nb), np.full(nb, 5.0),
                     np.array([[0, 1], [2, 3]], np.int32), 0.1, 1.0, W, fext)
     for t in range(4):
         tot0 = orc.totals(p, n)

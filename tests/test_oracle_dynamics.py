@@ -73,6 +73,41 @@ def test_shear_viscosity_general_gamma(orc, gs):
     assert rate == pytest.approx(nu * k * k, rel=5e-3)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_uniform_flow_advects_a_transverse_wave(orc, axis):
+    """Direction of streaming: a transverse velocity wave riding on a uniform
+    flow U along its wave vector is carried downstream (the advective term of
+    the Navier-Stokes limit, eq. LBE with the second-order equilibrium of
+    eq. original_equil_distrib): the phase of its Fourier mode moves by
+    k U t.  A standing wave alone cannot tell pull from push streaming; this
+    fixes the sign along each axis.  U = 0.05 leaves O(U^2) corrections of a
+    few per cent; bound 10 %."""
+    L, U, A, T = 32, 0.05, 1e-3, 40
+    dims = [2, 2, 2]
+    dims[axis] = L
+    nx, ny, nz = dims
+    p = orc.Params(nx=nx, ny=ny, nz=nz)
+    trans = (axis + 1) % 3
+    k = 2 * np.pi / L
+    coord = np.arange(L)
+    shape = [1, 1, 1]
+    shape[2 - axis] = L
+    u = np.zeros((3, nz, ny, nx))
+    u[axis] = U
+    u[trans] = np.broadcast_to((A * np.sin(k * coord)).reshape(shape), (nz, ny, nx))
+    n = orc.init_equilibrium(p, u=u)
+
+    def phase():
+        rho, uu = orc.fields(p, n)
+        j = (rho * uu[trans]).mean(axis=tuple(a for a in range(3) if a != 2 - axis))
+        return np.angle(np.sum(j * np.exp(-1j * k * coord)))
+
+    ph0 = phase()
+    orc.run(p, n, T)
+    shift = -(np.angle(np.exp(1j * (phase() - ph0))))
+    assert shift == pytest.approx(k * U * T, rel=0.1)
+
+
 def test_kolmogorov_steady_amplitude(orc):
     L = 32
     g = 1e-6
