@@ -48,7 +48,7 @@ def sampled_step_reference(orc, p, n_flat, dims, sites, step, force=None):
 
 def test_bench_workload_256_coupled(orc, lat):
     """The 256^3 coupled workload of bench.py (64 chains x 32 beads, kT 1e-4,
-    FP32, default launch configuration): bead update and the forced collision
+    FP32, launch configuration searched as in bench.py): bead update and the forced collision
     at bead-touched and random sites match the oracle."""
     import torch
     import bench
@@ -57,7 +57,7 @@ def test_bench_workload_256_coupled(orc, lat):
     N = L ** 3
     pos, mom, bonds = random_walk_chains(64, 32, (L, L, L), seed=0)
     nb = pos.shape[0]
-    pd = lat.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=bench.KT, seed=0, track_totals=True)
+    pd = lat.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=bench.KT, seed=0, track_totals=True, block=-1)
     dev = lat.Lattice(pd)
     dev.init_equilibrium()
     beads = lat.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, bench.K_BOND, 1.0)
