@@ -187,7 +187,7 @@ typedef struct lb_ctx lb_ctx;
  * bytes) and small bookkeeping on the current device, enqueues on `stream`
  * (a hipStream_t; NULL = the null stream).  The state is uninitialised until
  * lb_init_equilibrium or lb_set_populations.  The step counter starts at 0.
- * Errors: LB_EINVAL (any extent < 2, N >= 2^31, |gamma| out of range,
+ * Errors: LB_EINVAL (any extent < 2, N >= 2^30, |gamma| out of range,
  * kT < 0, rho0 <= 0, unknown storage, bad block), LB_ENOMEM, LB_EDEVICE. */
 int lb_create(const lb_params *params, void *stream, lb_ctx **out);
 
@@ -208,7 +208,8 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out);
  * Layout of the batch forms of lb_init_equilibrium / lb_set_populations /
  * lb_get_populations / lb_moments: box after box, each in the single-box
  * layout.  Errors: as lb_create, plus LB_EINVAL for nbox < 1, a box extent
- * < 2, a total site count >= 2^31, odd graph_steps or vacf_lags > 1024. */
+ * < 2, a box of 2^30 sites or more, a total site count >= 2^31, odd
+ * graph_steps or vacf_lags > 1024. */
 int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, void *stream, lb_ctx **out);
 
 /* Ensemble velocity autocorrelation of a batch: host out[nbox][vacf_lags],
