@@ -195,8 +195,10 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out);
  * dims[3*b .. 3*b+2] (host array), all with the physical parameters of
  * `params` (its extents are ignored).  Box b uses box id params->box_id + b
  * as the fourth Philox counter word, so every replica draws its own noise.
- * All boxes advance together: one persistent launch per step walks a list of
- * (box, tile) work items; with graph_steps > 0 the launches of graph_steps
+ * All boxes advance together: one launch per step walks a list of (box,
+ * tile) work items, each block a contiguous run of them (a run of one when
+ * no VACF is sampled and the launch search finds it faster); with
+ * graph_steps > 0 the launches of graph_steps
  * steps are captured once into a HIP graph and replayed.  Populations of all
  * boxes live in one allocation, box after box, each [19][N_b].  The context
  * runs on its own stream, ordered after / before the caller's `stream` at the
