@@ -1004,8 +1004,13 @@ void orc_backward(const orc_params *p, const double *n0, int32_t nsteps, uint32_
  * u_b = sum Delta u(node), the bond forces F^c(R') and the half drift
  * R' = R + (h/2) P/m.  The weights are differentiated with the kernels'
  * derivatives (phi_2: where R' is off the node planes).  The external force
- * is constant and has no adjoint.  Only harmonic bonds are differentiated:
- * with FENE bonds or the WCA interaction the bead adjoints come back NaN.
+ * is constant and has no adjoint.  Conservative forces F = mag(r^2) d along
+ * a separation d (bonds: d = R'_b - R'_a; WCA pairs: the minimum image of
+ * R'_j - R'_i) have the symmetric Jacobian dF/dd = mag I + 2 mag'(r^2) d d^T:
+ *   harmonic  mag = -k (r - r0)/r,           2 mag' = -k r0 / r^3
+ *   FENE      mag = -k / (1 - r^2/R0^2),     2 mag' = -2 k / (R0^2 (1 - r^2/R0^2)^2)
+ *   WCA       mag = 24 eps (2 s^2 - s)/r^2,  2 mag' = 24 eps (-28 s^2 + 8 s) / r^4,
+ *             s = (sigma^2/r^2)^3, below the cutoff (zero above).
  * Parity pinned by central finite differences of the coupled forward map. */
 void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, const orc_beadset *bs,
                         const double *pos, const double *mom, const double *force_bar, double *pos_bar,
@@ -1016,11 +1021,6 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const double h = 1.0;
     const int nb = bs->n, W = bs_width(bs);
-    if (bs->fene || bs->wca_eps > 0.0) {
-        /* only harmonic bonds are differentiated */
-        for (int k = 0; k < 3 * nb; ++k) pos_bar[k] = mom_bar[k] = NAN;
-        return;
-    }
     const size_t nb3 = 3 * (size_t)(nb > 0 ? nb : 1);
     double *half = (double *)malloc(sizeof(double) * nb3);
     double *fc = (double *)malloc(sizeof(double) * nb3);
@@ -1094,8 +1094,7 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
             for (int a = 0; a < 3; ++a) half_bar[3 * b + a] += wgt_bar[q] * dw[3 * q + a];
     }
 
-    /* bond forces F_b = mag d, F_a = -mag d, d = R'_b - R'_a,
-     * mag = -k (1 - r0/r): dF_b/dd = mag I - k r0 d d^T / r^3 (symmetric) */
+    /* bond forces F_b = mag d, F_a = -mag d, d = R'_b - R'_a */
     for (int q = 0; q < bs->nbonds; ++q) {
         const int ia = bs->bonds[2 * q], ib = bs->bonds[2 * q + 1];
         double d[3], r2 = 0.0;
@@ -1103,19 +1102,55 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
             d[a] = half[3 * ib + a] - half[3 * ia + a];
             r2 += d[a] * d[a];
         }
-        const double r = sqrt(r2);
-        if (r == 0.0) continue;
-        const double mag = -bs->kbond * (r - bs->r0) / r;
+        double mag, mag2p; /* mag and 2 dmag/d(r^2) */
+        if (bs->fene) {
+            const double x = r2 / (bs->r0 * bs->r0);
+            mag = -bs->kbond / (1.0 - x);
+            mag2p = -2.0 * bs->kbond / (bs->r0 * bs->r0 * (1.0 - x) * (1.0 - x));
+        } else {
+            const double r = sqrt(r2);
+            if (r == 0.0) continue;
+            mag = -bs->kbond * (r - bs->r0) / r;
+            mag2p = -bs->kbond * bs->r0 / (r * r * r);
+        }
         double v[3], dv = 0.0;
         for (int a = 0; a < 3; ++a) {
             v[a] = fc_bar[3 * ib + a] - fc_bar[3 * ia + a];
             dv += d[a] * v[a];
         }
         for (int a = 0; a < 3; ++a) {
-            const double d_bar = mag * v[a] - bs->kbond * bs->r0 * d[a] * dv / (r * r * r);
+            const double d_bar = mag * v[a] + mag2p * d[a] * dv;
             half_bar[3 * ib + a] += d_bar;
             half_bar[3 * ia + a] -= d_bar;
         }
+    }
+
+    /* WCA pairs F_j = mag d, F_i = -mag d, d = minimum image of R'_j - R'_i */
+    if (bs->wca_eps > 0.0) {
+        const double Lb[3] = {(double)p->nx, (double)p->ny, (double)p->nz};
+        const double rc2 = pow(2.0, 1.0 / 3.0) * bs->wca_sigma * bs->wca_sigma;
+        for (int i = 0; i < nb; ++i)
+            for (int j = i + 1; j < nb; ++j) {
+                double d[3], r2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = min_image(half[3 * j + a] - half[3 * i + a], Lb[a]);
+                    r2 += d[a] * d[a];
+                }
+                if (r2 >= rc2) continue;
+                const double s6 = pow(bs->wca_sigma * bs->wca_sigma / r2, 3.0);
+                const double mag = 24.0 * bs->wca_eps * (2.0 * s6 * s6 - s6) / r2;
+                const double mag2p = 24.0 * bs->wca_eps * (-28.0 * s6 * s6 + 8.0 * s6) / (r2 * r2);
+                double v[3], dv = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    v[a] = fc_bar[3 * j + a] - fc_bar[3 * i + a];
+                    dv += d[a] * v[a];
+                }
+                for (int a = 0; a < 3; ++a) {
+                    const double d_bar = mag * v[a] + mag2p * d[a] * dv;
+                    half_bar[3 * j + a] += d_bar;
+                    half_bar[3 * i + a] -= d_bar;
+                }
+            }
     }
 
     /* R' = R + (h/2) P/m */

@@ -209,6 +209,101 @@ def test_coupled_backward_matches_finite_differences(orc):
         assert gbar[k] == pytest.approx(fd, rel=1e-6)
 
 
+def _kg_system(orc, rng, L):
+    """Four Kremer-Grest chains of 8 (FENE + WCA at eps = 1e-3, sigma = 1): bonded
+    neighbours sit at 0.97, inside the WCA range, and a few unbonded pairs
+    too."""
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    pos, _, bonds = kremer_grest_chains(4, 8, L, seed=int(rng.integers(1 << 30)))
+    nb = pos.shape[0]
+    eps = 1e-3
+    return orc.Beads(pos, rng.normal(scale=0.01, size=(nb, 3)), np.ones(nb), np.full(nb, 0.5), bonds, 30 * eps, 1.5,
+                     fene=True, wca_eps=eps, wca_sigma=1.0)
+
+
+def test_kg_couple_adjoint_matches_finite_differences(orc):
+    """One particle half-step with FENE bonds and WCA pairs: the adjoint
+    w.r.t. n, g, R, P of L = wf.force + a.R_new + b.P_new (central
+    differences, eps = 1e-6; no pair lies within 1e-5 of the WCA cutoff,
+    where the force's derivative jumps)."""
+    rng = np.random.default_rng(15)
+    dims = (8, 8, 8)
+    p = orc.Params(nx=8, ny=8, nz=8, kT=1e-4, seed=4, g=(1e-4, -5e-5, 2e-5))
+    n = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 8, 8, 8)))
+    beads = _kg_system(orc, rng, dims)
+    nb = beads.pos.shape[0]
+    half = beads.pos + 0.5 * beads.mom
+    dd = half[:, None, :] - half[None, :, :]
+    dd -= 8 * np.round(dd / 8)
+    r = np.linalg.norm(dd, axis=2)
+    assert np.abs(r[np.triu_indices(nb, 1)] - 2 ** (1 / 6)).min() > 1e-5
+    assert (r[np.triu_indices(nb, 1)] < 2 ** (1 / 6)).sum() > len(beads.bonds)   # unbonded pairs interact too
+    wf = rng.normal(size=(3, 8, 8, 8))
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+
+    def loss(nn, pp, bb):
+        force = np.zeros((3, 8, 8, 8))
+        c = bb.copy()
+        orc.couple(pp, nn, 3, c, force)
+        return (wf * force).sum() + (a * c.pos).sum() + (b * c.mom).sum()
+
+    lam = np.zeros_like(n)
+    gbar = np.zeros(3)
+    pb, mb = a.copy(), b.copy()
+    orc.couple_adjoint(p, n, 3, beads, wf, pb, mb, lam, gbar)
+    eps = 1e-6
+    for name, bar in (("pos", pb), ("mom", mb)):
+        vb = rng.normal(size=(nb, 3))
+        bp_, bm_ = beads.copy(), beads.copy()
+        setattr(bp_, name, getattr(beads, name) + eps * vb)
+        setattr(bm_, name, getattr(beads, name) - eps * vb)
+        fd = (loss(n, p, bp_) - loss(n, p, bm_)) / (2 * eps)
+        assert (bar * vb).sum() == pytest.approx(fd, rel=1e-6, abs=1e-12), name
+    v = rng.normal(size=n.shape)
+    fd = (loss(n + eps * v, p, beads) - loss(n - eps * v, p, beads)) / (2 * eps)
+    assert (lam * v).sum() == pytest.approx(fd, rel=1e-6, abs=1e-12)
+
+
+def test_kg_coupled_backward_matches_finite_differences(orc):
+    """Whole coupled steps with FENE + WCA chains: the adjoint w.r.t. n(0),
+    g, R(0), P(0) of L = w.n(T) + a.R(T) + b.P(T)."""
+    rng = np.random.default_rng(16)
+    p = orc.Params(nx=8, ny=8, nz=8, kT=1e-4, seed=8, g=(1e-4, -5e-5, 2e-5))
+    n0 = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, 8, 8, 8)))
+    beads = _kg_system(orc, rng, (8, 8, 8))
+    nb = beads.pos.shape[0]
+    T = 4
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+
+    def loss(nn, pp, bb):
+        n = nn.copy()
+        c = bb.copy()
+        for t in range(T):
+            orc.coupled_step(pp, n, t, c)
+        return (w * n).sum() + (a * c.pos).sum() + (b * c.mom).sum()
+
+    lam0, gbar, pb0, mb0 = orc.backward_coupled(p, n0, T, beads, w, a, b)
+    eps = 1e-6
+    for name, bar in (("pos", pb0), ("mom", mb0)):
+        vb = rng.normal(size=(nb, 3))
+        bp_, bm_ = beads.copy(), beads.copy()
+        setattr(bp_, name, getattr(beads, name) + eps * vb)
+        setattr(bm_, name, getattr(beads, name) - eps * vb)
+        fd = (loss(n0, p, bp_) - loss(n0, p, bm_)) / (2 * eps)
+        assert (bar * vb).sum() == pytest.approx(fd, rel=1e-6), name
+    v = rng.normal(size=n0.shape)
+    fd = (loss(n0 + eps * v, p, beads) - loss(n0 - eps * v, p, beads)) / (2 * eps)
+    assert (lam0 * v).sum() == pytest.approx(fd, rel=1e-6)
+    gp, gm = list(p.g), list(p.g)
+    gp[0] += eps
+    gm[0] -= eps
+    pp = orc.Params(**{**p.__dict__, "g": tuple(gp)})
+    pm = orc.Params(**{**p.__dict__, "g": tuple(gm)})
+    fd = (loss(n0, pp, beads) - loss(n0, pm, beads)) / (2 * eps)
+    assert gbar[0] == pytest.approx(fd, rel=1e-6)
+
+
 def test_composed_reverse_sweep_equals_backward_coupled(orc):
     """The oracle's step and particle adjoints, composed by hand step by step,
     give the same gradients as orc_backward_coupled (the composition used by

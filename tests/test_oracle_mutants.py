@@ -83,9 +83,13 @@ MUTANTS = {
                                  [(TA.test_collision_adjoint_is_transpose_of_jacobian, {})]),
     "adjoint_weight_gradient": ("for (int a = 0; a < 3; ++a) half_bar[3 * b + a] += wgt_bar[q] * dw[3 * q + a];", ";",
                                 [(TA.test_couple_adjoint_matches_finite_differences, {})]),
-    "adjoint_bond_jacobian": ("const double d_bar = mag * v[a] - bs->kbond * bs->r0 * d[a] * dv / (r * r * r);",
-                              "const double d_bar = mag * v[a];",
+    "adjoint_bond_jacobian": ("mag2p = -bs->kbond * bs->r0 / (r * r * r);", "mag2p = 0.0;",
                               [(TA.test_couple_adjoint_matches_finite_differences, {})]),
+    "adjoint_fene_jacobian": ("mag2p = -2.0 * bs->kbond / (bs->r0 * bs->r0 * (1.0 - x) * (1.0 - x));",
+                              "mag2p = -bs->kbond / (bs->r0 * bs->r0 * (1.0 - x) * (1.0 - x));",
+                              [(TA.test_kg_couple_adjoint_matches_finite_differences, {})]),
+    "adjoint_wca_jacobian": ("(-28.0 * s6 * s6 + 8.0 * s6)", "(-28.0 * s6 * s6 + 4.0 * s6)",
+                             [(TA.test_kg_couple_adjoint_matches_finite_differences, {})]),
     "adjoint_body_force_half": ("gbar[a] += 0.5 * uq_bar[a] / rn[q];", "gbar[a] += 0.0;",
                                 [(TA.test_coupled_backward_matches_finite_differences, {})]),
 }
