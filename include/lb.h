@@ -277,8 +277,7 @@ int lb_step(lb_ctx *ctx, int32_t nsteps);
  * keyed by (bead index, step counter).  Errors: LB_EINVAL (n < 0, NULL
  * arrays with n > 0, unknown stencil or bond kind, non-finite or negative
  * bond or WCA parameters, r_c >= half a box extent), LB_EUNSUPPORTED (WCA
- * with walls; FENE or WCA while a tape is recording), LB_ESTATE (a previous
- * lb_couple's force not yet consumed). */
+ * with walls), LB_ESTATE (a previous lb_couple's force not yet consumed). */
 int lb_couple(lb_ctx *ctx, const lb_beads *beads);
 
 /* Density and velocity of the current state: rho = sum_i n_i,
@@ -332,8 +331,8 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * reverse sweep a coupled step rebuilds its spread force from the stored
  * bead state, the fluid adjoint also yields the adjoint of the bead force at
  * the touched nodes, and the adjoint of the particle half (half drift,
- * harmonic bonds, the interpolation with the stencil weights differentiated
- * in R, the momentum update eq. langevin_momentum_update with its noise
+ * harmonic or FENE bonds and WCA pairs (their Jacobians mag I + 2 mag' d d^T),
+ * the interpolation with the stencil weights differentiated in R, the momentum update eq. langevin_momentum_update with its noise
  * replayed, the spread reaction eq. ftotal) carries the bead adjoints back
  * and adds the interpolation's share to dL/dn and dL/dg.
  * lb_backward_coupled takes and returns the bead adjoints as well:

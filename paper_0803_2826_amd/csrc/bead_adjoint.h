@@ -4,7 +4,7 @@
 //
 // The forward map of the particle half, per bead (h = 1):
 //   R' = R + (h/2) P/m                      half drift (eq. pTrotter)
-//   F^c = F^c(R')                           harmonic bonds
+//   F^c = F^c(R')                           bonds (harmonic or FENE), WCA pairs, fext
 //   u_b = sum_q w_q(R') u_q,  u_q = (sum_i n_i c_i + g/2) / rho_q   (eq. ufluid_discrete)
 //   P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta   (eq. langevin_momentum_update)
 //   I = -(P'' - P - h F^c),  f(node_q) += w_q I / h                  (eq. ftotal)
@@ -138,11 +138,14 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
     }
 }
 
-// Bond forces F_b = mag d, F_a = -mag d (d = R'_b - R'_a, mag = -k (1 - r0/r)):
-// dF_b/dd = mag I - k r0 d d^T / r^3 (symmetric), so
-// dbar = (dF_b/dd)(fcbar_b - fcbar_a), half_bar_b += dbar, half_bar_a -= dbar.
+// Bond forces F_b = mag d, F_a = -mag d (d = R'_b - R'_a) have the
+// symmetric Jacobian dF_b/dd = mag I + 2 mag'(r^2) d d^T with
+//   harmonic  mag = -k (r - r0)/r,        2 mag' = -k r0 / r^3
+//   FENE      mag = -k / (1 - r^2/r0^2),  2 mag' = -2 k / (r0^2 (1 - r^2/r0^2)^2)
+// so dbar = (dF_b/dd)(fcbar_b - fcbar_a), half_bar_b += dbar, half_bar_a -= dbar.
 __global__ void k_bonds_adjoint(const double *__restrict__ half, const double *__restrict__ fc_bar, double *half_bar,
-                                const int32_t *__restrict__ bonds, int nbonds, double kb, double r0, int nbeads)
+                                const int32_t *__restrict__ bonds, int nbonds, double kb, double r0, int nbeads,
+                                int fene)
 {
     const int qd = blockIdx.x * blockDim.x + threadIdx.x;
     if (qd >= nbonds) return;
@@ -155,11 +158,19 @@ __global__ void k_bonds_adjoint(const double *__restrict__ half, const double *_
         r2 += d[c] * d[c];
         dv += d[c] * v[c];
     }
-    const double r = sqrt(r2);
-    if (r == 0.0) return;
-    const double mag = -kb * (r - r0) / r;
+    double mag, mag2p;
+    if (fene) {
+        const double x = r2 / (r0 * r0);
+        mag = -kb / (1.0 - x);
+        mag2p = -2.0 * kb / (r0 * r0 * (1.0 - x) * (1.0 - x));
+    } else {
+        const double r = sqrt(r2);
+        if (r == 0.0) return;
+        mag = -kb * (r - r0) / r;
+        mag2p = -kb * r0 / (r2 * r);
+    }
     for (int c = 0; c < 3; ++c) {
-        const double db = mag * v[c] - kb * r0 * d[c] * dv / (r2 * r);
+        const double db = mag * v[c] + mag2p * d[c] * dv;
         atomicAdd(&half_bar[3 * ib + c], db);
         atomicAdd(&half_bar[3 * ia + c], -db);
     }

@@ -462,12 +462,13 @@ int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
 
 // WCA forces at the half-step positions into c->fp: rebuild the cell list,
 // then kPairLanes lanes per bead over its neighbour cells.
-void launch_wca(lb_ctx *c, const lb_beads *b)
+// Cell list of the positions `half` (count, scan, fill, rank).
+CellGrid build_cells(lb_ctx *c, const lb_beads *b, const double *half)
 {
     const CellGrid cg = cell_grid(c, b);
     const size_t ncell = (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2];
     const unsigned gb = grid_for((size_t)b->n, 256);
-    hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(256), 0, c->stream, c->half, b->n, cg, c->bead_cell, c->bead_slot,
+    hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(256), 0, c->stream, half, b->n, cg, c->bead_cell, c->bead_slot,
                        c->cell_count);
     size_t tmp = c->scan_tmp_bytes;
     (void)hipcub::DeviceScan::ExclusiveSum(c->scan_tmp, tmp, c->cell_count, c->cell_start, (int)(ncell + 1),
@@ -475,9 +476,23 @@ void launch_wca(lb_ctx *c, const lb_beads *b)
     hipLaunchKernelGGL(k_cell_fill, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->bead_slot, c->cell_start,
                        c->cell_sorted, c->cell_count);
     hipLaunchKernelGGL(k_cell_rank, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->cell_start,
-                       c->cell_sorted, c->half, c->cell_pos);
+                       c->cell_sorted, half, c->cell_pos);
+    return cg;
+}
+
+void launch_wca(lb_ctx *c, const lb_beads *b)
+{
+    const CellGrid cg = build_cells(c, b, c->half);
     hipLaunchKernelGGL(k_wca, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, c->half, b->n,
                        cg, c->bead_cell, c->cell_start, c->cell_pos, c->fp);
+}
+
+// Adjoint of the WCA forces at the positions `half`: half_bar += J (fc_bar_i - fc_bar_j).
+void launch_wca_adjoint(lb_ctx *c, const lb_beads *b, const double *half, const double *fc_bar, double *half_bar)
+{
+    const CellGrid cg = build_cells(c, b, half);
+    hipLaunchKernelGGL(k_wca_adjoint, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, half,
+                       b->n, cg, c->bead_cell, c->cell_start, c->cell_pos, fc_bar, half_bar);
 }
 
 // Threads per block of the per-bead stencil kernels: one wave, so that a few
@@ -1164,8 +1179,6 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
             return fail(c, LB_EINVAL, "the WCA cutoff 2^(1/6) sigma must be below half of every box extent");
         if (c->p.walls) return fail(c, LB_EUNSUPPORTED, "WCA pair forces are only available in a periodic box");
     }
-    if (c->taping && (wca || (b->bond == LB_BOND_FENE && b->nbonds > 0)))
-        return fail(c, LB_EUNSUPPORTED, "FENE bonds and WCA pairs cannot be differentiated (tape recording)");
     LB_TRY(use_device(c));
     LB_TRY(ensure_bead_buffers(c, b->n));
     if (wca) {
@@ -1584,7 +1597,9 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 });
                 if (bc.nbonds > 0)
                     hipLaunchKernelGGL(k_bonds_adjoint, dim3(grid_for((size_t)bc.nbonds, 256)), dim3(256), 0, c->stream,
-                                       ba.half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd);
+                                       ba.half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd,
+                                       (int)(bc.bond == LB_BOND_FENE));
+                if (bc.wca_epsilon > 0.0) launch_wca_adjoint(c, &bc, ba.half, fc_bar, half_bar);
                 hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for((size_t)nbd, 256)), dim3(256), 0, c->stream,
                                    nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar);
                 clear_force();

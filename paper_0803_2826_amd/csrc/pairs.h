@@ -153,4 +153,70 @@ __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, in
         for (int a = 0; a < 3; ++a) fp[3 * i + a] = F[a];
 }
 
+// Adjoint of the pair forces: with fp_i = sum_j mag(r^2) d_ij, d_ij = R_i - R_j,
+// mag = 24 eps (2 s^2 - s)/r^2, s = (sigma^2/r^2)^3, the Jacobian of each term
+// is J = mag I + 2 mag' d d^T, 2 mag' = 24 eps (-28 s^2 + 8 s)/r^4, symmetric
+// and even in d, so half_bar_i += sum_j J(d_ij) (fc_bar_i - fc_bar_j).  Same
+// lanes and cell order as k_wca (fixed sums, no atomics).
+__global__ void __launch_bounds__(256) k_wca_adjoint(const double *__restrict__ half, int n, CellGrid cg,
+                                                     const int32_t *__restrict__ cell_of,
+                                                     const int32_t *__restrict__ start,
+                                                     const double4 *__restrict__ cpos,
+                                                     const double *__restrict__ fc_bar, double *half_bar)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / kPairLanes, l = t % kPairLanes;
+    double B[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+        const int span[3] = {cg.nc[0] >= 3 ? 1 : 0, cg.nc[1] >= 3 ? 1 : 0, cg.nc[2] >= 3 ? 1 : 0};
+        const int w0 = 2 * span[0] + 1, w1 = 2 * span[1] + 1, w2 = 2 * span[2] + 1;
+        if (l < w0 * w1 * w2) {
+            const int cell = cell_of[i];
+            const int o[3] = {l % w0 - span[0], (l / w0) % w1 - span[1], l / (w0 * w1) - span[2]};
+            const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
+            int cn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cn[a] = ci[a] + o[a];
+                cn[a] += cn[a] < 0 ? cg.nc[a] : (cn[a] >= cg.nc[a] ? -cg.nc[a] : 0);
+            }
+            const int nb = cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
+            const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
+            const double Gi[3] = {fc_bar[3 * i], fc_bar[3 * i + 1], fc_bar[3 * i + 2]};
+            const double self = (double)i;
+            const int hi = start[nb + 1];
+            for (int k = start[nb]; k < hi; ++k) {
+                const double4 q = cpos[k];
+                if (q.w == self) continue;
+                double d[3];
+                d[0] = nearest_image(Ri[0] - q.x, cg.L[0]);
+                d[1] = nearest_image(Ri[1] - q.y, cg.L[1]);
+                d[2] = nearest_image(Ri[2] - q.z, cg.L[2]);
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (!(r2 < cg.rc2)) continue;
+                const int j = (int)q.w;
+                double v[3], dv = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    v[a] = Gi[a] - fc_bar[3 * j + a];
+                    dv += d[a] * v[a];
+                }
+                const double s2 = cg.sig2 / r2;
+                const double s6 = s2 * s2 * s2;
+                const double mag = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
+                const double mag2p = cg.eps24 * (-28.0 * s6 * s6 + 8.0 * s6) / (r2 * r2);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) B[a] += mag * v[a] + mag2p * d[a] * dv;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int off = 1; off < kPairLanes; off <<= 1) B[a] += __shfl_xor(B[a], off, 64);
+    if (i < n && l == 0)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) half_bar[3 * i + a] += B[a];
+}
+
 }  // namespace lbmi

@@ -81,6 +81,36 @@ def test_gpu_coupled_adjoint_matches_oracle(orc, lat):
     assert max(errs) <= REL_TOL
 
 
+@pytest.mark.parametrize("K", [3, 8])
+def test_gpu_kg_coupled_adjoint_matches_oracle(orc, lat, K):
+    """Kremer-Grest chains (FENE bonds, WCA pairs through the cell list) in a
+    taped run: the recomputed segment keeps the pair forces, the reverse
+    sweep adds the bonds' and pairs' Jacobians (K = 8 keeps every coupled
+    step in one segment, K = 3 rebuilds the last step of each segment)."""
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    rng = np.random.default_rng(11)
+    L, eps = 10, 1e-3
+    po = orc.Params(nx=L, ny=L, nz=L, kT=1e-4, seed=6, g=(1e-4, -5e-5, 2e-5))
+    pd = lat.FluidParams(nx=L, ny=L, nz=L, kT=po.kT, seed=po.seed, body_force=po.g, track_totals=False)
+    pos, _, bonds = kremer_grest_chains(4, 8, (L, L, L), seed=3)
+    nb = pos.shape[0]
+    mom = rng.normal(scale=0.01, size=(nb, 3))
+    zeta = np.full(nb, 0.5)
+    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta, bonds.copy(), 30 * eps, 1.5, fene=True, wca_eps=eps,
+                   wca_sigma=1.0)
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 30 * eps, 1.5, bond="fene", wca_epsilon=eps,
+                         wca_sigma=1.0)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, L, L, L)))
+    T = 8
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+    n0r, (dn0, dg, dR0, dP0) = run_gpu(lat, pd, n0, db, T, K, w, a, b)
+    lam0, gbar, pb0, mb0 = orc.backward_coupled(po, n0r, T, ob, w, a, b)
+    errs = [rel_err(dn0, lam0), rel_err(dg, gbar), rel_err(dR0, pb0), rel_err(dP0, mb0)]
+    print("KG coupled adjoint rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
+    assert max(errs) <= REL_TOL
+
+
 def oracle_mixed_backward(orc, po, n0, ob, T, plain_steps, w, a, b):
     """Reverse sweep composed from the oracle's step and particle adjoints
     for a run whose steps in `plain_steps` have no particle half."""

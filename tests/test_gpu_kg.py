@@ -221,8 +221,8 @@ def test_kg_argument_errors(lat):
     assert code(p8, wca_epsilon=EPS, wca_sigma=3.6) == LB_EINVAL        # 2 r_c = 8.08 > 8
     assert code(p8, wca_epsilon=EPS, wca_sigma=3.5) == 0
     assert code(lat.FluidParams(nx=8, ny=8, nz=8, walls=True), wca_epsilon=EPS) == LB_EUNSUPPORTED
-    assert code(p8, tape=True, bond="fene") == LB_EUNSUPPORTED
-    assert code(p8, tape=True, wca_epsilon=EPS) == LB_EUNSUPPORTED
+    assert code(p8, tape=True, bond="fene") == 0          # differentiated since the adjoint covers them
+    assert code(p8, tape=True, wca_epsilon=EPS) == 0
     assert code(p8, tape=True) == 0
     with pytest.raises(ValueError):
         lat.DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), bonds, bond="morse")
