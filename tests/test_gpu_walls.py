@@ -142,6 +142,42 @@ def test_coupled_parity_with_walls(orc, lat):
     dev.close()
 
 
+def test_coupled_adjoint_with_walls_matches_oracle(orc, lat):
+    """Taped coupled steps in a channel (beads kept off the walls): the
+    reverse sweep with the walls' reflected adjoint and the particle
+    adjoint, against the oracle's FP64 adjoint of whole coupled steps."""
+    import torch
+    rng = np.random.default_rng(5)
+    po, pd = pair(orc, lat, 10, 8, 12, kT=1e-4, seed=3, g=(1e-4, 0.0, -2e-5), gamma_shear=0.1)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, 12, 8, 10)))
+    nb = 12
+    pos = np.column_stack([rng.uniform(0, 10, nb), rng.uniform(0, 8, nb), rng.uniform(3.5, 7.5, nb)])
+    mom = rng.normal(scale=0.01, size=(nb, 3))
+    bonds = np.array([[k, k + 1] for k in range(0, nb - 1, 2)], dtype=np.int32)
+    zeta = np.full(nb, 1.0)
+    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta, bonds.copy(), 1e-3, 1.0)
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 1e-3, 1.0)
+    T = 6
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n0))
+    n0r = dev.get_populations().cpu().numpy()
+    dev.tape_begin(4)
+    for _ in range(T):
+        dev.coupled_step(db)
+    dn0, dg, dR0, dP0 = dev.backward_coupled(torch.from_numpy(w), torch.from_numpy(a), torch.from_numpy(b))
+    dev.close()
+    lam0, gbar, pb0, mb0 = orc.backward_coupled(po, n0r, T, ob, w, a, b)
+
+    def rel(x, ref):
+        return np.abs(np.asarray(x) - ref).max() / np.abs(ref).max()
+
+    errs = [rel(dn0.cpu().numpy(), lam0), rel(dg, gbar), rel(dR0.cpu().numpy(), pb0), rel(dP0.cpu().numpy(), mb0)]
+    print("coupled adjoint with walls rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
+    assert max(errs) <= 2e-5
+
+
 def test_batch_rejects_walls(lat):
     from paper_0803_2826_amd._lib import LB_EINVAL, LB_EUNSUPPORTED, LBError
     with pytest.raises(LBError) as ei:
