@@ -24,7 +24,8 @@ Prints ONE JSON line with, beside the throughput:
                 of the same workload (a few coupled steps of the full box);
   forms         the other throughputs the metric names: FP32 and BF16-storage
                 MLUPS (nearest and stochastic rounding, kT > 0 and kT = 0)
-                on the same box without beads, the batched form (512 replica boxes, edges drawn from
+                on the same box without beads and, per storage type, on the
+                512^3 box of the precision workload, the batched form (512 replica boxes, edges drawn from
                 {24, 32, 40, 48, 64}, HIP graph replay) and the
                 differentiation form (taped forward and adjoint of 500
                 coupled steps at 128^3 with 16 x 32 beads, checkpoints every
@@ -207,6 +208,11 @@ def run_forms(L: int) -> dict:
     for st, rd in (("bf16", "nearest"), ("bf16", "stochastic")):
         out[f"{st}_{rd}_mlups"] = round(forms.step_mlups(st, L, KT, steps=100, rounding=rd), 1)
     out["bf16_nearest_kT0_mlups"] = round(forms.step_mlups("bf16", L, 0.0, steps=100), 1)
+    # the precision workload's own box: 512^3, kT = 1e-4, per storage type and rounding
+    out["precision_512_mlups"] = {
+        f"{st}_{rd}": round(forms.step_mlups(st, 512, KT, steps=50, rounding=rd), 1)
+        for st, rd in (("f32", "nearest"), ("bf16", "nearest"), ("bf16", "stochastic"), ("f16", "nearest"),
+                       ("f16", "stochastic"))}
     print("# forms: precision done", file=sys.stderr, flush=True)
     b = forms.batch_study(nbox=512, steps=200, kT=KT, lags=0, graph_steps=10)
     out["batched_mlups"] = round(b["mlups"], 1)

@@ -159,10 +159,11 @@ typedef enum { LB_BOND_HARMONIC = 0, LB_BOND_FENE = 1 } lb_bond;
  *   wca_epsilon, wca_sigma  the Lennard-Jones potential of eq. ulennardjones
  *                cut and shifted at its minimum r_c = 2^(1/6) sigma (purely
  *                repulsive) between every pair of beads, bonded or not, at
- *                their periodic minimum-image distance; wca_epsilon = 0
- *                switches it off.  Pairs are found with a cell list of cells
- *                no narrower than r_c, rebuilt every call; r_c must be below
- *                half of every box extent, and the periodic box has no walls.
+ *                their minimum-image distance along the periodic axes (with
+ *                walls the z axis is not periodic: no pair interacts through
+ *                a wall); wca_epsilon = 0 switches it off.  Pairs are found
+ *                with a cell list of cells no narrower than r_c, rebuilt
+ *                every call; r_c must be below half of every periodic extent.
  * Units are lattice units (spacing a = 1, time step h = 1). */
 typedef struct {
     int32_t n;
@@ -276,8 +277,8 @@ int lb_step(lb_ctx *ctx, int32_t nsteps);
  * state.  The spread force is applied by the next lb_step.  Bead noise is
  * keyed by (bead index, step counter).  Errors: LB_EINVAL (n < 0, NULL
  * arrays with n > 0, unknown stencil or bond kind, non-finite or negative
- * bond or WCA parameters, r_c >= half a box extent), LB_EUNSUPPORTED (WCA
- * with walls), LB_ESTATE (a previous lb_couple's force not yet consumed). */
+ * bond or WCA parameters, r_c >= half a periodic box extent), LB_ESTATE (a
+ * previous lb_couple's force not yet consumed). */
 int lb_couple(lb_ctx *ctx, const lb_beads *beads);
 
 /* Density and velocity of the current state: rho = sum_i n_i,

@@ -645,9 +645,16 @@ static double wca_factor(double eps, double sigma, double r2)
 /* Minimum-image difference along one periodic axis of length L. */
 static double min_image(double d, double L) { return d - L * floor(d / L + 0.5); }
 
+/* Pair separation along axis a: the minimum image along periodic axes; with
+ * walls the z axis is not periodic and the plain difference is used. */
+static double pair_sep(const orc_params *p, int a, double d, double L)
+{
+    return (a == 2 && p->walls) ? d : min_image(d, L);
+}
+
 /* Half-step positions R' = R + (h/2) P/m and conservative forces at R':
- * bonds (harmonic or FENE), WCA between all pairs (minimum image in the
- * periodic box), plus the external force.  A FENE bond stretched to
+ * bonds (harmonic or FENE), WCA between all pairs (minimum image along the
+ * periodic axes; with walls z is not periodic), plus the external force.  A FENE bond stretched to
  * |d| >= R0 has no finite force (NaN). */
 static void half_and_forces(const orc_params *p, const orc_beadset *bs, const double *pos, const double *mom,
                             double *half, double *fc)
@@ -685,7 +692,7 @@ static void half_and_forces(const orc_params *p, const orc_beadset *bs, const do
             for (int j = i + 1; j < bs->n; ++j) {
                 double d[3], r2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    d[a] = min_image(half[3 * j + a] - half[3 * i + a], Lb[a]);
+                    d[a] = pair_sep(p, a, half[3 * j + a] - half[3 * i + a], Lb[a]);
                     r2 += d[a] * d[a];
                 }
                 const double f = wca_factor(bs->wca_eps, bs->wca_sigma, r2);
@@ -1005,8 +1012,8 @@ void orc_backward(const orc_params *p, const double *n0, int32_t nsteps, uint32_
  * R' = R + (h/2) P/m.  The weights are differentiated with the kernels'
  * derivatives (phi_2: where R' is off the node planes).  The external force
  * is constant and has no adjoint.  Conservative forces F = mag(r^2) d along
- * a separation d (bonds: d = R'_b - R'_a; WCA pairs: the minimum image of
- * R'_j - R'_i) have the symmetric Jacobian dF/dd = mag I + 2 mag'(r^2) d d^T:
+ * a separation d (bonds: d = R'_b - R'_a; WCA pairs: R'_j - R'_i at the
+ * minimum image along periodic axes) have the symmetric Jacobian dF/dd = mag I + 2 mag'(r^2) d d^T:
  *   harmonic  mag = -k (r - r0)/r,           2 mag' = -k r0 / r^3
  *   FENE      mag = -k / (1 - r^2/R0^2),     2 mag' = -2 k / (R0^2 (1 - r^2/R0^2)^2)
  *   WCA       mag = 24 eps (2 s^2 - s)/r^2,  2 mag' = 24 eps (-28 s^2 + 8 s) / r^4,
@@ -1125,7 +1132,7 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
         }
     }
 
-    /* WCA pairs F_j = mag d, F_i = -mag d, d = minimum image of R'_j - R'_i */
+    /* WCA pairs F_j = mag d, F_i = -mag d, d = pair_sep of R'_j - R'_i */
     if (bs->wca_eps > 0.0) {
         const double Lb[3] = {(double)p->nx, (double)p->ny, (double)p->nz};
         const double rc2 = pow(2.0, 1.0 / 3.0) * bs->wca_sigma * bs->wca_sigma;
@@ -1133,7 +1140,7 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
             for (int j = i + 1; j < nb; ++j) {
                 double d[3], r2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    d[a] = min_image(half[3 * j + a] - half[3 * i + a], Lb[a]);
+                    d[a] = pair_sep(p, a, half[3 * j + a] - half[3 * i + a], Lb[a]);
                     r2 += d[a] * d[a];
                 }
                 if (r2 >= rc2) continue;

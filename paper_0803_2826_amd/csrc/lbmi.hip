@@ -405,6 +405,7 @@ CellGrid cell_grid(const lb_ctx *c, const lb_beads *b)
     const int cap = std::min(128, std::max(3, (int)std::ceil(std::cbrt(512.0 * (double)b->n))));
     const int32_t ext[3] = {c->p.nx, c->p.ny, c->p.nz};
     for (int a = 0; a < 3; ++a) {
+        cg.periodic[a] = (a == 2 && c->p.walls) ? 0 : 1;
         cg.L[a] = (double)ext[a];
         int nc = (int)std::floor(cg.L[a] / rc);
         nc = std::min(nc, cap);
@@ -1175,9 +1176,9 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
         if (!(std::isfinite(b->wca_sigma) && b->wca_sigma > 0.0))
             return fail(c, LB_EINVAL, "wca_sigma must be finite and > 0");
         const double rc = std::cbrt(std::sqrt(2.0)) * b->wca_sigma;
-        if (!(2.0 * rc < (double)std::min(c->p.nx, std::min(c->p.ny, c->p.nz))))
-            return fail(c, LB_EINVAL, "the WCA cutoff 2^(1/6) sigma must be below half of every box extent");
-        if (c->p.walls) return fail(c, LB_EUNSUPPORTED, "WCA pair forces are only available in a periodic box");
+        const int32_t lmin = std::min(c->p.nx, c->p.walls ? c->p.ny : std::min(c->p.ny, c->p.nz));
+        if (!(2.0 * rc < (double)lmin))
+            return fail(c, LB_EINVAL, "the WCA cutoff 2^(1/6) sigma must be below half of every periodic box extent");
     }
     LB_TRY(use_device(c));
     LB_TRY(ensure_bead_buffers(c, b->n));

@@ -1,7 +1,8 @@
 // Kremer-Grest bead-spring interactions on the device (Sec. "Coarse-grained
 // models"): the purely repulsive Lennard-Jones (WCA) pair force of
 // eq. ulennardjones between all beads within r_c = 2^(1/6) sigma of each
-// other at their periodic minimum-image distance, found with a cell list.
+// other (minimum image along periodic axes; z is not periodic between
+// walls), found with a cell list.
 //
 // Cell list, rebuilt on every coupled step from the half-step positions R':
 //   cells per axis  n_a = floor(L_a / r_c) capped at a size tied to the bead
@@ -33,7 +34,8 @@ namespace lbmi {
 
 struct CellGrid {
     int32_t nc[3];     // cells per axis (1 or >= 3)
-    double L[3];       // periodic box extents
+    int32_t periodic[3];  // 1: periodic axis (minimum image); 0: z between walls
+    double L[3];       // box extents
     double inv_w[3];   // nc / L
     double rc2;        // squared cutoff 2^(1/3) sigma^2
     double sig2;       // sigma^2
@@ -41,10 +43,12 @@ struct CellGrid {
 };
 
 // Cell coordinate along one axis of a (possibly unwrapped, possibly
-// non-finite) position: always in [0, nc).
-__device__ __forceinline__ int cell_coord(double x, double L, double inv_w, int nc)
+// non-finite) position: always in [0, nc).  A periodic axis wraps the
+// position into the box; a non-periodic one clamps it to the edge cells, so
+// beads beyond a wall share the edge cell with those next to it.
+__device__ __forceinline__ int cell_coord(double x, double L, double inv_w, int nc, int periodic)
 {
-    const double xw = x - L * floor(x / L);
+    const double xw = periodic ? x - L * floor(x / L) : x;
     double t = floor(xw * inv_w);
     if (!(t >= 0.0)) t = 0.0;
     if (t > (double)(nc - 1)) t = (double)(nc - 1);
@@ -52,6 +56,22 @@ __device__ __forceinline__ int cell_coord(double x, double L, double inv_w, int 
 }
 
 __device__ __forceinline__ double nearest_image(double d, double L) { return d - L * floor(d / L + 0.5); }
+
+// Pair separation along one axis: the minimum image if periodic.
+__device__ __forceinline__ double pair_sep(double d, double L, int periodic)
+{
+    return periodic ? nearest_image(d, L) : d;
+}
+
+// Neighbour cell along one axis at offset o from c: wrapped on a periodic
+// axis, -1 (none) past the end of a non-periodic one.
+__device__ __forceinline__ int neighbour_cell(int c, int o, int nc, int periodic)
+{
+    int cn = c + o;
+    if (cn < 0) return periodic ? cn + nc : -1;
+    if (cn >= nc) return periodic ? cn - nc : -1;
+    return cn;
+}
 
 // count has ncell + 1 entries, zero on entry (the last stays zero, so the
 // exclusive scan's last entry is the bead count).
@@ -62,7 +82,7 @@ __global__ void k_cell_count(const double *__restrict__ half, int n, CellGrid cg
     if (b >= n) return;
     int c[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) c[a] = cell_coord(half[3 * b + a], cg.L[a], cg.inv_w[a], cg.nc[a]);
+    for (int a = 0; a < 3; ++a) c[a] = cell_coord(half[3 * b + a], cg.L[a], cg.inv_w[a], cg.nc[a], cg.periodic[a]);
     const int cell = c[0] + cg.nc[0] * (c[1] + cg.nc[1] * c[2]);
     cell_of[b] = cell;
     slot[b] = atomicAdd(&count[cell], 1);
@@ -111,14 +131,12 @@ __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, in
             const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
             int cn[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cn[a] = ci[a] + o[a];
-                cn[a] += cn[a] < 0 ? cg.nc[a] : (cn[a] >= cg.nc[a] ? -cg.nc[a] : 0);
-            }
-            const int nb = cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
+            for (int a = 0; a < 3; ++a) cn[a] = neighbour_cell(ci[a], o[a], cg.nc[a], cg.periodic[a]);
+            // a lane whose cell lies past a wall has no candidates
+            const int nb = (cn[0] < 0 || cn[1] < 0 || cn[2] < 0) ? -1 : cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
             const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
             const double self = (double)i;
-            const int lo = start[nb], hi = start[nb + 1];
+            const int lo = nb < 0 ? 0 : start[nb], hi = nb < 0 ? 0 : start[nb + 1];
             // four candidates per round, their loads issued together
             constexpr int U = 4;
             for (int k0 = lo; k0 < hi; k0 += U) {
@@ -128,9 +146,9 @@ __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, in
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (k0 + u >= hi || q[u].w == self) continue;
-                    const double d0 = nearest_image(Ri[0] - q[u].x, cg.L[0]);
-                    const double d1 = nearest_image(Ri[1] - q[u].y, cg.L[1]);
-                    const double d2 = nearest_image(Ri[2] - q[u].z, cg.L[2]);
+                    const double d0 = pair_sep(Ri[0] - q[u].x, cg.L[0], cg.periodic[0]);
+                    const double d1 = pair_sep(Ri[1] - q[u].y, cg.L[1], cg.periodic[1]);
+                    const double d2 = pair_sep(Ri[2] - q[u].z, cg.L[2], cg.periodic[2]);
                     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
                     if (!(r2 < cg.rc2)) continue;
                     const double s2 = cg.sig2 / r2;
@@ -176,22 +194,20 @@ __global__ void __launch_bounds__(256) k_wca_adjoint(const double *__restrict__ 
             const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
             int cn[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cn[a] = ci[a] + o[a];
-                cn[a] += cn[a] < 0 ? cg.nc[a] : (cn[a] >= cg.nc[a] ? -cg.nc[a] : 0);
-            }
-            const int nb = cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
+            for (int a = 0; a < 3; ++a) cn[a] = neighbour_cell(ci[a], o[a], cg.nc[a], cg.periodic[a]);
+            // a lane whose cell lies past a wall has no candidates
+            const int nb = (cn[0] < 0 || cn[1] < 0 || cn[2] < 0) ? -1 : cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
             const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
             const double Gi[3] = {fc_bar[3 * i], fc_bar[3 * i + 1], fc_bar[3 * i + 2]};
             const double self = (double)i;
-            const int hi = start[nb + 1];
-            for (int k = start[nb]; k < hi; ++k) {
+            const int lo = nb < 0 ? 0 : start[nb], hi = nb < 0 ? 0 : start[nb + 1];
+            for (int k = lo; k < hi; ++k) {
                 const double4 q = cpos[k];
                 if (q.w == self) continue;
                 double d[3];
-                d[0] = nearest_image(Ri[0] - q.x, cg.L[0]);
-                d[1] = nearest_image(Ri[1] - q.y, cg.L[1]);
-                d[2] = nearest_image(Ri[2] - q.z, cg.L[2]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) d[a] = pair_sep(Ri[a] - (a == 0 ? q.x : (a == 1 ? q.y : q.z)), cg.L[a],
+                                                           cg.periodic[a]);
                 const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                 if (!(r2 < cg.rc2)) continue;
                 const int j = (int)q.w;

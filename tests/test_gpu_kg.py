@@ -37,10 +37,10 @@ def shifted_chains(pos, length, L, rng):
     return pos
 
 
-def gpu_forces(lat, dims, pos, bonds, eps=EPS, sig=SIG, bond="fene", k=K_FENE, r0=R0):
+def gpu_forces(lat, dims, pos, bonds, eps=EPS, sig=SIG, bond="fene", k=K_FENE, r0=R0, walls=False):
     import torch
     nb = pos.shape[0]
-    dev = lat.Lattice(lat.FluidParams(nx=dims[0], ny=dims[1], nz=dims[2], track_totals=False))
+    dev = lat.Lattice(lat.FluidParams(nx=dims[0], ny=dims[1], nz=dims[2], track_totals=False, walls=walls))
     dev.init_equilibrium()
     db = lat.DeviceBeads(pos, np.zeros((nb, 3)), np.ones(nb), np.zeros(nb), bonds, k, r0, bond=bond,
                          wca_epsilon=eps, wca_sigma=sig)
@@ -54,8 +54,8 @@ def gpu_forces(lat, dims, pos, bonds, eps=EPS, sig=SIG, bond="fene", k=K_FENE, r
     return F, R
 
 
-def oracle_forces(orc, dims, pos, bonds, eps=EPS, sig=SIG, fene=True, k=K_FENE, r0=R0):
-    p = orc.Params(nx=dims[0], ny=dims[1], nz=dims[2])
+def oracle_forces(orc, dims, pos, bonds, eps=EPS, sig=SIG, fene=True, k=K_FENE, r0=R0, walls=False):
+    p = orc.Params(nx=dims[0], ny=dims[1], nz=dims[2], walls=walls)
     nb = pos.shape[0]
     b = orc.Beads(pos.copy(), np.zeros((nb, 3)), np.ones(nb), np.zeros(nb), bonds, k, r0, fene=fene, wca_eps=eps,
                   wca_sigma=sig)
@@ -109,6 +109,32 @@ def test_wca_edge_positions_and_dense_cluster(orc, lat):
     print("edge/cluster err", err, "scale", scale, "beads", pos.shape[0])
     assert err <= 1e-12 * scale
     assert np.abs(ref[:3]).max() > 0   # beads 0, 1, 2 interact across the boundary
+
+
+@pytest.mark.parametrize("nz", [12, 2])
+def test_kg_forces_between_walls(orc, lat, nz):
+    """With walls the z axis is not periodic: beads spread over the whole
+    channel, next to both walls (and, at nz = 2, a channel narrower than
+    2 r_c, one cell along z), WCA only, against the oracle; a pair 0.7
+    apart only through the wall feels nothing."""
+    dims = (12, 10, nz)
+    rng = np.random.default_rng(nz)
+    keep = []
+    while len(keep) < 60:
+        x = np.array([rng.uniform(0, 12), rng.uniform(0, 10), rng.uniform(-0.45, nz - 0.55)])
+        if all(np.linalg.norm(x - y) >= 0.8 for y in keep):
+            keep.append(x)
+    pos = np.array(keep)
+    none = np.zeros((0, 2), np.int32)
+    F, _ = gpu_forces(lat, dims, pos, none, bond="harmonic", k=0.0, r0=1.0, walls=True)
+    ref = oracle_forces(orc, dims, pos, none, fene=False, k=0.0, r0=1.0, walls=True)
+    scale = np.abs(ref).max()
+    err = np.abs(F - ref).max()
+    print(f"nz={nz} KG force err with walls", err, "scale", scale)
+    assert scale > 0 and err <= 1e-12 * scale
+    two = np.array([[3.0, 3.0, -0.3], [3.2, 3.0, nz - 0.6]])
+    F2, _ = gpu_forces(lat, dims, two, none, bond="harmonic", k=0.0, r0=1.0, walls=True)
+    assert np.abs(F2).max() == 0.0
 
 
 def test_kg_forces_are_reproducible(lat):
@@ -220,7 +246,9 @@ def test_kg_argument_errors(lat):
     assert code(p8, wca_epsilon=EPS, wca_sigma=0.0) == LB_EINVAL
     assert code(p8, wca_epsilon=EPS, wca_sigma=3.6) == LB_EINVAL        # 2 r_c = 8.08 > 8
     assert code(p8, wca_epsilon=EPS, wca_sigma=3.5) == 0
-    assert code(lat.FluidParams(nx=8, ny=8, nz=8, walls=True), wca_epsilon=EPS) == LB_EUNSUPPORTED
+    assert code(lat.FluidParams(nx=8, ny=8, nz=8, walls=True), wca_epsilon=EPS) == 0
+    assert code(lat.FluidParams(nx=8, ny=8, nz=3, walls=True), wca_epsilon=EPS) == 0    # z not periodic
+    assert code(lat.FluidParams(nx=8, ny=2, nz=8, walls=True), wca_epsilon=EPS) == LB_EINVAL     # 2 r_c > 2
     assert code(p8, tape=True, bond="fene") == 0          # differentiated since the adjoint covers them
     assert code(p8, tape=True, wca_epsilon=EPS) == 0
     assert code(p8, tape=True) == 0

@@ -122,3 +122,24 @@ def test_frictionless_chains_conserve_energy(orc):
     ke0 = 0.5 * (mom0 ** 2).sum()
     assert np.abs(Es - E0).max() < 0.05 * ke0
     assert abs(Es[-4:].mean() - Es[:4].mean()) < 0.01 * ke0
+
+
+def test_wca_does_not_act_through_walls(orc):
+    """With walls at z = -1/2 and z = nz - 1/2 the z axis is not periodic:
+    beads close to opposite walls, 0.7 apart through the periodic image,
+    do not interact; the same pair near the middle does, and its force is
+    minus the gradient of the closed-form energy."""
+    p = orc.Params(nx=8, ny=8, nz=8, walls=True)
+    pos = np.array([[2.0, 2.0, 0.2], [2.1, 2.0, 7.5]])
+    b = orc.Beads(pos.copy(), np.zeros((2, 3)), np.ones(2), np.zeros(2), np.zeros((0, 2), np.int32), 0.0, 1.0,
+                  wca_eps=EPS, wca_sigma=SIG)
+    assert np.abs(orc.bead_forces(p, b, pos)).max() == 0.0
+    pp = orc.Params(nx=8, ny=8, nz=8)          # periodic: the image pair interacts
+    assert np.abs(orc.bead_forces(pp, b, pos)).max() > 0.0
+    mid = np.array([[2.0, 2.0, 3.6], [2.1, 2.0, 4.3]])
+    F = orc.bead_forces(p, b, mid)
+    r = np.linalg.norm(mid[1] - mid[0])
+    e = 1e-6
+    dVdr = (v_wca(r + e) - v_wca(r - e)) / (2 * e)
+    np.testing.assert_allclose(F[1], -dVdr * (mid[1] - mid[0]) / r, rtol=1e-6)
+    np.testing.assert_allclose(F[0], -F[1], rtol=1e-15)
