@@ -919,6 +919,16 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
     if (p.graph_steps < 0 || (p.graph_steps & 1)) return fail(nullptr, LB_EINVAL, "graph_steps must be even and >= 0");
     if (p.walls) return fail(nullptr, LB_EUNSUPPORTED, "walls are available for a single box only");
     if (p.vacf_lags < 0 || p.vacf_lags > 1024) return fail(nullptr, LB_EINVAL, "vacf_lags must be in [0, 1024]");
+    // every box's extents before any device call
+    uint64_t total = 0;
+    for (int b = 0; b < nbox; ++b) {
+        const int32_t *e = dims + 3 * b;
+        if (e[0] < 2 || e[1] < 2 || e[2] < 2) return fail(nullptr, LB_EINVAL, "every box extent must be >= 2");
+        const uint64_t Nb = (uint64_t)e[0] * e[1] * e[2];
+        if (Nb >= (1ull << 30)) return fail(nullptr, LB_EINVAL, "box site count must be < 2^30");
+        total += Nb;
+    }
+    if (total >= (1ull << 31)) return fail(nullptr, LB_EINVAL, "total site count must be < 2^31");
     lb_ctx *c = new lb_ctx();
     c->p = p;
     c->batch = true;
@@ -930,15 +940,7 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
     uint64_t off = 0;
     for (int b = 0; b < nbox; ++b) {
         const int32_t *e = dims + 3 * b;
-        if (e[0] < 2 || e[1] < 2 || e[2] < 2) {
-            delete c;
-            return fail(nullptr, LB_EINVAL, "every box extent must be >= 2");
-        }
         const uint64_t Nb = (uint64_t)e[0] * e[1] * e[2];
-        if (Nb >= (1ull << 30)) {
-            delete c;
-            return fail(nullptr, LB_EINVAL, "box site count must be < 2^30");
-        }
         BoxDesc d{};
         d.geo.nx = e[0];
         d.geo.ny = e[1];
@@ -955,10 +957,6 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
         c->boxes_h.push_back(d);
         off += 19 * Nb;
         c->total_sites += Nb;
-    }
-    if (c->total_sites >= (1ull << 31)) {
-        delete c;
-        return fail(nullptr, LB_EINVAL, "total site count must be < 2^31");
     }
     c->geo = c->boxes_h[0].geo;  // first box (diagnostic helpers loop over all boxes)
     c->elem = storage_bytes(p.storage);

@@ -1,0 +1,113 @@
+"""Host-side behaviour of the C ABI that needs no GPU: lb_create and
+lb_create_batch validate their parameters before any device call (the
+stability bound |gamma| of Sec. "D3Q19 model II", kT >= 0, sizes), every
+entry point rejects a NULL context, and on a machine without a GPU a valid
+request fails loudly with LB_EDEVICE instead of falling back to anything."""
+import ctypes
+
+import pytest
+
+from conftest import gpu_available
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0803_2826_amd import _lib
+    return _lib.load()
+
+
+def params(**kw):
+    from paper_0803_2826_amd.lattice import FluidParams
+    base = dict(nx=8, ny=8, nz=8)
+    base.update(kw)
+    return FluidParams(**base).to_c()
+
+
+def create(L, p):
+    ctx = ctypes.c_void_p()
+    rc = L.lb_create(ctypes.byref(p), None, ctypes.byref(ctx))
+    msg = L.lb_last_error(None).decode()
+    if ctx.value:
+        L.lb_destroy(ctx)
+    return rc, msg
+
+
+@pytest.mark.parametrize("kw,text", [
+    (dict(nx=1), "extent"),
+    (dict(nx=1024, ny=1024, nz=1024), "2^30"),
+    (dict(rho0=0.0), "rho0"),
+    (dict(kT=-1e-4), "kT"),
+    (dict(gamma_shear=1.0), "gamma_shear"),
+    (dict(gamma_bulk=-1.0), "gamma_bulk"),
+    (dict(gamma_3a=1.5), "kinetic"),
+    (dict(body_force=(float("nan"), 0.0, 0.0)), "body force"),
+    (dict(rounding="stochastic"), "16-bit"),
+    (dict(block=100), "block"),
+])
+def test_create_rejects_bad_parameters(L, kw, text):
+    from paper_0803_2826_amd._lib import LB_EINVAL
+    rc, msg = create(L, params(**kw))
+    assert rc == LB_EINVAL
+    assert text in msg
+
+
+def test_create_rejects_raw_field_values(L):
+    from paper_0803_2826_amd._lib import LB_EINVAL
+    for field, value in (("storage", 7), ("rounding", 5), ("walls", 2)):
+        p = params()
+        setattr(p, field, value)
+        rc, _ = create(L, p)
+        assert rc == LB_EINVAL, field
+    ctx = ctypes.c_void_p()
+    assert L.lb_create(None, None, ctypes.byref(ctx)) == LB_EINVAL
+    assert L.lb_create(ctypes.byref(params()), None, None) == LB_EINVAL
+
+
+def test_create_batch_rejects_bad_boxes(L):
+    from paper_0803_2826_amd._lib import LB_EINVAL
+
+    def batch(dims, **kw):
+        arr = (ctypes.c_int32 * (3 * len(dims)))(*[v for d in dims for v in d])
+        ctx = ctypes.c_void_p()
+        rc = L.lb_create_batch(ctypes.byref(params(**kw)), len(dims), arr, None, ctypes.byref(ctx))
+        if ctx.value:
+            L.lb_destroy(ctx)
+        return rc, L.lb_last_error(None).decode()
+
+    assert batch([])[0] == LB_EINVAL
+    assert batch([(8, 8, 8), (8, 1, 8)])[0] == LB_EINVAL
+    assert batch([(1024, 1024, 1024)])[0] == LB_EINVAL
+    rc, msg = batch([(1023, 1024, 1024)] * 3)          # each box < 2^30 sites, together >= 2^31
+    assert rc == LB_EINVAL and "2^31" in msg
+    assert batch([(8, 8, 8)], graph_steps=3)[0] == LB_EINVAL
+    assert batch([(8, 8, 8)], vacf_lags=2000)[0] == LB_EINVAL
+
+
+def test_null_context_is_rejected_everywhere(L):
+    from paper_0803_2826_amd._lib import LB_EINVAL, LB_OK
+    out = (ctypes.c_double * 19)()
+    cfg = (ctypes.c_int32 * 4)()
+    n64 = ctypes.c_int64()
+    assert L.lb_step(None, 1) == LB_EINVAL
+    assert L.lb_couple(None, None) == LB_EINVAL
+    assert L.lb_moments(None, None, None) == LB_EINVAL
+    assert L.lb_totals(None, out) == LB_EINVAL
+    assert L.lb_totals_exact(None, out) == LB_EINVAL
+    assert L.lb_mode_stats(None, out) == LB_EINVAL
+    assert L.lb_sync(None) == LB_EINVAL
+    assert L.lb_tape_begin(None, 4) == LB_EINVAL
+    assert L.lb_backward(None, None, 1, None, out) == LB_EINVAL
+    assert L.lb_vacf(None, out, ctypes.byref(n64)) == LB_EINVAL
+    assert L.lb_launch_config(None, 0, cfg) == LB_EINVAL
+    assert L.lb_save(None, b"/nonexistent") == LB_EINVAL
+    assert L.lb_load(None, b"/nonexistent") == LB_EINVAL
+    assert L.lb_step_count(None) == 0
+    assert L.lb_destroy(None) == LB_OK
+
+
+def test_valid_request_without_gpu_fails_loudly(L):
+    from paper_0803_2826_amd._lib import LB_EDEVICE
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    rc, msg = create(L, params())
+    assert rc == LB_EDEVICE and msg

@@ -150,6 +150,37 @@ def test_bond_force_is_gradient(orc):
     np.testing.assert_allclose(beads.mom[0], -Fb, atol=1e-15)
 
 
+@pytest.mark.parametrize("W", [2, 3, 4])
+def test_spreading_is_the_transpose_of_interpolation(orc, W):
+    """The reaction is spread with the interpolation's own weights
+    (eq. ftotal with the Delta of eq. ufluid_discrete): every stencil node
+    receives w_q I / h, I = -(P'' - P - h F^c), nothing else is touched, so
+    sum_r f(r).v(r) = I . (sum_q w_q v(q)) for any field v (the adjoint
+    pairing of spreading and interpolation)."""
+    rng = np.random.default_rng(W)
+    L = 8
+    p = orc.Params(nx=L, ny=L, nz=L, g=(1e-5, 0.0, 0.0))
+    n = orc.init_equilibrium(p, u=rng.normal(scale=0.02, size=(3, L, L, L)))
+    R = np.array([3.37, 6.81, 0.22])
+    b = one_bead(orc, R, mom=(0.01, -0.02, 0.005), m=1.3, zeta=0.9)
+    b.stencil = W
+    P0 = b.mom[0].copy()
+    half = R + 0.5 * P0 / 1.3
+    f = np.zeros((3, L, L, L))
+    orc.couple(p, n, 0, b, f)
+    I = -(b.mom[0] - P0)                      # no conservative force, h = 1
+    nodes, w, _ = orc.stencil_w(p, half, W)
+    flat = f.reshape(3, -1)
+    expect = np.zeros_like(flat)
+    for q, wq in zip(nodes, w):
+        expect[:, q] += wq * I
+    np.testing.assert_allclose(flat, expect, rtol=0, atol=1e-17)
+    v = rng.normal(size=(3, L ** 3))
+    lhs = (flat * v).sum()
+    rhs = I @ sum(wq * v[:, q] for q, wq in zip(nodes, w))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
 def test_spread_sums_to_impulse_and_total_momentum(orc):
     """Coupled step: sum of spread force = sum of bead impulses; total fluid +
     bead momentum changes by exactly N g; fluid mass unchanged."""
