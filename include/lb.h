@@ -133,10 +133,10 @@ typedef struct {
  * LB_BOND_HARMONIC: (k_bond/2)(r - r0)^2;
  * LB_BOND_FENE: -(k_bond/2) r0^2 ln(1 - r^2/r0^2) for r < r0 (eq. ufene,
  *   r0 = R_0 the maximum extension).  A bond at r >= r0 has no finite
- *   force: the step gives its beads' momenta a NaN, spreads their NaN
- *   impulse to the fluid at their stencil nodes (the oracle does the same)
- *   and latches a device flag that the next synchronising call reports as
- *   LB_ENONFINITE. */
+ *   force: the step gives its beads' momenta a NaN (as the oracle does),
+ *   does not spread their non-finite impulse (the fluid stays finite; the
+ *   oracle spreads the NaN) and latches a device flag that the next
+ *   synchronising call reports as LB_ENONFINITE. */
 typedef enum { LB_BOND_HARMONIC = 0, LB_BOND_FENE = 1 } lb_bond;
 
 /* Point particles with bonds and an optional purely repulsive pair

@@ -34,7 +34,7 @@ struct AdjArgs {
     double *partials;       // [gridDim][3] block sums of Fbar, accumulated over the steps of a sweep
     // bead force of the step (FORCE variant): F = g + force at sites whose
     // bit is set in fmask; the adjoint of that force is written to fbar there
-    const float *force;     // [3][N]
+    const long long *force; // [3][N] fixed point (kForceScale)
     const uint32_t *fmask;  // [ceil(N/32)]
     float *fbar;            // [3][N]
 };
@@ -70,9 +70,9 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         if (FORCE) {
             flagged = (a.fmask[s >> 5] >> (s & 31u)) & 1u;
             if (flagged) {
-                F[0] += a.force[s];
-                F[1] += a.force[(size_t)N + s];
-                F[2] += a.force[2 * (size_t)N + s];
+                F[0] += force_value(a.force[s]);
+                F[1] += force_value(a.force[(size_t)N + s]);
+                F[2] += force_value(a.force[2 * (size_t)N + s]);
             }
         }
         const float rho = a.cc.rho0 + m0;

@@ -193,8 +193,8 @@ __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, co
 // compactly (its touched nodes and their force values) before the step
 // consumes it, so that the adjoint sweep can restore it without running the
 // particle half again.
-__global__ void k_save_touched(const float *force, const int32_t *list, const int32_t *count, int cap, uint32_t N,
-                               int32_t *slist, int32_t *scount, float *svals)
+__global__ void k_save_touched(const long long *force, const int32_t *list, const int32_t *count, int cap,
+                               uint32_t N, int32_t *slist, int32_t *scount, long long *svals)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int cnt = min(*count, cap);
@@ -207,8 +207,8 @@ __global__ void k_save_touched(const float *force, const int32_t *list, const in
 
 // Adjoint sweep: put a saved spread force back (values, bitmap bits, the
 // touched-node list and its count).  The force field is zero on entry.
-__global__ void k_restore_touched(const int32_t *slist, const int32_t *scount, const float *svals, int cap,
-                                  uint32_t N, float *force, uint32_t *fmask, int32_t *list, int32_t *count)
+__global__ void k_restore_touched(const int32_t *slist, const int32_t *scount, const long long *svals, int cap,
+                                  uint32_t N, long long *force, uint32_t *fmask, int32_t *list, int32_t *count)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int cnt = min(*scount, cap);
@@ -221,14 +221,14 @@ __global__ void k_restore_touched(const int32_t *slist, const int32_t *scount, c
 }
 
 // Zero the force, its adjoint and the bitmap word of every touched node.
-__global__ void k_clear_touched_adj(float *force, float *fbar, uint32_t *fmask, const int32_t *list,
+__global__ void k_clear_touched_adj(long long *force, float *fbar, uint32_t *fmask, const int32_t *list,
                                     const int32_t *count, int cap, uint32_t N)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= cap || idx >= *count) return;
     const uint32_t s = (uint32_t)list[idx];
     for (int c = 0; c < 3; ++c) {
-        force[(size_t)c * N + s] = 0.f;
+        force[(size_t)c * N + s] = 0;
         fbar[(size_t)c * N + s] = 0.f;
     }
     fmask[s >> 5] = 0u;

@@ -18,7 +18,10 @@
 //                   every lane then evaluates P'' = C1 P + C2 (F^c + zeta u_b)
 //                   + C3 theta (eq. langevin_momentum_update) and spreads
 //                   w I / h with I = -(P'' - P - h F^c) to its own node
-//                   (eq. ftotal), setting the node's bit in the force bitmap
+//                   (eq. ftotal; fixed-point integer atomics, so the sum
+//                   does not depend on the order; a non-finite or absurdly
+//                   large contribution is refused and latched as bit 2 of the
+//                   device flags), setting the node's bit in the force bitmap
 //                   (and, for the backward sweep, listing the nodes it is the
 //                   first to flag); R = R' + (h/2) P''/m
 //   (next lb_step)  the fused stream-collide kernel adds the bead force at
@@ -57,7 +60,7 @@ struct CoupleArgs {
     int32_t fene;         // 1: FENE bonds, 0: harmonic
     double kb, r0;
     int32_t *flags;       // bit 1: a FENE bond at r >= r0
-    float *force;         // [3][N] sparse force field (zero outside touched nodes)
+    long long *force;     // [3][N] sparse force field, fixed point (zero outside touched nodes)
     uint32_t *fmask;      // [ceil(N/32)] force bitmap
     int32_t *list;        // [W^3 n] touched nodes, or NULL (no list kept)
     int32_t *count;       // number of entries in list
@@ -261,7 +264,14 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
     }
     bool first = false;  // this lane set its node's bit: the node joins the touched list
     if (wq != 0.0) {
-        for (int c = 0; c < 3; ++c) atomicAdd(&a.force[(size_t)c * g.N + node], (float)(wq * I[c] / h));
+        for (int c = 0; c < 3; ++c) {
+            const double v = wq * I[c] / h;
+            if (fabs(v) < kForceLimit)  // false for NaN too
+                atomicAdd(reinterpret_cast<unsigned long long *>(&a.force[(size_t)c * g.N + node]),
+                          (unsigned long long)__double2ll_rn(v * kForceScale));
+            else
+                __hip_atomic_fetch_or(a.flags, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         const uint32_t bit = 1u << (node & 31u);
         if (a.list)
             first = (atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u;

@@ -231,6 +231,16 @@ __device__ __forceinline__ void st_plane_nt(void *plane, uint32_t nbytes, uint32
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)(idx * 2u), 0, 2);
 }
 
+// The bead force field is kept in fixed point, in units of 2^-44: the spread
+// contributions of many beads then add up with integer atomics, whose sum does
+// not depend on their order (coupled runs repeat bit for bit).  2^-44 is
+// finer than the FP32 spacing of any force above 2^-21 and leaves |f| < 2^18
+// for the sum.
+constexpr double kForceScale = 17592186044416.0;  // 2^44
+constexpr double kForceLimit = 262144.0;          // 2^18: larger or non-finite contributions are refused
+
+__device__ __forceinline__ float force_value(long long q) { return (float)((double)q * (1.0 / kForceScale)); }
+
 // Arguments of the fused step kernel.
 struct StepArgs {
     const void *src;      // buffer A, [19][N]
@@ -244,7 +254,7 @@ struct StepArgs {
     double *partials;     // [gridDim][4] per-block totals (TOTALS only)
     int32_t *flags;       // bit 0: non-finite density seen
     uint32_t *fmask;        // [ceil(N/32)] 1 bit per site: bead force present (FORCE only)
-    float *force;           // [3][N] bead force density at flagged sites (FORCE only)
+    long long *force;       // [3][N] bead force density at flagged sites, fixed point (FORCE only)
     uint32_t consume;       // FORCE: 1 = zero the force rows and bitmap words this step read
 };
 
@@ -371,13 +381,13 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         if (FORCE) {
             const uint32_t word = a.fmask[s >> 5];
             if ((word >> (s & 31u)) & 1u) {
-                F[0] += a.force[s];
-                F[1] += a.force[(size_t)N + s];
-                F[2] += a.force[2 * (size_t)N + s];
+                F[0] += force_value(a.force[s]);
+                F[1] += force_value(a.force[(size_t)N + s]);
+                F[2] += force_value(a.force[2 * (size_t)N + s]);
                 if (a.consume) {
-                    a.force[s] = 0.f;
-                    a.force[(size_t)N + s] = 0.f;
-                    a.force[2 * (size_t)N + s] = 0.f;
+                    a.force[s] = 0;
+                    a.force[(size_t)N + s] = 0;
+                    a.force[2 * (size_t)N + s] = 0;
                 }
             }
             // The 32 sites of a bitmap word lie in one wave (waves start at

@@ -50,7 +50,7 @@ struct lb_ctx {
     bool totals_valid = false;       // fused totals of the last step are in `partials`
     bool thermal = false;
     // bead coupling (allocated on first lb_couple)
-    float *force = nullptr;          // [3][N]
+    long long *force = nullptr;      // [3][N] fixed point (kForceScale)
     uint32_t *fmask = nullptr;       // [ceil(N/32)] bit per site: bead force present
     int32_t *list = nullptr;         // touched nodes of the pending force
     int32_t *count = nullptr;
@@ -317,6 +317,7 @@ int read_flags(lb_ctx *c)
     LB_TRY(check(c, hipMemcpyAsync(&h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream), "flags copy"));
     LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
     if (h & 2) return fail(c, LB_ENONFINITE, "a FENE bond was stretched to r >= r0 (bead momentum is NaN)");
+    if (h & 4) return fail(c, LB_ENONFINITE, "a bead's spread force was not finite (not applied)");
     if (h & 1) return fail(c, LB_ENONFINITE, "non-finite population encountered on the device");
     return LB_OK;
 }
@@ -326,11 +327,12 @@ int ensure_bead_buffers(lb_ctx *c, int n)
     const size_t N = c->geo.N;
     const size_t nwords = (N + 31) / 32;
     if (!c->force) {
-        if (hipMalloc(&c->force, 3 * N * sizeof(float)) != hipSuccess ||
+        if (hipMalloc(&c->force, 3 * N * sizeof(long long)) != hipSuccess ||
             hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess ||
             hipMalloc(&c->count, sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead force field allocation failed");
-        hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->force, 3 * N);
+        hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->force),
+                           6 * N);
         hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nwords, 256)), dim3(256), 0, c->stream,
                            reinterpret_cast<int32_t *>(c->fmask), (uint32_t)nwords);
         LB_LAUNCH_CHECK(c, "zero force field");
@@ -1389,6 +1391,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     double *pos_bar = nullptr, *mom_bar = nullptr;
     int seg_rows = 0;       // touched-node capacity per saved step
     size_t seg_stride = 0;  // bytes per saved step in seg_bead
+    int seg_vals_offset = 0;  // int32 offset of the saved force values from the saved count
     if (coupled) {
         if (c->bead_work_n < nbd) {
             (void)hipFree(c->bead_work);
@@ -1407,7 +1410,9 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         int wmax = 2;
         for (const lb_beads &bt : c->tape_beads) wmax = std::max(wmax, (bt.stencil == 3 || bt.stencil == 4) ? bt.stencil : 2);
         seg_rows = wmax * wmax * wmax * nbd;
-        seg_stride = 3 * n3 * sizeof(double) + (size_t)seg_rows * 4 * sizeof(float) + 256;
+        seg_vals_offset = 64 + ((seg_rows + 1) & ~1);  // int32 units from the count: 8-byte aligned values
+        seg_stride = 3 * n3 * sizeof(double) + (size_t)seg_vals_offset * sizeof(int32_t) +
+                     3 * (size_t)seg_rows * sizeof(long long);
         if (c->seg_bead_bytes < (size_t)K * seg_stride) {
             (void)hipFree(c->seg_bead);
             c->seg_bead = nullptr;
@@ -1460,11 +1465,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                            c->force, c->fbar, c->fmask, c->list, c->count, 64 * nbd, c->geo.N);
     };
     // saved step k of the segment: R' [n3], F^c [n3], P'' [n3] (FP64), then
-    // the touched count, nodes and force values
+    // the touched count (64 int32 slots), nodes and fixed-point force values
     struct Saved {
         double *half, *fc, *mom;
         int32_t *count, *list;
-        float *vals;
+        long long *vals;
     };
     auto saved = [&](int k) {
         char *b = static_cast<char *>(c->seg_bead) + (size_t)k * seg_stride;
@@ -1475,7 +1480,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         v.mom = v.fc + n3;
         v.count = reinterpret_cast<int32_t *>(v.mom + n3);
         v.list = v.count + 64;
-        v.vals = reinterpret_cast<float *>(v.list + seg_rows);
+        v.vals = reinterpret_cast<long long *>(v.count + seg_vals_offset);
         return v;
     };
     double *const ctx_half = c->half, *const ctx_fc = c->fc;

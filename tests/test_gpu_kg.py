@@ -211,13 +211,9 @@ def test_fene_overstretch_is_reported(lat):
     mom = db.mom.cpu().numpy()
     assert not np.isfinite(mom[:2]).any()
     assert np.isfinite(mom[2:]).all()     # the other chain is unaffected
-    # the NaN impulse reaches the fluid only at the broken bond's stencil nodes
-    # (x in 2..4, y = z = 2) and, after one step, their neighbours
+    # the NaN impulse is refused by the fixed-point force field: the fluid stays finite
     dev.step(1)
-    bad = np.argwhere(~np.isfinite(dev.get_populations().cpu().numpy()).all(0))   # (z, y, x)
-    assert bad.shape[0] > 0
-    assert (bad[:, 2] >= 1).all() and (bad[:, 2] <= 5).all()
-    assert (bad[:, :2] >= 1).all() and (bad[:, :2] <= 3).all()
+    assert np.isfinite(dev.get_populations().cpu().numpy()).all()
     dev.close()
     torch.cuda.synchronize()
 
