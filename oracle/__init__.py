@@ -68,6 +68,7 @@ class OrcBeadset(ctypes.Structure):
         ("stencil", ctypes.c_int32), ("fene", ctypes.c_int32),
         ("fext", ctypes.POINTER(ctypes.c_double)),
         ("wca_eps", ctypes.c_double), ("wca_sigma", ctypes.c_double),
+        ("three_point", ctypes.c_int32),
     ]
 
 @dataclass
@@ -128,6 +129,7 @@ def lib():
         L.orc_philox4x32_10.argtypes = [up, up, up]
         L.orc_fluid_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
         L.orc_bead_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.orc_bead_three_point.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc_moments_site.argtypes = [dp, dp]
         L.orc_back_site.argtypes = [dp, dp]
@@ -154,7 +156,7 @@ def lib():
                                            dp, dp, dp, dp]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
-        for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals",
+        for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals", "orc_bead_three_point",
                      "orc_equilibrium", "orc_moments_site", "orc_back_site", "orc_collide_site",
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
                      "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step",
@@ -210,6 +212,12 @@ def fluid_normals(seed: int, site: int, step: int, box: int = 0) -> np.ndarray:
 def bead_normals(seed: int, bead: int, step: int, box: int = 0) -> np.ndarray:
     g = np.zeros(3)
     lib().orc_bead_normals(seed, bead, step, box, _dp(g))
+    return g
+
+
+def bead_three_point(seed: int, bead: int, step: int, box: int = 0) -> np.ndarray:
+    g = np.zeros(3)
+    lib().orc_bead_three_point(seed, bead, step, box, _dp(g))
     return g
 
 
@@ -321,11 +329,13 @@ class Beads:
     fene: bool = False               # FENE bonds (k_bond = k, r0 = R0) instead of harmonic
     wca_eps: float = 0.0             # WCA interaction strength (0: off)
     wca_sigma: float = 1.0
+    three_point: bool = False        # bead noise from the three-point distribution instead of Gaussians
 
     def copy(self) -> "Beads":
         return Beads(self.pos.copy(), self.mom.copy(), self.mass.copy(), self.zeta.copy(),
                      self.bonds.copy(), self.k_bond, self.r0, self.stencil,
-                     None if self.fext is None else self.fext.copy(), self.fene, self.wca_eps, self.wca_sigma)
+                     None if self.fext is None else self.fext.copy(), self.fene, self.wca_eps, self.wca_sigma,
+                     self.three_point)
 
     def c(self):
         """ctypes bead-set descriptor (and the arrays it points to)."""
@@ -345,6 +355,7 @@ class Beads:
         b.fext = _dp(keep[3]) if keep[3] is not None else None
         b.wca_eps = float(self.wca_eps)
         b.wca_sigma = float(self.wca_sigma)
+        b.three_point = 1 if self.three_point else 0
         return b, keep
 
 

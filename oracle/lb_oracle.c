@@ -222,6 +222,28 @@ void orc_bead_normals(uint64_t seed, uint32_t bead, uint32_t step, uint32_t box,
     box_muller(w[2] >> 8, w[3] >> 8, &g[2], &g3);
 }
 
+/* Three finite-range variates for the Langevin noise of bead `bead` at
+ * `step` (Sec. "Force coupling", the three-point distribution given after
+ * eq. langevin_momentum_update: theta = 0 with probability 2/3 and
+ * +-sqrt(3) with probability 1/6 each, so that its moments match a unit
+ * Gaussian's through the fourth).  The same Philox call as the Gaussian
+ * variant (stream 1); word a picks a sixth k = floor(6 w_a / 2^32) of the
+ * 32-bit range: k = 0 gives -sqrt(3), k = 5 gives +sqrt(3), any other k 0.
+ * Parity pinned: the sixth is checked against exact rational thresholds
+ * on the words orc_philox4x32_10 returns, and the frozen-fluid OU variance
+ * holds with these variates. */
+void orc_bead_three_point(uint64_t seed, uint32_t bead, uint32_t step, uint32_t box, double g[3])
+{
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    const uint32_t ctr[4] = {bead, step, (1u << 16) | 0u, box};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    for (int a = 0; a < 3; ++a) {
+        const uint64_t k = ((uint64_t)w[a] * 6u) >> 32;
+        g[a] = (k == 0) ? -sqrt(3.0) : (k == 5) ? sqrt(3.0) : 0.0;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Parameters                                                                */
 /* ------------------------------------------------------------------------ */
@@ -627,7 +649,17 @@ typedef struct {
     int32_t fene;         /* 0: harmonic bonds, 1: FENE bonds */
     const double *fext;   /* [n][3] or NULL */
     double wca_eps, wca_sigma;
+    int32_t three_point;  /* bead noise: 0 unit Gaussians, 1 the three-point variates */
 } orc_beadset;
+
+/* The bead noise theta of eq. langevin_momentum_update for bead b at `step`. */
+static void bead_noise(const orc_params *p, const orc_beadset *bs, int b, uint32_t step, double th[3])
+{
+    if (bs->three_point)
+        orc_bead_three_point(p->seed, (uint32_t)b, step, p->box, th);
+    else
+        orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
+}
 
 static int bs_width(const orc_beadset *bs) { return (bs->stencil == 3 || bs->stencil == 4) ? bs->stencil : 2; }
 
@@ -754,7 +786,8 @@ static void site_velocity(const orc_params *p, const double *n, int64_t N, int64
  *      current (pre-collision) populations n: u = (sum n c + g/2)/rho;
  *   4. P'' = C1 P + C2 (F^c + zeta u_b) + C3 theta, with
  *      C1 = exp(-zeta h/m), C2 = (m/zeta)(1 - C1),
- *      C3 = sqrt(m kT (1 - exp(-2 zeta h/m)));
+ *      C3 = sqrt(m kT (1 - exp(-2 zeta h/m))), theta unit Gaussians or,
+ *      with three_point set, the three-point variates;
  *   5. the fluid receives the momentum the bead exchanged with it,
  *      I = -(P'' - P - h F^c), spread as force density I Delta / h into
  *      `force` (layout [3][N], accumulated);
@@ -787,7 +820,7 @@ void orc_couple(const orc_params *p, const double *n, uint32_t step, const orc_b
         double C1, C2, C3;
         ou_constants(m, z, p->kT, &C1, &C2, &C3);
         double th[3] = {0.0, 0.0, 0.0};
-        if (p->kT > 0.0 && z > 0.0) orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
+        if (p->kT > 0.0 && z > 0.0) bead_noise(p, bs, b, step, th);
         double Pn[3], I[3];
         for (int a = 0; a < 3; ++a) {
             Pn[a] = C1 * mom[3 * b + a] + C2 * (fc[3 * b + a] + z * ub[a]) + C3 * th[a];
@@ -1049,7 +1082,7 @@ void orc_couple_adjoint(const orc_params *p, const double *n, uint32_t step, con
         double C1, C2, C3;
         ou_constants(m, z, p->kT, &C1, &C2, &C3);
         double th[3] = {0.0, 0.0, 0.0};
-        if (p->kT > 0.0 && z > 0.0) orc_bead_normals(p->seed, (uint32_t)b, step, p->box, th);
+        if (p->kT > 0.0 && z > 0.0) bead_noise(p, bs, b, step, th);
         double I[3];
         for (int a = 0; a < 3; ++a) {
             const double Pn = C1 * mom[3 * b + a] + C2 * (fc[3 * b + a] + z * ub[a]) + C3 * th[a];

@@ -107,21 +107,31 @@ def test_bead_in_forced_fluid_at_rest_sees_half_the_force(orc, W):
     np.testing.assert_allclose(b.mom[0], m * (1 - math.exp(-z / m)) * g / 2, rtol=1e-12)
 
 
-def test_ou_variance_frozen_fluid(orc):
+@pytest.mark.parametrize("three_point", [False, True])
+def test_ou_variance_frozen_fluid(orc, three_point):
+    """The exact OU update gives Var P'' = m kT (1 - exp(-2 zeta h/m)) after
+    one step from P = 0 in a fluid at rest, for either bead noise (both have
+    unit variance)."""
     kT = 1e-4
     p = orc.Params(nx=4, ny=4, nz=4, kT=kT, seed=5)
     n = orc.init_equilibrium(p)
     nb = 20000
     m, z = 1.0, 20.0
     rng = np.random.default_rng(2)
-    beads = orc.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z))
+    beads = orc.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z),
+                      three_point=three_point)
     f = np.zeros((3, 4, 4, 4))
     orc.couple(p, n, 0, beads, f)
     var1 = beads.mom.var()
     assert var1 == pytest.approx(m * kT * (1 - math.exp(-2 * z / m)), rel=0.03)
+    if three_point:
+        # every component is C1 P + C2 zeta u + C3 theta with P = u = 0: one of three values
+        C3 = math.sqrt(m * kT * (1 - math.exp(-2 * z / m)))
+        np.testing.assert_allclose(np.unique(np.round(beads.mom / C3, 9)), [-math.sqrt(3), 0, math.sqrt(3)], atol=1e-8)
     # a bead with small friction approaches m kT
     z2 = 0.05
-    beads = orc.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z2))
+    beads = orc.Beads(rng.uniform(0, 4, (nb, 3)), np.zeros((nb, 3)), np.full(nb, m), np.full(nb, z2),
+                      three_point=three_point)
     for t in range(3):
         orc.couple(p, n, t, beads, np.zeros((3, 4, 4, 4)))
     expect = m * kT * (1 - math.exp(-2 * z2 * 3 / m))

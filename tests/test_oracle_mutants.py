@@ -62,8 +62,12 @@ MUTANTS = {
                                                                {"W": 3})]),
     "ou_noise_amplitude": ("*C3 = sqrt(m * kT * (1.0 - exp(-2.0 * z * h / m)));",
                            "*C3 = sqrt(m * kT * (1.0 - exp(-z * h / m)));",
-                           [(TB.test_ou_variance_frozen_fluid, {})]),
+                           [(TB.test_ou_variance_frozen_fluid, {"three_point": False})]),
     "ou_decay": ("*C1 = exp(-z * h / m);", "*C1 = exp(-0.5 * z * h / m);", [(TB.test_ou_mean_decay_frozen_fluid, {})]),
+    "three_point_upper_sixth": ("(k == 5) ? sqrt(3.0)", "(k == 4) ? sqrt(3.0)",
+                                [(TR.test_bead_three_point_follows_exact_thresholds, {})]),
+    "three_point_selected": ("if (bs->three_point)", "if (0)",
+                             [(TB.test_ou_variance_frozen_fluid, {"three_point": True})]),
     "impulse_sign": ("I[a] = -(Pn[a] - mom[3 * b + a] - h * fc[3 * b + a]);",
                      "I[a] = (Pn[a] - mom[3 * b + a] - h * fc[3 * b + a]);",
                      [(TB.test_spread_sums_to_impulse_and_total_momentum, {})]),

@@ -75,3 +75,36 @@ def test_bead_normals_distribution(orc):
     assert s.var() == pytest.approx(1.0, abs=0.05)
     # bead stream differs from the fluid stream at the same counter
     assert not np.allclose(orc.bead_normals(9, 5, 5)[:2], orc.fluid_normals(9, 5, 5)[:2])
+
+
+def test_bead_three_point_follows_exact_thresholds(orc):
+    """The three-point variate (Sec. "Force coupling", after eq.
+    langevin_momentum_update) reads the first three words w of the bead
+    stream's Philox call and maps w / 2^32 < 1/6 to -sqrt(3), >= 5/6 to
+    +sqrt(3), anything else to 0; checked here with exact rational
+    thresholds on the pinned Philox words, including words at the edges."""
+    import math
+    from fractions import Fraction
+    seed = (7 << 32) | 3
+    for bead, step, box in [(b, t, x) for b in range(60) for t in range(4) for x in (0, 5)]:
+        w = orc.philox4x32_10([bead, step, 1 << 16, box], [seed & 0xFFFFFFFF, seed >> 32])
+        got = orc.bead_three_point(seed, bead, step, box)
+        for a in range(3):
+            u = Fraction(int(w[a]), 2 ** 32)
+            want = -math.sqrt(3.0) if u < Fraction(1, 6) else math.sqrt(3.0) if u >= Fraction(5, 6) else 0.0
+            assert got[a] == want, (bead, step, box, a, int(w[a]))
+
+
+def test_bead_three_point_moments(orc):
+    """Probabilities 1/6, 2/3, 1/6 and the Gaussian moments the paper asks
+    the distribution to reproduce: mean 0, variance 1, fourth moment 3."""
+    s = np.array([orc.bead_three_point(11, b, t) for b in range(4000) for t in range(4)]).reshape(-1)
+    r3 = np.sqrt(3.0)
+    assert set(np.unique(s)) <= {-r3, 0.0, r3}
+    n = s.size
+    for value, prob in ((-r3, 1 / 6), (0.0, 2 / 3), (r3, 1 / 6)):
+        frac = np.mean(s == value)
+        assert abs(frac - prob) < 5 * np.sqrt(prob * (1 - prob) / n), value
+    assert abs(s.mean()) < 5 / np.sqrt(n)
+    assert (s ** 2).mean() == pytest.approx(1.0, abs=5 * np.sqrt(2 / n))
+    assert (s ** 4).mean() == pytest.approx(3.0, abs=5 * np.sqrt(24 / n))
