@@ -139,6 +139,17 @@ typedef struct {
  *   synchronising call reports as LB_ENONFINITE. */
 typedef enum { LB_BOND_HARMONIC = 0, LB_BOND_FENE = 1 } lb_bond;
 
+/* Distribution of the bead noise theta in the momentum update of eq.
+ * langevin_momentum_update (Sec. "Force coupling"):
+ * LB_NOISE_GAUSSIAN: unit Gaussians (Box-Muller);
+ * LB_NOISE_THREE_POINT: the finite-range distribution given after that
+ *   equation, theta = 0 with probability 2/3 and +-sqrt(3) with
+ *   probability 1/6 each; its moments agree with a unit Gaussian's up to
+ *   the fourth, which keeps the update's O(h^2) accuracy, and no draw is
+ *   ever large.  Both read the same Philox call (stream 1, keyed by bead,
+ *   step and box), so a taped run replays either exactly. */
+typedef enum { LB_NOISE_GAUSSIAN = 0, LB_NOISE_THREE_POINT = 1 } lb_noise;
+
 /* Point particles with bonds and an optional purely repulsive pair
  * potential (Sec. "Force coupling"; the Kremer-Grest bead-spring model of
  * Sec. "Coarse-grained models").  All arrays are device FP64 (bonds int32), caller-owned:
@@ -164,6 +175,7 @@ typedef enum { LB_BOND_HARMONIC = 0, LB_BOND_FENE = 1 } lb_bond;
  *                a wall); wca_epsilon = 0 switches it off.  Pairs are found
  *                with a cell list of cells no narrower than r_c, rebuilt
  *                every call; r_c must be below half of every periodic extent.
+ *   noise        distribution of the bead noise (lb_noise)
  * Units are lattice units (spacing a = 1, time step h = 1). */
 typedef struct {
     int32_t n;
@@ -180,6 +192,7 @@ typedef struct {
     int32_t bond;      /* lb_bond */
     double wca_epsilon;
     double wca_sigma;
+    int32_t noise;     /* lb_noise */
 } lb_beads;
 
 typedef struct lb_ctx lb_ctx;

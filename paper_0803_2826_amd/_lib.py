@@ -37,6 +37,7 @@ EXPORTS = (
 
 LB_ROUND_NEAREST, LB_ROUND_STOCHASTIC = 0, 1
 LB_BOND_HARMONIC, LB_BOND_FENE = 0, 1
+LB_NOISE_GAUSSIAN, LB_NOISE_THREE_POINT = 0, 1
 
 
 class lb_params(ctypes.Structure):
@@ -71,6 +72,7 @@ class lb_beads(ctypes.Structure):
         ("fext", ctypes.c_void_p),
         ("stencil", ctypes.c_int32), ("bond", ctypes.c_int32),
         ("wca_epsilon", ctypes.c_double), ("wca_sigma", ctypes.c_double),
+        ("noise", ctypes.c_int32),
     ]
 
 

@@ -61,7 +61,8 @@ class LBCoupledRollout(torch.autograd.Function):
         lat = Lattice(p)
         lat.set_populations(n0.detach())
         b = DeviceBeads(pos0.detach(), mom0.detach(), beads.mass, beads.zeta, beads.bonds, beads.k_bond, beads.r0,
-                        device=n0.device, stencil=beads.stencil, fext=beads.fext)
+                        device=n0.device, stencil=beads.stencil, fext=beads.fext, bond=beads.bond,
+                        wca_epsilon=beads.wca_epsilon, wca_sigma=beads.wca_sigma, noise=beads.noise)
         lat.tape_begin(checkpoint_every)
         for _ in range(nsteps):
             lat.coupled_step(b)

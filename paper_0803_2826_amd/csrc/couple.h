@@ -58,6 +58,7 @@ struct CoupleArgs {
     const int32_t *bonds; // [nbonds][2]
     int32_t nbonds;
     int32_t fene;         // 1: FENE bonds, 0: harmonic
+    int32_t three_point;  // bead noise: 1 the three-point variates, 0 unit Gaussians
     double kb, r0;
     int32_t *flags;       // bit 1: a FENE bond at r >= r0
     long long *force;     // [3][N] sparse force field, fixed point (zero outside touched nodes)
@@ -251,7 +252,12 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
         C3 = 0.0;
     }
     double th[3] = {0.0, 0.0, 0.0};
-    if (a.kT > 0.0 && z > 0.0) bead_normals((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
+    if (a.kT > 0.0 && z > 0.0) {
+        if (a.three_point)
+            bead_three_point((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
+        else
+            bead_normals((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
+    }
     double Pn[3], I[3], Fc[3];
     for (int c = 0; c < 3; ++c) {
         // F^c = (bonds + pairs) + fext

@@ -539,6 +539,7 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     a.bonds = b->bonds;
     a.nbonds = b->nbonds;
     a.fene = (int32_t)(b->bond == LB_BOND_FENE);
+    a.three_point = (int32_t)(b->noise == LB_NOISE_THREE_POINT);
     a.kb = b->k_bond;
     a.r0 = b->r0;
     a.flags = c->flags;
@@ -1167,6 +1168,8 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     if (b->stencil != 0 && b->stencil != 2 && b->stencil != 3 && b->stencil != 4)
         return fail(c, LB_EINVAL, "stencil must be 0, 2, 3 or 4");
     if (b->bond != LB_BOND_HARMONIC && b->bond != LB_BOND_FENE) return fail(c, LB_EINVAL, "unknown bond kind");
+    if (b->noise != LB_NOISE_GAUSSIAN && b->noise != LB_NOISE_THREE_POINT)
+        return fail(c, LB_EINVAL, "unknown bead noise distribution");
     if (b->bond == LB_BOND_FENE && b->nbonds > 0 && !(b->r0 > 0.0 && b->k_bond >= 0.0))
         return fail(c, LB_EINVAL, "FENE bonds need r0 > 0 and k_bond >= 0");
     if (!(std::isfinite(b->wca_epsilon) && b->wca_epsilon >= 0.0))

@@ -110,4 +110,22 @@ __device__ __forceinline__ void bead_normals(uint32_t bead, uint32_t step, uint3
     g[2] = r1 * cos(two_pi * ub1);
 }
 
+// Three finite-range variates for the Langevin noise of one bead (Sec.
+// "Force coupling", the three-point distribution given after eq.
+// langevin_momentum_update): the same Philox call as bead_normals; word a
+// falls in the sixth k = floor(6 w / 2^32) of the 32-bit range, k = 0 gives
+// -sqrt(3), k = 5 gives +sqrt(3), the four middle sixths give 0.
+__device__ __forceinline__ void bead_three_point(uint32_t bead, uint32_t step, uint32_t box, uint32_t k0,
+                                                 uint32_t k1, double g[3])
+{
+    const Philox4 A = philox4x32_10(bead, step, 1u << 16, box, k0, k1);
+    const double r3 = 1.7320508075688772;  // the double nearest sqrt(3)
+    const uint32_t w[3] = {A.v0, A.v1, A.v2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t k = __umulhi(w[a], 6u);
+        g[a] = (k == 0u) ? -r3 : (k == 5u) ? r3 : 0.0;
+    }
+}
+
 }  // namespace lbmi

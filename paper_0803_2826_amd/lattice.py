@@ -91,13 +91,21 @@ class DeviceBeads:
     """Bead state on the device (float64 tensors, positions unwrapped)."""
 
     def __init__(self, pos, mom, mass, zeta, bonds=None, k_bond=0.0, r0=1.0, device="cuda", stencil: int = 2,
-                 fext=None, bond: str = "harmonic", wca_epsilon: float = 0.0, wca_sigma: float = 1.0):
+                 fext=None, bond: str = "harmonic", wca_epsilon: float = 0.0, wca_sigma: float = 1.0,
+                 noise: str = "gaussian"):
         """stencil: points per axis of the interpolation kernel (2, 3, 4 for
         phi_2, phi_3, phi_4); fext: optional [n, 3] external force per bead;
         bond: "harmonic" ((k/2)(r - r0)^2) or "fene" (-(k/2) r0^2 ln(1 - r^2/r0^2),
         r0 the maximum extension); wca_epsilon > 0 adds the purely repulsive
-        Lennard-Jones pair force (cut at 2^(1/6) wca_sigma) between all beads."""
+        Lennard-Jones pair force (cut at 2^(1/6) wca_sigma) between all beads;
+        noise: "gaussian" or "three_point" (the finite-range variate 0, +-sqrt(3)
+        with probabilities 2/3, 1/6, 1/6) for the bead momentum update."""
         dev = torch.device(device)
+        noises = {"gaussian": _lib.LB_NOISE_GAUSSIAN, "three_point": _lib.LB_NOISE_THREE_POINT}
+        if noise not in noises:
+            raise ValueError(f"noise must be one of {sorted(noises)}")
+        self.noise = noise
+        self._noise_code = noises[noise]
         self.stencil = int(stencil)
         kinds = {"harmonic": _lib.LB_BOND_HARMONIC, "fene": _lib.LB_BOND_FENE}
         if bond not in kinds:
@@ -142,6 +150,7 @@ class DeviceBeads:
         b.bond = self._bond_code
         b.wca_epsilon = self.wca_epsilon
         b.wca_sigma = self.wca_sigma
+        b.noise = self._noise_code
         return b
 
 

@@ -57,7 +57,7 @@ int main(void) {
   F(lb_params, vacf_lags) F(lb_params, graph_steps) F(lb_params, rounding) F(lb_params, walls)
   F(lb_beads, pos) F(lb_beads, mom) F(lb_beads, mass) F(lb_beads, zeta) F(lb_beads, bonds)
   F(lb_beads, k_bond) F(lb_beads, r0) F(lb_beads, fext) F(lb_beads, stencil) F(lb_beads, bond)
-  F(lb_beads, wca_epsilon) F(lb_beads, wca_sigma)
+  F(lb_beads, wca_epsilon) F(lb_beads, wca_sigma) F(lb_beads, noise)
   return 0;
 }
 '''

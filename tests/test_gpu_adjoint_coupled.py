@@ -5,9 +5,10 @@ coupled steps, which is itself pinned by central finite differences.
 Tolerance: as for the fluid-only adjoint, the GPU computes the fluid forward
 and adjoint in FP32 (~1e-7 relative per step, random-walking over T steps)
 and the particle adjoint in FP64 from FP32 inputs; bound 2e-5 relative to the
-largest entry of each gradient.  The spread force of several beads meets at
-shared nodes through FP32 atomics, so runs differ in the last bits; the
-checkpoint-interval test compares at 1e-6 relative.
+largest entry of each gradient.  The particle adjoint adds its share of the
+interpolation into the fluid adjoint with FP32 atomics and the bond
+Jacobians meet at shared beads through FP64 atomics, so backward runs differ
+in the last bits; the checkpoint-interval test compares at 1e-6 relative.
 """
 import numpy as np
 import pytest
@@ -34,7 +35,7 @@ def rel_err(got, ref):
     return np.abs(np.asarray(got) - ref).max() / np.abs(ref).max()
 
 
-def system(orc, lat, rng, dims=(12, 10, 8), chains=2, length=4, **kw):
+def system(orc, lat, rng, dims=(12, 10, 8), chains=2, length=4, noise="gaussian", **kw):
     nx, ny, nz = dims
     from paper_0803_2826_amd.inputs import random_walk_chains
     po = orc.Params(nx=nx, ny=ny, nz=nz, **kw)
@@ -44,8 +45,9 @@ def system(orc, lat, rng, dims=(12, 10, 8), chains=2, length=4, **kw):
     mom = rng.normal(scale=0.01, size=mom.shape)
     nb = pos.shape[0]
     zeta = np.where(np.arange(nb) % 2 == 0, 0.5, 2.0)
-    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta, bonds.copy(), 0.05, 1.0)
-    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 0.05, 1.0)
+    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta, bonds.copy(), 0.05, 1.0,
+                   three_point=(noise == "three_point"))
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 0.05, 1.0, noise=noise)
     n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, nz, ny, nx)))
     return po, pd, n0, ob, db
 
@@ -67,10 +69,13 @@ def run_gpu(lat, pd, n0, db, T, K, w, a, b, plain_steps=()):
     return n0r, out
 
 
-def test_gpu_coupled_adjoint_matches_oracle(orc, lat):
+@pytest.mark.parametrize("noise", ["gaussian", "three_point"])
+def test_gpu_coupled_adjoint_matches_oracle(orc, lat, noise):
+    """Eight coupled steps, checkpoints every 3: the recompute sweep replays
+    the bead noise of either distribution from its Philox counters."""
     rng = np.random.default_rng(0)
     po, pd, n0, ob, db = system(orc, lat, rng, kT=1e-4, seed=5, g=(1e-4, -5e-5, 2e-5), gamma_shear=0.2,
-                                gamma_bulk=-0.1)
+                                gamma_bulk=-0.1, noise=noise)
     T, K = 8, 3
     w = rng.normal(size=n0.shape)
     a, b = rng.normal(size=(ob.pos.shape[0], 3)), rng.normal(size=(ob.pos.shape[0], 3))
@@ -225,6 +230,55 @@ def test_autograd_probe_drag_loss_matches_oracle(orc, lat):
             rel_err(R0.grad.cpu().numpy(), dR0), rel_err(P0.grad.cpu().numpy(), dP0)]
     print("probe+drag loss gradient rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
     assert max(errs) <= 1e-4
+
+
+def test_autograd_keeps_bead_kind(orc, lat):
+    """coupled_rollout with Kremer-Grest beads (FENE bonds, WCA pairs) and
+    three-point bead noise: the autograd Function must run the same bead
+    model as the descriptor it is given, forward and backward, against the
+    oracle's forward and FP64 adjoint for a linear loss."""
+    import torch
+    from paper_0803_2826_amd.autograd import coupled_rollout
+    from paper_0803_2826_amd.inputs import kremer_grest_chains
+    rng = np.random.default_rng(21)
+    L, eps = 10, 1e-3
+    po = orc.Params(nx=L, ny=L, nz=L, kT=1e-4, seed=8, g=(1e-4, 0.0, -5e-5))
+    pd = lat.FluidParams(nx=L, ny=L, nz=L, kT=po.kT, seed=po.seed, body_force=po.g, track_totals=False)
+    pos, _, bonds = kremer_grest_chains(4, 8, (L, L, L), seed=5)
+    nb = pos.shape[0]
+    mom = rng.normal(scale=0.01, size=(nb, 3))
+    zeta = np.full(nb, 0.5)
+    ob = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), zeta, bonds.copy(), 30 * eps, 1.5, fene=True, wca_eps=eps,
+                   wca_sigma=1.0, three_point=True)
+    db = lat.DeviceBeads(pos, mom, np.ones(nb), zeta, bonds, 30 * eps, 1.5, bond="fene", wca_epsilon=eps,
+                         wca_sigma=1.0, noise="three_point")
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, L, L, L)))
+    T = 6
+    n0_t = torch.tensor(n0, device="cuda", requires_grad=True)
+    g_t = torch.tensor(po.g, dtype=torch.float64, device="cuda", requires_grad=True)
+    R0 = torch.tensor(ob.pos, device="cuda", requires_grad=True)
+    P0 = torch.tensor(ob.mom, device="cuda", requires_grad=True)
+    nT, RT, PT = coupled_rollout(n0_t, g_t, R0, P0, db, pd, T, checkpoint_every=4)
+    w = rng.normal(size=n0.shape)
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+    loss = (nT * torch.from_numpy(w).cuda()).sum() + (RT * torch.from_numpy(a).cuda()).sum() + \
+        (PT * torch.from_numpy(b).cuda()).sum()
+    loss.backward()
+    probe = lat.Lattice(pd)  # the state the device starts from (FP32 shifted storage of n0)
+    probe.set_populations(torch.from_numpy(n0))
+    n0r = probe.get_populations().cpu().numpy()
+    probe.close()
+    n, bb = n0r.copy(), ob.copy()
+    for t in range(T):
+        orc.coupled_step(po, n, t, bb)
+    assert np.abs(nT.detach().cpu().numpy() - n).max() <= 1e-6
+    np.testing.assert_allclose(RT.detach().cpu().numpy(), bb.pos, atol=1e-7)
+    np.testing.assert_allclose(PT.detach().cpu().numpy(), bb.mom, atol=1e-7)
+    lam0, gbar, dR0, dP0 = orc.backward_coupled(po, n0r, T, ob, w, a, b)
+    errs = [rel_err(n0_t.grad.cpu().numpy(), lam0), rel_err(g_t.grad.cpu().numpy(), gbar),
+            rel_err(R0.grad.cpu().numpy(), dR0), rel_err(P0.grad.cpu().numpy(), dP0)]
+    print("KG autograd rel errors (n0, g, R0, P0):", ["%.2e" % e for e in errs])
+    assert max(errs) <= REL_TOL
 
 
 def test_coupled_backward_error_paths(orc, lat):

@@ -1,6 +1,7 @@
 """GPU parity of the point-particle coupling against the FP64 oracle, through
-the C ABI.  Tolerances: bead positions/momenta 1e-7 absolute (FP32
-populations interpolated; FP32 atomic spreading in arbitrary order);
+the C ABI.  Tolerances: bead positions/momenta 1e-7 absolute (velocities
+interpolated from FP32 populations; the spread force summed in fixed point
+with 2^-44 resolution and rounded to FP32 where the step reads it);
 populations 1e-6 as for the fluid path."""
 import numpy as np
 import pytest
@@ -18,7 +19,8 @@ def lat():
     return lattice
 
 
-def chains_setup(orc, lat, L, n_chains, length, kT, seed, g=(0.0, 0.0, 0.0), zeta=20.0, k=1.0, p0=0.0):
+def chains_setup(orc, lat, L, n_chains, length, kT, seed, g=(0.0, 0.0, 0.0), zeta=20.0, k=1.0, p0=0.0,
+                 noise="gaussian"):
     """Bead-spring chains.  k = 1 is the stiffest bond (lattice units) for which
     the explicit coupled scheme is stable at zeta = 20, m = 1, h = 1."""
     from paper_0803_2826_amd.inputs import random_walk_chains
@@ -28,16 +30,20 @@ def chains_setup(orc, lat, L, n_chains, length, kT, seed, g=(0.0, 0.0, 0.0), zet
     nb = pos.shape[0]
     po = orc.Params(nx=L, ny=L, nz=L, kT=kT, seed=seed, g=g)
     pd = lat.FluidParams(nx=L, ny=L, nz=L, kT=kT, seed=seed, body_force=g)
-    bo = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), np.full(nb, zeta), bonds.copy(), k, 1.0)
-    bd = lat.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, zeta), bonds, k, 1.0)
+    bo = orc.Beads(pos.copy(), mom.copy(), np.ones(nb), np.full(nb, zeta), bonds.copy(), k, 1.0,
+                   three_point=(noise == "three_point"))
+    bd = lat.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, zeta), bonds, k, 1.0, noise=noise)
     return po, pd, bo, bd
 
 
-@pytest.mark.parametrize("kT", [0.0, 1e-4])
-def test_coupled_parity(orc, lat, kT):
+@pytest.mark.parametrize("kT,noise", [(0.0, "gaussian"), (1e-4, "gaussian"), (1e-4, "three_point")])
+def test_coupled_parity(orc, lat, kT, noise):
+    """Twenty coupled steps of 4 chains x 8 beads in a 16^3 box, with either
+    bead noise (the three-point variates of Sec. "Force coupling" come from
+    the same Philox words on both sides, so the noise is identical)."""
     import torch
     L = 16
-    po, pd, bo, bd = chains_setup(orc, lat, L, 4, 8, kT, seed=7, g=(1e-5, 0, 0), p0=0.01)
+    po, pd, bo, bd = chains_setup(orc, lat, L, 4, 8, kT, seed=7, g=(1e-5, 0, 0), p0=0.01, noise=noise)
     n = orc.init_equilibrium(po)
     dev = lat.Lattice(pd)
     dev.set_populations(torch.from_numpy(n))

@@ -49,6 +49,12 @@ def test_bead_descriptor_fields():
         DeviceBeads(pos, np.zeros((3, 3)), np.ones(2), np.ones(2), device="cpu")
     with pytest.raises(ValueError):
         DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), device="cpu", bond="morse")
+    assert DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), device="cpu").to_c().noise == \
+        _lib.LB_NOISE_GAUSSIAN
+    assert DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), device="cpu",
+                       noise="three_point").to_c().noise == _lib.LB_NOISE_THREE_POINT
+    with pytest.raises(ValueError):
+        DeviceBeads(pos, np.zeros((2, 3)), np.ones(2), np.ones(2), device="cpu", noise="uniform")
 
 
 def test_random_walk_chains():
