@@ -33,9 +33,11 @@ struct AdjArgs {
     uint32_t step;
     double *partials;       // [gridDim][3] block sums of Fbar, accumulated over the steps of a sweep
     // bead force of the step (FORCE variant): F = g + force at sites whose
-    // bit is set in fmask; the adjoint of that force is written to fbar there
-    const long long *force; // [3][N] fixed point (kForceScale)
-    const uint32_t *fmask;  // [ceil(N/32)]
+    // bit is set in fmask; the adjoint of that force is written to fbar
+    // there, and the force rows and bitmap words read are left zero (each
+    // coupled step of the sweep puts its own force back first)
+    long long *force;       // [3][N] fixed point (kForceScale)
+    uint32_t *fmask;        // [ceil(N/32)]
     float *fbar;            // [3][N]
 };
 
@@ -68,12 +70,19 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         bool flagged = false;
         if (FORCE) {
-            flagged = (a.fmask[s >> 5] >> (s & 31u)) & 1u;
+            const uint32_t word = a.fmask[s >> 5];
+            flagged = (word >> (s & 31u)) & 1u;
             if (flagged) {
                 F[0] += force_value(a.force[s]);
                 F[1] += force_value(a.force[(size_t)N + s]);
                 F[2] += force_value(a.force[2 * (size_t)N + s]);
+                a.force[s] = 0;
+                a.force[(size_t)N + s] = 0;
+                a.force[2 * (size_t)N + s] = 0;
             }
+            // one site per block of 64 consecutive sites (one wave) clears a
+            // bitmap word once the wave has loaded it
+            if ((s & 31u) == 0u && word != 0u) a.fmask[s >> 5] = 0u;
         }
         const float rho = a.cc.rho0 + m0;
         const float inv_rho = 1.0f / rho;

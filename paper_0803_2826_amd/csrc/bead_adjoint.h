@@ -176,11 +176,19 @@ __global__ void k_bonds_adjoint(const double *__restrict__ half, const double *_
     }
 }
 
-// R' = R + (h/2) P/m:  Rbar = R'bar,  Pbar = pbar + (h/2m) R'bar.
+// R' = R + (h/2) P/m:  Rbar = R'bar,  Pbar = pbar + (h/2m) R'bar.  Threads
+// below the touched count also zero the spread force's adjoint at the
+// touched nodes (every bead has read it by now), leaving fbar zero for the
+// next coupled step of the sweep.
 __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, const double *__restrict__ half_bar,
-                                      const double *__restrict__ p_bar, double *pos_bar, double *mom_bar)
+                                      const double *__restrict__ p_bar, double *pos_bar, double *mom_bar, float *fbar,
+                                      const int32_t *list, const int32_t *count, int cap, uint32_t N)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < cap && b < *count) {
+        const uint32_t s = (uint32_t)list[b];
+        for (int c = 0; c < 3; ++c) fbar[(size_t)c * N + s] = 0.f;
+    }
     if (b >= n) return;
     const double hm = 0.5 / mass[b];
     for (int c = 0; c < 3; ++c) {
@@ -218,20 +226,6 @@ __global__ void k_restore_touched(const int32_t *slist, const int32_t *scount, c
     for (int c = 0; c < 3; ++c) force[(size_t)c * N + s] = svals[3 * idx + c];
     atomicOr(&fmask[s >> 5], 1u << (s & 31u));
     list[idx] = (int32_t)s;
-}
-
-// Zero the force, its adjoint and the bitmap word of every touched node.
-__global__ void k_clear_touched_adj(long long *force, float *fbar, uint32_t *fmask, const int32_t *list,
-                                    const int32_t *count, int cap, uint32_t N)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cap || idx >= *count) return;
-    const uint32_t s = (uint32_t)list[idx];
-    for (int c = 0; c < 3; ++c) {
-        force[(size_t)c * N + s] = 0;
-        fbar[(size_t)c * N + s] = 0.f;
-    }
-    fmask[s >> 5] = 0u;
 }
 
 }  // namespace lbmi

@@ -7,7 +7,8 @@
 //                   (FP64 atomics into a zeroed accumulator: a bead with at
 //                   most two bonds gets the same bits on every run); zero the
 //                   other accumulator for the next call; reset the
-//                   touched-node count
+//                   touched-node count; when taping, copy the starting
+//                   state (R, P) to its tape slot
 //   k_cell_* k_wca  WCA pair forces at R' with a cell list (pairs.h), when on
 //   k_bead_update   one lane per stencil node (W^3 of them, W = 2, 3, 4 for the
 //                   kernels phi_2, phi_3, phi_4 of eq. 2point, eq. 3point,
@@ -63,6 +64,7 @@ struct CoupleArgs {
     int32_t *flags;       // bit 1: a FENE bond at r >= r0
     long long *force;     // [3][N] sparse force field, fixed point (zero outside touched nodes)
     uint32_t *fmask;      // [ceil(N/32)] force bitmap
+    double *snap;         // [2][n][3] or NULL: receives pos_in, mom_in (a taped step's starting state)
     int32_t *list;        // [W^3 n] touched nodes, or NULL (no list kept)
     int32_t *count;       // number of entries in list
 };
@@ -115,8 +117,14 @@ __global__ void k_bead_half(CoupleArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0 && a.list) *a.count = 0;
-    if (t < a.n)
+    if (t < a.n) {
         for (int c = 0; c < 3; ++c) a.half[3 * t + c] = half_coord(a, t, c);
+        if (a.snap)
+            for (int c = 0; c < 3; ++c) {
+                a.snap[3 * t + c] = a.pos_in[3 * t + c];
+                a.snap[3 * ((size_t)a.n + t) + c] = a.mom_in[3 * t + c];
+            }
+    }
     if (t < a.cap)
         for (int c = 0; c < 3; ++c) a.fb_next[3 * t + c] = 0.0;
     if (t < a.nbonds) bond_force(a, t);

@@ -507,7 +507,7 @@ constexpr int kBeadBlock = 64;
 // (pos, mom) (the same arrays for lb_couple), spreading into the force field,
 // its bitmap and the touched-node list, with R' in c->half and F^c in c->fc.
 void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *pos_in, const double *mom_in,
-                   double *pos, double *mom, uint32_t step, bool with_list)
+                   double *pos, double *mom, uint32_t step, bool with_list, double *snap = nullptr)
 {
     CoupleArgs a;
     a.pop = pop;
@@ -548,6 +548,7 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     // the touched-node list is only read by the backward sweep (the step
     // finds the touched nodes in the bitmap and clears them itself)
     a.list = with_list ? c->list : nullptr;
+    a.snap = snap;
     a.count = c->count;
     const size_t roles = std::max<size_t>({(size_t)b->n, (size_t)b->nbonds, (size_t)c->bead_cap});
     hipLaunchKernelGGL(k_bead_half, dim3(grid_for(roles, 256)), dim3(256), 0, c->stream, a);
@@ -564,7 +565,9 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
 }
 
 // Snapshot of the bead state at the start of a taped coupled step.
-int tape_bead_snapshot(lb_ctx *c, const lb_beads *b)
+// Reserves the tape slot of a coupled step's starting bead state; the
+// particle half's first kernel fills it (*dst).
+int tape_bead_snapshot(lb_ctx *c, const lb_beads *b, double **dst)
 {
     if (c->tape_nb == 0) c->tape_nb = b->n;
     if (b->n != c->tape_nb)
@@ -586,11 +589,7 @@ int tape_bead_snapshot(lb_ctx *c, const lb_beads *b)
         c->snap = p;
         c->snap_cap = cap;
     }
-    double *dst = c->snap + slot * slot_doubles;
-    LB_TRY(check(c, hipMemcpyAsync(dst, b->pos, 3 * (size_t)b->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
-                 "bead snapshot"));
-    LB_TRY(check(c, hipMemcpyAsync(dst + 3 * (size_t)b->n, b->mom, 3 * (size_t)b->n * sizeof(double),
-                                   hipMemcpyDeviceToDevice, c->stream), "bead snapshot"));
+    *dst = c->snap + slot * slot_doubles;
     c->tape_beads.push_back(*b);
     c->pending_slot = (int)slot;
     return LB_OK;
@@ -1190,8 +1189,9 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
         LB_TRY(ensure_pair_buffers(c, b->n, (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2]));
     }
     c->pending_slot = -1;
-    if (c->taping) LB_TRY(tape_bead_snapshot(c, b));
-    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step, false);
+    double *snap = nullptr;
+    if (c->taping) LB_TRY(tape_bead_snapshot(c, b, &snap));
+    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step, false, snap);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
     const int W = (b->stencil == 3 || b->stencil == 4) ? b->stencil : 2;
@@ -1463,10 +1463,6 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         const double *snap = c->snap + (size_t)slot * 2 * n3;
         launch_couple(c, pop, &c->tape_beads[slot], snap, snap + n3, pos_w, mom_w, step, true);
     };
-    auto clear_force = [&]() {
-        hipLaunchKernelGGL(k_clear_touched_adj, dim3(grid_for(64 * (size_t)nbd, 256)), dim3(256), 0, c->stream,
-                           c->force, c->fbar, c->fmask, c->list, c->count, 64 * nbd, c->geo.N);
-    };
     // saved step k of the segment: R' [n3], F^c [n3], P'' [n3] (FP64), then
     // the touched count (64 int32 slots), nodes and fixed-point force values
     struct Saved {
@@ -1607,9 +1603,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                                        ba.half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd,
                                        (int)(bc.bond == LB_BOND_FENE));
                 if (bc.wca_epsilon > 0.0) launch_wca_adjoint(c, &bc, ba.half, fc_bar, half_bar);
-                hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for((size_t)nbd, 256)), dim3(256), 0, c->stream,
-                                   nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar);
-                clear_force();
+                // (the adjoint step consumed the force and its bitmap; the
+                // finishing kernel clears fbar at the touched nodes)
+                hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for(64 * (size_t)nbd, 256)), dim3(256), 0,
+                                   c->stream, nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar, c->fbar, c->list,
+                                   c->count, 64 * nbd, c->geo.N);
             }
             std::swap(c->lamA, c->lamB);
         }
