@@ -16,7 +16,7 @@
 // nodes and w_q ubar_b / (2 rho_q) to gbar.  The stencil weights are
 // differentiated with the kernels' derivatives (phi_2 where R' is off the
 // node planes).  The bead noise is not needed: P'' is taken from the
-// recomputed forward update; the external bead force is constant.
+// forward update's tape; the external bead force is constant.
 #pragma once
 
 #include "couple.h"
@@ -30,7 +30,7 @@ struct BeadAdjArgs {
     double g[3];
     int32_t n;
     const double *mom0;     // P at the start of the step [n][3]
-    const double *mom1;     // P'' of the recomputed forward update [n][3]
+    const double *mom1;     // P'' of the forward update [n][3]
     const double *mass;
     const double *zeta;
     const double *half;     // R' [n][3]
@@ -177,17 +177,18 @@ __global__ void k_bonds_adjoint(const double *__restrict__ half, const double *_
 }
 
 // R' = R + (h/2) P/m:  Rbar = R'bar,  Pbar = pbar + (h/2m) R'bar.  Threads
-// below the touched count also zero the spread force's adjoint at the
-// touched nodes (every bead has read it by now), leaving fbar zero for the
-// next coupled step of the sweep.
+// below the number of tape entries also zero the spread force's adjoint at
+// the nodes of the step's contributions (every bead has read it by now),
+// leaving fbar zero for the next coupled step of the sweep.
 __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, const double *__restrict__ half_bar,
                                       const double *__restrict__ p_bar, double *pos_bar, double *mom_bar, float *fbar,
-                                      const int32_t *list, const int32_t *count, int cap, uint32_t N)
+                                      const long long *contrib, int entries, uint32_t N)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < cap && b < *count) {
-        const uint32_t s = (uint32_t)list[b];
-        for (int c = 0; c < 3; ++c) fbar[(size_t)c * N + s] = 0.f;
+    if (b < entries) {
+        const long long node = contrib[4 * (size_t)b];
+        if (node >= 0)
+            for (int c = 0; c < 3; ++c) fbar[(size_t)c * N + (size_t)node] = 0.f;
     }
     if (b >= n) return;
     const double hm = 0.5 / mass[b];
@@ -197,35 +198,23 @@ __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, co
     }
 }
 
-// Recompute sweep of a segment: keep the spread force of a coupled step
-// compactly (its touched nodes and their force values) before the step
-// consumes it, so that the adjoint sweep can restore it without running the
-// particle half again.
-__global__ void k_save_touched(const long long *force, const int32_t *list, const int32_t *count, int cap,
-                               uint32_t N, int32_t *slist, int32_t *scount, long long *svals)
+// Backward sweeps: put a taped coupled step's spread force back from the
+// contributions k_bead_update recorded (one entry per bead and lane).  The
+// sums are integer, so the field gets the forward's bits in any order; the
+// bitmap bits are set as the forward set them.
+__global__ void k_respread(const long long *__restrict__ contrib, int entries, uint32_t N, long long *force,
+                           uint32_t *fmask)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int cnt = min(*count, cap);
-    if (idx == 0) *scount = cnt;
-    if (idx >= cnt) return;
-    const uint32_t s = (uint32_t)list[idx];
-    slist[idx] = (int32_t)s;
-    for (int c = 0; c < 3; ++c) svals[3 * idx + c] = force[(size_t)c * N + s];
-}
-
-// Adjoint sweep: put a saved spread force back (values, bitmap bits, the
-// touched-node list and its count).  The force field is zero on entry.
-__global__ void k_restore_touched(const int32_t *slist, const int32_t *scount, const long long *svals, int cap,
-                                  uint32_t N, long long *force, uint32_t *fmask, int32_t *list, int32_t *count)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int cnt = min(*scount, cap);
-    if (idx == 0) *count = cnt;
-    if (idx >= cnt) return;
-    const uint32_t s = (uint32_t)slist[idx];
-    for (int c = 0; c < 3; ++c) force[(size_t)c * N + s] = svals[3 * idx + c];
-    atomicOr(&fmask[s >> 5], 1u << (s & 31u));
-    list[idx] = (int32_t)s;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= entries) return;
+    const long long *p = contrib + 4 * (size_t)e;
+    const long long node = p[0];
+    if (node < 0) return;
+    for (int c = 0; c < 3; ++c)
+        if (p[1 + c] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&force[(size_t)c * N + (size_t)node]),
+                      (unsigned long long)p[1 + c]);
+    atomicOr(&fmask[(uint32_t)node >> 5], 1u << ((uint32_t)node & 31u));
 }
 
 }  // namespace lbmi

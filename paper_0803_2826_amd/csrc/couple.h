@@ -6,9 +6,8 @@
 //   k_bead_half     R' = R + (h/2) P/m; harmonic or FENE bond forces at R'
 //                   (FP64 atomics into a zeroed accumulator: a bead with at
 //                   most two bonds gets the same bits on every run); zero the
-//                   other accumulator for the next call; reset the
-//                   touched-node count; when taping, copy the starting
-//                   state (R, P) to its tape slot
+//                   other accumulator for the next call; when taping,
+//                   copy the starting momenta P to the step's tape slot
 //   k_cell_* k_wca  WCA pair forces at R' with a cell list (pairs.h), when on
 //   k_bead_update   one lane per stencil node (W^3 of them, W = 2, 3, 4 for the
 //                   kernels phi_2, phi_3, phi_4 of eq. 2point, eq. 3point,
@@ -22,9 +21,9 @@
 //                   (eq. ftotal; fixed-point integer atomics, so the sum
 //                   does not depend on the order; a non-finite or absurdly
 //                   large contribution is refused and latched as bit 2 of the
-//                   device flags), setting the node's bit in the force bitmap
-//                   (and, for the backward sweep, listing the nodes it is the
-//                   first to flag); R = R' + (h/2) P''/m
+//                   device flags), setting the node's bit in the force bitmap;
+//                   R = R' + (h/2) P''/m; when taping, P'' and each lane's
+//                   fixed-point contribution go to the step's tape slot
 //   (next lb_step)  the fused stream-collide kernel adds the bead force at
 //                   flagged sites and leaves those force rows and bitmap
 //                   words zero.
@@ -64,9 +63,13 @@ struct CoupleArgs {
     int32_t *flags;       // bit 1: a FENE bond at r >= r0
     long long *force;     // [3][N] sparse force field, fixed point (zero outside touched nodes)
     uint32_t *fmask;      // [ceil(N/32)] force bitmap
-    double *snap;         // [2][n][3] or NULL: receives pos_in, mom_in (a taped step's starting state)
-    int32_t *list;        // [W^3 n] touched nodes, or NULL (no list kept)
-    int32_t *count;       // number of entries in list
+    // tape of a coupled step (all NULL when not taping): P at the start
+    // [n][3], P'' [n][3] and the spread contributions, one entry of four
+    // int64 per (bead, lane): node (or -1: nothing spread) and the three
+    // fixed-point values added there
+    double *tape_mom0;
+    double *tape_momn;
+    long long *tape_contrib;
 };
 
 // R' = R + (h/2) P/m of bead b, component c (one expression wherever R' is
@@ -111,19 +114,14 @@ __device__ __forceinline__ void bond_force(const CoupleArgs &a, int q)
 // One thread per bead, per bond and per entry of the idle bond accumulator
 // (grid of max(n, nbonds, cap) threads): R' of the bead, the bond's forces
 // (each bond forms R' of its two beads itself, so nothing waits for the
-// first role), zero the accumulator of the next call, reset the touched-node
-// count.
+// first role), zero the accumulator of the next call, copy P to the tape.
 __global__ void k_bead_half(CoupleArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0 && a.list) *a.count = 0;
     if (t < a.n) {
         for (int c = 0; c < 3; ++c) a.half[3 * t + c] = half_coord(a, t, c);
-        if (a.snap)
-            for (int c = 0; c < 3; ++c) {
-                a.snap[3 * t + c] = a.pos_in[3 * t + c];
-                a.snap[3 * ((size_t)a.n + t) + c] = a.mom_in[3 * t + c];
-            }
+        if (a.tape_mom0)
+            for (int c = 0; c < 3; ++c) a.tape_mom0[3 * t + c] = a.mom_in[3 * t + c];
     }
     if (t < a.cap)
         for (int c = 0; c < 3; ++c) a.fb_next[3 * t + c] = 0.0;
@@ -276,38 +274,33 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
         Pn[c] = C1 * P + C2 * (Fc[c] + z * ub[c]) + C3 * th[c];
         I[c] = -(Pn[c] - P - h * Fc[c]);
     }
-    bool first = false;  // this lane set its node's bit: the node joins the touched list
+    long long iv[3] = {0, 0, 0};
     if (wq != 0.0) {
         for (int c = 0; c < 3; ++c) {
             const double v = wq * I[c] / h;
-            if (fabs(v) < kForceLimit)  // false for NaN too
+            if (fabs(v) < kForceLimit) {  // false for NaN too
+                iv[c] = __double2ll_rn(v * kForceScale);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&a.force[(size_t)c * g.N + node]),
-                          (unsigned long long)__double2ll_rn(v * kForceScale));
-            else
+                          (unsigned long long)iv[c]);
+            } else {
                 __hip_atomic_fetch_or(a.flags, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
-        const uint32_t bit = 1u << (node & 31u);
-        if (a.list)
-            first = (atomicOr(&a.fmask[node >> 5], bit) & bit) == 0u;
-        else
-            atomicOr(&a.fmask[node >> 5], bit);  // no list: the old bits are not needed
+        atomicOr(&a.fmask[node >> 5], 1u << (node & 31u));
     }
-    // list slots for the whole wave with one atomic on the shared count (the
-    // lanes still running here are exactly the live ones)
-    const uint64_t newcomers = a.list ? __ballot(first) : 0ull;
-    if (newcomers) {
-        const int lane = (int)__lane_id();
-        const int leader = __ffsll((unsigned long long)newcomers) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(a.count, (int)__popcll(newcomers));
-        base = __shfl(base, leader, 64);
-        if (first) a.list[base + (int)__popcll(newcomers & ((1ull << lane) - 1ull))] = (int32_t)node;
+    if (a.tape_contrib) {
+        long long *e = a.tape_contrib + 4 * ((size_t)b * LANES + q);
+        e[0] = wq != 0.0 ? (long long)node : -1ll;
+        e[1] = iv[0];
+        e[2] = iv[1];
+        e[3] = iv[2];
     }
     if (q == 0)
         for (int c = 0; c < 3; ++c) {
             a.mom[3 * b + c] = Pn[c];
             a.pos[3 * b + c] = a.half[3 * b + c] + 0.5 * h * Pn[c] / m;
             a.fc[3 * b + c] = Fc[c];
+            if (a.tape_momn) a.tape_momn[3 * b + c] = Pn[c];
         }
 }
 

@@ -52,9 +52,6 @@ struct lb_ctx {
     // bead coupling (allocated on first lb_couple)
     long long *force = nullptr;      // [3][N] fixed point (kForceScale)
     uint32_t *fmask = nullptr;       // [ceil(N/32)] bit per site: bead force present
-    int32_t *list = nullptr;         // touched nodes of the pending force
-    int32_t *count = nullptr;
-    int list_cap = 0;
     double *half = nullptr;
     double *fc = nullptr;
     double *fb2 = nullptr;           // [2][cap][3] bond-force accumulators, used by alternate calls
@@ -62,7 +59,6 @@ struct lb_ctx {
     int fb_par = 0;                  // accumulator of the next call
     int bead_cap = 0;
     bool pending_force = false;
-    int pending_rows = 0;            // upper bound of touched nodes (8 per bead)
     // WCA cell list (allocated on the first lb_couple with wca_epsilon > 0)
     int32_t *cell_count = nullptr;   // [ncell + 1] counts, then (cell_start) their exclusive scan
     int32_t *cell_start = nullptr;   // [ncell + 1]
@@ -106,22 +102,22 @@ struct lb_ctx {
     std::vector<void *> checkpoints;  // A-buffer copies at tape_step0 + s * tape_k
     void *seg = nullptr;              // tape_k step buffers of one segment
     size_t seg_bytes = 0;
-    void *seg_bead = nullptr;         // per step of a segment: R', F^c, P'' and the compact spread force
-    size_t seg_bead_bytes = 0;
     float *lamA = nullptr, *lamB = nullptr;
     double *gbar_d = nullptr;
     double *adj_partials = nullptr;
-    // bead state of the taped coupled steps: slot per taped step (-1: no
-    // bead force), the bead configuration and a snapshot of (R, P) at the
-    // start of each coupled step, [slot][2][n][3] FP64
+    // particle halves of the taped coupled steps: slot per taped step (-1:
+    // no bead force), the bead configuration of each slot and its record in
+    // tape_bead at byte offset tape_off[slot] (TapeSlot)
     std::vector<int32_t> tape_slot;
     std::vector<lb_beads> tape_beads;
+    std::vector<size_t> tape_off;
     int pending_slot = -1;
     int tape_nb = 0;
-    double *snap = nullptr;
-    size_t snap_cap = 0;              // slots allocated
+    char *tape_bead = nullptr;
+    size_t tape_bead_bytes = 0;       // allocated
+    size_t tape_bead_used = 0;
     // backward scratch of the particle adjoint
-    double *bead_work = nullptr;      // [7][n][3]: pos_w, mom_w, half_bar, fc_bar, p_bar, pos_bar, mom_bar
+    double *bead_work = nullptr;      // [5][n][3]: half_bar, fc_bar, p_bar, pos_bar, mom_bar
     int bead_work_n = 0;
     float *fbar = nullptr;            // [3][N] adjoint of the spread force (zero outside touched nodes)
     std::string err;
@@ -328,8 +324,7 @@ int ensure_bead_buffers(lb_ctx *c, int n)
     const size_t nwords = (N + 31) / 32;
     if (!c->force) {
         if (hipMalloc(&c->force, 3 * N * sizeof(long long)) != hipSuccess ||
-            hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&c->count, sizeof(int32_t)) != hipSuccess)
+            hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead force field allocation failed");
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->force),
                            6 * N);
@@ -340,18 +335,15 @@ int ensure_bead_buffers(lb_ctx *c, int n)
     if (n > c->bead_cap) {
         (void)hipFree(c->half);
         (void)hipFree(c->fc);
-        (void)hipFree(c->list);
         (void)hipFree(c->fb2);
         (void)hipFree(c->fp);
         c->half = c->fc = c->fb2 = c->fp = nullptr;
-        c->list = nullptr;
         c->bead_cap = 0;
         const int cap = n < 64 ? 64 : n;
         if (hipMalloc(&c->half, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->fc, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->fb2, 6 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fp, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->list, 64 * (size_t)cap * sizeof(int32_t)) != hipSuccess)
+            hipMalloc(&c->fp, 3 * (size_t)cap * sizeof(double)) != hipSuccess)
             return fail(c, LB_ENOMEM, "bead scratch allocation failed");
         // both bond accumulators start at zero; each call zeroes the other one
         hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(12 * (size_t)cap, 256)), dim3(256), 0, c->stream,
@@ -359,7 +351,6 @@ int ensure_bead_buffers(lb_ctx *c, int n)
         LB_LAUNCH_CHECK(c, "zero bond accumulators");
         c->fb_par = 0;
         c->bead_cap = cap;
-        c->list_cap = 64 * cap;
     }
     return LB_OK;
 }
@@ -387,6 +378,8 @@ void free_tape(lb_ctx *c)
     c->taping = false;
     c->tape_slot.clear();
     c->tape_beads.clear();
+    c->tape_off.clear();
+    c->tape_bead_used = 0;
     c->pending_slot = -1;
     c->tape_nb = 0;
 }
@@ -483,10 +476,10 @@ CellGrid build_cells(lb_ctx *c, const lb_beads *b, const double *half)
     return cg;
 }
 
-void launch_wca(lb_ctx *c, const lb_beads *b)
+void launch_wca(lb_ctx *c, const lb_beads *b, const double *half)
 {
-    const CellGrid cg = build_cells(c, b, c->half);
-    hipLaunchKernelGGL(k_wca, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, c->half, b->n,
+    const CellGrid cg = build_cells(c, b, half);
+    hipLaunchKernelGGL(k_wca, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, half, b->n,
                        cg, c->bead_cell, c->cell_start, c->cell_pos, c->fp);
 }
 
@@ -502,12 +495,46 @@ void launch_wca_adjoint(lb_ctx *c, const lb_beads *b, const double *half, const 
 // thousand beads spread over many CUs (the kernels are latency-bound).
 constexpr int kBeadBlock = 64;
 
+// Record of one taped coupled step in the bead tape: P at the start, R',
+// F^c and P'' ([n][3] FP64 each), then the spread contributions, one entry
+// of four int64 (node or -1, three fixed-point values) per bead and
+// stencil lane.
+struct TapeSlot {
+    double *mom0, *half, *fc, *momn;
+    long long *contrib;
+    int entries;
+};
+
+int stencil_width(const lb_beads *b) { return (b->stencil == 3 || b->stencil == 4) ? b->stencil : 2; }
+
+int stencil_lanes(int W) { return W == 4 ? StencilLanes<4>::value : W == 3 ? StencilLanes<3>::value : StencilLanes<2>::value; }
+
+size_t tape_slot_bytes(const lb_beads *b)
+{
+    return 12 * (size_t)b->n * sizeof(double) + 4 * (size_t)stencil_lanes(stencil_width(b)) * b->n * sizeof(long long);
+}
+
+TapeSlot tape_slot_at(const lb_ctx *c, int slot)
+{
+    const lb_beads &b = c->tape_beads[slot];
+    const size_t n3 = 3 * (size_t)b.n;
+    TapeSlot t;
+    t.mom0 = reinterpret_cast<double *>(c->tape_bead + c->tape_off[slot]);
+    t.half = t.mom0 + n3;
+    t.fc = t.half + n3;
+    t.momn = t.fc + n3;
+    t.contrib = reinterpret_cast<long long *>(t.momn + n3);
+    t.entries = stencil_lanes(stencil_width(&b)) * b.n;
+    return t;
+}
+
 // The particle half of one coupled step (k_bead_half with the bonds, the WCA
 // pair search, k_bead_update) on the populations `pop`: (pos_in, mom_in) ->
-// (pos, mom) (the same arrays for lb_couple), spreading into the force field,
-// its bitmap and the touched-node list, with R' in c->half and F^c in c->fc.
+// (pos, mom) (the same arrays for lb_couple), spreading into the force field
+// and its bitmap, with R' and F^c in c->half, c->fc, or, for a taped step, in
+// its tape slot together with P, P'' and the contributions.
 void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *pos_in, const double *mom_in,
-                   double *pos, double *mom, uint32_t step, bool with_list, double *snap = nullptr)
+                   double *pos, double *mom, uint32_t step, const TapeSlot *tape = nullptr)
 {
     CoupleArgs a;
     a.pop = pop;
@@ -526,8 +553,8 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     a.mom = mom;
     a.mass = b->mass;
     a.zeta = b->zeta;
-    a.half = c->half;
-    a.fc = c->fc;
+    a.half = tape ? tape->half : c->half;
+    a.fc = tape ? tape->fc : c->fc;
     const size_t n3cap = 3 * (size_t)c->bead_cap;
     a.fb = c->fb2 + (size_t)c->fb_par * n3cap;
     a.fb_next = c->fb2 + (size_t)(c->fb_par ^ 1) * n3cap;
@@ -545,14 +572,12 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     a.flags = c->flags;
     a.force = c->force;
     a.fmask = c->fmask;
-    // the touched-node list is only read by the backward sweep (the step
-    // finds the touched nodes in the bitmap and clears them itself)
-    a.list = with_list ? c->list : nullptr;
-    a.snap = snap;
-    a.count = c->count;
+    a.tape_mom0 = tape ? tape->mom0 : nullptr;
+    a.tape_momn = tape ? tape->momn : nullptr;
+    a.tape_contrib = tape ? tape->contrib : nullptr;
     const size_t roles = std::max<size_t>({(size_t)b->n, (size_t)b->nbonds, (size_t)c->bead_cap});
     hipLaunchKernelGGL(k_bead_half, dim3(grid_for(roles, 256)), dim3(256), 0, c->stream, a);
-    if (wca) launch_wca(c, b);
+    if (wca) launch_wca(c, b, a.half);
     by_storage(c->p.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         by_stencil(b->stencil, [&](auto w) {
@@ -564,34 +589,33 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     });
 }
 
-// Snapshot of the bead state at the start of a taped coupled step.
-// Reserves the tape slot of a coupled step's starting bead state; the
-// particle half's first kernel fills it (*dst).
-int tape_bead_snapshot(lb_ctx *c, const lb_beads *b, double **dst)
+// Reserves the tape slot of a taped coupled step (the particle half's
+// kernels fill it).
+int tape_reserve(lb_ctx *c, const lb_beads *b, TapeSlot *out)
 {
     if (c->tape_nb == 0) c->tape_nb = b->n;
     if (b->n != c->tape_nb)
         return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
-    const size_t slot_doubles = 6 * (size_t)b->n;
-    const size_t slot = c->tape_beads.size();
-    if (slot + 1 > c->snap_cap) {
-        const size_t cap = std::max<size_t>(16, 2 * c->snap_cap);
-        double *p = nullptr;
-        if (hipMalloc(&p, cap * slot_doubles * sizeof(double)) != hipSuccess)
-            return fail(c, LB_ENOMEM, "bead tape allocation failed");
-        if (c->snap && slot > 0)
-            LB_TRY(check(c, hipMemcpyAsync(p, c->snap, slot * slot_doubles * sizeof(double), hipMemcpyDeviceToDevice,
-                                           c->stream), "bead tape copy"));
-        if (c->snap) {
+    const size_t need = tape_slot_bytes(b);
+    if (c->tape_bead_used + need > c->tape_bead_bytes) {
+        const size_t cap = std::max<size_t>(16 * need, 2 * (c->tape_bead_used + need));
+        char *p = nullptr;
+        if (hipMalloc(&p, cap) != hipSuccess) return fail(c, LB_ENOMEM, "bead tape allocation failed");
+        if (c->tape_bead && c->tape_bead_used > 0)
+            LB_TRY(check(c, hipMemcpyAsync(p, c->tape_bead, c->tape_bead_used, hipMemcpyDeviceToDevice, c->stream),
+                         "bead tape copy"));
+        if (c->tape_bead) {
             LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
-            (void)hipFree(c->snap);
+            (void)hipFree(c->tape_bead);
         }
-        c->snap = p;
-        c->snap_cap = cap;
+        c->tape_bead = p;
+        c->tape_bead_bytes = cap;
     }
-    *dst = c->snap + slot * slot_doubles;
+    c->tape_off.push_back(c->tape_bead_used);
+    c->tape_bead_used += need;
     c->tape_beads.push_back(*b);
-    c->pending_slot = (int)slot;
+    c->pending_slot = (int)c->tape_beads.size() - 1;
+    *out = tape_slot_at(c, c->pending_slot);
     return LB_OK;
 }
 
@@ -1008,7 +1032,7 @@ int lb_destroy(lb_ctx *c)
     use_device(c);
     (void)hipStreamSynchronize(c->stream);
     void *ptrs[] = {c->bufA,       c->bufB,      c->partials,  c->scratch,   c->dev_out,   c->flags,
-                    c->force,      c->fmask,     c->list,      c->count,     c->half,      c->fc,
+                    c->force,      c->fmask,     c->half,      c->fc,
                     c->boxes_d,    c->tile_box,  c->dstep,     c->amp,       c->ring,      c->corr,
                     c->cell_count, c->cell_start, c->bead_cell, c->bead_slot, c->cell_sorted, c->scan_tmp,
                     c->cell_pos,   c->fb2,        c->fp};
@@ -1017,7 +1041,7 @@ int lb_destroy(lb_ctx *c)
     for (int k = 0; k < 2; ++k)
         if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
     free_tape(c);
-    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials, c->snap, c->bead_work, c->fbar, c->seg_bead};
+    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials, c->tape_bead, c->bead_work, c->fbar};
     for (void *q : adj)
         if (q) (void)hipFree(q);
     if (c->batch) {
@@ -1189,13 +1213,11 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
         LB_TRY(ensure_pair_buffers(c, b->n, (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2]));
     }
     c->pending_slot = -1;
-    double *snap = nullptr;
-    if (c->taping) LB_TRY(tape_bead_snapshot(c, b, &snap));
-    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step, false, snap);
+    TapeSlot slot;
+    if (c->taping) LB_TRY(tape_reserve(c, b, &slot));
+    launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step, c->taping ? &slot : nullptr);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
-    const int W = (b->stencil == 3 || b->stencil == 4) ? b->stencil : 2;
-    c->pending_rows = W * W * W * b->n;
     return LB_OK;
 }
 
@@ -1353,14 +1375,15 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
 }
 
 // Reverse sweep over the tape.  Per segment: restore its checkpoint and
-// recompute its step buffers with the forward kernels (the bead force of a
-// coupled step is rebuilt from that step's bead snapshot, with the same
-// noise); then, from the last step of the segment back, the adjoint step:
-// for a coupled step the force is rebuilt once more, the fluid adjoint
-// (FORCE variant) also writes the adjoint of the spread force at the
-// flagged sites, and the particle adjoint (k_bead_adjoint, k_bonds_adjoint,
-// k_bead_adjoint_finish) carries the bead adjoints back and adds the
-// interpolation's share to lambda and gbar.
+// recompute its step buffers with the forward step kernel (a coupled step's
+// bead force is put back from the contributions its particle half recorded,
+// k_respread; the bead kernels do not run again); then, from the last step
+// of the segment back, the adjoint step: for a coupled step the force is put
+// back once more, the fluid adjoint (FORCE variant) also writes the adjoint
+// of the spread force at the flagged sites, and the particle adjoint
+// (k_bead_adjoint, the bond and pair Jacobians, k_bead_adjoint_finish)
+// carries the bead adjoints back from the taped R', F^c, P and P'' and adds
+// the interpolation's share to lambda and gbar.
 static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const double *dR_T, const double *dP_T,
                          void *dL_dn_0, double dL_dg[3], double *dR_0, double *dP_0)
 {
@@ -1390,17 +1413,14 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             hipMalloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double)) != hipSuccess)
             return fail(c, LB_ENOMEM, "adjoint buffers allocation failed");
     }
-    double *pos_w = nullptr, *mom_w = nullptr, *half_bar = nullptr, *fc_bar = nullptr, *p_bar = nullptr;
+    double *half_bar = nullptr, *fc_bar = nullptr, *p_bar = nullptr;
     double *pos_bar = nullptr, *mom_bar = nullptr;
-    int seg_rows = 0;       // touched-node capacity per saved step
-    size_t seg_stride = 0;  // bytes per saved step in seg_bead
-    int seg_vals_offset = 0;  // int32 offset of the saved force values from the saved count
     if (coupled) {
         if (c->bead_work_n < nbd) {
             (void)hipFree(c->bead_work);
             c->bead_work = nullptr;
             c->bead_work_n = 0;
-            if (hipMalloc(&c->bead_work, 21 * (size_t)nbd * sizeof(double)) != hipSuccess)
+            if (hipMalloc(&c->bead_work, 15 * (size_t)nbd * sizeof(double)) != hipSuccess)
                 return fail(c, LB_ENOMEM, "bead adjoint buffers allocation failed");
             c->bead_work_n = nbd;
         }
@@ -1410,23 +1430,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->fbar, 3 * N);
         }
         const size_t n3 = 3 * (size_t)nbd;
-        int wmax = 2;
-        for (const lb_beads &bt : c->tape_beads) wmax = std::max(wmax, (bt.stencil == 3 || bt.stencil == 4) ? bt.stencil : 2);
-        seg_rows = wmax * wmax * wmax * nbd;
-        seg_vals_offset = 64 + ((seg_rows + 1) & ~1);  // int32 units from the count: 8-byte aligned values
-        seg_stride = 3 * n3 * sizeof(double) + (size_t)seg_vals_offset * sizeof(int32_t) +
-                     3 * (size_t)seg_rows * sizeof(long long);
-        if (c->seg_bead_bytes < (size_t)K * seg_stride) {
-            (void)hipFree(c->seg_bead);
-            c->seg_bead = nullptr;
-            c->seg_bead_bytes = 0;
-            if (hipMalloc(&c->seg_bead, (size_t)K * seg_stride) != hipSuccess)
-                return fail(c, LB_ENOMEM, "segment bead buffer allocation failed");
-            c->seg_bead_bytes = (size_t)K * seg_stride;
-        }
-        pos_w = c->bead_work;
-        mom_w = pos_w + n3;
-        half_bar = mom_w + n3;
+        half_bar = c->bead_work;
         fc_bar = half_bar + n3;
         p_bar = fc_bar + n3;
         pos_bar = p_bar + n3;
@@ -1457,32 +1461,12 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                        reinterpret_cast<float *>(c->adj_partials), 6 * (size_t)nb);
     LB_LAUNCH_CHECK(c, "backward set-up");
 
-    // rebuild the bead force of taped step t (slot >= 0) from its snapshot on the populations `pop`
-    auto rebuild_force = [&](int slot, const void *pop, uint32_t step) {
-        const size_t n3 = 3 * (size_t)nbd;
-        const double *snap = c->snap + (size_t)slot * 2 * n3;
-        launch_couple(c, pop, &c->tape_beads[slot], snap, snap + n3, pos_w, mom_w, step, true);
+    // put the spread force of taped coupled step `slot` back into the (zero) field
+    auto respread = [&](int slot) {
+        const TapeSlot ts = tape_slot_at(c, slot);
+        hipLaunchKernelGGL(k_respread, dim3(grid_for((size_t)ts.entries, 256)), dim3(256), 0, c->stream, ts.contrib,
+                           ts.entries, c->geo.N, c->force, c->fmask);
     };
-    // saved step k of the segment: R' [n3], F^c [n3], P'' [n3] (FP64), then
-    // the touched count (64 int32 slots), nodes and fixed-point force values
-    struct Saved {
-        double *half, *fc, *mom;
-        int32_t *count, *list;
-        long long *vals;
-    };
-    auto saved = [&](int k) {
-        char *b = static_cast<char *>(c->seg_bead) + (size_t)k * seg_stride;
-        const size_t n3 = 3 * (size_t)nbd;
-        Saved v;
-        v.half = reinterpret_cast<double *>(b);
-        v.fc = v.half + n3;
-        v.mom = v.fc + n3;
-        v.count = reinterpret_cast<int32_t *>(v.mom + n3);
-        v.list = v.count + 64;
-        v.vals = reinterpret_cast<long long *>(v.count + seg_vals_offset);
-        return v;
-    };
-    double *const ctx_half = c->half, *const ctx_fc = c->fc;
 
     const unsigned saved_blocks = c->nblocks;
     const int saved_block = c->block;
@@ -1502,18 +1486,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             const int slot = c->tape_slot[t0 + k];
             StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb, step);
             if (slot >= 0) {
-                // the particle half writes R', F^c and P'' straight into the saved step
-                const Saved v = saved(k);
-                const size_t n3 = 3 * (size_t)nbd;
-                const double *snap = c->snap + (size_t)slot * 2 * n3;
-                c->half = v.half;
-                c->fc = v.fc;
-                launch_couple(c, seg + (size_t)k * sb, &c->tape_beads[slot], snap, snap + n3, pos_w, v.mom, step,
-                              true);
-                c->half = ctx_half;
-                c->fc = ctx_fc;
-                hipLaunchKernelGGL(k_save_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
-                                   c->force, c->list, c->count, seg_rows, c->geo.N, v.list, v.count, v.vals);
+                respread(slot);
                 a.fmask = c->fmask;
                 a.force = c->force;
                 a.consume = 1u;
@@ -1536,16 +1509,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             aa.force = c->force;
             aa.fmask = c->fmask;
             aa.fbar = c->fbar;
-            // a coupled step recomputed above gets its spread force back from the
-            // saved step; the last step of the segment runs its particle half again
-            const bool have = slot >= 0 && k + 1 < len;
-            if (have) {
-                const Saved v = saved(k);
-                hipLaunchKernelGGL(k_restore_touched, dim3(grid_for((size_t)seg_rows, 256)), dim3(256), 0, c->stream,
-                                   v.list, v.count, v.vals, seg_rows, c->geo.N, c->force, c->fmask, c->list, c->count);
-            } else if (slot >= 0) {
-                rebuild_force(slot, pop, step);
-            }
+            if (slot >= 0) respread(slot);
             by_storage(c->p.storage, [&](auto st) {
                 constexpr int ST = decltype(st)::value;
                 auto go = [&](auto th, auto frc) {
@@ -1567,19 +1531,19 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             });
             if (slot >= 0) {
                 const lb_beads &bc = c->tape_beads[slot];
-                const size_t n3 = 3 * (size_t)nbd;
+                const TapeSlot ts = tape_slot_at(c, slot);
                 BeadAdjArgs ba;
                 ba.pop = pop;
                 ba.geo = c->geo;
                 ba.rho0 = c->p.rho0;
                 for (int q = 0; q < 3; ++q) ba.g[q] = c->p.body_force[q];
                 ba.n = nbd;
-                ba.mom0 = c->snap + (size_t)slot * 2 * n3 + n3;
-                ba.mom1 = have ? saved(k).mom : mom_w;
+                ba.mom0 = ts.mom0;
+                ba.mom1 = ts.momn;
                 ba.mass = bc.mass;
                 ba.zeta = bc.zeta;
-                ba.half = have ? saved(k).half : c->half;
-                ba.fc = have ? saved(k).fc : c->fc;
+                ba.half = ts.half;
+                ba.fc = ts.fc;
                 ba.fbar = c->fbar;
                 ba.pos_bar = pos_bar;
                 ba.mom_bar = mom_bar;
@@ -1604,10 +1568,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                                        (int)(bc.bond == LB_BOND_FENE));
                 if (bc.wca_epsilon > 0.0) launch_wca_adjoint(c, &bc, ba.half, fc_bar, half_bar);
                 // (the adjoint step consumed the force and its bitmap; the
-                // finishing kernel clears fbar at the touched nodes)
-                hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for(64 * (size_t)nbd, 256)), dim3(256), 0,
-                                   c->stream, nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar, c->fbar, c->list,
-                                   c->count, 64 * nbd, c->geo.N);
+                // finishing kernel clears fbar at the step's nodes)
+                hipLaunchKernelGGL(k_bead_adjoint_finish,
+                                   dim3(grid_for(std::max<size_t>((size_t)nbd, (size_t)ts.entries), 256)), dim3(256),
+                                   0, c->stream, nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar, c->fbar, ts.contrib,
+                                   ts.entries, c->geo.N);
             }
             std::swap(c->lamA, c->lamB);
         }
