@@ -258,6 +258,12 @@ __global__ void k_zero_i32(int32_t *p, uint32_t n)
     if (i < n) p[i] = 0;
 }
 
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_zero_f32(float *p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)

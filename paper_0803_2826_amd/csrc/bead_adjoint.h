@@ -180,9 +180,12 @@ __global__ void k_bonds_adjoint(const double *__restrict__ half, const double *_
 // below the number of tape entries also zero the spread force's adjoint at
 // the nodes of the step's contributions (every bead has read it by now),
 // leaving fbar zero for the next coupled step of the sweep.
+// With a WCA cell list (cell_head not NULL) each bead also puts its cell's
+// head back to -1.
 __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, const double *__restrict__ half_bar,
                                       const double *__restrict__ p_bar, double *pos_bar, double *mom_bar, float *fbar,
-                                      const long long *contrib, int entries, uint32_t N)
+                                      const long long *contrib, int entries, uint32_t N, int32_t *cell_head,
+                                      const int32_t *__restrict__ cell_of)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < entries) {
@@ -191,6 +194,7 @@ __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, co
             for (int c = 0; c < 3; ++c) fbar[(size_t)c * N + (size_t)node] = 0.f;
     }
     if (b >= n) return;
+    if (cell_head) cell_head[cell_of[b]] = -1;
     const double hm = 0.5 / mass[b];
     for (int c = 0; c < 3; ++c) {
         pos_bar[3 * b + c] = half_bar[3 * b + c];

@@ -70,6 +70,12 @@ struct CoupleArgs {
     double *tape_mom0;
     double *tape_momn;
     long long *tape_contrib;
+    // WCA cell list (cell_head NULL: no pair force): k_bead_half links each
+    // bead into its cell at R', k_bead_update puts the heads back to -1
+    CellGrid cg;
+    int32_t *cell_head;
+    int32_t *cell_next;
+    int32_t *cell_of;
 };
 
 // R' = R + (h/2) P/m of bead b, component c (one expression wherever R' is
@@ -114,12 +120,18 @@ __device__ __forceinline__ void bond_force(const CoupleArgs &a, int q)
 // One thread per bead, per bond and per entry of the idle bond accumulator
 // (grid of max(n, nbonds, cap) threads): R' of the bead, the bond's forces
 // (each bond forms R' of its two beads itself, so nothing waits for the
-// first role), zero the accumulator of the next call, copy P to the tape.
+// first role), zero the accumulator of the next call, copy P to the tape,
+// link the bead into its WCA cell.
 __global__ void k_bead_half(CoupleArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < a.n) {
-        for (int c = 0; c < 3; ++c) a.half[3 * t + c] = half_coord(a, t, c);
+        double R[3];
+        for (int c = 0; c < 3; ++c) {
+            R[c] = half_coord(a, t, c);
+            a.half[3 * t + c] = R[c];
+        }
+        if (a.cell_head) cell_link(t, R, a.cg, a.cell_of, a.cell_head, a.cell_next);
         if (a.tape_mom0)
             for (int c = 0; c < 3; ++c) a.tape_mom0[3 * t + c] = a.mom_in[3 * t + c];
     }
@@ -302,6 +314,8 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
             a.fc[3 * b + c] = Fc[c];
             if (a.tape_momn) a.tape_momn[3 * b + c] = Pn[c];
         }
+    // the pair forces were read (k_wca ran before): this bead's cell list is done
+    if (q == 0 && a.cell_head) a.cell_head[a.cell_of[b]] = -1;
 }
 
 }  // namespace lbmi

@@ -15,7 +15,6 @@
 #include <vector>
 
 #include "../../include/lb.h"
-#include <hipcub/hipcub.hpp>
 
 #include "adjoint.h"
 #include "bead_adjoint.h"
@@ -60,16 +59,11 @@ struct lb_ctx {
     int bead_cap = 0;
     bool pending_force = false;
     // WCA cell list (allocated on the first lb_couple with wca_epsilon > 0)
-    int32_t *cell_count = nullptr;   // [ncell + 1] counts, then (cell_start) their exclusive scan
-    int32_t *cell_start = nullptr;   // [ncell + 1]
-    size_t cell_cap = 0;             // cells allocated (plus one)
-    int32_t *bead_cell = nullptr;    // [n] cell, slot within the cell, cell-ordered bead list
-    int32_t *bead_slot = nullptr;
-    int32_t *cell_sorted = nullptr;
-    double4 *cell_pos = nullptr;     // [n] positions in cell order (x, y, z, bead index)
+    int32_t *cell_head = nullptr;    // [cell_cap] first bead of each cell's list (-1 at rest)
+    size_t cell_cap = 0;             // cells allocated
+    int32_t *cell_next = nullptr;    // [n] next bead in the same cell
+    int32_t *cell_of = nullptr;      // [n] cell of each bead
     int pair_cap = 0;
-    void *scan_tmp = nullptr;        // hipcub scan workspace
-    size_t scan_tmp_bytes = 0;
     bool tuned = false;              // launch configuration chosen (autotune done or fixed)
     uint32_t xcd_remap = LBMI_XCD_REMAP;  // step kernel: consecutive tiles on one XCD (if the grid allows)
     // single box: launch configuration of the step kernel without / with a
@@ -413,82 +407,48 @@ CellGrid cell_grid(const lb_ctx *c, const lb_beads *b)
 
 int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
 {
-    if (ncell + 1 > c->cell_cap) {
-        (void)hipFree(c->cell_count);
-        (void)hipFree(c->cell_start);
-        c->cell_count = c->cell_start = nullptr;
+    if (ncell > c->cell_cap) {
+        (void)hipFree(c->cell_head);
+        c->cell_head = nullptr;
         c->cell_cap = 0;
-        if (hipMalloc(&c->cell_count, (ncell + 1) * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->cell_start, (ncell + 1) * sizeof(int32_t)) != hipSuccess)
+        if (hipMalloc(&c->cell_head, ncell * sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "cell list allocation failed");
-        c->cell_cap = ncell + 1;
-        // counts start at zero; each use leaves them at zero (k_cell_fill)
-        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(ncell + 1, 256)), dim3(256), 0, c->stream, c->cell_count,
-                           (uint32_t)(ncell + 1));
-        LB_LAUNCH_CHECK(c, "zero cell counts");
-    }
-    size_t tmp = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, c->cell_count, c->cell_start, (int)(ncell + 1), c->stream) !=
-        hipSuccess)
-        return fail(c, LB_EDEVICE, "scan workspace query failed");
-    if (tmp > c->scan_tmp_bytes) {
-        (void)hipFree(c->scan_tmp);
-        c->scan_tmp = nullptr;
-        c->scan_tmp_bytes = 0;
-        if (hipMalloc(&c->scan_tmp, tmp) != hipSuccess) return fail(c, LB_ENOMEM, "scan workspace allocation failed");
-        c->scan_tmp_bytes = tmp;
+        c->cell_cap = ncell;
+        // every head starts at -1 (all bits set); each use puts back the heads it set
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ncell, 256)), dim3(256), 0, c->stream,
+                           reinterpret_cast<uint32_t *>(c->cell_head), (uint32_t)ncell, 0xffffffffu);
+        LB_LAUNCH_CHECK(c, "reset cell heads");
     }
     if (n > c->pair_cap) {
-        (void)hipFree(c->bead_cell);
-        (void)hipFree(c->bead_slot);
-        (void)hipFree(c->cell_sorted);
-        (void)hipFree(c->cell_pos);
-        c->bead_cell = c->bead_slot = c->cell_sorted = nullptr;
-        c->cell_pos = nullptr;
+        (void)hipFree(c->cell_next);
+        (void)hipFree(c->cell_of);
+        c->cell_next = c->cell_of = nullptr;
         c->pair_cap = 0;
-        if (hipMalloc(&c->bead_cell, (size_t)n * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->bead_slot, (size_t)n * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->cell_sorted, (size_t)n * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->cell_pos, (size_t)n * sizeof(double4)) != hipSuccess)
+        if (hipMalloc(&c->cell_next, (size_t)n * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->cell_of, (size_t)n * sizeof(int32_t)) != hipSuccess)
             return fail(c, LB_ENOMEM, "cell list allocation failed");
         c->pair_cap = n;
     }
     return LB_OK;
 }
 
-// WCA forces at the half-step positions into c->fp: rebuild the cell list,
-// then kPairLanes lanes per bead over its neighbour cells.
-// Cell list of the positions `half` (count, scan, fill, rank).
-CellGrid build_cells(lb_ctx *c, const lb_beads *b, const double *half)
+// WCA forces at the positions `half` (linked into the cell list by
+// k_bead_half) into c->fp.
+void launch_wca(lb_ctx *c, const lb_beads *b, const double *half, const CellGrid &cg)
 {
-    const CellGrid cg = cell_grid(c, b);
-    const size_t ncell = (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2];
-    const unsigned gb = grid_for((size_t)b->n, 256);
-    hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(256), 0, c->stream, half, b->n, cg, c->bead_cell, c->bead_slot,
-                       c->cell_count);
-    size_t tmp = c->scan_tmp_bytes;
-    (void)hipcub::DeviceScan::ExclusiveSum(c->scan_tmp, tmp, c->cell_count, c->cell_start, (int)(ncell + 1),
-                                           c->stream);
-    hipLaunchKernelGGL(k_cell_fill, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->bead_slot, c->cell_start,
-                       c->cell_sorted, c->cell_count);
-    hipLaunchKernelGGL(k_cell_rank, dim3(gb), dim3(256), 0, c->stream, b->n, c->bead_cell, c->cell_start,
-                       c->cell_sorted, half, c->cell_pos);
-    return cg;
-}
-
-void launch_wca(lb_ctx *c, const lb_beads *b, const double *half)
-{
-    const CellGrid cg = build_cells(c, b, half);
     hipLaunchKernelGGL(k_wca, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, half, b->n,
-                       cg, c->bead_cell, c->cell_start, c->cell_pos, c->fp);
+                       cg, c->cell_of, c->cell_head, c->cell_next, c->fp);
 }
 
-// Adjoint of the WCA forces at the positions `half`: half_bar += J (fc_bar_i - fc_bar_j).
+// Adjoint of the WCA forces at the positions `half`: half_bar += J (fc_bar_i -
+// fc_bar_j).  Links the cell list; k_bead_adjoint_finish puts the heads back.
 void launch_wca_adjoint(lb_ctx *c, const lb_beads *b, const double *half, const double *fc_bar, double *half_bar)
 {
-    const CellGrid cg = build_cells(c, b, half);
+    const CellGrid cg = cell_grid(c, b);
+    hipLaunchKernelGGL(k_cell_link, dim3(grid_for((size_t)b->n, 256)), dim3(256), 0, c->stream, half, b->n, cg,
+                       c->cell_of, c->cell_head, c->cell_next);
     hipLaunchKernelGGL(k_wca_adjoint, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, half,
-                       b->n, cg, c->bead_cell, c->cell_start, c->cell_pos, fc_bar, half_bar);
+                       b->n, cg, c->cell_of, c->cell_head, c->cell_next, fc_bar, half_bar);
 }
 
 // Threads per block of the per-bead stencil kernels: one wave, so that a few
@@ -575,9 +535,13 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
     a.tape_mom0 = tape ? tape->mom0 : nullptr;
     a.tape_momn = tape ? tape->momn : nullptr;
     a.tape_contrib = tape ? tape->contrib : nullptr;
+    a.cell_head = wca ? c->cell_head : nullptr;
+    a.cell_next = c->cell_next;
+    a.cell_of = c->cell_of;
+    if (wca) a.cg = cell_grid(c, b);
     const size_t roles = std::max<size_t>({(size_t)b->n, (size_t)b->nbonds, (size_t)c->bead_cap});
     hipLaunchKernelGGL(k_bead_half, dim3(grid_for(roles, 256)), dim3(256), 0, c->stream, a);
-    if (wca) launch_wca(c, b, a.half);
+    if (wca) launch_wca(c, b, a.half, a.cg);
     by_storage(c->p.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         by_stencil(b->stencil, [&](auto w) {
@@ -1034,8 +998,7 @@ int lb_destroy(lb_ctx *c)
     void *ptrs[] = {c->bufA,       c->bufB,      c->partials,  c->scratch,   c->dev_out,   c->flags,
                     c->force,      c->fmask,     c->half,      c->fc,
                     c->boxes_d,    c->tile_box,  c->dstep,     c->amp,       c->ring,      c->corr,
-                    c->cell_count, c->cell_start, c->bead_cell, c->bead_slot, c->cell_sorted, c->scan_tmp,
-                    c->cell_pos,   c->fb2,        c->fp};
+                    c->cell_head,  c->cell_next,  c->cell_of,   c->fb2,       c->fp};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int k = 0; k < 2; ++k)
@@ -1572,7 +1535,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 hipLaunchKernelGGL(k_bead_adjoint_finish,
                                    dim3(grid_for(std::max<size_t>((size_t)nbd, (size_t)ts.entries), 256)), dim3(256),
                                    0, c->stream, nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar, c->fbar, ts.contrib,
-                                   ts.entries, c->geo.N);
+                                   ts.entries, c->geo.N, bc.wca_epsilon > 0.0 ? c->cell_head : nullptr, c->cell_of);
             }
             std::swap(c->lamA, c->lamB);
         }

@@ -10,21 +10,19 @@
 //                   with fewer than 3 cells gets one cell (then all beads along
 //                   it are candidates and the minimum image picks the pair's
 //                   single image within r_c < L_a / 2)
-//   k_cell_count    cell of each bead, its slot = atomic increment of the
-//                   cell's count (the counts are zero on entry: zeroed once
-//                   at allocation, then by k_cell_fill after their use)
-//   (scan)          exclusive prefix sum of the counts: first entry per cell
-//   k_cell_fill     members[start[cell] + slot] = bead (in arrival order);
-//                   the cell's count back to zero
-//   k_cell_rank     each bead's rank in its cell by index (the number of
-//                   members with a smaller index) and a copy of its position
-//                   at that place, cpos[start + rank] = (R', index): cells in
-//                   index order, one 32-byte load per candidate below
-//   k_wca           32 lanes per bead, lane l scans neighbour cell l (27 cells,
-//                   fewer on one-cell axes) in cell order; a fixed butterfly
-//                   sums the lanes.  Every pair is evaluated from both ends,
-//                   so no atomics are needed and the bits are the same on
-//                   every run.
+//   linking         (in k_bead_half, or k_cell_link for the adjoint) the cell
+//                   of each bead and next[b] = the cell's previous head, the
+//                   head swapped to b atomically; heads are -1 at rest (set
+//                   at allocation; the kernel after the last reader of a
+//                   step's list puts its beads' heads back to -1)
+//   k_wca           32 lanes per bead, lane l visits neighbour cell l (27
+//                   cells, fewer on one-cell axes) and takes the cell's
+//                   members in increasing bead index, whatever order the
+//                   linking left them in (batches of the 16 smallest
+//                   indices above the last one done, one walk of the list
+//                   per batch); a fixed butterfly sums the lanes.  Every pair is
+//                   evaluated from both ends, so no atomics are needed and
+//                   the bits are the same on every run.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -73,41 +71,85 @@ __device__ __forceinline__ int neighbour_cell(int c, int o, int nc, int periodic
     return cn;
 }
 
-// count has ncell + 1 entries, zero on entry (the last stays zero, so the
-// exclusive scan's last entry is the bead count).
-__global__ void k_cell_count(const double *__restrict__ half, int n, CellGrid cg, int32_t *cell_of, int32_t *slot,
-                             int32_t *count)
+// Cell of a position (flattened).
+__device__ __forceinline__ int cell_index(const double R[3], const CellGrid &cg)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
     int c[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) c[a] = cell_coord(half[3 * b + a], cg.L[a], cg.inv_w[a], cg.nc[a], cg.periodic[a]);
-    const int cell = c[0] + cg.nc[0] * (c[1] + cg.nc[1] * c[2]);
+    for (int a = 0; a < 3; ++a) c[a] = cell_coord(R[a], cg.L[a], cg.inv_w[a], cg.nc[a], cg.periodic[a]);
+    return c[0] + cg.nc[0] * (c[1] + cg.nc[1] * c[2]);
+}
+
+// Put bead b at R into its cell's list.
+__device__ __forceinline__ void cell_link(int b, const double R[3], const CellGrid &cg, int32_t *cell_of,
+                                          int32_t *head, int32_t *next)
+{
+    const int cell = cell_index(R, cg);
     cell_of[b] = cell;
-    slot[b] = atomicAdd(&count[cell], 1);
+    next[b] = atomicExch(&head[cell], b);
 }
 
-__global__ void k_cell_fill(int n, const int32_t *__restrict__ cell_of, const int32_t *__restrict__ slot,
-                            const int32_t *__restrict__ start, int32_t *members, int32_t *count)
+__global__ void k_cell_link(const double *__restrict__ half, int n, CellGrid cg, int32_t *cell_of, int32_t *head,
+                            int32_t *next)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
-    const int cell = cell_of[b];
-    members[start[cell] + slot[b]] = b;
-    count[cell] = 0;
+    const double R[3] = {half[3 * b], half[3 * b + 1], half[3 * b + 2]};
+    cell_link(b, R, cg, cell_of, head, next);
 }
 
-__global__ void k_cell_rank(int n, const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
-                            const int32_t *__restrict__ members, const double *__restrict__ half, double4 *cpos)
+// Neighbour cell l of `cell` (flattened), or -1 past a wall or beyond the
+// neighbourhood (lanes l >= the number of neighbour cells).
+__device__ __forceinline__ int lane_cell(int cell, int l, const CellGrid &cg)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
-    const int cell = cell_of[b];
-    const int lo = start[cell], hi = start[cell + 1];
-    int rank = 0;
-    for (int k = lo; k < hi; ++k) rank += members[k] < b ? 1 : 0;
-    cpos[lo + rank] = make_double4(half[3 * b], half[3 * b + 1], half[3 * b + 2], (double)b);
+    const int span[3] = {cg.nc[0] >= 3 ? 1 : 0, cg.nc[1] >= 3 ? 1 : 0, cg.nc[2] >= 3 ? 1 : 0};
+    const int w0 = 2 * span[0] + 1, w1 = 2 * span[1] + 1, w2 = 2 * span[2] + 1;
+    if (l >= w0 * w1 * w2) return -1;
+    const int o[3] = {l % w0 - span[0], (l / w0) % w1 - span[1], l / (w0 * w1) - span[2]};
+    const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
+    int cn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cn[a] = neighbour_cell(ci[a], o[a], cg.nc[a], cg.periodic[a]);
+    return (cn[0] < 0 || cn[1] < 0 || cn[2] < 0) ? -1 : cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
+}
+
+// Calls f(j) for every member j != self of cell `cell`'s list in increasing
+// index order.  Each walk keeps the 16 smallest indices above the last one
+// done in a sorted register array (a compare-exchange chain).  The walks are
+// bounded (n hops, indices checked against n), so a list that is not what
+// the linking left could only give wrong members, never run away.
+template <typename F>
+__device__ __forceinline__ void for_members_in_order(int cell, int self, int n, const int32_t *__restrict__ head,
+                                                     const int32_t *__restrict__ next, F &&f)
+{
+    if (cell < 0) return;
+    const int first = head[cell];
+    constexpr int B = 16;
+    constexpr int kNone = 0x7fffffff;
+    int last = -1;
+    for (int batch = 0; batch <= n / B; ++batch) {
+        int a[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) a[u] = kNone;
+        int j = first;
+        for (int hops = 0; j >= 0 && j < n && hops < n; ++hops) {
+            if (j > last && j != self) {
+                int x = j;
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int lo = min(a[u], x);
+                    x = max(a[u], x);
+                    a[u] = lo;
+                }
+            }
+            j = next[j];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (a[u] != kNone) f(a[u]);
+        if (a[B - 1] == kNone) return;
+        last = a[B - 1];
+    }
 }
 
 constexpr int kPairLanes = 32;
@@ -116,50 +158,28 @@ constexpr int kPairLanes = 32;
 // f = 24 eps (2 (sigma/r)^12 - (sigma/r)^6) / r^2 = -V'(r)/r of eq. ulennardjones.
 // kPairLanes consecutive lanes per bead (blockDim a multiple of 64).
 __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, int n, CellGrid cg,
-                                             const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
-                                             const double4 *__restrict__ cpos, double *fp)
+                                             const int32_t *__restrict__ cell_of, const int32_t *__restrict__ head,
+                                             const int32_t *__restrict__ next, double *fp)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kPairLanes, l = t % kPairLanes;
     double F[3] = {0.0, 0.0, 0.0};
     if (i < n) {
-        const int span[3] = {cg.nc[0] >= 3 ? 1 : 0, cg.nc[1] >= 3 ? 1 : 0, cg.nc[2] >= 3 ? 1 : 0};
-        const int w0 = 2 * span[0] + 1, w1 = 2 * span[1] + 1, w2 = 2 * span[2] + 1;
-        if (l < w0 * w1 * w2) {
-            const int cell = cell_of[i];
-            const int o[3] = {l % w0 - span[0], (l / w0) % w1 - span[1], l / (w0 * w1) - span[2]};
-            const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
-            int cn[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) cn[a] = neighbour_cell(ci[a], o[a], cg.nc[a], cg.periodic[a]);
-            // a lane whose cell lies past a wall has no candidates
-            const int nb = (cn[0] < 0 || cn[1] < 0 || cn[2] < 0) ? -1 : cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
-            const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
-            const double self = (double)i;
-            const int lo = nb < 0 ? 0 : start[nb], hi = nb < 0 ? 0 : start[nb + 1];
-            // four candidates per round, their loads issued together
-            constexpr int U = 4;
-            for (int k0 = lo; k0 < hi; k0 += U) {
-                double4 q[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) q[u] = cpos[k0 + u < hi ? k0 + u : lo];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (k0 + u >= hi || q[u].w == self) continue;
-                    const double d0 = pair_sep(Ri[0] - q[u].x, cg.L[0], cg.periodic[0]);
-                    const double d1 = pair_sep(Ri[1] - q[u].y, cg.L[1], cg.periodic[1]);
-                    const double d2 = pair_sep(Ri[2] - q[u].z, cg.L[2], cg.periodic[2]);
-                    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    if (!(r2 < cg.rc2)) continue;
-                    const double s2 = cg.sig2 / r2;
-                    const double s6 = s2 * s2 * s2;
-                    const double f = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
-                    F[0] += f * d0;
-                    F[1] += f * d1;
-                    F[2] += f * d2;
-                }
-            }
-        }
+        const int nb = lane_cell(cell_of[i], l, cg);
+        const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
+        for_members_in_order(nb, i, n, head, next, [&](int j) {
+            const double d0 = pair_sep(Ri[0] - half[3 * j], cg.L[0], cg.periodic[0]);
+            const double d1 = pair_sep(Ri[1] - half[3 * j + 1], cg.L[1], cg.periodic[1]);
+            const double d2 = pair_sep(Ri[2] - half[3 * j + 2], cg.L[2], cg.periodic[2]);
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            if (!(r2 < cg.rc2)) return;
+            const double s2 = cg.sig2 / r2;
+            const double s6 = s2 * s2 * s2;
+            const double f = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
+            F[0] += f * d0;
+            F[1] += f * d1;
+            F[2] += f * d2;
+        });
     }
     // butterfly over the bead's lanes (every lane ends with the same bits)
 #pragma unroll
@@ -178,53 +198,36 @@ __global__ void __launch_bounds__(256) k_wca(const double *__restrict__ half, in
 // lanes and cell order as k_wca (fixed sums, no atomics).
 __global__ void __launch_bounds__(256) k_wca_adjoint(const double *__restrict__ half, int n, CellGrid cg,
                                                      const int32_t *__restrict__ cell_of,
-                                                     const int32_t *__restrict__ start,
-                                                     const double4 *__restrict__ cpos,
+                                                     const int32_t *__restrict__ head,
+                                                     const int32_t *__restrict__ next,
                                                      const double *__restrict__ fc_bar, double *half_bar)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kPairLanes, l = t % kPairLanes;
     double B[3] = {0.0, 0.0, 0.0};
     if (i < n) {
-        const int span[3] = {cg.nc[0] >= 3 ? 1 : 0, cg.nc[1] >= 3 ? 1 : 0, cg.nc[2] >= 3 ? 1 : 0};
-        const int w0 = 2 * span[0] + 1, w1 = 2 * span[1] + 1, w2 = 2 * span[2] + 1;
-        if (l < w0 * w1 * w2) {
-            const int cell = cell_of[i];
-            const int o[3] = {l % w0 - span[0], (l / w0) % w1 - span[1], l / (w0 * w1) - span[2]};
-            const int ci[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
-            int cn[3];
+        const int nb = lane_cell(cell_of[i], l, cg);
+        const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
+        const double Gi[3] = {fc_bar[3 * i], fc_bar[3 * i + 1], fc_bar[3 * i + 2]};
+        for_members_in_order(nb, i, n, head, next, [&](int j) {
+            double d[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) cn[a] = neighbour_cell(ci[a], o[a], cg.nc[a], cg.periodic[a]);
-            // a lane whose cell lies past a wall has no candidates
-            const int nb = (cn[0] < 0 || cn[1] < 0 || cn[2] < 0) ? -1 : cn[0] + cg.nc[0] * (cn[1] + cg.nc[1] * cn[2]);
-            const double Ri[3] = {half[3 * i], half[3 * i + 1], half[3 * i + 2]};
-            const double Gi[3] = {fc_bar[3 * i], fc_bar[3 * i + 1], fc_bar[3 * i + 2]};
-            const double self = (double)i;
-            const int lo = nb < 0 ? 0 : start[nb], hi = nb < 0 ? 0 : start[nb + 1];
-            for (int k = lo; k < hi; ++k) {
-                const double4 q = cpos[k];
-                if (q.w == self) continue;
-                double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = pair_sep(Ri[a] - half[3 * j + a], cg.L[a], cg.periodic[a]);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 < cg.rc2)) return;
+            double v[3], dv = 0.0;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) d[a] = pair_sep(Ri[a] - (a == 0 ? q.x : (a == 1 ? q.y : q.z)), cg.L[a],
-                                                           cg.periodic[a]);
-                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                if (!(r2 < cg.rc2)) continue;
-                const int j = (int)q.w;
-                double v[3], dv = 0.0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    v[a] = Gi[a] - fc_bar[3 * j + a];
-                    dv += d[a] * v[a];
-                }
-                const double s2 = cg.sig2 / r2;
-                const double s6 = s2 * s2 * s2;
-                const double mag = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
-                const double mag2p = cg.eps24 * (-28.0 * s6 * s6 + 8.0 * s6) / (r2 * r2);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) B[a] += mag * v[a] + mag2p * d[a] * dv;
+            for (int a = 0; a < 3; ++a) {
+                v[a] = Gi[a] - fc_bar[3 * j + a];
+                dv += d[a] * v[a];
             }
-        }
+            const double s2 = cg.sig2 / r2;
+            const double s6 = s2 * s2 * s2;
+            const double mag = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
+            const double mag2p = cg.eps24 * (-28.0 * s6 * s6 + 8.0 * s6) / (r2 * r2);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) B[a] += mag * v[a] + mag2p * d[a] * dv;
+        });
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
