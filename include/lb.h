@@ -337,18 +337,22 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * with the states of a segment recomputed forward (checkpoint_every step
  * buffers are allocated), the noise replayed from its Philox counters.
  * Taped coupled steps (lb_couple before lb_step) are differentiated too:
- * each lb_couple while recording stores a device copy of the bead state
- * (R, P) it starts from and keeps the lb_beads descriptor, so the arrays
- * mass, zeta and bonds must stay valid and unchanged until lb_backward, the
- * bead count must be the same in every taped coupled step, and the bead
- * state must change only through lb_couple between taped steps.  In the
- * reverse sweep a coupled step rebuilds its spread force from the stored
- * bead state, the fluid adjoint also yields the adjoint of the bead force at
- * the touched nodes, and the adjoint of the particle half (half drift,
- * harmonic or FENE bonds and WCA pairs (their Jacobians mag I + 2 mag' d d^T),
- * the interpolation with the stencil weights differentiated in R, the momentum update eq. langevin_momentum_update with its noise
- * replayed, the spread reaction eq. ftotal) carries the bead adjoints back
- * and adds the interpolation's share to dL/dn and dL/dg.
+ * each lb_couple while recording keeps its particle half on the device (P
+ * at the start, R', F^c and P'': 12 doubles per bead, and each stencil
+ * node's fixed-point spread contribution: 32 bytes per entry, 8, 32 or 64
+ * entries per bead for phi_2, phi_3, phi_4) and the lb_beads descriptor, so the arrays mass, zeta and
+ * bonds must stay valid and unchanged until lb_backward, the bead count
+ * must be the same in every taped coupled step, and the bead state must
+ * change only through lb_couple between taped steps.  Both sweeps put a
+ * coupled step's spread force back from its recorded contributions (the
+ * bead kernels do not run again); in the reverse sweep the fluid adjoint
+ * also yields the adjoint of the bead force at the touched nodes, and the
+ * adjoint of the particle half (half drift, harmonic or FENE bonds and WCA
+ * pairs (their Jacobians mag I + 2 mag' d d^T), the interpolation with the
+ * stencil weights differentiated in R, the momentum update
+ * eq. langevin_momentum_update, the spread reaction eq. ftotal) carries the
+ * bead adjoints back and adds the interpolation's share to dL/dn and
+ * dL/dg.
  * lb_backward_coupled takes and returns the bead adjoints as well:
  *   dL_dR_T, dL_dP_T: dL/dR, dL/dP of the bead state after the last step
  *                     (device FP64 [n][3]; NULL = zero),
