@@ -234,64 +234,72 @@ __global__ void __launch_bounds__(256) k_bead_update(CoupleArgs a)
     double ub[3] = {0.0, 0.0, 0.0};
     uint32_t node = 0;
     double wq = 0.0;
+    // per-bead inputs: loaded together with R' (one round trip), and the
+    // OU constants and the noise computed while the gather below is in flight
+    double m = 1.0, z = 0.0, P[3] = {0.0, 0.0, 0.0}, Fc[3] = {0.0, 0.0, 0.0};
+    const double h = 1.0;
+    float v[Q];
     if (live) {
         const double R[3] = {a.half[3 * b], a.half[3 * b + 1], a.half[3 * b + 2]};
+        m = a.mass[b];
+        z = a.zeta[b];
+        for (int c = 0; c < 3; ++c) {
+            // F^c = (bonds + pairs) + fext
+            Fc[c] = a.fb[3 * b + c];
+            if (a.fp) Fc[c] += a.fp[3 * b + c];
+            if (a.fext) Fc[c] += a.fext[3 * b + c];
+            P[c] = a.mom_in[3 * b + c];
+        }
         stencil_node<W>(R, q, g, node, wq, nullptr);
         if (q < W * W * W) {
             uint32_t xx, yy, zz;
             const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
             const T *pop = static_cast<const T *>(a.pop);
-            double m = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
-                m += v;
-                j[0] += v * kCX[i];
-                j[1] += v * kCY[i];
-                j[2] += v * kCZ[i];
-            }
-            const double rho = a.rho0 + m;
-            for (int c = 0; c < 3; ++c) ub[c] = wq * (j[c] + 0.5 * a.g[c]) / rho;
+            for (int i = 0; i < Q; ++i) v[i] = S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
         }
     }
-    // sum the node contributions of the bead (its LANES lanes)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ub[c] = bead_sum<LANES>(ub[c]);
-    if (!live) return;
-    const double m = a.mass[b], z = a.zeta[b], h = 1.0;
-    double C1, C2, C3;
+    double C1 = 1.0, C2 = h, C3 = 0.0;
     if (z > 0.0) {
         C1 = exp(-z * h / m);
         C2 = (m / z) * (1.0 - C1);
         C3 = sqrt(m * a.kT * (1.0 - C1 * C1));  // exp(-2 zeta h/m) = C1^2
-    } else {
-        C1 = 1.0;
-        C2 = h;
-        C3 = 0.0;
     }
     double th[3] = {0.0, 0.0, 0.0};
-    if (a.kT > 0.0 && z > 0.0) {
+    if (live && a.kT > 0.0 && z > 0.0) {
         if (a.three_point)
             bead_three_point((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
         else
             bead_normals((uint32_t)b, a.step, a.box, a.key0, a.key1, th);
     }
-    double Pn[3], I[3], Fc[3];
+    if (live && q < W * W * W) {
+        double ms = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double vi = (double)v[i];
+            ms += vi;
+            j[0] += vi * kCX[i];
+            j[1] += vi * kCY[i];
+            j[2] += vi * kCZ[i];
+        }
+        const double rho = a.rho0 + ms;
+        for (int c = 0; c < 3; ++c) ub[c] = wq * (j[c] + 0.5 * a.g[c]) / rho;
+    }
+    // sum the node contributions of the bead (its LANES lanes)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ub[c] = bead_sum<LANES>(ub[c]);
+    if (!live) return;
+    double Pn[3], I[3];
     for (int c = 0; c < 3; ++c) {
-        // F^c = (bonds + pairs) + fext
-        Fc[c] = a.fb[3 * b + c];
-        if (a.fp) Fc[c] += a.fp[3 * b + c];
-        if (a.fext) Fc[c] += a.fext[3 * b + c];
-        const double P = a.mom_in[3 * b + c];
-        Pn[c] = C1 * P + C2 * (Fc[c] + z * ub[c]) + C3 * th[c];
-        I[c] = -(Pn[c] - P - h * Fc[c]);
+        Pn[c] = C1 * P[c] + C2 * (Fc[c] + z * ub[c]) + C3 * th[c];
+        I[c] = -(Pn[c] - P[c] - h * Fc[c]);
     }
     long long iv[3] = {0, 0, 0};
     if (wq != 0.0) {
         for (int c = 0; c < 3; ++c) {
-            const double v = wq * I[c] / h;
-            if (fabs(v) < kForceLimit) {  // false for NaN too
-                iv[c] = __double2ll_rn(v * kForceScale);
+            const double fq = wq * I[c] / h;
+            if (fabs(fq) < kForceLimit) {  // false for NaN too
+                iv[c] = __double2ll_rn(fq * kForceScale);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&a.force[(size_t)c * g.N + node]),
                           (unsigned long long)iv[c]);
             } else {
