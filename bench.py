@@ -202,6 +202,8 @@ def run_forms(L: int) -> dict:
 
     from paper_0803_2826_amd import forms, lattice
 
+    import numpy as np
+
     out = {}
     for kT in (KT, 0.0):
         out[f"f32_fluid_only_kT{kT:g}_mlups"] = round(forms.step_mlups("f32", L, kT, steps=100), 1)
@@ -213,13 +215,27 @@ def run_forms(L: int) -> dict:
         f"{st}_{rd}": round(forms.step_mlups(st, 512, KT, steps=50, rounding=rd), 1)
         for st, rd in (("f32", "nearest"), ("bf16", "nearest"), ("bf16", "stochastic"), ("f16", "nearest"),
                        ("f16", "stochastic"))}
+    # errors of each storage form against closed forms that the oracle pins:
+    # the decay rate of the 512^3 workload's shear wave (k = 2 pi / 512, on a
+    # 64 x 64 x 512 box: the same wave and per-site statistics) against
+    # -ln lambda(k), beside the rate change round-to-nearest is predicted to
+    # add; the stationary per-mode variances (32^3) against 3 kT w_k rho0
+    errs = {}
+    for st, rd in (("f32", "nearest"), ("bf16", "nearest"), ("bf16", "stochastic"), ("f16", "nearest"),
+                   ("f16", "stochastic")):
+        d = forms.decay_rate(st, 64, 64, 512, steps=2000, kT=KT, rounding=rd)
+        v = forms.mode_variances(st, 32, KT, 300, rounding=rd)
+        errs[f"{st}_{rd}"] = {
+            "decay_rate_rel_err": round(float(d["rel_err"]), 5),
+            "decay_rate_rel_err_predicted": round(forms.rounding_shrink(st) / d["rate_exact"], 5) if rd == "nearest"
+            else 0.0,
+            "mode_variance_max_rel_dev": round(float(np.abs(v - 1.0).max()), 6)}
+    out["precision_errors"] = errs
     print("# forms: precision done", file=sys.stderr, flush=True)
     b = forms.batch_study(nbox=512, steps=200, kT=KT, lags=0, graph_steps=10)
     out["batched_mlups"] = round(b["mlups"], 1)
     out["batched_sites"] = b["sites"]
     print("# forms: batch done", file=sys.stderr, flush=True)
-    import numpy as np
-
     from paper_0803_2826_amd.inputs import random_walk_chains
 
     Lb, T, K = 128, 500, 50
@@ -253,16 +269,17 @@ def run_forms(L: int) -> dict:
     # WCA pairs (cell list rebuilt every step), eps = kT, sigma = 1
     from paper_0803_2826_amd.inputs import kremer_grest_chains
 
-    pk = lattice.FluidParams(nx=L, ny=L, nz=L, kT=KT, seed=0, track_totals=True)
+    pk = lattice.FluidParams(nx=L, ny=L, nz=L, kT=KT, seed=0, track_totals=True, block=-1)
     lat = lattice.Lattice(pk)
     lat.init_equilibrium()
     pos, mom, bonds = kremer_grest_chains(64, 32, (L, L, L), seed=0)
     nb = pos.shape[0]
     kg = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, KG_ZETA), bonds, 30 * KT, 1.5, bond="fene",
                              wca_epsilon=KT, wca_sigma=1.0)
-    for _ in range(5):
+    lat.step(1)
+    for _ in range(20):
         lat.coupled_step(kg)
-    Tk = 50
+    Tk = 100
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     half = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(Tk)]
     torch.cuda.synchronize()
