@@ -20,6 +20,7 @@
 // so the forward state needed is re-gathered from the stored step buffer.
 #pragma once
 
+#include "bead_adjoint.h"
 #include "kernels.h"
 
 namespace lbmi {
@@ -39,6 +40,9 @@ struct AdjArgs {
     long long *force;       // [3][N] fixed point (kForceScale)
     uint32_t *fmask;        // [ceil(N/32)]
     float *fbar;            // [3][N]
+    // blocks from main_blocks on do the side jobs instead of sites
+    uint32_t main_blocks;
+    AdjSide side;
 };
 
 
@@ -47,6 +51,10 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
+    if (blockIdx.x >= a.main_blocks) {  // whole blocks: no barrier below is split
+        adjoint_side_work(a.side, (int)((blockIdx.x - a.main_blocks) * blockDim.x + threadIdx.x), a.geo.N);
+        return;
+    }
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = s < a.geo.N;
     float Fbs[3] = {0.f, 0.f, 0.f};

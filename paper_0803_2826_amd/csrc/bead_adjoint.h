@@ -43,6 +43,15 @@ struct BeadAdjArgs {
     double *p_bar;          // out: adjoint of P without the half-drift term [n][3]
     float *lam;             // [19][N] adjoint of n_t, accumulated at the nodes
     double *gbar;           // [3] accumulated
+    // fold = 1: the adjoint of (R_new, P_new) is formed here, per bead, from
+    // the later coupled step's half_bar and p_bar as they stand on entry
+    // (R_new bar = R'bar, P_new bar = pbar + R'bar h / (2m), m = fold_mass)
+    // instead of being read from pos_bar, mom_bar; that step's WCA cell
+    // heads (fold_cell_head, NULL if none) are put back to -1 on the way
+    int32_t fold;
+    const double *fold_mass;
+    int32_t *fold_cell_head;
+    const int32_t *fold_cell_of;
 };
 
 // StencilLanes<W> lanes per bead, one per stencil node (node order and
@@ -88,6 +97,22 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
 #pragma unroll
     for (int c = 0; c < 3; ++c) Ib[c] = bead_sum<LANES>(wq * fb[c]) / h;
     if (!live) return;
+    // adjoint of the state after the step (the same expressions as
+    // k_bead_adjoint_finish when folded)
+    double Rnb[3], Pnb_in[3];
+    if (a.fold) {
+        const double hm = 0.5 / a.fold_mass[b];
+        for (int c = 0; c < 3; ++c) {
+            Rnb[c] = a.half_bar[3 * b + c];
+            Pnb_in[c] = a.p_bar[3 * b + c] + hm * Rnb[c];
+        }
+        if (q == 0 && a.fold_cell_head) a.fold_cell_head[a.fold_cell_of[b]] = -1;
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            Rnb[c] = a.pos_bar[3 * b + c];
+            Pnb_in[c] = a.mom_bar[3 * b + c];
+        }
+    }
     const double m = a.mass[b], z = a.zeta[b];
     double C1, C2;
     if (z > 0.0) {
@@ -102,7 +127,7 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
         const double P = a.mom0[3 * b + c], Pn = a.mom1[3 * b + c], Fc = a.fc[3 * b + c];
         I[c] = -(Pn - P - h * Fc);
         // R_new = R' + (h/2) P''/m, P_new = P'';  I = -(P'' - P - h F^c)
-        Pnb[c] = a.mom_bar[3 * b + c] + 0.5 * h / m * a.pos_bar[3 * b + c] - Ib[c];
+        Pnb[c] = Pnb_in[c] + 0.5 * h / m * Rnb[c] - Ib[c];
         pb[c] = Ib[c] + C1 * Pnb[c];
         fcb[c] = h * Ib[c] + C2 * Pnb[c];
         ubb[c] = C2 * z * Pnb[c];
@@ -130,7 +155,7 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
     }
     if (q == 0) {
         for (int c = 0; c < 3; ++c) {
-            a.half_bar[3 * b + c] = a.pos_bar[3 * b + c] + hb[c];
+            a.half_bar[3 * b + c] = Rnb[c] + hb[c];
             a.fc_bar[3 * b + c] = fcb[c];
             a.p_bar[3 * b + c] = pb[c];
             atomicAdd(&a.gbar[c], gq[c]);
@@ -143,12 +168,10 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
 //   harmonic  mag = -k (r - r0)/r,        2 mag' = -k r0 / r^3
 //   FENE      mag = -k / (1 - r^2/r0^2),  2 mag' = -2 k / (r0^2 (1 - r^2/r0^2)^2)
 // so dbar = (dF_b/dd)(fcbar_b - fcbar_a), half_bar_b += dbar, half_bar_a -= dbar.
-__global__ void k_bonds_adjoint(const double *__restrict__ half, const double *__restrict__ fc_bar, double *half_bar,
-                                const int32_t *__restrict__ bonds, int nbonds, double kb, double r0, int nbeads,
-                                int fene)
+__device__ __forceinline__ void bond_adjoint(const double *__restrict__ half, const double *__restrict__ fc_bar,
+                                             double *half_bar, const int32_t *__restrict__ bonds, int qd, double kb,
+                                             double r0, int nbeads, int fene)
 {
-    const int qd = blockIdx.x * blockDim.x + threadIdx.x;
-    if (qd >= nbonds) return;
     const int ia = bonds[2 * qd], ib = bonds[2 * qd + 1];
     if (ia < 0 || ib < 0 || ia >= nbeads || ib >= nbeads) return;
     double d[3], v[3], r2 = 0.0, dv = 0.0;
@@ -174,6 +197,14 @@ __global__ void k_bonds_adjoint(const double *__restrict__ half, const double *_
         atomicAdd(&half_bar[3 * ib + c], db);
         atomicAdd(&half_bar[3 * ia + c], -db);
     }
+}
+
+__global__ void k_bonds_adjoint(const double *__restrict__ half, const double *__restrict__ fc_bar, double *half_bar,
+                                const int32_t *__restrict__ bonds, int nbonds, double kb, double r0, int nbeads,
+                                int fene)
+{
+    const int qd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qd < nbonds) bond_adjoint(half, fc_bar, half_bar, bonds, qd, kb, r0, nbeads, fene);
 }
 
 // R' = R + (h/2) P/m:  Rbar = R'bar,  Pbar = pbar + (h/2m) R'bar.  Threads
@@ -206,11 +237,9 @@ __global__ void k_bead_adjoint_finish(int n, const double *__restrict__ mass, co
 // contributions k_bead_update recorded (one entry per bead and lane).  The
 // sums are integer, so the field gets the forward's bits in any order; the
 // bitmap bits are set as the forward set them.
-__global__ void k_respread(const long long *__restrict__ contrib, int entries, uint32_t N, long long *force,
-                           uint32_t *fmask)
+__device__ __forceinline__ void respread_entry(const long long *__restrict__ contrib, int e, uint32_t N,
+                                               long long *force, uint32_t *fmask)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= entries) return;
     const long long *p = contrib + 4 * (size_t)e;
     const long long node = p[0];
     if (node < 0) return;
@@ -219,6 +248,46 @@ __global__ void k_respread(const long long *__restrict__ contrib, int entries, u
             atomicAdd(reinterpret_cast<unsigned long long *>(&force[(size_t)c * N + (size_t)node]),
                       (unsigned long long)p[1 + c]);
     atomicOr(&fmask[(uint32_t)node >> 5], 1u << ((uint32_t)node & 31u));
+}
+
+__global__ void k_respread(const long long *__restrict__ contrib, int entries, uint32_t N, long long *force,
+                           uint32_t *fmask)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < entries) respread_entry(contrib, e, N, force, fmask);
+}
+
+// Small jobs of the reverse sweep that run as extra blocks of the adjoint
+// step kernel (nothing in that kernel reads what they touch): put the next
+// (earlier) coupled step's force back into its own field, the bond
+// Jacobians of the coupled step whose particle adjoint ran last (its F^c
+// adjoint is complete), and the clearing of that step's fbar at its nodes.
+// A count of zero skips a job.
+struct AdjSide {
+    const long long *put_contrib;  // k_respread of the next step
+    int put_entries;
+    long long *put_force;
+    uint32_t *put_fmask;
+    const double *half;            // bond Jacobians of the pending step
+    const double *fc_bar;
+    double *half_bar;
+    const int32_t *bonds;
+    int nbonds, nbeads, fene;
+    double kb, r0;
+    float *clear_fbar;             // fbar of the pending step, cleared at its nodes
+    const long long *clear_contrib;
+    int clear_entries;
+};
+
+__device__ __forceinline__ void adjoint_side_work(const AdjSide &s, int e, uint32_t N)
+{
+    if (e < s.put_entries) respread_entry(s.put_contrib, e, N, s.put_force, s.put_fmask);
+    if (e < s.nbonds) bond_adjoint(s.half, s.fc_bar, s.half_bar, s.bonds, e, s.kb, s.r0, s.nbeads, s.fene);
+    if (e < s.clear_entries) {
+        const long long node = s.clear_contrib[4 * (size_t)e];
+        if (node >= 0)
+            for (int c = 0; c < 3; ++c) s.clear_fbar[(size_t)c * N + (size_t)node] = 0.f;
+    }
 }
 
 }  // namespace lbmi

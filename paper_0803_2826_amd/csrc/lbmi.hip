@@ -113,7 +113,9 @@ struct lb_ctx {
     // backward scratch of the particle adjoint
     double *bead_work = nullptr;      // [5][n][3]: half_bar, fc_bar, p_bar, pos_bar, mom_bar
     int bead_work_n = 0;
-    float *fbar = nullptr;            // [3][N] adjoint of the spread force (zero outside touched nodes)
+    float *fbar = nullptr;            // [2][3][N] adjoint of the spread force by step parity (zero outside touched nodes)
+    long long *force2 = nullptr;      // the reverse sweep's second force field and bitmap (step parity)
+    uint32_t *fmask2 = nullptr;
     std::string err;
 };
 
@@ -1004,7 +1006,8 @@ int lb_destroy(lb_ctx *c)
     for (int k = 0; k < 2; ++k)
         if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
     free_tape(c);
-    void *adj[] = {c->seg, c->lamA, c->lamB, c->gbar_d, c->adj_partials, c->tape_bead, c->bead_work, c->fbar};
+    void *adj[] = {c->seg,       c->lamA, c->lamB,   c->gbar_d, c->adj_partials, c->tape_bead,
+                   c->bead_work, c->fbar, c->force2, c->fmask2};
     for (void *q : adj)
         if (q) (void)hipFree(q);
     if (c->batch) {
@@ -1388,9 +1391,16 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             c->bead_work_n = nbd;
         }
         if (!c->fbar) {
-            if (hipMalloc(&c->fbar, 3 * N * sizeof(float)) != hipSuccess)
+            const size_t nwords = (N + 31) / 32;
+            if (hipMalloc(&c->fbar, 6 * N * sizeof(float)) != hipSuccess ||
+                hipMalloc(&c->force2, 3 * N * sizeof(long long)) != hipSuccess ||
+                hipMalloc(&c->fmask2, nwords * sizeof(uint32_t)) != hipSuccess)
                 return fail(c, LB_ENOMEM, "force adjoint allocation failed");
-            hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->fbar, 3 * N);
+            hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->fbar, 6 * N);
+            hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->force2),
+                               6 * N);
+            hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nwords, 256)), dim3(256), 0, c->stream,
+                               reinterpret_cast<int32_t *>(c->fmask2), (uint32_t)nwords);
         }
         const size_t n3 = 3 * (size_t)nbd;
         half_bar = c->bead_work;
@@ -1424,11 +1434,29 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                        reinterpret_cast<float *>(c->adj_partials), 6 * (size_t)nb);
     LB_LAUNCH_CHECK(c, "backward set-up");
 
-    // put the spread force of taped coupled step `slot` back into the (zero) field
-    auto respread = [&](int slot) {
-        const TapeSlot ts = tape_slot_at(c, slot);
+    // Put the spread force of taped step t (coupled) back into a (zero) field.
+    auto respread = [&](uint64_t t, long long *force, uint32_t *fmask) {
+        const TapeSlot ts = tape_slot_at(c, c->tape_slot[t]);
         hipLaunchKernelGGL(k_respread, dim3(grid_for((size_t)ts.entries, 256)), dim3(256), 0, c->stream, ts.contrib,
-                           ts.entries, c->geo.N, c->force, c->fmask);
+                           ts.entries, c->geo.N, force, fmask);
+    };
+    auto coupled_at = [&](uint64_t t) { return c->tape_slot[t] >= 0; };
+    // The reverse sweep alternates two force fields and two fbar halves by
+    // the parity of the tape index, so that the extra blocks of each adjoint
+    // step can put the next step's force back and clear the fbar of the
+    // coupled step before it while the step reads its own.  A coupled step's
+    // particle adjoint is finished late: its bond Jacobians run in those extra
+    // blocks, its pair Jacobians after that kernel, and R'bar -> (Rbar, Pbar)
+    // inside the next coupled step's k_bead_adjoint (or k_bead_adjoint_finish
+    // after the last one).
+    long long *const fpar[2] = {c->force, c->force2};
+    uint32_t *const mpar[2] = {c->fmask, c->fmask2};
+    float *const fbpar[2] = {c->fbar, c->fbar ? c->fbar + 3 * N : nullptr};
+    int64_t pending = -1;  // tape index of the coupled step whose particle adjoint is not finished
+    bool pending_jac = false;  // ... and whose bond and pair Jacobians are still to come
+    auto pair_jacobians = [&](int64_t t) {
+        const lb_beads &bp = c->tape_beads[c->tape_slot[t]];
+        if (bp.wca_epsilon > 0.0) launch_wca_adjoint(c, &bp, tape_slot_at(c, c->tape_slot[t]).half, fc_bar, half_bar);
     };
 
     const unsigned saved_blocks = c->nblocks;
@@ -1444,22 +1472,28 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         rc = check(c, hipMemcpyAsync(seg, c->checkpoints[sg], sb, hipMemcpyDeviceToDevice, c->stream),
                    "checkpoint restore");
         if (rc != LB_OK) break;
+        // recompute steps 0 .. len-2 of the segment (first force field)
         for (int k = 0; k + 1 < len; ++k) {
-            const uint32_t step = (uint32_t)(c->tape_step0 + t0 + k);
-            const int slot = c->tape_slot[t0 + k];
+            const uint64_t t = t0 + k;
+            const uint32_t step = (uint32_t)(c->tape_step0 + t);
             StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb, step);
-            if (slot >= 0) {
-                respread(slot);
+            const bool frc = coupled_at(t);
+            if (frc) {
+                respread(t, c->force, c->fmask);
                 a.fmask = c->fmask;
                 a.force = c->force;
                 a.consume = 1u;
             }
-            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, slot >= 0); });
+            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, frc); });
         }
         if ((rc = hipGetLastError() == hipSuccess ? LB_OK : fail(c, LB_EDEVICE, "backward recompute")) != LB_OK) break;
+        // adjoint steps len-1 .. 0
+        if (coupled_at(t0 + len - 1)) respread(t0 + len - 1, fpar[(t0 + len - 1) & 1u], mpar[(t0 + len - 1) & 1u]);
         for (int k = len - 1; k >= 0; --k) {
-            const uint32_t step = (uint32_t)(c->tape_step0 + t0 + k);
-            const int slot = c->tape_slot[t0 + k];
+            const uint64_t t = t0 + k;
+            const int q = (int)(t & 1u);
+            const uint32_t step = (uint32_t)(c->tape_step0 + t);
+            const int slot = c->tape_slot[t];
             const void *pop = seg + (size_t)k * sb;
             AdjArgs aa;
             aa.state = pop;
@@ -1469,18 +1503,47 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             aa.cc = c->cc;
             aa.step = step;
             aa.partials = c->adj_partials;
-            aa.force = c->force;
-            aa.fmask = c->fmask;
-            aa.fbar = c->fbar;
-            if (slot >= 0) respread(slot);
+            aa.force = fpar[q];
+            aa.fmask = mpar[q];
+            aa.fbar = fbpar[q];
+            aa.main_blocks = nb;
+            AdjSide &sd = aa.side;
+            sd = AdjSide{};
+            if (k >= 1 && coupled_at(t - 1)) {
+                const TapeSlot tn = tape_slot_at(c, c->tape_slot[t - 1]);
+                sd.put_contrib = tn.contrib;
+                sd.put_entries = tn.entries;
+                sd.put_force = fpar[(t - 1) & 1u];
+                sd.put_fmask = mpar[(t - 1) & 1u];
+            }
+            if (pending >= 0 && pending_jac) {
+                const lb_beads &bp = c->tape_beads[c->tape_slot[pending]];
+                const TapeSlot tp = tape_slot_at(c, c->tape_slot[pending]);
+                sd.half = tp.half;
+                sd.fc_bar = fc_bar;
+                sd.half_bar = half_bar;
+                sd.bonds = bp.bonds;
+                sd.nbonds = bp.nbonds;
+                sd.nbeads = nbd;
+                sd.fene = (int)(bp.bond == LB_BOND_FENE);
+                sd.kb = bp.k_bond;
+                sd.r0 = bp.r0;
+                sd.clear_fbar = fbpar[pending & 1];
+                sd.clear_contrib = tp.contrib;
+                sd.clear_entries = tp.entries;
+            }
+            const int side_jobs = std::max({sd.put_entries, sd.nbonds, sd.clear_entries});
+            const unsigned grid = nb + (side_jobs > 0 ? grid_for((size_t)side_jobs, 256) : 0u);
             by_storage(c->p.storage, [&](auto st) {
                 constexpr int ST = decltype(st)::value;
                 auto go = [&](auto th, auto frc) {
                     constexpr bool TH = decltype(th)::value, FRC = decltype(frc)::value;
                     if (c->geo.walls)
-                        hipLaunchKernelGGL((k_adjoint_step<ST, TH, FRC, true>), dim3(nb), dim3(256), 0, c->stream, aa);
+                        hipLaunchKernelGGL((k_adjoint_step<ST, TH, FRC, true>), dim3(grid), dim3(256), 0, c->stream,
+                                           aa);
                     else
-                        hipLaunchKernelGGL((k_adjoint_step<ST, TH, FRC, false>), dim3(nb), dim3(256), 0, c->stream, aa);
+                        hipLaunchKernelGGL((k_adjoint_step<ST, TH, FRC, false>), dim3(grid), dim3(256), 0, c->stream,
+                                           aa);
                 };
                 using T_ = std::true_type;
                 using F_ = std::false_type;
@@ -1492,6 +1555,10 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                     else go(F_{}, F_{});
                 }
             });
+            if (pending >= 0 && pending_jac) {
+                pair_jacobians(pending);
+                pending_jac = false;
+            }
             if (slot >= 0) {
                 const lb_beads &bc = c->tape_beads[slot];
                 const TapeSlot ts = tape_slot_at(c, slot);
@@ -1499,7 +1566,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 ba.pop = pop;
                 ba.geo = c->geo;
                 ba.rho0 = c->p.rho0;
-                for (int q = 0; q < 3; ++q) ba.g[q] = c->p.body_force[q];
+                for (int r = 0; r < 3; ++r) ba.g[r] = c->p.body_force[r];
                 ba.n = nbd;
                 ba.mom0 = ts.mom0;
                 ba.mom1 = ts.momn;
@@ -1507,7 +1574,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 ba.zeta = bc.zeta;
                 ba.half = ts.half;
                 ba.fc = ts.fc;
-                ba.fbar = c->fbar;
+                ba.fbar = fbpar[q];
                 ba.pos_bar = pos_bar;
                 ba.mom_bar = mom_bar;
                 ba.half_bar = half_bar;
@@ -1515,6 +1582,15 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 ba.p_bar = p_bar;
                 ba.lam = c->lamB;
                 ba.gbar = c->gbar_d;
+                ba.fold = pending >= 0 ? 1 : 0;
+                ba.fold_mass = nullptr;
+                ba.fold_cell_head = nullptr;
+                ba.fold_cell_of = c->cell_of;
+                if (pending >= 0) {
+                    const lb_beads &bp = c->tape_beads[c->tape_slot[pending]];
+                    ba.fold_mass = bp.mass;
+                    ba.fold_cell_head = bp.wca_epsilon > 0.0 ? c->cell_head : nullptr;
+                }
                 by_storage(c->p.storage, [&](auto st) {
                     constexpr int ST = decltype(st)::value;
                     by_stencil(bc.stencil, [&](auto w) {
@@ -1525,21 +1601,29 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                                            c->stream, ba);
                     });
                 });
-                if (bc.nbonds > 0)
-                    hipLaunchKernelGGL(k_bonds_adjoint, dim3(grid_for((size_t)bc.nbonds, 256)), dim3(256), 0, c->stream,
-                                       ba.half, fc_bar, half_bar, bc.bonds, bc.nbonds, bc.k_bond, bc.r0, nbd,
-                                       (int)(bc.bond == LB_BOND_FENE));
-                if (bc.wca_epsilon > 0.0) launch_wca_adjoint(c, &bc, ba.half, fc_bar, half_bar);
-                // (the adjoint step consumed the force and its bitmap; the
-                // finishing kernel clears fbar at the step's nodes)
-                hipLaunchKernelGGL(k_bead_adjoint_finish,
-                                   dim3(grid_for(std::max<size_t>((size_t)nbd, (size_t)ts.entries), 256)), dim3(256),
-                                   0, c->stream, nbd, bc.mass, half_bar, p_bar, pos_bar, mom_bar, c->fbar, ts.contrib,
-                                   ts.entries, c->geo.N, bc.wca_epsilon > 0.0 ? c->cell_head : nullptr, c->cell_of);
+                pending = (int64_t)t;
+                pending_jac = true;
             }
             std::swap(c->lamA, c->lamB);
         }
         if (hipGetLastError() != hipSuccess) rc = fail(c, LB_EDEVICE, "adjoint step");
+    }
+    if (rc == LB_OK && pending >= 0) {
+        // the earliest coupled step: bond and pair Jacobians, then the finish
+        const lb_beads &bp = c->tape_beads[c->tape_slot[pending]];
+        const TapeSlot tp = tape_slot_at(c, c->tape_slot[pending]);
+        if (pending_jac) {
+            if (bp.nbonds > 0)
+                hipLaunchKernelGGL(k_bonds_adjoint, dim3(grid_for((size_t)bp.nbonds, 256)), dim3(256), 0, c->stream,
+                                   tp.half, fc_bar, half_bar, bp.bonds, bp.nbonds, bp.k_bond, bp.r0, nbd,
+                                   (int)(bp.bond == LB_BOND_FENE));
+            pair_jacobians(pending);
+        }
+        hipLaunchKernelGGL(k_bead_adjoint_finish, dim3(grid_for(std::max<size_t>((size_t)nbd, (size_t)tp.entries), 256)),
+                           dim3(256), 0, c->stream, nbd, bp.mass, half_bar, p_bar, pos_bar, mom_bar,
+                           fbpar[pending & 1], tp.contrib, tp.entries, c->geo.N,
+                           bp.wca_epsilon > 0.0 ? c->cell_head : nullptr, c->cell_of);
+        if (hipGetLastError() != hipSuccess) rc = fail(c, LB_EDEVICE, "bead adjoint");
     }
     c->block = saved_block;
     c->nblocks = (int)saved_blocks;
