@@ -143,11 +143,13 @@ def oracle_mixed_backward(orc, po, n0, ob, T, plain_steps, w, a, b):
     return lam, gbar, pb, mb
 
 
-def test_gpu_mixed_tape_matches_oracle(orc, lat):
-    """Coupled and plain steps interleaved (plain steps keep the bead state)."""
+@pytest.mark.parametrize("T,K,plain", [(9, 4, (3, 4, 7)), (7, 3, (0, 3, 6)), (6, 2, (1, 2, 3, 4))])
+def test_gpu_mixed_tape_matches_oracle(orc, lat, T, K, plain):
+    """Coupled and plain steps interleaved (plain steps keep the bead state):
+    plain steps inside and at both ends of segments, runs of plain steps
+    between two coupled ones, a plain first and last step."""
     rng = np.random.default_rng(1)
     po, pd, n0, ob, db = system(orc, lat, rng, kT=1e-4, seed=9, g=(5e-5, 0.0, -2e-5))
-    T, K, plain = 9, 4, (3, 4, 7)
     w = rng.normal(size=n0.shape)
     a, b = rng.normal(size=(ob.pos.shape[0], 3)), rng.normal(size=(ob.pos.shape[0], 3))
     n0r, (dn0, dg, dR0, dP0) = run_gpu(lat, pd, n0, db, T, K, w, a, b, plain_steps=plain)
