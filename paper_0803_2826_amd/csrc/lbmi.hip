@@ -318,10 +318,19 @@ int ensure_bead_buffers(lb_ctx *c, int n)
 {
     const size_t N = c->geo.N;
     const size_t nwords = (N + 31) / 32;
-    if (!c->force) {
+    if (!c->force || !c->fmask) {
+        auto release = [&]() {
+            (void)hipFree(c->force);
+            (void)hipFree(c->fmask);
+            c->force = nullptr;
+            c->fmask = nullptr;
+        };
+        release();
         if (hipMalloc(&c->force, 3 * N * sizeof(long long)) != hipSuccess ||
-            hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess)
+            hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess) {
+            release();
             return fail(c, LB_ENOMEM, "bead force field allocation failed");
+        }
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->force),
                            6 * N);
         hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nwords, 256)), dim3(256), 0, c->stream,
@@ -1373,11 +1382,22 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         c->seg_bytes = (size_t)K * sb;
     }
     const unsigned nb = grid_for(N, 256);
-    if (!c->lamA) {
+    if (!c->lamA || !c->lamB || !c->gbar_d || !c->adj_partials) {
+        auto release = [&]() {
+            (void)hipFree(c->lamA);
+            (void)hipFree(c->lamB);
+            (void)hipFree(c->gbar_d);
+            (void)hipFree(c->adj_partials);
+            c->lamA = c->lamB = nullptr;
+            c->gbar_d = c->adj_partials = nullptr;
+        };
+        release();
         if (hipMalloc(&c->lamA, n19 * sizeof(float)) != hipSuccess || hipMalloc(&c->lamB, n19 * sizeof(float)) != hipSuccess ||
             hipMalloc(&c->gbar_d, 3 * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double)) != hipSuccess)
+            hipMalloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double)) != hipSuccess) {
+            release();
             return fail(c, LB_ENOMEM, "adjoint buffers allocation failed");
+        }
     }
     double *half_bar = nullptr, *fc_bar = nullptr, *p_bar = nullptr;
     double *pos_bar = nullptr, *mom_bar = nullptr;
@@ -1390,12 +1410,23 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 return fail(c, LB_ENOMEM, "bead adjoint buffers allocation failed");
             c->bead_work_n = nbd;
         }
-        if (!c->fbar) {
+        if (!c->fbar || !c->force2 || !c->fmask2) {
             const size_t nwords = (N + 31) / 32;
+            auto release = [&]() {
+                (void)hipFree(c->fbar);
+                (void)hipFree(c->force2);
+                (void)hipFree(c->fmask2);
+                c->fbar = nullptr;
+                c->force2 = nullptr;
+                c->fmask2 = nullptr;
+            };
+            release();
             if (hipMalloc(&c->fbar, 6 * N * sizeof(float)) != hipSuccess ||
                 hipMalloc(&c->force2, 3 * N * sizeof(long long)) != hipSuccess ||
-                hipMalloc(&c->fmask2, nwords * sizeof(uint32_t)) != hipSuccess)
+                hipMalloc(&c->fmask2, nwords * sizeof(uint32_t)) != hipSuccess) {
+                release();
                 return fail(c, LB_ENOMEM, "force adjoint allocation failed");
+            }
             hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->fbar, 6 * N);
             hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->force2),
                                6 * N);
