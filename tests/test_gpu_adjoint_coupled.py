@@ -348,3 +348,40 @@ def test_full_size_coupled_directional_derivative(orc, lat):
     got = (dR0 * vR).sum() + (dP0 * vP).sum()
     print(f"bead direction: gpu {got:.10e} fd {fd:.10e}")
     assert got == pytest.approx(fd, rel=1e-4)
+
+
+def test_full_size_hundred_steps_two_segments(orc, lat):
+    """The differentiation workload over 100 coupled steps with its own
+    checkpoint interval (K = 50: two segments, so the checkpoint restore and
+    the recompute sweep run at full size): the directional derivative of the
+    linear loss along one direction in (n(0), g, R(0), P(0)) at once, from
+    lb_backward_coupled, against a central difference (eps = 1e-4) of the
+    FP64 oracle forward."""
+    import dataclasses
+    rng = np.random.default_rng(8)
+    L, T, K = 128, 100, 50
+    po, pd, n0, ob, db = system(orc, lat, rng, dims=(L, L, L), chains=16, length=32, kT=1e-4, seed=2,
+                                g=(1e-5, 0.0, 0.0))
+    w = rng.normal(size=n0.shape)
+    nb = ob.pos.shape[0]
+    a, b = rng.normal(size=(nb, 3)), rng.normal(size=(nb, 3))
+    n0r, (dn0, dg, dR0, dP0) = run_gpu(lat, pd, n0, db, T, K, w, a, b)
+    eps = 1e-4
+    vn = rng.normal(size=n0.shape) * 1e-3
+    vg = rng.normal(size=3) * 1e-6
+    vR, vP = rng.normal(size=(nb, 3)) * 1e-5, rng.normal(size=(nb, 3)) * 1e-3
+
+    def fwd(sign):
+        p = dataclasses.replace(po, g=tuple(np.asarray(po.g) + sign * eps * vg))
+        n = n0r + sign * eps * vn
+        bb = ob.copy()
+        bb.pos = ob.pos + sign * eps * vR
+        bb.mom = ob.mom + sign * eps * vP
+        for t in range(T):
+            orc.coupled_step(p, n, t, bb)
+        return (w * n).sum() + (a * bb.pos).sum() + (b * bb.mom).sum()
+
+    fd = (fwd(1.0) - fwd(-1.0)) / (2 * eps)
+    got = (dn0 * vn).sum() + (np.asarray(dg) * vg).sum() + (dR0 * vR).sum() + (dP0 * vP).sum()
+    print(f"100 steps, K = 50: gpu {got:.10e} fd {fd:.10e} rel {abs(got - fd) / abs(fd):.2e}", flush=True)
+    assert got == pytest.approx(fd, rel=1e-4)
