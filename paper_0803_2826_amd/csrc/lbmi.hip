@@ -390,10 +390,9 @@ void free_tape(lb_ctx *c)
 }
 
 // Cell grid of the WCA pair search for n beads: cells no narrower than
-// r_c, at most about 512 n cells and 128 per axis (rebuilding the list costs
-// a few passes over the cells; dilute chains cluster, so cells much wider
-// than r_c would give long candidate lists), an axis with fewer than 3
-// cells folded into one.
+// r_c, at most about 512 n cells and 128 per axis (the heads cost 4 bytes
+// per cell; dilute chains cluster, so cells much wider than r_c would give
+// long candidate lists), an axis with fewer than 3 cells folded into one.
 CellGrid cell_grid(const lb_ctx *c, const lb_beads *b)
 {
     CellGrid cg;
