@@ -390,7 +390,7 @@ def main() -> int:
             traffic = tr.get("traffic_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_stream_collide<f32,thermal,totals,force>", "kernel_ms": round(kern_ms, 5),
+                "kernel": "k_stream_collide<f32,thermal,totals,force,full relaxation>", "kernel_ms": round(kern_ms, 5),
                 "alg_bytes_per_launch": alg_bytes,
                 "launch": {"threads": cfg[0], "blocks": cfg[1], "xcd_map": cfg[3]}}
     lat.close()

@@ -57,7 +57,11 @@ struct CollideConst {
 
 // d[19]: shifted pre-collision populations (in), out[19]: shifted
 // post-collision populations.  F: total force density at the site.
-template <bool THERMAL>
+// FULL: every non-conserved gamma_k is 0 (complete relaxation, tau = 1 for
+// the stress modes and the kinetic modes fully relaxed), so m*_k =
+// m^eq_k + S_k/2 (+ noise) and the moments m_4..m_18 of the input are never
+// needed; the result equals the general expressions at gamma = 0.
+template <bool THERMAL, bool FULL = false>
 __device__ __forceinline__ void collide_site(const float d[19], const float F[3], const CollideConst &cc,
                                              uint32_t site, uint32_t step, float out[19])
 {
@@ -130,11 +134,18 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     ms[1] = m[1] + F[0];
     ms[2] = m[2] + F[1];
     ms[3] = m[3] + F[2];
+    if constexpr (FULL) {
 #pragma unroll
-    for (int k = 4; k <= 9; ++k)
-        ms[k] = meq[k] + cc.gam[k] * (m[k] - meq[k]) + 0.5f * (1.f + cc.gam[k]) * Sf[k];
+        for (int k = 4; k <= 9; ++k) ms[k] = meq[k] + 0.5f * Sf[k];
 #pragma unroll
-    for (int k = 10; k <= 18; ++k) ms[k] = cc.gam[k] * m[k];
+        for (int k = 10; k <= 18; ++k) ms[k] = 0.f;
+    } else {
+#pragma unroll
+        for (int k = 4; k <= 9; ++k)
+            ms[k] = meq[k] + cc.gam[k] * (m[k] - meq[k]) + 0.5f * (1.f + cc.gam[k]) * Sf[k];
+#pragma unroll
+        for (int k = 10; k <= 18; ++k) ms[k] = cc.gam[k] * m[k];
+    }
 
     if (THERMAL) {
         // r_k sqrt(rho_n): the density factor of the amplitude rides on the

@@ -352,7 +352,7 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
 
 // One site of the fused step: gather with pull streaming, collide, store,
 // optionally accumulate the block's totals.
-template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS>
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL>
 __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 {
     using S = Storage<ST>;
@@ -396,7 +396,7 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
             if (a.consume && (s & 31u) == 0u && word != 0u) a.fmask[s >> 5] = 0u;
         }
         float out[Q];
-        collide_site<THERMAL>(d, F, a.cc, s, a.step, out);
+        collide_site<THERMAL, FULL>(d, F, a.cc, s, a.step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Philox4 rw = {0u, 0u, 0u, 0u};
         if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, a.step, a.cc.box, a.cc.key0, a.cc.key1);
@@ -410,10 +410,12 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 // makes it keep 16-20 bytes per lane in scratch memory, whose traffic (about
 // 16 B per site, 10 % of the kernel's own) costs more than the extra wave
 // gains.
-template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS>
+// FULL (thermal only): the complete-relaxation collision (every
+// non-conserved gamma_k = 0).
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL>
 __global__ void __launch_bounds__(1024) k_stream_collide(StepArgs a)
 {
-    stream_collide_site<ST, THERMAL, TOTALS, FORCE, WALLS>(a);
+    stream_collide_site<ST, THERMAL, TOTALS, FORCE, WALLS, FULL>(a);
 }
 
 }  // namespace lbmi

@@ -48,6 +48,7 @@ struct lb_ctx {
     int32_t *flags = nullptr;        // latched device errors
     bool totals_valid = false;       // fused totals of the last step are in `partials`
     bool thermal = false;
+    bool full_relax = false;         // every non-conserved gamma_k is 0
     // bead coupling (allocated on first lb_couple)
     long long *force = nullptr;      // [3][N] fixed point (kForceScale)
     uint32_t *fmask = nullptr;       // [ceil(N/32)] bit per site: bead force present
@@ -225,15 +226,29 @@ void fill_collide_const(lb_ctx *c)
     c->cc.box = (uint32_t)p.box_id;
     c->cc.noise_rho0 = p.noise_rho0 ? 1 : 0;
     c->thermal = p.kT > 0.0;
+    c->full_relax = true;
+    for (int k = 4; k < 19; ++k) c->full_relax = c->full_relax && gam[k] == 0.0;
 }
 
+template <int ST, bool TH, bool TOT, bool FRC, bool FULL>
+void launch_step_w(lb_ctx *c, const StepArgs &a)
+{
+    if (c->geo.walls)
+        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, true, FULL>), dim3(c->nblocks), dim3(c->block), 0,
+                           c->stream, a);
+    else
+        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, false, FULL>), dim3(c->nblocks), dim3(c->block), 0,
+                           c->stream, a);
+}
+
+// The complete-relaxation variant serves thermal runs whose non-conserved
+// rates are all 0 (it saves arithmetic where the 16-bit kernels are bound by
+// it; without noise the step is bound by memory either way).
 template <int ST, bool TH, bool TOT, bool FRC>
 void launch_step_t(lb_ctx *c, const StepArgs &a)
 {
-    if (c->geo.walls)
-        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, true>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
-    else
-        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, false>), dim3(c->nblocks), dim3(c->block), 0, c->stream, a);
+    if (TH && c->full_relax) launch_step_w<ST, TH, TOT, FRC, TH>(c, a);
+    else launch_step_w<ST, TH, TOT, FRC, false>(c, a);
 }
 
 template <int ST, bool TH, bool TOT>
