@@ -75,7 +75,8 @@ __device__ __forceinline__ void flush_amp12(float acc[12], float *dst)
     }
 }
 
-template <int ST, bool THERMAL, bool VACF>
+// FULL: the complete-relaxation collision (every non-conserved gamma_k = 0).
+template <int ST, bool THERMAL, bool VACF, bool FULL>
 __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
 {
     using S = Storage<ST>;
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
         }
         cc.box = d.box_id;
         float out[Q];
-        collide_site<THERMAL>(dd, cc.g, cc, s, step, out);
+        collide_site<THERMAL, FULL>(dd, cc.g, cc, s, step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         void *dstp[Q];
 #pragma unroll

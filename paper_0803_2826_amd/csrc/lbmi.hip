@@ -681,7 +681,10 @@ int batch_build_tiles(lb_ctx *c, int block)
 template <int ST, bool TH, bool VA>
 void batch_launch_t(lb_ctx *c, const BatchArgs &a, unsigned grid)
 {
-    hipLaunchKernelGGL((k_batch_step<ST, TH, VA>), dim3(grid), dim3(c->block), 0, c->stream, a);
+    if (TH && c->full_relax)
+        hipLaunchKernelGGL((k_batch_step<ST, TH, VA, TH>), dim3(grid), dim3(c->block), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_batch_step<ST, TH, VA, false>), dim3(grid), dim3(c->block), 0, c->stream, a);
 }
 
 void batch_launch_step(lb_ctx *c, const void *src, void *dst, bool vacf)
