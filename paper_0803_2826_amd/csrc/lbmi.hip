@@ -1675,7 +1675,14 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     }
     c->block = saved_block;
     c->nblocks = (int)saved_blocks;
-    if (rc != LB_OK) return rc;
+    if (rc != LB_OK) {
+        // a sweep that stopped part way may leave WCA cell heads linked: put
+        // them all back so that the next particle half starts from empty lists
+        if (c->cell_head)
+            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(c->cell_cap, 256)), dim3(256), 0, c->stream,
+                               reinterpret_cast<uint32_t *>(c->cell_head), (uint32_t)c->cell_cap, 0xffffffffu);
+        return rc;
+    }
     hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3, c->gbar_d);
     if (dtype == LB_F64)
         hipLaunchKernelGGL(k_from_f32<double>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
