@@ -78,8 +78,8 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         bool flagged = false;
         if (FORCE) {
-            const uint32_t word = a.fmask[s >> 5];
-            flagged = (word >> (s & 31u)) & 1u;
+            const uint32_t bit = 1u << (s & 31u);
+            flagged = (a.fmask[s >> 5] & bit) != 0u;
             if (flagged) {
                 F[0] += force_value(a.force[s]);
                 F[1] += force_value(a.force[(size_t)N + s]);
@@ -87,10 +87,8 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
                 a.force[s] = 0;
                 a.force[(size_t)N + s] = 0;
                 a.force[2 * (size_t)N + s] = 0;
+                atomicAnd(&a.fmask[s >> 5], ~bit);
             }
-            // one site per block of 64 consecutive sites (one wave) clears a
-            // bitmap word once the wave has loaded it
-            if ((s & 31u) == 0u && word != 0u) a.fmask[s >> 5] = 0u;
         }
         const float rho = a.cc.rho0 + m0;
         const float inv_rho = 1.0f / rho;

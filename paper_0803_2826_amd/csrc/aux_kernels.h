@@ -54,7 +54,7 @@ __global__ void k_init_equilibrium(void *buf, Geom g, double rho0, const double 
         const double usq = ux * ux + uy * uy + uz * uz;
         const double a = weight_of(j);
         const double neq = a * rr * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * usq);
-        b[(size_t)i * g.N + s] = S::st((float)(neq - a * rho0), 0.f);
+        b[pop_index(i, s, z, g)] = S::st((float)(neq - a * rho0), 0.f);
     }
 }
 
@@ -76,7 +76,7 @@ __global__ void k_set_pops(void *buf, Geom g, double rho0, const TIn *__restrict
         const uint32_t r = wall ? s : push_dst(x, y, z, g, i);
         double v = (double)src[(size_t)j * g.N + r];
         if (!shifted) v -= weight_of(j) * rho0;
-        b[(size_t)i * g.N + s] = S::st((float)v, 0.f);
+        b[pop_index(i, s, z, g)] = S::st((float)v, 0.f);
     }
 }
 
@@ -162,8 +162,9 @@ __global__ void __launch_bounds__(256) k_totals_exact(const void *buf, Geom g, d
     const T *b = static_cast<const T *>(buf);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
+        const uint32_t z = fdiv(fdiv(s, g.div_nx), g.div_ny);
         for (int i = 0; i < Q; ++i) {
-            const double v = (double)S::ld(b[(size_t)i * g.N + s], 0.f);
+            const double v = (double)S::ld(b[pop_index(i, s, z, g)], 0.f);
             acc[0] += v;
             acc[1] += v * kCX[i];
             acc[2] += v * kCY[i];

@@ -20,9 +20,10 @@ __global__ void k_copy16(const float4 *__restrict__ src, float4 *__restrict__ ds
     __builtin_nontemporal_store(v.w, &dst[i].w);
 }
 
-// The memory pattern of the LB step without its arithmetic: 19 planes of
-// N = 2^(3 lg) floats, each site pulls plane i from its periodic neighbour
-// r - c_i (D3Q19 velocity set) and stores it non-temporally at r.
+// The memory pattern of the LB step without its arithmetic, in the step's
+// z-major layout ([z][i][y][x], 19 values per site, N = 2^(3 lg) sites):
+// each site pulls population i from its periodic neighbour r - c_i (D3Q19
+// velocity set) and stores it non-temporally at r.
 __constant__ int kPX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 __constant__ int kPY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __constant__ int kPZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -30,24 +31,25 @@ __constant__ int kPZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -
 __global__ void __launch_bounds__(1024) k_pull19(const float *__restrict__ src, float *__restrict__ dst, uint32_t lg)
 {
     const uint32_t m = (1u << lg) - 1u;
-    const size_t N = (size_t)1 << (3 * lg);
+    const size_t layer = (size_t)1 << (2 * lg);
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t x = s & m, y = (s >> lg) & m, z = s >> (2 * lg);
     float v[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const uint32_t xs = (x - kPX[i]) & m, ys = (y - kPY[i]) & m, zs = (z - kPZ[i]) & m;
-        v[i] = src[i * N + (xs + ((ys + (zs << lg)) << lg))];
+        v[i] = src[((size_t)zs * 19 + i) * layer + (xs + (ys << lg))];
     }
 #pragma unroll
-    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(v[i], &dst[i * N + s]);
+    for (int i = 0; i < 19; ++i)
+        __builtin_nontemporal_store(v[i], &dst[((size_t)z * 19 + i) * layer + (x + (y << lg))]);
 }
 
 }  // namespace
 
 extern "C" {
 
-// The pull pattern of one LB step over a cube of edge 2^lg (4 <= lg <= 10):
+// The pull pattern of one LB step (z-major layout) over a cube of edge 2^lg (4 <= lg <= 10):
 // src and dst are device arrays of 19 * 2^(3 lg) floats; `block` threads per
 // block (64..1024, dividing 2^(3 lg)).  Returns 0, -1 for bad arguments, or
 // the HIP error code of the launch.

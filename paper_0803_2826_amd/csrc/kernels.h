@@ -119,7 +119,19 @@ struct Geom {
     uint32_t nx, ny, nz, N, nxny;
     FastDiv div_nx, div_ny;
     uint32_t walls;  // 1: stationary walls at z = -1/2 and z = nz - 1/2
+    uint32_t zmajor; // population layout, see pop_index
 };
+
+// Element index of population i of site s (layer z) in a population buffer.
+// zmajor = 1 (a single box): [z][i][y][x], the 19 planes of one z-layer side
+// by side, so that the 38 streams of a step stay within a few MB of each
+// other (measured faster than [i][z][y][x] for the pull pattern); zmajor = 0
+// (the boxes of a batch): [i][z][y][x].
+__device__ __forceinline__ size_t pop_index(int i, uint32_t s, uint32_t z, const Geom &g)
+{
+    if (g.zmajor) return (size_t)(19u * z + (uint32_t)i) * g.nxny + (s - z * g.nxny);
+    return (size_t)i * g.N + s;
+}
 
 // Neighbour offsets of site s: off[c+1] for c = -1, 0, +1 along each axis is
 // the index offset of the site r - c (pull source) with periodic wrap.
@@ -194,13 +206,21 @@ __device__ __forceinline__ bool push_crosses(const Geom &g, uint32_t z, int i)
     return g.walls && ((kCZ[i] < 0 && z == 0u) || (kCZ[i] > 0 && z + 1u == g.nz));
 }
 
-// Flat index (plane * N + site) of the stored value that population i of
-// site s (layer z) pulls.
+// Layer of the pull source of population i at layer z (periodic).
+__device__ __forceinline__ uint32_t pull_z(uint32_t z, int i, const Geom &g)
+{
+    if (kCZ[i] > 0) return z == 0u ? g.nz - 1u : z - 1u;
+    if (kCZ[i] < 0) return z + 1u == g.nz ? 0u : z + 1u;
+    return z;
+}
+
+// Element index (pop_index) of the stored value that population i of site s
+// (layer z) pulls.
 template <bool WALLS = true>
 __device__ __forceinline__ size_t pull_index(uint32_t s, const PullOffsets &o, int i, uint32_t z, const Geom &g)
 {
-    if (pull_crosses<WALLS>(g, z, i)) return (size_t)opp(i) * g.N + s;
-    return (size_t)i * g.N + pull_src(s, o, i);
+    if (pull_crosses<WALLS>(g, z, i)) return pop_index(opp(i), s, z, g);
+    return pop_index(i, pull_src(s, o, i), pull_z(z, i, g), g);
 }
 
 // Load element idx of population plane `plane` (byte offset arithmetic kept
@@ -243,11 +263,11 @@ __device__ __forceinline__ float force_value(long long q) { return (float)((doub
 
 // Arguments of the fused step kernel.
 struct StepArgs {
-    const void *src;      // buffer A, [19][N]
-    void *dst;            // buffer B, [19][N]
-    const void *srcp[19]; // plane i of A (scalar base of every load)
-    void *dstp[19];       // plane i of B (scalar base of every store)
+    const void *src;      // buffer A (layout pop_index, zmajor)
+    void *dst;            // buffer B
     Geom geo;
+    uint32_t tiles;       // blocks per z-layer: ceil(nxny / blockDim)
+    FastDiv div_tiles;
     CollideConst cc;
     uint32_t step;
     uint32_t xcd_remap;   // 1: map blocks so that consecutive tiles share an XCD
@@ -351,56 +371,77 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
 }
 
 // One site of the fused step: gather with pull streaming, collide, store,
-// optionally accumulate the block's totals.
+// optionally accumulate the block's totals.  Blocks are dealt out layer by
+// layer (block b: layer z = b / tiles, in-layer sites r = (b - z tiles)
+// blockDim + thread), so the base of every plane a block loads from or
+// stores to is uniform over the block (the buffers are z-major, pop_index).
 template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL>
 __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
-    const uint32_t s = tile_index(a.xcd_remap) * blockDim.x + threadIdx.x;
-    const bool active = s < a.geo.N;
+    const uint32_t b = tile_index(a.xcd_remap);
+    const uint32_t z = fdiv(b, a.div_tiles);
+    const uint32_t nxny = a.geo.nxny;
+    const uint32_t r = (b - z * a.tiles) * blockDim.x + threadIdx.x;
+    const bool active = r < nxny;
+    const uint32_t s = z * nxny + r;
+    const size_t plane = (size_t)nxny * sizeof(T);
+    const char *src = static_cast<const char *>(a.src);
+    char *dst = static_cast<char *>(a.dst);
     double mass = 0.0;
     float mom[3] = {0.f, 0.f, 0.f};
     if (active) {
-        uint32_t x, y, z;
-        const PullOffsets o = pull_offsets(s, a.geo, x, y, z);
+        uint32_t x, y, zs;
+        const PullOffsets o = pull_offsets(s, a.geo, x, y, zs);
+        PullOffsets oxy = o;  // in-layer part of each pull; the layer picks the plane base
+        oxy.oz_m = 0;
+        oxy.oz_p = 0;
         const uint32_t N = a.geo.N;
         float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = S::ld(ld_plane(static_cast<const T *>(a.srcp[i]), pull_src(s, o, i)), 0.f);
+        for (int i = 0; i < Q; ++i) {
+            const T *base = reinterpret_cast<const T *>(src + (size_t)(19u * pull_z(z, i, a.geo) + (uint32_t)i) * plane);
+            d[i] = S::ld(ld_plane(base, pull_src(r, oxy, i)), 0.f);
+        }
         if constexpr (WALLS) {
             if (z == 0u || z + 1u == a.geo.nz) {
                 // wall layers: the populations coming off a wall are the reversed ones of this site
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
-                    if (pull_crosses(a.geo, z, i)) d[i] = S::ld(ld_plane(static_cast<const T *>(a.srcp[opp(i)]), s), 0.f);
+                    if (pull_crosses(a.geo, z, i))
+                        d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(src + (size_t)(19u * z + (uint32_t)opp(i)) * plane),
+                                              r),
+                                     0.f);
             }
         }
         const mass_acc_t<ST> m_in = site_mass<ST>(d);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         if (FORCE) {
-            const uint32_t word = a.fmask[s >> 5];
-            if ((word >> (s & 31u)) & 1u) {
+            const uint32_t bit = 1u << (s & 31u);
+            if (a.fmask[s >> 5] & bit) {
                 F[0] += force_value(a.force[s]);
                 F[1] += force_value(a.force[(size_t)N + s]);
                 F[2] += force_value(a.force[2 * (size_t)N + s]);
                 if (a.consume) {
+                    // leave the field and this site's bit zero (the other
+                    // sites of the word have read or will read their own bits)
                     a.force[s] = 0;
                     a.force[(size_t)N + s] = 0;
                     a.force[2 * (size_t)N + s] = 0;
+                    atomicAnd(&a.fmask[s >> 5], ~bit);
                 }
             }
-            // The 32 sites of a bitmap word lie in one wave (waves start at
-            // multiples of 64 sites) and read the word with one instruction;
-            // its first site clears it once the loaded value is known.
-            if (a.consume && (s & 31u) == 0u && word != 0u) a.fmask[s >> 5] = 0u;
         }
         float out[Q];
         collide_site<THERMAL, FULL>(d, F, a.cc, s, a.step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Philox4 rw = {0u, 0u, 0u, 0u};
         if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, a.step, a.cc.box, a.cc.key0, a.cc.key1);
-        store_site<ST, TOTALS>(a.dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
+        void *dstp[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dstp[i] = dst + (size_t)(19u * z + (uint32_t)i) * plane;
+        store_site<ST, TOTALS>(dstp, (uint32_t)plane, r, m_in, out, mass, mom, rw);
     }
     if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)blockIdx.x, mass, mom);
 }

@@ -165,6 +165,13 @@ size_t storage_bytes(int st)
 
 unsigned grid_for(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Blocks of a single-box step launch: every z-layer is cut into
+// ceil(nxny / block) tiles (a layer's last tile may be partial).
+unsigned step_blocks(const lb_ctx *c, int block)
+{
+    return c->geo.nz * (unsigned)((c->geo.nxny + (uint32_t)block - 1u) / (uint32_t)block);
+}
+
 int validate(const lb_params *p, std::string &msg)
 {
     if (!p) { msg = "params is NULL"; return LB_EINVAL; }
@@ -613,11 +620,9 @@ StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
     StepArgs a;
     a.src = src;
     a.dst = dst;
-    for (int i = 0; i < 19; ++i) {
-        a.srcp[i] = static_cast<const char *>(src) + (size_t)i * c->geo.N * c->elem;
-        a.dstp[i] = static_cast<char *>(dst) + (size_t)i * c->geo.N * c->elem;
-    }
     a.geo = c->geo;
+    a.tiles = (c->geo.nxny + (uint32_t)c->block - 1u) / (uint32_t)c->block;
+    a.div_tiles = make_fastdiv(a.tiles);
     a.cc = c->cc;
     a.step = step;
     a.xcd_remap = c->xcd_remap;
@@ -801,7 +806,7 @@ int autotune_single(lb_ctx *c, bool frc)
     for (int cand = 0; cand < 10; ++cand) {
         c->block = blocks[cand >> 1];
         c->xcd_remap = (uint32_t)(cand & 1);
-        c->nblocks = (int)grid_for(c->geo.N, c->block);
+        c->nblocks = (int)step_blocks(c, c->block);
         StepArgs a = plain_step_args(c, c->bufA, c->bufB, (uint32_t)c->step);
         if (frc) {
             a.fmask = c->fmask;
@@ -829,7 +834,7 @@ int select_launch(lb_ctx *c, bool frc)
     if (c->search && !c->tuned_f[k]) LB_TRY(autotune_single(c, frc));
     c->block = c->block_f[k];
     c->xcd_remap = c->remap_f[k];
-    c->nblocks = (int)grid_for(c->geo.N, c->block);
+    c->nblocks = (int)step_blocks(c, c->block);
     return LB_OK;
 }
 
@@ -898,16 +903,19 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     c->geo.div_nx = make_fastdiv(nx);
     c->geo.div_ny = make_fastdiv(ny);
     c->geo.walls = (uint32_t)params->walls;
+    c->geo.zmajor = 1u;
     c->elem = storage_bytes(params->storage);
     c->block = params->block > 0 ? params->block : 256;
     c->tuned = true;
     c->search = params->block == -1;
     c->block_f[0] = c->block_f[1] = c->block;
-    c->nblocks = (int)grid_for(c->geo.N, c->block);
+    c->nblocks = (int)step_blocks(c, c->block);
     fill_collide_const(c);
     const size_t bytes = (size_t)19 * c->geo.N * c->elem;
+    // per-block totals rows: the most blocks any block size gives (64 threads)
+    const size_t rows = std::max<size_t>(grid_for(c->geo.N, 64), step_blocks(c, 64));
     if (hipMalloc(&c->bufA, bytes) != hipSuccess || hipMalloc(&c->bufB, bytes) != hipSuccess ||
-        hipMalloc(&c->partials, (size_t)grid_for(c->geo.N, 64) * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->partials, rows * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->dev_out, 64 * sizeof(double)) != hipSuccess || hipMalloc(&c->flags, sizeof(int32_t)) != hipSuccess) {
         lb_destroy(c);
         return fail(nullptr, LB_ENOMEM, "device allocation failed");
@@ -1510,7 +1518,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     const unsigned saved_blocks = c->nblocks;
     const int saved_block = c->block;
     c->block = 256;
-    c->nblocks = (int)nb;
+    c->nblocks = (int)step_blocks(c, 256);
     const int nseg = (int)((T + K - 1) / K);
     int rc = LB_OK;
     for (int sg = nseg - 1; sg >= 0 && rc == LB_OK; --sg) {
@@ -1792,6 +1800,8 @@ struct SaveHeader {
     uint64_t total_sites;
 };
 static const char kSaveMagic[8] = {'L', 'B', 'M', 'I', 'C', 'K', 'P', '1'};
+// version 2: single-box populations in the z-major layout (pop_index)
+static const uint32_t kSaveVersion = 2;
 
 static void ctx_dims(const lb_ctx *c, std::vector<int32_t> &dims)
 {
@@ -1819,7 +1829,7 @@ int lb_save(lb_ctx *c, const char *path)
     ctx_dims(c, dims);
     SaveHeader h{};
     std::memcpy(h.magic, kSaveMagic, 8);
-    h.version = 1;
+    h.version = kSaveVersion;
     h.header_bytes = (uint32_t)sizeof(SaveHeader);
     h.params = c->p;
     h.nbox = c->batch ? c->nbox : 1;
@@ -1858,7 +1868,7 @@ int lb_load(lb_ctx *c, const char *path)
     const size_t bytes = (size_t)19 * ctx_sites(c) * c->elem;
     std::vector<char> host;
     std::string why;
-    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1 ||
+    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != kSaveVersion ||
         h.header_bytes != sizeof(SaveHeader)) {
         why = "not a checkpoint of this library";
     } else if (h.nbox != (c->batch ? c->nbox : 1) || h.params.storage != c->p.storage || h.elem != (int32_t)c->elem ||
