@@ -16,7 +16,9 @@
  *     (+,+,0),(-,-,0),(+,-,0),(-,+,0),(+,0,+),(-,0,-),(+,0,-),(-,0,+),
  *     (0,+,+),(0,-,-),(0,+,-),(0,-,+).  Opposite directions are adjacent.
  *   - Site index s = x + nx*(y + ny*z); population arrays are [19][N]
- *     (structure of arrays), vector fields are [3][N].
+ *     (structure of arrays), vector fields are [3][N].  (The library's own
+ *     state buffers use a layout of their own; every entry point takes and
+ *     returns this one.)
  *   - "The state" is the pre-collision population n_i(r,t) of eq. LBE.
  *     One step is collision at every site followed by streaming
  *     n_i(r + c_i, t+1) = n*_i(r, t).
