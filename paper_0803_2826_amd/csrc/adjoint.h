@@ -27,8 +27,8 @@ namespace lbmi {
 
 struct AdjArgs {
     const void *state;      // step buffer A_t (AB layout: pre-collision n_t(r) = A_t,i(r - c_i))
-    const float *lam_in;    // lambda(t+1), natural layout [19][N]
-    float *lam_out;         // lambda(t), natural layout [19][N]
+    const float *lam_in;    // lambda(t+1), the state's layout (pop_index)
+    float *lam_out;         // lambda(t), the state's layout
     Geom geo;
     CollideConst cc;
     uint32_t step;
@@ -40,7 +40,11 @@ struct AdjArgs {
     long long *force;       // [3][N] fixed point (kForceScale)
     uint32_t *fmask;        // [ceil(N/32)]
     float *fbar;            // [3][N]
-    // blocks from main_blocks on do the side jobs instead of sites
+    // blocks are dealt out layer by layer as in the forward step: block b <
+    // main_blocks = nz tiles works on layer b / tiles; blocks from
+    // main_blocks on do the side jobs instead of sites
+    uint32_t tiles;
+    FastDiv div_tiles;
     uint32_t main_blocks;
     AdjSide side;
 };
@@ -55,18 +59,34 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         adjoint_side_work(a.side, (int)((blockIdx.x - a.main_blocks) * blockDim.x + threadIdx.x), a.geo.N);
         return;
     }
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = s < a.geo.N;
+    const uint32_t z = fdiv(blockIdx.x, a.div_tiles);
+    const uint32_t nxny = a.geo.nxny;
+    const uint32_t r = (blockIdx.x - z * a.tiles) * blockDim.x + threadIdx.x;
+    const bool active = r < nxny;
+    const uint32_t s = z * nxny + r;
     float Fbs[3] = {0.f, 0.f, 0.f};
     if (active) {
-        uint32_t x, y, z;
-        const PullOffsets o = pull_offsets(s, a.geo, x, y, z);
+        uint32_t x, y, zs;
+        const PullOffsets o = pull_offsets(s, a.geo, x, y, zs);
+        PullOffsets oxy = o;  // in-layer part of each pull; the layer picks the plane base
+        oxy.oz_m = 0;
+        oxy.oz_p = 0;
         const uint32_t N = a.geo.N;
-        const T *st = static_cast<const T *>(a.state);
+        const size_t plane = (size_t)nxny * sizeof(T);
+        const char *st = static_cast<const char *>(a.state);
         // forward hydrodynamic fields of n(r, t)
         float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = S::ld(st[pull_index<WALLS>(s, o, i, z, a.geo)], 0.f);
+        for (int i = 0; i < Q; ++i) {
+            if (pull_crosses<WALLS>(a.geo, z, i))  // pull source beyond a wall: opp(i) of this site
+                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(19u * z + (uint32_t)opp(i)) * plane), r),
+                             0.f);
+            else
+                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(19u * pull_z(z, i, a.geo) + (uint32_t)i) *
+                                                                           plane),
+                                      pull_src(r, oxy, i)),
+                             0.f);
+        }
         float m0 = d[0], jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -102,8 +122,11 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         float q[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float lb = push_crosses<WALLS>(a.geo, z, i) ? a.lam_in[(size_t)opp(i) * N + s]
-                                                        : ld_plane(a.lam_in + (size_t)i * N, pull_src(s, o, opp(i)));
+            const size_t lplane = (size_t)nxny;
+            const float lb = push_crosses<WALLS>(a.geo, z, i)
+                                 ? ld_plane(a.lam_in + (size_t)(19u * z + (uint32_t)opp(i)) * lplane, r)
+                                 : ld_plane(a.lam_in + (size_t)(19u * pull_z(z, opp(i), a.geo) + (uint32_t)i) * lplane,
+                                            pull_src(r, oxy, opp(i)));
             q[i] = lb * (i == 0 ? (1.f / 3.f) : (i <= 6 ? (1.f / 18.f) : (1.f / 36.f)));
         }
         // msb_k = (1/w_k) sum_i e_ki (a_i nbar*_i): the moment map applied to q
@@ -226,7 +249,8 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         out[17] = E9 + O9;
         out[18] = E9 - O9;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) st_plane_nt<float>(a.lam_out + (size_t)i * N, N * 4u, s, out[i]);
+        for (int i = 0; i < Q; ++i)
+            st_plane_nt<float>(a.lam_out + (size_t)(19u * z + (uint32_t)i) * nxny, nxny * 4u, r, out[i]);
         if (FORCE && flagged) {
             a.fbar[s] = Fbs[0];
             a.fbar[(size_t)N + s] = Fbs[1];
@@ -269,19 +293,24 @@ __global__ void __launch_bounds__(256) k_accumulate_cols(const double *__restric
     if (threadIdx.x == 0) acc[c] += red[0];
 }
 
-// Natural-layout conversions between the caller's arrays and FP32 adjoints.
+// Conversions between the caller's [19][N] arrays and the FP32 adjoints in
+// the state's layout (pop_index).
 template <typename TIn>
-__global__ void k_to_f32(const TIn *__restrict__ in, float *__restrict__ out, size_t n)
+__global__ void k_to_lam(const TIn *__restrict__ in, float *__restrict__ lam, Geom g)
 {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        out[i] = (float)in[i];
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
+        const uint32_t z = fdiv(fdiv(s, g.div_nx), g.div_ny);
+        for (int i = 0; i < Q; ++i) lam[pop_index(i, s, z, g)] = (float)in[(size_t)i * g.N + s];
+    }
 }
 
 template <typename TOut>
-__global__ void k_from_f32(const float *__restrict__ in, TOut *__restrict__ out, size_t n)
+__global__ void k_from_lam(const float *__restrict__ lam, TOut *__restrict__ out, Geom g)
 {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        out[i] = (TOut)in[i];
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
+        const uint32_t z = fdiv(fdiv(s, g.div_nx), g.div_ny);
+        for (int i = 0; i < Q; ++i) out[(size_t)i * g.N + s] = (TOut)lam[pop_index(i, s, z, g)];
+    }
 }
 
 }  // namespace lbmi

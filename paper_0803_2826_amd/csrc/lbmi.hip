@@ -1406,7 +1406,9 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         if (hipMalloc(&c->seg, (size_t)K * sb) != hipSuccess) return fail(c, LB_ENOMEM, "segment buffer allocation failed");
         c->seg_bytes = (size_t)K * sb;
     }
-    const unsigned nb = grid_for(N, 256);
+    // the adjoint step's blocks, dealt out layer by layer (256 threads)
+    const unsigned nb = step_blocks(c, 256);
+    const uint32_t adj_tiles = (c->geo.nxny + 255u) / 256u;
     if (!c->lamA || !c->lamB || !c->gbar_d || !c->adj_partials) {
         auto release = [&]() {
             (void)hipFree(c->lamA);
@@ -1478,11 +1480,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                                reinterpret_cast<float *>(mom_bar), 2 * n3);
     }
     if (dtype == LB_F64)
-        hipLaunchKernelGGL(k_to_f32<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double *>(dL_dn_T),
-                           c->lamA, n19);
+        hipLaunchKernelGGL(k_to_lam<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double *>(dL_dn_T),
+                           c->lamA, c->geo);
     else
-        hipLaunchKernelGGL(k_to_f32<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float *>(dL_dn_T),
-                           c->lamA, n19);
+        hipLaunchKernelGGL(k_to_lam<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float *>(dL_dn_T),
+                           c->lamA, c->geo);
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<float *>(c->gbar_d), (size_t)6);
     // the adjoint steps add their block sums of dL/dg into adj_partials; one
     // reduction at the end of the sweep
@@ -1562,6 +1564,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             aa.force = fpar[q];
             aa.fmask = mpar[q];
             aa.fbar = fbpar[q];
+            aa.tiles = adj_tiles;
+            aa.div_tiles = make_fastdiv(adj_tiles);
             aa.main_blocks = nb;
             AdjSide &sd = aa.side;
             sd = AdjSide{};
@@ -1693,11 +1697,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     }
     hipLaunchKernelGGL(k_accumulate_cols, dim3(3), dim3(256), 0, c->stream, c->adj_partials, (int)nb, 3, c->gbar_d);
     if (dtype == LB_F64)
-        hipLaunchKernelGGL(k_from_f32<double>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
-                           static_cast<double *>(dL_dn_0), n19);
+        hipLaunchKernelGGL(k_from_lam<double>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
+                           static_cast<double *>(dL_dn_0), c->geo);
     else
-        hipLaunchKernelGGL(k_from_f32<float>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
-                           static_cast<float *>(dL_dn_0), n19);
+        hipLaunchKernelGGL(k_from_lam<float>, dim3(1024), dim3(256), 0, c->stream, c->lamA,
+                           static_cast<float *>(dL_dn_0), c->geo);
     LB_LAUNCH_CHECK(c, "backward output");
     if (coupled) {
         const size_t n3 = 3 * (size_t)nbd;
