@@ -28,8 +28,9 @@ Prints ONE JSON line with, beside the throughput:
                 512^3 box of the precision workload, the batched form (512 replica boxes, edges drawn from
                 {24, 32, 40, 48, 64}, HIP graph replay) and the
                 differentiation form (taped forward and adjoint of 500
-                coupled steps at 128^3 with 16 x 32 beads, checkpoints every
-                50), and the coupled step with Kremer-Grest chains (FENE
+                coupled steps at 128^3 with 16 x 32 beads, the whole tape
+                resident in HBM, 80 GB, and with checkpoints every 50
+                steps), and the coupled step with Kremer-Grest chains (FENE
                 bonds, WCA pairs with a cell list) in place of the harmonic
                 ones.
 """
@@ -238,7 +239,7 @@ def run_forms(L: int) -> dict:
     print("# forms: batch done", file=sys.stderr, flush=True)
     from paper_0803_2826_amd.inputs import random_walk_chains
 
-    Lb, T, K = 128, 500, 50
+    Lb, T = 128, 500
     p = lattice.FluidParams(nx=Lb, ny=Lb, nz=Lb, kT=KT, seed=0, body_force=(1e-5, 0.0, 0.0), track_totals=False)
     lat = lattice.Lattice(p)
     lat.init_equilibrium()
@@ -248,21 +249,27 @@ def run_forms(L: int) -> dict:
     lat.step(2)
     w = torch.randn(19 * Lb ** 3, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    torch.cuda.synchronize()
-    e[0].record(lat.stream)
-    lat.tape_begin(K)
-    for _ in range(T):
-        lat.coupled_step(beads)
-    e[1].record(lat.stream)
-    lat.backward_coupled(w)
-    e[2].record(lat.stream)
-    torch.cuda.synchronize()
+    # K = T: every step buffer stays on the tape (T x 159 MB), nothing is
+    # recomputed; K = 50: checkpoints, one recomputed step per backward step
+    # outside the last segment.  The first tape_begin allocates the buffers.
+    for K, tag in ((T, ""), (50, "_k50")):
+        lat.tape_begin(K)
+        torch.cuda.synchronize()
+        e[0].record(lat.stream)
+        lat.tape_begin(K)
+        for _ in range(T):
+            lat.coupled_step(beads)
+        e[1].record(lat.stream)
+        lat.backward_coupled(w)
+        e[2].record(lat.stream)
+        torch.cuda.synchronize()
+        fwd_ms, bwd_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        out["taped_forward_mlups" + tag] = round(Lb ** 3 * T / (fwd_ms * 1e-3) / 1e6, 1)
+        out["backward_mlups" + tag] = round(Lb ** 3 * T / (bwd_ms * 1e-3) / 1e6, 1)
     lat.close()
-    fwd_ms, bwd_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
-    out["taped_forward_mlups"] = round(Lb ** 3 * T / (fwd_ms * 1e-3) / 1e6, 1)
-    out["backward_mlups"] = round(Lb ** 3 * T / (bwd_ms * 1e-3) / 1e6, 1)
-    out["backward_config"] = (f"{Lb}^3, {T} coupled steps with 16 x 32 beads (zeta 20, k 10 kT), checkpoints every "
-                              f"{K}, FP32 fluid, FP64 beads; gradients w.r.t. n(0), g, R(0), P(0)")
+    out["backward_config"] = (f"{Lb}^3, {T} coupled steps with 16 x 32 beads (zeta 20, k 10 kT), the whole tape "
+                              f"resident (_k50: checkpoints every 50 steps), FP32 fluid, FP64 beads; gradients "
+                              f"w.r.t. n(0), g, R(0), P(0)")
     print("# forms: backward done", file=sys.stderr, flush=True)
 
     # Kremer-Grest chains: the same box and chain count with FENE bonds and

@@ -336,8 +336,13 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * by reverse-mode differentiation of eq. LBE: the transpose of streaming
  * and of the moment-space collision (eq. lco_update, eq. stochupdaterule1,
  * eq. moment_two_external_force), segment by segment from the checkpoints
- * with the states of a segment recomputed forward (checkpoint_every step
- * buffers are allocated), the noise replayed from its Philox counters.
+ * with the states of a segment recomputed forward, the noise replayed from
+ * its Philox counters.  lb_tape_begin allocates checkpoint_every step
+ * buffers, and the taped steps write each segment's states into them, so the
+ * reverse sweep recomputes no step of the last segment (none at all when
+ * checkpoint_every >= T; a second lb_backward on the same tape recomputes
+ * every segment if the first one had more than one).  If they do not fit,
+ * recording goes on without them and lb_backward allocates them itself.
  * Taped coupled steps (lb_couple before lb_step) are differentiated too:
  * each lb_couple while recording keeps its particle half on the device (P
  * at the start, R', F^c and P'': 12 doubles per bead, and each stencil

@@ -36,8 +36,13 @@ struct lb_ctx {
     Geom geo{};
     CollideConst cc{};
     size_t elem = 4;
+    // bufA holds the state, bufB is free for the next step's output.  While a
+    // tape records, bufA may point into the segment buffer; own[] are the
+    // two state buffers the context allocated, and bufB is always one of
+    // them
     void *bufA = nullptr;
     void *bufB = nullptr;
+    void *own[2] = {nullptr, nullptr};
     uint64_t step = 0;
     int block = 256;
     int nblocks = 0;
@@ -97,6 +102,9 @@ struct lb_ctx {
     std::vector<void *> checkpoints;  // A-buffer copies at tape_step0 + s * tape_k
     void *seg = nullptr;              // tape_k step buffers of one segment
     size_t seg_bytes = 0;
+    // the taped forward writes its step buffers into seg, so slots 1.. of the
+    // last segment hold them until a reverse sweep recomputes over them
+    bool seg_fwd = false;
     float *lamA = nullptr, *lamB = nullptr;
     double *gbar_d = nullptr;
     double *adj_partials = nullptr;
@@ -398,11 +406,24 @@ int push_checkpoint(lb_ctx *c)
     return check(c, hipMemcpyAsync(p, c->bufA, state_bytes(c), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
 }
 
+// Put a state that sits in a slot of the segment buffer back into one of
+// the context's own buffers (both are free then).
+int settle_state(lb_ctx *c)
+{
+    if (c->bufA == c->own[0] || c->bufA == c->own[1]) return LB_OK;
+    LB_TRY(check(c, hipMemcpyAsync(c->own[0], c->bufA, state_bytes(c), hipMemcpyDeviceToDevice, c->stream),
+                 "state copy"));
+    c->bufA = c->own[0];
+    c->bufB = c->own[1];
+    return LB_OK;
+}
+
 void free_tape(lb_ctx *c)
 {
     for (void *p : c->checkpoints) (void)hipFree(p);
     c->checkpoints.clear();
     c->taping = false;
+    c->seg_fwd = false;
     c->tape_slot.clear();
     c->tape_beads.clear();
     c->tape_off.clear();
@@ -921,6 +942,8 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
         return fail(nullptr, LB_ENOMEM, "device allocation failed");
     }
     c->buf0 = c->bufA;
+    c->own[0] = c->bufA;
+    c->own[1] = c->bufB;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, c->flags, 1u);
     if (hipGetLastError() != hipSuccess) {
         lb_destroy(c);
@@ -1006,6 +1029,8 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
         return fail(nullptr, LB_ENOMEM, "batch allocation failed");
     }
     c->buf0 = c->bufA;
+    c->own[0] = c->bufA;
+    c->own[1] = c->bufB;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, c->flags, 1u);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t *>(c->dstep), 2u);
     if (R > 0) {
@@ -1031,7 +1056,9 @@ int lb_destroy(lb_ctx *c)
     if (!c) return LB_OK;
     use_device(c);
     (void)hipStreamSynchronize(c->stream);
-    void *ptrs[] = {c->bufA,       c->bufB,      c->partials,  c->scratch,   c->dev_out,   c->flags,
+    void *ptrs[] = {c->own[0] ? c->own[0] : c->bufA,
+                    c->own[1] ? c->own[1] : c->bufB,
+                    c->partials,  c->scratch,   c->dev_out,   c->flags,
                     c->force,      c->fmask,     c->half,      c->fc,
                     c->boxes_d,    c->tile_box,  c->dstep,     c->amp,       c->ring,      c->corr,
                     c->cell_head,  c->cell_next,  c->cell_of,   c->fb2,       c->fp};
@@ -1155,7 +1182,14 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         const bool frc = c->pending_force;
         LB_TRY(select_launch(c, frc));
         if (c->taping) c->tape_slot.push_back(frc ? c->pending_slot : -1);
-        StepArgs a = plain_step_args(c, c->bufA, c->bufB, (uint32_t)c->step);
+        void *dst = c->bufB;
+        if (c->taping && c->seg_fwd) {
+            // inside a segment the step writes the segment buffer's next slot,
+            // the step buffer the reverse sweep would otherwise recompute
+            const uint64_t k = (c->step - c->tape_step0) % (uint64_t)c->tape_k;
+            if (k + 1 < (uint64_t)c->tape_k) dst = static_cast<char *>(c->seg) + (size_t)(k + 1) * state_bytes(c);
+        }
+        StepArgs a = plain_step_args(c, c->bufA, dst, (uint32_t)c->step);
         if (frc) {
             // the step reads the bead force and leaves the field and its bitmap zero
             a.fmask = c->fmask;
@@ -1168,7 +1202,9 @@ int lb_step(lb_ctx *c, int32_t nsteps)
             c->pending_force = false;
             c->pending_slot = -1;
         }
-        std::swap(c->bufA, c->bufB);
+        // the state moves to dst; bufB becomes an own buffer that does not hold it
+        c->bufB = (c->bufA == c->own[0] || c->bufA == c->own[1]) ? c->bufA : (dst == c->own[0] ? c->own[1] : c->own[0]);
+        c->bufA = dst;
         ++c->step;
         c->totals_valid = tot;
         if (c->taping && (c->step - c->tape_step0) % (uint64_t)c->tape_k == 0) LB_TRY(push_checkpoint(c));
@@ -1367,7 +1403,26 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
     if (checkpoint_every < 1) return fail(c, LB_EINVAL, "checkpoint_every must be >= 1");
     if (c->pending_force) return fail(c, LB_ESTATE, "lb_tape_begin between lb_couple and lb_step");
     LB_TRY(use_device(c));
+    LB_TRY(settle_state(c));
     free_tape(c);
+    // the forward writes each segment's step buffers straight into the
+    // segment buffer, so the reverse sweep recomputes no step of the last
+    // segment (none at all when checkpoint_every covers the whole run); if
+    // the buffer does not fit, the sweep recomputes every segment
+    const bool fits = (size_t)checkpoint_every <= SIZE_MAX / state_bytes(c);
+    const size_t need = fits ? (size_t)checkpoint_every * state_bytes(c) : SIZE_MAX;
+    if (fits && c->seg_bytes < need) {
+        (void)hipFree(c->seg);
+        c->seg = nullptr;
+        c->seg_bytes = 0;
+        if (hipMalloc(&c->seg, need) == hipSuccess) {
+            c->seg_bytes = need;
+        } else {
+            c->seg = nullptr;
+            (void)hipGetLastError();  // an allocation that did not fit is no error here
+        }
+    }
+    c->seg_fwd = c->seg_bytes >= need;
     c->tape_k = checkpoint_every;
     c->tape_step0 = c->step;
     c->taping = true;
@@ -1375,7 +1430,8 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
 }
 
 // Reverse sweep over the tape.  Per segment: restore its checkpoint and
-// recompute its step buffers with the forward step kernel (a coupled step's
+// recompute its step buffers with the forward step kernel, except for the
+// last segment, whose buffers the taped forward left in place (a coupled step's
 // bead force is put back from the contributions its particle half recorded,
 // k_respread; the bead kernels do not run again); then, from the last step
 // of the segment back, the adjoint step: for a coupled step the force is put
@@ -1399,6 +1455,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     const size_t sb = state_bytes(c);
     const int nbd = c->tape_nb;
     const bool coupled = !c->tape_beads.empty();
+    LB_TRY(settle_state(c));  // the sweep may overwrite the segment buffer
     if (c->seg_bytes < (size_t)K * sb) {
         (void)hipFree(c->seg);
         c->seg = nullptr;
@@ -1530,8 +1587,12 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         rc = check(c, hipMemcpyAsync(seg, c->checkpoints[sg], sb, hipMemcpyDeviceToDevice, c->stream),
                    "checkpoint restore");
         if (rc != LB_OK) break;
+        // the last segment's step buffers 1 .. len-1 are still those the
+        // forward wrote, unless an earlier sweep recomputed over them
+        const bool kept = c->seg_fwd && sg == nseg - 1;
+        if (!kept) c->seg_fwd = false;
         // recompute steps 0 .. len-2 of the segment (first force field)
-        for (int k = 0; k + 1 < len; ++k) {
+        for (int k = 0; !kept && k + 1 < len; ++k) {
             const uint64_t t = t0 + k;
             const uint32_t step = (uint32_t)(c->tape_step0 + t);
             StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb, step);

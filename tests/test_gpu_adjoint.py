@@ -168,3 +168,41 @@ def test_full_size_directional_derivative(orc, lat):
     got = (dn0.cpu().numpy() * v).sum()
     print(f"directional derivative: gpu {got:.10e} fd {fd:.10e}")
     assert got == pytest.approx(fd, rel=1e-4)
+
+
+def test_repeated_backward_and_continued_tape(orc, lat):
+    """The taped steps leave the last segment's step buffers in place for the
+    reverse sweep; a second backward over the same tape (after a sweep that
+    recomputed over them, or one that did not) and a backward after more
+    taped steps must give what a fresh tape gives, and no sweep may change
+    the forward state."""
+    import torch
+    rng = np.random.default_rng(5)
+    po, pd = pair(orc, lat, 9, 8, 10, kT=1e-4, seed=4)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, 10, 8, 9)))
+    w = torch.from_numpy(rng.normal(size=n0.shape))
+
+    def fresh(K, T):
+        dev = lat.Lattice(pd)
+        dev.set_populations(torch.from_numpy(n0))
+        dev.tape_begin(K)
+        dev.step(T)
+        return dev
+
+    for K in (4, 20):
+        ref9, ref13 = fresh(K, 9), fresh(K, 13)
+        g9, g13 = ref9.backward(w), ref13.backward(w)
+        n13 = ref13.get_populations()
+        ref9.close()
+        ref13.close()
+        dev = fresh(K, 9)
+        n9 = dev.get_populations()
+        for _ in range(2):
+            dn, dg = dev.backward(w)
+            assert torch.equal(dn, g9[0]) and dg == g9[1], K
+            assert torch.equal(dev.get_populations(), n9), K
+        dev.step(4)
+        dn, dg = dev.backward(w)
+        assert torch.equal(dn, g13[0]) and dg == g13[1], K
+        assert torch.equal(dev.get_populations(), n13), K
+        dev.close()
