@@ -1456,12 +1456,20 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     const int nbd = c->tape_nb;
     const bool coupled = !c->tape_beads.empty();
     LB_TRY(settle_state(c));  // the sweep may overwrite the segment buffer
-    if (c->seg_bytes < (size_t)K * sb) {
+    // a segment holds at most min(K, T) step buffers
+    const uint64_t slots = std::min<uint64_t>((uint64_t)K, T);
+    if (slots > SIZE_MAX / sb) return fail(c, LB_ENOMEM, "segment buffer too large");
+    if (c->seg_bytes < slots * sb) {
         (void)hipFree(c->seg);
         c->seg = nullptr;
         c->seg_bytes = 0;
-        if (hipMalloc(&c->seg, (size_t)K * sb) != hipSuccess) return fail(c, LB_ENOMEM, "segment buffer allocation failed");
-        c->seg_bytes = (size_t)K * sb;
+        c->seg_fwd = false;
+        if (hipMalloc(&c->seg, slots * sb) != hipSuccess) {
+            c->seg = nullptr;
+            (void)hipGetLastError();
+            return fail(c, LB_ENOMEM, "segment buffer allocation failed");
+        }
+        c->seg_bytes = slots * sb;
     }
     // the adjoint step's blocks, dealt out layer by layer (256 threads)
     const unsigned nb = step_blocks(c, 256);
