@@ -1,11 +1,13 @@
 // Device kernels of liblbmi (gfx950): fused pull-stream + collide, state
 // conversions, diagnostics and the point-particle coupling.
 //
-// Memory layout: two population buffers A (read) and B (written) of
-// [19][N] storage elements.  The buffer the next step reads holds the
-// post-collision populations of the previous step at their pre-streaming
-// site, so the pre-collision state is n_i(r,t) = A_i(r - c_i) (pull).  One
-// step reads A at r - c_i, collides at r and writes B at r; then A and B swap.
+// Memory layout: two population buffers A (read) and B (written) of 19 N
+// storage elements, z-major for a single box (pop[z][i][y][x], pop_index)
+// and [19][N] for the boxes of a batch.  The buffer the next step reads
+// holds the post-collision populations of the previous step at their
+// pre-streaming site, so the pre-collision state is n_i(r,t) = A_i(r - c_i)
+// (pull).  One step reads A at r - c_i, collides at r and writes B at r; then
+// A and B swap.
 #pragma once
 
 #include <hip/hip_runtime.h>
