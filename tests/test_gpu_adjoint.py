@@ -199,6 +199,11 @@ def test_repeated_backward_and_continued_tape(orc, lat):
         ref13.close()
         dev = fresh(K, 9)
         n9 = dev.get_populations()
+        plain = lat.Lattice(pd)  # the same steps with no tape: ping-pong buffers only
+        plain.set_populations(torch.from_numpy(n0))
+        plain.step(9)
+        assert torch.equal(plain.get_populations(), n9), K
+        plain.close()
         for _ in range(2):
             dn, dg = dev.backward(w)
             assert torch.equal(dn, g9[0]) and dg == g9[1], K
