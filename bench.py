@@ -12,8 +12,10 @@ synthetic (seeded), resident in HBM before the timed region.
 Prints ONE JSON line with, beside the throughput:
   roofline      the dominant kernel (fused stream-collide, bead-force
                 variant): algorithmic bytes per launch (19 reads + 19 writes
-                of a 4-byte population per site, plus the 1-bit-per-site
-                force bitmap) over its average duration, timed with events
+                of a 4-byte population per site, the read and write of the
+                rest population's 4-byte rounding residual that keeps each
+                site's mass exact, plus the 1-bit-per-site force bitmap)
+                over its average duration, timed with events
                 on the launch stream around each step's launch inside the
                 timed region, against the 8 TB/s HBM peak, and beside it
                 the rate of a plain device copy of one population buffer
@@ -55,6 +57,8 @@ KT = 1e-4
 # the explicit bead-fluid scheme diverge within ten steps at zeta = 20, m = 1.
 K_BOND = 10.0 * KT
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_256.json")
+# coupled steps of the workload over which the relative mass drift is reported
+DRIFT_STEPS = 1000
 # Friction of the Kremer-Grest chains: velocity relaxation time m/zeta = 5 steps
 # (0.05 of the Lennard-Jones time sigma sqrt(m/eps) = 100 steps at eps = kT).
 # With the harmonic chains' zeta = 20 the beads follow the lattice-scale fluid
@@ -382,12 +386,19 @@ def main() -> int:
     torch.cuda.synchronize()
     half_ms = sum(c0.elapsed_time(c1) for c0, c1 in cev) / len(cev)
 
+    # conservation over at least 1000 coupled steps of the workload (after
+    # the timed region, not part of the throughput)
+    done = 1 + args.warmup + args.steps + len(cev)
+    for _ in range(max(0, DRIFT_STEPS - done)):
+        lat.coupled_step(beads)
+    drift_steps = max(done, DRIFT_STEPS)
     tot1 = lat.totals()
     tot1x = lat.totals(exact=True)
     lat.sync()
     cfg = lat.launch_config(force=True)
 
-    alg_bytes = 2 * 19 * 4 * N + N // 8
+    planes = 20  # FP32 storage: 19 populations + the rest population's rounding residual
+    alg_bytes = 2 * planes * 4 * N + N // 8
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -403,10 +414,10 @@ def main() -> int:
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    ceiling, cblock = copy_ceiling(19 * 4 * N)
+    ceiling, cblock = copy_ceiling(planes * 4 * N)
     roofline["copy_ceiling"] = {"achieved": round(ceiling, 1), "unit": "GB/s",
                                 "kernel": f"streaming copy (16 B per thread, {cblock} threads per block) of one "
-                                          f"{19 * 4 * N / 1e9:.2f} GB population buffer",
+                                          f"{planes * 4 * N / 1e9:.2f} GB population buffer",
                                 "frac_of_copy": round(achieved / ceiling, 4)}
     pull, pblock = pull_ceiling(L)
     if pull:
@@ -444,6 +455,7 @@ def main() -> int:
         "forms": forms,
         "particle_half_ms": round(half_ms, 5),
         "mass_drift_rel": (tot1x[0] - tot0[0]) / tot0[0],
+        "mass_drift_steps": drift_steps,
         "fused_vs_exact_totals_abs": max(abs(a - b) for a, b in zip(tot1, tot1x)),
         "source_hash": source_hash(),
     }

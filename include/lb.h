@@ -199,9 +199,13 @@ typedef struct {
 
 typedef struct lb_ctx lb_ctx;
 
-/* Create a context: allocates two population buffers (2 * 19 * N * storage
+/* Create a context: allocates two population buffers (2 * P * N * storage
  * bytes) and small bookkeeping on the current device, enqueues on `stream`
- * (a hipStream_t; NULL = the null stream).  The state is uninitialised until
+ * (a hipStream_t; NULL = the null stream).  P = 20 for LB_F32 storage,
+ * whose rest population is held as its FP32 value plus its FP32 rounding
+ * residual, so that every step keeps each site's mass to ~1e-17 (the
+ * collision conserves mass: the constraint after eq. LBE); P = 19 for 16-bit
+ * storage, which rounds that residual once per site and step.  The state is uninitialised until
  * lb_init_equilibrium or lb_set_populations.  The step counter starts at 0.
  * Errors: LB_EINVAL (any extent < 2, N >= 2^30, |gamma| out of range,
  * kT < 0, rho0 <= 0, unknown storage, bad block), LB_ENOMEM, LB_EDEVICE. */
@@ -303,7 +307,8 @@ int lb_couple(lb_ctx *ctx, const lb_beads *beads);
 int lb_moments(lb_ctx *ctx, double *rho, double *u);
 
 /* FP64 totals of the current state, host out[4] = {sum rho, sum j_x, sum j_y,
- * sum j_z} with j = sum_i n_i c_i.  With track_totals the values come from
+ * sum j_z} with j = sum_i n_i c_i: the conserved quantities of eq. LBE
+ * (mass exactly, momentum up to the forcing of eq. moment_one_external_force).  With track_totals the values come from
  * the last step's fused accumulation (stored, rounded populations);
  * otherwise (or before any step) from a full reduction pass.  Synchronises;
  * returns LB_ENONFINITE if a non-finite population was seen. */
@@ -327,7 +332,7 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
 
 /* Differentiation form.  lb_tape_begin starts recording at the current step:
  * the state is checkpointed now and after every `checkpoint_every` steps
- * (device copies of the population buffer, 19 * N * storage bytes each).
+ * (device copies of the population buffer, P * N * storage bytes each).
  * lb_backward then returns, for the T steps taken since lb_tape_begin,
  *   dL_dn_0 = dL/dn(t0) given dL_dn_T = dL/dn(t0 + T)   (device [19][N] of
  *             `dtype` LB_F64 or LB_F32, full populations, natural layout),

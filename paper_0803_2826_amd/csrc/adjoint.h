@@ -27,7 +27,7 @@ namespace lbmi {
 
 struct AdjArgs {
     const void *state;      // step buffer A_t (AB layout: pre-collision n_t(r) = A_t,i(r - c_i))
-    const float *lam_in;    // lambda(t+1), the state's layout (pop_index)
+    const float *lam_in;    // lambda(t+1), z-major with 19 planes per layer (lam_index)
     float *lam_out;         // lambda(t), the state's layout
     Geom geo;
     CollideConst cc;
@@ -73,16 +73,17 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         oxy.oz_p = 0;
         const uint32_t N = a.geo.N;
         const size_t plane = (size_t)nxny * sizeof(T);
+        const uint32_t P = a.geo.planes;  // state planes per layer (lambda keeps 19)
         const char *st = static_cast<const char *>(a.state);
         // forward hydrodynamic fields of n(r, t)
         float d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             if (pull_crosses<WALLS>(a.geo, z, i))  // pull source beyond a wall: opp(i) of this site
-                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(19u * z + (uint32_t)opp(i)) * plane), r),
+                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(P * z + (uint32_t)opp(i)) * plane), r),
                              0.f);
             else
-                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(19u * pull_z(z, i, a.geo) + (uint32_t)i) *
+                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(P * pull_z(z, i, a.geo) + (uint32_t)i) *
                                                                            plane),
                                       pull_src(r, oxy, i)),
                              0.f);
@@ -293,14 +294,14 @@ __global__ void __launch_bounds__(256) k_accumulate_cols(const double *__restric
     if (threadIdx.x == 0) acc[c] += red[0];
 }
 
-// Conversions between the caller's [19][N] arrays and the FP32 adjoints in
-// the state's layout (pop_index).
+// Conversions between the caller's [19][N] arrays and the FP32 adjoints
+// (z-major, lam_index).
 template <typename TIn>
 __global__ void k_to_lam(const TIn *__restrict__ in, float *__restrict__ lam, Geom g)
 {
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
         const uint32_t z = fdiv(fdiv(s, g.div_nx), g.div_ny);
-        for (int i = 0; i < Q; ++i) lam[pop_index(i, s, z, g)] = (float)in[(size_t)i * g.N + s];
+        for (int i = 0; i < Q; ++i) lam[lam_index(i, s, z, g)] = (float)in[(size_t)i * g.N + s];
     }
 }
 
@@ -309,7 +310,7 @@ __global__ void k_from_lam(const float *__restrict__ lam, TOut *__restrict__ out
 {
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
         const uint32_t z = fdiv(fdiv(s, g.div_nx), g.div_ny);
-        for (int i = 0; i < Q; ++i) out[(size_t)i * g.N + s] = (TOut)lam[pop_index(i, s, z, g)];
+        for (int i = 0; i < Q; ++i) out[(size_t)i * g.N + s] = (TOut)lam[lam_index(i, s, z, g)];
     }
 }
 

@@ -25,6 +25,31 @@ __device__ __forceinline__ void site_xyz(uint32_t s, const Geom &g, uint32_t &x,
     y = q - z * g.ny;
 }
 
+// Store the deviation v of population i at site s; the rest population of
+// FP32 storage keeps its FP64 value as hi + lo (the residual plane, see
+// store_site).
+template <int ST>
+__device__ __forceinline__ void store_pop(typename Storage<ST>::T *b, int i, uint32_t s, uint32_t z, const Geom &g,
+                                          double v)
+{
+    using S = Storage<ST>;
+    const typename S::T h = S::st((float)v, 0.f);
+    b[pop_index(i, s, z, g)] = h;
+    if constexpr (S::rest_lo)
+        if (i == 0) b[pop_index(kRestLo, s, z, g)] = (float)(v - (double)S::ld(h, 0.f));
+}
+
+// Stored value of the rest population at site s as FP64 (hi + lo for FP32
+// storage).
+template <int ST>
+__device__ __forceinline__ double load_rest(const typename Storage<ST>::T *b, uint32_t s, uint32_t z, const Geom &g)
+{
+    using S = Storage<ST>;
+    double v = (double)S::ld(b[pop_index(0, s, z, g)], 0.f);
+    if constexpr (S::rest_lo) v += (double)b[pop_index(kRestLo, s, z, g)];
+    return v;
+}
+
 // Buffer A_i(r) = S_i(r + c_i) with S = n^eq(rho, u) of eq. original_equil_distrib,
 // shifted by a_i rho0.
 template <int ST>
@@ -54,7 +79,7 @@ __global__ void k_init_equilibrium(void *buf, Geom g, double rho0, const double 
         const double usq = ux * ux + uy * uy + uz * uz;
         const double a = weight_of(j);
         const double neq = a * rr * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * usq);
-        b[pop_index(i, s, z, g)] = S::st((float)(neq - a * rho0), 0.f);
+        store_pop<ST>(b, i, s, z, g, neq - a * rho0);
     }
 }
 
@@ -76,7 +101,7 @@ __global__ void k_set_pops(void *buf, Geom g, double rho0, const TIn *__restrict
         const uint32_t r = wall ? s : push_dst(x, y, z, g, i);
         double v = (double)src[(size_t)j * g.N + r];
         if (!shifted) v -= weight_of(j) * rho0;
-        b[pop_index(i, s, z, g)] = S::st((float)v, 0.f);
+        store_pop<ST>(b, i, s, z, g, v);
     }
 }
 
@@ -92,7 +117,7 @@ __global__ void k_get_pops(const void *buf, Geom g, double rho0, TOut *__restric
     const PullOffsets o = pull_offsets(s, g, x, y, z);
     const T *b = static_cast<const T *>(buf);
     for (int i = 0; i < Q; ++i) {
-        double v = (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
+        double v = i == 0 ? load_rest<ST>(b, s, z, g) : (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
         if (!shifted) v += weight_of(i) * rho0;
         dst[(size_t)i * g.N + s] = (TOut)v;
     }
@@ -112,7 +137,7 @@ __global__ void k_moments(const void *buf, Geom g, double rho0, double gx, doubl
     const T *b = static_cast<const T *>(buf);
     double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int i = 0; i < Q; ++i) {
-        const double v = (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
+        const double v = i == 0 ? load_rest<ST>(b, s, z, g) : (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
         m += v;
         jx += v * kCX[i];
         jy += v * kCY[i];
@@ -164,7 +189,7 @@ __global__ void __launch_bounds__(256) k_totals_exact(const void *buf, Geom g, d
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
         const uint32_t z = fdiv(fdiv(s, g.div_nx), g.div_ny);
         for (int i = 0; i < Q; ++i) {
-            const double v = (double)S::ld(b[pop_index(i, s, z, g)], 0.f);
+            const double v = i == 0 ? load_rest<ST>(b, s, z, g) : (double)S::ld(b[pop_index(i, s, z, g)], 0.f);
             acc[0] += v;
             acc[1] += v * kCX[i];
             acc[2] += v * kCY[i];
@@ -215,7 +240,8 @@ __global__ void __launch_bounds__(256) k_mode_stats(const void *buf, Geom g, dou
         uint32_t x, y, z;
         const PullOffsets o = pull_offsets(s, g, x, y, z);
         double n[Q];
-        for (int i = 0; i < Q; ++i) n[i] = (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
+        for (int i = 0; i < Q; ++i)
+            n[i] = i == 0 ? load_rest<ST>(b, s, z, g) : (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
         for (int k = 0; k < Q; ++k) {
             double m = (k == 0) ? rho0 : 0.0;
             for (int i = 0; i < Q; ++i) m += basis_k(k, kCX[i], kCY[i], kCZ[i]) * n[i];

@@ -2,7 +2,8 @@
 // advanced by ONE persistent launch per time step, replayable as a HIP graph.
 //
 // Layout: all boxes share two population buffers; box b owns the element
-// range [off_b, off_b + 19 N_b) of each ([19][N_b] structure of arrays).
+// range [off_b, off_b + P N_b) of each ([P][N_b] structure of arrays, P = 20
+// with the rest residual plane of FP32 storage, else 19).
 // Work list: the sites of each box are cut into tiles of blockDim sites; the
 // tile -> box table is built on the host.  Each block walks a contiguous chunk
 // of tiles, so it stays inside one box for long stretches; that is what lets
@@ -29,7 +30,7 @@ namespace lbmi {
 
 struct BoxDesc {
     Geom geo;
-    uint64_t off;         // element offset of this box's [19][N_b] block
+    uint64_t off;         // element offset of this box's [P][N_b] block
     uint32_t box_id;      // fourth Philox counter word
     uint32_t first_tile;  // index of the box's first tile in the work list
     float inv_L[3];       // 1 / L_x, 1 / L_y, 1 / L_z
@@ -110,7 +111,9 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
         float dd[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) dd[i] = S::ld(ld_plane(src + (size_t)i * N, pull_src(s, o, i)), 0.f);
-        const mass_acc_t<ST> m_in = site_mass<ST>(dd);
+        float lo_in = 0.f;
+        if constexpr (S::rest_lo) lo_in = ld_plane(src + (size_t)kRestLo * N, s);
+        const mass_acc_t<ST> m_in = site_mass_lo<ST>(dd, lo_in);
         if (VACF) {
             const float jx = (dd[1] - dd[2]) + (dd[7] - dd[8]) + (dd[9] - dd[10]) + (dd[11] - dd[12]) + (dd[13] - dd[14]);
             const float jy = (dd[3] - dd[4]) + (dd[7] - dd[8]) - (dd[9] - dd[10]) + (dd[15] - dd[16]) + (dd[17] - dd[18]);
@@ -131,9 +134,9 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
         float out[Q];
         collide_site<THERMAL, FULL>(dd, cc.g, cc, s, step, out);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        void *dstp[Q];
+        void *dstp[Q + 1];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dstp[i] = dst + (size_t)i * N;
+        for (int i = 0; i < Q + (S::rest_lo ? 1 : 0); ++i) dstp[i] = dst + (size_t)i * N;
         double mass;
         float mom[3];
         Philox4 rw = {0u, 0u, 0u, 0u};

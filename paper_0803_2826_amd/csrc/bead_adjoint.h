@@ -41,7 +41,7 @@ struct BeadAdjArgs {
     double *half_bar;       // out: adjoint of R' without the bond term [n][3]
     double *fc_bar;         // out: adjoint of F^c [n][3]
     double *p_bar;          // out: adjoint of P without the half-drift term [n][3]
-    float *lam;             // adjoint of n_t (the state's layout, pop_index), accumulated at the nodes
+    float *lam;             // adjoint of n_t (lam_index layout), accumulated at the nodes
     double *gbar;           // [3] accumulated
     // fold = 1: the adjoint of (R_new, P_new) is formed here, per bead, from
     // the later coupled step's half_bar and p_bar as they stand on entry
@@ -140,12 +140,12 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
     }
     // u_q = (sum n c + g/2) / rho: lambda_i(node) += w_q (c_i - u_q) . ubar / rho
     if (wq != 0.0) {
-        const uint32_t node_z = fdiv(fdiv(node, g.div_nx), g.div_ny);  // lambda has the state's layout
+        const uint32_t node_z = fdiv(fdiv(node, g.div_nx), g.div_ny);  // lambda is z-major (lam_index)
         const double s0 = -(uq[0] * ubb[0] + uq[1] * ubb[1] + uq[2] * ubb[2]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double v = wq * (s0 + kCX[i] * ubb[0] + kCY[i] * ubb[1] + kCZ[i] * ubb[2]) / rho;
-            atomicAdd(&a.lam[pop_index(i, node, node_z, g)], (float)v);
+            atomicAdd(&a.lam[lam_index(i, node, node_z, g)], (float)v);
         }
     }
     double hb[3];

@@ -1,9 +1,12 @@
 // Device kernels of liblbmi (gfx950): fused pull-stream + collide, state
 // conversions, diagnostics and the point-particle coupling.
 //
-// Memory layout: two population buffers A (read) and B (written) of 19 N
+// Memory layout: two population buffers A (read) and B (written) of P N
 // storage elements, z-major for a single box (pop[z][i][y][x], pop_index)
-// and [19][N] for the boxes of a batch.  The buffer the next step reads
+// and [P][N] for the boxes of a batch.  P = 19 planes for 16-bit storage;
+// FP32 storage has P = 20: plane 19 holds the FP32 rounding residual of the
+// rest population, whose value is the unevaluated sum of planes 0 and 19
+// (see store_site).  The buffer the next step reads
 // holds the post-collision populations of the previous step at their
 // pre-streaming site, so the pre-collision state is n_i(r,t) = A_i(r - c_i)
 // (pull).  One step reads A at r - c_i, collides at r and writes B at r; then
@@ -53,16 +56,19 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
 template <int ST> struct Storage;
 template <> struct Storage<1> {  // LB_F32
     using T = float;
+    static constexpr bool rest_lo = true;  // rest population carries its residual plane
     static __device__ __forceinline__ float ld(T v, float) { return v; }
     static __device__ __forceinline__ T st(float f, float) { return f; }
 };
 template <> struct Storage<2> {  // LB_BF16
     using T = __bf16;
+    static constexpr bool rest_lo = false;
     static __device__ __forceinline__ float ld(T v, float) { return (float)v; }
     static __device__ __forceinline__ T st(float f, float) { return (__bf16)f; }
 };
 template <> struct Storage<3> {  // LB_F16, stored value = 2^8 * deviation
     using T = _Float16;
+    static constexpr bool rest_lo = false;
     static __device__ __forceinline__ float ld(T v, float) { return (float)v * 0x1p-8f; }
     static __device__ __forceinline__ T st(float f, float) { return (_Float16)(f * 0x1p8f); }
 };
@@ -122,17 +128,30 @@ struct Geom {
     FastDiv div_nx, div_ny;
     uint32_t walls;  // 1: stationary walls at z = -1/2 and z = nz - 1/2
     uint32_t zmajor; // population layout, see pop_index
+    uint32_t planes; // planes per layer (z-major) or per box: 19, or 20 with the rest residual plane
 };
 
-// Element index of population i of site s (layer z) in a population buffer.
-// zmajor = 1 (a single box): [z][i][y][x], the 19 planes of one z-layer side
+// Plane of the rest population's rounding residual (FP32 storage only).
+constexpr int kRestLo = 19;
+
+// Element index of population i of site s (layer z) in a population buffer
+// (i = kRestLo: the rest residual plane).
+// zmajor = 1 (a single box): [z][i][y][x], the planes of one z-layer side
 // by side, so that the 38 streams of a step stay within a few MB of each
 // other (measured faster than [i][z][y][x] for the pull pattern); zmajor = 0
 // (the boxes of a batch): [i][z][y][x].
 __device__ __forceinline__ size_t pop_index(int i, uint32_t s, uint32_t z, const Geom &g)
 {
-    if (g.zmajor) return (size_t)(19u * z + (uint32_t)i) * g.nxny + (s - z * g.nxny);
+    if (g.zmajor) return (size_t)(g.planes * z + (uint32_t)i) * g.nxny + (s - z * g.nxny);
     return (size_t)i * g.N + s;
+}
+
+// Element index of the adjoint lambda_i of site s (layer z): z-major with 19
+// planes per layer whatever the storage (the adjoint is FP32 and has no
+// residual plane).
+__device__ __forceinline__ size_t lam_index(int i, uint32_t s, uint32_t z, const Geom &g)
+{
+    return (size_t)(19u * z + (uint32_t)i) * g.nxny + (s - z * g.nxny);
 }
 
 // Neighbour offsets of site s: off[c+1] for c = -1, 0, +1 along each axis is
@@ -334,11 +353,28 @@ __device__ __forceinline__ mass_acc_t<ST> site_mass(const float d[Q])
     return m;
 }
 
+// Input mass of a site with the rest residual plane (FP32 storage): the
+// gathered deviations plus the residual lo of the site's rest population.
+template <int ST>
+__device__ __forceinline__ mass_acc_t<ST> site_mass_lo(const float d[Q], float lo)
+{
+    mass_acc_t<ST> m = site_mass<ST>(d);
+    if constexpr (Storage<ST>::rest_lo) m += (double)lo;
+    return m;
+}
+
 // Store the post-collision populations of site s.  The rest population is
-// replaced by the residual that makes the stored values of the site sum to the
-// stored input values (m_in, from site_mass), so the site's mass changes only
-// by the single rounding of that residual to the storage type.  Returns the
-// stored values' mass (FP64) and momentum (FP32) for the totals.
+// replaced by the residual x = m_in - sum_{i>=1} stored_i that makes the
+// stored values of the site sum to its input mass m_in (site_mass_lo): the
+// collision conserves each site's mass (the constraint on the collision after
+// eq. LBE), and so does the store.  16-bit storage rounds x once.  FP32
+// storage keeps x as hi + lo: hi = fp32(x) in the rest plane and
+// lo = fp32(x - hi) in the residual plane dstp[kRestLo], so the site's stored
+// mass differs from m_in only by the rounding of lo (below 2^-25 ulp(hi))
+// and the FP64 sums (2^-53 relative): total mass is conserved to ~1e-16
+// relative per step instead of random-walking by one FP32 rounding per site
+// and step.  Returns the stored values' mass (FP64) and momentum (FP32) for
+// the totals.
 template <int ST, bool TOTALS>
 __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_bytes, uint32_t s, mass_acc_t<ST> m_in,
                                            const float out[Q], double &mass, float mom[3], const Philox4 &rw)
@@ -356,13 +392,17 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
         back[i] = S::ld(v[i], 0.f);
         sum += (Acc)back[i];
     }
-    if constexpr (is_stochastic<ST>::value) v[0] = S::st_sr((float)(m_in - sum), rounding_field(rw, 0));
-    else v[0] = S::st((float)(m_in - sum), 0.f);
+    const Acc x = m_in - sum;
+    if constexpr (is_stochastic<ST>::value) v[0] = S::st_sr((float)x, rounding_field(rw, 0));
+    else v[0] = S::st((float)x, 0.f);
     back[0] = S::ld(v[0], 0.f);
+    float lo = 0.f;
+    if constexpr (S::rest_lo) lo = (float)(x - (Acc)back[0]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) st_plane_nt<T>(dstp[i], plane_bytes, s, v[i]);
+    if constexpr (S::rest_lo) st_plane_nt<float>(dstp[kRestLo], plane_bytes, s, lo);
     if (TOTALS) {
-        mass = (double)back[0] + (double)sum;
+        mass = ((double)back[0] + (double)lo) + (double)sum;
         mom[0] = (back[1] - back[2]) + (back[7] - back[8]) + (back[9] - back[10]) + (back[11] - back[12]) +
                  (back[13] - back[14]);
         mom[1] = (back[3] - back[4]) + (back[7] - back[8]) - (back[9] - back[10]) + (back[15] - back[16]) +
@@ -389,6 +429,7 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
     const bool active = r < nxny;
     const uint32_t s = z * nxny + r;
     const size_t plane = (size_t)nxny * sizeof(T);
+    const uint32_t P = a.geo.planes;
     const char *src = static_cast<const char *>(a.src);
     char *dst = static_cast<char *>(a.dst);
     double mass = 0.0;
@@ -403,21 +444,24 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         float d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const T *base = reinterpret_cast<const T *>(src + (size_t)(19u * pull_z(z, i, a.geo) + (uint32_t)i) * plane);
+            const T *base = reinterpret_cast<const T *>(src + (size_t)(P * pull_z(z, i, a.geo) + (uint32_t)i) * plane);
             d[i] = S::ld(ld_plane(base, pull_src(r, oxy, i)), 0.f);
         }
+        float lo_in = 0.f;
+        if constexpr (S::rest_lo)
+            lo_in = ld_plane(reinterpret_cast<const float *>(src + (size_t)(P * z + (uint32_t)kRestLo) * plane), r);
         if constexpr (WALLS) {
             if (z == 0u || z + 1u == a.geo.nz) {
                 // wall layers: the populations coming off a wall are the reversed ones of this site
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     if (pull_crosses(a.geo, z, i))
-                        d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(src + (size_t)(19u * z + (uint32_t)opp(i)) * plane),
+                        d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(src + (size_t)(P * z + (uint32_t)opp(i)) * plane),
                                               r),
                                      0.f);
             }
         }
-        const mass_acc_t<ST> m_in = site_mass<ST>(d);
+        const mass_acc_t<ST> m_in = site_mass_lo<ST>(d, lo_in);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         if (FORCE) {
             const uint32_t bit = 1u << (s & 31u);
@@ -440,9 +484,9 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Philox4 rw = {0u, 0u, 0u, 0u};
         if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, a.step, a.cc.box, a.cc.key0, a.cc.key1);
-        void *dstp[Q];
+        void *dstp[Q + 1];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dstp[i] = dst + (size_t)(19u * z + (uint32_t)i) * plane;
+        for (int i = 0; i < Q + (S::rest_lo ? 1 : 0); ++i) dstp[i] = dst + (size_t)(P * z + (uint32_t)i) * plane;
         store_site<ST, TOTALS>(dstp, (uint32_t)plane, r, m_in, out, mass, mom, rw);
     }
     if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)blockIdx.x, mass, mom);

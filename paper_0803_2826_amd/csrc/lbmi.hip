@@ -173,6 +173,10 @@ size_t storage_bytes(int st)
 
 unsigned grid_for(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Planes per layer (single box) or per box (batch) of a population buffer:
+// FP32 storage adds the rest population's residual plane (kRestLo).
+uint32_t state_planes(int st) { return st == LB_F32 ? 20u : 19u; }
+
 // Blocks of a single-box step launch: every z-layer is cut into
 // ceil(nxny / block) tiles (a layer's last tile may be partial).
 unsigned step_blocks(const lb_ctx *c, int block)
@@ -396,7 +400,7 @@ int ensure_bead_buffers(lb_ctx *c, int n)
 // differentiation: checkpoints and the adjoint sweep
 // ---------------------------------------------------------------------------
 
-size_t state_bytes(const lb_ctx *c) { return (size_t)19 * c->geo.N * c->elem; }
+size_t state_bytes(const lb_ctx *c) { return (size_t)c->geo.planes * c->geo.N * c->elem; }
 
 int push_checkpoint(lb_ctx *c)
 {
@@ -925,6 +929,7 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     c->geo.div_ny = make_fastdiv(ny);
     c->geo.walls = (uint32_t)params->walls;
     c->geo.zmajor = 1u;
+    c->geo.planes = state_planes(params->storage);
     c->elem = storage_bytes(params->storage);
     c->block = params->block > 0 ? params->block : 256;
     c->tuned = true;
@@ -932,7 +937,7 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     c->block_f[0] = c->block_f[1] = c->block;
     c->nblocks = (int)step_blocks(c, c->block);
     fill_collide_const(c);
-    const size_t bytes = (size_t)19 * c->geo.N * c->elem;
+    const size_t bytes = state_bytes(c);
     // per-block totals rows: the most blocks any block size gives (64 threads)
     const size_t rows = std::max<size_t>(grid_for(c->geo.N, 64), step_blocks(c, 64));
     if (hipMalloc(&c->bufA, bytes) != hipSuccess || hipMalloc(&c->bufB, bytes) != hipSuccess ||
@@ -998,13 +1003,14 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
         d.geo.N = (uint32_t)Nb;
         d.geo.div_nx = make_fastdiv(e[0]);
         d.geo.div_ny = make_fastdiv(e[1]);
+        d.geo.planes = state_planes(p.storage);
         d.off = off;
         d.box_id = (uint32_t)(p.box_id + b);
         d.inv_L[0] = 1.0f / (float)e[0];
         d.inv_L[1] = 1.0f / (float)e[1];
         d.inv_L[2] = 1.0f / (float)e[2];
         c->boxes_h.push_back(d);
-        off += 19 * Nb;
+        off += (uint64_t)d.geo.planes * Nb;
         c->total_sites += Nb;
     }
     c->geo = c->boxes_h[0].geo;  // first box (diagnostic helpers loop over all boxes)
@@ -1127,8 +1133,11 @@ int lb_set_populations(lb_ctx *c, const void *src, int32_t dtype, int32_t shifte
         });
     };
     if (c->batch) {
-        for (const BoxDesc &d : c->boxes_h)
-            one(static_cast<char *>(c->bufA) + d.off * c->elem, d.geo, static_cast<const char *>(src) + d.off * isz);
+        uint64_t site0 = 0;  // the caller's array holds [19][N_b] per box, box after box
+        for (const BoxDesc &d : c->boxes_h) {
+            one(static_cast<char *>(c->bufA) + d.off * c->elem, d.geo, static_cast<const char *>(src) + 19 * site0 * isz);
+            site0 += d.geo.N;
+        }
     } else {
         one(c->bufA, c->geo, src);
     }
@@ -1157,8 +1166,11 @@ int lb_get_populations(lb_ctx *c, void *dst, int32_t dtype, int32_t shifted)
         });
     };
     if (c->batch) {
-        for (const BoxDesc &d : c->boxes_h)
-            one(static_cast<const char *>(c->bufA) + d.off * c->elem, d.geo, static_cast<char *>(dst) + d.off * isz);
+        uint64_t site0 = 0;  // the caller's array holds [19][N_b] per box, box after box
+        for (const BoxDesc &d : c->boxes_h) {
+            one(static_cast<const char *>(c->bufA) + d.off * c->elem, d.geo, static_cast<char *>(dst) + 19 * site0 * isz);
+            site0 += d.geo.N;
+        }
     } else {
         one(c->bufA, c->geo, dst);
     }
@@ -1873,8 +1885,9 @@ struct SaveHeader {
     uint64_t total_sites;
 };
 static const char kSaveMagic[8] = {'L', 'B', 'M', 'I', 'C', 'K', 'P', '1'};
-// version 2: single-box populations in the z-major layout (pop_index)
-static const uint32_t kSaveVersion = 2;
+// version 3: single-box populations in the z-major layout (pop_index), FP32
+// storage with the rest residual plane
+static const uint32_t kSaveVersion = 3;
 
 static void ctx_dims(const lb_ctx *c, std::vector<int32_t> &dims)
 {
@@ -1891,6 +1904,9 @@ static void ctx_dims(const lb_ctx *c, std::vector<int32_t> &dims)
 }
 
 static size_t ctx_sites(const lb_ctx *c) { return c->batch ? (size_t)c->total_sites : (size_t)c->geo.N; }
+
+// Bytes of the stored populations of every box (the state lb_save writes).
+static size_t ctx_state_bytes(const lb_ctx *c) { return (size_t)state_planes(c->p.storage) * ctx_sites(c) * c->elem; }
 
 int lb_save(lb_ctx *c, const char *path)
 {
@@ -1909,7 +1925,7 @@ int lb_save(lb_ctx *c, const char *path)
     h.elem = (int32_t)c->elem;
     h.step = c->step;
     h.total_sites = ctx_sites(c);
-    const size_t bytes = (size_t)19 * h.total_sites * c->elem;
+    const size_t bytes = ctx_state_bytes(c);
     std::vector<char> host(bytes);
     {
         Join j(c);
@@ -1938,7 +1954,7 @@ int lb_load(lb_ctx *c, const char *path)
     SaveHeader h{};
     std::vector<int32_t> dims, want;
     ctx_dims(c, want);
-    const size_t bytes = (size_t)19 * ctx_sites(c) * c->elem;
+    const size_t bytes = ctx_state_bytes(c);
     std::vector<char> host;
     std::string why;
     if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != kSaveVersion ||
