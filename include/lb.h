@@ -286,6 +286,44 @@ int lb_get_populations(lb_ctx *ctx, void *dst, int32_t dtype, int32_t shifted);
  * only; the counter increases by nsteps. */
 int lb_step(lb_ctx *ctx, int32_t nsteps);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One step
+ * of lb_step (the fused collision and pull streaming, no bead force) without
+ * a context and without any allocation: it reads the stored state `src` of
+ * step `step` (the step counter keys the noise) and writes the stored state
+ * of step + 1 to `dst`; with `totals` != NULL it also writes the FP64 totals
+ * of the new state to device memory totals[4] = {sum rho, sum j_x, sum j_y,
+ * sum j_z}, the same bits lb_totals gives for a context with track_totals
+ * and the same block.  Nothing is synchronised; all work is enqueued on
+ * `stream` (a hipStream_t; NULL = null stream) of the current device, and
+ * src, dst, totals are device memory of that device, owned by the caller.
+ *   params: as for lb_create (walls, rounding and storage included), with
+ *           block 0 (256 threads) or 64..1024; -1 is refused (no launch
+ *           search without a context).
+ *   src, dst: the stored form of the state, P * N elements of the storage
+ *           type (P = 20 for LB_F32, 19 for 16-bit storage), non-overlapping.
+ *           Stored form: element (P z + i) nx ny + x + nx y holds, for
+ *           i < 19, A_i(r) = n_i(r + c_i) - a_i rho0 (the pre-collision
+ *           population of the site it streams to, shifted; FP16 values are
+ *           scaled by 2^8; with walls, n_{opp(i)}(r) - a_i rho0 where the
+ *           link r -> r + c_i crosses a wall), and for i = 19 (LB_F32 only)
+ *           the FP32 residual of the rest population, whose value is
+ *           A_0 + A_19.  A caller builds it once from [19][N] populations,
+ *           e.g. outside the captured region.
+ * The step kernel's per-block totals go to a static device array of
+ * 2^19 rows (16 MiB per device, held until the process ends): steps with
+ * more than 2^19 blocks (nz * ceil(nx ny / block)) are refused with
+ * LB_EINVAL; use a larger block.  Every call on a device shares that array:
+ * calls that overlap on one device (other streams, other threads) race on
+ * it and their totals are undefined; calls ordered on one stream do not.
+ * The first call on each device resolves the array's address
+ * (hipGetSymbolAddress), which allocates nothing.  Errors (LB_EINVAL for a
+ * bad argument, LB_EDEVICE for a launch failure) leave a message for
+ * lb_last_error(NULL); non-finite populations show up as non-finite
+ * totals. */
+int lb_step_noalloc(const lb_params *params, const void *src, void *dst, uint64_t step, double *totals,
+                    void *stream);
+
 /* Particle half of one coupled time step (Sec. "Force coupling"): half
  * drift; conservative forces at the half-step positions (bonds, WCA pairs,
  * fext); interpolation of u at each bead with the stencil's kernel
@@ -389,7 +427,8 @@ uint64_t lb_step_count(const lb_ctx *ctx);
 int lb_set_step_count(lb_ctx *ctx, uint64_t step);
 
 /* Message for the last error on this context ("" if none). ctx may be NULL
- * (then: the last lb_create failure). */
+ * (then: the last failure of lb_create, lb_create_batch or
+ * lb_step_noalloc). */
 const char *lb_last_error(const lb_ctx *ctx);
 
 #ifdef __cplusplus

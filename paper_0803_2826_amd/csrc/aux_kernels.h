@@ -253,9 +253,9 @@ __global__ void __launch_bounds__(256) k_mode_stats(const void *buf, Geom g, dou
 }
 
 // Column sums of a [rows][ncols] FP64 array (deterministic order), one block
-// per column, out[ncols].
+// per column, out[ncols]; add0 is added to column 0's sum (add0 + sum).
 __global__ void __launch_bounds__(256) k_reduce_cols(const double *__restrict__ in, int rows, int ncols,
-                                                     double *__restrict__ out)
+                                                     double *__restrict__ out, double add0)
 {
     __shared__ double red[256];
     const int c = blockIdx.x;
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(256) k_reduce_cols(const double *__restrict__ 
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = red[0];
+    if (threadIdx.x == 0) out[c] = c == 0 ? add0 + red[0] : red[0];
 }
 
 __global__ void k_noise_sample(uint32_t site0, uint32_t count, uint32_t step, CollideConst cc, float *out)

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <functional>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -129,6 +130,18 @@ struct lb_ctx {
 };
 
 static std::string g_create_error;
+
+// Static scratch of lb_step_noalloc (for callers that cannot allocate): the
+// step kernel's per-block FP64 totals rows, then one word for its device
+// error flag.  Each device holds its own copy from module load until the
+// process ends; host code uses the address hipGetSymbolAddress returns for
+// the current device (g_noalloc_scratch), never the array's name, which is a
+// host-side stand-in.
+constexpr size_t kNoallocRows = size_t(1) << 19;  // 16 MiB of totals rows
+static __device__ __align__(256) double scratch[4 * kNoallocRows + 32];
+constexpr int kMaxDevices = 64;
+static double *g_noalloc_scratch[kMaxDevices] = {};
+static std::mutex g_noalloc_mu;
 
 namespace {
 
@@ -334,6 +347,25 @@ int ensure_scratch(lb_ctx *c, size_t bytes)
     c->scratch_bytes = 0;
     if (hipMalloc(&c->scratch, bytes) != hipSuccess) return fail(c, LB_ENOMEM, "scratch allocation failed");
     c->scratch_bytes = bytes;
+    return LB_OK;
+}
+
+// Device address of the static scratch on the current device, resolved once
+// per device (with that device current).
+int noalloc_scratch(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, LB_EDEVICE, "lb_step_noalloc: no usable current HIP device");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, LB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_noalloc_scratch[dev];
     return LB_OK;
 }
 
@@ -640,6 +672,23 @@ int tape_reserve(lb_ctx *c, const lb_beads *b, TapeSlot *out)
     return LB_OK;
 }
 
+// Geometry and element size of a single box (z-major layout).
+void init_single_box(lb_ctx *c, const lb_params *p)
+{
+    const uint32_t nx = p->nx, ny = p->ny, nz = p->nz;
+    c->geo.nx = nx;
+    c->geo.ny = ny;
+    c->geo.nz = nz;
+    c->geo.nxny = nx * ny;
+    c->geo.N = nx * ny * nz;
+    c->geo.div_nx = make_fastdiv(nx);
+    c->geo.div_ny = make_fastdiv(ny);
+    c->geo.walls = (uint32_t)p->walls;
+    c->geo.zmajor = 1u;
+    c->geo.planes = state_planes(p->storage);
+    c->elem = storage_bytes(p->storage);
+}
+
 StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
 {
     StepArgs a;
@@ -919,18 +968,7 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     }
     c->stream = static_cast<hipStream_t>(stream);
     c->user_stream = c->stream;
-    const uint32_t nx = params->nx, ny = params->ny, nz = params->nz;
-    c->geo.nx = nx;
-    c->geo.ny = ny;
-    c->geo.nz = nz;
-    c->geo.nxny = nx * ny;
-    c->geo.N = nx * ny * nz;
-    c->geo.div_nx = make_fastdiv(nx);
-    c->geo.div_ny = make_fastdiv(ny);
-    c->geo.walls = (uint32_t)params->walls;
-    c->geo.zmajor = 1u;
-    c->geo.planes = state_planes(params->storage);
-    c->elem = storage_bytes(params->storage);
+    init_single_box(c, params);
     c->block = params->block > 0 ? params->block : 256;
     c->tuned = true;
     c->search = params->block == -1;
@@ -1224,6 +1262,46 @@ int lb_step(lb_ctx *c, int32_t nsteps)
     return LB_OK;
 }
 
+int lb_step_noalloc(const lb_params *params, const void *src, void *dst, uint64_t step, double *totals, void *stream)
+{
+    std::string msg;
+    const int v = validate(params, msg);
+    if (v != LB_OK) return fail(nullptr, v, msg);
+    if (params->block == -1) return fail(nullptr, LB_EINVAL, "lb_step_noalloc needs block 0 or 64..1024 (no launch search)");
+    if (!src || !dst) return fail(nullptr, LB_EINVAL, "src and dst must be non-NULL");
+    if (step > 0xffffffffull) return fail(nullptr, LB_EINVAL, "step must be < 2^32");
+    lb_ctx c;  // host bookkeeping only: no device memory is attached to it
+    c.p = *params;
+    c.stream = static_cast<hipStream_t>(stream);
+    init_single_box(&c, params);
+    const uintptr_t bytes = (uintptr_t)state_bytes(&c);
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(src), b0 = reinterpret_cast<uintptr_t>(dst);
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(nullptr, LB_EINVAL, "src and dst overlap");
+    c.block = params->block > 0 ? params->block : 256;
+    c.nblocks = (int)step_blocks(&c, c.block);
+    if ((size_t)c.nblocks > kNoallocRows)
+        return fail(nullptr, LB_EINVAL,
+                    "the step needs " + std::to_string(c.nblocks) + " blocks; the static scratch holds totals for " +
+                        std::to_string(kNoallocRows) + " (use a larger block)");
+    double *scr = nullptr;
+    LB_TRY(noalloc_scratch(&scr));
+    c.partials = scr;
+    c.flags = reinterpret_cast<int32_t *>(scr + 4 * kNoallocRows);
+    fill_collide_const(&c);
+    const StepArgs a = plain_step_args(&c, src, dst, (uint32_t)step);
+    const bool tot = totals != nullptr;
+    by_step_storage(c.p, [&](auto st) { launch_step_st<decltype(st)::value>(&c, a, tot, false); });
+    if (hipGetLastError() != hipSuccess) return fail(nullptr, LB_EDEVICE, "lb_step_noalloc: step launch failed");
+    if (tot) {
+        // same reduction order as lb_totals: column sums of the partial rows,
+        // mass + N rho0 in FP64
+        hipLaunchKernelGGL(k_reduce_cols, dim3(4), dim3(256), 0, c.stream, scr, c.nblocks, 4, totals,
+                           (double)c.geo.N * params->rho0);
+        if (hipGetLastError() != hipSuccess) return fail(nullptr, LB_EDEVICE, "lb_step_noalloc: totals launch failed");
+    }
+    return LB_OK;
+}
+
 int lb_couple(lb_ctx *c, const lb_beads *b)
 {
     if (!c) return LB_EINVAL;
@@ -1297,7 +1375,7 @@ int lb_moments(lb_ctx *c, double *rho, double *u)
 
 static int totals_from_partials(lb_ctx *c, const double *partials, int rows, double out[4])
 {
-    hipLaunchKernelGGL(k_reduce_cols, dim3(4), dim3(256), 0, c->stream, partials, rows, 4, c->dev_out);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(4), dim3(256), 0, c->stream, partials, rows, 4, c->dev_out, 0.0);
     LB_LAUNCH_CHECK(c, "reduce totals");
     double h[4] = {0, 0, 0, 0};
     LB_TRY(check(c, hipMemcpyAsync(h, c->dev_out, sizeof(h), hipMemcpyDeviceToHost, c->stream), "totals copy"));
@@ -1374,7 +1452,7 @@ int lb_mode_stats(lb_ctx *c, double var[19])
                                c->geo, c->p.rho0, c->scratch);
         });
     }
-    hipLaunchKernelGGL(k_reduce_cols, dim3(38), dim3(256), 0, c->stream, c->scratch, rows, 38, c->dev_out);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(38), dim3(256), 0, c->stream, c->scratch, rows, 38, c->dev_out, 0.0);
     LB_LAUNCH_CHECK(c, "mode_stats");
     double h[38];
     LB_TRY(check(c, hipMemcpyAsync(h, c->dev_out, sizeof(h), hipMemcpyDeviceToHost, c->stream), "mode stats copy"));
