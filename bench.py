@@ -20,8 +20,9 @@ Prints ONE JSON line with, beside the throughput:
                 timed region, against the 8 TB/s HBM peak, and beside it
                 the rate of a plain device copy of one population buffer
                 (the practical ceiling of a streaming kernel) and of the
-                step's 19-plane pull pattern alone (the ceiling of its
-                access pattern);
+                step's memory pattern alone (19 pulled planes and the
+                residual plane, no arithmetic: the ceiling of its access
+                pattern);
   cpu_baseline  the FP64 oracle on the host cores, timed on a bounded sample
                 of the same workload (a few coupled steps of the full box);
   forms         the other throughputs the metric names: FP32 and BF16-storage
@@ -125,79 +126,6 @@ def cpu_baseline(L: int, n_chains: int, length: int, steps: int):
         "sample": f"{steps} coupled steps (after 1 warm-up) of the full {L}^3 box with {n_chains}x{length} beads, "
                   f"FP64, OpenMP over sites; {dt:.1f} s",
     }
-
-
-def copy_ceiling(nbytes: int) -> tuple:
-    """(GB/s, threads per block) of the best plain streaming copy of nbytes
-    (read + write, the copy kernel of libbwprobe.so over 256 / 512 / 1024
-    threads per block): the practical HBM ceiling a streaming kernel can
-    reach."""
-    import ctypes
-
-    import torch
-
-    from paper_0803_2826_amd import build as hip_build
-
-    if not os.path.exists(hip_build.PROBE):
-        raise RuntimeError(f"{hip_build.PROBE} is not built (run __graft_entry__.build())")
-    P = ctypes.CDLL(hip_build.PROBE)
-    P.bw_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]
-    a = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    s = torch.cuda.current_stream()
-    best = (0.0, 0)
-    for block in (256, 512, 1024):
-        launch = lambda: P.bw_copy(a.data_ptr(), b.data_ptr(), nbytes, block, ctypes.c_void_p(s.cuda_stream))
-        if launch() != 0:
-            raise RuntimeError("bw_copy failed")
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(20):
-            launch()
-        e1.record(s)
-        torch.cuda.synchronize()
-        gbs = 2 * nbytes / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
-        best = max(best, (gbs, block))
-    del a, b
-    torch.cuda.empty_cache()
-    return best
-
-
-def pull_ceiling(L: int) -> tuple:
-    """(GB/s, threads per block) of the best run of the step's memory pattern
-    alone (bw_pull19: 19 planes pulled from the D3Q19 neighbours, no
-    arithmetic) over an L^3 box, or (None, None) if L is not a power of two."""
-    import ctypes
-
-    import torch
-
-    from paper_0803_2826_amd import build as hip_build
-
-    lg = L.bit_length() - 1
-    if (1 << lg) != L or not 4 <= lg <= 10:
-        return None, None
-    P = ctypes.CDLL(hip_build.PROBE)
-    P.bw_pull19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
-    N = L ** 3
-    a = torch.zeros(19 * N, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    s = torch.cuda.current_stream()
-    best = (0.0, 0)
-    for block in (256, 512, 1024):
-        launch = lambda: P.bw_pull19(a.data_ptr(), b.data_ptr(), lg, block, ctypes.c_void_p(s.cuda_stream))
-        if launch() != 0:
-            raise RuntimeError("bw_pull19 failed")
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(20):
-            launch()
-        e1.record(s)
-        torch.cuda.synchronize()
-        gbs = 2 * 19 * 4 * N / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
-        best = max(best, (gbs, block))
-    del a, b
-    torch.cuda.empty_cache()
-    return best
 
 
 def run_forms(L: int) -> dict:
@@ -414,15 +342,17 @@ def main() -> int:
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    from paper_0803_2826_amd.bw_ceilings import copy_ceiling, pull_ceiling
     ceiling, cblock = copy_ceiling(planes * 4 * N)
     roofline["copy_ceiling"] = {"achieved": round(ceiling, 1), "unit": "GB/s",
                                 "kernel": f"streaming copy (16 B per thread, {cblock} threads per block) of one "
                                           f"{planes * 4 * N / 1e9:.2f} GB population buffer",
                                 "frac_of_copy": round(achieved / ceiling, 4)}
-    pull, pblock = pull_ceiling(L)
+    pull, pblock = pull_ceiling(L, planes)
     if pull:
         roofline["pull_pattern_ceiling"] = {"achieved": round(pull, 1), "unit": "GB/s",
-                                            "kernel": f"the step's 19-plane pull pattern without arithmetic "
+                                            "kernel": f"the step's memory pattern without arithmetic: 19 planes "
+                                                      f"pulled, the residual plane read, 20 stored "
                                                       f"({pblock} threads per block)",
                                             "frac_of_pattern": round(achieved / pull, 4)}
 
