@@ -199,6 +199,18 @@ typedef struct {
 
 typedef struct lb_ctx lb_ctx;
 
+/* Two-rate relaxation (Sec. "D3Q19 model II": one even rate for the bulk,
+ * shear and even kinetic modes, one odd rate for the odd kinetic modes):
+ * sets gamma_shear = gamma_bulk = gamma_4a = gamma_4b = gamma_e and
+ * gamma_3a = gamma_3b = gamma_o in *params (the other fields are left as
+ * they are), with gamma_o chosen so that the product of the two relaxation
+ * times, Lambda = (1/(1 - gamma_e) - 1/2)(1/(1 - gamma_o) - 1/2), equals
+ * `magic`.  magic = 3/16 puts a stationary mid-link bounce-back wall
+ * exactly half way along the link for plane Poiseuille flow at every
+ * viscosity.  Host only.  Errors: LB_EINVAL (params NULL, |gamma_e| >= 1,
+ * magic <= 0 or not finite). */
+int lb_params_two_rate(double gamma_e, double magic, lb_params *params);
+
 /* Create a context: allocates two population buffers (2 * P * N * storage
  * bytes) and small bookkeeping on the current device, enqueues on `stream`
  * (a hipStream_t; NULL = the null stream).  P = 20 for LB_F32 storage,
@@ -261,8 +273,8 @@ int lb_launch_config(lb_ctx *ctx, int32_t force, int32_t out[4]);
  * file are not applied.  Bead state is caller-owned and saved by the caller;
  * a batch's VACF accumulators are not saved.  Both synchronise.  Errors:
  * LB_EIO (open / read / write failure, not a checkpoint, other layout),
- * LB_ESTATE (called between lb_couple and lb_step; lb_load while a tape is
- * recording). */
+ * LB_ESTATE (called between lb_couple and lb_step).  lb_load ends a tape
+ * (see lb_tape_begin). */
 int lb_save(lb_ctx *ctx, const char *path);
 int lb_load(lb_ctx *ctx, const char *path);
 
@@ -276,7 +288,10 @@ int lb_init_equilibrium(lb_ctx *ctx, const double *rho, const double *u);
 
 /* Copy the state in / out.  src/dst: device arrays [19][N] of type `dtype`
  * (LB_F64 or LB_F32).  shifted = 0: full populations n_i; shifted = 1:
- * deviations n_i - a_i rho0.  Storage rounding applies on the way in. */
+ * deviations n_i - a_i rho0.  Storage rounding applies on the way in (the
+ * rest population of LB_F32 storage keeps its FP64 value as value plus
+ * residual).  lb_set_populations and lb_init_equilibrium end a tape (see
+ * lb_tape_begin). */
 int lb_set_populations(lb_ctx *ctx, const void *src, int32_t dtype, int32_t shifted);
 int lb_get_populations(lb_ctx *ctx, void *dst, int32_t dtype, int32_t shifted);
 
@@ -385,7 +400,13 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * reverse sweep recomputes no step of the last segment (none at all when
  * checkpoint_every >= T; a second lb_backward on the same tape recomputes
  * every segment if the first one had more than one).  If they do not fit,
- * recording goes on without them and lb_backward allocates them itself.
+ * recording goes on without them and lb_backward allocates them itself;
+ * they are also left to lb_backward when they would take more than half of
+ * the device's free memory (T is not known at lb_tape_begin).
+ * A tape lasts until the next lb_tape_begin; a call that replaces the state
+ * or the step counter (lb_set_populations, lb_init_equilibrium,
+ * lb_set_step_count, lb_load) ends it, so a later lb_backward returns
+ * LB_ESTATE.
  * Taped coupled steps (lb_couple before lb_step) are differentiated too:
  * each lb_couple while recording keeps its particle half on the device (P
  * at the start, R', F^c and P'': 12 doubles per bead, and each stencil
@@ -410,8 +431,9 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  *                     coupled step (device FP64 [n][3]; NULL = not wanted);
  * without taped coupled steps they are ignored.  lb_backward is
  * lb_backward_coupled with all four NULL.
- * Errors: LB_ESTATE (no tape, or called between lb_couple and lb_step;
- * lb_tape_begin between lb_couple and lb_step), LB_EUNSUPPORTED (a batch
+ * Errors: LB_ESTATE (no tape, a tape ended by one of the calls above, or
+ * called between lb_couple and lb_step; lb_tape_begin between lb_couple and
+ * lb_step), LB_EUNSUPPORTED (a batch
  * context; the bead count changed between taped coupled steps), LB_ENOMEM. */
 int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
 int lb_backward(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3]);
@@ -422,7 +444,8 @@ int lb_backward_coupled(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, const d
 int lb_sync(lb_ctx *ctx);
 
 /* Step counter (keys the noise).  lb_set_step_count lets a restarted run
- * continue the same random stream. */
+ * continue the same random stream; it ends a tape (see lb_tape_begin) and
+ * returns LB_ESTATE between lb_couple and lb_step. */
 uint64_t lb_step_count(const lb_ctx *ctx);
 int lb_set_step_count(lb_ctx *ctx, uint64_t step);
 

@@ -31,7 +31,7 @@ EXPORTS = (
     "lb_create", "lb_destroy", "lb_init_equilibrium", "lb_set_populations", "lb_get_populations", "lb_step",
     "lb_couple", "lb_moments", "lb_totals", "lb_totals_exact", "lb_mode_stats", "lb_noise_sample", "lb_sync", "lb_step_count",
     "lb_set_step_count", "lb_last_error", "lb_create_batch", "lb_vacf", "lb_launch_config", "lb_save", "lb_load", "lb_backward_coupled",
-    "lb_tape_begin", "lb_backward", "lb_step_noalloc",
+    "lb_tape_begin", "lb_backward", "lb_step_noalloc", "lb_params_two_rate",
 )
 
 
@@ -125,6 +125,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.lb_save.argtypes = [vp, ctypes.c_char_p]
     L.lb_load.argtypes = [vp, ctypes.c_char_p]
     L.lb_step_noalloc.argtypes = [ctypes.POINTER(lb_params), vp, vp, ctypes.c_uint64, vp, vp]
+    L.lb_params_two_rate.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.POINTER(lb_params)]
     L.lb_last_error.argtypes = [vp]
     L.lb_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

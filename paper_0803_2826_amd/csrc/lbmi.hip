@@ -454,6 +454,19 @@ int settle_state(lb_ctx *c)
     return LB_OK;
 }
 
+void free_tape(lb_ctx *c);
+
+// A call that replaces the state or the step counter ends a tape: the
+// state it sets is not the end of the taped trajectory.  The state leaves
+// the segment buffer first (the taped steps may have left it in a slot).
+int end_tape(lb_ctx *c)
+{
+    if (!c->taping) return LB_OK;
+    LB_TRY(settle_state(c));
+    free_tape(c);
+    return LB_OK;
+}
+
 void free_tape(lb_ctx *c)
 {
     for (void *p : c->checkpoints) (void)hipFree(p);
@@ -953,6 +966,20 @@ int batch_step(lb_ctx *c, int32_t nsteps)
 
 extern "C" {
 
+int lb_params_two_rate(double gamma_e, double magic, lb_params *params)
+{
+    if (!params) return fail(nullptr, LB_EINVAL, "params is NULL");
+    if (!(std::fabs(gamma_e) < 1.0)) return fail(nullptr, LB_EINVAL, "two-rate relaxation needs |gamma_e| < 1");
+    if (!(magic > 0.0) || !std::isfinite(magic)) return fail(nullptr, LB_EINVAL, "magic must be finite and > 0");
+    // relaxation times tau = 1 / (1 - gamma); Lambda = (tau_e - 1/2)(tau_o - 1/2)
+    const double tau_e = 1.0 / (1.0 - gamma_e);
+    const double tau_o = 0.5 + magic / (tau_e - 0.5);
+    const double gamma_o = 1.0 - 1.0 / tau_o;
+    params->gamma_shear = params->gamma_bulk = params->gamma_4a = params->gamma_4b = gamma_e;
+    params->gamma_3a = params->gamma_3b = gamma_o;
+    return LB_OK;
+}
+
 int lb_create(const lb_params *params, void *stream, lb_ctx **out)
 {
     std::string msg;
@@ -1142,6 +1169,7 @@ int lb_init_equilibrium(lb_ctx *c, const double *rho, const double *u)
         LB_LAUNCH_CHECK(c, "init_equilibrium");
         return LB_OK;
     }
+    LB_TRY(end_tape(c));
     by_storage(c->p.storage, [&](auto st) {
         hipLaunchKernelGGL((k_init_equilibrium<decltype(st)::value>), dim3(grid_for(c->geo.N, 256)), dim3(256), 0,
                            c->stream, c->bufA, c->geo, c->p.rho0, rho, u);
@@ -1177,6 +1205,7 @@ int lb_set_populations(lb_ctx *c, const void *src, int32_t dtype, int32_t shifte
             site0 += d.geo.N;
         }
     } else {
+        LB_TRY(end_tape(c));
         one(c->bufA, c->geo, src);
     }
     LB_LAUNCH_CHECK(c, "set_populations");
@@ -1499,8 +1528,16 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
     // segment buffer, so the reverse sweep recomputes no step of the last
     // segment (none at all when checkpoint_every covers the whole run); if
     // the buffer does not fit, the sweep recomputes every segment
-    const bool fits = (size_t)checkpoint_every <= SIZE_MAX / state_bytes(c);
+    // The buffer is taken up front only while it leaves at least half of the
+    // device's free memory to the checkpoints, the backward buffers and the
+    // caller (T is not known yet); otherwise the reverse sweep allocates it
+    // and recomputes every segment.
+    bool fits = (size_t)checkpoint_every <= SIZE_MAX / state_bytes(c);
     const size_t need = fits ? (size_t)checkpoint_every * state_bytes(c) : SIZE_MAX;
+    if (fits && c->seg_bytes < need) {
+        size_t free_b = 0, total_b = 0;
+        fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess && need <= (free_b + c->seg_bytes) / 2;
+    }
     if (fits && c->seg_bytes < need) {
         (void)hipFree(c->seg);
         c->seg = nullptr;
@@ -1540,8 +1577,12 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
     LB_TRY(use_device(c));
     const size_t N = c->geo.N, n19 = 19 * N;
+    if (c->step < c->tape_step0 || c->tape_k < 1) return fail(c, LB_ESTATE, "the tape does not match the step counter");
     const uint64_t T = c->step - c->tape_step0;
     const int K = c->tape_k;
+    // one slot per taped step, one checkpoint at the start and after every K steps
+    if (T != (uint64_t)c->tape_slot.size() || (uint64_t)c->checkpoints.size() != 1 + T / (uint64_t)K)
+        return fail(c, LB_ESTATE, "the tape does not match the steps taken since lb_tape_begin");
     const size_t sb = state_bytes(c);
     const int nbd = c->tape_nb;
     const bool coupled = !c->tape_beads.empty();
@@ -1939,6 +1980,11 @@ int lb_set_step_count(lb_ctx *c, uint64_t step)
 {
     if (!c) return LB_EINVAL;
     if (step > 0xffffffffull) return fail(c, LB_EINVAL, "step counter must be < 2^32");
+    if (c->pending_force) return fail(c, LB_ESTATE, "lb_set_step_count between lb_couple and lb_step");
+    if (!c->batch) {
+        LB_TRY(use_device(c));
+        LB_TRY(end_tape(c));
+    }
     c->step = step;
     if (c->batch) {
         LB_TRY(use_device(c));
@@ -2025,7 +2071,6 @@ int lb_load(lb_ctx *c, const char *path)
     if (!c) return LB_EINVAL;
     if (!path) return fail(c, LB_EINVAL, "path is NULL");
     if (c->pending_force) return fail(c, LB_ESTATE, "lb_load between lb_couple and lb_step");
-    if (c->taping) return fail(c, LB_ESTATE, "lb_load while a tape is recording");
     LB_TRY(use_device(c));
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(c, LB_EIO, std::string("cannot open for reading: ") + path);
@@ -2052,6 +2097,7 @@ int lb_load(lb_ctx *c, const char *path)
     std::fclose(f);
     if (!why.empty()) return fail(c, LB_EIO, why + ": " + path);
     if (h.step > 0xffffffffull) return fail(c, LB_EIO, "checkpoint step counter out of range");
+    if (!c->batch) LB_TRY(end_tape(c));
     {
         Join j(c);
         LB_TRY(check(c, hipMemcpyAsync(c->bufA, host.data(), bytes, hipMemcpyHostToDevice, c->stream), "state copy"));

@@ -19,20 +19,18 @@ _STORAGE = {"f32": LB_F32, "bf16": LB_BF16, "f16": LB_F16, LB_F32: LB_F32, LB_BF
 
 
 def two_rate(gamma_e: float, magic: float = 3.0 / 16.0) -> dict:
-    """Two-rate relaxation (Sec. "D3Q19 model II": a single even rate for
-    bulk, shear and the even kinetic modes, gamma_v = gamma_s = gamma_4a =
-    gamma_4b = gamma_e, and a single odd rate gamma_3a = gamma_3b = gamma_o).
-    gamma_o follows from the product of the two relaxation times,
-    Lambda = (1/(1 - gamma_e) - 1/2)(1/(1 - gamma_o) - 1/2); Lambda = 3/16
-    puts a stationary bounce-back wall exactly half way along the link for
-    plane Poiseuille flow.  Returns keyword arguments for FluidParams."""
-    if not abs(gamma_e) < 1.0 or not magic > 0.0:
-        raise ValueError("two_rate needs |gamma_e| < 1 and magic > 0")
-    te = 1.0 / (1.0 - gamma_e)
-    to = 0.5 + magic / (te - 0.5)
-    go = 1.0 - 1.0 / to
-    return dict(gamma_shear=gamma_e, gamma_bulk=gamma_e, gamma_4a=gamma_e, gamma_4b=gamma_e, gamma_3a=go,
-                gamma_3b=go)
+    """Two-rate relaxation (Sec. "D3Q19 model II"): keyword arguments for
+    FluidParams from lb_params_two_rate, which sets the even rate gamma_e on
+    the bulk, shear and even kinetic modes and the odd rate on the odd
+    kinetic modes so that the product of the two relaxation times equals
+    `magic` (3/16: a stationary bounce-back wall exactly half way along the
+    link for plane Poiseuille flow)."""
+    p = _lib.lb_params()
+    rc = _lib.load().lb_params_two_rate(float(gamma_e), float(magic), ctypes.byref(p))
+    if rc != 0:
+        raise ValueError(_lib.load().lb_last_error(None).decode())
+    return dict(gamma_shear=p.gamma_shear, gamma_bulk=p.gamma_bulk, gamma_4a=p.gamma_4a, gamma_4b=p.gamma_4b,
+                gamma_3a=p.gamma_3a, gamma_3b=p.gamma_3b)
 
 
 @dataclass
@@ -176,6 +174,7 @@ class Lattice:
         if getattr(self, "ctx", None):
             self.L.lb_destroy(self.ctx)
             self.ctx = None
+        self._tape_refs = []
 
     def __del__(self):
         try:
@@ -205,6 +204,7 @@ class Lattice:
         self._check(self.L.lb_init_equilibrium(self.ctx, r.data_ptr() if r is not None else None,
                                                uu.data_ptr() if uu is not None else None))
         self._keep = (r, uu)
+        self._tape_ended()
 
     def set_populations(self, n, shifted: bool = False) -> None:
         t = torch.as_tensor(n, device=self.device)
@@ -216,6 +216,12 @@ class Lattice:
         dt = LB_F64 if t.dtype == torch.float64 else LB_F32
         self._check(self.L.lb_set_populations(self.ctx, t.data_ptr(), dt, 1 if shifted else 0))
         self._keep = t
+        self._tape_ended()
+
+    def _tape_ended(self) -> None:
+        # the library ends a tape when the state or the step counter is replaced
+        self._taped_beads = None
+        self._tape_refs = []
 
     def get_populations(self, dtype=torch.float64, shifted: bool = False) -> torch.Tensor:
         out = torch.empty((Q, self.params.nz, self.params.ny, self.params.nx), dtype=dtype, device=self.device)
@@ -232,6 +238,10 @@ class Lattice:
         self._check(self.L.lb_couple(self.ctx, ctypes.byref(b)))
         if getattr(self, "_taped_beads", None) is not None:
             self._taped_beads = beads.n
+            # the tape keeps this call's lb_beads descriptor (mass, zeta,
+            # bonds, fext pointers) until backward: keep the tensors alive
+            if not any(x is beads for x in self._tape_refs):
+                self._tape_refs.append(beads)
 
     def coupled_step(self, beads: DeviceBeads) -> None:
         """Particle update + spreading, then one LB step (the paper's schedule)."""
@@ -268,6 +278,7 @@ class Lattice:
     def tape_begin(self, checkpoint_every: int) -> None:
         self._check(self.L.lb_tape_begin(self.ctx, int(checkpoint_every)))
         self._taped_beads = 0
+        self._tape_refs = []
 
     def backward(self, dL_dnT: torch.Tensor):
         """dL/dn(t0) and dL/dg for the steps taken since tape_begin."""
@@ -321,6 +332,7 @@ class Lattice:
     def load(self, path: str) -> None:
         """Resume from a checkpoint file of the same layout (lb_load)."""
         self._check(self.L.lb_load(self.ctx, os.fsencode(path)))
+        self._tape_ended()
 
     def launch_config(self, force: bool = False):
         """(threads per block, blocks per step, tiles per block, XCD mapping) of
@@ -336,6 +348,7 @@ class Lattice:
     @step_count.setter
     def step_count(self, v: int) -> None:
         self._check(self.L.lb_set_step_count(self.ctx, int(v)))
+        self._tape_ended()
 
 
 class BatchLattice(Lattice):

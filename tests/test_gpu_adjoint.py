@@ -141,6 +141,45 @@ def test_backward_error_paths(orc, lat):
     B.close()
 
 
+@pytest.mark.parametrize("replace", ["set_populations", "init_equilibrium", "step_count"])
+def test_replacing_the_state_ends_the_tape(orc, lat, replace):
+    """A call that replaces the state or the step counter in the middle of a
+    tape ends it: lb_backward then returns LB_ESTATE from its host-side
+    checks (it never indexes a tape that does not match the steps).  A new
+    tape after such a call differentiates as usual, matching the oracle."""
+    import torch
+    from paper_0803_2826_amd._lib import LB_ESTATE, LBError
+    rng = np.random.default_rng(6)
+    po = orc.Params(nx=8, ny=6, nz=5, kT=1e-4, seed=3)
+    pd = lat.FluidParams(nx=8, ny=6, nz=5, kT=1e-4, seed=3, track_totals=False)
+    n0 = orc.init_equilibrium(po, u=rng.normal(scale=0.02, size=(3, 5, 6, 8)))
+    w = rng.normal(size=n0.shape)
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n0))
+    dev.tape_begin(2)                       # the forward writes its step buffers into the segment slots
+    dev.step(3)
+    if replace == "set_populations":
+        dev.set_populations(torch.from_numpy(n0))
+    elif replace == "init_equilibrium":
+        dev.init_equilibrium()
+    else:
+        dev.step_count = 7
+    dev.step(2)
+    with pytest.raises(LBError) as ei:
+        dev.backward(torch.from_numpy(w))
+    assert ei.value.code == LB_ESTATE
+    # a fresh tape on the same context
+    dev.step_count = 0
+    dev.set_populations(torch.from_numpy(n0))
+    n0r = dev.get_populations().cpu().numpy()
+    dev.tape_begin(2)
+    dev.step(5)
+    dn0, dg = dev.backward(torch.from_numpy(w))
+    lam0, gbar = orc.backward(po, n0r, 5, w)
+    dev.close()
+    assert np.abs(dn0.cpu().numpy() - lam0).max() / np.abs(lam0).max() <= REL_TOL
+
+
 @pytest.mark.slow
 def test_full_size_directional_derivative(orc, lat):
     """128^3 (the differentiation workload's box), 10 steps: <dL/dn0, v> from the

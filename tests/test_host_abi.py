@@ -111,3 +111,26 @@ def test_valid_request_without_gpu_fails_loudly(L):
         pytest.skip("a GPU is present")
     rc, msg = create(L, params())
     assert rc == LB_EDEVICE and msg
+
+
+def test_params_two_rate(L):
+    """lb_params_two_rate (Sec. "D3Q19 model II"): one even rate on the bulk,
+    shear and even kinetic modes, one odd rate on the odd kinetic modes, the
+    product of the relaxation times (tau - 1/2) equal to `magic`; other
+    fields untouched; bad arguments refused on the host."""
+    from paper_0803_2826_amd._lib import LB_EINVAL
+    p = params(kT=3e-4, seed=11)
+    assert L.lb_params_two_rate(0.25, 3.0 / 16.0, ctypes.byref(p)) == 0
+    te, to = 1.0 / (1.0 - p.gamma_shear), 1.0 / (1.0 - p.gamma_3a)
+    assert (te - 0.5) * (to - 0.5) == pytest.approx(3.0 / 16.0, rel=1e-14)
+    assert p.gamma_bulk == p.gamma_4a == p.gamma_4b == p.gamma_shear == 0.25
+    assert p.gamma_3b == p.gamma_3a and abs(p.gamma_3a) < 1.0
+    assert p.kT == 3e-4 and p.seed == 11 and p.nx == 8
+    # tau_e = 1 and Lambda = 3/16: tau_o = 7/8 exactly
+    q = params()
+    assert L.lb_params_two_rate(0.0, 3.0 / 16.0, ctypes.byref(q)) == 0
+    assert 1.0 / (1.0 - q.gamma_3a) == pytest.approx(7.0 / 8.0, rel=1e-15)
+    for ge, magic in ((1.0, 0.1875), (-1.0, 0.1875), (0.2, 0.0), (0.2, -1.0), (float("nan"), 0.1875),
+                      (0.2, float("inf"))):
+        assert L.lb_params_two_rate(ge, magic, ctypes.byref(q)) == LB_EINVAL
+    assert L.lb_params_two_rate(0.2, 0.1875, None) == LB_EINVAL
