@@ -28,14 +28,16 @@ Prints ONE JSON line with, beside the throughput:
   forms         the other throughputs the metric names: FP32 and BF16-storage
                 MLUPS (nearest and stochastic rounding, kT > 0 and kT = 0)
                 on the same box without beads and, per storage type, on the
-                512^3 box of the precision workload, the batched form (512 replica boxes, edges drawn from
-                {24, 32, 40, 48, 64}, HIP graph replay) and the
-                differentiation form (taped forward and adjoint of 500
-                coupled steps at 128^3 with 16 x 32 beads, the whole tape
-                resident in HBM, 80 GB, and with checkpoints every 50
-                steps), and the coupled step with Kremer-Grest chains (FENE
-                bonds, WCA pairs with a cell list) in place of the harmonic
-                ones.
+                512^3 box of the precision workload, the batched form (512
+                replica boxes, edges drawn from {24, 32, 40, 48, 64}, HIP
+                graph replay; with and without the ensemble VACF reduced on
+                the device) and the differentiation form (taped forward and
+                adjoint of 500 coupled steps at 128^3 with 16 x 32 beads and
+                the probe + drag loss, checkpoints every 50 steps, and with
+                the whole tape resident in HBM; the gradient's error against
+                stored FP64 oracle central differences), and the coupled
+                step with Kremer-Grest chains (FENE bonds, WCA pairs with a
+                cell list) in place of the harmonic ones.
 """
 from __future__ import annotations
 
@@ -58,6 +60,8 @@ KT = 1e-4
 # the explicit bead-fluid scheme diverge within ten steps at zeta = 20, m = 1.
 K_BOND = 10.0 * KT
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_256.json")
+# FP64 oracle central differences of the differentiation workload's loss
+C5_GOLDEN = os.path.join(ROOT, "tests", "golden", "c5_directional.json")
 # coupled steps of the workload over which the relative mass drift is reported
 DRIFT_STEPS = 1000
 # Friction of the Kremer-Grest chains: velocity relaxation time m/zeta = 5 steps
@@ -134,6 +138,7 @@ def run_forms(L: int) -> dict:
     import torch
 
     from paper_0803_2826_amd import forms, lattice
+    from paper_0803_2826_amd.inputs import DIFF_WORKLOAD
 
     import numpy as np
 
@@ -168,40 +173,43 @@ def run_forms(L: int) -> dict:
     b = forms.batch_study(nbox=512, steps=200, kT=KT, lags=0, graph_steps=10)
     out["batched_mlups"] = round(b["mlups"], 1)
     out["batched_sites"] = b["sites"]
+    # the batched workload as specified: 500 steps, the ensemble VACF of
+    # every replica sampled and reduced on the device every step (persistent
+    # launch), graph replay; C(tau)/C(0) per edge class against lambda(k)^tau
+    bv = forms.batch_study(nbox=512, steps=500, kT=KT, lags=32, graph_steps=10)
+    out["batched_vacf_mlups"] = round(bv["mlups"], 1)
+    out["batched_vacf_launch"] = {"threads": bv["launch"][0], "blocks": bv["launch"][1],
+                                  "tiles_per_block": bv["launch"][2]}
+    out["batched_vacf_max_abs_dev"] = {str(k): round(v["max_abs_dev"], 4) for k, v in bv["vacf_by_edge"].items()}
+    out["batched_vacf_edge_counts"] = {str(k): v["count"] for k, v in bv["vacf_by_edge"].items()}
     print("# forms: batch done", file=sys.stderr, flush=True)
-    from paper_0803_2826_amd.inputs import random_walk_chains
 
-    Lb, T = 128, 500
-    p = lattice.FluidParams(nx=Lb, ny=Lb, nz=Lb, kT=KT, seed=0, body_force=(1e-5, 0.0, 0.0), track_totals=False)
-    lat = lattice.Lattice(p)
-    lat.init_equilibrium()
-    pos, mom, bonds = random_walk_chains(16, 32, (Lb, Lb, Lb), seed=0)
-    nb = pos.shape[0]
-    beads = lattice.DeviceBeads(pos, mom, np.ones(nb), np.full(nb, 20.0), bonds, K_BOND, 1.0)
-    lat.step(2)
-    w = torch.randn(19 * Lb ** 3, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    # K = T: every step buffer stays on the tape (T x 159 MB), nothing is
-    # recomputed; K = 50: checkpoints, one recomputed step per backward step
-    # outside the last segment.  The first tape_begin allocates the buffers.
-    for K, tag in ((T, ""), (50, "_k50")):
-        lat.tape_begin(K)
-        torch.cuda.synchronize()
-        e[0].record(lat.stream)
-        lat.tape_begin(K)
-        for _ in range(T):
-            lat.coupled_step(beads)
-        e[1].record(lat.stream)
-        lat.backward_coupled(w)
-        e[2].record(lat.stream)
-        torch.cuda.synchronize()
-        fwd_ms, bwd_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
-        out["taped_forward_mlups" + tag] = round(Lb ** 3 * T / (fwd_ms * 1e-3) / 1e6, 1)
-        out["backward_mlups" + tag] = round(Lb ** 3 * T / (bwd_ms * 1e-3) / 1e6, 1)
-    lat.close()
-    out["backward_config"] = (f"{Lb}^3, {T} coupled steps with 16 x 32 beads (zeta 20, k 10 kT), the whole tape "
-                              f"resident (_k50: checkpoints every 50 steps), FP32 fluid, FP64 beads; gradients "
-                              f"w.r.t. n(0), g, R(0), P(0)")
+    # the differentiation workload (128^3, 16 x 32 beads, 500 coupled steps,
+    # probe + drag loss): checkpoints every 50 steps (the workload's own
+    # interval; the reverse sweep recomputes all but the last segment), and
+    # the whole tape resident in HBM (84 GB, nothing recomputed); the error
+    # of the timed K = 50 gradient against the FP64 oracle's central
+    # differences along seeded directions, stored by
+    # tests/golden/make_c5_directional.py
+    W = DIFF_WORKLOAD
+    for K, tag in ((W["checkpoint_every"], ""), (W["steps"], "_tape_resident")):
+        d = forms.differentiation_study(K)
+        out["taped_forward_mlups" + tag] = round(d["sites"] * d["steps"] / (d["forward_ms"] * 1e-3) / 1e6, 1)
+        out["backward_mlups" + tag] = round(d["sites"] * d["steps"] / (d["backward_ms"] * 1e-3) / 1e6, 1)
+        if tag == "" and os.path.exists(C5_GOLDEN):
+            with open(C5_GOLDEN) as f:
+                golden = json.load(f)
+            errs = forms.directional_errors(d, golden)
+            out["backward_grad_rel_err"] = max(e["rel_err"] for e in errs)
+            out["backward_grad_check"] = [{k: e[k] for k in ("seed", "gpu", "oracle_fd", "rel_err", "loss_rel_err")}
+                                          for e in errs]
+        del d
+    out["backward_config"] = (f"{W['L']}^3, {W['steps']} coupled steps from rest with {W['chains']} x "
+                              f"{W['length']} beads (zeta {W['zeta']:g}, k 10 kT), probe + drag loss; "
+                              f"checkpoints every {W['checkpoint_every']} steps (_tape_resident: all {W['steps']} "
+                              f"step buffers kept, nothing recomputed); FP32 fluid, FP64 beads; gradients w.r.t. "
+                              f"n(0), g, R(0), P(0); grad error: directional derivatives against FP64 oracle "
+                              f"central differences (eps 1e-4)")
     print("# forms: backward done", file=sys.stderr, flush=True)
 
     # Kremer-Grest chains: the same box and chain count with FENE bonds and

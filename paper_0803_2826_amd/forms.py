@@ -7,6 +7,11 @@ precision_study  storage FP32 / BF16 / FP16 (shifted deviations, FP32
                  form, plus MLUPS.
 batch_study      many uneven replica boxes in one persistent launch per step
                  (HIP graph replay): MLUPS and the ensemble VACF.
+differentiation_study
+                 the differentiation workload (inputs.DIFF_WORKLOAD): taped
+                 forward, the loss gradient at the final state, the reverse
+                 sweep (lb_backward_coupled), with their timings and the
+                 gradients w.r.t. n(0), g, R(0), P(0).
 
 The closed forms used as references (both pinned against the FP64 oracle in
 the test suite):
@@ -25,7 +30,7 @@ import time
 import numpy as np
 import torch
 
-from .inputs import shear_wave
+from .inputs import DIFF_WORKLOAD, direction, random_walk_chains, shear_wave
 from .lattice import BatchLattice, DeviceBeads, FluidParams, Lattice
 
 W_K = np.array([1, 1 / 3, 1 / 3, 1 / 3, 2 / 3, 4 / 3, 4 / 9, 1 / 9, 1 / 9, 1 / 9, 2 / 3, 2 / 3, 2 / 3, 2 / 9, 2 / 9, 2 / 9,
@@ -149,8 +154,11 @@ def batch_study(nbox: int = 512, steps: int = 500, kT: float = 1e-4, lags: int =
         sel = edges == Lb
         lam = 1 - (2 / 3) * math.sin(math.pi / Lb) ** 2
         c = C[sel].mean(axis=0)
-        by_L[int(Lb)] = {"count": int(sel.sum()), "C0": float(c[0]), "C_ratio": [float(x) for x in (c / c[0])[:8]],
-                         "lambda_pow": [float(lam ** k) for k in range(8)]}
+        ratio = c / c[0]
+        pw = lam ** np.arange(len(c))
+        by_L[int(Lb)] = {"count": int(sel.sum()), "C0": float(c[0]), "C_ratio": [float(x) for x in ratio[:8]],
+                         "lambda_pow": [float(x) for x in pw[:8]],
+                         "max_abs_dev": float(np.abs(ratio - pw).max())}
     B.close()
     return {"sites": int(sum(d[0] * d[1] * d[2] for d in dims)), "ms_per_step": ms,
             "mlups": sum(d[0] * d[1] * d[2] for d in dims) / (ms * 1e-3) / 1e6, "launch": cfg, "samples": ns,
@@ -197,3 +205,68 @@ def settling_study(L: int = 16, steps: int = 2500, a0: float = 1.0, force: float
                   "mobility_spread": float((mob.max() - mob.min()) / mob.mean())}
     return out
 
+
+
+def differentiation_study(checkpoint_every: int, steps: int | None = None, workload: dict = DIFF_WORKLOAD):
+    """One run of the differentiation workload: `steps` coupled steps from the
+    fluid at rest with the workload's chains, taped with a checkpoint every
+    `checkpoint_every` steps (the step buffers are allocated before the
+    timed forward), the probe + drag loss at the final state (its gradient
+    w.r.t. n(T), R(T), P(T) and its direct dependence on g through
+    u = (sum n c + g/2)/rho, by torch autograd), then the reverse sweep.
+    Returns the timings (events on the context stream), the loss and the
+    gradients (dL/dn(0) [19 N] float64, dL/dg [3], dL/dR(0), dL/dP(0)
+    [n, 3]) on the host."""
+    from .autograd import probe_drag_loss
+    W = workload
+    L, T = W["L"], steps or W["steps"]
+    lo, hi = W["probe"]
+    p = FluidParams(nx=L, ny=L, nz=L, kT=W["kT"], seed=W["seed"], body_force=W["g"], track_totals=False)
+    lat = Lattice(p)
+    lat.init_equilibrium()
+    pos, mom, bonds = random_walk_chains(W["chains"], W["length"], (L, L, L), seed=W["chain_seed"])
+    nb = pos.shape[0]
+    beads = DeviceBeads(pos, mom, np.full(nb, W["mass"]), np.full(nb, W["zeta"]), bonds, W["k_bond"], W["r0"])
+    lat.tape_begin(checkpoint_every)  # allocates the segment buffer outside the timed region
+    lat.tape_begin(checkpoint_every)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record(lat.stream)
+    for _ in range(T):
+        lat.coupled_step(beads)
+    ev[1].record(lat.stream)
+    nT = lat.get_populations(dtype=torch.float64).requires_grad_()
+    g_t = torch.tensor(W["g"], dtype=torch.float64, device=nT.device, requires_grad=True)
+    RT = beads.pos.detach().clone().requires_grad_()
+    PT = beads.mom.detach().clone().requires_grad_()
+    loss = probe_drag_loss(nT, g_t, RT, PT, beads.mass, beads.zeta, lo, hi)
+    loss.backward()
+    torch.cuda.synchronize()
+    ev[2].record(lat.stream)
+    dn0, dg, dR0, dP0 = lat.backward_coupled(nT.grad.contiguous(), RT.grad, PT.grad)
+    ev[3].record(lat.stream)
+    torch.cuda.synchronize()
+    out = {"sites": L ** 3, "steps": T, "checkpoint_every": checkpoint_every,
+           "forward_ms": ev[0].elapsed_time(ev[1]), "backward_ms": ev[2].elapsed_time(ev[3]),
+           "loss": float(loss.detach()),
+           "dn0": dn0.detach().reshape(-1).double().cpu().numpy(),
+           "dg": np.asarray(dg, dtype=np.float64) + g_t.grad.detach().cpu().numpy(),
+           "dR0": dR0.detach().cpu().numpy(), "dP0": dP0.detach().cpu().numpy()}
+    lat.close()
+    return out
+
+
+def directional_errors(study: dict, golden: dict) -> list:
+    """Relative errors of <grad, v> from a differentiation_study against the
+    stored central differences d_v L of the FP64 oracle (one per seeded
+    direction of inputs.direction), and of the loss against their mean
+    L(x +- eps v) / 2."""
+    out = []
+    nb = study["dR0"].shape[0]
+    for d in golden["directions"]:
+        vn, vg, vR, vP = direction(study["dn0"].size, nb, d["seed"])
+        got = float(study["dn0"] @ vn + study["dg"] @ vg + (study["dR0"] * vR).sum() + (study["dP0"] * vP).sum())
+        out.append({"seed": d["seed"], "gpu": got, "oracle_fd": d["d_v_L"],
+                    "rel_err": abs(got - d["d_v_L"]) / abs(d["d_v_L"]),
+                    "loss_rel_err": abs(study["loss"] - d["L_mid"]) / abs(d["L_mid"])})
+    return out

@@ -102,3 +102,21 @@ def kremer_grest_chains(n_chains: int, length: int, box, seed: int, bond: float 
     bonds = np.array([(c * length + k, c * length + k + 1) for c in range(n_chains) for k in range(length - 1)],
                      dtype=np.int32).reshape(-1, 2)
     return pos, np.zeros_like(pos), bonds
+
+
+# The differentiation workload (lattice units): a 128^3 box at rest, kT 1e-4,
+# Philox seed 0, uniform body force g, 16 random-walk chains of 32 beads
+# (harmonic bonds k = 10 kT, r0 = 1, zeta = 20, m = 1), 500 coupled steps with
+# a checkpoint every 50; loss = mean abs(u)^2 over the probe cube [56, 72)^3
+# plus the mean squared bead drag abs(zeta (P/m - u(R)))^2 at the final step.
+DIFF_WORKLOAD = dict(L=128, steps=500, checkpoint_every=50, chains=16, length=32, chain_seed=0, zeta=20.0,
+                     k_bond=1e-3, r0=1.0, mass=1.0, kT=1e-4, seed=0, g=(1e-5, 0.0, 0.0), probe=(56, 72))
+
+
+def direction(n_pops: int, n_beads: int, seed: int, scale_n: float = 1e-3, scale_g: float = 1e-6,
+              scale_R: float = 1e-5, scale_P: float = 1e-3):
+    """A seeded random direction (v_n [n_pops], v_g [3], v_R [n_beads, 3],
+    v_P [n_beads, 3]) in (n(0), g, R(0), P(0)) for directional derivatives."""
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=n_pops) * scale_n, rng.normal(size=3) * scale_g, rng.normal(size=(n_beads, 3)) * scale_R,
+            rng.normal(size=(n_beads, 3)) * scale_P)
