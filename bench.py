@@ -201,15 +201,16 @@ def run_forms(L: int) -> dict:
                 golden = json.load(f)
             errs = forms.directional_errors(d, golden)
             out["backward_grad_rel_err"] = max(e["rel_err"] for e in errs)
-            out["backward_grad_check"] = [{k: e[k] for k in ("seed", "gpu", "oracle_fd", "rel_err", "loss_rel_err")}
-                                          for e in errs]
+            out["backward_grad_check"] = [{k: e[k] for k in ("seed", "gpu", "oracle_fd", "rel_err", "rel_err_signed",
+                                                             "cancellation", "loss_rel_err")} for e in errs]
         del d
     out["backward_config"] = (f"{W['L']}^3, {W['steps']} coupled steps from rest with {W['chains']} x "
                               f"{W['length']} beads (zeta {W['zeta']:g}, k 10 kT), probe + drag loss; "
                               f"checkpoints every {W['checkpoint_every']} steps (_tape_resident: all {W['steps']} "
                               f"step buffers kept, nothing recomputed); FP32 fluid, FP64 beads; gradients w.r.t. "
-                              f"n(0), g, R(0), P(0); grad error: directional derivatives against FP64 oracle "
-                              f"central differences (eps 1e-4)")
+                              f"n(0), g, R(0), P(0); grad error: directional derivatives along seeded random "
+                              f"directions against FP64 oracle central differences (eps 1e-4), relative to "
+                              f"sum |g_i v_i|")
     print("# forms: backward done", file=sys.stderr, flush=True)
 
     # Kremer-Grest chains: the same box and chain count with FENE bonds and

@@ -70,7 +70,7 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16 = 2, LB_F16 = 3 } lb_dtype;
  * LB_ROUND_STOCHASTIC: unbiased stochastic rounding with 6-bit probability
  *   resolution (a value is stored as one of its two representable
  *   neighbours, the one away from zero with probability equal, to within
- *   1/64, to its position between them, and exactly so on average over the
+ *   1/128, to its position between them, and exactly so on average over the
  *   FP32 values between them); the random bits come from Philox4x32-10 with counter
  *   (site, step, 3 << 16, box) and key seed, so runs stay reproducible.
  *   Only with LB_BF16 or LB_F16 storage. */

@@ -6,9 +6,7 @@
 // with the rest residual plane of FP32 storage, else 19).
 // Work list: the sites of each box are cut into tiles of blockDim sites; the
 // tile -> box table is built on the host.  Each block walks a contiguous chunk
-// of tiles, so it stays inside one box for long stretches; that is what lets
-// the ensemble-VACF accumulation (below) keep per-thread partial sums and
-// flush them only when the box changes.
+// of tiles (one tile per block when the launch search finds that faster).
 //
 // The step counter that keys the noise lives in device memory and is advanced
 // by a one-thread kernel after each step, so a captured sequence of launches
@@ -17,8 +15,11 @@
 // Ensemble velocity autocorrelation (sampled every step, pre-collision
 // momentum j = sum_i n_i c_i): for each box and each axis a, the lowest
 // Fourier mode k = 2 pi / L_a of the two momentum components transverse to
-// a, j_hat(k) = sum_r j(r) exp(-i k r_a) (6 complex amplitudes per box).  A
-// ring buffer of the last R samples per box gives
+// a, j_hat(k) = sum_r j(r) exp(-i k r_a) (6 complex amplitudes per box).
+// Every tile writes its 12 partial sums to a row of its own (no atomics);
+// k_vacf_update adds a box's rows in a fixed order, so the amplitudes, like
+// the populations, do not depend on the order in which blocks run.  A ring
+// buffer of the last R samples per box gives
 // C_b(tau) += sum_modes Re[j_hat(t) conj(j_hat(t - tau))].  At gamma = 0 its
 // mean is N_b kT rho0 lambda(k)^tau, lambda = 1 - (2/3) sin^2(k/2)
 // (linear dynamics of eq. LBE with the equipartition of eq. Pdistneq).
@@ -46,13 +47,13 @@ struct BatchArgs {
     uint32_t chunk;            // tiles per block (contiguous)
     CollideConst cc;           // `box` is replaced per tile
     const uint32_t *step_ptr;  // device step counter
-    float *amp;                // [nbox][12] VACF accumulators (re, im of 6 modes)
+    float *amp;                // [ntiles][12] VACF partial sums of each tile (re, im of 6 modes)
     int32_t *flags;
 };
 
-// Block-wide sum of 12 floats, atomically added to dst[0..11].  Every thread
+// Block-wide sum of 12 floats into dst[0..11] (fixed order).  Every thread
 // of the block must call it (it synchronises).
-__device__ __forceinline__ void flush_amp12(float acc[12], float *dst)
+__device__ __forceinline__ void tile_sum12(float acc[12], float *dst)
 {
     __shared__ float red[16][12];
 #pragma unroll
@@ -72,7 +73,7 @@ __device__ __forceinline__ void flush_amp12(float acc[12], float *dst)
         const int nw = (blockDim.x + 63) >> 6;
         float s = 0.f;
         for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
-        atomicAdd(&dst[threadIdx.x], s);
+        dst[threadIdx.x] = s;
     }
 }
 
@@ -85,91 +86,111 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
     const uint32_t step = *a.step_ptr;
     const uint32_t t_begin = blockIdx.x * a.chunk;
     const uint32_t t_end = min(t_begin + a.chunk, a.ntiles);
-    float acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = 0.f;
-    int cur_box = -1;
     CollideConst cc = a.cc;
     for (uint32_t t = t_begin; t < t_end; ++t) {
         const uint32_t box = a.tile_box[t];
-        if (VACF && (int)box != cur_box) {
-            if (cur_box >= 0) {
-                flush_amp12(acc, a.amp + 12 * (size_t)cur_box);
+        float acc[12];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) acc[c] = 0.f;
-            }
-            cur_box = (int)box;
-        }
+        for (int c = 0; c < 12; ++c) acc[c] = 0.f;
         const BoxDesc d = a.boxes[box];
         const uint32_t s = (t - d.first_tile) * blockDim.x + threadIdx.x;
-        if (s >= d.geo.N) continue;
-        uint32_t x, y, z;
-        const PullOffsets o = pull_offsets(s, d.geo, x, y, z);
-        const T *__restrict__ src = static_cast<const T *>(a.src) + d.off;
-        T *__restrict__ dst = static_cast<T *>(a.dst) + d.off;
-        const uint32_t N = d.geo.N;
-        float dd[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dd[i] = S::ld(ld_plane(src + (size_t)i * N, pull_src(s, o, i)), 0.f);
-        float lo_in = 0.f;
-        if constexpr (S::rest_lo) lo_in = ld_plane(src + (size_t)kRestLo * N, s);
-        const mass_acc_t<ST> m_in = site_mass_lo<ST>(dd, lo_in);
-        if (VACF) {
-            const float jx = (dd[1] - dd[2]) + (dd[7] - dd[8]) + (dd[9] - dd[10]) + (dd[11] - dd[12]) + (dd[13] - dd[14]);
-            const float jy = (dd[3] - dd[4]) + (dd[7] - dd[8]) - (dd[9] - dd[10]) + (dd[15] - dd[16]) + (dd[17] - dd[18]);
-            const float jz = (dd[5] - dd[6]) + (dd[11] - dd[12]) - (dd[13] - dd[14]) + (dd[15] - dd[16]) - (dd[17] - dd[18]);
-            const float fx = (float)x * d.inv_L[0], fy = (float)y * d.inv_L[1], fz = (float)z * d.inv_L[2];
-            const float cx = __builtin_amdgcn_cosf(fx), sx = __builtin_amdgcn_sinf(fx);
-            const float cy = __builtin_amdgcn_cosf(fy), sy = __builtin_amdgcn_sinf(fy);
-            const float cz = __builtin_amdgcn_cosf(fz), sz = __builtin_amdgcn_sinf(fz);
-            // exp(-i phi) = cos - i sin
-            acc[0] += jx * cz;  acc[1] -= jx * sz;   // k along z, j_x
-            acc[2] += jy * cz;  acc[3] -= jy * sz;   // k along z, j_y
-            acc[4] += jx * cy;  acc[5] -= jx * sy;   // k along y, j_x
-            acc[6] += jz * cy;  acc[7] -= jz * sy;   // k along y, j_z
-            acc[8] += jy * cx;  acc[9] -= jy * sx;   // k along x, j_y
-            acc[10] += jz * cx; acc[11] -= jz * sx;  // k along x, j_z
+        if (s < d.geo.N) {
+            uint32_t x, y, z;
+            const PullOffsets o = pull_offsets(s, d.geo, x, y, z);
+            const T *__restrict__ src = static_cast<const T *>(a.src) + d.off;
+            T *__restrict__ dst = static_cast<T *>(a.dst) + d.off;
+            const uint32_t N = d.geo.N;
+            float dd[Q];
+    #pragma unroll
+            for (int i = 0; i < Q; ++i) dd[i] = S::ld(ld_plane(src + (size_t)i * N, pull_src(s, o, i)), 0.f);
+            float lo_in = 0.f;
+            if constexpr (S::rest_lo) lo_in = ld_plane(src + (size_t)kRestLo * N, s);
+            mass_acc_t<ST> m_in = 0;
+            if constexpr (S::rest_lo) m_in = site_mass_lo<ST>(dd, lo_in);
+            if (VACF) {
+                const float jx = (dd[1] - dd[2]) + (dd[7] - dd[8]) + (dd[9] - dd[10]) + (dd[11] - dd[12]) + (dd[13] - dd[14]);
+                const float jy = (dd[3] - dd[4]) + (dd[7] - dd[8]) - (dd[9] - dd[10]) + (dd[15] - dd[16]) + (dd[17] - dd[18]);
+                const float jz = (dd[5] - dd[6]) + (dd[11] - dd[12]) - (dd[13] - dd[14]) + (dd[15] - dd[16]) - (dd[17] - dd[18]);
+                const float fx = (float)x * d.inv_L[0], fy = (float)y * d.inv_L[1], fz = (float)z * d.inv_L[2];
+                const float cx = __builtin_amdgcn_cosf(fx), sx = __builtin_amdgcn_sinf(fx);
+                const float cy = __builtin_amdgcn_cosf(fy), sy = __builtin_amdgcn_sinf(fy);
+                const float cz = __builtin_amdgcn_cosf(fz), sz = __builtin_amdgcn_sinf(fz);
+                // exp(-i phi) = cos - i sin
+                acc[0] += jx * cz;  acc[1] -= jx * sz;   // k along z, j_x
+                acc[2] += jy * cz;  acc[3] -= jy * sz;   // k along z, j_y
+                acc[4] += jx * cy;  acc[5] -= jx * sy;   // k along y, j_x
+                acc[6] += jz * cy;  acc[7] -= jz * sy;   // k along y, j_z
+                acc[8] += jy * cx;  acc[9] -= jy * sx;   // k along x, j_y
+                acc[10] += jz * cx; acc[11] -= jz * sx;  // k along x, j_z
+            }
+            cc.box = d.box_id;
+            float out[Q], m0;
+            collide_site<THERMAL, FULL, out_scale<ST>::value>(dd, cc.g, cc, s, step, out, m0);
+            if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            void *dstp[Q + 1];
+    #pragma unroll
+            for (int i = 0; i < Q + (S::rest_lo ? 1 : 0); ++i) dstp[i] = dst + (size_t)i * N;
+            double mass;
+            float mom[3];
+            Philox4 rw = {0u, 0u, 0u, 0u};
+            if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, step, d.box_id, cc.key0, cc.key1);
+            if constexpr (S::rest_lo) store_site<ST, false>(dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
+            else store_site16<ST, false>(dstp, N * (uint32_t)sizeof(T), s, m0, out, mass, mom, rw);
         }
-        cc.box = d.box_id;
-        float out[Q];
-        collide_site<THERMAL, FULL>(dd, cc.g, cc, s, step, out);
-        if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        void *dstp[Q + 1];
-#pragma unroll
-        for (int i = 0; i < Q + (S::rest_lo ? 1 : 0); ++i) dstp[i] = dst + (size_t)i * N;
-        double mass;
-        float mom[3];
-        Philox4 rw = {0u, 0u, 0u, 0u};
-        if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, step, d.box_id, cc.key0, cc.key1);
-        store_site<ST, false>(dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
+        if (VACF) tile_sum12(acc, a.amp + 12 * (size_t)t);  // block-uniform: every thread takes part
     }
-    if (VACF && cur_box >= 0) flush_amp12(acc, a.amp + 12 * (size_t)cur_box);
 }
 
-// Push this step's amplitudes into the ring, accumulate C_b(tau), clear the
-// accumulators.  One block per box, one thread per lag (blockDim >= R).
-__global__ void k_vacf_update(float *amp, float *ring, double *corr, int R, const uint32_t *nsamp_ptr)
+// Sum this step's tile rows of each box into its 12 amplitudes (FP64, fixed
+// order), push them into the ring, accumulate C_b(tau).  One block per box,
+// blockDim >= max(R, 64); `block` is the step kernel's tile size.
+__global__ void __launch_bounds__(1024) k_vacf_update(const float *__restrict__ rows, const BoxDesc *__restrict__ boxes,
+                                                      uint32_t block, float *ring, double *corr, int R,
+                                                      const uint32_t *nsamp_ptr)
 {
     const int b = blockIdx.x;
+    const BoxDesc d = boxes[b];
+    const uint32_t nt = (d.geo.N + block - 1u) / block;
+    const float *rb = rows + 12 * (size_t)d.first_tile;
+    double acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+    for (uint32_t r = threadIdx.x; r < nt; r += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] += (double)rb[12 * (size_t)r + c];
+    __shared__ double red[16][12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        double x = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        acc[c] = x;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) red[wid][c] = acc[c];
+    __syncthreads();
     const uint32_t ns = *nsamp_ptr;  // samples taken before this one
     const int slot = (int)(ns % (uint32_t)R);
     float *ringb = ring + (size_t)b * R * 12;
     __shared__ float cur[12];
     if (threadIdx.x < 12) {
-        cur[threadIdx.x] = amp[12 * (size_t)b + threadIdx.x];
-        ringb[slot * 12 + threadIdx.x] = cur[threadIdx.x];
+        const int nw = (blockDim.x + 63) >> 6;
+        double v = 0.0;
+        for (int w = 0; w < nw; ++w) v += red[w][threadIdx.x];
+        cur[threadIdx.x] = (float)v;
+        ringb[slot * 12 + threadIdx.x] = (float)v;
     }
     __syncthreads();
     const int tau = threadIdx.x;
     if (tau < R && (uint32_t)tau <= ns) {
         const float *old = ringb + ((slot - tau + R) % R) * 12;
-        double s = 0.0;
+        double sum = 0.0;
         for (int m = 0; m < 6; ++m)
-            s += (double)cur[2 * m] * old[2 * m] + (double)cur[2 * m + 1] * old[2 * m + 1];
-        corr[(size_t)b * R + tau] += s;
+            sum += (double)cur[2 * m] * old[2 * m] + (double)cur[2 * m + 1] * old[2 * m + 1];
+        corr[(size_t)b * R + tau] += sum;
     }
-    __syncthreads();
-    if (threadIdx.x < 12) amp[12 * (size_t)b + threadIdx.x] = 0.f;
 }
 
 // Advance the device step counter (and the VACF sample count).

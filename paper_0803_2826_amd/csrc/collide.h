@@ -35,10 +35,12 @@ namespace lbmi {
 // in FP32: x * (hi + lo) with hi = fl(a), lo = fl(a - hi), so the product is
 // rounded once from the (near) exact value instead of carrying the constant's
 // own rounding error, which would bias every step the same way.
-template <int DEN>
+// OSC: the output is scaled by 2^OSC (exact), for storage types that keep a
+// scaled value (FP16 stores 2^8 times the deviation).
+template <int DEN, int OSC = 0>
 __device__ __forceinline__ float mul_weight(float x)
 {
-    constexpr double a = 1.0 / (double)DEN;
+    constexpr double a = (double)(1 << OSC) / (double)DEN;
     constexpr float hi = (float)a;
     constexpr float lo = (float)(a - (double)hi);
     return __builtin_fmaf(x, hi, x * lo);
@@ -48,6 +50,7 @@ __device__ __forceinline__ float mul_weight(float x)
 struct CollideConst {
     float gam[19];   // gamma_k, modes 4..18 used
     float sig[19];   // sigma_k = sqrt(w_k mu (1 - gamma_k^2)), modes 4..18 used
+    float sigw[19];  // sigma_k / w_k (the noise of a kinetic mode as it enters the back-transformation)
     float rho0;
     float sqrt_rho0;
     float g[3];      // uniform body force
@@ -56,14 +59,15 @@ struct CollideConst {
 };
 
 // d[19]: shifted pre-collision populations (in), out[19]: shifted
-// post-collision populations.  F: total force density at the site.
+// post-collision populations times 2^OSC, m0: the input's mass deviation
+// sum_i d_i (the collision keeps it).  F: total force density at the site.
 // FULL: every non-conserved gamma_k is 0 (complete relaxation, tau = 1 for
 // the stress modes and the kinetic modes fully relaxed), so m*_k =
 // m^eq_k + S_k/2 (+ noise) and the moments m_4..m_18 of the input are never
 // needed; the result equals the general expressions at gamma = 0.
-template <bool THERMAL, bool FULL = false>
+template <bool THERMAL, bool FULL = false, int OSC = 0>
 __device__ __forceinline__ void collide_site(const float d[19], const float F[3], const CollideConst &cc,
-                                             uint32_t site, uint32_t step, float out[19])
+                                             uint32_t site, uint32_t step, float out[19], float &m0)
 {
     // ---- moments through opposite-pair sums/differences
     const float S1 = d[1] + d[2], D1 = d[1] - d[2];
@@ -106,9 +110,11 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     m[14] = (D5 - D4) + (D8 + D9);
     m[15] = (D6 - D7) - (D8 - D9);
 
-    // ---- hydrodynamic fields
+    m0 = m[0];
+
+    // ---- hydrodynamic fields (1/rho from the hardware reciprocal, 1 ulp)
     const float rho = cc.rho0 + m[0];
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);
     const float jx = m[1] + 0.5f * F[0], jy = m[2] + 0.5f * F[1], jz = m[3] + 0.5f * F[2];
     const float ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
 
@@ -147,13 +153,13 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
         for (int k = 10; k <= 18; ++k) ms[k] = cc.gam[k] * m[k];
     }
 
+    float r[15];
     if (THERMAL) {
         // r_k sqrt(rho_n): the density factor of the amplitude rides on the
         // Box-Muller radius
-        float r[15];
         fluid_normals(site, step, cc.box, cc.key0, cc.key1, cc.noise_rho0 ? cc.rho0 : rho, r);
 #pragma unroll
-        for (int k = 4; k <= 18; ++k) ms[k] += cc.sig[k] * r[k - 4];
+        for (int k = 4; k <= (FULL ? 9 : 18); ++k) ms[k] += cc.sig[k] * r[k - 4];
     }
 
     // ---- back-transformation: scale by 1/w_k, then pair even/odd parts
@@ -161,11 +167,22 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     const float u1 = 3.f * ms[1], u2 = 3.f * ms[2], u3 = 3.f * ms[3];
     const float u4 = 1.5f * ms[4], u5 = 0.75f * ms[5], u6 = 2.25f * ms[6];
     const float u7 = 9.f * ms[7], u8 = 9.f * ms[8], u9 = 9.f * ms[9];
-    const float u10 = 1.5f * ms[10], u11 = 1.5f * ms[11], u12 = 1.5f * ms[12];
-    const float u13 = 4.5f * ms[13], u14 = 4.5f * ms[14], u15 = 4.5f * ms[15];
-    const float u16 = 0.5f * ms[16], u17 = 0.75f * ms[17], u18 = 2.25f * ms[18];
+    float uk[19];
+    if constexpr (FULL) {
+        // fully relaxed kinetic modes carry only their noise: u_k = (sigma_k / w_k) r_k
+#pragma unroll
+        for (int k = 10; k <= 18; ++k) uk[k] = THERMAL ? cc.sigw[k] * r[k - 4] : 0.f;
+    } else {
+        const float inv_w[19] = {1.f, 3.f, 3.f, 3.f, 1.5f, 0.75f, 2.25f, 9.f, 9.f, 9.f,
+                                 1.5f, 1.5f, 1.5f, 4.5f, 4.5f, 4.5f, 0.5f, 0.75f, 2.25f};
+#pragma unroll
+        for (int k = 10; k <= 18; ++k) uk[k] = inv_w[k] * ms[k];
+    }
+    const float u10 = uk[10], u11 = uk[11], u12 = uk[12];
+    const float u13 = uk[13], u14 = uk[14], u15 = uk[15];
+    const float u16 = uk[16], u17 = uk[17], u18 = uk[18];
 
-    out[0] = mul_weight<3>((u0 - u4) + u16);
+    out[0] = mul_weight<3, OSC>((u0 - u4) + u16);
 
     // speed-1 pairs
     const float e1c = (u0 - 2.f * u16);  // common even part of the axis directions
@@ -173,12 +190,12 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     const float E2 = e1c - u5 + u6 + u17 - u18;
     const float E3 = e1c - u5 - u6 + u17 + u18;
     const float O1 = u1 - 2.f * u10, O2 = u2 - 2.f * u11, O3 = u3 - 2.f * u12;
-    out[1] = mul_weight<18>(E1 + O1);
-    out[2] = mul_weight<18>(E1 - O1);
-    out[3] = mul_weight<18>(E2 + O2);
-    out[4] = mul_weight<18>(E2 - O2);
-    out[5] = mul_weight<18>(E3 + O3);
-    out[6] = mul_weight<18>(E3 - O3);
+    out[1] = mul_weight<18, OSC>(E1 + O1);
+    out[2] = mul_weight<18, OSC>(E1 - O1);
+    out[3] = mul_weight<18, OSC>(E2 + O2);
+    out[4] = mul_weight<18, OSC>(E2 - O2);
+    out[5] = mul_weight<18, OSC>(E3 + O3);
+    out[6] = mul_weight<18, OSC>(E3 - O3);
 
     // speed-sqrt2 pairs
     const float e2c = (u0 + u4) + u16;
@@ -195,18 +212,18 @@ __device__ __forceinline__ void collide_site(const float d[19], const float F[3]
     const float O7 = (px - pz) - (u13 + u15);
     const float O8 = (py + pz) + (u14 - u15);
     const float O9 = (py - pz) + (u14 + u15);
-    out[7] = mul_weight<36>(E4 + O4);
-    out[8] = mul_weight<36>(E4 - O4);
-    out[9] = mul_weight<36>(E5 + O5);
-    out[10] = mul_weight<36>(E5 - O5);
-    out[11] = mul_weight<36>(E6 + O6);
-    out[12] = mul_weight<36>(E6 - O6);
-    out[13] = mul_weight<36>(E7 + O7);
-    out[14] = mul_weight<36>(E7 - O7);
-    out[15] = mul_weight<36>(E8 + O8);
-    out[16] = mul_weight<36>(E8 - O8);
-    out[17] = mul_weight<36>(E9 + O9);
-    out[18] = mul_weight<36>(E9 - O9);
+    out[7] = mul_weight<36, OSC>(E4 + O4);
+    out[8] = mul_weight<36, OSC>(E4 - O4);
+    out[9] = mul_weight<36, OSC>(E5 + O5);
+    out[10] = mul_weight<36, OSC>(E5 - O5);
+    out[11] = mul_weight<36, OSC>(E6 + O6);
+    out[12] = mul_weight<36, OSC>(E6 - O6);
+    out[13] = mul_weight<36, OSC>(E7 + O7);
+    out[14] = mul_weight<36, OSC>(E7 - O7);
+    out[15] = mul_weight<36, OSC>(E8 + O8);
+    out[16] = mul_weight<36, OSC>(E8 - O8);
+    out[17] = mul_weight<36, OSC>(E9 + O9);
+    out[18] = mul_weight<36, OSC>(E9 - O9);
 }
 
 }  // namespace lbmi

@@ -84,34 +84,46 @@ template <> struct Storage<3> {  // LB_F16, stored value = 2^8 * deviation
 // a value is rounded up in magnitude with probability equal to its distance
 // from the lower neighbour in units of the spacing.  Here the probability is
 // resolved to 1/64: with D dropped FP32 mantissa bits (16 for BF16, 13 for
-// FP16) the offset r6 2^(D-6) + c, c = 2^(D-7) - 1 + (r6 & 1), is added to
-// the magnitude bits before they are cut.  Its mean is (2^D - 1) / 2, the
-// mean of the dropped bits, so over the FP32 values of a cell the rounding
-// is exactly unbiased (a constant c = 2^(D-7) would add half an FP32 ulp to
-// every magnitude: a growth of 2^-24 per step); the binade-edge term left by
-// the 1/64 resolution is 4096 times smaller than that of nearest rounding.
-// The 6-bit fields come from one Philox4x32-10 call of its own stream.
+// FP16) the offset r6 2^(D-6) + c is added to the magnitude bits before
+// they are cut, c = 2^(D-7) - 1 + b with b a fair bit shared by the site's
+// values.  Its mean is (2^D - 1) / 2, the mean of the dropped bits, so over
+// the FP32 values of a cell the rounding is exactly unbiased (a constant
+// c = 2^(D-7) would add half an FP32 ulp to every magnitude: a growth of
+// 2^-24 per step), and every value's round-up probability is within 1/128
+// of its exact one; the binade-edge term left by the 1/64 resolution is
+// 4096 times smaller than that of nearest rounding.  The 6-bit fields r6
+// and the bit b come from one Philox4x32-10 call of its own stream.
+template <int D>
+__device__ __forceinline__ uint32_t sr_offset(uint32_t r6, uint32_t b)
+{
+    return (r6 << (D - 6)) + ((1u << (D - 7)) - 1u) + b;
+}
 template <> struct Storage<4> : Storage<2> {  // LB_BF16, stochastic rounding
-    static __device__ __forceinline__ T st_sr(float f, uint32_t r6)
+    static __device__ __forceinline__ T st_sr(float f, uint32_t r6, uint32_t b)
     {
-        const uint32_t b = (__float_as_uint(f) + ((r6 << 10) + 511u + (r6 & 1u))) >> 16;
-        return __builtin_bit_cast(__bf16, (uint16_t)b);
+        const uint32_t x = (__float_as_uint(f) + sr_offset<16>(r6, b)) >> 16;
+        return __builtin_bit_cast(__bf16, (uint16_t)x);
     }
 };
 template <> struct Storage<5> : Storage<3> {  // LB_F16, stochastic rounding
-    static __device__ __forceinline__ T st_sr(float f, uint32_t r6)
+    static __device__ __forceinline__ T st_sr(float f, uint32_t r6, uint32_t b)
     {
         // clear the 13 mantissa bits FP16 drops; the conversion of the result
         // is exact wherever 2^8 |f| is an FP16 normal number (|f| >= 2^-22)
-        const uint32_t b = (__float_as_uint(f * 0x1p8f) + ((r6 << 7) + 63u + (r6 & 1u))) & 0xFFFFE000u;
-        return (_Float16)__uint_as_float(b);
+        const uint32_t x = (__float_as_uint(f * 0x1p8f) + sr_offset<13>(r6, b)) & 0xFFFFE000u;
+        return (_Float16)__uint_as_float(x);
     }
 };
 template <int ST> struct is_stochastic { static constexpr bool value = ST >= 4; };
 
+// log2 of the scale of the stored value (FP16 stores 2^8 times the
+// deviation): the collision's outputs come out in that scale.
+template <int ST> struct out_scale { static constexpr int value = (ST == 3 || ST == 5) ? 8 : 0; };
+
 // The four random words of one site's stochastic rounding: Philox counter
 // (site, step, stream 3 << 16, box), key = seed.  Population i uses the
-// 6-bit field (i % 5) of word i / 5.
+// 6-bit field (i % 5) of word i / 5; the site's offset bit b is bit 24 of
+// the fourth word (its fields use bits 0..23).
 __device__ __forceinline__ Philox4 rounding_words(uint32_t s, uint32_t step, uint32_t box, uint32_t k0, uint32_t k1)
 {
     return philox4x32_10(s, step, 3u << 16, box, k0, k1);
@@ -121,6 +133,7 @@ __device__ __forceinline__ uint32_t rounding_field(const Philox4 &w, int i)
     const uint32_t word = (i < 5) ? w.v0 : (i < 10) ? w.v1 : (i < 15) ? w.v2 : w.v3;
     return (word >> (6 * (i % 5))) & 63u;
 }
+__device__ __forceinline__ uint32_t rounding_bit(const Philox4 &w) { return (w.v3 >> 24) & 1u; }
 
 // Geometry of one periodic box.
 struct Geom {
@@ -307,32 +320,46 @@ __device__ __forceinline__ uint32_t tile_index(uint32_t remap)
 }
 
 // Block-wide sums of (FP64 mass, 3 FP32 momentum components) into one FP64
-// partial row per block.  Every thread of the block must call it.
+// partial row per block, in a fixed order.  Every thread writes its values
+// to LDS; the block's first wave adds them (each lane a strided subset, then
+// across the wave) and writes the row, so the other waves spend two LDS
+// stores and a barrier on it instead of a wave reduction each.  Every
+// thread of the block must call it.
+// The LDS it uses is the launch's dynamic shared memory, kTotalsLds bytes
+// per thread.
+constexpr uint32_t kTotalsLds = 20;
+
 __device__ __forceinline__ void block_sum_totals(double *out, double mass, float mom[3])
 {
-    __shared__ double red[16][4];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mass += __shfl_xor(mass, off, 64);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float x = mom[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        mom[c] = x;
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[wid][0] = mass;
-        red[wid][1] = (double)mom[0];
-        red[wid][2] = (double)mom[1];
-        red[wid][3] = (double)mom[2];
-    }
+    extern __shared__ __align__(8) char totals_lds[];
+    double *red_m = reinterpret_cast<double *>(totals_lds);
+    float *red_p = reinterpret_cast<float *>(totals_lds + 8 * blockDim.x);
+    const uint32_t t = threadIdx.x, nb = blockDim.x;
+    red_m[t] = mass;
+    red_p[t] = mom[0];
+    red_p[nb + t] = mom[1];
+    red_p[2 * nb + t] = mom[2];
     __syncthreads();
-    if (threadIdx.x < 4) {
-        const int nw = (blockDim.x + 63) >> 6;
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
+    if (t >= 64) return;
+    double m = 0.0;
+    double p[3] = {0.0, 0.0, 0.0};
+    for (uint32_t k = t; k < nb; k += 64) {
+        m += red_m[k];
+        p[0] += (double)red_p[k];
+        p[1] += (double)red_p[nb + k];
+        p[2] += (double)red_p[2 * nb + k];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        m += __shfl_xor(m, off, 64);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[c] += __shfl_xor(p[c], off, 64);
+    }
+    if (t == 0) {
+        out[0] = m;
+        out[1] = p[0];
+        out[2] = p[1];
+        out[3] = p[2];
     }
 }
 
@@ -363,6 +390,118 @@ __device__ __forceinline__ mass_acc_t<ST> site_mass_lo(const float d[Q], float l
     return m;
 }
 
+// Pairs of 16-bit stored values in one 32-bit word (population 2p+1 in the
+// low half, 2p+2 in the high half) and their FP32 sums with gfx950's
+// two-element dot products (v_dot2c_f32_bf16 / v_dot2_f32_f16) against +-1
+// (BF16) or +-2^-8 (FP16, whose stored value is 2^8 times the deviation):
+// one instruction adds a pair to a sum, exactly the deviations the stored
+// bits represent.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
+// pack(a, b, rw, i): a, b are in the stored scale (2^8 d for FP16);
+// stochastic rounding reads the 6-bit fields i and i + 1 of rw.
+template <int ST> struct Pair16;
+template <> struct Pair16<2> {  // BF16, round to nearest even
+    static __device__ __forceinline__ uint32_t pack(float a, float b, const Philox4 &, int)
+    {
+        const bf16x2_t v = {(__bf16)a, (__bf16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    static __device__ __forceinline__ float dot(uint32_t pk, float lo_c, float hi_c, float acc)
+    {
+        const bf16x2_t c = {(__bf16)lo_c, (__bf16)hi_c};
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, pk), c, acc, false);
+    }
+};
+template <> struct Pair16<3> {  // FP16 (scaled by 2^8), round to nearest even
+    static __device__ __forceinline__ uint32_t pack(float a, float b, const Philox4 &, int)
+    {
+        const f16x2_t v = {(_Float16)a, (_Float16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    static __device__ __forceinline__ float dot(uint32_t pk, float lo_c, float hi_c, float acc)
+    {
+        const f16x2_t c = {(_Float16)(lo_c * 0x1p-8f), (_Float16)(hi_c * 0x1p-8f)};
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, pk), c, acc, false);
+    }
+};
+
+// The bits of the FP32 value f plus the stochastic-rounding offset of field
+// i (sr_offset, D dropped bits): a bit-field extract of the Philox word, a
+// shift-and-add and an add of the site's constant part.
+template <int D>
+__device__ __forceinline__ uint32_t sr_add(float f, const Philox4 &rw, int i)
+{
+    const uint32_t w = (i < 5) ? rw.v0 : (i < 10) ? rw.v1 : (i < 15) ? rw.v2 : rw.v3;
+    const uint32_t r6 = __builtin_amdgcn_ubfe(w, 6u * (uint32_t)(i % 5), 6u);
+    return __float_as_uint(f) + sr_offset<D>(r6, rounding_bit(rw));
+}
+template <> struct Pair16<4> : Pair16<2> {  // BF16, stochastic rounding
+    static __device__ __forceinline__ uint32_t pack(float a, float b, const Philox4 &rw, int i)
+    {
+        // the high halves of the two offset words, a in the low half
+        return __builtin_amdgcn_perm(sr_add<16>(b, rw, i + 1), sr_add<16>(a, rw, i), 0x07060302u);
+    }
+};
+template <> struct Pair16<5> : Pair16<3> {  // FP16, stochastic rounding
+    static __device__ __forceinline__ uint32_t pack(float a, float b, const Philox4 &rw, int i)
+    {
+        // clear the 13 mantissa bits FP16 drops; the conversion of the result
+        // is exact wherever |value| >= 2^-14 (FP16 normal)
+        const float ra = __uint_as_float(sr_add<13>(a, rw, i) & 0xFFFFE000u);
+        const float rb = __uint_as_float(sr_add<13>(b, rw, i + 1) & 0xFFFFE000u);
+        const f16x2_t v = {(_Float16)ra, (_Float16)rb};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+};
+
+// Store of a site in 16-bit storage (the 16-bit counterpart of store_site
+// below): the 18 moving populations (out[], in the stored scale) rounded in
+// pairs, their stored values summed by dot products, the rest population
+// set to the residual x = m_in - sum and rounded once.  With TOTALS also the stored values'
+// mass (FP64) and momentum (dot products against the pairs' signs: the two
+// members of every pair are opposite directions).
+template <int ST, bool TOTALS>
+__device__ __forceinline__ void store_site16(void *const *dstp, uint32_t plane_bytes, uint32_t s, float m_in,
+                                             const float out[Q], double &mass, float mom[3], const Philox4 &rw)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    using P = Pair16<ST>;
+    uint32_t pk[9];
+    float sum = 0.f;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        pk[p] = P::pack(out[2 * p + 1], out[2 * p + 2], rw, 2 * p + 1);
+        // keep the packed word as it is: the stores take its halves (the low
+        // half as is, the high half with a d16_hi store) instead of the
+        // compiler converting each value a second time
+        __asm__ volatile("" : "+v"(pk[p]));
+        sum = P::dot(pk[p], 1.f, 1.f, sum);
+    }
+    const float x = m_in - sum;
+    T v0;
+    if constexpr (is_stochastic<ST>::value) v0 = S::st_sr(x, rounding_field(rw, 0), rounding_bit(rw));
+    else v0 = S::st(x, 0.f);
+    st_plane_nt<T>(dstp[0], plane_bytes, s, v0);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        st_plane_nt<T>(dstp[2 * p + 1], plane_bytes, s, __builtin_bit_cast(T, (uint16_t)pk[p]));
+        st_plane_nt<T>(dstp[2 * p + 2], plane_bytes, s, __builtin_bit_cast(T, (uint16_t)(pk[p] >> 16)));
+    }
+    if (TOTALS) {
+        mass = (double)S::ld(v0, 0.f) + (double)sum;
+        // x: pairs 0 (+-x), 3, 4, 5, 6; y: 1 (+-y), 3, 4 (-), 7, 8; z: 2 (+-z), 5, 6 (-), 7, 8 (-)
+        mom[0] = P::dot(pk[6], 1.f, -1.f, P::dot(pk[5], 1.f, -1.f, P::dot(pk[4], 1.f, -1.f,
+                 P::dot(pk[3], 1.f, -1.f, P::dot(pk[0], 1.f, -1.f, 0.f)))));
+        mom[1] = P::dot(pk[8], 1.f, -1.f, P::dot(pk[7], 1.f, -1.f, P::dot(pk[4], -1.f, 1.f,
+                 P::dot(pk[3], 1.f, -1.f, P::dot(pk[1], 1.f, -1.f, 0.f)))));
+        mom[2] = P::dot(pk[8], -1.f, 1.f, P::dot(pk[7], 1.f, -1.f, P::dot(pk[6], -1.f, 1.f,
+                 P::dot(pk[5], 1.f, -1.f, P::dot(pk[2], 1.f, -1.f, 0.f)))));
+    }
+}
+
 // Store the post-collision populations of site s.  The rest population is
 // replaced by the residual x = m_in - sum_{i>=1} stored_i that makes the
 // stored values of the site sum to its input mass m_in (site_mass_lo): the
@@ -385,16 +524,15 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
     T v[Q];
     float back[Q];
     Acc sum = 0;
+    static_assert(S::rest_lo, "store_site is the FP32 store; 16-bit storage uses store_site16");
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        if constexpr (is_stochastic<ST>::value) v[i] = S::st_sr(out[i], rounding_field(rw, i));
-        else v[i] = S::st(out[i], 0.f);
+        v[i] = S::st(out[i], 0.f);
         back[i] = S::ld(v[i], 0.f);
         sum += (Acc)back[i];
     }
     const Acc x = m_in - sum;
-    if constexpr (is_stochastic<ST>::value) v[0] = S::st_sr((float)x, rounding_field(rw, 0));
-    else v[0] = S::st((float)x, 0.f);
+    v[0] = S::st((float)x, 0.f);
     back[0] = S::ld(v[0], 0.f);
     float lo = 0.f;
     if constexpr (S::rest_lo) lo = (float)(x - (Acc)back[0]);
@@ -461,7 +599,10 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
                                      0.f);
             }
         }
-        const mass_acc_t<ST> m_in = site_mass_lo<ST>(d, lo_in);
+        // FP32 storage: the input mass in FP64 with the rest residual (exact);
+        // 16-bit storage: the collision's own FP32 sum below
+        mass_acc_t<ST> m_in = 0;
+        if constexpr (S::rest_lo) m_in = site_mass_lo<ST>(d, lo_in);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         if (FORCE) {
             const uint32_t bit = 1u << (s & 31u);
@@ -479,15 +620,16 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
                 }
             }
         }
-        float out[Q];
-        collide_site<THERMAL, FULL>(d, F, a.cc, s, a.step, out);
+        float out[Q], m0;
+        collide_site<THERMAL, FULL, out_scale<ST>::value>(d, F, a.cc, s, a.step, out, m0);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Philox4 rw = {0u, 0u, 0u, 0u};
         if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, a.step, a.cc.box, a.cc.key0, a.cc.key1);
         void *dstp[Q + 1];
 #pragma unroll
         for (int i = 0; i < Q + (S::rest_lo ? 1 : 0); ++i) dstp[i] = dst + (size_t)(P * z + (uint32_t)i) * plane;
-        store_site<ST, TOTALS>(dstp, (uint32_t)plane, r, m_in, out, mass, mom, rw);
+        if constexpr (S::rest_lo) store_site<ST, TOTALS>(dstp, (uint32_t)plane, r, m_in, out, mass, mom, rw);
+        else store_site16<ST, TOTALS>(dstp, (uint32_t)plane, r, m0, out, mass, mom, rw);
     }
     if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)blockIdx.x, mass, mom);
 }

@@ -92,7 +92,7 @@ struct lb_ctx {
     hipStream_t bstream = nullptr;   // private stream of a batch (graph capture)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     uint32_t *dstep = nullptr;       // [2]: device step counter, VACF sample count
-    float *amp = nullptr;            // [nbox][12]
+    float *amp = nullptr;            // [tiles][12] VACF partial sums per tile (sized for 64-site tiles)
     float *ring = nullptr;           // [nbox][R][12]
     double *corr = nullptr;          // [nbox][R]
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // per buffer parity
@@ -249,6 +249,7 @@ void fill_collide_const(lb_ctx *c)
     for (int k = 0; k < 19; ++k) {
         c->cc.gam[k] = (float)gam[k];
         c->cc.sig[k] = (k >= 4) ? (float)std::sqrt(wk[k] * mu * (1.0 - gam[k] * gam[k])) : 0.f;
+        c->cc.sigw[k] = (k >= 4) ? (float)(std::sqrt(wk[k] * mu * (1.0 - gam[k] * gam[k])) / wk[k]) : 0.f;
     }
     c->cc.rho0 = (float)p.rho0;
     c->cc.sqrt_rho0 = (float)std::sqrt(p.rho0);
@@ -265,11 +266,12 @@ void fill_collide_const(lb_ctx *c)
 template <int ST, bool TH, bool TOT, bool FRC, bool FULL>
 void launch_step_w(lb_ctx *c, const StepArgs &a)
 {
+    const size_t lds = TOT ? (size_t)kTotalsLds * (size_t)c->block : 0;  // block_sum_totals
     if (c->geo.walls)
-        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, true, FULL>), dim3(c->nblocks), dim3(c->block), 0,
+        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, true, FULL>), dim3(c->nblocks), dim3(c->block), lds,
                            c->stream, a);
     else
-        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, false, FULL>), dim3(c->nblocks), dim3(c->block), 0,
+        hipLaunchKernelGGL((k_stream_collide<ST, TH, TOT, FRC, false, FULL>), dim3(c->nblocks), dim3(c->block), lds,
                            c->stream, a);
 }
 
@@ -813,8 +815,8 @@ void batch_enqueue_step(lb_ctx *c, const void *src, void *dst)
     batch_launch_step(c, src, dst, vacf);
     if (vacf) {
         const int R = c->p.vacf_lags;
-        hipLaunchKernelGGL(k_vacf_update, dim3(c->nbox), dim3(std::max(R, 64)), 0, c->stream, c->amp, c->ring, c->corr,
-                           R, c->dstep + 1);
+        hipLaunchKernelGGL(k_vacf_update, dim3(c->nbox), dim3(std::max(R, 64)), 0, c->stream, c->amp, c->boxes_d,
+                           (uint32_t)c->block, c->ring, c->corr, R, c->dstep + 1);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->dstep, c->dstep + 1, vacf ? 1 : 0);
 }
@@ -851,8 +853,8 @@ int autotune(lb_ctx *c)
 {
     if (c->batch) {
         // blocks per CU of the persistent launch; 0 = one tile per block (no
-        // tile loop, the hardware deals tiles out), only without the VACF,
-        // whose per-box sums are flushed once per block
+        // tile loop, the hardware deals tiles out); with the VACF the
+        // candidates run the VACF variant of the kernel
         const int blocks[] = {128, 256, 512, 1024};
         const int per_cu[] = {2, 4, 8, 16, 0};
         float best = 1e30f;
@@ -861,10 +863,9 @@ int autotune(lb_ctx *c)
         for (int blk : blocks) {
             LB_TRY(batch_build_tiles(c, blk));
             for (int pc : per_cu) {
-                if (pc == 0 && c->p.vacf_lags > 0) continue;
                 const uint32_t grid = pc > 0 ? 256u * (uint32_t)pc : c->ntiles;
                 c->chunk = std::max<uint32_t>(1u, (c->ntiles + grid - 1) / grid);
-                const float ms = time_launches(c, 3, [&] { batch_launch_step(c, c->bufA, c->bufB, false); });
+                const float ms = time_launches(c, 3, [&] { batch_launch_step(c, c->bufA, c->bufB, c->p.vacf_lags > 0); });
                 LB_LAUNCH_CHECK(c, "autotune batch");
                 if (ms < best) {
                     best = ms;
@@ -1084,6 +1085,9 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
     c->user_stream = static_cast<hipStream_t>(stream);
     const size_t bytes = (size_t)off * c->elem;
     const int R = p.vacf_lags;
+    // VACF rows: one per tile of the smallest tile (64 sites) any launch uses
+    size_t amp_rows = 0;
+    for (const BoxDesc &d : c->boxes_h) amp_rows += (d.geo.N + 63u) / 64u;
     bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) == hipSuccess;
@@ -1092,7 +1096,7 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
          hipMalloc(&c->dstep, 2 * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc(&c->dev_out, 64 * sizeof(double)) == hipSuccess && hipMalloc(&c->flags, sizeof(int32_t)) == hipSuccess;
     if (ok && R > 0)
-        ok = hipMalloc(&c->amp, (size_t)nbox * 12 * sizeof(float)) == hipSuccess &&
+        ok = hipMalloc(&c->amp, amp_rows * 12 * sizeof(float)) == hipSuccess &&
              hipMalloc(&c->ring, (size_t)nbox * R * 12 * sizeof(float)) == hipSuccess &&
              hipMalloc(&c->corr, (size_t)nbox * R * sizeof(double)) == hipSuccess;
     if (!ok) {
@@ -1105,7 +1109,6 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, c->flags, 1u);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t *>(c->dstep), 2u);
     if (R > 0) {
-        hipLaunchKernelGGL(k_zero_f32, dim3(64), dim3(256), 0, c->stream, c->amp, (size_t)nbox * 12);
         hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, c->stream, reinterpret_cast<float *>(c->corr),
                            (size_t)nbox * R * 2);
     }

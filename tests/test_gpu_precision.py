@@ -112,14 +112,18 @@ def grid_neighbours(d, storage):
 
 def stochastic_up_probability(d, storage):
     """Probability of rounding away from zero of the 6-bit stochastic
-    rounding, from the D dropped bits L of the FP32 value: the offsets
-    r 2^(D-6) + 2^(D-7) - 1 + (r & 1), r = 0..63, that carry past 2^D."""
+    rounding, from the D dropped bits L of the FP32 value: the fraction of
+    the offsets r 2^(D-6) + 2^(D-7) - 1 + b, r = 0..63, b = 0, 1 (the
+    site's fair bit), that carry past 2^D."""
     D = 16 if storage == "bf16" else 13
     x = (d if storage == "bf16" else d * 256.0).astype(np.float32)
     L = (x.view(np.uint32) & np.uint32((1 << D) - 1)).astype(np.int64)
     r = np.arange(64)
-    c = (r << (D - 6)) + (1 << (D - 7)) - 1 + (r & 1)
-    return (64 - np.searchsorted(c, (1 << D) - L, side="left")) / 64
+    p = 0.0
+    for b in (0, 1):
+        c = (r << (D - 6)) + (1 << (D - 7)) - 1 + b
+        p = p + (64 - np.searchsorted(c, (1 << D) - L, side="left")) / 128
+    return p
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
