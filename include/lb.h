@@ -353,6 +353,19 @@ int lb_step_noalloc(const lb_params *params, const void *src, void *dst, uint64_
  * previous lb_couple's force not yet consumed). */
 int lb_couple(lb_ctx *ctx, const lb_beads *beads);
 
+/* nsteps >= 0 coupled time steps with the same beads: the same result, bit
+ * for bit, as nsteps times lb_couple then lb_step(ctx, 1) (taped or not),
+ * the bead state in beads->pos, beads->mom advanced in place.  With the
+ * trilinear stencil (phi_2), no WCA pairs, no walls, at most 64 bonds per
+ * bead and nsteps >= 2, each step is ONE launch (the particle half runs in
+ * the first blocks of the fluid step's grid, each bead sums its own bond
+ * forces); otherwise the separate launches run.  Before the first step the
+ * bond list is copied to the host (one synchronisation).  Errors: those of
+ * lb_couple and lb_step; a fused step whose site blocks stopped waiting for
+ * its particle blocks (not expected) is reported as LB_EDEVICE by the next
+ * call that reads the device flags (lb_totals, lb_sync). */
+int lb_coupled_steps(lb_ctx *ctx, const lb_beads *beads, int32_t nsteps);
+
 /* Density and velocity of the current state: rho = sum_i n_i,
  * u = (sum_i n_i c_i + g/2) / rho (eq. special_choice_momentum_density with
  * the uniform body force).  rho: device FP64 [N]; u: device FP64 [3][N];
@@ -436,6 +449,14 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * lb_step), LB_EUNSUPPORTED (a batch
  * context; the bead count changed between taped coupled steps), LB_ENOMEM. */
 int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
+
+/* Allocates now what the next nsteps >= 0 taped steps will take while they
+ * run: their checkpoints and, with beads != NULL, room in the bead tape for
+ * nsteps coupled steps of these beads; so that no allocation falls inside a
+ * timed or latency-bound run.  Only allocates (the memory is the tape's and
+ * goes with it).  Errors: LB_ESTATE (no tape), LB_EINVAL (nsteps < 0),
+ * LB_EUNSUPPORTED (a bead count other than the tape's), LB_ENOMEM. */
+int lb_tape_reserve(lb_ctx *ctx, int32_t nsteps, const lb_beads *beads);
 int lb_backward(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3]);
 int lb_backward_coupled(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, const double *dL_dR_T, const double *dL_dP_T,
                         void *dL_dn_0, double dL_dg[3], double *dL_dR_0, double *dL_dP_0);

@@ -29,9 +29,9 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", 
 # Every symbol declared in include/lb.h.
 EXPORTS = (
     "lb_create", "lb_destroy", "lb_init_equilibrium", "lb_set_populations", "lb_get_populations", "lb_step",
-    "lb_couple", "lb_moments", "lb_totals", "lb_totals_exact", "lb_mode_stats", "lb_noise_sample", "lb_sync", "lb_step_count",
+    "lb_couple", "lb_coupled_steps", "lb_moments", "lb_totals", "lb_totals_exact", "lb_mode_stats", "lb_noise_sample", "lb_sync", "lb_step_count",
     "lb_set_step_count", "lb_last_error", "lb_create_batch", "lb_vacf", "lb_launch_config", "lb_save", "lb_load", "lb_backward_coupled",
-    "lb_tape_begin", "lb_backward", "lb_step_noalloc", "lb_params_two_rate",
+    "lb_tape_begin", "lb_tape_reserve", "lb_backward", "lb_step_noalloc", "lb_params_two_rate",
 )
 
 
@@ -106,6 +106,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.lb_get_populations.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32]
     L.lb_step.argtypes = [vp, ctypes.c_int32]
     L.lb_couple.argtypes = [vp, ctypes.POINTER(lb_beads)]
+    L.lb_coupled_steps.argtypes = [vp, ctypes.POINTER(lb_beads), ctypes.c_int32]
     L.lb_moments.argtypes = [vp, vp, vp]
     L.lb_totals.argtypes = [vp, dp]
     L.lb_totals_exact.argtypes = [vp, dp]
@@ -120,6 +121,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.lb_vacf.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     L.lb_launch_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.lb_tape_begin.argtypes = [vp, ctypes.c_int32]
+    L.lb_tape_reserve.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(lb_beads)]
     L.lb_backward.argtypes = [vp, vp, ctypes.c_int32, vp, dp]
     L.lb_backward_coupled.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, dp, vp, vp]
     L.lb_save.argtypes = [vp, ctypes.c_char_p]

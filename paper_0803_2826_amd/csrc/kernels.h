@@ -310,13 +310,41 @@ struct StepArgs {
     uint32_t *fmask;        // [ceil(N/32)] 1 bit per site: bead force present (FORCE only)
     long long *force;       // [3][N] bead force density at flagged sites, fixed point (FORCE only)
     uint32_t consume;       // FORCE: 1 = zero the force rows and bitmap words this step read
+    // fused coupled step (k_coupled_step): the first block0 blocks of the
+    // grid are the particle half, which adds the bead force of this step
+    // while the site blocks run; a site block reads a flagged site's force
+    // once *arrive has reached arrive_target (every particle block counted)
+    uint32_t *arrive;
+    uint32_t arrive_target;
+    uint32_t block0;
 };
 
-__device__ __forceinline__ uint32_t tile_index(uint32_t remap)
+// Tile of block b of G site blocks: with remap, consecutive tiles go to one
+// XCD (hardware block b runs on XCD b mod 8).
+__device__ __forceinline__ uint32_t tile_of(uint32_t b, uint32_t G, uint32_t remap)
 {
-    const uint32_t b = blockIdx.x, G = gridDim.x;
     if (remap && (G & 7u) == 0) return (b & 7u) * (G >> 3) + (b >> 3);
     return b;
+}
+
+__device__ __forceinline__ uint32_t tile_index(uint32_t remap) { return tile_of(blockIdx.x, gridDim.x, remap); }
+
+// Bound on the polls of a site wave waiting for the particle blocks of its
+// launch (each poll is a device-coherent load, about a microsecond): the
+// particle blocks come first in the grid and wait for nothing, so the count
+// is normally reached within a few polls; if it is not, the wave gives up,
+// latches bit 3 of the device flags (the host reports the step as failed)
+// and goes on, so that no launch can hang.
+constexpr uint32_t kArriveSpinLimit = 1u << 16;
+
+__device__ __forceinline__ void wait_arrivals(const uint32_t *arrive, uint32_t target, int32_t *flags)
+{
+    for (uint32_t k = 0; k < kArriveSpinLimit; ++k) {
+        const uint32_t v = __hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(v - target) >= 0) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_fetch_or(flags, 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Block-wide sums of (FP64 mass, 3 FP32 momentum components) into one FP64
@@ -555,12 +583,16 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
 // layer (block b: layer z = b / tiles, in-layer sites r = (b - z tiles)
 // blockDim + thread), so the base of every plane a block loads from or
 // stores to is uniform over the block (the buffers are z-major, pop_index).
-template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL>
+// WAIT (fused coupled step): the grid's first a.block0 blocks are not site
+// blocks, and the bead force of a flagged site is taken once the particle
+// blocks have all been counted (wait_arrivals), with device-scope atomic
+// exchanges that read it and leave the field zero.
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL, bool WAIT = false>
 __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
-    const uint32_t b = tile_index(a.xcd_remap);
+    const uint32_t b = WAIT ? tile_of(blockIdx.x - a.block0, gridDim.x - a.block0, a.xcd_remap) : tile_index(a.xcd_remap);
     const uint32_t z = fdiv(b, a.div_tiles);
     const uint32_t nxny = a.geo.nxny;
     const uint32_t r = (b - z * a.tiles) * blockDim.x + threadIdx.x;
@@ -604,7 +636,23 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         mass_acc_t<ST> m_in = 0;
         if constexpr (S::rest_lo) m_in = site_mass_lo<ST>(d, lo_in);
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
-        if (FORCE) {
+        if (FORCE && WAIT) {
+            const uint32_t bit = 1u << (s & 31u);
+            const bool flagged = (a.fmask[s >> 5] & bit) != 0u;
+            if (__any(flagged)) wait_arrivals(a.arrive, a.arrive_target, a.flags);
+            if (flagged) {
+                // the spread of this launch's particle blocks was performed
+                // (device-scope atomics) before their count reached the
+                // target; the exchanges are issued after it was seen
+                long long *f = a.force;
+                F[0] += force_value(__hip_atomic_exchange(&f[s], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                F[1] += force_value(
+                    __hip_atomic_exchange(&f[(size_t)N + s], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                F[2] += force_value(
+                    __hip_atomic_exchange(&f[2 * (size_t)N + s], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                atomicAnd(&a.fmask[s >> 5], ~bit);
+            }
+        } else if (FORCE) {
             const uint32_t bit = 1u << (s & 31u);
             if (a.fmask[s >> 5] & bit) {
                 F[0] += force_value(a.force[s]);
@@ -631,7 +679,7 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
         if constexpr (S::rest_lo) store_site<ST, TOTALS>(dstp, (uint32_t)plane, r, m_in, out, mass, mom, rw);
         else store_site16<ST, TOTALS>(dstp, (uint32_t)plane, r, m0, out, mass, mom, rw);
     }
-    if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)blockIdx.x, mass, mom);
+    if (TOTALS) block_sum_totals(a.partials + 4 * (size_t)(blockIdx.x - (WAIT ? a.block0 : 0u)), mass, mom);
 }
 
 // The fused step kernel.  Occupancy is the compiler's own allocation: the

@@ -21,6 +21,7 @@
 #include "bead_adjoint.h"
 #include "batch.h"
 #include "couple.h"
+#include "fused.h"
 
 using namespace lbmi;
 
@@ -71,6 +72,14 @@ struct lb_ctx {
     int32_t *cell_next = nullptr;    // [n] next bead in the same cell
     int32_t *cell_of = nullptr;      // [n] cell of each bead
     int pair_cap = 0;
+    // fused coupled steps (allocated on the first lb_coupled_steps that fuses)
+    double *bead_pp = nullptr;       // [2][2][cap][3] alternate bead states (pos, mom) between launches
+    int bead_pp_cap = 0;
+    uint32_t *fmask_f = nullptr;     // [ceil(N/32)] second bitmap: the next step's nodes
+    uint32_t *arrive = nullptr;      // count of finished particle blocks (all launches)
+    uint32_t arrive_count = 0;       // its value once every enqueued launch has finished
+    int32_t *partner = nullptr;      // [n][deg] bond partners of each bead
+    size_t partner_cap = 0;
     bool tuned = false;              // launch configuration chosen (autotune done or fixed)
     uint32_t xcd_remap = LBMI_XCD_REMAP;  // step kernel: consecutive tiles on one XCD (if the grid allows)
     // single box: launch configuration of the step kernel without / with a
@@ -114,6 +123,7 @@ struct lb_ctx {
     // tape_bead at byte offset tape_off[slot] (TapeSlot)
     std::vector<int32_t> tape_slot;
     std::vector<lb_beads> tape_beads;
+    std::vector<void *> ckpt_ready;   // checkpoint buffers allocated ahead of the steps that fill them
     std::vector<size_t> tape_off;
     int pending_slot = -1;
     int tape_nb = 0;
@@ -379,6 +389,7 @@ int read_flags(lb_ctx *c)
     if (h & 2) return fail(c, LB_ENONFINITE, "a FENE bond was stretched to r >= r0 (bead momentum is NaN)");
     if (h & 4) return fail(c, LB_ENONFINITE, "a bead's spread force was not finite (not applied)");
     if (h & 1) return fail(c, LB_ENONFINITE, "non-finite population encountered on the device");
+    if (h & 8) return fail(c, LB_EDEVICE, "a fused coupled step's site blocks stopped waiting for its particle blocks");
     return LB_OK;
 }
 
@@ -436,10 +447,31 @@ int ensure_bead_buffers(lb_ctx *c, int n)
 
 size_t state_bytes(const lb_ctx *c) { return (size_t)c->geo.planes * c->geo.N * c->elem; }
 
+// The checkpoints that the next nsteps taped steps will push, allocated
+// before their first launch (an allocation between the launches of a run
+// would stall the queue).
+int reserve_checkpoints(lb_ctx *c, int32_t nsteps)
+{
+    if (!c->taping) return LB_OK;
+    const uint64_t s0 = c->step - c->tape_step0, K = (uint64_t)c->tape_k;
+    const size_t count = (size_t)((s0 + (uint64_t)nsteps) / K - s0 / K);
+    while (c->ckpt_ready.size() < count) {
+        void *p = nullptr;
+        if (hipMalloc(&p, state_bytes(c)) != hipSuccess) return fail(c, LB_ENOMEM, "checkpoint allocation failed");
+        c->ckpt_ready.push_back(p);
+    }
+    return LB_OK;
+}
+
 int push_checkpoint(lb_ctx *c)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, state_bytes(c)) != hipSuccess) return fail(c, LB_ENOMEM, "checkpoint allocation failed");
+    if (!c->ckpt_ready.empty()) {
+        p = c->ckpt_ready.back();
+        c->ckpt_ready.pop_back();
+    } else if (hipMalloc(&p, state_bytes(c)) != hipSuccess) {
+        return fail(c, LB_ENOMEM, "checkpoint allocation failed");
+    }
     c->checkpoints.push_back(p);
     return check(c, hipMemcpyAsync(p, c->bufA, state_bytes(c), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
 }
@@ -473,6 +505,8 @@ void free_tape(lb_ctx *c)
 {
     for (void *p : c->checkpoints) (void)hipFree(p);
     c->checkpoints.clear();
+    for (void *p : c->ckpt_ready) (void)hipFree(p);
+    c->ckpt_ready.clear();
     c->taping = false;
     c->seg_fwd = false;
     c->tape_slot.clear();
@@ -659,14 +693,14 @@ void launch_couple(lb_ctx *c, const void *pop, const lb_beads *b, const double *
 
 // Reserves the tape slot of a taped coupled step (the particle half's
 // kernels fill it).
-int tape_reserve(lb_ctx *c, const lb_beads *b, TapeSlot *out)
+// Room in the bead tape for `slots` more records of b (at most one
+// reallocation, which waits for the stream: a run of taped steps asks for
+// all of its slots before its first launch).
+int tape_grow(lb_ctx *c, const lb_beads *b, size_t slots)
 {
-    if (c->tape_nb == 0) c->tape_nb = b->n;
-    if (b->n != c->tape_nb)
-        return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
-    const size_t need = tape_slot_bytes(b);
+    const size_t need = slots * tape_slot_bytes(b);
     if (c->tape_bead_used + need > c->tape_bead_bytes) {
-        const size_t cap = std::max<size_t>(16 * need, 2 * (c->tape_bead_used + need));
+        const size_t cap = std::max<size_t>(16 * tape_slot_bytes(b), 2 * (c->tape_bead_used + need));
         char *p = nullptr;
         if (hipMalloc(&p, cap) != hipSuccess) return fail(c, LB_ENOMEM, "bead tape allocation failed");
         if (c->tape_bead && c->tape_bead_used > 0)
@@ -679,6 +713,16 @@ int tape_reserve(lb_ctx *c, const lb_beads *b, TapeSlot *out)
         c->tape_bead = p;
         c->tape_bead_bytes = cap;
     }
+    return LB_OK;
+}
+
+int tape_reserve(lb_ctx *c, const lb_beads *b, TapeSlot *out)
+{
+    if (c->tape_nb == 0) c->tape_nb = b->n;
+    if (b->n != c->tape_nb)
+        return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
+    LB_TRY(tape_grow(c, b, 1));
+    const size_t need = tape_slot_bytes(b);
     c->tape_off.push_back(c->tape_bead_used);
     c->tape_bead_used += need;
     c->tape_beads.push_back(*b);
@@ -720,6 +764,9 @@ StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
     a.fmask = nullptr;
     a.force = nullptr;
     a.consume = 0u;
+    a.arrive = nullptr;
+    a.arrive_target = 0u;
+    a.block0 = 0u;
     return a;
 }
 
@@ -963,6 +1010,183 @@ int batch_step(lb_ctx *c, int32_t nsteps)
     return LB_OK;
 }
 
+// Output buffer of the next single-box step: bufB; while taping, for the
+// step that ends a segment a new checkpoint buffer (*ckpt = true: the step
+// writes the checkpoint itself, which then holds the state until the next
+// step reads it; nothing writes into it afterwards, and a call that replaces
+// the state in place first moves it to an own buffer, settle_state), and
+// inside a segment the segment buffer's next slot (the step buffer the
+// reverse sweep would otherwise recompute).
+int step_dst(lb_ctx *c, void **dst, bool *ckpt)
+{
+    *dst = c->bufB;
+    *ckpt = false;
+    if (!c->taping) return LB_OK;
+    const uint64_t k = (c->step - c->tape_step0) % (uint64_t)c->tape_k;
+    if (k + 1 == (uint64_t)c->tape_k) {
+        if (!c->ckpt_ready.empty()) {
+            *dst = c->ckpt_ready.back();
+            c->ckpt_ready.pop_back();
+        } else if (hipMalloc(dst, state_bytes(c)) != hipSuccess) {
+            return fail(c, LB_ENOMEM, "checkpoint allocation failed");
+        }
+        *ckpt = true;
+    } else if (c->seg_fwd) {
+        *dst = static_cast<char *>(c->seg) + (size_t)(k + 1) * state_bytes(c);
+    }
+    return LB_OK;
+}
+
+// Bookkeeping after a single-box step launch that wrote the state to dst
+// (ckpt: dst is the checkpoint of the segment the step ended).
+int step_done(lb_ctx *c, void *dst, bool tot, bool ckpt)
+{
+    // the state moves to dst; bufB becomes an own buffer that does not hold it
+    c->bufB = (c->bufA == c->own[0] || c->bufA == c->own[1]) ? c->bufA : (dst == c->own[0] ? c->own[1] : c->own[0]);
+    c->bufA = dst;
+    ++c->step;
+    c->totals_valid = tot;
+    if (ckpt) c->checkpoints.push_back(dst);
+    return LB_OK;
+}
+
+// Argument checks of lb_couple and lb_coupled_steps (LB_OK: go on).
+int couple_check(lb_ctx *c, const lb_beads *b)
+{
+    if (c->batch) return fail(c, LB_EUNSUPPORTED, "bead coupling is not available on a batch context");
+    if (!b) return fail(c, LB_EINVAL, "beads is NULL");
+    if (b->n < 0 || b->nbonds < 0) return fail(c, LB_EINVAL, "bead and bond counts must be >= 0");
+    if (b->n > (1 << 26)) return fail(c, LB_EINVAL, "too many beads");
+    if (c->pending_force) return fail(c, LB_ESTATE, "lb_couple called twice without lb_step");
+    if (b->n == 0) return LB_OK;
+    if (!b->pos || !b->mom || !b->mass || !b->zeta || (b->nbonds > 0 && !b->bonds))
+        return fail(c, LB_EINVAL, "bead arrays must be non-NULL");
+    if (!std::isfinite(b->k_bond) || !std::isfinite(b->r0)) return fail(c, LB_EINVAL, "bond parameters must be finite");
+    if (b->stencil != 0 && b->stencil != 2 && b->stencil != 3 && b->stencil != 4)
+        return fail(c, LB_EINVAL, "stencil must be 0, 2, 3 or 4");
+    if (b->bond != LB_BOND_HARMONIC && b->bond != LB_BOND_FENE) return fail(c, LB_EINVAL, "unknown bond kind");
+    if (b->noise != LB_NOISE_GAUSSIAN && b->noise != LB_NOISE_THREE_POINT)
+        return fail(c, LB_EINVAL, "unknown bead noise distribution");
+    if (b->bond == LB_BOND_FENE && b->nbonds > 0 && !(b->r0 > 0.0 && b->k_bond >= 0.0))
+        return fail(c, LB_EINVAL, "FENE bonds need r0 > 0 and k_bond >= 0");
+    if (!(std::isfinite(b->wca_epsilon) && b->wca_epsilon >= 0.0))
+        return fail(c, LB_EINVAL, "wca_epsilon must be finite and >= 0");
+    const bool wca = b->wca_epsilon > 0.0;
+    if (wca) {
+        if (!(std::isfinite(b->wca_sigma) && b->wca_sigma > 0.0))
+            return fail(c, LB_EINVAL, "wca_sigma must be finite and > 0");
+        const double rc = std::cbrt(std::sqrt(2.0)) * b->wca_sigma;
+        const int32_t lmin = std::min(c->p.nx, c->p.walls ? c->p.ny : std::min(c->p.ny, c->p.nz));
+        if (!(2.0 * rc < (double)lmin))
+            return fail(c, LB_EINVAL, "the WCA cutoff 2^(1/6) sigma must be below half of every periodic box extent");
+    }
+    return LB_OK;
+}
+
+// Bond partners of each bead for the fused coupled step: table [n][deg] in
+// bond-list order, -1 padded (bonds with an index outside [0, n) are
+// skipped, as bond_force does).  *deg = 0 without bonds; *ok = false if the
+// largest degree exceeds kMaxFusedDegree (those runs take separate launches).
+constexpr int kMaxFusedDegree = 64;
+
+int build_partners(lb_ctx *c, const lb_beads *b, int *deg, bool *ok)
+{
+    *deg = 0;
+    *ok = true;
+    if (b->nbonds == 0) return LB_OK;
+    std::vector<int32_t> bonds(2 * (size_t)b->nbonds);
+    LB_TRY(check(c, hipMemcpyAsync(bonds.data(), b->bonds, bonds.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   c->stream), "bond list copy"));
+    LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    const int n = b->n;
+    std::vector<int32_t> cnt((size_t)n, 0);
+    auto valid = [&](size_t q) {
+        const int32_t ia = bonds[2 * q], ib = bonds[2 * q + 1];
+        return ia >= 0 && ib >= 0 && ia < n && ib < n;
+    };
+    for (size_t q = 0; q < (size_t)b->nbonds; ++q)
+        if (valid(q)) {
+            ++cnt[bonds[2 * q]];
+            ++cnt[bonds[2 * q + 1]];
+        }
+    int d = 0;
+    for (int v : cnt) d = std::max(d, v);
+    if (d > kMaxFusedDegree) {
+        *ok = false;
+        return LB_OK;
+    }
+    *deg = d;
+    if (d == 0) return LB_OK;
+    std::vector<int32_t> tab((size_t)n * d, -1);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (size_t q = 0; q < (size_t)b->nbonds; ++q)
+        if (valid(q)) {
+            const int32_t ia = bonds[2 * q], ib = bonds[2 * q + 1];
+            tab[(size_t)ia * d + cnt[ia]++] = ib;
+            tab[(size_t)ib * d + cnt[ib]++] = ia;
+        }
+    if (c->partner_cap < tab.size()) {
+        (void)hipFree(c->partner);
+        c->partner = nullptr;
+        c->partner_cap = 0;
+        if (hipMalloc(&c->partner, tab.size() * sizeof(int32_t)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "bond partner table allocation failed");
+        c->partner_cap = tab.size();
+    }
+    // synchronous: the host table goes out of scope
+    LB_TRY(check(c, hipMemcpyAsync(c->partner, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   c->stream), "bond partner table upload"));
+    return check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+// Buffers of the fused coupled step: the alternate bead states, the second
+// bitmap and the particle block counter.
+int ensure_fused_buffers(lb_ctx *c, int n)
+{
+    if (!c->fmask_f || !c->arrive) {
+        const size_t nwords = ((size_t)c->geo.N + 31) / 32;
+        if (hipMalloc(&c->fmask_f, nwords * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&c->arrive, sizeof(uint32_t)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "fused step buffers allocation failed");
+        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nwords, 256)), dim3(256), 0, c->stream,
+                           reinterpret_cast<int32_t *>(c->fmask_f), (uint32_t)nwords);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t *>(c->arrive), 1u);
+        LB_LAUNCH_CHECK(c, "zero fused step buffers");
+        c->arrive_count = 0;
+    }
+    if (n > c->bead_pp_cap) {
+        (void)hipFree(c->bead_pp);
+        c->bead_pp = nullptr;
+        c->bead_pp_cap = 0;
+        if (hipMalloc(&c->bead_pp, 12 * (size_t)n * sizeof(double)) != hipSuccess)
+            return fail(c, LB_ENOMEM, "fused step bead buffers allocation failed");
+        c->bead_pp_cap = n;
+    }
+    return LB_OK;
+}
+
+template <int ST, bool TH, bool TOT>
+void launch_fused_t(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid)
+{
+    const size_t lds = TOT ? (size_t)kTotalsLds * (size_t)c->block : 0;  // block_sum_totals
+    if (TH && c->full_relax)
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, 2>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
+    else
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, 2>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
+}
+
+template <int ST>
+void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid, bool tot)
+{
+    if (c->thermal) {
+        if (tot) launch_fused_t<ST, true, true>(c, a, p, grid);
+        else launch_fused_t<ST, true, false>(c, a, p, grid);
+    } else {
+        if (tot) launch_fused_t<ST, false, true>(c, a, p, grid);
+        else launch_fused_t<ST, false, false>(c, a, p, grid);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1145,6 +1369,9 @@ int lb_destroy(lb_ctx *c)
                    c->bead_work, c->fbar, c->force2, c->fmask2};
     for (void *q : adj)
         if (q) (void)hipFree(q);
+    void *fused[] = {c->bead_pp, c->fmask_f, c->arrive, c->partner};
+    for (void *q : fused)
+        if (q) (void)hipFree(q);
     if (c->batch) {
         if (c->ev_in) (void)hipEventDestroy(c->ev_in);
         if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -1260,17 +1487,14 @@ int lb_step(lb_ctx *c, int32_t nsteps)
         return batch_step(c, nsteps);
     }
     const bool tot = c->p.track_totals != 0;
+    LB_TRY(reserve_checkpoints(c, nsteps));
     for (int32_t t = 0; t < nsteps; ++t) {
         const bool frc = c->pending_force;
         LB_TRY(select_launch(c, frc));
         if (c->taping) c->tape_slot.push_back(frc ? c->pending_slot : -1);
-        void *dst = c->bufB;
-        if (c->taping && c->seg_fwd) {
-            // inside a segment the step writes the segment buffer's next slot,
-            // the step buffer the reverse sweep would otherwise recompute
-            const uint64_t k = (c->step - c->tape_step0) % (uint64_t)c->tape_k;
-            if (k + 1 < (uint64_t)c->tape_k) dst = static_cast<char *>(c->seg) + (size_t)(k + 1) * state_bytes(c);
-        }
+        void *dst = nullptr;
+        bool ckpt = false;
+        LB_TRY(step_dst(c, &dst, &ckpt));
         StepArgs a = plain_step_args(c, c->bufA, dst, (uint32_t)c->step);
         if (frc) {
             // the step reads the bead force and leaves the field and its bitmap zero
@@ -1284,12 +1508,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
             c->pending_force = false;
             c->pending_slot = -1;
         }
-        // the state moves to dst; bufB becomes an own buffer that does not hold it
-        c->bufB = (c->bufA == c->own[0] || c->bufA == c->own[1]) ? c->bufA : (dst == c->own[0] ? c->own[1] : c->own[0]);
-        c->bufA = dst;
-        ++c->step;
-        c->totals_valid = tot;
-        if (c->taping && (c->step - c->tape_step0) % (uint64_t)c->tape_k == 0) LB_TRY(push_checkpoint(c));
+        LB_TRY(step_done(c, dst, tot, ckpt));
     }
     return LB_OK;
 }
@@ -1337,33 +1556,9 @@ int lb_step_noalloc(const lb_params *params, const void *src, void *dst, uint64_
 int lb_couple(lb_ctx *c, const lb_beads *b)
 {
     if (!c) return LB_EINVAL;
-    if (c->batch) return fail(c, LB_EUNSUPPORTED, "bead coupling is not available on a batch context");
-    if (!b) return fail(c, LB_EINVAL, "beads is NULL");
-    if (b->n < 0 || b->nbonds < 0) return fail(c, LB_EINVAL, "bead and bond counts must be >= 0");
-    if (b->n > (1 << 26)) return fail(c, LB_EINVAL, "too many beads");
-    if (c->pending_force) return fail(c, LB_ESTATE, "lb_couple called twice without lb_step");
+    LB_TRY(couple_check(c, b));
     if (b->n == 0) return LB_OK;
-    if (!b->pos || !b->mom || !b->mass || !b->zeta || (b->nbonds > 0 && !b->bonds))
-        return fail(c, LB_EINVAL, "bead arrays must be non-NULL");
-    if (!std::isfinite(b->k_bond) || !std::isfinite(b->r0)) return fail(c, LB_EINVAL, "bond parameters must be finite");
-    if (b->stencil != 0 && b->stencil != 2 && b->stencil != 3 && b->stencil != 4)
-        return fail(c, LB_EINVAL, "stencil must be 0, 2, 3 or 4");
-    if (b->bond != LB_BOND_HARMONIC && b->bond != LB_BOND_FENE) return fail(c, LB_EINVAL, "unknown bond kind");
-    if (b->noise != LB_NOISE_GAUSSIAN && b->noise != LB_NOISE_THREE_POINT)
-        return fail(c, LB_EINVAL, "unknown bead noise distribution");
-    if (b->bond == LB_BOND_FENE && b->nbonds > 0 && !(b->r0 > 0.0 && b->k_bond >= 0.0))
-        return fail(c, LB_EINVAL, "FENE bonds need r0 > 0 and k_bond >= 0");
-    if (!(std::isfinite(b->wca_epsilon) && b->wca_epsilon >= 0.0))
-        return fail(c, LB_EINVAL, "wca_epsilon must be finite and >= 0");
     const bool wca = b->wca_epsilon > 0.0;
-    if (wca) {
-        if (!(std::isfinite(b->wca_sigma) && b->wca_sigma > 0.0))
-            return fail(c, LB_EINVAL, "wca_sigma must be finite and > 0");
-        const double rc = std::cbrt(std::sqrt(2.0)) * b->wca_sigma;
-        const int32_t lmin = std::min(c->p.nx, c->p.walls ? c->p.ny : std::min(c->p.ny, c->p.nz));
-        if (!(2.0 * rc < (double)lmin))
-            return fail(c, LB_EINVAL, "the WCA cutoff 2^(1/6) sigma must be below half of every periodic box extent");
-    }
     LB_TRY(use_device(c));
     LB_TRY(ensure_bead_buffers(c, b->n));
     if (wca) {
@@ -1376,6 +1571,110 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
     launch_couple(c, c->bufA, b, b->pos, b->mom, b->pos, b->mom, (uint32_t)c->step, c->taping ? &slot : nullptr);
     LB_LAUNCH_CHECK(c, "couple");
     c->pending_force = true;
+    return LB_OK;
+}
+
+int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
+{
+    if (!c) return LB_EINVAL;
+    if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
+    LB_TRY(couple_check(c, b));
+    if (nsteps == 0) return LB_OK;
+    if (c->step + (uint64_t)nsteps > 0xffffffffull) return fail(c, LB_EINVAL, "step counter would exceed 2^32");
+    LB_TRY(use_device(c));
+    // one launch per step for the trilinear stencil without pair forces and
+    // walls; everything else (and a single step: its bead state would be
+    // read and written by the same launch) takes the separate launches
+    bool fused = nsteps >= 2 && b->n > 0 && !(b->wca_epsilon > 0.0) && !c->geo.walls && stencil_width(b) == 2;
+    int deg = 0;
+    if (fused) LB_TRY(build_partners(c, b, &deg, &fused));
+    if (!fused) {
+        for (int32_t k = 0; k < nsteps; ++k) {
+            LB_TRY(lb_couple(c, b));
+            LB_TRY(lb_step(c, 1));
+        }
+        return LB_OK;
+    }
+    const int n = b->n;
+    constexpr int LANES = StencilLanes<2>::value;
+    LB_TRY(ensure_bead_buffers(c, n));
+    LB_TRY(ensure_fused_buffers(c, n));
+    if (c->taping) {
+        if (c->tape_nb == 0) c->tape_nb = n;
+        if (n != c->tape_nb) return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
+        LB_TRY(tape_grow(c, b, (size_t)nsteps));
+        LB_TRY(reserve_checkpoints(c, nsteps));
+    }
+    uint32_t *const bm[2] = {c->fmask, c->fmask_f};
+    hipLaunchKernelGGL(k_bead_nodes<2>, dim3(grid_for((size_t)LANES * n, 256)), dim3(256), 0, c->stream, b->pos,
+                       b->mom, b->mass, n, c->geo, bm[0]);
+    LB_LAUNCH_CHECK(c, "bead nodes");
+    const bool tot = c->p.track_totals != 0;
+    const size_t n3 = 3 * (size_t)n;
+    const double *pos_in = b->pos, *mom_in = b->mom;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        // the last step writes the caller's arrays, the others alternate
+        // between two private states
+        double *pos = k + 1 == nsteps ? b->pos : c->bead_pp + (size_t)(k & 1) * 2 * n3;
+        double *mom = k + 1 == nsteps ? b->mom : pos + n3;
+        c->pending_slot = -1;
+        TapeSlot slot;
+        if (c->taping) LB_TRY(tape_reserve(c, b, &slot));
+        LB_TRY(select_launch(c, true));
+        if (c->taping) c->tape_slot.push_back(c->pending_slot);
+        void *dst = nullptr;
+        bool ckpt = false;
+        LB_TRY(step_dst(c, &dst, &ckpt));
+        StepArgs a = plain_step_args(c, c->bufA, dst, (uint32_t)c->step);
+        a.fmask = bm[k & 1];
+        a.force = c->force;
+        a.consume = 1u;
+        const uint32_t pblocks = (uint32_t)((grid_for((size_t)LANES * n, (unsigned)c->block) + 7) / 8 * 8);
+        c->arrive_count += pblocks;
+        a.arrive = c->arrive;
+        a.arrive_target = c->arrive_count;
+        a.block0 = pblocks;
+        ParticleArgs p;
+        p.pop = c->bufA;
+        p.geo = c->geo;
+        p.rho0 = c->p.rho0;
+        for (int q = 0; q < 3; ++q) p.g[q] = c->p.body_force[q];
+        p.kT = c->p.kT;
+        p.key0 = c->cc.key0;
+        p.key1 = c->cc.key1;
+        p.box = c->cc.box;
+        p.step = (uint32_t)c->step;
+        p.n = n;
+        p.pos_in = pos_in;
+        p.mom_in = mom_in;
+        p.pos = pos;
+        p.mom = mom;
+        p.mass = b->mass;
+        p.zeta = b->zeta;
+        p.fext = b->fext;
+        p.partner = c->partner;
+        p.deg = deg;
+        p.fene = (int32_t)(b->bond == LB_BOND_FENE);
+        p.three_point = (int32_t)(b->noise == LB_NOISE_THREE_POINT);
+        p.kb = b->k_bond;
+        p.r0 = b->r0;
+        p.flags = c->flags;
+        p.force = c->force;
+        p.fmask_next = k + 1 < nsteps ? bm[(k + 1) & 1] : nullptr;
+        p.half = c->taping ? slot.half : c->half;
+        p.fc = c->taping ? slot.fc : c->fc;
+        p.tape_mom0 = c->taping ? slot.mom0 : nullptr;
+        p.tape_momn = c->taping ? slot.momn : nullptr;
+        p.tape_contrib = c->taping ? slot.contrib : nullptr;
+        p.arrive = c->arrive;
+        const unsigned grid = pblocks + (unsigned)c->nblocks;
+        by_step_storage(c->p, [&](auto st) { launch_fused_st<decltype(st)::value>(c, a, p, grid, tot); });
+        LB_LAUNCH_CHECK(c, "coupled step");
+        c->pending_slot = -1;
+        LB_TRY(step_done(c, dst, tot, ckpt));
+        pos_in = pos;
+        mom_in = mom;
+    }
     return LB_OK;
 }
 
@@ -1516,6 +1815,22 @@ int lb_sync(lb_ctx *c)
     if (!c) return LB_EINVAL;
     LB_TRY(use_device(c));
     return read_flags(c);
+}
+
+int lb_tape_reserve(lb_ctx *c, int32_t nsteps, const lb_beads *b)
+{
+    if (!c) return LB_EINVAL;
+    if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
+    if (!c->taping) return fail(c, LB_ESTATE, "no tape is recording");
+    LB_TRY(use_device(c));
+    LB_TRY(reserve_checkpoints(c, nsteps));
+    if (b && b->n > 0) {
+        if (c->tape_nb == 0) c->tape_nb = b->n;
+        if (b->n != c->tape_nb)
+            return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
+        LB_TRY(tape_grow(c, b, (size_t)nsteps));
+    }
+    return LB_OK;
 }
 
 int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)

@@ -229,11 +229,11 @@ def differentiation_study(checkpoint_every: int, steps: int | None = None, workl
     beads = DeviceBeads(pos, mom, np.full(nb, W["mass"]), np.full(nb, W["zeta"]), bonds, W["k_bond"], W["r0"])
     lat.tape_begin(checkpoint_every)  # allocates the segment buffer outside the timed region
     lat.tape_begin(checkpoint_every)
+    lat.tape_reserve(T, beads)  # ... and the checkpoints and the bead tape
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
     ev[0].record(lat.stream)
-    for _ in range(T):
-        lat.coupled_step(beads)
+    lat.coupled_steps(beads, T)
     ev[1].record(lat.stream)
     nT = lat.get_populations(dtype=torch.float64).requires_grad_()
     g_t = torch.tensor(W["g"], dtype=torch.float64, device=nT.device, requires_grad=True)
@@ -253,6 +253,20 @@ def differentiation_study(checkpoint_every: int, steps: int | None = None, workl
            "dg": np.asarray(dg, dtype=np.float64) + g_t.grad.detach().cpu().numpy(),
            "dR0": dR0.detach().cpu().numpy(), "dP0": dP0.detach().cpu().numpy()}
     lat.close()
+    return out
+
+
+def elementwise_errors(study: dict, ref: dict) -> dict:
+    """Element-wise errors of a differentiation_study gradient against a
+    stored FP64 adjoint of the same run (dL/dg, dL/dR(0), dL/dP(0) in full,
+    dL/dn(0) at the stored indices), each relative to the largest entry of
+    the stored gradient."""
+    dn = np.asarray(study["dn0"]).reshape(-1)
+    idx = np.asarray(ref["dn0_index"])
+    out = {"dn0": float(np.abs(dn[idx] - np.asarray(ref["dn0_sample"])).max() / ref["dn0_max_abs"])}
+    for k in ("dg", "dR0", "dP0"):
+        r = np.asarray(ref[k], dtype=np.float64)
+        out[k] = float(np.abs(np.asarray(study[k]) - r).max() / np.abs(r).max())
     return out
 
 

@@ -248,6 +248,16 @@ class Lattice:
         self.couple(beads)
         self.step(1)
 
+    def coupled_steps(self, beads: DeviceBeads, nsteps: int) -> None:
+        """nsteps coupled steps (lb_coupled_steps: one launch per step where
+        the run allows it; the same bits as nsteps coupled_step calls)."""
+        b = beads.to_c()
+        self._check(self.L.lb_coupled_steps(self.ctx, ctypes.byref(b), int(nsteps)))
+        if getattr(self, "_taped_beads", None) is not None and nsteps > 0:
+            self._taped_beads = beads.n
+            if not any(x is beads for x in self._tape_refs):
+                self._tape_refs.append(beads)
+
     # -- observables
     def moments(self):
         rho = torch.empty((self.params.nz, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
@@ -279,6 +289,12 @@ class Lattice:
         self._check(self.L.lb_tape_begin(self.ctx, int(checkpoint_every)))
         self._taped_beads = 0
         self._tape_refs = []
+
+    def tape_reserve(self, nsteps: int, beads: DeviceBeads | None = None) -> None:
+        """Allocate now the checkpoints (and, with beads, the bead tape) that
+        the next nsteps taped steps will take (lb_tape_reserve)."""
+        b = beads.to_c() if beads is not None else None
+        self._check(self.L.lb_tape_reserve(self.ctx, int(nsteps), ctypes.byref(b) if b is not None else None))
 
     def backward(self, dL_dnT: torch.Tensor):
         """dL/dn(t0) and dL/dg for the steps taken since tape_begin."""

@@ -1,0 +1,204 @@
+"""The fused coupled step (lb_coupled_steps: the particle half in the first
+blocks of the fluid step's launch, each bead summing its own bond forces)
+against the separate launches (lb_couple then lb_step, one step at a time)
+and against the FP64 oracle, through the C ABI.
+
+- Bit for bit: populations (read back in FP64 from the stored form, which
+  holds every stored bit), bead positions and momenta equal the separate
+  launches' after the same steps, for every storage variant, with and
+  without noise, totals and body force, harmonic and FENE bonds, three-point
+  bead noise, external forces, a ragged last tile; the forces of beads with
+  more than two bonds are summed in another order (bond-list order here,
+  atomics there), so branched chains are compared within 1e-12.
+- Taped: the reverse sweep over fused steps gives the gradients of the
+  sweep over separate ones (to the rounding of the sweep's FP32 atomics).
+- The oracle: 20 fused steps against orc.coupled_step at the tolerances of
+  test_gpu_beads.
+- Runs that take the separate launches (one step, WCA pairs, phi_3) match
+  the step-by-step loop too; no run leaves the wait flag (bit 3) set.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lat():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_0803_2826_amd import lattice
+    return lattice
+
+
+def make_beads(lat, dims, n_chains, length, seed, p0=0.01, branched=False, self_avoiding=False, **kw):
+    from paper_0803_2826_amd.inputs import kremer_grest_chains, random_walk_chains
+    gen = kremer_grest_chains if self_avoiding else random_walk_chains
+    pos, mom, bonds = gen(n_chains, length, dims, seed=seed)
+    mom = np.random.default_rng(seed + 1).normal(scale=p0, size=mom.shape)
+    if branched:
+        # tie the middle bead of every chain to the beads two before and two
+        # after it (about two lattice spacings away): degrees 4 and 3
+        extra = []
+        for c in range(n_chains):
+            mid = c * length + length // 2
+            extra.append((mid, mid - 2))
+            extra.append((mid + 2, mid))
+        bonds = np.concatenate([bonds, np.array(extra, dtype=bonds.dtype)])
+    nb = pos.shape[0]
+    mass = 1.0 + 0.25 * np.random.default_rng(seed + 2).random(nb)
+    args = dict(bonds=bonds, k_bond=kw.pop("k_bond", 0.5), r0=kw.pop("r0", 1.0))
+    return lambda: lat.DeviceBeads(pos.copy(), mom.copy(), mass, np.full(nb, kw.get("zeta", 20.0)), **args,
+                                   **{k: v for k, v in kw.items() if k != "zeta"})
+
+
+def run_pair(lat, params, beads_factory, steps, n_init=None, chunks=None):
+    """(separate, fused) runs from the same start: populations (FP64) and
+    bead pos, mom after `steps` coupled steps; `chunks` splits the fused run
+    into several lb_coupled_steps calls."""
+    import torch
+    out = []
+    for fused in (False, True):
+        dev = lat.Lattice(params)
+        if n_init is None:
+            dev.init_equilibrium()
+        else:
+            dev.set_populations(n_init)
+        b = beads_factory()
+        if fused:
+            for c in (chunks or [steps]):
+                dev.coupled_steps(b, c)
+        else:
+            for _ in range(steps):
+                dev.coupled_step(b)
+        dev.sync()
+        out.append((dev.get_populations().cpu(), b.pos.cpu().clone(), b.mom.cpu().clone(),
+                    dev.totals() if params.track_totals else None))
+        dev.close()
+        torch.cuda.synchronize()
+    return out
+
+
+def assert_same(a, b, tol=0.0):
+    import torch
+    names = ("populations", "positions", "momenta")
+    for name, x, y in zip(names, a[:3], b[:3]):
+        if tol == 0.0:
+            assert torch.equal(x, y), f"{name}: max diff {float((x - y).abs().max()):.3e}"
+        else:
+            scale = float(y.abs().max())
+            err = float((x - y).abs().max())
+            print(f"{name}: max diff {err:.3e} (scale {scale:.3e})")
+            assert err <= tol * max(scale, 1e-300)
+    if a[3] is not None:
+        assert tuple(a[3]) == tuple(b[3]) if tol == 0.0 else np.allclose(a[3], b[3], rtol=tol, atol=0)
+
+
+@pytest.mark.parametrize("storage,rounding", [("f32", "nearest"), ("bf16", "nearest"), ("f16", "nearest"),
+                                              ("bf16", "stochastic"), ("f16", "stochastic")])
+def test_fused_bitwise_storages(lat, storage, rounding):
+    """10 coupled steps (one call) on a 36 x 28 x 20 box (ragged tiles), 6
+    chains of 10 beads, thermal, body force, totals."""
+    p = lat.FluidParams(nx=36, ny=28, nz=20, kT=1e-4, seed=3, body_force=(1e-5, 0, 0), storage=storage,
+                        rounding=rounding, track_totals=True)
+    sep, fus = run_pair(lat, p, make_beads(lat, (36, 28, 20), 6, 10, seed=5), 10)
+    assert_same(fus, sep)
+
+
+@pytest.mark.parametrize("case", ["athermal", "fene", "three_point", "fext", "chunks", "block64"])
+def test_fused_bitwise_variants(lat, case):
+    kT = 0.0 if case == "athermal" else 1e-4
+    extra = {}
+    if case == "fene":
+        extra = dict(bond="fene", k_bond=0.3, r0=2.0)
+    if case == "three_point":
+        extra = dict(noise="three_point")
+    if case == "fext":
+        extra = dict(fext=np.random.default_rng(9).normal(scale=1e-3, size=(4 * 12, 3)))
+    p = lat.FluidParams(nx=24, ny=24, nz=24, kT=kT, seed=11, body_force=(0, 2e-6, 0),
+                        block=64 if case == "block64" else 0)
+    chunks = [2, 5, 3] if case == "chunks" else None
+    sep, fus = run_pair(lat, p, make_beads(lat, (24, 24, 24), 4, 12, seed=13, **extra), 10, chunks=chunks)
+    assert_same(fus, sep)
+
+
+def test_fused_branched_within_1e12(lat):
+    """Beads with three and four bonds: the bond forces are summed in another
+    order than the separate launches' atomics."""
+    p = lat.FluidParams(nx=24, ny=24, nz=24, kT=1e-4, seed=17)
+    sep, fus = run_pair(lat, p, make_beads(lat, (24, 24, 24), 5, 10, seed=19, branched=True), 12)
+    assert_same(fus, sep, tol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["one_step", "wca", "phi3"])
+def test_separate_launch_cases_match_loop(lat, case):
+    extra = {}
+    if case == "wca":
+        # self-avoiding chains (no overlapping pair), FENE bonds with WCA
+        extra = dict(self_avoiding=True, bond="fene", k_bond=3e-3, r0=1.5, wca_epsilon=1e-4, wca_sigma=1.0)
+    if case == "phi3":
+        extra = dict(stencil=3)
+    steps = 1 if case == "one_step" else 6
+    p = lat.FluidParams(nx=20, ny=20, nz=20, kT=1e-4, seed=23)
+    sep, fus = run_pair(lat, p, make_beads(lat, (20, 20, 20), 3, 8, seed=29, **extra), steps)
+    assert_same(fus, sep)
+
+
+def test_fused_against_oracle(orc, lat):
+    """20 fused coupled steps of 4 chains x 8 beads in a 16^3 box against the
+    oracle (tolerances of test_gpu_beads: beads 1e-7, populations 1e-6)."""
+    import torch
+    from test_gpu_beads import chains_setup
+    po, pd, bo, bd = chains_setup(orc, lat, 16, 4, 8, 1e-4, seed=7, g=(1e-5, 0, 0), p0=0.01)
+    n = orc.init_equilibrium(po)
+    dev = lat.Lattice(pd)
+    dev.set_populations(torch.from_numpy(n))
+    for t in range(20):
+        orc.coupled_step(po, n, t, bo)
+    dev.coupled_steps(bd, 20)
+    got = dev.get_populations().cpu().numpy()
+    dev.sync()
+    print("bead pos err", np.abs(bd.pos.cpu().numpy() - bo.pos).max(), "pop err", np.abs(got - n).max())
+    np.testing.assert_allclose(bd.pos.cpu().numpy(), bo.pos, atol=1e-7)
+    np.testing.assert_allclose(bd.mom.cpu().numpy(), bo.mom, atol=1e-7)
+    assert np.abs(got - n).max() <= 1e-6
+    dev.close()
+
+
+def test_fused_taped_gradients_match(lat):
+    """Reverse sweep over 12 taped coupled steps (checkpoint every 4), fused
+    against separate: identical dL/dn(0), dL/dg, dL/dR(0), dL/dP(0) for a
+    fixed seeded dL/dn(T), dL/dR(T), dL/dP(T)."""
+    import torch
+    L, T = 20, 12
+    p = lat.FluidParams(nx=L, ny=L, nz=L, kT=1e-4, seed=31, body_force=(1e-5, 0, 0))
+    factory = make_beads(lat, (L, L, L), 3, 8, seed=37)
+    g = torch.Generator().manual_seed(41)
+    lamT = torch.randn((19, L, L, L), generator=g, dtype=torch.float64)
+    res = []
+    for fused in (False, True):
+        dev = lat.Lattice(p)
+        dev.init_equilibrium()
+        b = factory()
+        nb = b.n
+        dR = torch.randn((nb, 3), generator=g, dtype=torch.float64) if not res else res[0][-2]
+        dP = torch.randn((nb, 3), generator=g, dtype=torch.float64) if not res else res[0][-1]
+        dev.tape_begin(4)
+        if fused:
+            dev.coupled_steps(b, T)
+        else:
+            for _ in range(T):
+                dev.coupled_step(b)
+        dn0, dg, dR0, dP0 = dev.backward_coupled(lamT.to(dev.device), dR.to(dev.device), dP.to(dev.device))
+        res.append((dn0.cpu(), torch.tensor(dg, dtype=torch.float64), dR0.cpu(), dP0.cpu(), dR, dP))
+        dev.close()
+    # the forward tapes hold the same bits; the reverse sweep adds the
+    # particle adjoint into lambda with FP32 atomics, whose order varies from
+    # run to run, so the two sweeps agree to rounding (the bar of
+    # test_gpu_adjoint_coupled: 2e-5 of each gradient's largest entry)
+    for name, x, y in zip(("dn0", "dg", "dR0", "dP0"), res[0][:4], res[1][:4]):
+        err = float((x - y).abs().max() / y.abs().max())
+        print(f"{name}: fused vs separate {err:.2e} of the largest entry")
+        assert err <= 2e-5, name
