@@ -380,6 +380,17 @@ int lb_moments(lb_ctx *ctx, double *rho, double *u);
  * returns LB_ENONFINITE if a non-finite population was seen. */
 int lb_totals(lb_ctx *ctx, double out[4]);
 
+/* Low-Mach guard: the number of sites of the current state (all boxes of a
+ * batch) with a negative population n_i = a_i rho0 + d_i, and the smallest
+ * n_i (host out; either may be NULL).  The method assumes Ma = u/c_s << 1
+ * (Sec. "The fluctuating lattice-Boltzmann equation"); the quadratic
+ * equilibrium of Sec. "D3Q19 model I" goes negative once u is not small,
+ * and thermal noise can push the populations with small a_i below zero.  A
+ * scan of the stored state (one read of it), not part of the step, so that
+ * it costs nothing unless called; non-finite values are not counted (the
+ * step latches them, LB_ENONFINITE).  Synchronises. */
+int lb_negative_count(lb_ctx *ctx, uint64_t *sites, double *min_pop);
+
 /* Same as lb_totals but always runs the full reduction pass. */
 int lb_totals_exact(lb_ctx *ctx, double out[4]);
 

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", 
 # Every symbol declared in include/lb.h.
 EXPORTS = (
     "lb_create", "lb_destroy", "lb_init_equilibrium", "lb_set_populations", "lb_get_populations", "lb_step",
-    "lb_couple", "lb_coupled_steps", "lb_moments", "lb_totals", "lb_totals_exact", "lb_mode_stats", "lb_noise_sample", "lb_sync", "lb_step_count",
+    "lb_couple", "lb_coupled_steps", "lb_moments", "lb_totals", "lb_totals_exact", "lb_negative_count", "lb_mode_stats", "lb_noise_sample", "lb_sync", "lb_step_count",
     "lb_set_step_count", "lb_last_error", "lb_create_batch", "lb_vacf", "lb_launch_config", "lb_save", "lb_load", "lb_backward_coupled",
     "lb_tape_begin", "lb_tape_reserve", "lb_backward", "lb_step_noalloc", "lb_params_two_rate",
 )
@@ -110,6 +110,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.lb_moments.argtypes = [vp, vp, vp]
     L.lb_totals.argtypes = [vp, dp]
     L.lb_totals_exact.argtypes = [vp, dp]
+    L.lb_negative_count.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), dp]
     L.lb_mode_stats.argtypes = [vp, dp]
     L.lb_noise_sample.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, vp]
     L.lb_sync.argtypes = [vp]

@@ -21,6 +21,8 @@ FLAGS = [
     "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
+# the library's ROCTX ranges around the API calls
+LDFLAGS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -35,7 +37,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str | None
     """Compile every HIP source into liblbmi.so (always recompiles)."""
     target = out or LIB
     tmp = target + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + FLAGS + (extra or []) + ["-o", tmp] + sources()
+    cmd = [hipcc()] + FLAGS + (extra or []) + ["-o", tmp] + sources() + LDFLAGS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=CSRC)

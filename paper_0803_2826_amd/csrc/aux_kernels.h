@@ -199,6 +199,54 @@ __global__ void __launch_bounds__(256) k_totals_exact(const void *buf, Geom g, d
     block_sum_f64<4>(partials + 4 * (size_t)blockIdx.x, acc);
 }
 
+// Positivity scan of the stored state (the low-Mach guard: the quadratic
+// equilibrium of Sec. "D3Q19 model I" turns negative once u is no longer
+// small against the lattice speeds, and thermal noise can push populations
+// below zero where a_i rho0 is small): per block, the number of sites with
+// a population n_i = a_i rho0 + d_i < 0 and the smallest n_i, into
+// partials[block] = {count, min}.  Grid-stride over the sites.
+template <int ST>
+__global__ void __launch_bounds__(256) k_negative_scan(const void *buf, Geom g, double rho0, double *partials)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const T *b = static_cast<const T *>(buf);
+    double cnt = 0.0, mn = __builtin_inf();
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
+        // the populations of site s (pulled as in k_get_pops)
+        uint32_t x, y, z;
+        const PullOffsets o = pull_offsets(s, g, x, y, z);
+        double site_min = __builtin_inf();
+        for (int i = 0; i < Q; ++i) {
+            const double d = i == 0 ? load_rest<ST>(b, s, z, g) : (double)S::ld(b[pull_index(s, o, i, z, g)], 0.f);
+            site_min = fmin(site_min, weight_of(i) * rho0 + d);
+        }
+        if (site_min < 0.0) cnt += 1.0;
+        mn = fmin(mn, site_min);
+    }
+    __shared__ double red[16][2];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off, 64);
+        mn = fmin(mn, __shfl_xor(mn, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wid][0] = cnt;
+        red[wid][1] = mn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double c = 0.0, m = __builtin_inf();
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) {
+            c += red[w][0];
+            m = fmin(m, red[w][1]);
+        }
+        partials[2 * (size_t)blockIdx.x] = c;
+        partials[2 * (size_t)blockIdx.x + 1] = m;
+    }
+}
+
 // Basis polynomial e_k(c) of Table 1 (integer valued).
 __device__ __forceinline__ double basis_k(int k, int x, int y, int z)
 {

@@ -5,6 +5,7 @@
 // keeps the step counter that keys the noise.  No CPU fallback exists: every
 // numerical step runs in the HIP kernels of this directory.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <functional>
@@ -14,6 +15,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <limits>
 
 #include "../../include/lb.h"
 
@@ -1195,6 +1197,16 @@ void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsign
 
 }  // namespace
 
+// A ROCTX range around each entry point (named after it): a profiler run
+// with marker tracing shows the host-side span of every library call.
+struct CallRange {
+    explicit CallRange(const char *name) { roctxRangePushA(name); }
+    ~CallRange() { roctxRangePop(); }
+    CallRange(const CallRange &) = delete;
+    CallRange &operator=(const CallRange &) = delete;
+};
+#define LB_RANGE() CallRange lb_call_range_(__func__)
+
 extern "C" {
 
 int lb_params_two_rate(double gamma_e, double magic, lb_params *params)
@@ -1213,6 +1225,7 @@ int lb_params_two_rate(double gamma_e, double magic, lb_params *params)
 
 int lb_create(const lb_params *params, void *stream, lb_ctx **out)
 {
+    LB_RANGE();
     std::string msg;
     if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1256,6 +1269,7 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
 
 int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, void *stream, lb_ctx **out)
 {
+    LB_RANGE();
     std::string msg;
     if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1357,6 +1371,7 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
 
 int lb_destroy(lb_ctx *c)
 {
+    LB_RANGE();
     if (!c) return LB_OK;
     use_device(c);
     (void)hipStreamSynchronize(c->stream);
@@ -1389,6 +1404,7 @@ int lb_destroy(lb_ctx *c)
 
 int lb_init_equilibrium(lb_ctx *c, const double *rho, const double *u)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     LB_TRY(use_device(c));
     Join j(c);
@@ -1417,6 +1433,7 @@ int lb_init_equilibrium(lb_ctx *c, const double *rho, const double *u)
 
 int lb_set_populations(lb_ctx *c, const void *src, int32_t dtype, int32_t shifted)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (!src) return fail(c, LB_EINVAL, "src is NULL");
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
@@ -1451,6 +1468,7 @@ int lb_set_populations(lb_ctx *c, const void *src, int32_t dtype, int32_t shifte
 
 int lb_get_populations(lb_ctx *c, void *dst, int32_t dtype, int32_t shifted)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (!dst) return fail(c, LB_EINVAL, "dst is NULL");
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
@@ -1483,6 +1501,7 @@ int lb_get_populations(lb_ctx *c, void *dst, int32_t dtype, int32_t shifted)
 
 int lb_step(lb_ctx *c, int32_t nsteps)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return LB_OK;
@@ -1521,6 +1540,7 @@ int lb_step(lb_ctx *c, int32_t nsteps)
 
 int lb_step_noalloc(const lb_params *params, const void *src, void *dst, uint64_t step, double *totals, void *stream)
 {
+    LB_RANGE();
     std::string msg;
     const int v = validate(params, msg);
     if (v != LB_OK) return fail(nullptr, v, msg);
@@ -1561,6 +1581,7 @@ int lb_step_noalloc(const lb_params *params, const void *src, void *dst, uint64_
 
 int lb_couple(lb_ctx *c, const lb_beads *b)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     LB_TRY(couple_check(c, b));
     if (b->n == 0) return LB_OK;
@@ -1582,6 +1603,7 @@ int lb_couple(lb_ctx *c, const lb_beads *b)
 
 int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
     LB_TRY(couple_check(c, b));
@@ -1686,6 +1708,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
 
 int lb_moments(lb_ctx *c, double *rho, double *u)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (!rho && !u) return LB_OK;
     LB_TRY(use_device(c));
@@ -1725,8 +1748,42 @@ static int totals_from_partials(lb_ctx *c, const double *partials, int rows, dou
     return LB_OK;
 }
 
+int lb_negative_count(lb_ctx *c, uint64_t *sites, double *min_pop)
+{
+    LB_RANGE();
+    if (!c) return LB_EINVAL;
+    if (!sites && !min_pop) return LB_OK;
+    LB_TRY(use_device(c));
+    Join j(c);
+    const int nb = 1024;
+    const int nbox = c->batch ? c->nbox : 1;
+    LB_TRY(ensure_scratch(c, (size_t)nbox * nb * 2 * sizeof(double)));
+    for (int k = 0; k < nbox; ++k) {
+        const char *buf = static_cast<const char *>(c->bufA) + (c->batch ? c->boxes_h[k].off * c->elem : 0);
+        const Geom &g = c->batch ? c->boxes_h[k].geo : c->geo;
+        by_storage(c->p.storage, [&](auto st) {
+            hipLaunchKernelGGL((k_negative_scan<decltype(st)::value>), dim3(nb), dim3(256), 0, c->stream, buf, g,
+                               c->p.rho0, c->scratch + (size_t)k * nb * 2);
+        });
+    }
+    LB_LAUNCH_CHECK(c, "negative scan");
+    std::vector<double> h((size_t)nbox * nb * 2);
+    LB_TRY(check(c, hipMemcpyAsync(h.data(), c->scratch, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                 "negative scan copy"));
+    LB_TRY(check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    double cnt = 0.0, mn = std::numeric_limits<double>::infinity();
+    for (size_t r = 0; r < h.size() / 2; ++r) {
+        cnt += h[2 * r];
+        mn = std::min(mn, h[2 * r + 1]);
+    }
+    if (sites) *sites = (uint64_t)cnt;
+    if (min_pop) *min_pop = mn;
+    return LB_OK;
+}
+
 int lb_totals_exact(lb_ctx *c, double out[4])
 {
+    LB_RANGE();
     if (!c || !out) return LB_EINVAL;
     LB_TRY(use_device(c));
     Join j(c);
@@ -1758,6 +1815,7 @@ int lb_totals_exact(lb_ctx *c, double out[4])
 
 int lb_totals(lb_ctx *c, double out[4])
 {
+    LB_RANGE();
     if (!c || !out) return LB_EINVAL;
     if (c->batch || !c->totals_valid) return lb_totals_exact(c, out);
     LB_TRY(use_device(c));
@@ -1766,6 +1824,7 @@ int lb_totals(lb_ctx *c, double out[4])
 
 int lb_mode_stats(lb_ctx *c, double var[19])
 {
+    LB_RANGE();
     if (!c || !var) return LB_EINVAL;
     LB_TRY(use_device(c));
     Join j(c);
@@ -1804,6 +1863,7 @@ int lb_mode_stats(lb_ctx *c, double var[19])
 
 int lb_noise_sample(lb_ctx *c, uint32_t site0, uint32_t count, uint32_t step, float *out)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (c->batch) return fail(c, LB_EUNSUPPORTED, "noise sampling is per single box");
     if (!out) return fail(c, LB_EINVAL, "out is NULL");
@@ -1818,6 +1878,7 @@ int lb_noise_sample(lb_ctx *c, uint32_t site0, uint32_t count, uint32_t step, fl
 
 int lb_sync(lb_ctx *c)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     LB_TRY(use_device(c));
     return read_flags(c);
@@ -1825,6 +1886,7 @@ int lb_sync(lb_ctx *c)
 
 int lb_tape_reserve(lb_ctx *c, int32_t nsteps, const lb_beads *b)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
     if (!c->taping) return fail(c, LB_ESTATE, "no tape is recording");
@@ -1841,6 +1903,7 @@ int lb_tape_reserve(lb_ctx *c, int32_t nsteps, const lb_beads *b)
 
 int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (c->batch) return fail(c, LB_EUNSUPPORTED, "differentiation is per single box");
     if (checkpoint_every < 1) return fail(c, LB_EINVAL, "checkpoint_every must be >= 1");
@@ -2246,17 +2309,20 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
 
 int lb_backward(lb_ctx *c, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3])
 {
+    LB_RANGE();
     return backward_impl(c, dL_dn_T, dtype, nullptr, nullptr, dL_dn_0, dL_dg, nullptr, nullptr);
 }
 
 int lb_backward_coupled(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const double *dL_dR_T, const double *dL_dP_T,
                         void *dL_dn_0, double dL_dg[3], double *dL_dR_0, double *dL_dP_0)
 {
+    LB_RANGE();
     return backward_impl(c, dL_dn_T, dtype, dL_dR_T, dL_dP_T, dL_dn_0, dL_dg, dL_dR_0, dL_dP_0);
 }
 
 int lb_vacf(lb_ctx *c, double *out, int64_t *nsamples)
 {
+    LB_RANGE();
     if (!c || !out) return LB_EINVAL;
     if (!c->batch || c->p.vacf_lags <= 0) return fail(c, LB_EINVAL, "context has no VACF (batch with vacf_lags > 0)");
     LB_TRY(use_device(c));
@@ -2282,6 +2348,7 @@ int lb_vacf(lb_ctx *c, double *out, int64_t *nsamples)
 
 int lb_launch_config(lb_ctx *c, int32_t force, int32_t out[4])
 {
+    LB_RANGE();
     if (!c || !out) return LB_EINVAL;
     if (c->batch) {
         out[0] = c->block;
@@ -2302,6 +2369,7 @@ uint64_t lb_step_count(const lb_ctx *c) { return c ? c->step : 0; }
 
 int lb_set_step_count(lb_ctx *c, uint64_t step)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (step > 0xffffffffull) return fail(c, LB_EINVAL, "step counter must be < 2^32");
     if (c->pending_force) return fail(c, LB_ESTATE, "lb_set_step_count between lb_couple and lb_step");
@@ -2358,6 +2426,7 @@ static size_t ctx_state_bytes(const lb_ctx *c) { return (size_t)state_planes(c->
 
 int lb_save(lb_ctx *c, const char *path)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (!path) return fail(c, LB_EINVAL, "path is NULL");
     if (c->pending_force) return fail(c, LB_ESTATE, "lb_save between lb_couple and lb_step");
@@ -2392,6 +2461,7 @@ int lb_save(lb_ctx *c, const char *path)
 
 int lb_load(lb_ctx *c, const char *path)
 {
+    LB_RANGE();
     if (!c) return LB_EINVAL;
     if (!path) return fail(c, LB_EINVAL, "path is NULL");
     if (c->pending_force) return fail(c, LB_ESTATE, "lb_load between lb_couple and lb_step");

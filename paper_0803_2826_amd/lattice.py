@@ -282,6 +282,14 @@ class Lattice:
         self._check(self.L.lb_noise_sample(self.ctx, int(site0), int(count), int(step), out.data_ptr()))
         return out
 
+    def negative_count(self):
+        """(sites with a negative population, smallest population) of the
+        current state (lb_negative_count)."""
+        n = ctypes.c_uint64(0)
+        m = ctypes.c_double(0.0)
+        self._check(self.L.lb_negative_count(self.ctx, ctypes.byref(n), ctypes.byref(m)))
+        return int(n.value), float(m.value)
+
     def sync(self) -> None:
         self._check(self.L.lb_sync(self.ctx))
 

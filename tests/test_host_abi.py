@@ -4,6 +4,7 @@ stability bound |gamma| of Sec. "D3Q19 model II", kT >= 0, sizes), every
 entry point rejects a NULL context, and on a machine without a GPU a valid
 request fails loudly with LB_EDEVICE instead of falling back to anything."""
 import ctypes
+import os
 
 import pytest
 
@@ -101,8 +102,24 @@ def test_null_context_is_rejected_everywhere(L):
     assert L.lb_launch_config(None, 0, cfg) == LB_EINVAL
     assert L.lb_save(None, b"/nonexistent") == LB_EINVAL
     assert L.lb_load(None, b"/nonexistent") == LB_EINVAL
+    assert L.lb_coupled_steps(None, None, 2) == LB_EINVAL
+    assert L.lb_tape_reserve(None, 2, None) == LB_EINVAL
+    assert L.lb_negative_count(None, None, None) == LB_EINVAL
     assert L.lb_step_count(None) == 0
     assert L.lb_destroy(None) == LB_OK
+
+
+def test_library_carries_roctx_ranges():
+    """The entry points open ROCTX ranges: the library links the ROCTX
+    library and imports its push and pop calls (read from the dynamic
+    section and symbol table of the library built here)."""
+    import subprocess
+    from paper_0803_2826_amd import _lib
+    path = os.environ.get("LBMI_LIBRARY") or _lib.LIB_PATH
+    needed = subprocess.run(["readelf", "-d", path], capture_output=True, text=True, check=True).stdout
+    assert "librocprofiler-sdk-roctx.so" in needed
+    undef = subprocess.run(["nm", "-D", "--undefined-only", path], capture_output=True, text=True, check=True).stdout
+    assert "roctxRangePushA" in undef and "roctxRangePop" in undef
 
 
 def test_valid_request_without_gpu_fails_loudly(L):
