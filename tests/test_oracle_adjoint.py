@@ -368,3 +368,25 @@ def test_coupled_backward_wide_stencils_match_finite_differences(orc, W):
         setattr(bm_, name, getattr(beads, name) - eps * vb)
         fd = (loss(n0, p, bp_) - loss(n0, p, bm_)) / (2 * eps)
         assert (bar * vb).sum() == pytest.approx(fd, rel=1e-6), name
+
+
+def test_c5_references_agree():
+    """The two stored references of the differentiation workload pin each
+    other: the directional derivatives of the oracle's FP64 adjoint of the
+    500 coupled steps (c5_adjoint.json: dL/dx . v for each seeded direction,
+    summed over n(0), g, R(0), P(0)) equal the central differences of the
+    oracle's forward along the same directions (c5_directional.json,
+    eps = 3e-5) to 1e-6 relative (measured 3e-7 and 6e-7)."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(here, "c5_adjoint.json")) as f:
+        adj = json.load(f)
+    with open(os.path.join(here, "c5_directional.json")) as f:
+        fd = json.load(f)
+    assert adj["workload"] == fd["workload"]
+    by_seed = {d["seed"]: d["d_v_L"] for d in fd["directions"]}
+    assert set(by_seed) == {d["seed"] for d in adj["dots"]}
+    for d in adj["dots"]:
+        dot = d["dn0_dot_vn"] + d["dg_dot_vg"] + d["dR0_dot_vR"] + d["dP0_dot_vP"]
+        assert abs(dot - by_seed[d["seed"]]) <= 1e-6 * abs(by_seed[d["seed"]]), (d["seed"], dot, by_seed[d["seed"]])
