@@ -27,6 +27,7 @@
 // so a fused run gives the same bits as the separate launches.
 #pragma once
 
+#include "bead_adjoint.h"
 #include "couple.h"
 
 namespace lbmi {
@@ -265,6 +266,25 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) 
         return;
     }
     stream_collide_site<ST, THERMAL, TOTALS, true, false, FULL, true>(a);
+}
+
+// Recompute sweep of the reverse pass over taped coupled steps: the fluid
+// step with the bead force of its own field (the sites of grid blocks
+// [0, site_blocks)) and, in the grid's last blocks, the spread force of the
+// next taped coupled step put back from its recorded contributions into the
+// other field (k_respread's work; the fields alternate by step parity, so
+// the two never touch the same field in one launch).  site_blocks is the
+// step's own grid (no XCD remapping: the tile of block b is b).
+template <int ST, bool THERMAL, bool WALLS, bool FULL>
+__global__ void __launch_bounds__(1024) k_recompute_step(StepArgs a, uint32_t site_blocks, const long long *contrib,
+                                                         int entries, long long *force_next, uint32_t *fmask_next)
+{
+    if (blockIdx.x >= site_blocks) {
+        const int e = (int)((blockIdx.x - site_blocks) * blockDim.x + threadIdx.x);
+        if (e < entries) respread_entry(contrib, e, a.geo.N, force_next, fmask_next);
+        return;
+    }
+    stream_collide_site<ST, THERMAL, false, true, WALLS, FULL>(a);
 }
 
 }  // namespace lbmi

@@ -2105,31 +2105,64 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     c->block = 256;
     c->nblocks = (int)step_blocks(c, 256);
     const int nseg = (int)((T + K - 1) / K);
+    // the state at step k of segment sg: the segment's checkpoint itself for
+    // k = 0 (read in place, never written), then the segment buffer's slots
+    auto state_at = [&](int sg, int k) -> char * {
+        return k == 0 ? static_cast<char *>(c->checkpoints[sg]) : static_cast<char *>(c->seg) + (size_t)k * sb;
+    };
     int rc = LB_OK;
     for (int sg = nseg - 1; sg >= 0 && rc == LB_OK; --sg) {
         const uint64_t t0 = (uint64_t)sg * K;
         const int len = (int)std::min<uint64_t>((uint64_t)K, T - t0);
         char *seg = static_cast<char *>(c->seg);
-        rc = check(c, hipMemcpyAsync(seg, c->checkpoints[sg], sb, hipMemcpyDeviceToDevice, c->stream),
-                   "checkpoint restore");
-        if (rc != LB_OK) break;
         // the last segment's step buffers 1 .. len-1 are still those the
         // forward wrote, unless an earlier sweep recomputed over them
         const bool kept = c->seg_fwd && sg == nseg - 1;
         if (!kept) c->seg_fwd = false;
-        // recompute steps 0 .. len-2 of the segment (first force field)
+        // recompute steps 0 .. len-2 of the segment; the force fields
+        // alternate by step parity, and a coupled step's launch puts the
+        // next recomputed coupled step's force back in its last blocks
+        if (!kept && len >= 2 && coupled_at(t0)) respread(t0, fpar[t0 & 1u], mpar[t0 & 1u]);
         for (int k = 0; !kept && k + 1 < len; ++k) {
             const uint64_t t = t0 + k;
             const uint32_t step = (uint32_t)(c->tape_step0 + t);
-            StepArgs a = plain_step_args(c, seg + (size_t)k * sb, seg + (size_t)(k + 1) * sb, step);
+            StepArgs a = plain_step_args(c, state_at(sg, k), seg + (size_t)(k + 1) * sb, step);
             const bool frc = coupled_at(t);
+            const bool next = k + 2 < len && coupled_at(t + 1);
             if (frc) {
-                respread(t, c->force, c->fmask);
-                a.fmask = c->fmask;
-                a.force = c->force;
+                a.fmask = mpar[t & 1u];
+                a.force = fpar[t & 1u];
                 a.consume = 1u;
+                a.xcd_remap = 0u;  // the side blocks follow the step's own grid
+                const TapeSlot tn = next ? tape_slot_at(c, c->tape_slot[t + 1]) : TapeSlot{};
+                const int entries = next ? tn.entries : 0;
+                const unsigned grid = (unsigned)c->nblocks + (entries > 0 ? grid_for((size_t)entries, 256) : 0u);
+                by_step_storage(c->p, [&](auto st) {
+                    constexpr int ST = decltype(st)::value;
+                    auto go = [&](auto th, auto walls, auto full) {
+                        constexpr bool TH = decltype(th)::value, WL = decltype(walls)::value,
+                                       FU = decltype(full)::value;
+                        hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU>), dim3(grid), dim3(256), 0, c->stream, a,
+                                           (uint32_t)c->nblocks, next ? tn.contrib : nullptr, entries,
+                                           fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
+                    };
+                    using T_ = std::true_type;
+                    using F_ = std::false_type;
+                    const bool full = c->thermal && c->full_relax;
+                    if (c->geo.walls) {
+                        if (!c->thermal) go(F_{}, T_{}, F_{});
+                        else if (full) go(T_{}, T_{}, T_{});
+                        else go(T_{}, T_{}, F_{});
+                    } else {
+                        if (!c->thermal) go(F_{}, F_{}, F_{});
+                        else if (full) go(T_{}, F_{}, T_{});
+                        else go(T_{}, F_{}, F_{});
+                    }
+                });
+            } else {
+                if (next) respread(t + 1, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
+                by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
             }
-            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, frc); });
         }
         if ((rc = hipGetLastError() == hipSuccess ? LB_OK : fail(c, LB_EDEVICE, "backward recompute")) != LB_OK) break;
         // adjoint steps len-1 .. 0
@@ -2139,7 +2172,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             const int q = (int)(t & 1u);
             const uint32_t step = (uint32_t)(c->tape_step0 + t);
             const int slot = c->tape_slot[t];
-            const void *pop = seg + (size_t)k * sb;
+            const void *pop = state_at(sg, k);
             AdjArgs aa;
             aa.state = pop;
             aa.lam_in = c->lamA;
