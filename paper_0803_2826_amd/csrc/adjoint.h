@@ -47,6 +47,10 @@ struct AdjArgs {
     FastDiv div_tiles;
     uint32_t main_blocks;
     AdjSide side;
+    // the state's moments (rho - rho0, j) per site, [z][4][y][x], written by
+    // the recompute step that read this state (stream_collide_site MOM), or
+    // NULL: then they are formed from the state itself (19 pulled values)
+    const float *moments;
 };
 
 
@@ -75,26 +79,41 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
         const size_t plane = (size_t)nxny * sizeof(T);
         const uint32_t P = a.geo.planes;  // state planes per layer (lambda keeps 19)
         const char *st = static_cast<const char *>(a.state);
-        // forward hydrodynamic fields of n(r, t)
-        float d[Q];
+        // forward hydrodynamic fields of n(r, t): the only part of the state
+        // the collision's Jacobian depends on
+        float m0, jx, jy, jz;
+        if (a.moments) {
+            const float *mp = a.moments + (size_t)(4u * z) * nxny;
+            m0 = ld_plane(mp, r);
+            jx = ld_plane(mp + nxny, r);
+            jy = ld_plane(mp + 2 * (size_t)nxny, r);
+            jz = ld_plane(mp + 3 * (size_t)nxny, r);
+        } else {
+            float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if (pull_crosses<WALLS>(a.geo, z, i))  // pull source beyond a wall: opp(i) of this site
-                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(P * z + (uint32_t)opp(i)) * plane), r),
-                             0.f);
-            else
-                d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(P * pull_z(z, i, a.geo) + (uint32_t)i) *
-                                                                           plane),
-                                      pull_src(r, oxy, i)),
-                             0.f);
-        }
-        float m0 = d[0], jx = 0.f, jy = 0.f, jz = 0.f;
+            for (int i = 0; i < Q; ++i) {
+                if (pull_crosses<WALLS>(a.geo, z, i))  // pull source beyond a wall: opp(i) of this site
+                    d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(P * z + (uint32_t)opp(i)) * plane),
+                                          r),
+                                 0.f);
+                else
+                    d[i] = S::ld(ld_plane(reinterpret_cast<const T *>(st + (size_t)(P * pull_z(z, i, a.geo) +
+                                                                                    (uint32_t)i) *
+                                                                               plane),
+                                          pull_src(r, oxy, i)),
+                                 0.f);
+            }
+            m0 = d[0];
+            jx = 0.f;
+            jy = 0.f;
+            jz = 0.f;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            m0 += d[i];
-            jx += (float)kCX[i] * d[i];
-            jy += (float)kCY[i] * d[i];
-            jz += (float)kCZ[i] * d[i];
+            for (int i = 1; i < Q; ++i) {
+                m0 += d[i];
+                jx += (float)kCX[i] * d[i];
+                jy += (float)kCY[i] * d[i];
+                jz += (float)kCZ[i] * d[i];
+            }
         }
         float F[3] = {a.cc.g[0], a.cc.g[1], a.cc.g[2]};
         bool flagged = false;

@@ -268,14 +268,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) 
     stream_collide_site<ST, THERMAL, TOTALS, true, false, FULL, true>(a);
 }
 
-// Recompute sweep of the reverse pass over taped coupled steps: the fluid
-// step with the bead force of its own field (the sites of grid blocks
-// [0, site_blocks)) and, in the grid's last blocks, the spread force of the
-// next taped coupled step put back from its recorded contributions into the
-// other field (k_respread's work; the fields alternate by step parity, so
-// the two never touch the same field in one launch).  site_blocks is the
-// step's own grid (no XCD remapping: the tile of block b is b).
-template <int ST, bool THERMAL, bool WALLS, bool FULL>
+// Recompute sweep of the reverse pass over taped steps: the fluid step (the
+// sites of grid blocks [0, site_blocks)), with FORCE the bead force of its
+// own field, with MOM
+// writing the input state's moments for the adjoint step, and, in the grid's last
+// blocks, the spread force of the next taped coupled step put back from its
+// recorded contributions into the other field (k_respread's work; the
+// fields alternate by step parity, so the two never touch the same field in
+// one launch).  site_blocks is the step's own grid (no XCD remapping: the
+// tile of block b is b).
+template <int ST, bool THERMAL, bool WALLS, bool FULL, bool FORCE, bool MOM>
 __global__ void __launch_bounds__(1024) k_recompute_step(StepArgs a, uint32_t site_blocks, const long long *contrib,
                                                          int entries, long long *force_next, uint32_t *fmask_next)
 {
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(1024) k_recompute_step(StepArgs a, uint32_t si
         if (e < entries) respread_entry(contrib, e, a.geo.N, force_next, fmask_next);
         return;
     }
-    stream_collide_site<ST, THERMAL, false, true, WALLS, FULL>(a);
+    stream_collide_site<ST, THERMAL, false, FORCE, WALLS, FULL, false, MOM>(a);
 }
 
 }  // namespace lbmi

@@ -317,6 +317,10 @@ struct StepArgs {
     uint32_t *arrive;
     uint32_t arrive_target;
     uint32_t block0;
+    // MOM (recompute sweep of the reverse pass): the input state's moments
+    // (rho - rho0, j) per site, 4 planes per layer [z][4][y][x], FP32 sums
+    // in the order the adjoint step forms them from the same stored values
+    float *moments;
 };
 
 // Tile of block b of G site blocks: with remap, consecutive tiles go to one
@@ -587,7 +591,7 @@ __device__ __forceinline__ void store_site(void *const *dstp, uint32_t plane_byt
 // blocks, and the bead force of a flagged site is taken once the particle
 // blocks have all been counted (wait_arrivals), with device-scope atomic
 // exchanges that read it and leave the field zero.
-template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL, bool WAIT = false>
+template <int ST, bool THERMAL, bool TOTALS, bool FORCE, bool WALLS, bool FULL, bool WAIT = false, bool MOM = false>
 __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
 {
     using S = Storage<ST>;
@@ -630,6 +634,22 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
                                               r),
                                      0.f);
             }
+        }
+        if constexpr (MOM) {
+            // the input state's (rho - rho0, j) for the reverse sweep's adjoint step
+            float m0 = d[0], jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                m0 += d[i];
+                jx += (float)kCX[i] * d[i];
+                jy += (float)kCY[i] * d[i];
+                jz += (float)kCZ[i] * d[i];
+            }
+            float *mp = a.moments + (size_t)(4u * z) * nxny;
+            st_plane_nt<float>(mp, (uint32_t)(nxny * 4u), r, m0);
+            st_plane_nt<float>(mp + nxny, (uint32_t)(nxny * 4u), r, jx);
+            st_plane_nt<float>(mp + 2 * (size_t)nxny, (uint32_t)(nxny * 4u), r, jy);
+            st_plane_nt<float>(mp + 3 * (size_t)nxny, (uint32_t)(nxny * 4u), r, jz);
         }
         // FP32 storage: the input mass in FP64 with the rest residual (exact);
         // 16-bit storage: the collision's own FP32 sum below

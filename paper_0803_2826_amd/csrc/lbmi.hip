@@ -82,6 +82,8 @@ struct lb_ctx {
     uint32_t arrive_count = 0;       // its value once every enqueued launch has finished
     int32_t *partner = nullptr;      // [n][deg] bond partners of each bead
     size_t partner_cap = 0;
+    float *moments = nullptr;        // reverse sweep: [slots][z][4][y][x] moments of the recomputed states
+    size_t moments_slots = 0;
     bool tuned = false;              // launch configuration chosen (autotune done or fixed)
     uint32_t xcd_remap = LBMI_XCD_REMAP;  // step kernel: consecutive tiles on one XCD (if the grid allows)
     // single box: launch configuration of the step kernel without / with a
@@ -769,6 +771,7 @@ StepArgs plain_step_args(lb_ctx *c, const void *src, void *dst, uint32_t step)
     a.arrive = nullptr;
     a.arrive_target = 0u;
     a.block0 = 0u;
+    a.moments = nullptr;
     return a;
 }
 
@@ -1390,7 +1393,7 @@ int lb_destroy(lb_ctx *c)
                    c->bead_work, c->fbar, c->force2, c->fmask2};
     for (void *q : adj)
         if (q) (void)hipFree(q);
-    void *fused[] = {c->bead_pp, c->fmask_f, c->arrive, c->partner};
+    void *fused[] = {c->bead_pp, c->fmask_f, c->arrive, c->partner, c->moments};
     for (void *q : fused)
         if (q) (void)hipFree(q);
     if (c->batch) {
@@ -1989,6 +1992,26 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         }
         c->seg_bytes = slots * sb;
     }
+    // the moments (rho - rho0, j) of the recomputed states, 16 B per site
+    // and state (the adjoint step reads them instead of the 19 pulled
+    // values): taken when a segment is recomputed at all and the buffer
+    // leaves half of the free memory; otherwise the adjoint reads the states
+    const size_t mom_stride = 4 * N;
+    const bool recompute = T > (uint64_t)K || !c->seg_fwd;
+    if (recompute && slots >= 2 && c->moments_slots < slots - 1) {
+        (void)hipFree(c->moments);
+        c->moments = nullptr;
+        c->moments_slots = 0;
+        const size_t need = (size_t)(slots - 1) * mom_stride * sizeof(float);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need <= free_b / 2) {
+            if (hipMalloc(&c->moments, need) == hipSuccess) c->moments_slots = (size_t)(slots - 1);
+            else {
+                c->moments = nullptr;
+                (void)hipGetLastError();  // the states serve instead
+            }
+        }
+    }
     // the adjoint step's blocks, dealt out layer by layer (256 threads)
     const unsigned nb = step_blocks(c, 256);
     const uint32_t adj_tiles = (c->geo.nxny + 255u) / 256u;
@@ -2121,19 +2144,30 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         if (!kept) c->seg_fwd = false;
         // recompute steps 0 .. len-2 of the segment; the force fields
         // alternate by step parity, and a coupled step's launch puts the
-        // next recomputed coupled step's force back in its last blocks
+        // next recomputed coupled step's force back in its last blocks.  Each
+        // recompute step also writes its input state's moments, which the
+        // adjoint step of that state reads instead of the state itself.
+        const bool mom = !kept && len >= 2 && c->moments && (size_t)(len - 1) <= c->moments_slots;
         if (!kept && len >= 2 && coupled_at(t0)) respread(t0, fpar[t0 & 1u], mpar[t0 & 1u]);
         for (int k = 0; !kept && k + 1 < len; ++k) {
             const uint64_t t = t0 + k;
             const uint32_t step = (uint32_t)(c->tape_step0 + t);
             StepArgs a = plain_step_args(c, state_at(sg, k), seg + (size_t)(k + 1) * sb, step);
-            const bool frc = coupled_at(t);
             const bool next = k + 2 < len && coupled_at(t + 1);
-            if (frc) {
-                a.fmask = mpar[t & 1u];
-                a.force = fpar[t & 1u];
-                a.consume = 1u;
+            const bool frc = coupled_at(t);
+            if (mom || frc) {
+                if (frc) {
+                    a.fmask = mpar[t & 1u];
+                    a.force = fpar[t & 1u];
+                    a.consume = 1u;
+                    // the force variant reads the bitmap at every site
+                    if (!a.fmask || !a.force) {
+                        rc = fail(c, LB_EDEVICE, "backward recompute: a coupled step without its force field");
+                        break;
+                    }
+                }
                 a.xcd_remap = 0u;  // the side blocks follow the step's own grid
+                a.moments = mom ? c->moments + (size_t)k * mom_stride : nullptr;
                 const TapeSlot tn = next ? tape_slot_at(c, c->tape_slot[t + 1]) : TapeSlot{};
                 const int entries = next ? tn.entries : 0;
                 const unsigned grid = (unsigned)c->nblocks + (entries > 0 ? grid_for((size_t)entries, 256) : 0u);
@@ -2142,9 +2176,19 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                     auto go = [&](auto th, auto walls, auto full) {
                         constexpr bool TH = decltype(th)::value, WL = decltype(walls)::value,
                                        FU = decltype(full)::value;
-                        hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU>), dim3(grid), dim3(256), 0, c->stream, a,
-                                           (uint32_t)c->nblocks, next ? tn.contrib : nullptr, entries,
-                                           fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
+                        // (force, moments): (yes, yes), (yes, no), (no, yes)
+                        if (frc && mom)
+                            hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, true, true>), dim3(grid), dim3(256),
+                                               0, c->stream, a, (uint32_t)c->nblocks, next ? tn.contrib : nullptr,
+                                               entries, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
+                        else if (frc)
+                            hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, true, false>), dim3(grid), dim3(256),
+                                               0, c->stream, a, (uint32_t)c->nblocks, next ? tn.contrib : nullptr,
+                                               entries, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
+                        else
+                            hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, false, true>), dim3(grid), dim3(256),
+                                               0, c->stream, a, (uint32_t)c->nblocks, next ? tn.contrib : nullptr,
+                                               entries, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
                     };
                     using T_ = std::true_type;
                     using F_ = std::false_type;
@@ -2164,6 +2208,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
             }
         }
+        if (rc != LB_OK) break;
         if ((rc = hipGetLastError() == hipSuccess ? LB_OK : fail(c, LB_EDEVICE, "backward recompute")) != LB_OK) break;
         // adjoint steps len-1 .. 0
         if (coupled_at(t0 + len - 1)) respread(t0 + len - 1, fpar[(t0 + len - 1) & 1u], mpar[(t0 + len - 1) & 1u]);
@@ -2174,6 +2219,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             const int slot = c->tape_slot[t];
             const void *pop = state_at(sg, k);
             AdjArgs aa;
+            aa.moments = (mom && k + 1 < len) ? c->moments + (size_t)k * mom_stride : nullptr;
             aa.state = pop;
             aa.lam_in = c->lamA;
             aa.lam_out = c->lamB;
