@@ -1661,9 +1661,11 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         a.force = c->force;
         a.consume = 1u;
         const uint32_t pblocks = (uint32_t)((grid_for((size_t)LANES * n, (unsigned)c->block) + 7) / 8 * 8);
-        c->arrive_count += pblocks;
+        // the counter's value once this launch's particle blocks are counted
+        // (taken over only once the launch is enqueued)
+        const uint32_t target = c->arrive_count + pblocks;
         a.arrive = c->arrive;
-        a.arrive_target = c->arrive_count;
+        a.arrive_target = target;
         a.block0 = pblocks;
         ParticleArgs p;
         p.pop = c->bufA;
@@ -1701,6 +1703,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         const unsigned grid = pblocks + (unsigned)c->nblocks;
         by_step_storage(c->p, [&](auto st) { launch_fused_st<decltype(st)::value>(c, a, p, grid, tot); });
         LB_LAUNCH_CHECK(c, "coupled step");
+        c->arrive_count = target;
         c->pending_slot = -1;
         LB_TRY(step_done(c, dst, tot, ckpt));
         pos_in = pos;
