@@ -11,7 +11,7 @@
 //     for a bead with at most two bonds the sum has the same bits as the
 //     separate launches' (0 + f1 + f2 in either order);
 //   - the grid's first blocks are particle blocks: one lane per bead and
-//     stencil node as in k_bead_update, reading the bead state of the step
+//     stencil node as in k_bead_update (phi_2, phi_3 or phi_4), reading the bead state of the step
 //     from (pos_in, mom_in) and writing the next one to (pos, mom), distinct
 //     arrays, so that a bead can read its partners' start state while they
 //     are being updated; each block is counted in *arrive once its spread

@@ -1176,25 +1176,25 @@ int ensure_fused_buffers(lb_ctx *c, int n)
     return LB_OK;
 }
 
-template <int ST, bool TH, bool TOT>
+template <int ST, bool TH, bool TOT, int W>
 void launch_fused_t(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid)
 {
     const size_t lds = TOT ? (size_t)kTotalsLds * (size_t)c->block : 0;  // block_sum_totals
     if (TH && c->full_relax)
-        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, 2>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, W>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
     else
-        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, 2>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, W>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
 }
 
-template <int ST>
+template <int ST, int W>
 void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid, bool tot)
 {
     if (c->thermal) {
-        if (tot) launch_fused_t<ST, true, true>(c, a, p, grid);
-        else launch_fused_t<ST, true, false>(c, a, p, grid);
+        if (tot) launch_fused_t<ST, true, true, W>(c, a, p, grid);
+        else launch_fused_t<ST, true, false, W>(c, a, p, grid);
     } else {
-        if (tot) launch_fused_t<ST, false, true>(c, a, p, grid);
-        else launch_fused_t<ST, false, false>(c, a, p, grid);
+        if (tot) launch_fused_t<ST, false, true, W>(c, a, p, grid);
+        else launch_fused_t<ST, false, false, W>(c, a, p, grid);
     }
 }
 
@@ -1613,10 +1613,10 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
     if (nsteps == 0) return LB_OK;
     if (c->step + (uint64_t)nsteps > 0xffffffffull) return fail(c, LB_EINVAL, "step counter would exceed 2^32");
     LB_TRY(use_device(c));
-    // one launch per step for the trilinear stencil without pair forces and
-    // walls; everything else (and a single step: its bead state would be
-    // read and written by the same launch) takes the separate launches
-    bool fused = nsteps >= 2 && b->n > 0 && !(b->wca_epsilon > 0.0) && !c->geo.walls && stencil_width(b) == 2;
+    // one launch per step without pair forces and walls; everything else
+    // (and a single step: its bead state would be read and written by the
+    // same launch) takes the separate launches
+    bool fused = nsteps >= 2 && b->n > 0 && !(b->wca_epsilon > 0.0) && !c->geo.walls;
     int deg = 0;
     if (fused) LB_TRY(build_partners(c, b, &deg, &fused));
     if (!fused) {
@@ -1627,7 +1627,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         return LB_OK;
     }
     const int n = b->n;
-    constexpr int LANES = StencilLanes<2>::value;
+    const int LANES = stencil_lanes(stencil_width(b));
     LB_TRY(ensure_bead_buffers(c, n));
     LB_TRY(ensure_fused_buffers(c, n));
     if (c->taping) {
@@ -1637,8 +1637,10 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         LB_TRY(reserve_checkpoints(c, nsteps));
     }
     uint32_t *const bm[2] = {c->fmask, c->fmask_f};
-    hipLaunchKernelGGL(k_bead_nodes<2>, dim3(grid_for((size_t)LANES * n, 256)), dim3(256), 0, c->stream, b->pos,
-                       b->mom, b->mass, n, c->geo, bm[0]);
+    by_stencil(b->stencil, [&](auto w) {
+        hipLaunchKernelGGL(k_bead_nodes<decltype(w)::value>, dim3(grid_for((size_t)LANES * n, 256)), dim3(256), 0,
+                           c->stream, b->pos, b->mom, b->mass, n, c->geo, bm[0]);
+    });
     LB_LAUNCH_CHECK(c, "bead nodes");
     const bool tot = c->p.track_totals != 0;
     const size_t n3 = 3 * (size_t)n;
@@ -1701,7 +1703,11 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         p.tape_contrib = c->taping ? slot.contrib : nullptr;
         p.arrive = c->arrive;
         const unsigned grid = pblocks + (unsigned)c->nblocks;
-        by_step_storage(c->p, [&](auto st) { launch_fused_st<decltype(st)::value>(c, a, p, grid, tot); });
+        by_step_storage(c->p, [&](auto st) {
+            by_stencil(b->stencil, [&](auto w) {
+                launch_fused_st<decltype(st)::value, decltype(w)::value>(c, a, p, grid, tot);
+            });
+        });
         LB_LAUNCH_CHECK(c, "coupled step");
         c->arrive_count = target;
         c->pending_slot = -1;

@@ -14,7 +14,8 @@ and against the FP64 oracle, through the C ABI.
   sweep over separate ones (to the rounding of the sweep's FP32 atomics).
 - The oracle: 20 fused steps against orc.coupled_step at the tolerances of
   test_gpu_beads.
-- Runs that take the separate launches (one step, WCA pairs, phi_3) match
+- The three- and four-point kernels phi_3, phi_4 fused as well.
+- Runs that take the separate launches (one step, WCA pairs, walls) match
   the step-by-step loop too; no run leaves the wait flag (bit 3) set.
 """
 import numpy as np
@@ -107,10 +108,12 @@ def test_fused_bitwise_storages(lat, storage, rounding):
     assert_same(fus, sep)
 
 
-@pytest.mark.parametrize("case", ["athermal", "fene", "three_point", "fext", "chunks", "block64"])
+@pytest.mark.parametrize("case", ["athermal", "fene", "three_point", "fext", "chunks", "block64", "phi3", "phi4"])
 def test_fused_bitwise_variants(lat, case):
     kT = 0.0 if case == "athermal" else 1e-4
     extra = {}
+    if case in ("phi3", "phi4"):
+        extra = dict(stencil=int(case[-1]))
     if case == "fene":
         extra = dict(bond="fene", k_bond=0.3, r0=2.0)
     if case == "three_point":
@@ -132,16 +135,14 @@ def test_fused_branched_within_1e12(lat):
     assert_same(fus, sep, tol=1e-12)
 
 
-@pytest.mark.parametrize("case", ["one_step", "wca", "phi3"])
+@pytest.mark.parametrize("case", ["one_step", "wca", "walls"])
 def test_separate_launch_cases_match_loop(lat, case):
     extra = {}
     if case == "wca":
         # self-avoiding chains (no overlapping pair), FENE bonds with WCA
         extra = dict(self_avoiding=True, bond="fene", k_bond=3e-3, r0=1.5, wca_epsilon=1e-4, wca_sigma=1.0)
-    if case == "phi3":
-        extra = dict(stencil=3)
     steps = 1 if case == "one_step" else 6
-    p = lat.FluidParams(nx=20, ny=20, nz=20, kT=1e-4, seed=23)
+    p = lat.FluidParams(nx=20, ny=20, nz=20, kT=1e-4, seed=23, walls=(case == "walls"))
     sep, fus = run_pair(lat, p, make_beads(lat, (20, 20, 20), 3, 8, seed=29, **extra), steps)
     assert_same(fus, sep)
 
