@@ -355,9 +355,10 @@ int lb_couple(lb_ctx *ctx, const lb_beads *beads);
 
 /* nsteps >= 0 coupled time steps with the same beads: the same result, bit
  * for bit, as nsteps times lb_couple then lb_step(ctx, 1) (taped or not),
- * the bead state in beads->pos, beads->mom advanced in place.  Without WCA
- * pairs and walls, with at most 64 bonds per bead and nsteps >= 2 (any of
- * the stencils phi_2, phi_3, phi_4), each step is ONE launch (the particle half runs in
+ * the bead state in beads->pos, beads->mom advanced in place.  Without
+ * walls, with at most 64 bonds per bead and nsteps >= 2 (any of the
+ * stencils phi_2, phi_3, phi_4; with WCA pairs phi_2, the cell lists built
+ * by the launches themselves), each step is ONE launch (the particle half runs in
  * the first blocks of the fluid step's grid, each bead sums its own bond
  * forces); otherwise the separate launches run.  Before the first step the
  * bond list is copied to the host (one synchronisation).  Errors: those of

@@ -62,6 +62,28 @@ struct ParticleArgs {
     double *tape_momn;
     long long *tape_contrib;
     uint32_t *arrive;       // count of finished particle blocks
+    // WCA pairs (the PAIRS kernels): three cell lists rotate over the steps
+    // of a run; the launch of a step reads the list of its own R' (built by
+    // the previous launch or k_bead_nodes), puts the heads of the previous
+    // step's list back to -1, and builds the next step's list from the
+    // positions it writes, so that no launch writes a list it reads
+    CellGrid cg;
+    const int32_t *head;           // this step's list
+    const int32_t *next;
+    const int32_t *cell_of;
+    int32_t *head_reset;           // the previous step's list, or NULL
+    const int32_t *cell_of_reset;
+    int32_t *head_build;           // the next step's list, or NULL
+    int32_t *next_build;
+    int32_t *cell_of_build;
+};
+
+// Lanes per bead of the fused particle blocks: the stencil's, and at least
+// kPairLanes with WCA pairs (one neighbour cell per lane, as k_wca).
+template <int W, bool PAIRS>
+struct FusedLanes {
+    static constexpr int value =
+        PAIRS && StencilLanes<W>::value < kPairLanes ? kPairLanes : StencilLanes<W>::value;
 };
 
 // R' = R + (h/2) P/m of bead j from the launch's start state (the expression
@@ -101,9 +123,11 @@ __device__ __forceinline__ void partner_force(const ParticleArgs &a, const doubl
 }
 
 // Marks the stencil nodes of R' = R + (h/2) P/m of every bead (nonzero
-// weights) in `fmask`: the bitmap of the first step of a fused run.
+// weights) in `fmask`: the bitmap of the first step of a fused run; with
+// head != NULL also links every bead at R' into that (empty) cell list.
 template <int W>
-__global__ void k_bead_nodes(const double *pos, const double *mom, const double *mass, int n, Geom g, uint32_t *fmask)
+__global__ void k_bead_nodes(const double *pos, const double *mom, const double *mass, int n, Geom g, uint32_t *fmask,
+                             CellGrid cg, int32_t *head, int32_t *next, int32_t *cell_of)
 {
     constexpr int LANES = StencilLanes<W>::value;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,23 +139,31 @@ __global__ void k_bead_nodes(const double *pos, const double *mom, const double 
     double w;
     stencil_node<W>(R, q, g, node, w, nullptr);
     if (w != 0.0) atomicOr(&fmask[node >> 5], 1u << (node & 31u));
+    if (head && q == 0) cell_link(b, R, cg, cell_of, head, next);
+}
+
+// Puts the heads of a cell list back to -1 (each bead its own cell).
+__global__ void k_cell_unlink(const int32_t *__restrict__ cell_of, int n, int32_t *head)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) head[cell_of[b]] = -1;
 }
 
 // The particle half of one coupled step, lane t = (bead, stencil node): the
 // work of k_bead_half and k_bead_update for that lane (see couple.h), with
 // the bead's bond forces summed over its partners.  Every thread of the
 // block calls it; the block is counted in *arrive when its spread is done.
-template <int ST, int W>
+template <int ST, int W, bool PAIRS>
 __device__ __forceinline__ void particle_block(const ParticleArgs &a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
-    constexpr int LANES = StencilLanes<W>::value;
+    constexpr int LANES = FusedLanes<W, PAIRS>::value;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = t / LANES, q = t % LANES;
     const bool live = b < a.n;
     const Geom &g = a.geo;
-    double ub[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0};
+    double ub[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0}, fp[3] = {0.0, 0.0, 0.0};
     uint32_t node = 0;
     double wq = 0.0;
     double m = 1.0, z = 0.0, P[3] = {0.0, 0.0, 0.0}, R[3] = {0.0, 0.0, 0.0};
@@ -142,6 +174,29 @@ __device__ __forceinline__ void particle_block(const ParticleArgs &a)
         for (int c = 0; c < 3; ++c) {
             P[c] = a.mom_in[3 * b + c];
             R[c] = start_half(a, b, c);
+        }
+        if constexpr (PAIRS) {
+            // WCA pairs (before the gather, whose values would otherwise be
+            // live across the cell walks): lane q visits neighbour cell q of
+            // the bead's cell, its members in increasing index (the terms
+            // and order of k_wca)
+            if (q < kPairLanes) {
+                const CellGrid &cg = a.cg;
+                const int nbc = lane_cell(a.cell_of[b], q, cg);
+                for_members_in_order(nbc, b, a.n, a.head, a.next, [&](int j) {
+                    const double d0 = pair_sep(R[0] - start_half(a, j, 0), cg.L[0], cg.periodic[0]);
+                    const double d1 = pair_sep(R[1] - start_half(a, j, 1), cg.L[1], cg.periodic[1]);
+                    const double d2 = pair_sep(R[2] - start_half(a, j, 2), cg.L[2], cg.periodic[2]);
+                    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    if (!(r2 < cg.rc2)) return;
+                    const double s2 = cg.sig2 / r2;
+                    const double s6 = s2 * s2 * s2;
+                    const double f = cg.eps24 * (2.0 * s6 * s6 - s6) / r2;
+                    fp[0] += f * d0;
+                    fp[1] += f * d1;
+                    fp[2] += f * d2;
+                });
+            }
         }
         stencil_node<W>(R, q, g, node, wq, nullptr);
         if (q < W * W * W) {
@@ -188,14 +243,16 @@ __device__ __forceinline__ void particle_block(const ParticleArgs &a)
     for (int c = 0; c < 3; ++c) {
         ub[c] = bead_sum<LANES>(ub[c]);
         fb[c] = bead_sum<LANES>(fb[c]);
+        if constexpr (PAIRS) fp[c] = bead_sum<LANES>(fp[c]);
     }
     double Pn[3] = {0.0, 0.0, 0.0}, Fc[3] = {0.0, 0.0, 0.0};
     long long iv[3] = {0, 0, 0};
     if (live) {
         double I[3];
         for (int c = 0; c < 3; ++c) {
-            // F^c = bonds + fext
+            // F^c = (bonds + pairs) + fext
             Fc[c] = fb[c];
+            if constexpr (PAIRS) Fc[c] += fp[c];
             if (a.fext) Fc[c] += a.fext[3 * b + c];
             Pn[c] = C1 * P[c] + C2 * (Fc[c] + z * ub[c]) + C3 * th[c];
             I[c] = -(Pn[c] - P[c] - h * Fc[c]);
@@ -224,8 +281,11 @@ __device__ __forceinline__ void particle_block(const ParticleArgs &a)
         __hip_atomic_fetch_add(a.arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!live) return;
-    if (a.tape_contrib) {
-        long long *e = a.tape_contrib + 4 * ((size_t)b * LANES + q);
+    // the tape keeps one entry per bead and stencil lane (StencilLanes<W>,
+    // the layout of k_bead_update's record), whatever the lanes per bead here
+    constexpr int SL = StencilLanes<W>::value;
+    if (a.tape_contrib && q < SL) {
+        long long *e = a.tape_contrib + 4 * ((size_t)b * SL + q);
         e[0] = wq != 0.0 ? (long long)node : -1ll;
         e[1] = iv[0];
         e[2] = iv[1];
@@ -242,8 +302,8 @@ __device__ __forceinline__ void particle_block(const ParticleArgs &a)
             if (a.tape_mom0) a.tape_mom0[3 * b + c] = P[c];
             if (a.tape_momn) a.tape_momn[3 * b + c] = Pn[c];
         }
-    // the next step's stencil nodes, from the state just written (the next
-    // launch forms R' from it with the same expression)
+    // the next step's stencil nodes (and cell list), from the state just
+    // written (the next launch forms R' from it with the same expression)
     if (a.fmask_next && q < W * W * W) {
         double Rh[3];
         for (int c = 0; c < 3; ++c) Rh[c] = Rn[c] + 0.5 * Pn[c] / m;
@@ -251,18 +311,22 @@ __device__ __forceinline__ void particle_block(const ParticleArgs &a)
         double wn;
         stencil_node<W>(Rh, q, g, nn, wn, nullptr);
         if (wn != 0.0) atomicOr(&a.fmask_next[nn >> 5], 1u << (nn & 31u));
+        if constexpr (PAIRS)
+            if (q == 0 && a.head_build) cell_link(b, Rh, a.cg, a.cell_of_build, a.head_build, a.next_build);
     }
+    if constexpr (PAIRS)
+        if (q == 0 && a.head_reset) a.head_reset[a.cell_of_reset[b]] = -1;
 }
 
 // One fused coupled step: blocks [0, a.block0) are the particle half
 // (particle_block), the rest the fluid step with the bead force
 // (stream_collide_site in WAIT mode).  blockDim a multiple of 64; a.block0 a
 // multiple of 8 so that the site blocks keep their XCD mapping.
-template <int ST, bool THERMAL, bool TOTALS, bool FULL, int W>
+template <int ST, bool THERMAL, bool TOTALS, bool FULL, int W, bool PAIRS = false>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) k_coupled_step(StepArgs a, ParticleArgs p)
 {
     if (blockIdx.x < a.block0) {
-        particle_block<ST, W>(p);
+        particle_block<ST, W, PAIRS>(p);
         return;
     }
     stream_collide_site<ST, THERMAL, TOTALS, true, false, FULL, true>(a);

@@ -82,6 +82,9 @@ struct lb_ctx {
     uint32_t arrive_count = 0;       // its value once every enqueued launch has finished
     int32_t *partner = nullptr;      // [n][deg] bond partners of each bead
     size_t partner_cap = 0;
+    int32_t *flist = nullptr;        // fused WCA: three cell lists, [3][cap] heads then [3][n] next, [3][n] cell_of
+    size_t flist_cells = 0;
+    int flist_n = 0;
     float *moments = nullptr;        // reverse sweep: [slots][z][4][y][x] moments of the recomputed states
     size_t moments_slots = 0;
     bool tuned = false;              // launch configuration chosen (autotune done or fixed)
@@ -584,13 +587,17 @@ void launch_wca(lb_ctx *c, const lb_beads *b, const double *half, const CellGrid
 
 // Adjoint of the WCA forces at the positions `half`: half_bar += J (fc_bar_i -
 // fc_bar_j).  Links the cell list; k_bead_adjoint_finish puts the heads back.
-void launch_wca_adjoint(lb_ctx *c, const lb_beads *b, const double *half, const double *fc_bar, double *half_bar)
+int launch_wca_adjoint(lb_ctx *c, const lb_beads *b, const double *half, const double *fc_bar, double *half_bar)
 {
     const CellGrid cg = cell_grid(c, b);
+    if (!c->cell_head || !c->cell_of || !c->cell_next || c->pair_cap < b->n ||
+        c->cell_cap < (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2])
+        return fail(c, LB_EDEVICE, "the pair adjoint needs the context's cell list, which no coupled step allocated");
     hipLaunchKernelGGL(k_cell_link, dim3(grid_for((size_t)b->n, 256)), dim3(256), 0, c->stream, half, b->n, cg,
                        c->cell_of, c->cell_head, c->cell_next);
     hipLaunchKernelGGL(k_wca_adjoint, dim3(grid_for((size_t)kPairLanes * b->n, 256)), dim3(256), 0, c->stream, half,
                        b->n, cg, c->cell_of, c->cell_head, c->cell_next, fc_bar, half_bar);
+    return LB_OK;
 }
 
 // Threads per block of the per-bead stencil kernels: one wave, so that a few
@@ -1176,25 +1183,47 @@ int ensure_fused_buffers(lb_ctx *c, int n)
     return LB_OK;
 }
 
-template <int ST, bool TH, bool TOT, int W>
+// The three rotating cell lists of fused steps with WCA pairs: heads all -1
+// on entry and after every call.
+int ensure_fused_lists(lb_ctx *c, int n, size_t ncell)
+{
+    if (c->flist && c->flist_cells >= ncell && c->flist_n >= n) return LB_OK;
+    (void)hipFree(c->flist);
+    c->flist = nullptr;
+    c->flist_cells = 0;
+    c->flist_n = 0;
+    const size_t words = 3 * ncell + 6 * (size_t)n;
+    if (hipMalloc(&c->flist, words * sizeof(int32_t)) != hipSuccess)
+        return fail(c, LB_ENOMEM, "fused cell lists allocation failed");
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(3 * ncell, 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<uint32_t *>(c->flist), (uint32_t)(3 * ncell), 0xffffffffu);
+    LB_LAUNCH_CHECK(c, "fused cell lists");
+    c->flist_cells = ncell;
+    c->flist_n = n;
+    return LB_OK;
+}
+
+template <int ST, bool TH, bool TOT, int W, bool PAIRS>
 void launch_fused_t(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid)
 {
     const size_t lds = TOT ? (size_t)kTotalsLds * (size_t)c->block : 0;  // block_sum_totals
     if (TH && c->full_relax)
-        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, W>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, W, PAIRS>), dim3(grid), dim3(c->block), lds, c->stream, a,
+                           p);
     else
-        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, W>), dim3(grid), dim3(c->block), lds, c->stream, a, p);
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, W, PAIRS>), dim3(grid), dim3(c->block), lds, c->stream,
+                           a, p);
 }
 
-template <int ST, int W>
+template <int ST, int W, bool PAIRS>
 void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid, bool tot)
 {
     if (c->thermal) {
-        if (tot) launch_fused_t<ST, true, true, W>(c, a, p, grid);
-        else launch_fused_t<ST, true, false, W>(c, a, p, grid);
+        if (tot) launch_fused_t<ST, true, true, W, PAIRS>(c, a, p, grid);
+        else launch_fused_t<ST, true, false, W, PAIRS>(c, a, p, grid);
     } else {
-        if (tot) launch_fused_t<ST, false, true, W>(c, a, p, grid);
-        else launch_fused_t<ST, false, false, W>(c, a, p, grid);
+        if (tot) launch_fused_t<ST, false, true, W, PAIRS>(c, a, p, grid);
+        else launch_fused_t<ST, false, false, W, PAIRS>(c, a, p, grid);
     }
 }
 
@@ -1393,7 +1422,7 @@ int lb_destroy(lb_ctx *c)
                    c->bead_work, c->fbar, c->force2, c->fmask2};
     for (void *q : adj)
         if (q) (void)hipFree(q);
-    void *fused[] = {c->bead_pp, c->fmask_f, c->arrive, c->partner, c->moments};
+    void *fused[] = {c->bead_pp, c->fmask_f, c->arrive, c->partner, c->moments, c->flist};
     for (void *q : fused)
         if (q) (void)hipFree(q);
     if (c->batch) {
@@ -1613,10 +1642,11 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
     if (nsteps == 0) return LB_OK;
     if (c->step + (uint64_t)nsteps > 0xffffffffull) return fail(c, LB_EINVAL, "step counter would exceed 2^32");
     LB_TRY(use_device(c));
-    // one launch per step without pair forces and walls; everything else
-    // (and a single step: its bead state would be read and written by the
-    // same launch) takes the separate launches
-    bool fused = nsteps >= 2 && b->n > 0 && !(b->wca_epsilon > 0.0) && !c->geo.walls;
+    // one launch per step without walls (WCA pairs with phi_2 only);
+    // everything else (and a single step: its bead state would be read and
+    // written by the same launch) takes the separate launches
+    const bool wca = b->wca_epsilon > 0.0;
+    bool fused = nsteps >= 2 && b->n > 0 && !c->geo.walls && (!wca || stencil_width(b) == 2);
     int deg = 0;
     if (fused) LB_TRY(build_partners(c, b, &deg, &fused));
     if (!fused) {
@@ -1628,8 +1658,25 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
     }
     const int n = b->n;
     const int LANES = stencil_lanes(stencil_width(b));
+    const int PLANES = wca ? std::max(LANES, kPairLanes) : LANES;  // lanes per bead of the particle blocks
     LB_TRY(ensure_bead_buffers(c, n));
     LB_TRY(ensure_fused_buffers(c, n));
+    CellGrid cg{};
+    size_t ncell = 0;
+    int32_t *lh[3] = {nullptr, nullptr, nullptr}, *ln[3] = {nullptr, nullptr, nullptr},
+            *lc[3] = {nullptr, nullptr, nullptr};
+    if (wca) {
+        cg = cell_grid(c, b);
+        ncell = (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2];
+        LB_TRY(ensure_fused_lists(c, n, ncell));
+        // the context's own cell list too: the reverse sweep's pair Jacobians use it
+        LB_TRY(ensure_pair_buffers(c, n, ncell));
+        for (int r = 0; r < 3; ++r) {
+            lh[r] = c->flist + (size_t)r * c->flist_cells;
+            ln[r] = c->flist + 3 * c->flist_cells + (size_t)r * c->flist_n;
+            lc[r] = c->flist + 3 * c->flist_cells + 3 * (size_t)c->flist_n + (size_t)r * c->flist_n;
+        }
+    }
     if (c->taping) {
         if (c->tape_nb == 0) c->tape_nb = n;
         if (n != c->tape_nb) return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
@@ -1639,7 +1686,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
     uint32_t *const bm[2] = {c->fmask, c->fmask_f};
     by_stencil(b->stencil, [&](auto w) {
         hipLaunchKernelGGL(k_bead_nodes<decltype(w)::value>, dim3(grid_for((size_t)LANES * n, 256)), dim3(256), 0,
-                           c->stream, b->pos, b->mom, b->mass, n, c->geo, bm[0]);
+                           c->stream, b->pos, b->mom, b->mass, n, c->geo, bm[0], cg, lh[0], ln[0], lc[0]);
     });
     LB_LAUNCH_CHECK(c, "bead nodes");
     const bool tot = c->p.track_totals != 0;
@@ -1662,7 +1709,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         a.fmask = bm[k & 1];
         a.force = c->force;
         a.consume = 1u;
-        const uint32_t pblocks = (uint32_t)((grid_for((size_t)LANES * n, (unsigned)c->block) + 7) / 8 * 8);
+        const uint32_t pblocks = (uint32_t)((grid_for((size_t)PLANES * n, (unsigned)c->block) + 7) / 8 * 8);
         // the counter's value once this launch's particle blocks are counted
         // (taken over only once the launch is enqueued)
         const uint32_t target = c->arrive_count + pblocks;
@@ -1702,11 +1749,23 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         p.tape_momn = c->taping ? slot.momn : nullptr;
         p.tape_contrib = c->taping ? slot.contrib : nullptr;
         p.arrive = c->arrive;
+        // the cell lists of steps k - 1, k, k + 1 (distinct: k mod 3 rotates)
+        p.cg = cg;
+        p.head = lh[k % 3];
+        p.next = ln[k % 3];
+        p.cell_of = lc[k % 3];
+        p.head_reset = (wca && k >= 1) ? lh[(k + 2) % 3] : nullptr;
+        p.cell_of_reset = lc[(k + 2) % 3];
+        p.head_build = (wca && k + 1 < nsteps) ? lh[(k + 1) % 3] : nullptr;
+        p.next_build = ln[(k + 1) % 3];
+        p.cell_of_build = lc[(k + 1) % 3];
         const unsigned grid = pblocks + (unsigned)c->nblocks;
         by_step_storage(c->p, [&](auto st) {
-            by_stencil(b->stencil, [&](auto w) {
-                launch_fused_st<decltype(st)::value, decltype(w)::value>(c, a, p, grid, tot);
-            });
+            constexpr int ST = decltype(st)::value;
+            if (wca)
+                launch_fused_st<ST, 2, true>(c, a, p, grid, tot);
+            else
+                by_stencil(b->stencil, [&](auto w) { launch_fused_st<ST, decltype(w)::value, false>(c, a, p, grid, tot); });
         });
         LB_LAUNCH_CHECK(c, "coupled step");
         c->arrive_count = target;
@@ -1714,6 +1773,12 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         LB_TRY(step_done(c, dst, tot, ckpt));
         pos_in = pos;
         mom_in = mom;
+    }
+    if (wca) {
+        // the last step's list back to -1 (the one before it the last launch reset)
+        hipLaunchKernelGGL(k_cell_unlink, dim3(grid_for((size_t)n, 256)), dim3(256), 0, c->stream, lc[(nsteps - 1) % 3],
+                           n, lh[(nsteps - 1) % 3]);
+        LB_LAUNCH_CHECK(c, "cell list reset");
     }
     return LB_OK;
 }
@@ -2127,10 +2192,22 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     float *const fbpar[2] = {c->fbar, c->fbar ? c->fbar + 3 * N : nullptr};
     int64_t pending = -1;  // tape index of the coupled step whose particle adjoint is not finished
     bool pending_jac = false;  // ... and whose bond and pair Jacobians are still to come
+    // a refused pair adjoint (no cell list: not expected, the buffers are
+    // checked before the sweep) leaves its error for the end of the sweep
+    int pair_rc = LB_OK;
     auto pair_jacobians = [&](int64_t t) {
         const lb_beads &bp = c->tape_beads[c->tape_slot[t]];
-        if (bp.wca_epsilon > 0.0) launch_wca_adjoint(c, &bp, tape_slot_at(c, c->tape_slot[t]).half, fc_bar, half_bar);
+        if (bp.wca_epsilon > 0.0 && pair_rc == LB_OK)
+            pair_rc = launch_wca_adjoint(c, &bp, tape_slot_at(c, c->tape_slot[t]).half, fc_bar, half_bar);
     };
+    // the pair adjoint relinks the context's cell list at each taped R'
+    for (const lb_beads &bp : c->tape_beads) {
+        if (!(bp.wca_epsilon > 0.0)) continue;
+        const CellGrid cg = cell_grid(c, &bp);
+        if (!c->cell_head || !c->cell_of || !c->cell_next || c->pair_cap < bp.n ||
+            c->cell_cap < (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2])
+            return fail(c, LB_EDEVICE, "the pair adjoint needs the context's cell list, which no coupled step allocated");
+    }
 
     const unsigned saved_blocks = c->nblocks;
     const int saved_block = c->block;
@@ -2362,6 +2439,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     }
     c->block = saved_block;
     c->nblocks = (int)saved_blocks;
+    if (rc == LB_OK && pair_rc != LB_OK) rc = pair_rc;
     if (rc != LB_OK) {
         // a sweep that stopped part way may leave WCA cell heads linked: put
         // them all back so that the next particle half starts from empty lists

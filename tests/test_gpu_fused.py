@@ -15,8 +15,9 @@ and against the FP64 oracle, through the C ABI.
 - The oracle: 20 fused steps against orc.coupled_step at the tolerances of
   test_gpu_beads.
 - The three- and four-point kernels phi_3, phi_4 fused as well.
-- Runs that take the separate launches (one step, WCA pairs, walls) match
-  the step-by-step loop too; no run leaves the wait flag (bit 3) set.
+- WCA pairs (Kremer-Grest chains) fused too, over several calls.
+- Runs that take the separate launches (one step, walls) match the
+  step-by-step loop too; no run leaves the wait flag (bit 3) set.
 """
 import numpy as np
 import pytest
@@ -135,12 +136,24 @@ def test_fused_branched_within_1e12(lat):
     assert_same(fus, sep, tol=1e-12)
 
 
-@pytest.mark.parametrize("case", ["one_step", "wca", "walls"])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_fused_kremer_grest_bitwise(lat, storage):
+    """WCA pairs in the fused launch (three rotating cell lists built by the
+    launches): 12 steps of 6 self-avoiding FENE chains of 10 in a 20 x 18 x
+    16 box, in three calls, bit for bit against the separate launches; a
+    second run afterwards starts from clean lists (the last list's heads
+    are put back)."""
+    p = lat.FluidParams(nx=20, ny=18, nz=16, kT=1e-4, seed=41, storage=storage)
+    factory = make_beads(lat, (20, 18, 16), 6, 10, seed=43, self_avoiding=True, bond="fene", k_bond=3e-3, r0=1.5,
+                         wca_epsilon=1e-4, wca_sigma=1.0, zeta=2.0)
+    for chunks in ([5, 4, 3], [12]):
+        sep, fus = run_pair(lat, p, factory, 12, chunks=chunks)
+        assert_same(fus, sep)
+
+
+@pytest.mark.parametrize("case", ["one_step", "walls"])
 def test_separate_launch_cases_match_loop(lat, case):
     extra = {}
-    if case == "wca":
-        # self-avoiding chains (no overlapping pair), FENE bonds with WCA
-        extra = dict(self_avoiding=True, bond="fene", k_bond=3e-3, r0=1.5, wca_epsilon=1e-4, wca_sigma=1.0)
     steps = 1 if case == "one_step" else 6
     p = lat.FluidParams(nx=20, ny=20, nz=20, kT=1e-4, seed=23, walls=(case == "walls"))
     sep, fus = run_pair(lat, p, make_beads(lat, (20, 20, 20), 3, 8, seed=29, **extra), steps)
@@ -168,14 +181,20 @@ def test_fused_against_oracle(orc, lat):
     dev.close()
 
 
-def test_fused_taped_gradients_match(lat):
+@pytest.mark.parametrize("kind", ["harmonic", "kremer_grest"])
+def test_fused_taped_gradients_match(lat, kind):
     """Reverse sweep over 12 taped coupled steps (checkpoint every 4), fused
-    against separate: identical dL/dn(0), dL/dg, dL/dR(0), dL/dP(0) for a
-    fixed seeded dL/dn(T), dL/dR(T), dL/dP(T)."""
+    against separate: the same dL/dn(0), dL/dg, dL/dR(0), dL/dP(0) for a
+    fixed seeded dL/dn(T), dL/dR(T), dL/dP(T); harmonic chains, and
+    Kremer-Grest chains (FENE + WCA pairs)."""
     import torch
     L, T = 20, 12
     p = lat.FluidParams(nx=L, ny=L, nz=L, kT=1e-4, seed=31, body_force=(1e-5, 0, 0))
-    factory = make_beads(lat, (L, L, L), 3, 8, seed=37)
+    if kind == "harmonic":
+        factory = make_beads(lat, (L, L, L), 3, 8, seed=37)
+    else:
+        factory = make_beads(lat, (L, L, L), 4, 8, seed=37, self_avoiding=True, bond="fene", k_bond=3e-3, r0=1.5,
+                             wca_epsilon=1e-4, wca_sigma=1.0, zeta=2.0)
     g = torch.Generator().manual_seed(41)
     lamT = torch.randn((19, L, L, L), generator=g, dtype=torch.float64)
     res = []
