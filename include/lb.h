@@ -464,9 +464,11 @@ int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
 
 /* Allocates now what the next nsteps >= 0 taped steps will take while they
  * run: their checkpoints and, with beads != NULL, room in the bead tape for
- * nsteps coupled steps of these beads; so that no allocation falls inside a
- * timed or latency-bound run.  Only allocates (the memory is the tape's and
- * goes with it).  Errors: LB_ESTATE (no tape), LB_EINVAL (nsteps < 0),
+ * nsteps coupled steps of these beads and the coupled steps' device buffers
+ * (force field, bitmaps, bond partner table, cell lists); so that no
+ * allocation falls inside a timed or latency-bound run.  Only allocates
+ * (and synchronises once for the bond table).  Errors: LB_ESTATE (no tape),
+ * LB_EINVAL (nsteps < 0, or the checks of lb_couple on beads),
  * LB_EUNSUPPORTED (a bead count other than the tape's), LB_ENOMEM. */
 int lb_tape_reserve(lb_ctx *ctx, int32_t nsteps, const lb_beads *beads);
 int lb_backward(lb_ctx *ctx, const void *dL_dn_T, int32_t dtype, void *dL_dn_0, double dL_dg[3]);

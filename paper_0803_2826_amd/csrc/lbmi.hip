@@ -1970,10 +1970,24 @@ int lb_tape_reserve(lb_ctx *c, int32_t nsteps, const lb_beads *b)
     LB_TRY(use_device(c));
     LB_TRY(reserve_checkpoints(c, nsteps));
     if (b && b->n > 0) {
+        LB_TRY(couple_check(c, b));
         if (c->tape_nb == 0) c->tape_nb = b->n;
         if (b->n != c->tape_nb)
             return fail(c, LB_EUNSUPPORTED, "the bead count must stay the same over the taped steps");
         LB_TRY(tape_grow(c, b, (size_t)nsteps));
+        // the coupled steps' own device buffers (force field, bitmaps, bond
+        // partner table, cell lists), which their first call would allocate
+        LB_TRY(ensure_bead_buffers(c, b->n));
+        LB_TRY(ensure_fused_buffers(c, b->n));
+        if (b->wca_epsilon > 0.0) {
+            const CellGrid cg = cell_grid(c, b);
+            const size_t ncell = (size_t)cg.nc[0] * cg.nc[1] * cg.nc[2];
+            LB_TRY(ensure_pair_buffers(c, b->n, ncell));
+            LB_TRY(ensure_fused_lists(c, b->n, ncell));
+        }
+        int deg = 0;
+        bool ok = true;
+        LB_TRY(build_partners(c, b, &deg, &ok));
     }
     return LB_OK;
 }
