@@ -98,6 +98,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--block", type=int, default=-1,
+                    help="threads per block of the timed loop's step launches: -1 (default) searches them on the "
+                         "first step; a fixed value skips the search (profiling runs whose counters would "
+                         "perturb the search's timings)")
     ap.add_argument("--chains", choices=("harmonic", "kg"), default="harmonic",
                     help="bead model of the timed loop: the harmonic chains of the workload (default) or "
                          "Kremer-Grest chains (FENE bonds + WCA pairs, eps = kT) for profiling that path")
@@ -280,7 +284,7 @@ def main() -> int:
     L = args.L
     n_chains, length = 64, 32
     N = L ** 3
-    pd = lattice.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=KT, seed=0, track_totals=True, block=-1)
+    pd = lattice.FluidParams(nx=L, ny=L, nz=L, storage="f32", kT=KT, seed=0, track_totals=True, block=args.block)
     lat = lattice.Lattice(pd)
     lat.init_equilibrium()
     if args.chains == "kg":
