@@ -192,13 +192,14 @@ def run_forms(L: int) -> dict:
 
     # the differentiation workload (128^3, 16 x 32 beads, 500 coupled steps,
     # probe + drag loss): checkpoints every 50 steps (the workload's own
-    # interval; the reverse sweep recomputes all but the last segment), and
-    # the whole tape resident in HBM (84 GB, nothing recomputed); the error
-    # of the timed K = 50 gradient against the FP64 oracle's central
+    # interval; the reverse sweep recomputes all but the last segment), the
+    # whole tape resident in HBM (84 GB, nothing recomputed), and a moments
+    # tape (every step's rho - rho0 and j, 16.8 GB, nothing recomputed); the
+    # error of the timed K = 50 gradient against the FP64 oracle's central
     # differences along seeded directions, stored by
     # tests/golden/make_c5_directional.py
     W = DIFF_WORKLOAD
-    for K, tag in ((W["checkpoint_every"], ""), (W["steps"], "_tape_resident")):
+    for K, tag in ((W["checkpoint_every"], ""), (W["steps"], "_tape_resident"), (0, "_moments_tape")):
         d = forms.differentiation_study(K)
         out["taped_forward_mlups" + tag] = round(d["sites"] * d["steps"] / (d["forward_ms"] * 1e-3) / 1e6, 1)
         out["backward_mlups" + tag] = round(d["sites"] * d["steps"] / (d["backward_ms"] * 1e-3) / 1e6, 1)
@@ -209,16 +210,17 @@ def run_forms(L: int) -> dict:
             out["backward_grad_rel_err"] = max(e["rel_err"] for e in errs)
             out["backward_grad_check"] = [{k: e[k] for k in ("seed", "gpu", "oracle_fd", "rel_err", "rel_err_signed",
                                                              "cancellation", "loss_rel_err")} for e in errs]
-        if tag == "" and os.path.exists(C5_ADJOINT):
+        if tag != "_tape_resident" and os.path.exists(C5_ADJOINT):
             with open(C5_ADJOINT) as f:
                 ref = json.load(f)
-            out["backward_grad_elementwise"] = {k: float(f"{v:.3e}")
-                                                for k, v in forms.elementwise_errors(d, ref).items()}
+            out["backward_grad_elementwise" + tag] = {k: float(f"{v:.3e}")
+                                                      for k, v in forms.elementwise_errors(d, ref).items()}
         del d
     out["backward_config"] = (f"{W['L']}^3, {W['steps']} coupled steps from rest with {W['chains']} x "
                               f"{W['length']} beads (zeta {W['zeta']:g}, k 10 kT), probe + drag loss; "
                               f"checkpoints every {W['checkpoint_every']} steps (_tape_resident: all {W['steps']} "
-                              f"step buffers kept, nothing recomputed); FP32 fluid, FP64 beads; gradients w.r.t. "
+                              f"step buffers kept, nothing recomputed; _moments_tape: every step's rho - rho0 and "
+                              f"j kept, 16 B per site, nothing recomputed); FP32 fluid, FP64 beads; gradients w.r.t. "
                               f"n(0), g, R(0), P(0); grad error: directional derivatives along seeded random "
                               f"directions against FP64 oracle central differences (eps 3e-5), relative to "
                               f"sum |g_i v_i|; elementwise: against the FP64 oracle's adjoint of the same 500 "

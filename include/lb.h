@@ -428,6 +428,15 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * recording goes on without them and lb_backward allocates them itself;
  * they are also left to lb_backward when they would take more than half of
  * the device's free memory (T is not known at lb_tape_begin).
+ * checkpoint_every = 0 records a moments tape instead: no checkpoints, and
+ * every taped step writes the moments (rho - rho0, j) of the state it
+ * starts from, 16 bytes per site and step in FP32 (the only part of the
+ * state the collision's Jacobian depends on), so the reverse sweep
+ * recomputes nothing and reads 16 B per site of each step instead of a
+ * state; the slots are allocated in chunks of up to 64 steps and 1 GiB by
+ * the steps (or lb_tape_reserve) and freed when the tape ends.  The taped
+ * steps take no fused totals (lb_totals forms them from the state), and
+ * taped coupled steps with phi_3 or phi_4 take the separate launches.
  * A tape lasts until the next lb_tape_begin; a call that replaces the state
  * or the step counter (lb_set_populations, lb_init_equilibrium,
  * lb_set_step_count, lb_load) ends it, so a later lb_backward returns
@@ -456,14 +465,14 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  *                     coupled step (device FP64 [n][3]; NULL = not wanted);
  * without taped coupled steps they are ignored.  lb_backward is
  * lb_backward_coupled with all four NULL.
- * Errors: LB_ESTATE (no tape, a tape ended by one of the calls above, or
- * called between lb_couple and lb_step; lb_tape_begin between lb_couple and
- * lb_step), LB_EUNSUPPORTED (a batch
+ * Errors: LB_EINVAL (checkpoint_every < 0), LB_ESTATE (no tape, a tape
+ * ended by one of the calls above, or called between lb_couple and lb_step;
+ * lb_tape_begin between lb_couple and lb_step), LB_EUNSUPPORTED (a batch
  * context; the bead count changed between taped coupled steps), LB_ENOMEM. */
 int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
 
 /* Allocates now what the next nsteps >= 0 taped steps will take while they
- * run: their checkpoints and, with beads != NULL, room in the bead tape for
+ * run: their checkpoints (or moment slots) and, with beads != NULL, room in the bead tape for
  * nsteps coupled steps of these beads and the coupled steps' device buffers
  * (force field, bitmaps, bond partner table, cell lists); so that no
  * allocation falls inside a timed or latency-bound run.  Only allocates

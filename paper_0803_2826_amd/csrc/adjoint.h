@@ -186,11 +186,11 @@ __global__ void __launch_bounds__(256) k_adjoint_step(AdjArgs a)
 
         float rhob = 0.f;
         if (THERMAL && !a.cc.noise_rho0) {
-            float r[15];
-            fluid_normals(s, a.step, a.cc.box, a.cc.key0, a.cc.key1, 1.0f, r);
+            float gn[15];
+            fluid_normals(s, a.step, a.cc.box, a.cc.key0, a.cc.key1, 1.0f, gn);
             const float h = 0.5f / __builtin_amdgcn_sqrtf(rho);
 #pragma unroll
-            for (int k = 4; k <= 18; ++k) rhob += mb[k] * a.cc.sig[k] * r[k - 4];
+            for (int k = 4; k <= 18; ++k) rhob += mb[k] * a.cc.sig[k] * gn[k - 4];
             rhob *= h;
         }
         // momentum modes: ms_{1..3} = m_{1..3} + F

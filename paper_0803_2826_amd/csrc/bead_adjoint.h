@@ -25,6 +25,7 @@ namespace lbmi {
 
 struct BeadAdjArgs {
     const void *pop;        // state buffer A of the step (pre-collision n_t(r) = A_i(r - c_i))
+    const float *moments;   // or NULL; else the step's (rho - rho0, j) per site, [z][4][y][x] (pop unused)
     Geom geo;
     double rho0;
     double g[3];
@@ -72,17 +73,26 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
         const double R[3] = {a.half[3 * b], a.half[3 * b + 1], a.half[3 * b + 2]};
         stencil_node<W>(R, q, g, node, wq, dw);
         if (q < W * W * W) {
-            uint32_t xx, yy, zz;
-            const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
-            const T *pop = static_cast<const T *>(a.pop);
             double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+            if (a.moments) {
+                const uint32_t nxny = g.nxny, zn = node / nxny, rn = node - zn * nxny;
+                const float *mp = a.moments + (size_t)(4u * zn) * nxny + rn;
+                m = (double)mp[0];
+                j[0] = (double)mp[nxny];
+                j[1] = (double)mp[2 * (size_t)nxny];
+                j[2] = (double)mp[3 * (size_t)nxny];
+            } else {
+                uint32_t xx, yy, zz;
+                const PullOffsets o = pull_offsets(node, g, xx, yy, zz);
+                const T *pop = static_cast<const T *>(a.pop);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
-                m += v;
-                j[0] += v * kCX[i];
-                j[1] += v * kCY[i];
-                j[2] += v * kCZ[i];
+                for (int i = 0; i < Q; ++i) {
+                    const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
+                    m += v;
+                    j[0] += v * kCX[i];
+                    j[1] += v * kCY[i];
+                    j[2] += v * kCZ[i];
+                }
             }
             rho = a.rho0 + m;
             for (int c = 0; c < 3; ++c) {

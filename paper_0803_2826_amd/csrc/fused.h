@@ -320,16 +320,17 @@ __device__ __forceinline__ void particle_block(const ParticleArgs &a)
 
 // One fused coupled step: blocks [0, a.block0) are the particle half
 // (particle_block), the rest the fluid step with the bead force
-// (stream_collide_site in WAIT mode).  blockDim a multiple of 64; a.block0 a
-// multiple of 8 so that the site blocks keep their XCD mapping.
-template <int ST, bool THERMAL, bool TOTALS, bool FULL, int W, bool PAIRS = false>
+// (stream_collide_site in WAIT mode; with MOM it also writes the input
+// state's moments, a step of a moments tape).  blockDim a multiple of 64;
+// a.block0 a multiple of 8 so that the site blocks keep their XCD mapping.
+template <int ST, bool THERMAL, bool TOTALS, bool FULL, int W, bool PAIRS = false, bool MOM = false>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) k_coupled_step(StepArgs a, ParticleArgs p)
 {
     if (blockIdx.x < a.block0) {
         particle_block<ST, W, PAIRS>(p);
         return;
     }
-    stream_collide_site<ST, THERMAL, TOTALS, true, false, FULL, true>(a);
+    stream_collide_site<ST, THERMAL, TOTALS, true, false, FULL, true, MOM>(a);
 }
 
 // Recompute sweep of the reverse pass over taped steps: the fluid step (the

@@ -122,6 +122,13 @@ struct lb_ctx {
     // the taped forward writes its step buffers into seg, so slots 1.. of the
     // last segment hold them until a reverse sweep recomputes over them
     bool seg_fwd = false;
+    // checkpoint_every = 0: no checkpoints; every taped step writes its input
+    // state's moments (rho - rho0, j: [z][4][y][x] FP32, 16 B per site) into
+    // a slot of mom_chunks (mom_chunk_steps slots per chunk), and the reverse
+    // sweep recomputes nothing
+    bool tape_mom = false;
+    std::vector<float *> mom_chunks;
+    size_t mom_chunk_steps = 0;
     float *lamA = nullptr, *lamB = nullptr;
     double *gbar_d = nullptr;
     double *adj_partials = nullptr;
@@ -454,12 +461,33 @@ int ensure_bead_buffers(lb_ctx *c, int n)
 
 size_t state_bytes(const lb_ctx *c) { return (size_t)c->geo.planes * c->geo.N * c->elem; }
 
-// The checkpoints that the next nsteps taped steps will push, allocated
-// before their first launch (an allocation between the launches of a run
-// would stall the queue).
+// Moments tape: the slot of taped step t.
+float *mom_slot(const lb_ctx *c, uint64_t t)
+{
+    return c->mom_chunks[t / c->mom_chunk_steps] + (size_t)(t % c->mom_chunk_steps) * 4 * (size_t)c->geo.N;
+}
+
+// The checkpoints (or, on a moments tape, the moment slots) that the next
+// nsteps taped steps will fill, allocated before their first launch (an
+// allocation between the launches of a run would stall the queue).
 int reserve_checkpoints(lb_ctx *c, int32_t nsteps)
 {
     if (!c->taping) return LB_OK;
+    if (c->tape_mom) {
+        // chunks of up to 64 slots and about 1 GiB
+        const size_t per = 4 * sizeof(float) * (size_t)c->geo.N;
+        if (c->mom_chunk_steps == 0) c->mom_chunk_steps = std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 30) / per));
+        const uint64_t need = c->step - c->tape_step0 + (uint64_t)nsteps;
+        while ((uint64_t)c->mom_chunks.size() * c->mom_chunk_steps < need) {
+            float *p = nullptr;
+            if (hipMalloc(&p, c->mom_chunk_steps * per) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, LB_ENOMEM, "moments tape allocation failed");
+            }
+            c->mom_chunks.push_back(p);
+        }
+        return LB_OK;
+    }
     const uint64_t s0 = c->step - c->tape_step0, K = (uint64_t)c->tape_k;
     const size_t count = (size_t)((s0 + (uint64_t)nsteps) / K - s0 / K);
     while (c->ckpt_ready.size() < count) {
@@ -514,6 +542,10 @@ void free_tape(lb_ctx *c)
     c->checkpoints.clear();
     for (void *p : c->ckpt_ready) (void)hipFree(p);
     c->ckpt_ready.clear();
+    for (float *p : c->mom_chunks) (void)hipFree(p);
+    c->mom_chunks.clear();
+    c->mom_chunk_steps = 0;
+    c->tape_mom = false;
     c->taping = false;
     c->seg_fwd = false;
     c->tape_slot.clear();
@@ -1039,7 +1071,7 @@ int step_dst(lb_ctx *c, void **dst, bool *ckpt)
 {
     *dst = c->bufB;
     *ckpt = false;
-    if (!c->taping) return LB_OK;
+    if (!c->taping || c->tape_mom) return LB_OK;
     const uint64_t k = (c->step - c->tape_step0) % (uint64_t)c->tape_k;
     if (k + 1 == (uint64_t)c->tape_k) {
         if (!c->ckpt_ready.empty()) {
@@ -1203,21 +1235,30 @@ int ensure_fused_lists(lb_ctx *c, int n, size_t ncell)
     return LB_OK;
 }
 
-template <int ST, bool TH, bool TOT, int W, bool PAIRS>
+template <int ST, bool TH, bool TOT, int W, bool PAIRS, bool MOM = false>
 void launch_fused_t(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid)
 {
     const size_t lds = TOT ? (size_t)kTotalsLds * (size_t)c->block : 0;  // block_sum_totals
     if (TH && c->full_relax)
-        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, W, PAIRS>), dim3(grid), dim3(c->block), lds, c->stream, a,
-                           p);
-    else
-        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, W, PAIRS>), dim3(grid), dim3(c->block), lds, c->stream,
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, TH, W, PAIRS, MOM>), dim3(grid), dim3(c->block), lds, c->stream,
                            a, p);
+    else
+        hipLaunchKernelGGL((k_coupled_step<ST, TH, TOT, false, W, PAIRS, MOM>), dim3(grid), dim3(c->block), lds,
+                           c->stream, a, p);
 }
 
+// mom: a step of a moments tape (no fused totals; phi_2 only, the caller
+// takes the separate launches for the wider kernels)
 template <int ST, int W, bool PAIRS>
-void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid, bool tot)
+void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsigned grid, bool tot, bool mom)
 {
+    if constexpr (W == 2) {
+        if (mom) {
+            if (c->thermal) launch_fused_t<ST, true, false, W, PAIRS, true>(c, a, p, grid);
+            else launch_fused_t<ST, false, false, W, PAIRS, true>(c, a, p, grid);
+            return;
+        }
+    }
     if (c->thermal) {
         if (tot) launch_fused_t<ST, true, true, W, PAIRS>(c, a, p, grid);
         else launch_fused_t<ST, true, false, W, PAIRS>(c, a, p, grid);
@@ -1225,6 +1266,46 @@ void launch_fused_st(lb_ctx *c, const StepArgs &a, const ParticleArgs &p, unsign
         if (tot) launch_fused_t<ST, false, true, W, PAIRS>(c, a, p, grid);
         else launch_fused_t<ST, false, false, W, PAIRS>(c, a, p, grid);
     }
+}
+
+// The step kernel of the reverse sweep's recompute and of a moments tape's
+// forward (k_recompute_step): with frc the bead force of a.force, with mom
+// the input state's moments written to a.moments (one of the two at least),
+// and in extra blocks the recorded force of the next taped coupled step put
+// back (entries > 0).  site_blocks blocks of `block` threads take the sites,
+// the tile of block b being b (a.xcd_remap = 0).
+void launch_recompute(lb_ctx *c, const StepArgs &a, int block, uint32_t site_blocks, bool frc, bool mom,
+                      const long long *contrib, int entries, long long *force_next, uint32_t *fmask_next)
+{
+    const unsigned grid = site_blocks + (entries > 0 ? grid_for((size_t)entries, block) : 0u);
+    by_step_storage(c->p, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        auto go = [&](auto th, auto walls, auto full) {
+            constexpr bool TH = decltype(th)::value, WL = decltype(walls)::value, FU = decltype(full)::value;
+            // (force, moments): (yes, yes), (yes, no), (no, yes)
+            if (frc && mom)
+                hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, true, true>), dim3(grid), dim3(block), 0,
+                                   c->stream, a, site_blocks, contrib, entries, force_next, fmask_next);
+            else if (frc)
+                hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, true, false>), dim3(grid), dim3(block), 0,
+                                   c->stream, a, site_blocks, contrib, entries, force_next, fmask_next);
+            else
+                hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, false, true>), dim3(grid), dim3(block), 0,
+                                   c->stream, a, site_blocks, contrib, entries, force_next, fmask_next);
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        const bool full = c->thermal && c->full_relax;
+        if (c->geo.walls) {
+            if (!c->thermal) go(F_{}, T_{}, F_{});
+            else if (full) go(T_{}, T_{}, T_{});
+            else go(T_{}, T_{}, F_{});
+        } else {
+            if (!c->thermal) go(F_{}, F_{}, F_{});
+            else if (full) go(T_{}, F_{}, T_{});
+            else go(T_{}, F_{}, F_{});
+        }
+    });
 }
 
 }  // namespace
@@ -1559,13 +1640,22 @@ int lb_step(lb_ctx *c, int32_t nsteps)
             a.force = c->force;
             a.consume = 1u;
         }
-        by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
+        // a step of a moments tape also writes its input state's moments
+        // (no fused totals then: lb_totals forms them from the state)
+        const bool mom = c->taping && c->tape_mom;
+        if (mom) {
+            a.xcd_remap = 0u;
+            a.moments = mom_slot(c, c->step - c->tape_step0);
+            launch_recompute(c, a, c->block, (uint32_t)c->nblocks, frc, true, nullptr, 0, nullptr, nullptr);
+        } else {
+            by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, tot, frc); });
+        }
         LB_LAUNCH_CHECK(c, "stream_collide");
         if (frc) {
             c->pending_force = false;
             c->pending_slot = -1;
         }
-        LB_TRY(step_done(c, dst, tot, ckpt));
+        LB_TRY(step_done(c, dst, tot && !mom, ckpt));
     }
     return LB_OK;
 }
@@ -1642,11 +1732,13 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
     if (nsteps == 0) return LB_OK;
     if (c->step + (uint64_t)nsteps > 0xffffffffull) return fail(c, LB_EINVAL, "step counter would exceed 2^32");
     LB_TRY(use_device(c));
-    // one launch per step without walls (WCA pairs with phi_2 only);
-    // everything else (and a single step: its bead state would be read and
-    // written by the same launch) takes the separate launches
+    // one launch per step without walls (WCA pairs, and the steps of a
+    // moments tape, with phi_2 only); everything else (and a single step: its
+    // bead state would be read and written by the same launch) takes the
+    // separate launches
     const bool wca = b->wca_epsilon > 0.0;
-    bool fused = nsteps >= 2 && b->n > 0 && !c->geo.walls && (!wca || stencil_width(b) == 2);
+    const bool mom_tape = c->taping && c->tape_mom;
+    bool fused = nsteps >= 2 && b->n > 0 && !c->geo.walls && ((!wca && !mom_tape) || stencil_width(b) == 2);
     int deg = 0;
     if (fused) LB_TRY(build_partners(c, b, &deg, &fused));
     if (!fused) {
@@ -1689,7 +1781,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
                            c->stream, b->pos, b->mom, b->mass, n, c->geo, bm[0], cg, lh[0], ln[0], lc[0]);
     });
     LB_LAUNCH_CHECK(c, "bead nodes");
-    const bool tot = c->p.track_totals != 0;
+    const bool tot = c->p.track_totals != 0 && !mom_tape;  // a moments tape's steps: no fused totals
     const size_t n3 = 3 * (size_t)n;
     const double *pos_in = b->pos, *mom_in = b->mom;
     for (int32_t k = 0; k < nsteps; ++k) {
@@ -1708,6 +1800,7 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         StepArgs a = plain_step_args(c, c->bufA, dst, (uint32_t)c->step);
         a.fmask = bm[k & 1];
         a.force = c->force;
+        if (mom_tape) a.moments = mom_slot(c, c->step - c->tape_step0);
         a.consume = 1u;
         const uint32_t pblocks = (uint32_t)((grid_for((size_t)PLANES * n, (unsigned)c->block) + 7) / 8 * 8);
         // the counter's value once this launch's particle blocks are counted
@@ -1763,9 +1856,10 @@ int lb_coupled_steps(lb_ctx *c, const lb_beads *b, int32_t nsteps)
         by_step_storage(c->p, [&](auto st) {
             constexpr int ST = decltype(st)::value;
             if (wca)
-                launch_fused_st<ST, 2, true>(c, a, p, grid, tot);
+                launch_fused_st<ST, 2, true>(c, a, p, grid, tot, mom_tape);
             else
-                by_stencil(b->stencil, [&](auto w) { launch_fused_st<ST, decltype(w)::value, false>(c, a, p, grid, tot); });
+                by_stencil(b->stencil,
+                           [&](auto w) { launch_fused_st<ST, decltype(w)::value, false>(c, a, p, grid, tot, mom_tape); });
         });
         LB_LAUNCH_CHECK(c, "coupled step");
         c->arrive_count = target;
@@ -1997,11 +2091,19 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
     LB_RANGE();
     if (!c) return LB_EINVAL;
     if (c->batch) return fail(c, LB_EUNSUPPORTED, "differentiation is per single box");
-    if (checkpoint_every < 1) return fail(c, LB_EINVAL, "checkpoint_every must be >= 1");
+    if (checkpoint_every < 0) return fail(c, LB_EINVAL, "checkpoint_every must be >= 0");
     if (c->pending_force) return fail(c, LB_ESTATE, "lb_tape_begin between lb_couple and lb_step");
     LB_TRY(use_device(c));
     LB_TRY(settle_state(c));
     free_tape(c);
+    if (checkpoint_every == 0) {
+        // moments tape: slots are reserved by the steps (or lb_tape_reserve)
+        c->tape_mom = true;
+        c->tape_k = 0;
+        c->tape_step0 = c->step;
+        c->taping = true;
+        return LB_OK;
+    }
     // the forward writes each segment's step buffers straight into the
     // segment buffer, so the reverse sweep recomputes no step of the last
     // segment (none at all when checkpoint_every covers the whole run); if
@@ -2055,18 +2157,27 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     if (dtype != LB_F64 && dtype != LB_F32) return fail(c, LB_EINVAL, "dtype must be LB_F64 or LB_F32");
     LB_TRY(use_device(c));
     const size_t N = c->geo.N, n19 = 19 * N;
-    if (c->step < c->tape_step0 || c->tape_k < 1) return fail(c, LB_ESTATE, "the tape does not match the step counter");
+    if (c->step < c->tape_step0 || (!c->tape_mom && c->tape_k < 1))
+        return fail(c, LB_ESTATE, "the tape does not match the step counter");
     const uint64_t T = c->step - c->tape_step0;
-    const int K = c->tape_k;
-    // one slot per taped step, one checkpoint at the start and after every K steps
-    if (T != (uint64_t)c->tape_slot.size() || (uint64_t)c->checkpoints.size() != 1 + T / (uint64_t)K)
+    // one slot per taped step; one checkpoint at the start and after every K
+    // steps, or (moments tape) one moment slot per step, the whole run being
+    // one segment whose states are never needed
+    if (T != (uint64_t)c->tape_slot.size())
         return fail(c, LB_ESTATE, "the tape does not match the steps taken since lb_tape_begin");
+    if (c->tape_mom) {
+        if (T > (uint64_t)INT32_MAX || (uint64_t)c->mom_chunks.size() * c->mom_chunk_steps < T)
+            return fail(c, LB_ESTATE, "the moments tape does not cover the steps taken since lb_tape_begin");
+    } else if ((uint64_t)c->checkpoints.size() != 1 + T / (uint64_t)c->tape_k) {
+        return fail(c, LB_ESTATE, "the tape does not match the steps taken since lb_tape_begin");
+    }
+    const int K = c->tape_mom ? (int)std::max<uint64_t>(T, 1) : c->tape_k;
     const size_t sb = state_bytes(c);
     const int nbd = c->tape_nb;
     const bool coupled = !c->tape_beads.empty();
     LB_TRY(settle_state(c));  // the sweep may overwrite the segment buffer
-    // a segment holds at most min(K, T) step buffers
-    const uint64_t slots = std::min<uint64_t>((uint64_t)K, T);
+    // a segment holds at most min(K, T) step buffers (none on a moments tape)
+    const uint64_t slots = c->tape_mom ? 0 : std::min<uint64_t>((uint64_t)K, T);
     if (slots > SIZE_MAX / sb) return fail(c, LB_ENOMEM, "segment buffer too large");
     if (c->seg_bytes < slots * sb) {
         (void)hipFree(c->seg);
@@ -2085,7 +2196,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
     // values): taken when a segment is recomputed at all and the buffer
     // leaves half of the free memory; otherwise the adjoint reads the states
     const size_t mom_stride = 4 * N;
-    const bool recompute = T > (uint64_t)K || !c->seg_fwd;
+    const bool recompute = !c->tape_mom && (T > (uint64_t)K || !c->seg_fwd);
     if (recompute && slots >= 2 && c->moments_slots < slots - 1) {
         (void)hipFree(c->moments);
         c->moments = nullptr;
@@ -2240,7 +2351,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         char *seg = static_cast<char *>(c->seg);
         // the last segment's step buffers 1 .. len-1 are still those the
         // forward wrote, unless an earlier sweep recomputed over them
-        const bool kept = c->seg_fwd && sg == nseg - 1;
+        const bool kept = c->tape_mom || (c->seg_fwd && sg == nseg - 1);
         if (!kept) c->seg_fwd = false;
         // recompute steps 0 .. len-2 of the segment; the force fields
         // alternate by step parity, and a coupled step's launch puts the
@@ -2269,40 +2380,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 a.xcd_remap = 0u;  // the side blocks follow the step's own grid
                 a.moments = mom ? c->moments + (size_t)k * mom_stride : nullptr;
                 const TapeSlot tn = next ? tape_slot_at(c, c->tape_slot[t + 1]) : TapeSlot{};
-                const int entries = next ? tn.entries : 0;
-                const unsigned grid = (unsigned)c->nblocks + (entries > 0 ? grid_for((size_t)entries, 256) : 0u);
-                by_step_storage(c->p, [&](auto st) {
-                    constexpr int ST = decltype(st)::value;
-                    auto go = [&](auto th, auto walls, auto full) {
-                        constexpr bool TH = decltype(th)::value, WL = decltype(walls)::value,
-                                       FU = decltype(full)::value;
-                        // (force, moments): (yes, yes), (yes, no), (no, yes)
-                        if (frc && mom)
-                            hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, true, true>), dim3(grid), dim3(256),
-                                               0, c->stream, a, (uint32_t)c->nblocks, next ? tn.contrib : nullptr,
-                                               entries, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
-                        else if (frc)
-                            hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, true, false>), dim3(grid), dim3(256),
-                                               0, c->stream, a, (uint32_t)c->nblocks, next ? tn.contrib : nullptr,
-                                               entries, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
-                        else
-                            hipLaunchKernelGGL((k_recompute_step<ST, TH, WL, FU, false, true>), dim3(grid), dim3(256),
-                                               0, c->stream, a, (uint32_t)c->nblocks, next ? tn.contrib : nullptr,
-                                               entries, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
-                    };
-                    using T_ = std::true_type;
-                    using F_ = std::false_type;
-                    const bool full = c->thermal && c->full_relax;
-                    if (c->geo.walls) {
-                        if (!c->thermal) go(F_{}, T_{}, F_{});
-                        else if (full) go(T_{}, T_{}, T_{});
-                        else go(T_{}, T_{}, F_{});
-                    } else {
-                        if (!c->thermal) go(F_{}, F_{}, F_{});
-                        else if (full) go(T_{}, F_{}, T_{});
-                        else go(T_{}, F_{}, F_{});
-                    }
-                });
+                launch_recompute(c, a, 256, (uint32_t)c->nblocks, frc, mom, next ? tn.contrib : nullptr,
+                                 next ? tn.entries : 0, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
             } else {
                 if (next) respread(t + 1, fpar[(t + 1) & 1u], mpar[(t + 1) & 1u]);
                 by_step_storage(c->p, [&](auto st) { launch_step_st<decltype(st)::value>(c, a, false, false); });
@@ -2317,9 +2396,11 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             const int q = (int)(t & 1u);
             const uint32_t step = (uint32_t)(c->tape_step0 + t);
             const int slot = c->tape_slot[t];
-            const void *pop = state_at(sg, k);
+            // the step's input state, or on a moments tape its moments only
+            const void *pop = c->tape_mom ? nullptr : state_at(sg, k);
+            float *const tmom = c->tape_mom ? mom_slot(c, t) : nullptr;
             AdjArgs aa;
-            aa.moments = (mom && k + 1 < len) ? c->moments + (size_t)k * mom_stride : nullptr;
+            aa.moments = c->tape_mom ? tmom : (mom && k + 1 < len) ? c->moments + (size_t)k * mom_stride : nullptr;
             aa.state = pop;
             aa.lam_in = c->lamA;
             aa.lam_out = c->lamB;
@@ -2390,6 +2471,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 const TapeSlot ts = tape_slot_at(c, slot);
                 BeadAdjArgs ba;
                 ba.pop = pop;
+                ba.moments = tmom;
                 ba.geo = c->geo;
                 ba.rho0 = c->p.rho0;
                 for (int r = 0; r < 3; ++r) ba.g[r] = c->p.body_force[r];

@@ -83,11 +83,11 @@ __device__ __forceinline__ void fluid_normals(uint32_t site, uint32_t step, uint
     uint32_t f[16];
 #pragma unroll
     for (int grp = 0; grp < 4; ++grp) {
-        const uint32_t a = w[3 * grp], b = w[3 * grp + 1], c = w[3 * grp + 2];
-        f[4 * grp + 0] = a >> 8;
-        f[4 * grp + 1] = b >> 8;
-        f[4 * grp + 2] = c >> 8;
-        f[4 * grp + 3] = (a & 0xffu) | ((b & 0xffu) << 8) | ((c & 0xffu) << 16);
+        const uint32_t wa = w[3 * grp], wb = w[3 * grp + 1], wc = w[3 * grp + 2];
+        f[4 * grp + 0] = wa >> 8;
+        f[4 * grp + 1] = wb >> 8;
+        f[4 * grp + 2] = wc >> 8;
+        f[4 * grp + 3] = (wa & 0xffu) | ((wb & 0xffu) << 8) | ((wc & 0xffu) << 16);
     }
 #pragma unroll
     for (int p = 0; p < 7; ++p) box_muller(f[2 * p], f[2 * p + 1], c, g[2 * p], g[2 * p + 1]);

@@ -131,7 +131,7 @@ def test_backward_error_paths(orc, lat):
         dev.backward(torch.zeros(19 * 512, dtype=torch.float64))
     assert ei.value.code == LB_ESTATE
     with pytest.raises(LBError) as ei:
-        dev.tape_begin(0)
+        dev.tape_begin(-1)
     assert ei.value.code == LB_EINVAL
     dev.close()
     B = lat.BatchLattice(lat.FluidParams(nx=2, ny=2, nz=2, kT=1e-4, block=256), [(8, 8, 8)])

@@ -3,7 +3,8 @@
 probe + drag loss of the final state, gradients w.r.t. n(0), g, R(0), P(0)),
 through forms.differentiation_study, the code path bench.py times (fused
 coupled steps, lb_coupled_steps, taped with a checkpoint every 50 steps: the
-restore and recompute run nine times).
+restore and recompute run nine times; and taped with a moments tape, the
+reverse sweep reading every step's moments, recomputing nothing).
 
 - 500 coupled steps, directional derivatives <grad, v> along the two seeded
   directions of tests/golden/c5_directional.json against the FP64 oracle's
@@ -56,12 +57,15 @@ def rel_err(got, ref):
     return float(np.abs(np.asarray(got) - ref).max() / np.abs(ref).max())
 
 
-@pytest.fixture(scope="module")
-def study500(forms):
+@pytest.fixture(scope="module", params=["checkpoints", "moments_tape"])
+def study500(forms, request):
+    """The 500-step run taped with a checkpoint every 50 steps, and with a
+    moments tape (lb_tape_begin(0): every step's (rho - rho0, j) kept,
+    nothing recomputed)."""
     from paper_0803_2826_amd.inputs import DIFF_WORKLOAD as W
-    print(f"differentiation workload: {W['L']}^3, {W['steps']} coupled steps, K = {W['checkpoint_every']}",
-          flush=True)
-    return forms.differentiation_study(W["checkpoint_every"])
+    K = W["checkpoint_every"] if request.param == "checkpoints" else 0
+    print(f"differentiation workload: {W['L']}^3, {W['steps']} coupled steps, K = {K} ({request.param})", flush=True)
+    return forms.differentiation_study(K)
 
 
 def test_c5_500_steps_against_oracle_central_differences(forms, study500):

@@ -151,3 +151,20 @@ def test_params_two_rate(L):
                       (0.2, float("inf"))):
         assert L.lb_params_two_rate(ge, magic, ctypes.byref(q)) == LB_EINVAL
     assert L.lb_params_two_rate(0.2, 0.1875, None) == LB_EINVAL
+
+
+def test_library_sources_declare_no_shadowed_names():
+    """The library's sources parse with every shadowing warning an error: a
+    local that hides an outer one of the same name (a bead momentum pointer
+    named like the moments-tape flag of the same function, for one) turns
+    the outer name's later uses into the inner one's silently."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_0803_2826_amd", "csrc")
+    for src in ("lbmi.hip", "bw_probe.hip"):
+        r = subprocess.run([hipcc, "-std=c++17", "--offload-arch=gfx950", "-Wshadow-all", "-Werror=shadow-all",
+                            "-fsyntax-only", src], cwd=csrc, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-4000:]
