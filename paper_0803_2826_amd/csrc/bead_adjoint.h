@@ -67,17 +67,42 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
     const int b = t / LANES, q = t % LANES;
     const bool live = b < a.n;
     const Geom &g = a.geo;
+    const double h = 1.0;
     uint32_t node = 0;
     double wq = 0.0, dw[3] = {0.0, 0.0, 0.0}, uq[3] = {0.0, 0.0, 0.0}, rho = 1.0, fb[3] = {0.0, 0.0, 0.0};
+    // the bead's own inputs are loaded, and the OU constants formed, while
+    // the node values are in flight (lanes past the last bead keep zeros and
+    // take part in the shuffles below)
+    double Rnb[3] = {0.0, 0.0, 0.0}, Pnb_in[3] = {0.0, 0.0, 0.0}, I[3] = {0.0, 0.0, 0.0};
+    double m = 1.0, z = 0.0, C1 = 1.0, C2 = h;
     if (live) {
         const double R[3] = {a.half[3 * b], a.half[3 * b + 1], a.half[3 * b + 2]};
+        // adjoint of the state after the step (the same expressions as
+        // k_bead_adjoint_finish when folded); every lane of the bead reads it
+        // before its first lane writes this step's half_bar and p_bar below
+        if (a.fold) {
+            const double hm = 0.5 / a.fold_mass[b];
+            for (int c = 0; c < 3; ++c) {
+                Rnb[c] = a.half_bar[3 * b + c];
+                Pnb_in[c] = a.p_bar[3 * b + c] + hm * Rnb[c];
+            }
+            if (q == 0 && a.fold_cell_head) a.fold_cell_head[a.fold_cell_of[b]] = -1;
+        } else {
+            for (int c = 0; c < 3; ++c) {
+                Rnb[c] = a.pos_bar[3 * b + c];
+                Pnb_in[c] = a.mom_bar[3 * b + c];
+            }
+        }
+        m = a.mass[b];
+        z = a.zeta[b];
+        for (int c = 0; c < 3; ++c) I[c] = -(a.mom1[3 * b + c] - a.mom0[3 * b + c] - h * a.fc[3 * b + c]);
         stencil_node<W>(R, q, g, node, wq, dw);
         if (q < W * W * W) {
-            double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+            double ms = 0.0, j[3] = {0.0, 0.0, 0.0};
             if (a.moments) {
                 const uint32_t nxny = g.nxny, zn = node / nxny, rn = node - zn * nxny;
                 const float *mp = a.moments + (size_t)(4u * zn) * nxny + rn;
-                m = (double)mp[0];
+                ms = (double)mp[0];
                 j[0] = (double)mp[nxny];
                 j[1] = (double)mp[2 * (size_t)nxny];
                 j[2] = (double)mp[3 * (size_t)nxny];
@@ -88,54 +113,27 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     const double v = (double)S::ld(pop[pull_index(node, o, i, zz, g)], 0.f);
-                    m += v;
+                    ms += v;
                     j[0] += v * kCX[i];
                     j[1] += v * kCY[i];
                     j[2] += v * kCZ[i];
                 }
             }
-            rho = a.rho0 + m;
-            for (int c = 0; c < 3; ++c) {
-                uq[c] = (j[c] + 0.5 * a.g[c]) / rho;
-                fb[c] = (double)a.fbar[(size_t)c * g.N + node];
-            }
+            for (int c = 0; c < 3; ++c) fb[c] = (double)a.fbar[(size_t)c * g.N + node];
+            rho = a.rho0 + ms;
+            for (int c = 0; c < 3; ++c) uq[c] = (j[c] + 0.5 * a.g[c]) / rho;
+        }
+        if (z > 0.0) {
+            C1 = exp(-z * h / m);
+            C2 = (m / z) * (1.0 - C1);
         }
     }
     // adjoint of the spread reaction: Ibar = sum_q w_q fbar(node_q) / h
-    const double h = 1.0;
     double Ib[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Ib[c] = bead_sum<LANES>(wq * fb[c]) / h;
-    if (!live) return;
-    // adjoint of the state after the step (the same expressions as
-    // k_bead_adjoint_finish when folded)
-    double Rnb[3], Pnb_in[3];
-    if (a.fold) {
-        const double hm = 0.5 / a.fold_mass[b];
-        for (int c = 0; c < 3; ++c) {
-            Rnb[c] = a.half_bar[3 * b + c];
-            Pnb_in[c] = a.p_bar[3 * b + c] + hm * Rnb[c];
-        }
-        if (q == 0 && a.fold_cell_head) a.fold_cell_head[a.fold_cell_of[b]] = -1;
-    } else {
-        for (int c = 0; c < 3; ++c) {
-            Rnb[c] = a.pos_bar[3 * b + c];
-            Pnb_in[c] = a.mom_bar[3 * b + c];
-        }
-    }
-    const double m = a.mass[b], z = a.zeta[b];
-    double C1, C2;
-    if (z > 0.0) {
-        C1 = exp(-z * h / m);
-        C2 = (m / z) * (1.0 - C1);
-    } else {
-        C1 = 1.0;
-        C2 = h;
-    }
-    double I[3], Pnb[3], ubb[3], pb[3], fcb[3];
+    double Pnb[3], ubb[3], pb[3], fcb[3];
     for (int c = 0; c < 3; ++c) {
-        const double P = a.mom0[3 * b + c], Pn = a.mom1[3 * b + c], Fc = a.fc[3 * b + c];
-        I[c] = -(Pn - P - h * Fc);
         // R_new = R' + (h/2) P''/m, P_new = P'';  I = -(P'' - P - h F^c)
         Pnb[c] = Pnb_in[c] + 0.5 * h / m * Rnb[c] - Ib[c];
         pb[c] = Ib[c] + C1 * Pnb[c];
@@ -149,7 +147,7 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
         gq[c] = 0.5 * wq * ubb[c] / rho;
     }
     // u_q = (sum n c + g/2) / rho: lambda_i(node) += w_q (c_i - u_q) . ubar / rho
-    if (wq != 0.0) {
+    if (live && wq != 0.0) {
         const uint32_t node_z = fdiv(fdiv(node, g.div_nx), g.div_ny);  // lambda is z-major (lam_index)
         const double s0 = -(uq[0] * ubb[0] + uq[1] * ubb[1] + uq[2] * ubb[2]);
 #pragma unroll
@@ -162,16 +160,22 @@ __global__ void __launch_bounds__(256) k_bead_adjoint(BeadAdjArgs a)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         hb[c] = bead_sum<LANES>(wb * dw[c]);
-        gq[c] = bead_sum<LANES>(gq[c]);
+        // dL/dg: the bead's sum (on every lane of the bead), then the beads
+        // of the wave (lanes of equal q), one atomic per wave
+        double v = bead_sum<LANES>(gq[c]);
+#pragma unroll
+        for (int off = LANES; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        gq[c] = v;
     }
-    if (q == 0) {
+    if (live && q == 0) {
         for (int c = 0; c < 3; ++c) {
             a.half_bar[3 * b + c] = Rnb[c] + hb[c];
             a.fc_bar[3 * b + c] = fcb[c];
             a.p_bar[3 * b + c] = pb[c];
-            atomicAdd(&a.gbar[c], gq[c]);
         }
     }
+    if ((threadIdx.x & 63u) == 0)
+        for (int c = 0; c < 3; ++c) atomicAdd(&a.gbar[c], gq[c]);
 }
 
 // Bond forces F_b = mag d, F_a = -mag d (d = R'_b - R'_a) have the
