@@ -6,7 +6,8 @@ fluctuating LB steps on the GPU from the pre-collision populations n0
 3) and returns n(T).  Its backward calls lb_backward: reverse streaming and
 the transposed moment-space collision with the noise replayed from its
 Philox counters, segment by segment from checkpoints taken every
-`checkpoint_every` steps.  Gradients flow to n0 and g.
+`checkpoint_every` steps (0: a moments tape, every step's density and
+momentum kept and nothing recomputed).  Gradients flow to n0 and g.
 
 LBCoupledRollout.apply(n0, g, pos0, mom0, beads, params, nsteps,
 checkpoint_every) runs `nsteps` coupled steps (particle half, then the LB

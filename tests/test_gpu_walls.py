@@ -142,10 +142,12 @@ def test_coupled_parity_with_walls(orc, lat):
     dev.close()
 
 
-def test_coupled_adjoint_with_walls_matches_oracle(orc, lat):
+@pytest.mark.parametrize("K", [4, 0])
+def test_coupled_adjoint_with_walls_matches_oracle(orc, lat, K):
     """Taped coupled steps in a channel (beads kept off the walls): the
     reverse sweep with the walls' reflected adjoint and the particle
-    adjoint, against the oracle's FP64 adjoint of whole coupled steps."""
+    adjoint, against the oracle's FP64 adjoint of whole coupled steps;
+    checkpoints every 4 steps, and a moments tape (K = 0)."""
     import torch
     rng = np.random.default_rng(5)
     po, pd = pair(orc, lat, 10, 8, 12, kT=1e-4, seed=3, g=(1e-4, 0.0, -2e-5), gamma_shear=0.1)
@@ -163,7 +165,7 @@ def test_coupled_adjoint_with_walls_matches_oracle(orc, lat):
     dev = lat.Lattice(pd)
     dev.set_populations(torch.from_numpy(n0))
     n0r = dev.get_populations().cpu().numpy()
-    dev.tape_begin(4)
+    dev.tape_begin(K)
     for _ in range(T):
         dev.coupled_step(db)
     dn0, dg, dR0, dP0 = dev.backward_coupled(torch.from_numpy(w), torch.from_numpy(a), torch.from_numpy(b))
