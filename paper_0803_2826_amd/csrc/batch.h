@@ -13,7 +13,9 @@
 // can be replayed unchanged.
 //
 // Ensemble velocity autocorrelation (sampled every step, pre-collision
-// momentum j = sum_i n_i c_i): for each box and each axis a, the lowest
+// momentum j = sum_i n_i c_i, formed after the collision as the stored
+// state's momentum less the force, which the collision adds to the
+// conserved j exactly): for each box and each axis a, the lowest
 // Fourier mode k = 2 pi / L_a of the two momentum components transverse to
 // a, j_hat(k) = sum_r j(r) exp(-i k r_a) (6 complex amplitudes per box).
 // Every tile writes its 12 partial sums to a row of its own (no atomics);
@@ -89,6 +91,8 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
     CollideConst cc = a.cc;
     for (uint32_t t = t_begin; t < t_end; ++t) {
         const uint32_t box = a.tile_box[t];
+        // this site's terms of the tile's 12 VACF sums, formed after the
+        // store so that they hold no registers across the collision
         float acc[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = 0.f;
@@ -107,22 +111,6 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
             if constexpr (S::rest_lo) lo_in = ld_plane(src + (size_t)kRestLo * N, s);
             mass_acc_t<ST> m_in = 0;
             if constexpr (S::rest_lo) m_in = site_mass_lo<ST>(dd, lo_in);
-            if (VACF) {
-                const float jx = (dd[1] - dd[2]) + (dd[7] - dd[8]) + (dd[9] - dd[10]) + (dd[11] - dd[12]) + (dd[13] - dd[14]);
-                const float jy = (dd[3] - dd[4]) + (dd[7] - dd[8]) - (dd[9] - dd[10]) + (dd[15] - dd[16]) + (dd[17] - dd[18]);
-                const float jz = (dd[5] - dd[6]) + (dd[11] - dd[12]) - (dd[13] - dd[14]) + (dd[15] - dd[16]) - (dd[17] - dd[18]);
-                const float fx = (float)x * d.inv_L[0], fy = (float)y * d.inv_L[1], fz = (float)z * d.inv_L[2];
-                const float cx = __builtin_amdgcn_cosf(fx), sx = __builtin_amdgcn_sinf(fx);
-                const float cy = __builtin_amdgcn_cosf(fy), sy = __builtin_amdgcn_sinf(fy);
-                const float cz = __builtin_amdgcn_cosf(fz), sz = __builtin_amdgcn_sinf(fz);
-                // exp(-i phi) = cos - i sin
-                acc[0] += jx * cz;  acc[1] -= jx * sz;   // k along z, j_x
-                acc[2] += jy * cz;  acc[3] -= jy * sz;   // k along z, j_y
-                acc[4] += jx * cy;  acc[5] -= jx * sy;   // k along y, j_x
-                acc[6] += jz * cy;  acc[7] -= jz * sy;   // k along y, j_z
-                acc[8] += jy * cx;  acc[9] -= jy * sx;   // k along x, j_y
-                acc[10] += jz * cx; acc[11] -= jz * sx;  // k along x, j_z
-            }
             cc.box = d.box_id;
             float out[Q], m0;
             collide_site<THERMAL, FULL, out_scale<ST>::value>(dd, cc.g, cc, s, step, out, m0);
@@ -134,8 +122,37 @@ __global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
             float mom[3];
             Philox4 rw = {0u, 0u, 0u, 0u};
             if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, step, d.box_id, cc.key0, cc.key1);
-            if constexpr (S::rest_lo) store_site<ST, false>(dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
-            else store_site16<ST, false>(dstp, N * (uint32_t)sizeof(T), s, m0, out, mass, mom, rw);
+            // with VACF the store also returns the stored values' momentum
+            if constexpr (S::rest_lo) store_site<ST, VACF>(dstp, N * (uint32_t)sizeof(T), s, m_in, out, mass, mom, rw);
+            else store_site16<ST, VACF>(dstp, N * (uint32_t)sizeof(T), s, m0, out, mass, mom, rw);
+            if (VACF) {
+                // the sampled momentum j = sum_i c_i n_i before the
+                // collision: the collision keeps j and adds the force
+                // (m*_k = m_k + g_k, k = 1..3), so j is the stored state's
+                // momentum less g, up to the storage rounding
+                const float jx = mom[0] - cc.g[0], jy = mom[1] - cc.g[1], jz = mom[2] - cc.g[2];
+                // the site's coordinates again (cheaper than keeping them)
+                const uint32_t q = fdiv(s, d.geo.div_nx);
+                const uint32_t zq = fdiv(q, d.geo.div_ny);
+                float fx = (float)(s - q * d.geo.nx) * d.inv_L[0];
+                float fy = (float)(q - zq * d.geo.ny) * d.inv_L[1];
+                float fz = (float)zq * d.inv_L[2];
+                // the phases pass through an empty asm that also takes a
+                // collision output, which keeps the compiler from forming
+                // the six Fourier factors before the collision (where they
+                // would hold registers across it)
+                __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fz) : "v"(out[0]));
+                const float cx = __builtin_amdgcn_cosf(fx), sx = __builtin_amdgcn_sinf(fx);
+                const float cy = __builtin_amdgcn_cosf(fy), sy = __builtin_amdgcn_sinf(fy);
+                const float cz = __builtin_amdgcn_cosf(fz), sz = __builtin_amdgcn_sinf(fz);
+                // exp(-i phi) = cos - i sin
+                acc[0] = jx * cz;  acc[1] = -(jx * sz);   // k along z, j_x
+                acc[2] = jy * cz;  acc[3] = -(jy * sz);   // k along z, j_y
+                acc[4] = jx * cy;  acc[5] = -(jx * sy);   // k along y, j_x
+                acc[6] = jz * cy;  acc[7] = -(jz * sy);   // k along y, j_z
+                acc[8] = jy * cx;  acc[9] = -(jy * sx);   // k along x, j_y
+                acc[10] = jz * cx; acc[11] = -(jz * sx);  // k along x, j_z
+            }
         }
         if (VACF) tile_sum12(acc, a.amp + 12 * (size_t)t);  // block-uniform: every thread takes part
     }
