@@ -80,8 +80,10 @@ __device__ __forceinline__ void tile_sum12(float acc[12], float *dst)
 }
 
 // FULL: the complete-relaxation collision (every non-conserved gamma_k = 0).
+// Its variants are held to 80 registers (6 waves per SIMD), which they fit
+// without scratch; the general-relaxation ones keep the compiler's choice.
 template <int ST, bool THERMAL, bool VACF, bool FULL>
-__global__ void __launch_bounds__(1024) k_batch_step(BatchArgs a)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(FULL ? 6 : 1))) k_batch_step(BatchArgs a)
 {
     using S = Storage<ST>;
     using T = typename S::T;
