@@ -47,15 +47,15 @@ def fluid_grads(lat, pd, n0, w, K, T):
     return dn0.cpu(), dg
 
 
-@pytest.mark.parametrize("case", ["f32", "bf16", "walls", "long"])
+@pytest.mark.parametrize("case", ["f32", "bf16", "f16", "walls", "long"])
 def test_fluid_moments_tape_bitwise(orc, lat, case):
     import torch
     rng = np.random.default_rng(3)
     nz = 8
     po, pd = pair(orc, lat, 12, 10, nz, kT=1e-4, seed=7, g=(1e-4, -5e-5, 2e-5), gamma_shear=0.2, gamma_bulk=-0.1,
                   gamma_3a=0.3, gamma_3b=-0.2, gamma_4a=0.1, gamma_4b=0.4)
-    if case == "bf16":
-        pd.storage = "bf16"
+    if case in ("bf16", "f16"):
+        pd.storage = case
     if case == "walls":
         pd.walls = True
     T = 70 if case == "long" else 13  # 70: past the first 64-step chunk of the tape
@@ -106,11 +106,14 @@ def compare(got, ref, tol, what):
     assert max(errs) <= tol
 
 
-@pytest.mark.parametrize("fused", [True, False])
-def test_coupled_moments_tape_matches_oracle(orc, lat, fused):
+@pytest.mark.parametrize("fused,storage", [(True, "f32"), (False, "f32"), (True, "bf16")])
+def test_coupled_moments_tape_matches_oracle(orc, lat, fused, storage):
+    """BF16 storage: against the checkpointed tape only (the oracle runs in
+    FP64, the stored trajectory in BF16)."""
     rng = np.random.default_rng(5)
     po, pd, n0, ob, db = system(orc, lat, rng, kT=1e-4, seed=5, g=(1e-4, -5e-5, 2e-5), gamma_shear=0.2,
                                 gamma_bulk=-0.1)
+    pd.storage = storage
     T = 8
     w = rng.normal(size=n0.shape)
     a, b = rng.normal(size=(ob.pos.shape[0], 3)), rng.normal(size=(ob.pos.shape[0], 3))
@@ -121,8 +124,9 @@ def test_coupled_moments_tape_matches_oracle(orc, lat, fused):
 
     n0r, got = coupled_grads(lat, pd, n0, make, T, 0, w, a, b, fused)
     _, ref = coupled_grads(lat, pd, n0, make, T, 3, w, a, b, fused)
-    lam0, gbar, pb0, mb0 = orc.backward_coupled(po, n0r, T, ob, w, a, b)
-    compare(got, (lam0, gbar, pb0, mb0), REL_TOL, "moments tape vs oracle")
+    if storage == "f32":
+        lam0, gbar, pb0, mb0 = orc.backward_coupled(po, n0r, T, ob, w, a, b)
+        compare(got, (lam0, gbar, pb0, mb0), REL_TOL, "moments tape vs oracle")
     compare(got, ref, 1e-5, "moments tape vs checkpoints every 3")
 
 
