@@ -222,3 +222,33 @@ def test_fused_taped_gradients_match(lat, kind):
         err = float((x - y).abs().max() / y.abs().max())
         print(f"{name}: fused vs separate {err:.2e} of the largest entry")
         assert err <= 2e-5, name
+
+
+@pytest.mark.parametrize("tape", [None, 4, 0])
+def test_empty_bead_set_is_plain_steps(lat, tape):
+    """No beads: lb_coupled_steps (and lb_couple) leave the fluid steps
+    plain, bit for bit, untaped and on a checkpointed or moments tape, and
+    the reverse sweep over them gives a fluid-only backward's gradient."""
+    import torch
+    p = lat.FluidParams(nx=16, ny=12, nz=10, kT=1e-4, seed=3, body_force=(1e-5, 0, 0), track_totals=False)
+    empty = lat.DeviceBeads(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    w = torch.randn((19, 10, 12, 16), generator=torch.Generator().manual_seed(5), dtype=torch.float64)
+    out = []
+    for coupled in (False, True):
+        dev = lat.Lattice(p)
+        dev.init_equilibrium()
+        if tape is not None:
+            dev.tape_begin(tape)
+        if coupled:
+            dev.coupled_steps(empty, 5)
+            dev.coupled_step(empty)
+        else:
+            dev.step(6)
+        n = dev.get_populations().cpu()
+        grads = dev.backward(w.to(dev.device)) if tape is not None else None
+        out.append((n, grads))
+        dev.close()
+    assert torch.equal(out[0][0], out[1][0])
+    if tape is not None:
+        assert torch.equal(out[0][1][0].cpu(), out[1][1][0].cpu())
+        assert tuple(out[0][1][1]) == tuple(out[1][1][1])
