@@ -93,8 +93,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         return _lib
     path = path or os.environ.get("LBMI_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
-        raise ImportError(f"liblbmi.so not built at {path}; run __graft_entry__.build() or "
-                          f"python paper_0803_2826_amd/build.py")
+        raise ImportError(f"liblbmi.so not built at {path}; run python -m paper_0803_2826_amd.build")
     import torch  # noqa: F401  (loads the HIP runtime the library will share)
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p

@@ -36,7 +36,7 @@ def probe() -> ctypes.CDLL:
     if _P is not None:
         return _P
     if not os.path.exists(hip_build.PROBE):
-        raise RuntimeError(f"{hip_build.PROBE} is not built (run __graft_entry__.build())")
+        raise RuntimeError(f"{hip_build.PROBE} is not built (run python -m paper_0803_2826_amd.build)")
     P = ctypes.CDLL(hip_build.PROBE)
     vp, i32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
     P.bw_copy.argtypes = [vp, vp, u64, i32, vp]
