@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(FULL 
             if constexpr (S::rest_lo) m_in = site_mass_lo<ST>(dd, lo_in);
             cc.box = d.box_id;
             float out[Q], m0;
-            collide_site<THERMAL, FULL, out_scale<ST>::value>(dd, cc.g, cc, s, step, out, m0);
+            collide_site<THERMAL, FULL, out_scale<ST>::value, ST == 1>(dd, cc.g, cc, s, step, out, m0);
             if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             void *dstp[Q + 1];
     #pragma unroll

@@ -689,7 +689,7 @@ __device__ __forceinline__ void stream_collide_site(const StepArgs &a)
             }
         }
         float out[Q], m0;
-        collide_site<THERMAL, FULL, out_scale<ST>::value>(d, F, a.cc, s, a.step, out, m0);
+        collide_site<THERMAL, FULL, out_scale<ST>::value, ST == 1>(d, F, a.cc, s, a.step, out, m0);
         if (!__builtin_isfinite(out[0])) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         Philox4 rw = {0u, 0u, 0u, 0u};
         if constexpr (is_stochastic<ST>::value) rw = rounding_words(s, a.step, a.cc.box, a.cc.key0, a.cc.key1);
