@@ -34,6 +34,9 @@
  *     context unchanged.  Errors found on the device (non-finite
  *     populations) latch and are returned by the next synchronising call
  *     (lb_totals, lb_mode_stats, lb_sync).  lb_last_error() gives a message.
+ *   - LB_ENOMEM: a device allocation was refused; the context stays
+ *     usable (the runtime's record of the refusal is cleared, so later
+ *     launches do not report it).
  *   - A context is not thread-safe.
  */
 #ifndef LB_H
@@ -468,7 +471,8 @@ int lb_noise_sample(lb_ctx *ctx, uint32_t site0, uint32_t count, uint32_t step, 
  * Errors: LB_EINVAL (checkpoint_every < 0), LB_ESTATE (no tape, a tape
  * ended by one of the calls above, or called between lb_couple and lb_step;
  * lb_tape_begin between lb_couple and lb_step), LB_EUNSUPPORTED (a batch
- * context; the bead count changed between taped coupled steps), LB_ENOMEM. */
+ * context; the bead count changed between taped coupled steps), LB_ENOMEM
+ * (from lb_tape_begin: no tape is left). */
 int lb_tape_begin(lb_ctx *ctx, int32_t checkpoint_every);
 
 /* Allocates now what the next nsteps >= 0 taped steps will take while they

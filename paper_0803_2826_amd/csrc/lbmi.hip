@@ -190,6 +190,19 @@ int check(lb_ctx *c, hipError_t e, const char *what)
 
 #define LB_LAUNCH_CHECK(c, what) LB_TRY(check((c), hipGetLastError(), (what)))
 
+// hipMalloc that leaves no error behind when it fails: the runtime keeps a
+// refused allocation as the last error, which the next launch check
+// (hipGetLastError) would then report as a failed launch, although the
+// caller was given LB_ENOMEM and the context stays usable.
+template <typename P>
+bool dev_alloc(P **p, size_t bytes)
+{
+    if (hipMalloc(reinterpret_cast<void **>(p), bytes) == hipSuccess) return true;
+    *p = nullptr;
+    (void)hipGetLastError();
+    return false;
+}
+
 int use_device(lb_ctx *c)
 {
     int cur = -1;
@@ -371,7 +384,7 @@ int ensure_scratch(lb_ctx *c, size_t bytes)
     if (c->scratch) (void)hipFree(c->scratch);
     c->scratch = nullptr;
     c->scratch_bytes = 0;
-    if (hipMalloc(&c->scratch, bytes) != hipSuccess) return fail(c, LB_ENOMEM, "scratch allocation failed");
+    if (!dev_alloc(&c->scratch, bytes)) return fail(c, LB_ENOMEM, "scratch allocation failed");
     c->scratch_bytes = bytes;
     return LB_OK;
 }
@@ -419,8 +432,8 @@ int ensure_bead_buffers(lb_ctx *c, int n)
             c->fmask = nullptr;
         };
         release();
-        if (hipMalloc(&c->force, 3 * N * sizeof(long long)) != hipSuccess ||
-            hipMalloc(&c->fmask, nwords * sizeof(uint32_t)) != hipSuccess) {
+        if (!dev_alloc(&c->force, 3 * N * sizeof(long long)) ||
+            !dev_alloc(&c->fmask, nwords * sizeof(uint32_t))) {
             release();
             return fail(c, LB_ENOMEM, "bead force field allocation failed");
         }
@@ -438,10 +451,10 @@ int ensure_bead_buffers(lb_ctx *c, int n)
         c->half = c->fc = c->fb2 = c->fp = nullptr;
         c->bead_cap = 0;
         const int cap = n < 64 ? 64 : n;
-        if (hipMalloc(&c->half, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fc, 3 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fb2, 6 * (size_t)cap * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fp, 3 * (size_t)cap * sizeof(double)) != hipSuccess)
+        if (!dev_alloc(&c->half, 3 * (size_t)cap * sizeof(double)) ||
+            !dev_alloc(&c->fc, 3 * (size_t)cap * sizeof(double)) ||
+            !dev_alloc(&c->fb2, 6 * (size_t)cap * sizeof(double)) ||
+            !dev_alloc(&c->fp, 3 * (size_t)cap * sizeof(double)))
             return fail(c, LB_ENOMEM, "bead scratch allocation failed");
         // both bond accumulators start at zero; each call zeroes the other one
         hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(12 * (size_t)cap, 256)), dim3(256), 0, c->stream,
@@ -480,10 +493,7 @@ int reserve_checkpoints(lb_ctx *c, int32_t nsteps)
         const uint64_t need = c->step - c->tape_step0 + (uint64_t)nsteps;
         while ((uint64_t)c->mom_chunks.size() * c->mom_chunk_steps < need) {
             float *p = nullptr;
-            if (hipMalloc(&p, c->mom_chunk_steps * per) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(c, LB_ENOMEM, "moments tape allocation failed");
-            }
+            if (!dev_alloc(&p, c->mom_chunk_steps * per)) return fail(c, LB_ENOMEM, "moments tape allocation failed");
             c->mom_chunks.push_back(p);
         }
         return LB_OK;
@@ -492,7 +502,7 @@ int reserve_checkpoints(lb_ctx *c, int32_t nsteps)
     const size_t count = (size_t)((s0 + (uint64_t)nsteps) / K - s0 / K);
     while (c->ckpt_ready.size() < count) {
         void *p = nullptr;
-        if (hipMalloc(&p, state_bytes(c)) != hipSuccess) return fail(c, LB_ENOMEM, "checkpoint allocation failed");
+        if (!dev_alloc(&p, state_bytes(c))) return fail(c, LB_ENOMEM, "checkpoint allocation failed");
         c->ckpt_ready.push_back(p);
     }
     return LB_OK;
@@ -504,7 +514,7 @@ int push_checkpoint(lb_ctx *c)
     if (!c->ckpt_ready.empty()) {
         p = c->ckpt_ready.back();
         c->ckpt_ready.pop_back();
-    } else if (hipMalloc(&p, state_bytes(c)) != hipSuccess) {
+    } else if (!dev_alloc(&p, state_bytes(c))) {
         return fail(c, LB_ENOMEM, "checkpoint allocation failed");
     }
     c->checkpoints.push_back(p);
@@ -588,7 +598,7 @@ int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
         (void)hipFree(c->cell_head);
         c->cell_head = nullptr;
         c->cell_cap = 0;
-        if (hipMalloc(&c->cell_head, ncell * sizeof(int32_t)) != hipSuccess)
+        if (!dev_alloc(&c->cell_head, ncell * sizeof(int32_t)))
             return fail(c, LB_ENOMEM, "cell list allocation failed");
         c->cell_cap = ncell;
         // every head starts at -1 (all bits set); each use puts back the heads it set
@@ -601,8 +611,8 @@ int ensure_pair_buffers(lb_ctx *c, int n, size_t ncell)
         (void)hipFree(c->cell_of);
         c->cell_next = c->cell_of = nullptr;
         c->pair_cap = 0;
-        if (hipMalloc(&c->cell_next, (size_t)n * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&c->cell_of, (size_t)n * sizeof(int32_t)) != hipSuccess)
+        if (!dev_alloc(&c->cell_next, (size_t)n * sizeof(int32_t)) ||
+            !dev_alloc(&c->cell_of, (size_t)n * sizeof(int32_t)))
             return fail(c, LB_ENOMEM, "cell list allocation failed");
         c->pair_cap = n;
     }
@@ -745,7 +755,7 @@ int tape_grow(lb_ctx *c, const lb_beads *b, size_t slots)
     if (c->tape_bead_used + need > c->tape_bead_bytes) {
         const size_t cap = std::max<size_t>(16 * tape_slot_bytes(b), 2 * (c->tape_bead_used + need));
         char *p = nullptr;
-        if (hipMalloc(&p, cap) != hipSuccess) return fail(c, LB_ENOMEM, "bead tape allocation failed");
+        if (!dev_alloc(&p, cap)) return fail(c, LB_ENOMEM, "bead tape allocation failed");
         if (c->tape_bead && c->tape_bead_used > 0)
             LB_TRY(check(c, hipMemcpyAsync(p, c->tape_bead, c->tape_bead_used, hipMemcpyDeviceToDevice, c->stream),
                          "bead tape copy"));
@@ -852,7 +862,7 @@ int batch_build_tiles(lb_ctx *c, int block)
     c->ntiles = first;
     (void)hipFree(c->tile_box);
     c->tile_box = nullptr;
-    if (hipMalloc(&c->tile_box, tiles.size() * sizeof(uint32_t)) != hipSuccess)
+    if (!dev_alloc(&c->tile_box, tiles.size() * sizeof(uint32_t)))
         return fail(c, LB_ENOMEM, "tile table allocation failed");
     LB_TRY(check(c, hipMemcpyAsync(c->tile_box, tiles.data(), tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                                    c->stream), "tile table upload"));
@@ -1077,7 +1087,7 @@ int step_dst(lb_ctx *c, void **dst, bool *ckpt)
         if (!c->ckpt_ready.empty()) {
             *dst = c->ckpt_ready.back();
             c->ckpt_ready.pop_back();
-        } else if (hipMalloc(dst, state_bytes(c)) != hipSuccess) {
+        } else if (!dev_alloc(dst, state_bytes(c))) {
             return fail(c, LB_ENOMEM, "checkpoint allocation failed");
         }
         *ckpt = true;
@@ -1179,7 +1189,7 @@ int build_partners(lb_ctx *c, const lb_beads *b, int *deg, bool *ok)
         (void)hipFree(c->partner);
         c->partner = nullptr;
         c->partner_cap = 0;
-        if (hipMalloc(&c->partner, tab.size() * sizeof(int32_t)) != hipSuccess)
+        if (!dev_alloc(&c->partner, tab.size() * sizeof(int32_t)))
             return fail(c, LB_ENOMEM, "bond partner table allocation failed");
         c->partner_cap = tab.size();
     }
@@ -1195,8 +1205,8 @@ int ensure_fused_buffers(lb_ctx *c, int n)
 {
     if (!c->fmask_f || !c->arrive) {
         const size_t nwords = ((size_t)c->geo.N + 31) / 32;
-        if (hipMalloc(&c->fmask_f, nwords * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&c->arrive, sizeof(uint32_t)) != hipSuccess)
+        if (!dev_alloc(&c->fmask_f, nwords * sizeof(uint32_t)) ||
+            !dev_alloc(&c->arrive, sizeof(uint32_t)))
             return fail(c, LB_ENOMEM, "fused step buffers allocation failed");
         hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nwords, 256)), dim3(256), 0, c->stream,
                            reinterpret_cast<int32_t *>(c->fmask_f), (uint32_t)nwords);
@@ -1208,7 +1218,7 @@ int ensure_fused_buffers(lb_ctx *c, int n)
         (void)hipFree(c->bead_pp);
         c->bead_pp = nullptr;
         c->bead_pp_cap = 0;
-        if (hipMalloc(&c->bead_pp, 12 * (size_t)n * sizeof(double)) != hipSuccess)
+        if (!dev_alloc(&c->bead_pp, 12 * (size_t)n * sizeof(double)))
             return fail(c, LB_ENOMEM, "fused step bead buffers allocation failed");
         c->bead_pp_cap = n;
     }
@@ -1225,7 +1235,7 @@ int ensure_fused_lists(lb_ctx *c, int n, size_t ncell)
     c->flist_cells = 0;
     c->flist_n = 0;
     const size_t words = 3 * ncell + 6 * (size_t)n;
-    if (hipMalloc(&c->flist, words * sizeof(int32_t)) != hipSuccess)
+    if (!dev_alloc(&c->flist, words * sizeof(int32_t)))
         return fail(c, LB_ENOMEM, "fused cell lists allocation failed");
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(3 * ncell, 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<uint32_t *>(c->flist), (uint32_t)(3 * ncell), 0xffffffffu);
@@ -1362,9 +1372,9 @@ int lb_create(const lb_params *params, void *stream, lb_ctx **out)
     const size_t bytes = state_bytes(c);
     // per-block totals rows: the most blocks any block size gives (64 threads)
     const size_t rows = std::max<size_t>(grid_for(c->geo.N, 64), step_blocks(c, 64));
-    if (hipMalloc(&c->bufA, bytes) != hipSuccess || hipMalloc(&c->bufB, bytes) != hipSuccess ||
-        hipMalloc(&c->partials, rows * 4 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->dev_out, 64 * sizeof(double)) != hipSuccess || hipMalloc(&c->flags, sizeof(int32_t)) != hipSuccess) {
+    if (!dev_alloc(&c->bufA, bytes) || !dev_alloc(&c->bufB, bytes) ||
+        !dev_alloc(&c->partials, rows * 4 * sizeof(double)) ||
+        !dev_alloc(&c->dev_out, 64 * sizeof(double)) || !dev_alloc(&c->flags, sizeof(int32_t))) {
         lb_destroy(c);
         return fail(nullptr, LB_ENOMEM, "device allocation failed");
     }
@@ -1448,14 +1458,14 @@ int lb_create_batch(const lb_params *params, int32_t nbox, const int32_t *dims, 
     bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipMalloc(&c->bufA, bytes) == hipSuccess && hipMalloc(&c->bufB, bytes) == hipSuccess &&
-         hipMalloc(&c->boxes_d, nbox * sizeof(BoxDesc)) == hipSuccess &&
-         hipMalloc(&c->dstep, 2 * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc(&c->dev_out, 64 * sizeof(double)) == hipSuccess && hipMalloc(&c->flags, sizeof(int32_t)) == hipSuccess;
+    ok = ok && dev_alloc(&c->bufA, bytes) && dev_alloc(&c->bufB, bytes) &&
+         dev_alloc(&c->boxes_d, nbox * sizeof(BoxDesc)) &&
+         dev_alloc(&c->dstep, 2 * sizeof(uint32_t)) &&
+         dev_alloc(&c->dev_out, 64 * sizeof(double)) && dev_alloc(&c->flags, sizeof(int32_t));
     if (ok && R > 0)
-        ok = hipMalloc(&c->amp, amp_rows * 12 * sizeof(float)) == hipSuccess &&
-             hipMalloc(&c->ring, (size_t)nbox * R * 12 * sizeof(float)) == hipSuccess &&
-             hipMalloc(&c->corr, (size_t)nbox * R * sizeof(double)) == hipSuccess;
+        ok = dev_alloc(&c->amp, amp_rows * 12 * sizeof(float)) &&
+             dev_alloc(&c->ring, (size_t)nbox * R * 12 * sizeof(float)) &&
+             dev_alloc(&c->corr, (size_t)nbox * R * sizeof(double));
     if (!ok) {
         lb_destroy(c);
         return fail(nullptr, LB_ENOMEM, "batch allocation failed");
@@ -2122,18 +2132,16 @@ int lb_tape_begin(lb_ctx *c, int32_t checkpoint_every)
         (void)hipFree(c->seg);
         c->seg = nullptr;
         c->seg_bytes = 0;
-        if (hipMalloc(&c->seg, need) == hipSuccess) {
-            c->seg_bytes = need;
-        } else {
-            c->seg = nullptr;
-            (void)hipGetLastError();  // an allocation that did not fit is no error here
-        }
+        if (dev_alloc(&c->seg, need)) c->seg_bytes = need;  // one that did not fit is no error here
     }
     c->seg_fwd = c->seg_bytes >= need;
     c->tape_k = checkpoint_every;
     c->tape_step0 = c->step;
     c->taping = true;
-    return push_checkpoint(c);
+    // a refused first checkpoint leaves no tape behind
+    const int rc = push_checkpoint(c);
+    if (rc != LB_OK) free_tape(c);
+    return rc;
 }
 
 // Reverse sweep over the tape.  Per segment: restore its checkpoint and
@@ -2184,11 +2192,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         c->seg = nullptr;
         c->seg_bytes = 0;
         c->seg_fwd = false;
-        if (hipMalloc(&c->seg, slots * sb) != hipSuccess) {
-            c->seg = nullptr;
-            (void)hipGetLastError();
-            return fail(c, LB_ENOMEM, "segment buffer allocation failed");
-        }
+        if (!dev_alloc(&c->seg, slots * sb)) return fail(c, LB_ENOMEM, "segment buffer allocation failed");
         c->seg_bytes = slots * sb;
     }
     // the moments (rho - rho0, j) of the recomputed states, 16 B per site
@@ -2204,11 +2208,8 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
         const size_t need = (size_t)(slots - 1) * mom_stride * sizeof(float);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need <= free_b / 2) {
-            if (hipMalloc(&c->moments, need) == hipSuccess) c->moments_slots = (size_t)(slots - 1);
-            else {
-                c->moments = nullptr;
-                (void)hipGetLastError();  // the states serve instead
-            }
+            // if it is refused, the states serve instead
+            if (dev_alloc(&c->moments, need)) c->moments_slots = (size_t)(slots - 1);
         }
     }
     // the adjoint step's blocks, dealt out layer by layer (256 threads)
@@ -2224,9 +2225,9 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             c->gbar_d = c->adj_partials = nullptr;
         };
         release();
-        if (hipMalloc(&c->lamA, n19 * sizeof(float)) != hipSuccess || hipMalloc(&c->lamB, n19 * sizeof(float)) != hipSuccess ||
-            hipMalloc(&c->gbar_d, 3 * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double)) != hipSuccess) {
+        if (!dev_alloc(&c->lamA, n19 * sizeof(float)) || !dev_alloc(&c->lamB, n19 * sizeof(float)) ||
+            !dev_alloc(&c->gbar_d, 3 * sizeof(double)) ||
+            !dev_alloc(&c->adj_partials, (size_t)nb * 3 * sizeof(double))) {
             release();
             return fail(c, LB_ENOMEM, "adjoint buffers allocation failed");
         }
@@ -2238,7 +2239,7 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
             (void)hipFree(c->bead_work);
             c->bead_work = nullptr;
             c->bead_work_n = 0;
-            if (hipMalloc(&c->bead_work, 15 * (size_t)nbd * sizeof(double)) != hipSuccess)
+            if (!dev_alloc(&c->bead_work, 15 * (size_t)nbd * sizeof(double)))
                 return fail(c, LB_ENOMEM, "bead adjoint buffers allocation failed");
             c->bead_work_n = nbd;
         }
@@ -2253,9 +2254,9 @@ static int backward_impl(lb_ctx *c, const void *dL_dn_T, int32_t dtype, const do
                 c->fmask2 = nullptr;
             };
             release();
-            if (hipMalloc(&c->fbar, 6 * N * sizeof(float)) != hipSuccess ||
-                hipMalloc(&c->force2, 3 * N * sizeof(long long)) != hipSuccess ||
-                hipMalloc(&c->fmask2, nwords * sizeof(uint32_t)) != hipSuccess) {
+            if (!dev_alloc(&c->fbar, 6 * N * sizeof(float)) ||
+                !dev_alloc(&c->force2, 3 * N * sizeof(long long)) ||
+                !dev_alloc(&c->fmask2, nwords * sizeof(uint32_t))) {
                 release();
                 return fail(c, LB_ENOMEM, "force adjoint allocation failed");
             }
