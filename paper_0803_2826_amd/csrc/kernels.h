@@ -507,8 +507,9 @@ __device__ __forceinline__ void store_site16(void *const *dstp, uint32_t plane_b
     for (int p = 0; p < 9; ++p) {
         pk[p] = P::pack(out[2 * p + 1], out[2 * p + 2], rw, 2 * p + 1);
         // keep the packed word as it is: the stores take its halves (the low
-        // half as is, the high half with a d16_hi store) instead of the
-        // compiler converting each value a second time
+        // half as is, the high half shifted down; the raw buffer store has
+        // no high-half form) instead of the compiler converting each value
+        // a second time
         __asm__ volatile("" : "+v"(pk[p]));
         sum = P::dot(pk[p], 1.f, 1.f, sum);
     }
