@@ -56,7 +56,9 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 // factor -2 ln 2 * scale (log2 -> ln) passed in as m2ln2_scale.
 __device__ __forceinline__ float bm_radius(uint32_t field24, float m2ln2_scale)
 {
-    const float ua = (float)(field24 + 1u) * 0x1p-24f;  // (0, 1], exact
+    // ua = (field24 + 1) 2^-24 in (0, 1], exact: one fused multiply-add of
+    // the exact conversion (the sum is a multiple of 2^-24 below 2^0)
+    const float ua = __builtin_fmaf((float)field24, 0x1p-24f, 0x1p-24f);
     return __builtin_amdgcn_sqrtf(m2ln2_scale * __builtin_amdgcn_logf(ua));
 }
 
@@ -87,7 +89,10 @@ __device__ __forceinline__ void fluid_normals(uint32_t site, uint32_t step, uint
         f[4 * grp + 0] = wa >> 8;
         f[4 * grp + 1] = wb >> 8;
         f[4 * grp + 2] = wc >> 8;
-        f[4 * grp + 3] = (wa & 0xffu) | ((wb & 0xffu) << 8) | ((wc & 0xffu) << 16);
+        // (wa & 255) | (wb & 255) << 8 | (wc & 255) << 16 with two byte
+        // permutes (selector byte 0x0c gives a zero byte)
+        const uint32_t ab = __builtin_amdgcn_perm(wb, wa, 0x0c0c0400u);
+        f[4 * grp + 3] = __builtin_amdgcn_perm(wc, ab, 0x0c040100u);
     }
 #pragma unroll
     for (int p = 0; p < 7; ++p) box_muller(f[2 * p], f[2 * p + 1], c, g[2 * p], g[2 * p + 1]);
