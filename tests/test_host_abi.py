@@ -168,3 +168,20 @@ def test_library_sources_declare_no_shadowed_names():
         r = subprocess.run([hipcc, "-std=c++17", "--offload-arch=gfx950", "-Wshadow-all", "-Werror=shadow-all",
                             "-fsyntax-only", src], cwd=csrc, capture_output=True, text=True, timeout=300)
         assert r.returncode == 0, r.stderr[-4000:]
+
+
+def test_device_allocations_go_through_the_clearing_helper():
+    """The HIP runtime keeps a refused hipMalloc as its last error, which the
+    library's launch checks would later report as a failed launch: every
+    device allocation of the library goes through dev_alloc, which clears
+    it (tests/test_gpu_alloc_failure.py checks the behaviour on the GPU)."""
+    import re
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_0803_2826_amd", "csrc",
+                       "lbmi.hip")
+    text = open(src).read()
+    helper = text[text.index("bool dev_alloc("):]
+    helper = helper[:helper.index("\n}\n")]
+    calls = [m.start() for m in re.finditer(r"\bhipMalloc\w*\s*\(", text)]
+    inside = [c for c in calls if text.index("bool dev_alloc(") <= c < text.index("bool dev_alloc(") + len(helper)]
+    assert len(calls) == 1 and inside == calls, "hipMalloc outside dev_alloc"
+    assert "hipGetLastError" in helper
