@@ -27,6 +27,8 @@
  *     The caller owns them; the library never frees or retains them past
  *     the call (stream-ordered: the work may still be in flight on the
  *     context stream when the call returns).
+ *   - A call on a context makes the context's device current
+ *     (hipSetDevice) when another one is, and leaves it current.
  *   - All work is enqueued on the stream given to lb_create, in call order.
  *     Calls that return data to host memory synchronise that stream.
  *   - Every function returns LB_OK (0) or a negative status.  Argument errors
