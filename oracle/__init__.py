@@ -140,6 +140,7 @@ def lib():
         L.orc_fields.argtypes = [pp, dp, dp, dp]
         L.orc_totals.argtypes = [pp, dp, dp]
         L.orc_mode_field.argtypes = [pp, dp, dp]
+        L.orc_transverse_modes.argtypes = [pp, dp, dp]
         L.orc_stencil.argtypes = [pp, dp, lp, dp]
         L.orc_couple.argtypes = [pp, dp, ctypes.c_uint32, ctypes.POINTER(OrcBeadset), dp, dp, dp]
         L.orc_coupled_step.argtypes = [pp, dp, dp, dp, ctypes.c_uint32, ctypes.POINTER(OrcBeadset), dp, dp]
@@ -159,7 +160,7 @@ def lib():
         for name in ("orc_tables", "orc_philox4x32_10", "orc_fluid_normals", "orc_bead_normals", "orc_bead_three_point",
                      "orc_equilibrium", "orc_moments_site", "orc_back_site", "orc_collide_site",
                      "orc_init_equilibrium", "orc_step", "orc_run", "orc_fields", "orc_totals",
-                     "orc_mode_field", "orc_stencil", "orc_couple", "orc_coupled_step",
+                     "orc_mode_field", "orc_transverse_modes", "orc_stencil", "orc_couple", "orc_coupled_step",
                      "orc_collide_site_adjoint", "orc_step_adjoint", "orc_backward", "orc_couple_adjoint",
                      "orc_backward_coupled", "orc_phi", "orc_bead_forces"):
             getattr(L, name).restype = None
@@ -303,6 +304,16 @@ def mode_field(p: Params, n: np.ndarray) -> np.ndarray:
     pc = p.c()
     lib().orc_mode_field(ctypes.byref(pc), _dp(n), _dp(m))
     return m
+
+
+def transverse_modes(p: Params, n: np.ndarray) -> np.ndarray:
+    """The six lowest transverse Fourier amplitudes (complex) of the
+    momentum density of n: k along z (j_x, j_y), along y (j_x, j_z), along x
+    (j_y, j_z)."""
+    out = np.zeros(12)
+    pc = p.c()
+    lib().orc_transverse_modes(ctypes.byref(pc), _dp(n), _dp(out))
+    return out[0::2] + 1j * out[1::2]
 
 
 def stencil(p: Params, R):

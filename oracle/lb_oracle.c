@@ -521,6 +521,44 @@ void orc_mode_field(const orc_params *p, const double *n, double *m)
     }
 }
 
+/* Lowest transverse Fourier amplitudes of the momentum density
+ * j(r) = sum_i c_i n_i(r) of the populations n at the start of a step (the
+ * momentum that step's collision sees and keeps).  For each axis a,
+ * k = 2 pi / L_a and the two components c normal to a,
+ *   j_hat_c(k) = sum_r j_c(r) exp(-i k r_a),
+ * the shear modes whose decay (eq. LBE at gamma = 0) and equal-time variance
+ * (the equipartition of eq. Pdistneq) the batch form's ensemble VACF
+ * samples.  out[12]: (re, im) of (k along z: j_x, j_y), (k along y: j_x,
+ * j_z), (k along x: j_y, j_z).  Plain sums over the sites. */
+void orc_transverse_modes(const orc_params *p, const double *n, double out[12])
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < 12; ++k) out[k] = 0.0;
+    for (int64_t s = 0; s < N; ++s) {
+        const int64_t x = s % p->nx, y = (s / p->nx) % p->ny, z = s / ((int64_t)p->nx * p->ny);
+        double j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < Q; ++i)
+            for (int a = 0; a < 3; ++a) j[a] += n[i * N + s] * CV[i][a];
+        const double fz = two_pi * (double)z / (double)p->nz;
+        const double fy = two_pi * (double)y / (double)p->ny;
+        const double fx = two_pi * (double)x / (double)p->nx;
+        /* exp(-i phi) = cos phi - i sin phi */
+        out[0] += j[0] * cos(fz);
+        out[1] -= j[0] * sin(fz);
+        out[2] += j[1] * cos(fz);
+        out[3] -= j[1] * sin(fz);
+        out[4] += j[0] * cos(fy);
+        out[5] -= j[0] * sin(fy);
+        out[6] += j[2] * cos(fy);
+        out[7] -= j[2] * sin(fy);
+        out[8] += j[1] * cos(fx);
+        out[9] -= j[1] * sin(fx);
+        out[10] += j[2] * cos(fx);
+        out[11] -= j[2] * sin(fx);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Point-particle coupling (Sec. "Force coupling", "Interpolating functions")*/
 /* ------------------------------------------------------------------------ */
