@@ -53,21 +53,38 @@ struct BatchArgs {
     int32_t *flags;
 };
 
+// Sum of x over the 64 lanes of a wave, complete in lane 63 (every lane of
+// the wave must be active): an inclusive scan within each row of 16 lanes
+// (DPP row shifts by 1, 2, 4 and 8), then the row totals carried up by the
+// row broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2 and 3).
+// A lane with no source in a shift, or outside the row mask, adds 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float add_dpp(float v)
+{
+    const int u = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+    return v + __builtin_bit_cast(float, u);
+}
+__device__ __forceinline__ float wave_sum_lane63(float x)
+{
+    x = add_dpp<0x111, 0xf>(x);  // row_shr:1
+    x = add_dpp<0x112, 0xf>(x);  // row_shr:2
+    x = add_dpp<0x114, 0xf>(x);  // row_shr:4
+    x = add_dpp<0x118, 0xf>(x);  // row_shr:8
+    x = add_dpp<0x142, 0xa>(x);  // row_bcast:15
+    x = add_dpp<0x143, 0xc>(x);  // row_bcast:31
+    return x;
+}
+
 // Block-wide sum of 12 floats into dst[0..11] (fixed order).  Every thread
 // of the block must call it (it synchronises).
 __device__ __forceinline__ void tile_sum12(float acc[12], float *dst)
 {
     __shared__ float red[16][12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        float x = acc[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        acc[c] = x;
-    }
+    for (int c = 0; c < 12; ++c) acc[c] = wave_sum_lane63(acc[c]);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0)
+    if (lane == 63)
 #pragma unroll
         for (int c = 0; c < 12; ++c) red[wid][c] = acc[c];
     __syncthreads();
