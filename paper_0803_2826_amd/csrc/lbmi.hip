@@ -958,25 +958,33 @@ int autotune(lb_ctx *c)
         // blocks per CU of the persistent launch; 0 = one tile per block (no
         // tile loop, the hardware deals tiles out); with the VACF the
         // candidates run the VACF variant of the kernel
+        // Two passes over the candidates, each candidate's better time
+        // counts (one pass of a few launches has picked a configuration
+        // several per cent slower than the best).
         const int blocks[] = {128, 256, 512, 1024};
         const int per_cu[] = {2, 4, 8, 16, 0};
+        float t[4][5];
         float best = 1e30f;
         int bb = 256;
         uint32_t bc = 1;
-        for (int blk : blocks) {
-            LB_TRY(batch_build_tiles(c, blk));
-            for (int pc : per_cu) {
-                const uint32_t grid = pc > 0 ? 256u * (uint32_t)pc : c->ntiles;
-                c->chunk = std::max<uint32_t>(1u, (c->ntiles + grid - 1) / grid);
-                const float ms = time_launches(c, 3, [&] { batch_launch_step(c, c->bufA, c->bufB, c->p.vacf_lags > 0); });
-                LB_LAUNCH_CHECK(c, "autotune batch");
-                if (ms < best) {
-                    best = ms;
-                    bb = blk;
-                    bc = c->chunk;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int ib = 0; ib < 4; ++ib) {
+                LB_TRY(batch_build_tiles(c, blocks[ib]));
+                for (int ip = 0; ip < 5; ++ip) {
+                    const int pc = per_cu[ip];
+                    const uint32_t grid = pc > 0 ? 256u * (uint32_t)pc : c->ntiles;
+                    c->chunk = std::max<uint32_t>(1u, (c->ntiles + grid - 1) / grid);
+                    const float ms =
+                        time_launches(c, 3, [&] { batch_launch_step(c, c->bufA, c->bufB, c->p.vacf_lags > 0); });
+                    LB_LAUNCH_CHECK(c, "autotune batch");
+                    t[ib][ip] = pass == 0 ? ms : std::min(t[ib][ip], ms);
+                    if (pass == 1 && t[ib][ip] < best) {
+                        best = t[ib][ip];
+                        bb = blocks[ib];
+                        bc = c->chunk;
+                    }
                 }
             }
-        }
         LB_TRY(batch_build_tiles(c, bb));
         c->chunk = bc;
         c->nblocks = (int)((c->ntiles + c->chunk - 1) / c->chunk);
