@@ -18,6 +18,7 @@ import test_oracle_dynamics as TD
 import test_oracle_kg as TK
 import test_oracle_lattice as TL
 import test_oracle_rng as TR
+import test_oracle_vacf as TV
 import test_oracle_walls as TW
 from test_oracle_rng import rocrand_ref  # noqa: F401  (fixture)
 
@@ -25,6 +26,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # name: (text in lb_oracle.c, replacement, pins as (function, keyword arguments))
 MUTANTS = {
+    "vacf_phase_sign": ("out[1] -= j[0] * sin(fz);", "out[1] += j[0] * sin(fz);",
+                        [(TV.test_transverse_modes_match_fft, {}), (TV.test_transverse_modes_shear_wave_and_uniform_flow, {})]),
+    "vacf_axis_extent": ("const double fy = two_pi * (double)y / (double)p->ny;",
+                         "const double fy = two_pi * (double)y / (double)p->nx;",
+                         [(TV.test_transverse_modes_match_fft, {})]),
     "philox_multiplier": ("M0 = 0xD2511F53u", "M0 = 0xD2511F57u", [(TR.test_philox_matches_rocrand, "rocrand")]),
     "philox_key_bump": ("k1 += W1;", "k1 += W0;", [(TR.test_philox_matches_rocrand, "rocrand")]),
     "box_muller_angle": ("*g1 = r * sin(TWO_PI * ub);", "*g1 = r * cos(TWO_PI * ub);",
