@@ -354,12 +354,39 @@ __device__ __forceinline__ void wait_arrivals(const uint32_t *arrive, uint32_t t
 // Block-wide sums of (FP64 mass, 3 FP32 momentum components) into one FP64
 // partial row per block, in a fixed order.  Every thread writes its values
 // to LDS; the block's first wave adds them (each lane a strided subset, then
-// across the wave) and writes the row, so the other waves spend two LDS
-// stores and a barrier on it instead of a wave reduction each.  Every
-// thread of the block must call it.
+// across the wave with DPP, no LDS) and writes the row, so the other waves
+// spend two LDS stores and a barrier on it instead of a wave reduction
+// each.  Every thread of the block must call it.
 // The LDS it uses is the launch's dynamic shared memory, kTotalsLds bytes
 // per thread.
 constexpr uint32_t kTotalsLds = 20;
+
+// v plus the value DPP control CTRL brings from another lane (0 for a lane
+// with no source, or outside ROW_MASK), for an FP64 value: both halves move
+// with the same control.  Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double add_dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the wave's 64 lanes, complete in lane 63: an inclusive scan in
+// each row of 16 lanes (row shifts by 1, 2, 4, 8), then the row totals
+// carried up by the row broadcasts (lane 15 into rows 1 and 3, lane 31 into
+// rows 2 and 3).
+__device__ __forceinline__ double wave_sum_lane63_f64(double x)
+{
+    x = add_dpp_f64<0x111, 0xf>(x);  // row_shr:1
+    x = add_dpp_f64<0x112, 0xf>(x);  // row_shr:2
+    x = add_dpp_f64<0x114, 0xf>(x);  // row_shr:4
+    x = add_dpp_f64<0x118, 0xf>(x);  // row_shr:8
+    x = add_dpp_f64<0x142, 0xa>(x);  // row_bcast:15
+    x = add_dpp_f64<0x143, 0xc>(x);  // row_bcast:31
+    return x;
+}
 
 __device__ __forceinline__ void block_sum_totals(double *out, double mass, float mom[3])
 {
@@ -381,13 +408,10 @@ __device__ __forceinline__ void block_sum_totals(double *out, double mass, float
         p[1] += (double)red_p[nb + k];
         p[2] += (double)red_p[2 * nb + k];
     }
+    m = wave_sum_lane63_f64(m);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        m += __shfl_xor(m, off, 64);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) p[c] += __shfl_xor(p[c], off, 64);
-    }
-    if (t == 0) {
+    for (int c = 0; c < 3; ++c) p[c] = wave_sum_lane63_f64(p[c]);
+    if (t == 63) {
         out[0] = m;
         out[1] = p[0];
         out[2] = p[1];
